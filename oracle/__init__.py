@@ -1,0 +1,278 @@
+"""Reference oracle for Shaped 2D-SSA -- test infrastructure, not product code.
+
+Only the test-suite, the smoke check and the CPU-baseline timing may import
+this package.  It computes everything in double precision from the plain
+definitions (explicit trajectory matrix, Jacobi SVD, explicit averaging),
+in C (``ssa_oracle.c``) driven from here through ctypes.  It shares no code
+with the GPU path.
+
+Conventions (0-based): images are (nx, ny) row-major arrays, x = row axis.
+Index sets are returned as (row, col) int arrays in column-major
+("lexicographic", row index fastest) order.  U is (L, d) and V is (K, d)
+with columns = singular vectors, sigma descending, and the sign of each
+triplet fixed so that the largest-magnitude entry of U_k is positive.
+
+Parity unpinned: none (each function is pinned in the oracle tests).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ssa_oracle.c")
+_LIB = os.path.join(_HERE, "libssa_oracle.so")
+_lib = None
+
+_d = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_i = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_u8 = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle library with gcc (OpenMP); returns its path."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        L.orc_nset.argtypes = [C.c_int, C.c_int, _d, C.c_void_p, _u8]
+        L.orc_window.argtypes = [C.c_int, C.c_int, C.c_void_p, _i, _i, C.POINTER(C.c_int),
+                                 C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_window.restype = C.c_int
+        L.orc_kset.argtypes = [C.c_int, C.c_int, _u8, C.c_int, _i, _i, C.c_int, C.c_int,
+                               _i, _i, C.POINTER(C.c_long)]
+        L.orc_weights.argtypes = [C.c_int, C.c_int, C.c_int, _i, _i, C.c_long, _i, _i, _d]
+        L.orc_trajectory.argtypes = [C.c_int, C.c_int, _d, C.c_int, _i, _i, C.c_long, _i, _i, _d]
+        L.orc_trajectory_mssa.argtypes = [C.c_int, _i, _d, C.c_int, _d]
+        L.orc_matvec.argtypes = [C.c_int, C.c_int, _d, C.c_int, _i, _i, C.c_long, _i, _i, _d, _d]
+        L.orc_rmatvec.argtypes = L.orc_matvec.argtypes
+        L.orc_svd_jacobi.argtypes = [C.c_long, C.c_long, _d, C.c_double, C.c_int, _d, _d, _d]
+        L.orc_svd_jacobi.restype = C.c_int
+        L.orc_svd_gram.argtypes = L.orc_svd_jacobi.argtypes
+        L.orc_svd_gram.restype = C.c_int
+        L.orc_reconstruct.argtypes = [C.c_int, C.c_int, C.c_int, _i, _i, C.c_long, _i, _i, C.c_int,
+                                      _d, _d, _d, C.c_int, _i, _d]
+        L.orc_reconstruct_mssa.argtypes = [C.c_int, _i, C.c_int, C.c_int, _d, _d, _d, C.c_int, _i, _d]
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
+
+
+# --------------------------------------------------------------------------
+# shapes
+# --------------------------------------------------------------------------
+
+class Shapes:
+    """N, L, K, W of one shaped decomposition (all 0-based)."""
+
+    def __init__(self, nx, ny, nset, li, lj, lxt, lyt, ki, kj, W):
+        self.nx, self.ny = nx, ny
+        self.nset = nset            # (nx, ny) uint8
+        self.li, self.lj = li, lj   # window cells, column-major order
+        self.lxt, self.lyt = lxt, lyt
+        self.ki, self.kj = ki, kj   # origins, column-major order
+        self.W = W                  # (nx, ny) float64 weights (counts)
+
+    @property
+    def L(self) -> int:
+        return len(self.li)
+
+    @property
+    def K(self) -> int:
+        return len(self.ki)
+
+    @property
+    def covered(self) -> np.ndarray:
+        return self.W > 0
+
+
+def shapes(x, mask=None, wmask=None, window=None) -> Shapes:
+    """N = mask & ~isnan(x); L = wmask trimmed; K by brute force; W by counting."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+    nx, ny = x.shape
+    lib_ = lib()
+    nset = np.zeros((nx, ny), np.uint8)
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    lib_.orc_nset(nx, ny, x, None if m is None else m.ctypes.data, nset)
+    if wmask is not None:
+        wm = np.ascontiguousarray(wmask, dtype=np.uint8)
+        if wm.ndim == 1:
+            wm = wm[:, None]
+        lx, ly = wm.shape
+        wptr = wm.ctypes.data
+    else:
+        if np.isscalar(window):
+            lx, ly = int(window), 1
+        else:
+            lx, ly = int(window[0]), int(window[1])
+        wm, wptr = None, None
+    li = np.zeros(lx * ly, np.int32)
+    lj = np.zeros(lx * ly, np.int32)
+    nl, lxt, lyt = C.c_int(), C.c_int(), C.c_int()
+    if lib_.orc_window(lx, ly, wptr, li, lj, C.byref(nl), C.byref(lxt), C.byref(lyt)) != 0:
+        raise ValueError("empty window")
+    li, lj = li[:nl.value].copy(), lj[:nl.value].copy()
+    kx, ky = nx - lxt.value + 1, ny - lyt.value + 1
+    if kx <= 0 or ky <= 0:
+        raise ValueError("window larger than the array")
+    ki = np.zeros(kx * ky, np.int32)
+    kj = np.zeros(kx * ky, np.int32)
+    nk = C.c_long()
+    lib_.orc_kset(nx, ny, nset, nl.value, li, lj, lxt.value, lyt.value, ki, kj, C.byref(nk))
+    ki, kj = ki[:nk.value].copy(), kj[:nk.value].copy()
+    W = np.zeros((nx, ny))
+    lib_.orc_weights(nx, ny, len(li), li, lj, len(ki), ki, kj, W)
+    return Shapes(nx, ny, nset, li, lj, lxt.value, lyt.value, ki, kj, W)
+
+
+def clean(x, sh: Shapes) -> np.ndarray:
+    """x with the cells outside N set to 0 (they never enter X)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+    return np.where(sh.nset.astype(bool), x, 0.0)
+
+
+def trajectory(x, sh: Shapes) -> np.ndarray:
+    """Explicit quasi-Hankel trajectory matrix, (L, K)."""
+    xc = clean(x, sh)
+    X = np.zeros((sh.L, sh.K))
+    lib().orc_trajectory(sh.nx, sh.ny, xc, sh.L, sh.li, sh.lj, sh.K, sh.ki, sh.kj, X)
+    return X
+
+
+def trajectory_mssa(series, L: int) -> np.ndarray:
+    """Explicit stacked Hankel matrix [T(x1):...:T(xs)], (L, sum K_p)."""
+    lens = np.array([len(s) for s in series], np.int32)
+    cat = np.ascontiguousarray(np.concatenate(series), dtype=np.float64)
+    K = int(np.sum(lens - L + 1))
+    X = np.zeros((L, K))
+    lib().orc_trajectory_mssa(len(series), lens, cat, L, X)
+    return X
+
+
+def matvec(x, sh: Shapes, v) -> np.ndarray:
+    """u = X v by explicit sums over the trajectory entries."""
+    xc = clean(x, sh)
+    u = np.zeros(sh.L)
+    lib().orc_matvec(sh.nx, sh.ny, xc, sh.L, sh.li, sh.lj, sh.K, sh.ki, sh.kj,
+                     np.ascontiguousarray(v, dtype=np.float64), u)
+    return u
+
+
+def rmatvec(x, sh: Shapes, u) -> np.ndarray:
+    """v = X^T u by explicit sums over the trajectory entries."""
+    xc = clean(x, sh)
+    v = np.zeros(sh.K)
+    lib().orc_rmatvec(sh.nx, sh.ny, xc, sh.L, sh.li, sh.lj, sh.K, sh.ki, sh.kj,
+                      np.ascontiguousarray(u, dtype=np.float64), v)
+    return v
+
+
+# --------------------------------------------------------------------------
+# SVD
+# --------------------------------------------------------------------------
+
+def svd(X, method: str = "jacobi", tol: float = 1e-14, max_sweeps: int = 100):
+    """All min(L, K) triplets of the explicit matrix X (L x K).
+
+    method "jacobi": one-sided Jacobi on the shorter dimension.
+    method "gram":   eigenpairs of S = X X^T, V_j = X^T U_j / sigma_j
+                     (the paper's statement of the SVD step).
+    Returns sigma (d,), U (L, d), V (K, d).
+    """
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    m, n = X.shape
+    d = min(m, n)
+    sig = np.zeros(d)
+    Ucm = np.zeros(m * d)
+    Vcm = np.zeros(n * d)
+    fn = lib().orc_svd_jacobi if method == "jacobi" else lib().orc_svd_gram
+    if method == "gram" and m > n:
+        # S = X X^T is the larger Gram; decompose X^T and swap roles
+        s, V, U = svd(X.T, "gram", tol, max_sweeps)
+        # keep the sign rule on U
+        for k in range(d):
+            a = int(np.argmax(np.abs(U[:, k])))
+            if U[a, k] < 0:
+                U[:, k] *= -1
+                V[:, k] *= -1
+        return s, U, V
+    sweeps = fn(m, n, X, tol, max_sweeps, sig, Ucm, Vcm)
+    if sweeps < 0:
+        raise RuntimeError("Jacobi iteration did not converge")
+    U = Ucm.reshape(d, m).T.copy()
+    V = Vcm.reshape(d, n).T.copy()
+    return sig, U, V
+
+
+def reconstruct(sh: Shapes, sigma, U, V, group) -> np.ndarray:
+    """Diagonal averaging of sum_{k in group} sigma_k U_k V_k^T; NaN off N'."""
+    out = np.zeros((sh.nx, sh.ny))
+    Ucm = np.ascontiguousarray(np.asarray(U, dtype=np.float64).T)
+    Vcm = np.ascontiguousarray(np.asarray(V, dtype=np.float64).T)
+    g = np.ascontiguousarray(group, dtype=np.int32)
+    lib().orc_reconstruct(sh.nx, sh.ny, sh.L, sh.li, sh.lj, sh.K, sh.ki, sh.kj, len(sigma),
+                          np.ascontiguousarray(sigma, dtype=np.float64), Ucm, Vcm, len(g), g, out)
+    return out
+
+
+def reconstruct_mssa(series_lens, L, sigma, U, V, group) -> list:
+    """MSSA diagonal averaging per series on the stacked Hankel matrix."""
+    lens = np.asarray(series_lens, np.int32)
+    out = np.zeros(int(lens.sum()))
+    Ucm = np.ascontiguousarray(np.asarray(U, dtype=np.float64).T)
+    Vcm = np.ascontiguousarray(np.asarray(V, dtype=np.float64).T)
+    g = np.ascontiguousarray(group, dtype=np.int32)
+    lib().orc_reconstruct_mssa(len(lens), lens, L, len(sigma),
+                               np.ascontiguousarray(sigma, dtype=np.float64), Ucm, Vcm, len(g), g, out)
+    return np.split(out, np.cumsum(lens)[:-1])
+
+
+# --------------------------------------------------------------------------
+# whole decompositions
+# --------------------------------------------------------------------------
+
+def decompose(x, mask=None, wmask=None, window=None, method: str = "jacobi"):
+    """Shaped decomposition: returns (Shapes, sigma, U, V) with all triplets."""
+    sh = shapes(x, mask, wmask, window)
+    if sh.K == 0:
+        raise ValueError("no window position fits")
+    X = trajectory(x, sh)
+    s, U, V = svd(X, method)
+    return sh, s, U, V
+
+
+def decompose_mssa(series, L: int, method: str = "jacobi"):
+    """MSSA decomposition on the stacked Hankel matrix: (sigma, U, V)."""
+    X = trajectory_mssa(series, L)
+    return svd(X, method)
+
+
+def grid(sh: Shapes, vec, which: str) -> np.ndarray:
+    """Place a compact vector on its (Lx, Ly) or (Kx, Ky) box, NaN elsewhere."""
+    if which == "L":
+        out = np.full((sh.lxt, sh.lyt), np.nan)
+        out[sh.li, sh.lj] = vec
+    else:
+        out = np.full((sh.nx - sh.lxt + 1, sh.ny - sh.lyt + 1), np.nan)
+        out[sh.ki, sh.kj] = vec
+    return out
