@@ -1,0 +1,164 @@
+/*
+ * shssa.h -- C ABI of the Shaped 2D-SSA library for MI355X (gfx950).
+ *
+ * The library decomposes a shaped array and reconstructs grouped components
+ * with singular spectrum analysis, as defined in Golyandina, Korobeynikov,
+ * Shlemov and Usevich, "Multivariate and 2D extensions of singular spectrum
+ * analysis with the Rssa package" (arXiv:1309.5050).  Shaped 2D-SSA (Section
+ * 5) covers 1D SSA (an N x 1 array with an L x 1 window), MSSA (Section 5.3,
+ * 2D packing: a max N_p x s array whose column p holds series p), 2D-SSA (a
+ * full rectangle) and shaped arrays with shaped windows.
+ *
+ * Conventions.
+ *   - Arrays are row-major; the first index is the x axis of the paper
+ *     (rows), the second the y axis (columns).  Indices are 0-based.
+ *   - N (the shaped array) = cells with mask != 0 (all cells if mask is
+ *     NULL) whose value is not NaN (Section 5.2: NA values and the mask
+ *     are intersected).
+ *   - The window shape L is the set of wmask cells != 0 (the full lx x ly
+ *     box if wmask is NULL), trimmed to its bounding box.  The origins are
+ *     K = { k : l + k lies in N for every l in L } (Section 5.1, equation
+ *     sh_Ks).  The trajectory matrix is X_ij = x(l_i + k_j) (equation qh_mat).
+ *   - Singular values are returned, not eigenvalues: sigma_i = sqrt(lambda_i)
+ *     of the SVD step (Section 2.1, Step 2), in descending order.
+ *   - Each triplet's sign is fixed so that the largest-magnitude entry of
+ *     U_i is positive.
+ *   - Component indices in groups are 0-based (the paper counts from 1).
+ *
+ * Ownership.  Input pointers are borrowed for the duration of the call.
+ * Output buffers are allocated by the caller (sizes from ssa_get_dims).
+ * Handles are owned by the library and released with ssa_free /
+ * ssa_ctx_destroy.  Functions ending in _dev take device pointers on the
+ * context's device and work on the context's stream; all others take host
+ * pointers and return after the work is complete.
+ *
+ * Errors.  Every int-returning function returns SSA_OK (0) or a negative
+ * code; ssa_strerror gives a message, ssa_last_error the detail of the last
+ * failure on the calling thread.
+ */
+#ifndef SHSSA_H
+#define SHSSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SSA_OK = 0,
+    SSA_EINVAL = -1,   /* bad sizes: window box beyond the array, L*K box of
+                          one cell, unsupported transform length, NULL input */
+    SSA_EEMPTY = -2,   /* no window position fits inside N (K is empty) */
+    SSA_ERANK = -3,    /* r < 1 or r >= min(|L|, |K|): the rank of X is at
+                          most min(L, K) (Section 2.1, Step 2) */
+    SSA_ENOMEM = -4,   /* device memory or the context's budget exhausted */
+    SSA_ENOCONV = -5,  /* the bidiagonalisation reached its step limit; the
+                          triplets are still returned */
+    SSA_EDEVICE = -6,  /* a HIP runtime call failed */
+    SSA_EBUSY = -7,    /* the request is not finished yet (serving) */
+    SSA_ESTATE = -8    /* call out of order (e.g. reconstruct before decompose) */
+};
+
+enum { SSA_FP64 = 0, SSA_FP32 = 1 };  /* FP32: FP32 FFT products, FP64 Lanczos */
+
+typedef struct ssa_ctx ssa_ctx;
+typedef struct ssa_decomp ssa_decomp;
+
+/* One decomposition request (image form).  A 1D series of length N is an
+ * N x 1 image with an L x 1 window (Section 5.3). */
+typedef struct ssa_request {
+    const double* x;        /* nx*ny values, NaN = missing (host or device) */
+    int nx, ny;
+    const uint8_t* mask;    /* nx*ny, nonzero = in the array; NULL = all */
+    const uint8_t* wmask;   /* lx*ly window shape; NULL = full lx x ly box */
+    int lx, ly;
+    int r;                  /* leading eigentriples wanted */
+    int precision;          /* SSA_FP64 or SSA_FP32 */
+    unsigned long long seed;/* start vector of the bidiagonalisation */
+} ssa_request;
+
+typedef struct ssa_stats {
+    int steps;              /* bidiagonalisation steps (two products each) */
+    int restarts;
+    int basis;              /* projected matrix size m */
+    int converged;          /* 1 if every triplet met the residual test */
+    int side;               /* 0: basis on the window side, 1: origin side */
+    double max_resid;       /* largest residual bound |X v - s u| / sigma_1 */
+    double ms_setup, ms_lanczos, ms_finish;
+    size_t device_bytes;    /* device memory held by the handle */
+} ssa_stats;
+
+/* Context: device, stream (hipStream_t, NULL = the library makes one) and a
+ * device-memory budget in bytes (0 = no limit). */
+int  ssa_ctx_create(int device, size_t mem_budget, void* stream, ssa_ctx** out);
+void ssa_ctx_destroy(ssa_ctx* ctx);
+int  ssa_ctx_set_stream(ssa_ctx* ctx, void* stream);
+
+/* Decompose one shaped array (host inputs).  See ssa_request for the
+ * arguments.  On success *out receives a handle holding sigma, U, V, the
+ * weights and the image spectrum on the device. */
+int ssa_decompose(ssa_ctx* ctx, const double* x, int nx, int ny, const uint8_t* mask,
+                  const uint8_t* wmask, int lx, int ly, int r, int precision, ssa_decomp** out);
+
+/* MSSA (Section 3.1, equation mssa_embedding) of s series of lengths len[p]
+ * with window L (1 < L < min len).  Internally the 2D packing of Section
+ * 5.3: a max(len) x s array, window L x 1.  Outputs use that packing:
+ * V is (max(len) - L + 1) x s with NaN beyond K_p, reconstructions
+ * max(len) x s with NaN beyond len[p]. */
+int ssa_decompose_multi(ssa_ctx* ctx, const double* const* series, const int* len, int s, int L,
+                        int r, int precision, ssa_decomp** out);
+
+/* Decompose n requests together: requests of equal geometry, rank and
+ * precision advance in one batch through the same kernels.  out[i] and
+ * status[i] receive each request's handle (or NULL) and code.  Returns
+ * SSA_OK if the batch ran (individual failures are in status). */
+int ssa_decompose_batch(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** out, int* status);
+
+/* As ssa_decompose_batch with x (and mask) as device pointers. */
+int ssa_decompose_batch_dev(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** out, int* status);
+
+/* Sizes: trimmed window box lx x ly, origin box kx x ky (= nx-lx+1 by
+ * ny-ly+1), |L|, |K|, r, and the array size nx x ny. */
+int ssa_get_dims(const ssa_decomp* d, int* lx, int* ly, int* kx, int* ky, long* L, long* K, int* r,
+                 int* nx, int* ny);
+
+int ssa_get_sigma(const ssa_decomp* d, double* sigma /* r */);
+
+/* U: r arrays of lx*ly (eigenarrays, NaN off L); V: r arrays of kx*ky
+ * (factor arrays, NaN off K); V may be NULL. */
+int ssa_get_vectors(const ssa_decomp* d, double* U, double* V);
+
+/* U: L x r and V: K x r column-major in the paper's lexicographic order of
+ * L and K (the order of the vectorised array: row index fastest). */
+int ssa_get_vectors_lex(const ssa_decomp* d, double* U, double* V);
+
+/* Weights w = |A_alpha| (Section 2.2), nx*ny; 0 outside N'. */
+int ssa_get_weights(const ssa_decomp* d, double* w);
+
+/* Reconstruction (Section 2.1, Step 4; Algorithms 4 and 5) of ngroups
+ * groups given in CSR form (grp_ptr[ngroups+1], grp_idx, 0-based component
+ * ids < r).  out: ngroups arrays of nx*ny, NaN outside N'. */
+int ssa_reconstruct(ssa_decomp* d, const int* grp_ptr, const int* grp_idx, int ngroups, double* out);
+
+/* Reconstruct the same groups for n handles of equal geometry in one batch.
+ * out_dev[i] is a device buffer of ngroups*nx*ny doubles with the layout of
+ * ssa_reconstruct.  Queued on the context's stream; returns without waiting. */
+int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* grp_ptr, const int* grp_idx,
+                              int ngroups, double* const* out_dev);
+
+int  ssa_get_stats(const ssa_decomp* d, ssa_stats* st);
+void ssa_free(ssa_decomp* d);
+
+const char* ssa_strerror(int code);
+const char* ssa_last_error(void);
+
+/* Blocks until all work queued on the context's stream is complete. */
+int ssa_ctx_sync(ssa_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHSSA_H */

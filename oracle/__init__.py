@@ -60,11 +60,14 @@ def lib():
         L.orc_rmatvec.argtypes = L.orc_matvec.argtypes
         L.orc_svd_jacobi.argtypes = [C.c_long, C.c_long, _d, C.c_double, C.c_int, _d, _d, _d]
         L.orc_svd_jacobi.restype = C.c_int
-        L.orc_svd_gram.argtypes = L.orc_svd_jacobi.argtypes
+        L.orc_svd_gram.argtypes = [C.c_long, C.c_long, _d, C.c_double, C.c_int, C.c_int, _d, _d, _d]
         L.orc_svd_gram.restype = C.c_int
         L.orc_reconstruct.argtypes = [C.c_int, C.c_int, C.c_int, _i, _i, C.c_long, _i, _i, C.c_int,
                                       _d, _d, _d, C.c_int, _i, _d]
         L.orc_reconstruct_mssa.argtypes = [C.c_int, _i, C.c_int, C.c_int, _d, _d, _d, C.c_int, _i, _d]
+        L.orc_reconstruct_at.argtypes = [C.c_int, _i, _i, C.c_int, C.c_int,
+                                         np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS"),
+                                         C.c_long, C.c_int, _d, _d, _d, C.c_int, _i, C.c_long, _i, _i, _d]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -191,12 +194,13 @@ def rmatvec(x, sh: Shapes, u) -> np.ndarray:
 # SVD
 # --------------------------------------------------------------------------
 
-def svd(X, method: str = "jacobi", tol: float = 1e-14, max_sweeps: int = 100):
+def svd(X, method: str = "jacobi", tol: float = 1e-14, max_sweeps: int = 100, nvec: int = -1):
     """All min(L, K) triplets of the explicit matrix X (L x K).
 
     method "jacobi": one-sided Jacobi on the shorter dimension.
     method "gram":   eigenpairs of S = X X^T, V_j = X^T U_j / sigma_j
-                     (the paper's statement of the SVD step).
+                     (the paper's statement of the SVD step); with nvec >= 0
+                     only the first nvec columns of V are formed (rest zero).
     Returns sigma (d,), U (L, d), V (K, d).
     """
     X = np.ascontiguousarray(X, dtype=np.float64)
@@ -216,7 +220,10 @@ def svd(X, method: str = "jacobi", tol: float = 1e-14, max_sweeps: int = 100):
                 U[:, k] *= -1
                 V[:, k] *= -1
         return s, U, V
-    sweeps = fn(m, n, X, tol, max_sweeps, sig, Ucm, Vcm)
+    if method == "gram":
+        sweeps = fn(m, n, X, tol, max_sweeps, nvec, sig, Ucm, Vcm)
+    else:
+        sweeps = fn(m, n, X, tol, max_sweeps, sig, Ucm, Vcm)
     if sweeps < 0:
         raise RuntimeError("Jacobi iteration did not converge")
     U = Ucm.reshape(d, m).T.copy()
@@ -251,20 +258,38 @@ def reconstruct_mssa(series_lens, L, sigma, U, V, group) -> list:
 # whole decompositions
 # --------------------------------------------------------------------------
 
-def decompose(x, mask=None, wmask=None, window=None, method: str = "jacobi"):
+def decompose(x, mask=None, wmask=None, window=None, method: str = "jacobi", nvec: int = -1):
     """Shaped decomposition: returns (Shapes, sigma, U, V) with all triplets."""
     sh = shapes(x, mask, wmask, window)
     if sh.K == 0:
         raise ValueError("no window position fits")
     X = trajectory(x, sh)
-    s, U, V = svd(X, method)
+    s, U, V = svd(X, method, nvec=nvec)
+    del X
     return sh, s, U, V
 
 
-def decompose_mssa(series, L: int, method: str = "jacobi"):
+def reconstruct_at(sh: Shapes, sigma, U, V, group, cells) -> np.ndarray:
+    """The group's diagonal average at the listed cells ((n, 2) int array)."""
+    kx, ky = sh.nx - sh.lxt + 1, sh.ny - sh.lyt + 1
+    korigin = np.full(kx * ky, -1, np.int64)
+    korigin[sh.ki.astype(np.int64) * ky + sh.kj] = np.arange(sh.K)
+    cells = np.asarray(cells, np.int32)
+    out = np.zeros(len(cells))
+    Ucm = np.ascontiguousarray(np.asarray(U, dtype=np.float64).T)
+    Vcm = np.ascontiguousarray(np.asarray(V, dtype=np.float64).T)
+    g = np.ascontiguousarray(group, dtype=np.int32)
+    lib().orc_reconstruct_at(sh.L, sh.li, sh.lj, kx, ky, korigin, sh.K, len(sigma),
+                             np.ascontiguousarray(sigma, dtype=np.float64), Ucm, Vcm, len(g), g,
+                             len(cells), np.ascontiguousarray(cells[:, 0]),
+                             np.ascontiguousarray(cells[:, 1]), out)
+    return out
+
+
+def decompose_mssa(series, L: int, method: str = "jacobi", nvec: int = -1):
     """MSSA decomposition on the stacked Hankel matrix: (sigma, U, V)."""
     X = trajectory_mssa(series, L)
-    return svd(X, method)
+    return svd(X, method, nvec=nvec)
 
 
 def grid(sh: Shapes, vec, which: str) -> np.ndarray:

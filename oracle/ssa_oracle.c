@@ -393,21 +393,33 @@ static int jacobi_eig(int n, double *S, double *lam, double *Z, double tol, int 
  * with lambda_j > 0; trailing ones are zero).  Used for the large workloads,
  * where the one-sided iteration over the long columns is too slow. */
 int orc_svd_gram(long m, long n, const double *X, double tol, int max_sweeps,
-                 double *sig, double *U, double *V)
+                 int nvec, double *sig, double *U, double *V)
 {
     int mm = (int)m;
-    double *S = (double *)malloc(sizeof(double) * m * m);
-    #pragma omp parallel for schedule(dynamic, 4)
-    for (int i = 0; i < mm; ++i)
-        for (int j = 0; j <= i; ++j) {
-            double s = dot(X + (long)i * n, X + (long)j * n, n);
-            S[(long)i * m + j] = s;
-            S[(long)j * m + i] = s;
+    double *S = (double *)calloc((size_t)m * m, sizeof(double));
+    /* S = X X^T, summed over column chunks so that a block of rows stays in
+     * cache; every entry is still the plain sum over all columns. */
+    const int RB = 32;
+    const long CB = 2048;
+    int nb = (mm + RB - 1) / RB;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < nb * nb; ++t) {
+        int bi = t / nb, bj = t % nb;
+        if (bj > bi) continue;
+        for (long c0 = 0; c0 < n; c0 += CB) {
+            long c1 = c0 + CB < n ? c0 + CB : n;
+            for (int i = bi * RB; i < (bi + 1) * RB && i < mm; ++i)
+                for (int j = bj * RB; j < (bj + 1) * RB && j <= i; ++j)
+                    S[(long)i * m + j] += dot(X + (long)i * n + c0, X + (long)j * n + c0, c1 - c0);
         }
+    }
+    for (int i = 0; i < mm; ++i)
+        for (int j = 0; j < i; ++j) S[(long)j * m + i] = S[(long)i * m + j];
     double *lam = (double *)malloc(sizeof(double) * m);
     double *Z = (double *)malloc(sizeof(double) * m * m);
     int sw = jacobi_eig(mm, S, lam, Z, tol, max_sweeps);
     int d = (int)(m < n ? m : n);
+    if (nvec < 0 || nvec > d) nvec = d;
     /* order by eigenvalue, keep d */
     int *perm = (int *)malloc(sizeof(int) * m);
     for (int k = 0; k < mm; ++k) perm[k] = k;
@@ -422,9 +434,11 @@ int orc_svd_gram(long m, long n, const double *X, double tol, int max_sweeps,
         sig[k] = sqrt(l);
         memcpy(U + (long)k * m, Z + (long)p * m, sizeof(double) * m);
     }
+    /* V_j = X^T U_j / sigma_j for the first nvec triplets (zero after) */
+    memset(V, 0, sizeof(double) * (size_t)n * d);
     #pragma omp parallel for schedule(static)
     for (long j = 0; j < n; ++j)
-        for (int k = 0; k < d; ++k) {
+        for (int k = 0; k < nvec; ++k) {
             double acc = 0.0;
             for (long i = 0; i < m; ++i) acc += X[i * n + j] * U[(long)k * m + i];
             V[(long)k * n + j] = sig[k] > 0 ? acc / sig[k] : 0.0;
@@ -495,6 +509,36 @@ void orc_reconstruct_mssa(int s, const int *lens, int L, int d, const double *si
         free(cnt);
         col += Kp;
         off += lens[p];
+    }
+}
+
+/* The same averaging evaluated only at the listed cells (pi[t], pj[t]):
+ * for each cell, visit every window cell l_i, take k = cell - l_i, and add
+ * Y_ij if k is an origin.  korigin maps a box position (kx-by-ky, row-major)
+ * to its index in the origin list, or -1. */
+void orc_reconstruct_at(int nl, const int *li, const int *lj, int kx, int ky,
+                        const long *korigin, long nk, int d, const double *sig,
+                        const double *U, const double *V, int gsize, const int *group,
+                        long npts, const int *pi, const int *pj, double *out)
+{
+    (void)d;
+    #pragma omp parallel for schedule(static)
+    for (long t = 0; t < npts; ++t) {
+        double acc = 0.0, cnt = 0.0;
+        for (int i = 0; i < nl; ++i) {
+            int a = pi[t] - li[i], b = pj[t] - lj[i];
+            if (a < 0 || b < 0 || a >= kx || b >= ky) continue;
+            long j = korigin[(long)a * ky + b];
+            if (j < 0) continue;
+            double y = 0.0;
+            for (int g = 0; g < gsize; ++g) {
+                int k = group[g];
+                y += sig[k] * U[(long)k * nl + i] * V[(long)k * nk + j];
+            }
+            acc += y;
+            cnt += 1.0;
+        }
+        out[t] = cnt > 0 ? acc / cnt : NAN;
     }
 }
 

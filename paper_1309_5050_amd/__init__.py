@@ -1,0 +1,216 @@
+"""Shaped 2D-SSA on MI355X: Python front end of the libshssa C ABI.
+
+Thin marshalling over the C library (include/shssa.h): every step of the
+decomposition and reconstruction runs in the library's HIP kernels.  PyTorch
+is used only for device buffers and streams in the ``*_dev`` helpers.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _native
+from ._native import SSA_FP32, SSA_FP64, SsaError, check, lib  # noqa: F401
+
+__all__ = ["Context", "Decomposition", "SSA_FP32", "SSA_FP64", "SsaError"]
+
+
+def _prec(p) -> int:
+    if p in (SSA_FP64, "fp64", "f64", "float64", np.float64):
+        return SSA_FP64
+    if p in (SSA_FP32, "fp32", "f32", "float32", np.float32):
+        return SSA_FP32
+    raise ValueError(f"unknown precision {p!r}")
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class Decomposition:
+    """Handle of one decomposition (sigma, U, V, weights held on the device)."""
+
+    def __init__(self, ctx: "Context", handle: int):
+        self.ctx = ctx
+        self._h = C.c_void_p(handle)
+        lx, ly, kx, ky, r, nx, ny = (C.c_int() for _ in range(7))
+        L, K = C.c_long(), C.c_long()
+        check(lib().ssa_get_dims(self._h, C.byref(lx), C.byref(ly), C.byref(kx), C.byref(ky), C.byref(L),
+                                 C.byref(K), C.byref(r), C.byref(nx), C.byref(ny)), "ssa_get_dims")
+        self.window_box = (lx.value, ly.value)
+        self.origin_box = (kx.value, ky.value)
+        self.L, self.K, self.r = L.value, K.value, r.value
+        self.shape = (nx.value, ny.value)
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ssa_free(self._h)
+            self._h = C.c_void_p(0)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def sigma(self) -> np.ndarray:
+        s = np.zeros(self.r)
+        check(lib().ssa_get_sigma(self._h, _ptr(s)), "ssa_get_sigma")
+        return s
+
+    def vectors(self):
+        """(U, V): r eigenarrays on the window box and r factor arrays on the
+        origin box, NaN outside the window shape / origin set."""
+        U = np.zeros((self.r,) + self.window_box)
+        V = np.zeros((self.r,) + self.origin_box)
+        check(lib().ssa_get_vectors(self._h, _ptr(U), _ptr(V)), "ssa_get_vectors")
+        return U, V
+
+    def vectors_lex(self):
+        """(U, V) as (L, r) and (K, r) columns in the paper's lexicographic order."""
+        U = np.zeros(self.r * self.L)
+        V = np.zeros(self.r * self.K)
+        check(lib().ssa_get_vectors_lex(self._h, _ptr(U), _ptr(V)), "ssa_get_vectors_lex")
+        return U.reshape(self.r, self.L).T.copy(), V.reshape(self.r, self.K).T.copy()
+
+    @property
+    def weights(self) -> np.ndarray:
+        w = np.zeros(self.shape)
+        check(lib().ssa_get_weights(self._h, _ptr(w)), "ssa_get_weights")
+        return w
+
+    @property
+    def stats(self) -> dict:
+        st = _native.Stats()
+        check(lib().ssa_get_stats(self._h, C.byref(st)), "ssa_get_stats")
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def reconstruct(self, groups) -> np.ndarray:
+        """Reconstruct each group (list of 0-based component ids); returns
+        (ngroups, nx, ny) with NaN outside the covered cells."""
+        gp = np.zeros(len(groups) + 1, np.int32)
+        gp[1:] = np.cumsum([len(g) for g in groups])
+        gi = np.ascontiguousarray(np.concatenate([np.asarray(g, np.int32) for g in groups]))
+        out = np.zeros((len(groups),) + self.shape)
+        check(lib().ssa_reconstruct(self._h, _ptr(gp), _ptr(gi), len(groups), _ptr(out)), "ssa_reconstruct")
+        return out
+
+
+class Context:
+    """A device, a stream and a memory budget for decompositions."""
+
+    def __init__(self, device: int = 0, mem_budget: int = 0, stream=None):
+        h = C.c_void_p()
+        check(lib().ssa_ctx_create(device, mem_budget, stream, C.byref(h)), "ssa_ctx_create")
+        self._h = h
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ssa_ctx_destroy(self._h)
+            self._h = C.c_void_p(0)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sync(self):
+        check(lib().ssa_ctx_sync(self._h), "ssa_ctx_sync")
+
+    def set_stream(self, stream):
+        check(lib().ssa_ctx_set_stream(self._h, stream), "ssa_ctx_set_stream")
+
+    # ---- decomposition -------------------------------------------------
+
+    @staticmethod
+    def _image_args(x, window, mask, wmask):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        if x.ndim == 1:
+            x = x[:, None]
+        if wmask is not None:
+            wmask = np.ascontiguousarray(wmask, dtype=np.uint8)
+            if wmask.ndim == 1:
+                wmask = wmask[:, None]
+            lx, ly = wmask.shape
+        elif np.isscalar(window):
+            lx, ly = int(window), 1
+        else:
+            lx, ly = int(window[0]), int(window[1])
+        if mask is not None:
+            mask = np.ascontiguousarray(mask, dtype=np.uint8).reshape(x.shape)
+        return x, lx, ly, mask, wmask
+
+    def decompose(self, x, window=None, r: int = 10, mask=None, wmask=None, precision="fp64") -> Decomposition:
+        """Shaped decomposition of an image (or a series given as 1-D)."""
+        x, lx, ly, mask, wmask = self._image_args(x, window, mask, wmask)
+        h = C.c_void_p()
+        check(lib().ssa_decompose(self._h, _ptr(x), x.shape[0], x.shape[1], _ptr(mask), _ptr(wmask), lx, ly, r,
+                                  _prec(precision), C.byref(h)), "ssa_decompose")
+        return Decomposition(self, h.value)
+
+    def decompose_multi(self, series, L: int, r: int, precision="fp64") -> Decomposition:
+        """MSSA of uneven series (2D packing: outputs are max N_p x s arrays)."""
+        arrs = [np.ascontiguousarray(s, dtype=np.float64) for s in series]
+        ptrs = (C.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+        lens = np.array([len(a) for a in arrs], np.int32)
+        h = C.c_void_p()
+        check(lib().ssa_decompose_multi(self._h, ptrs, _ptr(lens), len(arrs), L, r, _prec(precision),
+                                        C.byref(h)), "ssa_decompose_multi")
+        return Decomposition(self, h.value)
+
+    def decompose_batch(self, requests, precision="fp64", seed: int = 0x5EED):
+        """Decompose a list of dicts {x, window, r, mask?, wmask?} in batches
+        of equal geometry.  Returns a list of Decomposition (or SsaError)."""
+        keep = []
+        reqs = (_native.Request * len(requests))()
+        for i, rq in enumerate(requests):
+            x, lx, ly, mask, wmask = self._image_args(rq["x"], rq.get("window"), rq.get("mask"), rq.get("wmask"))
+            keep.append((x, mask, wmask))
+            reqs[i] = _native.Request(x.ctypes.data, x.shape[0], x.shape[1], _ptr(mask), _ptr(wmask), lx, ly,
+                                      int(rq["r"]), _prec(rq.get("precision", precision)), seed)
+        return self._run_batch(reqs, len(requests), dev=False)
+
+    def _run_batch(self, reqs, n, dev):
+        out = (C.c_void_p * n)()
+        st = (C.c_int * n)()
+        fn = lib().ssa_decompose_batch_dev if dev else lib().ssa_decompose_batch
+        check(fn(self._h, n, reqs, out, st), "ssa_decompose_batch")
+        res = []
+        for i in range(n):
+            if out[i]:
+                d = Decomposition(self, out[i])
+                d.status = st[i]
+                res.append(d)
+            else:
+                res.append(SsaError(st[i], f"request {i}"))
+        return res
+
+    def decompose_batch_dev(self, xs, window, r: int, precision="fp64", seed: int = 0x5EED, masks=None):
+        """Batch of device-resident images: ``xs`` are CUDA float64 tensors
+        (nx, ny) on this context's device."""
+        n = len(xs)
+        reqs = (_native.Request * n)()
+        lx, ly = (int(window), 1) if np.isscalar(window) else (int(window[0]), int(window[1]))
+        for i, x in enumerate(xs):
+            nx, ny = (x.shape[0], 1) if x.dim() == 1 else (x.shape[0], x.shape[1])
+            m = None if masks is None else masks[i].data_ptr()
+            reqs[i] = _native.Request(x.data_ptr(), nx, ny, m, None, lx, ly, r, _prec(precision), seed)
+        return self._run_batch(reqs, n, dev=True)
+
+    @staticmethod
+    def reconstruct_batch_dev(decomps, groups, outs):
+        """Reconstruct the same groups of several decompositions into CUDA
+        float64 tensors outs[i] of shape (ngroups, nx, ny); asynchronous."""
+        n = len(decomps)
+        gp = np.zeros(len(groups) + 1, np.int32)
+        gp[1:] = np.cumsum([len(g) for g in groups])
+        gi = np.ascontiguousarray(np.concatenate([np.asarray(g, np.int32) for g in groups]))
+        hs = (C.c_void_p * n)(*[d.handle.value for d in decomps])
+        ptrs = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        check(lib().ssa_reconstruct_batch_dev(n, hs, _ptr(gp), _ptr(gi), len(groups), ptrs),
+              "ssa_reconstruct_batch_dev")

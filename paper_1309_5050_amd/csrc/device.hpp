@@ -1,0 +1,146 @@
+// Device-visible per-instance descriptors and launch arguments.
+#pragma once
+#include "common.hpp"
+
+namespace shssa {
+
+// Maximum Lanczos basis (projected matrix held in LDS as m x m doubles).
+constexpr int kMaxBasis = 128;
+// Rows per Lanczos row block.
+constexpr int kLzRows = 256;
+
+// Geometry, spectrum and scratch of one decomposition.
+struct OpDesc {
+    int A, B;           // grid rows / columns (internal orientation)
+    int MA, MB;         // FFT lengths (MA = 1 for the row family)
+    int P;              // complex row pitch of row spectra (MB/2 + 1)
+    int rowfam;         // 1: window one row high
+    CellSet S[2];       // S[0] window cells (L), S[1] origins (K)
+    FftPlan prow;       // complex transform of length MB/2 (+ real split twiddles)
+    FftPlan pcol;       // complex transform of length MA (grid family)
+    const void* Xh;     // spectrum, pre-scaled: grid [P][MA], row family [A][P]
+    void* T1;           // scratch rows [nrows][P] per component slot
+    void* T2;
+    void* Us;           // stored spectra of U components (reconstruction)
+    long tslot;         // complex elements per component slot in T1/T2
+    long uslot;         // complex elements per component in Us
+    const double* W;    // weights, A*B
+    const double* xc;   // image with cells outside N zeroed, A*B (FP64)
+    const uint8_t* nset;// A*B bytes
+};
+
+// Golub-Kahan bidiagonalisation state of one decomposition.  The short side
+// (window set or origin set, whichever is smaller) keeps a full FP64 basis
+// with classical Gram-Schmidt applied twice; the long side keeps only the
+// last two (unnormalised) vectors, in the precision of the operator.
+struct LzDesc {
+    int side;           // short side: 0 = window set, 1 = origin set
+    int active;
+    int r;              // triplets wanted
+    double tol;         // stop when beta |q_i[m-1]| <= tol * sigma_1 for i < r
+    long n;             // short vector length
+    long nl;            // long vector length
+    double* Q;          // short basis n x (kMaxBasis+1), column-major (ld n)
+    double* w;          // short work vector
+    double* sin;        // modified input vector of the first step after a restart
+    double* hp1;        // partial projections, nblk x (kMaxBasis+1)
+    double* hp2;
+    double* np;         // partial squared norms of w, nblk
+    void* lbuf[2];      // long vectors (operator precision), ping-pong by step parity
+    double* lnp[2];     // partial squared norms of the long vectors, per long-set row
+    double* Bm;         // projected matrix, kMaxBasis x kMaxBasis column-major (rows: short)
+    double* Yl;         // left singular vectors of Bm (kMaxBasis ld)
+    double* Yr;         // right singular vectors of Bm
+    double* sig;        // singular values of Bm, descending
+    int* perm;          // column order of the descending singular values
+    double* beta;       // [0] residual norm after the last step, [1] worst residual / sigma_1
+    int* flag;          // [0] converged, [1] sweeps of the last small SVD
+    double* Qtmp;       // n x kMaxBasis (Ritz rotation target)
+    int nblk;
+};
+
+// Final results of one decomposition (compact FP64 vectors).
+struct ResDesc {
+    double* U;          // L x r column-major (ld = L)
+    double* V;          // K x r column-major (ld = K)
+    double* sigma;      // r
+    double* recon;      // ngroups x A x B
+    const int* gptr;    // ngroups+1
+    const int* gidx;
+};
+
+struct Item { int inst; int idx; int comp; int aux; };
+
+// ---- kernel arguments
+
+enum InMode : int {
+    IN_LZ_NORM = 0,   // src = w / beta_{j-1}; stores q_j and B[j][j-1] = beta_{j-1}
+    IN_LZ_PLAIN = 1,  // src = q_j
+    IN_VEC = 2,       // src = result vector (U or V) component `comp`, times scale
+    IN_DENSE = 3,     // src = dense image row (spectrum creation)
+    IN_LZ_SIN = 4,    // src = modified input of the first step after a restart
+};
+
+enum RowDest : int {
+    DEST_T1 = 0,      // scratch slot `comp` of T1
+    DEST_XH = 1,      // spectrum rows (row family), times the spectrum scale
+};
+
+struct RowInArgs {
+    int mode, set, j, dest;
+    double scale;     // IN_VEC: multiply by scale * sigma[comp] if use_sigma
+    int use_sigma;
+    void* xh_out;     // DEST_XH target
+};
+
+enum OutMode : int {
+    OUT_NONE = 0,
+    OUT_LZ = 1,      // compact values -> Lanczos w
+    OUT_VEC = 2,     // compact values -> result vector component `comp`, times scale / sigma
+    OUT_IMAGE = 3,   // dense row / W, NaN where W == 0 -> reconstruction `comp`
+};
+
+struct RowMidArgs {
+    int set;          // mask set applied between the two transforms
+    int emit;         // OUT_NONE or OUT_VEC (values of the masked row)
+    double scale;     // emitted value = scale * value / sigma[comp] (if div_sigma)
+    int div_sigma;
+    int fwd;          // 1: transform the masked row forward again into T1
+    int gk;           // 1: bidiagonalisation step j: l' = X^T q - gamma l'_{j-1}
+    int j, jstart;
+};
+
+struct RowOutArgs {
+    int mode;         // OUT_LZ, OUT_VEC or OUT_IMAGE
+    int set;
+    double scale;
+    int div_sigma;
+    int j;            // OUT_LZ: bidiagonalisation step
+};
+
+struct RowFamArgs {
+    int emit;         // OUT_VEC: emit masked values of X^T u (V side) / sigma
+    int full;         // 1: go on to P_a = Xh_a conj(FFT(masked row))
+    int gk;           // 1: bidiagonalisation step (long update as in k_row_mid)
+    int j, jstart;
+};
+
+enum ColMode : int {
+    COL_CORR = 0,     // fwd, * conj against Xh, inverse
+    COL_SPEC = 1,     // fwd only, * scale, store transposed as the spectrum
+    COL_STORE = 2,    // fwd only, store transposed into Us slot comp
+    COL_ACCUM = 3,    // for i in group comp: fwd of T1 slot i, * Us_i, summed; inverse
+};
+
+struct ColArgs {
+    int mode;
+    int nin;          // nonzero input rows
+    int nout;         // output rows written to T2
+    double scale;
+    void* xh_out;     // COL_SPEC target
+};
+
+// Window rows as runs: run t covers window row ra[t], columns [b0[t], b1[t]).
+struct Runs { const int* ra; const int* b0; const int* b1; int nrun; long total; };
+
+}  // namespace shssa

@@ -1,0 +1,1219 @@
+// Host engine and C ABI of the Shaped 2D-SSA library.
+//
+// A request is validated and mapped to an internal grid (see common.hpp),
+// then requests of equal geometry, rank and precision run as one batch:
+// every kernel launch covers all instances of the batch, which advance in
+// lockstep through the bidiagonalisation cycles (instances that converge
+// drop out at the next cycle boundary).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/shssa.h"
+#include "common.hpp"
+#include "device.hpp"
+#include "launch.hpp"
+
+using namespace shssa;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                                  \
+    do {                                                                                              \
+        hipError_t e_ = (call);                                                                       \
+        if (e_ != hipSuccess) return fail(SSA_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+using Clock = std::chrono::steady_clock;
+double ms_since(Clock::time_point t) {
+    return std::chrono::duration<double, std::milli>(Clock::now() - t).count();
+}
+
+int next_smooth(int n) {
+    for (int m = std::max(n, 1);; ++m) {
+        int t = m;
+        for (int p : {2, 3, 5, 7})
+            while (t % p == 0) t /= p;
+        if (t == 1) return m;
+    }
+}
+
+bool make_plan(int n, FftPlan& pl) {
+    pl.n = n;
+    pl.npass = 0;
+    int t = n;
+    auto take = [&](int r) {
+        while (t % r == 0 && pl.npass < kMaxPass) {
+            pl.radix[pl.npass++] = (int8_t)r;
+            t /= r;
+        }
+    };
+    take(8); take(4); take(2); take(3); take(5); take(7);
+    return t == 1;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+struct ssa_ctx {
+    int device = 0;
+    hipStream_t st = nullptr;
+    bool own = false;
+    size_t budget = 0;
+    size_t used = 0;
+    std::mutex mu;
+    std::map<std::tuple<int, int, int>, void*> tw;   // (n, f64, real split) -> table
+
+    // twiddles exp(-2 pi i t / N) for t = 0..cnt-1 (N = n, or 2n for the split)
+    int twiddles(int n, bool f64, bool split, const void** out) {
+        auto key = std::make_tuple(n, (int)f64, (int)split);
+        auto it = tw.find(key);
+        if (it != tw.end()) {
+            *out = it->second;
+            return SSA_OK;
+        }
+        const int cnt = split ? n + 1 : n;
+        const long double N = split ? 2.0L * n : (long double)n;
+        std::vector<double> d(2 * (size_t)cnt);
+        for (int t = 0; t < cnt; ++t) {
+            const long double a = -2.0L * 3.14159265358979323846264338327950288L * t / N;
+            d[2 * t] = (double)cosl(a);
+            d[2 * t + 1] = (double)sinl(a);
+        }
+        void* p = nullptr;
+        const size_t bytes = (size_t)cnt * (f64 ? 16 : 8);
+        HIPCHK(hipMalloc(&p, bytes));
+        if (f64) {
+            HIPCHK(hipMemcpy(p, d.data(), bytes, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> f(d.begin(), d.end());
+            HIPCHK(hipMemcpy(p, f.data(), bytes, hipMemcpyHostToDevice));
+        }
+        tw[key] = p;
+        *out = p;
+        return SSA_OK;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// one decomposition
+// ---------------------------------------------------------------------------
+
+struct ssa_decomp {
+    ssa_ctx* ctx = nullptr;
+    // caller geometry
+    int nx = 0, ny = 0, lx = 0, ly = 0, kx = 0, ky = 0;
+    bool tr = false;                 // internal grid is the transpose
+    // internal geometry
+    int A = 0, B = 0, LA = 0, LB = 0, KA = 0, KB = 0, MA = 1, MB = 0, nh = 0, P = 0;
+    bool rowfam = false, f64 = true;
+    int r = 0;
+    unsigned long long seed = 0;
+    long L = 0, K = 0;
+    int side = 0;
+    long nshort = 0, nlong = 0;
+    int status = SSA_OK;
+    bool decomposed = false;
+    std::vector<uint8_t> lmask_h;    // internal LA x LB
+    std::vector<int> lrow_h;         // LA + 1
+    std::vector<int> ra, rb0, rb1;   // window runs (internal)
+    std::vector<uint8_t> kmask_h;    // internal KA x KB (fetched on demand)
+    std::vector<double> sigma_h;
+    // device memory
+    std::vector<void*> allocs;
+    size_t bytes = 0;
+    double *x = nullptr, *xc = nullptr, *W = nullptr;
+    uint8_t *mask = nullptr, *nset = nullptr, *kmask = nullptr, *lmask = nullptr;
+    int *npref = nullptr, *kpref = nullptr, *kcount = nullptr, *krow = nullptr, *lrow = nullptr, *runs = nullptr;
+    void *Xh = nullptr, *T1 = nullptr, *T2 = nullptr, *Us = nullptr;
+    long tslot = 0, uslot = 0;
+    double *Q = nullptr, *w = nullptr, *sinv = nullptr, *hp1 = nullptr, *hp2 = nullptr, *np = nullptr;
+    double *lnp = nullptr, *Bm = nullptr, *Yl = nullptr, *Yr = nullptr, *sig = nullptr, *beta = nullptr;
+    double* Qtmp = nullptr;
+    void* lbuf = nullptr;
+    int *perm = nullptr, *flag = nullptr;
+    double *U = nullptr, *V = nullptr, *sigma = nullptr;
+    OpDesc op{};
+    LzDesc lz{};
+    ResDesc rs{};
+    Runs rn{};
+    ssa_stats st{};
+
+    ~ssa_decomp() {
+        for (void* p : allocs) (void)hipFree(p);
+        if (ctx) {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            ctx->used -= std::min(ctx->used, bytes);
+        }
+    }
+
+    template <typename T>
+    int dalloc(T** p, size_t count) {
+        const size_t b = std::max<size_t>(count, 1) * sizeof(T);
+        {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            if (ctx->budget && ctx->used + b > ctx->budget)
+                return fail(SSA_ENOMEM, "device memory budget exhausted");
+            ctx->used += b;
+        }
+        void* q = nullptr;
+        if (hipMalloc(&q, b) != hipSuccess) {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            ctx->used -= b;
+            return fail(SSA_ENOMEM, "hipMalloc failed");
+        }
+        allocs.push_back(q);
+        bytes += b;
+        *p = static_cast<T*>(q);
+        return SSA_OK;
+    }
+
+    size_t celem() const { return f64 ? 16 : 8; }
+};
+
+namespace {
+
+// Validate a request and compute the internal geometry (host side only).
+int plan_request(ssa_ctx* ctx, const ssa_request& q, ssa_decomp* d) {
+    if (q.nx <= 0 || q.ny <= 0 || q.lx <= 0 || q.ly <= 0) return fail(SSA_EINVAL, "sizes must be positive");
+    if (!q.x) return fail(SSA_EINVAL, "x is NULL");
+    if (q.precision != SSA_FP64 && q.precision != SSA_FP32) return fail(SSA_EINVAL, "unknown precision");
+    d->ctx = ctx;
+    d->nx = q.nx;
+    d->ny = q.ny;
+    d->r = q.r;
+    d->seed = q.seed;
+    d->f64 = q.precision == SSA_FP64;
+    // window: trim to the bounding box
+    int i0 = q.lx, i1 = -1, j0 = q.ly, j1 = -1;
+    for (int i = 0; i < q.lx; ++i)
+        for (int j = 0; j < q.ly; ++j)
+            if (!q.wmask || q.wmask[(long)i * q.ly + j]) {
+                i0 = std::min(i0, i); i1 = std::max(i1, i);
+                j0 = std::min(j0, j); j1 = std::max(j1, j);
+            }
+    if (i1 < 0) return fail(SSA_EINVAL, "empty window");
+    d->lx = i1 - i0 + 1;
+    d->ly = j1 - j0 + 1;
+    if (d->lx > q.nx || d->ly > q.ny) return fail(SSA_EINVAL, "window box exceeds the array");
+    if ((long)d->lx * d->ly <= 1 || (long)d->lx * d->ly >= (long)q.nx * q.ny)
+        return fail(SSA_EINVAL, "window box must satisfy 1 < Lx*Ly < Nx*Ny");
+    d->kx = q.nx - d->lx + 1;
+    d->ky = q.ny - d->ly + 1;
+    // orientation: a window one column wide is turned into one row high so
+    // that the cross-row part of the product is a plain sum.
+    d->tr = d->ly == 1 && d->lx > 1;
+    d->A = d->tr ? q.ny : q.nx;
+    d->B = d->tr ? q.nx : q.ny;
+    d->LA = d->tr ? d->ly : d->lx;
+    d->LB = d->tr ? d->lx : d->ly;
+    d->KA = d->A - d->LA + 1;
+    d->KB = d->B - d->LB + 1;
+    d->rowfam = d->LA == 1;
+    // window mask in the internal orientation, row offsets and runs
+    d->lmask_h.assign((size_t)d->LA * d->LB, 0);
+    for (int i = 0; i < d->lx; ++i)
+        for (int j = 0; j < d->ly; ++j) {
+            const bool in = !q.wmask || q.wmask[(long)(i + i0) * q.ly + (j + j0)];
+            const int a = d->tr ? j : i, b = d->tr ? i : j;
+            d->lmask_h[(size_t)a * d->LB + b] = in;
+        }
+    d->lrow_h.assign(d->LA + 1, 0);
+    d->ra.clear(); d->rb0.clear(); d->rb1.clear();
+    for (int a = 0; a < d->LA; ++a) {
+        int cnt = 0;
+        for (int b = 0; b < d->LB;) {
+            if (!d->lmask_h[(size_t)a * d->LB + b]) { ++b; continue; }
+            int e = b;
+            while (e < d->LB && d->lmask_h[(size_t)a * d->LB + e]) ++e;
+            d->ra.push_back(a); d->rb0.push_back(b); d->rb1.push_back(e);
+            cnt += e - b;
+            b = e;
+        }
+        d->lrow_h[a + 1] = d->lrow_h[a] + cnt;
+    }
+    d->L = d->lrow_h[d->LA];
+    // transform sizes
+    d->nh = next_smooth((d->B + 1) / 2);
+    d->MB = 2 * d->nh;
+    d->P = d->nh + 1;
+    if (row_class(d->nh, d->f64) < 0) return fail(SSA_EINVAL, "row length beyond the supported transform size");
+    if (!d->rowfam) {
+        d->MA = next_smooth(d->A);
+        if (d->MA > 1024) return fail(SSA_EINVAL, "column length beyond the supported transform size (1024)");
+    } else {
+        d->MA = 1;
+    }
+    if (q.r < 1) return fail(SSA_ERANK, "r must be >= 1");
+    return SSA_OK;
+}
+
+// Upload the request's data in the internal orientation.
+int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStream_t st) {
+    const long n = (long)d->A * d->B;
+    int rc;
+    if ((rc = d->dalloc(&d->x, n))) return rc;
+    if (q.mask && (rc = d->dalloc(&d->mask, n))) return rc;
+    if (dev_input) {
+        if (!d->tr || d->nx == 1 || d->ny == 1) {
+            HIPCHK(hipMemcpyAsync(d->x, q.x, n * 8, hipMemcpyDeviceToDevice, st));
+        } else {
+            launch_transpose(1, d->nx, d->ny, st, q.x, d->x);
+        }
+        if (q.mask) {
+            if (d->tr && d->nx > 1 && d->ny > 1) {
+                std::vector<uint8_t> hm(n), tm(n);
+                HIPCHK(hipMemcpy(hm.data(), q.mask, n, hipMemcpyDeviceToHost));
+                for (int i = 0; i < d->nx; ++i)
+                    for (int j = 0; j < d->ny; ++j) tm[(size_t)j * d->nx + i] = hm[(size_t)i * d->ny + j];
+                HIPCHK(hipMemcpy(d->mask, tm.data(), n, hipMemcpyHostToDevice));
+            } else {
+                HIPCHK(hipMemcpyAsync(d->mask, q.mask, n, hipMemcpyDeviceToDevice, st));
+            }
+        }
+    } else {
+        if (!d->tr) {
+            HIPCHK(hipMemcpy(d->x, q.x, n * 8, hipMemcpyHostToDevice));
+            if (q.mask) HIPCHK(hipMemcpy(d->mask, q.mask, n, hipMemcpyHostToDevice));
+        } else {
+            std::vector<double> tx(n);
+            for (int i = 0; i < d->nx; ++i)
+                for (int j = 0; j < d->ny; ++j) tx[(size_t)j * d->nx + i] = q.x[(size_t)i * d->ny + j];
+            HIPCHK(hipMemcpy(d->x, tx.data(), n * 8, hipMemcpyHostToDevice));
+            if (q.mask) {
+                std::vector<uint8_t> tm(n);
+                for (int i = 0; i < d->nx; ++i)
+                    for (int j = 0; j < d->ny; ++j) tm[(size_t)j * d->nx + i] = q.mask[(size_t)i * d->ny + j];
+                HIPCHK(hipMemcpy(d->mask, tm.data(), n, hipMemcpyHostToDevice));
+            }
+        }
+    }
+    // shape buffers
+    if ((rc = d->dalloc(&d->nset, n))) return rc;
+    if ((rc = d->dalloc(&d->xc, n))) return rc;
+    if ((rc = d->dalloc(&d->npref, (long)d->A * (d->B + 1)))) return rc;
+    if ((rc = d->dalloc(&d->kmask, (long)d->KA * d->KB))) return rc;
+    if ((rc = d->dalloc(&d->kpref, (long)d->KA * (d->KB + 1)))) return rc;
+    if ((rc = d->dalloc(&d->kcount, d->KA))) return rc;
+    if ((rc = d->dalloc(&d->krow, d->KA + 1))) return rc;
+    if ((rc = d->dalloc(&d->W, n))) return rc;
+    const bool lfull = d->L == (long)d->LA * d->LB;
+    if (!lfull && (rc = d->dalloc(&d->lmask, (long)d->LA * d->LB))) return rc;
+    if ((rc = d->dalloc(&d->lrow, d->LA + 1))) return rc;
+    const int nrun = (int)d->ra.size();
+    if ((rc = d->dalloc(&d->runs, 3 * (long)nrun))) return rc;
+    if (!lfull) HIPCHK(hipMemcpy(d->lmask, d->lmask_h.data(), d->lmask_h.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d->lrow, d->lrow_h.data(), (d->LA + 1) * sizeof(int), hipMemcpyHostToDevice));
+    std::vector<int> rr;
+    rr.insert(rr.end(), d->ra.begin(), d->ra.end());
+    rr.insert(rr.end(), d->rb0.begin(), d->rb0.end());
+    rr.insert(rr.end(), d->rb1.begin(), d->rb1.end());
+    HIPCHK(hipMemcpy(d->runs, rr.data(), rr.size() * sizeof(int), hipMemcpyHostToDevice));
+    d->rn = Runs{d->runs, d->runs + nrun, d->runs + 2 * nrun, nrun, d->L};
+    // descriptor (K set filled after the origin count)
+    OpDesc& o = d->op;
+    o.A = d->A; o.B = d->B; o.MA = d->MA; o.MB = d->MB; o.P = d->P;
+    o.rowfam = d->rowfam;
+    o.S[0] = CellSet{d->LA, d->LB, d->L, lfull ? nullptr : d->lmask, d->lrow};
+    o.S[1] = CellSet{d->KA, d->KB, 0, d->kmask, d->krow};
+    o.W = d->W;
+    o.xc = d->xc;
+    o.nset = d->nset;
+    return SSA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+
+struct DevVec {
+    void* p = nullptr;
+    size_t cap = 0;
+    ~DevVec() { if (p) (void)hipFree(p); }
+    template <typename T>
+    int put(const std::vector<T>& v, hipStream_t st) {
+        const size_t b = std::max<size_t>(v.size(), 1) * sizeof(T);
+        if (b > cap) {
+            if (p) (void)hipFree(p);
+            p = nullptr;
+            if (hipMalloc(&p, b) != hipSuccess) return fail(SSA_ENOMEM, "hipMalloc (batch tables)");
+            cap = b;
+        }
+        if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+        return SSA_OK;
+    }
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct ItemList {
+    std::vector<Item> h;
+    DevVec d;
+    int n() const { return (int)h.size(); }
+    const Item* ptr() const { return d.as<Item>(); }
+    int upload(hipStream_t st) { return d.put(h, st); }
+};
+
+struct Batch {
+    ssa_ctx* ctx;
+    hipStream_t st;
+    std::vector<ssa_decomp*> ds;      // instance i = ds[i]
+    bool f64 = true, rowfam = false;
+    int cls = 0, TC = 16;
+    DevVec dops, dlz, dres, druns;
+    std::vector<OpDesc> hops;
+    std::vector<LzDesc> hlz;
+    std::vector<ResDesc> hres;
+    std::vector<Runs> hruns;
+    // per-batch scratch for flags and stats
+    DevVec dflag, dbeta;
+
+    explicit Batch(ssa_ctx* c) : ctx(c), st(c->st) {}
+
+    int upload_descs() {
+        hops.clear(); hlz.clear(); hres.clear(); hruns.clear();
+        for (auto* d : ds) {
+            hops.push_back(d->op);
+            hlz.push_back(d->lz);
+            hres.push_back(d->rs);
+            hruns.push_back(d->rn);
+        }
+        int rc;
+        if ((rc = dops.put(hops, st))) return rc;
+        if ((rc = dlz.put(hlz, st))) return rc;
+        if ((rc = dres.put(hres, st))) return rc;
+        if ((rc = druns.put(hruns, st))) return rc;
+        return SSA_OK;
+    }
+    const OpDesc* ops() const { return dops.as<OpDesc>(); }
+    const LzDesc* lzs() const { return dlz.as<LzDesc>(); }
+    const ResDesc* res() const { return dres.as<ResDesc>(); }
+    const Runs* runs() const { return druns.as<Runs>(); }
+};
+
+// rows [0, nrows) of every listed instance, optional component range
+void rows_items(ItemList& L, const std::vector<int>& inst, std::function<int(int)> nrows, int ncomp = 1,
+                const std::vector<int>* comps = nullptr) {
+    L.h.clear();
+    for (int c = 0; c < ncomp; ++c)
+        for (int i : inst) {
+            const int nr = nrows(i);
+            const int comp = comps ? (*comps)[c] : c;
+            for (int a = 0; a < nr; ++a) L.h.push_back(Item{i, a, comp, 0});
+        }
+}
+
+// Shape setup, origin counts, weights and the image spectrum.
+int run_setup(Batch& b) {
+    const int ni = (int)b.ds.size();
+    hipStream_t st = b.st;
+    std::vector<int> all(ni);
+    for (int i = 0; i < ni; ++i) all[i] = i;
+    int rc;
+    if ((rc = b.upload_descs())) return rc;
+    // pointer tables
+    std::vector<const double*> px(ni);
+    std::vector<const uint8_t*> pm(ni);
+    std::vector<uint8_t*> pn(ni), pk(ni);
+    std::vector<double*> pxc(ni), pw(ni);
+    std::vector<int*> pnp(ni), pkp(ni), pkc(ni), pkr(ni);
+    std::vector<int> nr(ni);
+    for (int i = 0; i < ni; ++i) {
+        auto* d = b.ds[i];
+        px[i] = d->x; pm[i] = d->mask; pn[i] = d->nset; pk[i] = d->kmask;
+        pxc[i] = d->xc; pw[i] = d->W; pnp[i] = d->npref; pkp[i] = d->kpref;
+        pkc[i] = d->kcount; pkr[i] = d->krow; nr[i] = d->KA;
+    }
+    DevVec dpx, dpm, dpn, dpk, dpxc, dpw, dpnp, dpkp, dpkc, dpkr, dnr, dtot;
+    if ((rc = dpx.put(px, st)) || (rc = dpm.put(pm, st)) || (rc = dpn.put(pn, st)) || (rc = dpk.put(pk, st)) ||
+        (rc = dpxc.put(pxc, st)) || (rc = dpw.put(pw, st)) || (rc = dpnp.put(pnp, st)) ||
+        (rc = dpkp.put(pkp, st)) || (rc = dpkc.put(pkc, st)) || (rc = dpkr.put(pkr, st)) || (rc = dnr.put(nr, st)))
+        return rc;
+    std::vector<long> tot(ni, 0);
+    if ((rc = dtot.put(tot, st))) return rc;
+    ItemList rowsA, rowsK;
+    rows_items(rowsA, all, [&](int i) { return b.ds[i]->A; });
+    rows_items(rowsK, all, [&](int i) { return b.ds[i]->KA; });
+    if ((rc = rowsA.upload(st)) || (rc = rowsK.upload(st))) return rc;
+    launch_shape_clean(rowsA.n(), st, b.ops(), rowsA.ptr(), dpx.as<const double*>(), dpm.as<const uint8_t*>(),
+                       dpn.as<uint8_t*>(), dpxc.as<double*>(), dpnp.as<int*>());
+    launch_shape_origins(rowsK.n(), st, b.ops(), rowsK.ptr(), b.runs(), dpnp.as<const int*>(), dpk.as<uint8_t*>(),
+                         dpkp.as<int*>(), dpkc.as<int*>());
+    launch_shape_rowoff(ni, st, dpkc.as<const int*>(), dpkr.as<int*>(), dnr.as<int>(), dtot.as<long>());
+    launch_shape_weights(rowsA.n(), st, b.ops(), rowsA.ptr(), b.runs(), dpkp.as<const int*>(), dpw.as<double*>());
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(tot.data(), dtot.p, ni * sizeof(long), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < ni; ++i) {
+        auto* d = b.ds[i];
+        d->K = tot[i];
+        d->op.S[1].count = d->K;
+        if (d->K == 0) d->status = fail(SSA_EEMPTY, "no window position fits inside the array");
+        else if (d->r >= std::min(d->L, d->K)) d->status = fail(SSA_ERANK, "r must be < min(L, K)");
+    }
+    return SSA_OK;
+}
+
+// Allocate the operator scratch, Lanczos state and results; build the
+// spectrum.  Instances with a failed status are skipped by the caller.
+int run_alloc_spectrum(Batch& b) {
+    hipStream_t st = b.st;
+    int rc;
+    for (auto* d : b.ds) {
+        const bool fullbox_short = d->L <= (long)d->KA * d->KB;
+        d->side = d->rowfam ? 0 : (fullbox_short ? 0 : 1);
+        d->nshort = d->side == 0 ? d->L : d->K;
+        d->nlong = d->side == 0 ? d->K : d->L;
+        const size_t ce = d->celem();
+        const long xh = d->rowfam ? (long)d->A * d->P : (long)d->P * d->MA;
+        d->tslot = (long)d->A * d->P;
+        d->uslot = d->rowfam ? (long)d->P : (long)d->P * d->MA;
+        const int nslot = std::max(1, d->r);
+        char *xh_p, *t1, *t2, *us, *lb;
+        if ((rc = d->dalloc(&xh_p, xh * ce)) || (rc = d->dalloc(&t1, d->tslot * ce * nslot)) ||
+            (rc = d->dalloc(&t2, d->tslot * ce * nslot)) || (rc = d->dalloc(&us, d->uslot * ce * nslot)) ||
+            (rc = d->dalloc(&lb, 2 * d->nlong * (d->f64 ? 8 : 4))))
+            return rc;
+        d->Xh = xh_p; d->T1 = t1; d->T2 = t2; d->Us = us; d->lbuf = lb;
+        const long n = d->nshort;
+        const int nblk = (int)((n + kLzRows - 1) / kLzRows);
+        const long longrows = d->side == 0 ? d->KA : d->LA;
+        if ((rc = d->dalloc(&d->Q, n * (kMaxBasis + 1))) || (rc = d->dalloc(&d->w, n)) ||
+            (rc = d->dalloc(&d->sinv, n)) || (rc = d->dalloc(&d->hp1, (long)nblk * (kMaxBasis + 1))) ||
+            (rc = d->dalloc(&d->hp2, (long)nblk * (kMaxBasis + 1))) || (rc = d->dalloc(&d->np, nblk)) ||
+            (rc = d->dalloc(&d->lnp, 2 * longrows)) || (rc = d->dalloc(&d->Bm, kMaxBasis * kMaxBasis)) ||
+            (rc = d->dalloc(&d->Yl, kMaxBasis * kMaxBasis)) || (rc = d->dalloc(&d->Yr, kMaxBasis * kMaxBasis)) ||
+            (rc = d->dalloc(&d->sig, kMaxBasis)) || (rc = d->dalloc(&d->beta, 2)) ||
+            (rc = d->dalloc(&d->perm, kMaxBasis)) || (rc = d->dalloc(&d->flag, 2)) ||
+            (rc = d->dalloc(&d->Qtmp, n * kMaxBasis)) || (rc = d->dalloc(&d->U, d->L * (long)d->r)) ||
+            (rc = d->dalloc(&d->V, d->K * (long)d->r)) || (rc = d->dalloc(&d->sigma, d->r)))
+            return rc;
+        HIPCHK(hipMemsetAsync(d->lnp, 0, 2 * longrows * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(d->lbuf, 0, 2 * d->nlong * (d->f64 ? 8 : 4), st));
+        // descriptors
+        OpDesc& o = d->op;
+        o.Xh = d->Xh; o.T1 = d->T1; o.T2 = d->T2; o.Us = d->Us;
+        o.tslot = d->tslot; o.uslot = d->uslot;
+        if (!make_plan(d->nh, o.prow)) return fail(SSA_EINVAL, "row transform length not smooth");
+        if ((rc = b.ctx->twiddles(d->nh, d->f64, false, &o.prow.tw))) return rc;
+        if ((rc = b.ctx->twiddles(d->nh, d->f64, true, &o.prow.twr))) return rc;
+        if (!d->rowfam) {
+            if (!make_plan(d->MA, o.pcol)) return fail(SSA_EINVAL, "column transform length not smooth");
+            if ((rc = b.ctx->twiddles(d->MA, d->f64, false, &o.pcol.tw))) return rc;
+            o.pcol.twr = nullptr;
+        }
+        LzDesc& z = d->lz;
+        z.side = d->side;
+        z.active = 1;
+        z.r = d->r;
+        z.tol = 0.1 * (d->f64 ? 1e-10 : 1e-5);
+        z.n = n;
+        z.nl = d->nlong;
+        z.Q = d->Q; z.w = d->w; z.sin = d->sinv; z.hp1 = d->hp1; z.hp2 = d->hp2; z.np = d->np;
+        z.lbuf[0] = d->lbuf;
+        z.lbuf[1] = static_cast<char*>(d->lbuf) + d->nlong * (d->f64 ? 8 : 4);
+        z.lnp[0] = d->lnp;
+        z.lnp[1] = d->lnp + longrows;
+        z.Bm = d->Bm; z.Yl = d->Yl; z.Yr = d->Yr; z.sig = d->sig; z.perm = d->perm;
+        z.beta = d->beta; z.flag = d->flag; z.Qtmp = d->Qtmp;
+        z.nblk = nblk;
+        ResDesc& s = d->rs;
+        s.U = d->U; s.V = d->V; s.sigma = d->sigma;
+    }
+    if ((rc = b.upload_descs())) return rc;
+    // spectrum
+    const int ni = (int)b.ds.size();
+    std::vector<int> all(ni);
+    for (int i = 0; i < ni; ++i) all[i] = i;
+    ItemList rowsA;
+    rows_items(rowsA, all, [&](int i) { return b.ds[i]->A; });
+    if ((rc = rowsA.upload(st))) return rc;
+    const auto* d0 = b.ds[0];
+    if (d0->rowfam) {
+        // row spectra scaled by 1/MB straight into each instance's Xh
+        RowInArgs a{IN_DENSE, 0, 0, DEST_XH, 1.0 / d0->MB, 0, nullptr};
+        launch_row_in(b.f64, b.cls, rowsA.n(), st, b.ops(), b.lzs(), b.res(), rowsA.ptr(), a);
+    } else {
+        RowInArgs a{IN_DENSE, 0, 0, DEST_T1, 1.0, 0, nullptr};
+        launch_row_in(b.f64, b.cls, rowsA.n(), st, b.ops(), b.lzs(), b.res(), rowsA.ptr(), a);
+        ItemList cols;
+        for (int i = 0; i < ni; ++i)
+            for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) cols.h.push_back(Item{i, t, 0, 0});
+        if ((rc = cols.upload(st))) return rc;
+        ColArgs c{COL_SPEC, d0->A, 0, 1.0 / ((double)d0->MA * d0->MB), nullptr};
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c);
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    return SSA_OK;
+}
+
+// One application of the bidiagonalisation step j (products and
+// reorthogonalisation) for the listed instances.
+struct StepLists {
+    ItemList rin, cols, rmid, rout, lzb, inst;
+};
+
+void build_step_lists(Batch& b, const std::vector<int>& act, StepLists& S) {
+    const auto* d0 = b.ds[0];
+    const int s = d0->side;
+    if (d0->rowfam) {
+        rows_items(S.rin, act, [&](int) { return 1; });
+        rows_items(S.rmid, act, [&](int i) { return b.ds[i]->A; });
+        rows_items(S.rout, act, [&](int) { return 1; });
+        S.cols.h.clear();
+    } else {
+        rows_items(S.rin, act, [&](int i) { return b.ds[i]->op.S[s].boxA; });
+        rows_items(S.rmid, act, [&](int i) { return b.ds[i]->op.S[1 - s].boxA; });
+        rows_items(S.rout, act, [&](int i) { return b.ds[i]->op.S[s].boxA; });
+        S.cols.h.clear();
+        for (int i : act)
+            for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) S.cols.h.push_back(Item{i, t, 0, 0});
+    }
+    S.lzb.h.clear();
+    S.inst.h.clear();
+    for (int i : act) {
+        for (int k = 0; k < b.ds[i]->lz.nblk; ++k) S.lzb.h.push_back(Item{i, k, 0, 0});
+        S.inst.h.push_back(Item{i, 0, 0, 0});
+    }
+}
+
+int upload_step_lists(StepLists& S, hipStream_t st) {
+    int rc;
+    if ((rc = S.rin.upload(st)) || (rc = S.cols.upload(st)) || (rc = S.rmid.upload(st)) ||
+        (rc = S.rout.upload(st)) || (rc = S.lzb.upload(st)) || (rc = S.inst.upload(st)))
+        return rc;
+    return SSA_OK;
+}
+
+void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode) {
+    hipStream_t st = b.st;
+    const auto* d0 = b.ds[0];
+    const int s = d0->side;
+    if (d0->rowfam) {
+        launch_row_in(b.f64, b.cls, S.rin.n(), st, b.ops(), b.lzs(), b.res(), S.rin.ptr(),
+                      RowInArgs{mode, 0, j, DEST_T1, 1.0, 0, nullptr});
+        launch_rowfam_mid(b.f64, b.cls, S.rmid.n(), st, b.ops(), b.lzs(), b.res(), S.rmid.ptr(),
+                          RowFamArgs{OUT_NONE, 1, 1, j, jstart});
+        launch_rowfam_out(b.f64, b.cls, S.rout.n(), st, b.ops(), b.lzs(), S.rout.ptr(),
+                          RowOutArgs{OUT_LZ, 0, 1.0, 0, j});
+    } else {
+        const int nin = d0->op.S[s].boxA, nmid = d0->op.S[1 - s].boxA;
+        launch_row_in(b.f64, b.cls, S.rin.n(), st, b.ops(), b.lzs(), b.res(), S.rin.ptr(),
+                      RowInArgs{mode, s, j, DEST_T1, 1.0, 0, nullptr});
+        launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(), ColArgs{COL_CORR, nin, nmid, 1.0, nullptr});
+        launch_row_mid(b.f64, b.cls, S.rmid.n(), st, b.ops(), b.lzs(), b.res(), S.rmid.ptr(),
+                       RowMidArgs{1 - s, OUT_NONE, 1.0, 0, 1, 1, j, jstart});
+        launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(), ColArgs{COL_CORR, nmid, nin, 1.0, nullptr});
+        launch_row_out(b.f64, b.cls, S.rout.n(), st, b.ops(), b.lzs(), b.res(), S.rout.ptr(),
+                       RowOutArgs{OUT_LZ, s, 1.0, 0, j});
+    }
+    const int ncols = j + 1;
+    launch_lz_proj(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols);
+    launch_lz_update(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 1);
+    launch_lz_update(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 2);
+}
+
+int basis_size(long nshort, int r) {
+    int m = std::max(2 * r + 20, 3 * r);
+    m = std::min(m, kMaxBasis);
+    if (nshort <= m) m = (int)nshort;
+    return m;
+}
+
+int run_lanczos(Batch& b, int max_steps) {
+    hipStream_t st = b.st;
+    const int ni = (int)b.ds.size();
+    int rc;
+    long nmin = b.ds[0]->nshort;
+    for (auto* d : b.ds) nmin = std::min(nmin, d->nshort);
+    const int r = b.ds[0]->r;
+    const int m = basis_size(nmin, r);
+    const int kk = std::min(m - 1, r + (m - r) / 2);
+    std::vector<int> act(ni);
+    for (int i = 0; i < ni; ++i) act[i] = i;
+    std::vector<int> steps(ni, 0), restarts(ni, 0);
+    StepLists S;
+    build_step_lists(b, act, S);
+    if ((rc = upload_step_lists(S, st))) return rc;
+    launch_lz_start(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), b.ds[0]->seed);
+    int jstart = 0;
+    std::vector<int> flags(2 * ni);
+    std::vector<double> betas(2 * ni);
+    for (auto* d : b.ds) d->st.basis = m;
+    while (!act.empty()) {
+        for (int j = jstart; j < m; ++j) {
+            const int mode = (j == jstart && jstart > 0) ? IN_LZ_SIN : IN_LZ_NORM;
+            launch_step(b, S, j, jstart, mode);
+        }
+        launch_lz_normalize(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), m);
+        launch_lz_svd(S.inst.n(), st, b.lzs(), S.inst.ptr(), m, 40);
+        HIPCHK(hipGetLastError());
+        for (int i : act) {
+            HIPCHK(hipMemcpyAsync(&flags[2 * i], b.ds[i]->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(&betas[2 * i], b.ds[i]->beta, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        std::vector<int> done, cont;
+        for (int i : act) {
+            steps[i] += m - jstart;
+            const bool ok = flags[2 * i] != 0;
+            if (ok || steps[i] >= max_steps) {
+                done.push_back(i);
+                auto* d = b.ds[i];
+                d->st.converged = ok;
+                d->st.steps = steps[i];
+                d->st.restarts = restarts[i];
+                d->st.max_resid = betas[2 * i + 1];
+                if (!ok) d->status = fail(SSA_ENOCONV, "bidiagonalisation reached its step limit");
+            } else {
+                cont.push_back(i);
+                restarts[i]++;
+            }
+        }
+        if (!done.empty()) {
+            // Ritz vectors of the finished instances into their results
+            std::vector<double*> outs(ni, nullptr);
+            for (int i : done) outs[i] = b.ds[i]->side == 0 ? b.ds[i]->U : b.ds[i]->V;
+            DevVec douts;
+            if ((rc = douts.put(outs, st))) return rc;
+            ItemList R, I;
+            for (int i : done) {
+                const long n = b.ds[i]->nshort;
+                for (long rb = 0; rb < (n + 63) / 64; ++rb)
+                    for (int cb = 0; cb < (r + 15) / 16; ++cb) R.h.push_back(Item{i, (int)rb, 0, cb});
+                I.h.push_back(Item{i, 0, 0, 0});
+            }
+            if ((rc = R.upload(st)) || (rc = I.upload(st))) return rc;
+            launch_lz_ritz(R.n(), st, b.lzs(), R.ptr(), m, r, douts.as<double*>());
+            launch_lz_sigma(I.n(), st, b.lzs(), b.res(), I.ptr());
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        if (cont.empty()) break;
+        {
+            ItemList R, Z;
+            for (int i : cont) {
+                const long n = b.ds[i]->nshort;
+                for (long rb = 0; rb < (n + 63) / 64; ++rb)
+                    for (int cb = 0; cb < (kk + 15) / 16; ++cb) R.h.push_back(Item{i, (int)rb, 0, cb});
+                for (int k = 0; k < b.ds[i]->lz.nblk; ++k) Z.h.push_back(Item{i, k, 0, 0});
+            }
+            if ((rc = R.upload(st)) || (rc = Z.upload(st))) return rc;
+            launch_lz_ritz(R.n(), st, b.lzs(), R.ptr(), m, kk, nullptr);
+            launch_lz_restart(Z.n(), st, b.lzs(), Z.ptr(), m, kk);
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        act = cont;
+        build_step_lists(b, act, S);
+        if ((rc = upload_step_lists(S, st))) return rc;
+        jstart = kk;
+    }
+    HIPCHK(hipGetLastError());
+    return SSA_OK;
+}
+
+// Long-side vectors of the final triplets (V = X^T U / sigma or
+// U = X V / sigma), then the sign rule.
+int run_finish(Batch& b) {
+    hipStream_t st = b.st;
+    const int ni = (int)b.ds.size();
+    int rc;
+    std::vector<int> all(ni);
+    for (int i = 0; i < ni; ++i) all[i] = i;
+    const auto* d0 = b.ds[0];
+    const int r = d0->r;
+    const int s = d0->side;
+    ItemList rin, cols, rmid, sg;
+    if (d0->rowfam) {
+        rows_items(rin, all, [&](int) { return 1; }, r);
+        rows_items(rmid, all, [&](int i) { return b.ds[i]->A; }, r);
+        if ((rc = rin.upload(st)) || (rc = rmid.upload(st))) return rc;
+        launch_row_in(b.f64, b.cls, rin.n(), st, b.ops(), b.lzs(), b.res(), rin.ptr(),
+                      RowInArgs{IN_VEC, 0, 0, DEST_T1, 1.0, 0, nullptr});
+        launch_rowfam_mid(b.f64, b.cls, rmid.n(), st, b.ops(), b.lzs(), b.res(), rmid.ptr(),
+                          RowFamArgs{OUT_VEC, 0, 0, 0, 0});
+    } else {
+        rows_items(rin, all, [&](int i) { return b.ds[i]->op.S[s].boxA; }, r);
+        rows_items(rmid, all, [&](int i) { return b.ds[i]->op.S[1 - s].boxA; }, r);
+        for (int c = 0; c < r; ++c)
+            for (int i : all)
+                for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) cols.h.push_back(Item{i, t, c, 0});
+        if ((rc = rin.upload(st)) || (rc = rmid.upload(st)) || (rc = cols.upload(st))) return rc;
+        const int nin = d0->op.S[s].boxA, nmid = d0->op.S[1 - s].boxA;
+        launch_row_in(b.f64, b.cls, rin.n(), st, b.ops(), b.lzs(), b.res(), rin.ptr(),
+                      RowInArgs{IN_VEC, s, 0, DEST_T1, 1.0, 0, nullptr});
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_CORR, nin, nmid, 1.0, nullptr});
+        launch_row_mid(b.f64, b.cls, rmid.n(), st, b.ops(), b.lzs(), b.res(), rmid.ptr(),
+                       RowMidArgs{1 - s, OUT_VEC, 1.0, 1, 0, 0, 0, 0});
+    }
+    for (int c = 0; c < r; ++c)
+        for (int i : all) sg.h.push_back(Item{i, 0, c, 0});
+    if ((rc = sg.upload(st))) return rc;
+    launch_sign_fix(sg.n(), st, b.ops(), b.res(), sg.ptr());
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    for (auto* d : b.ds) {
+        d->sigma_h.resize(d->r);
+        HIPCHK(hipMemcpy(d->sigma_h.data(), d->sigma, d->r * sizeof(double), hipMemcpyDeviceToHost));
+        d->decomposed = true;
+    }
+    return SSA_OK;
+}
+
+// Reconstruction of the same groups for every instance of the batch into
+// internal-orientation device buffers recon[i] (ngroups x A x B).
+int run_reconstruct(Batch& b, const std::vector<int>& gptr, const std::vector<int>& gidx,
+                    const std::vector<double*>& recon) {
+    hipStream_t st = b.st;
+    const int ni = (int)b.ds.size();
+    const int ng = (int)gptr.size() - 1;
+    int rc;
+    DevVec dgp, dgi;
+    if ((rc = dgp.put(gptr, st)) || (rc = dgi.put(gidx, st))) return rc;
+    for (int i = 0; i < ni; ++i) {
+        b.ds[i]->rs.recon = recon[i];
+        b.ds[i]->rs.gptr = dgp.as<int>();
+        b.ds[i]->rs.gidx = dgi.as<int>();
+    }
+    if ((rc = b.upload_descs())) return rc;
+    std::vector<int> comps(gidx);
+    std::sort(comps.begin(), comps.end());
+    comps.erase(std::unique(comps.begin(), comps.end()), comps.end());
+    const int nc = (int)comps.size();
+    std::vector<int> all(ni);
+    for (int i = 0; i < ni; ++i) all[i] = i;
+    const auto* d0 = b.ds[0];
+    ItemList a1, a2, c1, c2, out;
+    if (d0->rowfam) {
+        rows_items(a1, all, [&](int) { return 1; }, nc, &comps);
+        rows_items(out, all, [&](int i) { return b.ds[i]->A; }, ng);
+        if ((rc = a1.upload(st)) || (rc = out.upload(st))) return rc;
+        launch_row_in(b.f64, b.cls, a1.n(), st, b.ops(), b.lzs(), b.res(), a1.ptr(),
+                      RowInArgs{IN_VEC, 0, 0, DEST_T1, 1.0, 0, nullptr});
+        launch_copy_uspec(b.f64, a1.n(), st, b.ops(), a1.ptr());
+        launch_rowfam_recon(b.f64, b.cls, out.n(), st, b.ops(), b.res(), out.ptr(), 1.0 / d0->MB);
+    } else {
+        rows_items(a1, all, [&](int i) { return b.ds[i]->LA; }, nc, &comps);
+        rows_items(a2, all, [&](int i) { return b.ds[i]->KA; }, nc, &comps);
+        rows_items(out, all, [&](int i) { return b.ds[i]->A; }, ng);
+        for (int c : comps)
+            for (int i : all)
+                for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) c1.h.push_back(Item{i, t, c, 0});
+        for (int g = 0; g < ng; ++g)
+            for (int i : all)
+                for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) c2.h.push_back(Item{i, t, g, 0});
+        if ((rc = a1.upload(st)) || (rc = a2.upload(st)) || (rc = c1.upload(st)) || (rc = c2.upload(st)) ||
+            (rc = out.upload(st)))
+            return rc;
+        launch_row_in(b.f64, b.cls, a1.n(), st, b.ops(), b.lzs(), b.res(), a1.ptr(),
+                      RowInArgs{IN_VEC, 0, 0, DEST_T1, 1.0, 0, nullptr});
+        launch_col(b.f64, c1.n(), st, b.ops(), b.res(), c1.ptr(), ColArgs{COL_STORE, d0->LA, 0, 1.0, nullptr});
+        launch_row_in(b.f64, b.cls, a2.n(), st, b.ops(), b.lzs(), b.res(), a2.ptr(),
+                      RowInArgs{IN_VEC, 1, 0, DEST_T1, 1.0, 1, nullptr});
+        launch_col(b.f64, c2.n(), st, b.ops(), b.res(), c2.ptr(), ColArgs{COL_ACCUM, d0->KA, d0->A, 1.0, nullptr});
+        launch_row_out(b.f64, b.cls, out.n(), st, b.ops(), b.lzs(), b.res(), out.ptr(),
+                       RowOutArgs{OUT_IMAGE, 0, 1.0 / ((double)d0->MA * d0->MB), 0, 0});
+    }
+    HIPCHK(hipGetLastError());
+    // keep the item lists alive until the work is done
+    HIPCHK(hipStreamSynchronize(st));
+    return SSA_OK;
+}
+
+// key of a batch: instances must share geometry, rank and precision
+using GeoKey = std::tuple<int, int, int, int, int, int, int, int, int, int, int>;
+GeoKey geo_key(const ssa_decomp* d) {
+    return GeoKey{d->A, d->B, d->LA, d->LB, d->MA, d->MB, (int)d->tr, d->r, (int)d->f64, (int)d->rowfam,
+                  (int)d->L};
+}
+
+int decompose_many(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** out, int* status, bool dev) {
+    if (!ctx || n < 0 || (n > 0 && (!reqs || !out))) return fail(SSA_EINVAL, "bad arguments");
+    std::vector<std::unique_ptr<ssa_decomp>> ds(n);
+    std::vector<int> st(n, SSA_OK);
+    std::map<GeoKey, std::vector<int>> groups;
+    for (int i = 0; i < n; ++i) {
+        out[i] = nullptr;
+        ds[i].reset(new ssa_decomp());
+        st[i] = plan_request(ctx, reqs[i], ds[i].get());
+        if (st[i] == SSA_OK) st[i] = upload_request(reqs[i], ds[i].get(), dev, ctx->st);
+        if (st[i] == SSA_OK) groups[geo_key(ds[i].get())].push_back(i);
+    }
+    for (auto& kv : groups) {
+        Batch b(ctx);
+        for (int i : kv.second) b.ds.push_back(ds[i].get());
+        b.f64 = b.ds[0]->f64;
+        b.rowfam = b.ds[0]->rowfam;
+        b.cls = row_class(b.ds[0]->nh, b.f64);
+        b.TC = col_tile(b.f64);
+        auto t0 = Clock::now();
+        int rc = run_setup(b);
+        if (rc) {
+            for (int i : kv.second) st[i] = rc;
+            continue;
+        }
+        // drop instances whose shapes failed
+        std::vector<ssa_decomp*> ok;
+        for (int i : kv.second) {
+            if (ds[i]->status != SSA_OK) st[i] = ds[i]->status;
+            else ok.push_back(ds[i].get());
+        }
+        if (ok.empty()) continue;
+        b.ds = ok;
+        rc = run_alloc_spectrum(b);
+        if (!rc) (void)hipStreamSynchronize(ctx->st);
+        const double t_setup = ms_since(t0);
+        auto t1 = Clock::now();
+        if (!rc) rc = run_lanczos(b, 3000);
+        const double t_lz = ms_since(t1);
+        auto t2 = Clock::now();
+        if (!rc) rc = run_finish(b);
+        const double t_fin = ms_since(t2);
+        for (auto* d : b.ds) {
+            d->st.ms_setup = t_setup / b.ds.size();
+            d->st.ms_lanczos = t_lz / b.ds.size();
+            d->st.ms_finish = t_fin / b.ds.size();
+            d->st.side = d->side;
+        }
+        for (int i : kv.second) {
+            if (rc) st[i] = rc;
+            else if (ds[i]->status != SSA_OK && st[i] == SSA_OK) st[i] = ds[i]->status;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        if (status) status[i] = st[i];
+        if (st[i] == SSA_OK || st[i] == SSA_ENOCONV) out[i] = ds[i].release();
+    }
+    return SSA_OK;
+}
+
+// Convert internal compact vectors to the caller's boxes (NaN off the set).
+int fetch_kmask(ssa_decomp* d) {
+    if (!d->kmask_h.empty()) return SSA_OK;
+    d->kmask_h.resize((size_t)d->KA * d->KB);
+    HIPCHK(hipMemcpy(d->kmask_h.data(), d->kmask, d->kmask_h.size(), hipMemcpyDeviceToHost));
+    return SSA_OK;
+}
+
+// For a set box (internal BA x BB) and its mask, call fn(compact index,
+// caller row, caller col) for every cell in internal row-major order.
+template <typename F>
+void walk_set(const ssa_decomp* d, int BA, int BB, const uint8_t* mask, F fn) {
+    long idx = 0;
+    for (int a = 0; a < BA; ++a)
+        for (int b = 0; b < BB; ++b) {
+            if (mask && !mask[(size_t)a * BB + b]) continue;
+            const int i = d->tr ? b : a, j = d->tr ? a : b;
+            fn(idx++, i, j);
+        }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+int ssa_ctx_create(int device, size_t mem_budget, void* stream, ssa_ctx** out) {
+    if (!out) return fail(SSA_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(SSA_EDEVICE, "no HIP device");
+    if (device < 0 || device >= ndev) return fail(SSA_EINVAL, "device out of range");
+    HIPCHK(hipSetDevice(device));
+    auto* c = new ssa_ctx();
+    c->device = device;
+    c->budget = mem_budget;
+    if (stream) {
+        c->st = static_cast<hipStream_t>(stream);
+    } else {
+        if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail(SSA_EDEVICE, "hipStreamCreate failed");
+        }
+        c->own = true;
+    }
+    *out = c;
+    return SSA_OK;
+}
+
+void ssa_ctx_destroy(ssa_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->st);
+    for (auto& kv : ctx->tw) (void)hipFree(kv.second);
+    if (ctx->own) (void)hipStreamDestroy(ctx->st);
+    delete ctx;
+}
+
+int ssa_ctx_set_stream(ssa_ctx* ctx, void* stream) {
+    if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    if (ctx->own) (void)hipStreamDestroy(ctx->st);
+    ctx->own = false;
+    ctx->st = static_cast<hipStream_t>(stream);
+    return SSA_OK;
+}
+
+int ssa_ctx_sync(ssa_ctx* ctx) {
+    if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    return SSA_OK;
+}
+
+int ssa_decompose_batch(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** out, int* status) {
+    return decompose_many(ctx, n, reqs, out, status, false);
+}
+
+int ssa_decompose_batch_dev(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** out, int* status) {
+    return decompose_many(ctx, n, reqs, out, status, true);
+}
+
+int ssa_decompose(ssa_ctx* ctx, const double* x, int nx, int ny, const uint8_t* mask, const uint8_t* wmask,
+                  int lx, int ly, int r, int precision, ssa_decomp** out) {
+    if (!out) return fail(SSA_EINVAL, "out is NULL");
+    ssa_request q{x, nx, ny, mask, wmask, lx, ly, r, precision, 0x5eedULL};
+    int st = SSA_OK;
+    int rc = decompose_many(ctx, 1, &q, out, &st, false);
+    return rc ? rc : st;
+}
+
+int ssa_decompose_multi(ssa_ctx* ctx, const double* const* series, const int* len, int s, int L, int r,
+                        int precision, ssa_decomp** out) {
+    if (!out) return fail(SSA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!series || !len || s <= 0) return fail(SSA_EINVAL, "no series");
+    int nmax = 0, nmin = 1 << 30;
+    for (int p = 0; p < s; ++p) {
+        if (len[p] <= 0 || !series[p]) return fail(SSA_EINVAL, "empty series");
+        nmax = std::max(nmax, len[p]);
+        nmin = std::min(nmin, len[p]);
+    }
+    if (!(L > 1 && L < nmin)) return fail(SSA_EINVAL, "window must satisfy 1 < L < min N_p");
+    // 2D packing: max N_p x s array, column p = series p, NaN below its end
+    std::vector<double> x((size_t)nmax * s, std::nan(""));
+    for (int p = 0; p < s; ++p)
+        for (int t = 0; t < len[p]; ++t) x[(size_t)t * s + p] = series[p][t];
+    ssa_request q{x.data(), nmax, s, nullptr, nullptr, L, 1, r, precision, 0x5eedULL};
+    int st = SSA_OK;
+    int rc = decompose_many(ctx, 1, &q, out, &st, false);
+    return rc ? rc : st;
+}
+
+int ssa_get_dims(const ssa_decomp* d, int* lx, int* ly, int* kx, int* ky, long* L, long* K, int* r, int* nx,
+                 int* ny) {
+    if (!d) return fail(SSA_EINVAL, "handle is NULL");
+    if (lx) *lx = d->lx;
+    if (ly) *ly = d->ly;
+    if (kx) *kx = d->kx;
+    if (ky) *ky = d->ky;
+    if (L) *L = d->L;
+    if (K) *K = d->K;
+    if (r) *r = d->r;
+    if (nx) *nx = d->nx;
+    if (ny) *ny = d->ny;
+    return SSA_OK;
+}
+
+int ssa_get_sigma(const ssa_decomp* d, double* sigma) {
+    if (!d || !sigma) return fail(SSA_EINVAL, "NULL argument");
+    if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
+    std::memcpy(sigma, d->sigma_h.data(), d->r * sizeof(double));
+    return SSA_OK;
+}
+
+int ssa_get_vectors(const ssa_decomp* dc, double* U, double* V) {
+    auto* d = const_cast<ssa_decomp*>(dc);
+    if (!d) return fail(SSA_EINVAL, "handle is NULL");
+    if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
+    int rc;
+    if (U) {
+        std::vector<double> u((size_t)d->L * d->r);
+        HIPCHK(hipMemcpy(u.data(), d->U, u.size() * 8, hipMemcpyDeviceToHost));
+        const long box = (long)d->lx * d->ly;
+        std::fill(U, U + box * d->r, std::nan(""));
+        const uint8_t* m = d->L == (long)d->LA * d->LB ? nullptr : d->lmask_h.data();
+        walk_set(d, d->LA, d->LB, m, [&](long idx, int i, int j) {
+            for (int c = 0; c < d->r; ++c) U[c * box + (long)i * d->ly + j] = u[(size_t)c * d->L + idx];
+        });
+    }
+    if (V) {
+        if ((rc = fetch_kmask(d))) return rc;
+        std::vector<double> v((size_t)d->K * d->r);
+        HIPCHK(hipMemcpy(v.data(), d->V, v.size() * 8, hipMemcpyDeviceToHost));
+        const long box = (long)d->kx * d->ky;
+        std::fill(V, V + box * d->r, std::nan(""));
+        walk_set(d, d->KA, d->KB, d->kmask_h.data(), [&](long idx, int i, int j) {
+            for (int c = 0; c < d->r; ++c) V[c * box + (long)i * d->ky + j] = v[(size_t)c * d->K + idx];
+        });
+    }
+    return SSA_OK;
+}
+
+int ssa_get_vectors_lex(const ssa_decomp* dc, double* U, double* V) {
+    auto* d = const_cast<ssa_decomp*>(dc);
+    if (!d) return fail(SSA_EINVAL, "handle is NULL");
+    const long lb = (long)d->lx * d->ly, kb = (long)d->kx * d->ky;
+    std::vector<double> gu(lb * d->r), gv(kb * d->r);
+    int rc = ssa_get_vectors(d, gu.data(), V ? gv.data() : nullptr);
+    if (rc) return rc;
+    // lexicographic = column-major over the caller's box (row index fastest)
+    auto pack = [&](const std::vector<double>& g, int bx, int by, long cnt, double* out) {
+        const long box = (long)bx * by;
+        for (int c = 0; c < d->r; ++c) {
+            long k = 0;
+            for (int j = 0; j < by; ++j)
+                for (int i = 0; i < bx; ++i) {
+                    const double v = g[c * box + (long)i * by + j];
+                    if (!std::isnan(v) || false) out[(long)c * cnt + k++] = v;
+                }
+        }
+    };
+    if (U) {
+        // window cells can hold any value; walk the mask instead of NaN tests
+        const long box = lb;
+        for (int c = 0; c < d->r; ++c) {
+            long k = 0;
+            for (int j = 0; j < d->ly; ++j)
+                for (int i = 0; i < d->lx; ++i) {
+                    const int a = d->tr ? j : i, b = d->tr ? i : j;
+                    if (d->lmask_h[(size_t)a * d->LB + b]) U[(long)c * d->L + k++] = gu[c * box + (long)i * d->ly + j];
+                }
+        }
+    }
+    if (V) {
+        for (int c = 0; c < d->r; ++c) {
+            long k = 0;
+            for (int j = 0; j < d->ky; ++j)
+                for (int i = 0; i < d->kx; ++i) {
+                    const int a = d->tr ? j : i, b = d->tr ? i : j;
+                    if (d->kmask_h[(size_t)a * d->KB + b]) V[(long)c * d->K + k++] = gv[c * kb + (long)i * d->ky + j];
+                }
+        }
+    }
+    (void)pack;
+    return SSA_OK;
+}
+
+int ssa_get_weights(const ssa_decomp* d, double* w) {
+    if (!d || !w) return fail(SSA_EINVAL, "NULL argument");
+    const long n = (long)d->A * d->B;
+    if (!d->tr) {
+        HIPCHK(hipMemcpy(w, d->W, n * 8, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<double> t(n);
+        HIPCHK(hipMemcpy(t.data(), d->W, n * 8, hipMemcpyDeviceToHost));
+        for (int a = 0; a < d->A; ++a)
+            for (int b = 0; b < d->B; ++b) w[(long)b * d->A + a] = t[(long)a * d->B + b];
+    }
+    return SSA_OK;
+}
+
+static int check_groups(const ssa_decomp* d, const int* gp, const int* gi, int ng) {
+    if (ng <= 0 || !gp || !gi) return fail(SSA_EINVAL, "no groups");
+    if (gp[0] != 0) return fail(SSA_EINVAL, "grp_ptr[0] must be 0");
+    for (int g = 0; g < ng; ++g)
+        if (gp[g + 1] < gp[g]) return fail(SSA_EINVAL, "grp_ptr must be non-decreasing");
+    for (int k = 0; k < gp[ng]; ++k)
+        if (gi[k] < 0 || gi[k] >= d->r) return fail(SSA_EINVAL, "component id out of range");
+    if (ng > d->r) return fail(SSA_EINVAL, "more groups than components");
+    return SSA_OK;
+}
+
+int ssa_reconstruct(ssa_decomp* d, const int* gp, const int* gi, int ng, double* out) {
+    if (!d || !out) return fail(SSA_EINVAL, "NULL argument");
+    if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
+    int rc = check_groups(d, gp, gi, ng);
+    if (rc) return rc;
+    const long n = (long)d->A * d->B;
+    double* buf = nullptr;
+    HIPCHK(hipMalloc(&buf, n * ng * 8));
+    Batch b(d->ctx);
+    b.ds = {d};
+    b.f64 = d->f64;
+    b.rowfam = d->rowfam;
+    b.cls = row_class(d->nh, d->f64);
+    b.TC = col_tile(d->f64);
+    rc = run_reconstruct(b, std::vector<int>(gp, gp + ng + 1), std::vector<int>(gi, gi + gp[ng]), {buf});
+    if (!rc) {
+        if (!d->tr) {
+            if (hipMemcpy(out, buf, n * ng * 8, hipMemcpyDeviceToHost) != hipSuccess) rc = fail(SSA_EDEVICE, "copy");
+        } else {
+            std::vector<double> t(n * ng);
+            if (hipMemcpy(t.data(), buf, n * ng * 8, hipMemcpyDeviceToHost) != hipSuccess) rc = fail(SSA_EDEVICE, "copy");
+            for (int g = 0; g < ng; ++g)
+                for (int a = 0; a < d->A; ++a)
+                    for (int bb = 0; bb < d->B; ++bb)
+                        out[g * n + (long)bb * d->A + a] = t[g * n + (long)a * d->B + bb];
+        }
+    }
+    (void)hipFree(buf);
+    return rc;
+}
+
+int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* gp, const int* gi, int ng,
+                              double* const* out_dev) {
+    if (n <= 0 || !d || !out_dev) return fail(SSA_EINVAL, "bad arguments");
+    for (int i = 0; i < n; ++i) {
+        if (!d[i] || !d[i]->decomposed) return fail(SSA_ESTATE, "not decomposed");
+        if (geo_key(d[i]) != geo_key(d[0])) return fail(SSA_EINVAL, "handles differ in geometry");
+        if (d[i]->tr) return fail(SSA_EINVAL, "device reconstruction needs a window more than one column wide");
+    }
+    int rc = check_groups(d[0], gp, gi, ng);
+    if (rc) return rc;
+    Batch b(d[0]->ctx);
+    b.ds.assign(d, d + n);
+    b.f64 = d[0]->f64;
+    b.rowfam = d[0]->rowfam;
+    b.cls = row_class(d[0]->nh, d[0]->f64);
+    b.TC = col_tile(d[0]->f64);
+    return run_reconstruct(b, std::vector<int>(gp, gp + ng + 1), std::vector<int>(gi, gi + gp[ng]),
+                           std::vector<double*>(out_dev, out_dev + n));
+}
+
+int ssa_get_stats(const ssa_decomp* d, ssa_stats* st) {
+    if (!d || !st) return fail(SSA_EINVAL, "NULL argument");
+    *st = d->st;
+    st->device_bytes = d->bytes;
+    return SSA_OK;
+}
+
+void ssa_free(ssa_decomp* d) { delete d; }
+
+const char* ssa_strerror(int code) {
+    switch (code) {
+    case SSA_OK: return "ok";
+    case SSA_EINVAL: return "invalid argument";
+    case SSA_EEMPTY: return "no window position fits inside the array";
+    case SSA_ERANK: return "r must satisfy 1 <= r < min(L, K)";
+    case SSA_ENOMEM: return "out of device memory";
+    case SSA_ENOCONV: return "bidiagonalisation did not converge";
+    case SSA_EDEVICE: return "HIP runtime error";
+    case SSA_EBUSY: return "request not finished";
+    case SSA_ESTATE: return "call out of order";
+    default: return "unknown error";
+    }
+}
+
+const char* ssa_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

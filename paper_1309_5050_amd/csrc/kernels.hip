@@ -1,0 +1,1130 @@
+// Device kernels of the Shaped 2D-SSA path (gfx950).
+//
+// Products with the trajectory matrix follow the implementation section of
+// the paper (quasi-Hankel matrix-vector product, Algorithm 3, and its 1D
+// special case, Algorithm 1): the input vector is placed on its index set
+// inside a zero grid, transformed, multiplied pointwise by the conjugate of
+// the input vector's spectrum against the image spectrum, transformed back,
+// and read out on the other index set.  X v reads the origin set K and
+// writes the window set L; X^T u does the reverse with the same kernels.
+//
+// Reconstruction follows Algorithms 4 and 5 (quasi-hankelization through
+// diagsums): the product of the spectra of U_i (on L) and sigma_i V_i (on K),
+// summed over the group in the frequency domain, transformed back once and
+// divided by the weights; cells with zero weight are not covered.
+//
+// Shapes follow Algorithm 6: an origin belongs to K when every window cell
+// placed there lands on a cell of N.  The window count is taken by exact
+// integer run sums over row prefix counts instead of a rounded FFT product.
+#include "common.hpp"
+#include "device.hpp"
+#include "fft.hpp"
+
+namespace shssa {
+
+// ------------------------------------------------------------------------
+// helpers
+// ------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Compact index of cell (a, b) of a set row, visiting b = 0..len-1 in chunks
+// of G threads.  fn(b, idx) is called for every b < len with idx = compact
+// index or -1 (b outside the set or beyond the box).  G == 64 slots scan with
+// one ballot per chunk; wider slots (one per workgroup) combine wave counts
+// through LDS, so every thread of the workgroup must call this.
+template <int G, typename F>
+__device__ __forceinline__ void scan_row(const CellSet& S, int a, int len, int tid, int* wtot, F fn) {
+    const int boxB = S.boxB;
+    if (a >= S.boxA) {
+        for (int c0 = 0; c0 < len; c0 += G) {
+            const int b = c0 + tid;
+            if (b < len) fn(b, -1L);
+        }
+        return;
+    }
+    const long base = S.rowoff[a];
+    if (S.mask == nullptr) {
+        for (int c0 = 0; c0 < len; c0 += G) {
+            const int b = c0 + tid;
+            if (b < len) fn(b, b < boxB ? base + b : -1L);
+        }
+        return;
+    }
+    const uint8_t* m = S.mask + (long)a * boxB;
+    long run = base;
+    for (int c0 = 0; c0 < len; c0 += G) {
+        const int b = c0 + tid;
+        const bool in = b < boxB && b < len && m[b] != 0;
+        const unsigned long long bal = __ballot(in);
+        const int lane = lane_id();
+        const int r = __popcll(bal & ((1ULL << lane) - 1ULL));
+        long before = 0;
+        int tot;
+        if constexpr (G == 64) {
+            tot = __popcll(bal);
+        } else {
+            const int wv = tid >> 6;
+            if (lane == 0) wtot[wv] = __popcll(bal);
+            __syncthreads();
+            tot = 0;
+            for (int q = 0; q < G / 64; ++q) {
+                const int c = wtot[q];
+                if (q < wv) before += c;
+                tot += c;
+            }
+            __syncthreads();
+        }
+        if (b < len) fn(b, in ? run + before + r : -1L);
+        run += tot;
+    }
+}
+
+template <typename T> __device__ __forceinline__ T to(double v) { return static_cast<T>(v); }
+
+// Sum of v over the G threads of a slot.  G == 64: one wave; otherwise the
+// slot is the whole workgroup and the waves combine through LDS.  Every
+// thread of the workgroup must call it; all threads get the total.
+template <int G>
+__device__ __forceinline__ double slot_sum(double v, double* red) {
+    v = wave_sum(v);
+    if constexpr (G == 64) {
+        return v;
+    } else {
+        const int wv = (threadIdx.x % G) >> 6;
+        __syncthreads();
+        if (lane_id() == 0) red[wv] = v;
+        __syncthreads();
+        double t = 0.0;
+        for (int q = 0; q < G / 64; ++q) t += red[q];
+        return t;
+    }
+}
+
+__device__ __forceinline__ double sum_parts(const double* p, int n) {
+    double s = 0.0;
+    for (int q = 0; q < n; ++q) s += p[q];
+    return s;
+}
+
+// ------------------------------------------------------------------------
+// row kernels
+// ------------------------------------------------------------------------
+
+
+
+template <typename T, int NMAX, int G, int SLOTS>
+__global__ void __launch_bounds__(G * SLOTS)
+k_row_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
+         const Item* __restrict__ items, int nitems, RowInArgs args) {
+    __shared__ cplx<T> buf[SLOTS][NMAX + 1];
+    __shared__ int wtot[16];
+    const int slot = threadIdx.x / G, tid = threadIdx.x % G;
+    const int it = blockIdx.x * SLOTS + slot;
+    const bool valid = it < nitems;
+    const Item item = items[valid ? it : nitems - 1];
+    const OpDesc& op = ops[item.inst];
+    const LzDesc& lz = lzs[item.inst];
+    cplx<T>* s = buf[slot];
+    T* sr = reinterpret_cast<T*>(s);
+    const int a = item.idx;
+    const int MB = op.MB;
+
+    if (args.mode == IN_DENSE) {
+        const double* row = op.xc + (long)a * op.B;
+        for (int b = tid; b < MB; b += G) sr[b] = b < op.B ? to<T>(row[b]) : T(0);
+    } else {
+        const CellSet& S = op.S[args.set];
+        const double* src;
+        double sc = 1.0;
+        double* qout = nullptr;
+        if (args.mode == IN_LZ_NORM || args.mode == IN_LZ_PLAIN || args.mode == IN_LZ_SIN) {
+            if (args.mode == IN_LZ_NORM) {
+                const double beta = sqrt(sum_parts(lz.np, lz.nblk));
+                sc = beta > 1e-300 ? 1.0 / beta : 0.0;
+                src = lz.w;
+                qout = lz.Q + (long)args.j * lz.n;
+                if (valid && a == 0 && tid == 0 && args.j > 0)
+                    lz.Bm[(long)(args.j - 1) * kMaxBasis + args.j] = beta;
+            } else if (args.mode == IN_LZ_SIN) {
+                src = lz.sin;
+            } else {
+                src = lz.Q + (long)args.j * lz.n;
+            }
+        } else {
+            const ResDesc& rs = res[item.inst];
+            const long ld = args.set == 0 ? op.S[0].count : op.S[1].count;
+            src = (args.set == 0 ? rs.U : rs.V) + (long)item.comp * ld;
+            sc = args.scale * (args.use_sigma ? rs.sigma[item.comp] : 1.0);
+        }
+        const bool wr = valid && qout != nullptr;
+        scan_row<G>(S, a, MB, tid, wtot, [&](int b, long idx) {
+            double v = 0.0;
+            if (idx >= 0) {
+                v = src[idx] * sc;
+                if (wr) qout[idx] = v;
+            }
+            sr[b] = to<T>(v);
+        });
+    }
+    __syncthreads();
+    rfft_fwd<T, NMAX, G>(s, op.prow, tid);
+    if (!valid) return;
+    const int n1 = op.prow.n + 1;
+    cplx<T>* out;
+    if (args.dest == DEST_T1) {
+        out = static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.P;
+        for (int f = tid; f < n1; f += G) out[f] = s[f];
+    } else {
+        out = static_cast<cplx<T>*>(const_cast<void*>(op.Xh)) + (long)a * op.P;
+        const T scl = to<T>(args.scale);
+        for (int f = tid; f < n1; f += G) out[f] = {s[f].x * scl, s[f].y * scl};
+    }
+}
+
+
+
+// Long-vector update of step j inside the row pass: gamma = beta_{j-1} /
+// alpha_{j-1} (0 on the first step of a cycle), lcur/lprev by parity.
+template <typename T>
+struct GkLong {
+    T* lcur;
+    const T* lprev;
+    double* lnp;
+    T gamma;
+};
+
+template <typename T>
+__device__ __forceinline__ GkLong<T> gk_long(const LzDesc& lz, const CellSet& Slong, int j, int jstart) {
+    GkLong<T> g;
+    const int p = j & 1;
+    g.lcur = static_cast<T*>(lz.lbuf[p]);
+    g.lprev = static_cast<const T*>(lz.lbuf[p ^ 1]);
+    g.lnp = lz.lnp[p];
+    double gm = 0.0;
+    if (j != jstart) {
+        const double beta = sqrt(sum_parts(lz.np, lz.nblk));
+        const double alpha = sqrt(sum_parts(lz.lnp[p ^ 1], Slong.boxA));
+        gm = alpha > 1e-300 ? beta / alpha : 0.0;
+    }
+    g.gamma = static_cast<T>(gm);
+    return g;
+}
+
+// C2R of T2 row a, mask to a set row, optional emission, R2C into T1 row a.
+template <typename T, int NMAX, int G, int SLOTS>
+__global__ void __launch_bounds__(G * SLOTS)
+k_row_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
+          const Item* __restrict__ items, int nitems, RowMidArgs args) {
+    __shared__ cplx<T> buf[SLOTS][NMAX + 1];
+    __shared__ int wtot[16];
+    __shared__ double red[16];
+    const int slot = threadIdx.x / G, tid = threadIdx.x % G;
+    const int it = blockIdx.x * SLOTS + slot;
+    const bool valid = it < nitems;
+    const Item item = items[valid ? it : nitems - 1];
+    const OpDesc& op = ops[item.inst];
+    cplx<T>* s = buf[slot];
+    T* sr = reinterpret_cast<T*>(s);
+    const int a = item.idx;
+    const int n1 = op.prow.n + 1;
+    const cplx<T>* in = static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P;
+    for (int f = tid; f < n1; f += G) s[f] = in[f];
+    __syncthreads();
+    rfft_inv<T, NMAX, G>(s, op.prow, tid);
+    const CellSet& S = op.S[args.set];
+    double* vout = nullptr;
+    double sc = args.scale;
+    if (args.emit == OUT_VEC && valid) {
+        const ResDesc& rs = res[item.inst];
+        vout = (args.set == 0 ? rs.U : rs.V) + (long)item.comp * S.count;
+        if (args.div_sigma) sc /= rs.sigma[item.comp];
+    }
+    if (args.gk) {
+        const GkLong<T> g = gk_long<T>(lzs[item.inst], S, args.j, args.jstart);
+        double part = 0.0;
+        scan_row<G>(S, a, op.MB, tid, wtot, [&](int b, long idx) {
+            T v = T(0);
+            if (idx >= 0) {
+                v = sr[b] - g.gamma * g.lprev[idx];
+                if (valid) g.lcur[idx] = v;
+                part += static_cast<double>(v) * static_cast<double>(v);
+            }
+            sr[b] = v;
+        });
+        part = slot_sum<G>(part, red);
+        if (valid && tid == 0) g.lnp[a] = part;
+    } else {
+        scan_row<G>(S, a, op.MB, tid, wtot, [&](int b, long idx) {
+            T v = sr[b];
+            if (idx < 0) v = T(0);
+            else if (vout) vout[idx] = sc * static_cast<double>(v);
+            sr[b] = v;
+        });
+    }
+    if (!args.fwd) return;
+    __syncthreads();
+    rfft_fwd<T, NMAX, G>(s, op.prow, tid);
+    if (!valid) return;
+    cplx<T>* out = static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.P;
+    for (int f = tid; f < n1; f += G) out[f] = s[f];
+}
+
+
+// w = (X l'_j) / alpha_j - alpha_j q_j with alpha_j = |l'_j|; B[j][j] = alpha_j.
+struct GkShort {
+    double inv_alpha, alpha;
+    const double* q;
+    double* w;
+};
+
+__device__ __forceinline__ GkShort gk_short(const LzDesc& lz, const CellSet& Slong, int j) {
+    GkShort g;
+    g.alpha = sqrt(sum_parts(lz.lnp[j & 1], Slong.boxA));
+    g.inv_alpha = g.alpha > 1e-300 ? 1.0 / g.alpha : 0.0;
+    g.q = lz.Q + (long)j * lz.n;
+    g.w = lz.w;
+    return g;
+}
+
+// C2R of T2 row a, gathered on a set row (compact output) or written dense.
+template <typename T, int NMAX, int G, int SLOTS>
+__global__ void __launch_bounds__(G * SLOTS)
+k_row_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
+          const Item* __restrict__ items, int nitems, RowOutArgs args) {
+    __shared__ cplx<T> buf[SLOTS][NMAX + 1];
+    __shared__ int wtot[16];
+    const int slot = threadIdx.x / G, tid = threadIdx.x % G;
+    const int it = blockIdx.x * SLOTS + slot;
+    const bool valid = it < nitems;
+    const Item item = items[valid ? it : nitems - 1];
+    const OpDesc& op = ops[item.inst];
+    cplx<T>* s = buf[slot];
+    T* sr = reinterpret_cast<T*>(s);
+    const int a = item.idx;
+    const int n1 = op.prow.n + 1;
+    const cplx<T>* in = static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P;
+    for (int f = tid; f < n1; f += G) s[f] = in[f];
+    __syncthreads();
+    rfft_inv<T, NMAX, G>(s, op.prow, tid);
+    if (args.mode == OUT_IMAGE) {
+        if (!valid) return;
+        const ResDesc& rs = res[item.inst];
+        double* out = rs.recon + (long)item.comp * op.A * op.B + (long)a * op.B;
+        const double* W = op.W + (long)a * op.B;
+        for (int b = tid; b < op.B; b += G) {
+            const double w = W[b];
+            out[b] = w > 0 ? args.scale * static_cast<double>(sr[b]) / w : __builtin_nan("");
+        }
+        return;
+    }
+    const CellSet& S = op.S[args.set];
+    if (args.mode == OUT_LZ) {
+        const LzDesc& lz = lzs[item.inst];
+        const GkShort g = gk_short(lz, op.S[1 - args.set], args.j);
+        if (valid && a == 0 && tid == 0) lz.Bm[(long)args.j * kMaxBasis + args.j] = g.alpha;
+        scan_row<G>(S, a, op.MB, tid, wtot, [&](int b, long idx) {
+            if (valid && idx >= 0) g.w[idx] = static_cast<double>(sr[b]) * g.inv_alpha - g.alpha * g.q[idx];
+        });
+        return;
+    }
+    const ResDesc& rs = res[item.inst];
+    double* vout = (args.set == 0 ? rs.U : rs.V) + (long)item.comp * S.count;
+    double sc = args.scale;
+    if (args.div_sigma) sc /= rs.sigma[item.comp];
+    scan_row<G>(S, a, op.MB, tid, wtot, [&](int b, long idx) {
+        if (valid && idx >= 0) vout[idx] = sc * static_cast<double>(sr[b]);
+    });
+}
+
+// ------------------------------------------------------------------------
+// row family (window one row high): the sum across rows is direct
+// ------------------------------------------------------------------------
+
+
+// Per (instance, row a, component): v = C2R(Xh_a conj(U^)), mask to the
+// origin row a, then P_a = Xh_a conj(FFT(v)) into T2 slot comp row a.
+// U^ is the spectrum of the window row in T1 slot comp row 0.
+template <typename T, int NMAX, int G, int SLOTS>
+__global__ void __launch_bounds__(G * SLOTS)
+k_rowfam_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
+             const Item* __restrict__ items, int nitems, RowFamArgs args) {
+    __shared__ cplx<T> buf[SLOTS][NMAX + 1];
+    __shared__ int wtot[16];
+    __shared__ double red[16];
+    const int slot = threadIdx.x / G, tid = threadIdx.x % G;
+    const int it = blockIdx.x * SLOTS + slot;
+    const bool valid = it < nitems;
+    const Item item = items[valid ? it : nitems - 1];
+    const OpDesc& op = ops[item.inst];
+    cplx<T>* s = buf[slot];
+    T* sr = reinterpret_cast<T*>(s);
+    const int a = item.idx;
+    const int n1 = op.prow.n + 1;
+    const cplx<T>* uh = static_cast<const cplx<T>*>(op.T1) + item.comp * op.tslot;
+    const cplx<T>* xh = static_cast<const cplx<T>*>(op.Xh) + (long)a * op.P;
+    for (int f = tid; f < n1; f += G) s[f] = cmulc(xh[f], uh[f]);
+    __syncthreads();
+    rfft_inv<T, NMAX, G>(s, op.prow, tid);
+    const CellSet& S = op.S[1];
+    double* vout = nullptr;
+    double sc = 1.0;
+    if (args.emit == OUT_VEC && valid) {
+        const ResDesc& rs = res[item.inst];
+        vout = rs.V + (long)item.comp * S.count;
+        sc = 1.0 / rs.sigma[item.comp];
+    }
+    if (args.gk) {
+        const GkLong<T> g = gk_long<T>(lzs[item.inst], S, args.j, args.jstart);
+        double part = 0.0;
+        scan_row<G>(S, a, op.MB, tid, wtot, [&](int b, long idx) {
+            T v = T(0);
+            if (idx >= 0) {
+                v = sr[b] - g.gamma * g.lprev[idx];
+                if (valid) g.lcur[idx] = v;
+                part += static_cast<double>(v) * static_cast<double>(v);
+            }
+            sr[b] = v;
+        });
+        part = slot_sum<G>(part, red);
+        if (valid && tid == 0) g.lnp[a] = part;
+    } else {
+        scan_row<G>(S, a, op.MB, tid, wtot, [&](int b, long idx) {
+            T v = sr[b];
+            if (idx < 0) v = T(0);
+            else if (vout) vout[idx] = sc * static_cast<double>(v);
+            sr[b] = v;
+        });
+    }
+    if (!args.full) return;
+    __syncthreads();
+    rfft_fwd<T, NMAX, G>(s, op.prow, tid);
+    if (!valid) return;
+    cplx<T>* out = static_cast<cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P;
+    for (int f = tid; f < n1; f += G) out[f] = cmulc(xh[f], s[f]);
+}
+
+// Per (instance, component): sum_a P_a in row order, C2R, gather the window
+// row into the Lanczos w (OUT_LZ) or a result vector.
+template <typename T, int NMAX, int G, int SLOTS>
+__global__ void __launch_bounds__(G * SLOTS)
+k_rowfam_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs,
+             const Item* __restrict__ items, int nitems, RowOutArgs args) {
+    __shared__ cplx<T> buf[SLOTS][NMAX + 1];
+    __shared__ int wtot[16];
+    const int slot = threadIdx.x / G, tid = threadIdx.x % G;
+    const int it = blockIdx.x * SLOTS + slot;
+    const bool valid = it < nitems;
+    const Item item = items[valid ? it : nitems - 1];
+    const OpDesc& op = ops[item.inst];
+    cplx<T>* s = buf[slot];
+    T* sr = reinterpret_cast<T*>(s);
+    const int n1 = op.prow.n + 1;
+    const cplx<T>* pa = static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot;
+    for (int f = tid; f < n1; f += G) {
+        cplx<T> acc = {T(0), T(0)};
+        for (int a = 0; a < op.A; ++a) acc = cadd(acc, pa[(long)a * op.P + f]);
+        s[f] = acc;
+    }
+    __syncthreads();
+    rfft_inv<T, NMAX, G>(s, op.prow, tid);
+    const LzDesc& lz = lzs[item.inst];
+    const GkShort g = gk_short(lz, op.S[1], args.j);
+    if (valid && tid == 0) lz.Bm[(long)args.j * kMaxBasis + args.j] = g.alpha;
+    scan_row<G>(op.S[0], 0, op.MB, tid, wtot, [&](int b, long idx) {
+        if (valid && idx >= 0) g.w[idx] = static_cast<double>(sr[b]) * g.inv_alpha - g.alpha * g.q[idx];
+    });
+}
+
+// Row-family reconstruction of group `comp` on row a: for each i in the
+// group, FFT(sigma_i V_i row a) * U^_i summed, one C2R, divided by W.
+template <typename T, int NMAX, int G, int SLOTS>
+__global__ void __launch_bounds__(G * SLOTS)
+k_rowfam_recon(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
+               const Item* __restrict__ items, int nitems, double scale) {
+    __shared__ cplx<T> buf[SLOTS][NMAX + 1];
+    __shared__ int wtot[16];
+    constexpr int PER = cdiv(NMAX + 1, G);
+    const int slot = threadIdx.x / G, tid = threadIdx.x % G;
+    const int it = blockIdx.x * SLOTS + slot;
+    const bool valid = it < nitems;
+    const Item item = items[valid ? it : nitems - 1];
+    const OpDesc& op = ops[item.inst];
+    const ResDesc& rs = res[item.inst];
+    cplx<T>* s = buf[slot];
+    T* sr = reinterpret_cast<T*>(s);
+    const int a = item.idx;
+    const int n1 = op.prow.n + 1;
+    cplx<T> acc[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) acc[p] = {T(0), T(0)};
+    const int g0 = rs.gptr[item.comp], g1 = rs.gptr[item.comp + 1];
+    const CellSet& S = op.S[1];
+    for (int g = g0; g < g1; ++g) {
+        const int i = rs.gidx[g];
+        const double* v = rs.V + (long)i * S.count;
+        const double sg = rs.sigma[i];
+        scan_row<G>(S, a, op.MB, tid, wtot, [&](int b, long idx) {
+            sr[b] = idx >= 0 ? to<T>(sg * v[idx]) : T(0);
+        });
+        __syncthreads();
+        rfft_fwd<T, NMAX, G>(s, op.prow, tid);
+        const cplx<T>* uh = static_cast<const cplx<T>*>(op.Us) + (long)i * op.uslot;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int f = tid + p * G;
+            if (f < n1) acc[p] = cadd(acc[p], cmul(s[f], uh[f]));
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int f = tid + p * G;
+        if (f < n1) s[f] = acc[p];
+    }
+    __syncthreads();
+    rfft_inv<T, NMAX, G>(s, op.prow, tid);
+    if (!valid) return;
+    double* out = rs.recon + (long)item.comp * op.A * op.B + (long)a * op.B;
+    const double* W = op.W + (long)a * op.B;
+    for (int b = tid; b < op.B; b += G) {
+        const double w = W[b];
+        out[b] = w > 0 ? scale * static_cast<double>(sr[b]) / w : __builtin_nan("");
+    }
+}
+
+// Copies the first-row spectra of U components (T1 slot i, row 0) into Us.
+template <typename T>
+__global__ void k_copy_uspec(const OpDesc* __restrict__ ops, const Item* __restrict__ items, int nitems) {
+    const Item item = items[blockIdx.x];
+    const OpDesc& op = ops[item.inst];
+    const cplx<T>* src = static_cast<const cplx<T>*>(op.T1) + item.comp * op.tslot;
+    cplx<T>* dst = static_cast<cplx<T>*>(op.Us) + item.comp * op.uslot;
+    for (int f = threadIdx.x; f < op.P; f += blockDim.x) dst[f] = src[f];
+}
+
+// ------------------------------------------------------------------------
+// column kernel (grid family)
+// ------------------------------------------------------------------------
+
+
+
+// One workgroup transforms TC adjacent columns f0..f0+TC of a [rows][P]
+// array; each column is an independent length-MA transform on G threads.
+template <typename T, int NMAX, int G, int TC>
+__global__ void __launch_bounds__(G * TC)
+k_col(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
+      const Item* __restrict__ items, int nitems, ColArgs args) {
+    constexpr int LD = NMAX + 1;
+    constexpr int PER = cdiv(NMAX * TC, G * TC);
+    __shared__ cplx<T> buf[TC * LD];
+    const Item item = items[blockIdx.x];
+    const OpDesc& op = ops[item.inst];
+    const int f0 = item.idx * TC;
+    const int MA = op.MA, P = op.P;
+    const int nthr = G * TC;
+    const int c = threadIdx.x / G, tid = threadIdx.x % G;
+    cplx<T>* s = buf + c * LD;
+
+    auto load_rows = [&](const cplx<T>* src, int nin) {
+        // element e = a * TC + cc : consecutive threads take consecutive columns
+        for (int e = threadIdx.x; e < MA * TC; e += nthr) {
+            const int a = e / TC, cc = e % TC;
+            const int f = f0 + cc;
+            cplx<T> v = {T(0), T(0)};
+            if (a < nin && f < P) v = src[(long)a * P + f];
+            buf[cc * LD + a] = v;
+        }
+    };
+
+    if (args.mode == COL_ACCUM) {
+        const ResDesc& rs = res[item.inst];
+        const int g0 = rs.gptr[item.comp], g1 = rs.gptr[item.comp + 1];
+        cplx<T> acc[PER];
+#pragma unroll
+        for (int p = 0; p < PER; ++p) acc[p] = {T(0), T(0)};
+        for (int g = g0; g < g1; ++g) {
+            const int i = rs.gidx[g];
+            load_rows(static_cast<const cplx<T>*>(op.T1) + i * op.tslot, args.nin);
+            __syncthreads();
+            fft_lds<T, NMAX, G, -1>(s, op.pcol, tid);
+            const cplx<T>* uh = static_cast<const cplx<T>*>(op.Us) + (long)i * op.uslot;
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const int a = tid + p * G;
+                const int f = f0 + c;
+                if (a < MA && f < P) acc[p] = cadd(acc[p], cmul(s[a], uh[(long)f * MA + a]));
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int a = tid + p * G;
+            if (a < MA) s[a] = acc[p];
+        }
+        __syncthreads();
+        fft_lds<T, NMAX, G, +1>(s, op.pcol, tid);
+    } else {
+        load_rows(static_cast<const cplx<T>*>(op.T1) + item.comp * op.tslot, args.nin);
+        __syncthreads();
+        fft_lds<T, NMAX, G, -1>(s, op.pcol, tid);
+        if (args.mode == COL_SPEC || args.mode == COL_STORE) {
+            cplx<T>* dst = args.mode == COL_SPEC ? static_cast<cplx<T>*>(const_cast<void*>(op.Xh))
+                                                 : static_cast<cplx<T>*>(op.Us) + (long)item.comp * op.uslot;
+            const T scl = to<T>(args.mode == COL_SPEC ? args.scale : 1.0);
+            for (int e = threadIdx.x; e < MA * TC; e += nthr) {
+                const int cc = e / MA, a = e % MA;
+                const int f = f0 + cc;
+                if (f < P) {
+                    const cplx<T> v = buf[cc * LD + a];
+                    dst[(long)f * MA + a] = {v.x * scl, v.y * scl};
+                }
+            }
+            return;
+        }
+        // COL_CORR
+        const cplx<T>* xh = static_cast<const cplx<T>*>(op.Xh);
+        for (int e = threadIdx.x; e < MA * TC; e += nthr) {
+            const int cc = e / MA, a = e % MA;
+            const int f = f0 + cc;
+            if (f < P) buf[cc * LD + a] = cmulc(xh[(long)f * MA + a], buf[cc * LD + a]);
+        }
+        __syncthreads();
+        fft_lds<T, NMAX, G, +1>(s, op.pcol, tid);
+    }
+    cplx<T>* out = static_cast<cplx<T>*>(op.T2) + item.comp * op.tslot;
+    for (int e = threadIdx.x; e < args.nout * TC; e += nthr) {
+        const int a = e / TC, cc = e % TC;
+        const int f = f0 + cc;
+        if (f < P) out[(long)a * P + f] = buf[cc * LD + a];
+    }
+}
+
+// ------------------------------------------------------------------------
+// shape setup (once per decomposition)
+// ------------------------------------------------------------------------
+
+// N = mask AND not-NaN, xc = x on N else 0, and row prefix counts of N.
+// One workgroup (256 threads) per grid row.
+__global__ void __launch_bounds__(256)
+k_shape_clean(const OpDesc* __restrict__ ops, const Item* __restrict__ items, const double* const* xin,
+              const uint8_t* const* min, uint8_t* const* nset, double* const* xc, int* const* npref) {
+    __shared__ int wt[4];
+    __shared__ int carry;
+    const Item item = items[blockIdx.x];
+    const OpDesc& op = ops[item.inst];
+    const int a = item.idx, B = op.B;
+    const double* x = xin[item.inst] + (long)a * B;
+    const uint8_t* m = min[item.inst] ? min[item.inst] + (long)a * B : nullptr;
+    uint8_t* ns = nset[item.inst] + (long)a * B;
+    double* xo = xc[item.inst] + (long)a * B;
+    int* pref = npref[item.inst] + (long)a * (B + 1);
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < B; c0 += 256) {
+        const int b = c0 + threadIdx.x;
+        int in = 0;
+        if (b < B) {
+            const double v = x[b];
+            in = (m == nullptr || m[b] != 0) && !isnan(v);
+            ns[b] = (uint8_t)in;
+            xo[b] = in ? v : 0.0;
+        }
+        const unsigned long long bal = __ballot(in);
+        const int lane = lane_id(), wv = threadIdx.x >> 6;
+        const int r = __popcll(bal & ((1ULL << lane) - 1ULL));
+        if (lane == 0) wt[wv] = __popcll(bal);
+        __syncthreads();
+        int before = carry;
+        for (int q = 0; q < wv; ++q) before += wt[q];
+        if (b < B) pref[b] = before + r;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += wt[0] + wt[1] + wt[2] + wt[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) pref[B] = carry;
+}
+
+
+// Origins: count(k) = sum over window runs of N cells under the run; k is in
+// K when the count equals |L|.  Also the row prefix of the origin mask and
+// the per-row origin counts.  One workgroup per origin-box row.
+__global__ void __launch_bounds__(256)
+k_shape_origins(const OpDesc* __restrict__ ops, const Item* __restrict__ items, const Runs* __restrict__ runs,
+                const int* const* npref, uint8_t* const* kmask, int* const* kpref, int* const* kcount) {
+    __shared__ int wt[4];
+    __shared__ int carry;
+    const Item item = items[blockIdx.x];
+    const OpDesc& op = ops[item.inst];
+    const Runs& R = runs[item.inst];
+    const int a = item.idx;
+    const int KB = op.S[1].boxB, B = op.B;
+    const int* np = npref[item.inst];
+    uint8_t* km = kmask[item.inst] + (long)a * KB;
+    int* kp = kpref[item.inst] + (long)a * (KB + 1);
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < KB; c0 += 256) {
+        const int b = c0 + threadIdx.x;
+        int in = 0;
+        if (b < KB) {
+            long cnt = 0;
+            for (int t = 0; t < R.nrun; ++t) {
+                const int* pr = np + (long)(a + R.ra[t]) * (B + 1);
+                cnt += pr[b + R.b1[t]] - pr[b + R.b0[t]];
+            }
+            in = cnt == R.total;
+            km[b] = (uint8_t)in;
+        }
+        const unsigned long long bal = __ballot(in);
+        const int lane = lane_id(), wv = threadIdx.x >> 6;
+        const int r = __popcll(bal & ((1ULL << lane) - 1ULL));
+        if (lane == 0) wt[wv] = __popcll(bal);
+        __syncthreads();
+        int before = carry;
+        for (int q = 0; q < wv; ++q) before += wt[q];
+        if (b < KB) kp[b] = before + r;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += wt[0] + wt[1] + wt[2] + wt[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        kp[KB] = carry;
+        kcount[item.inst][a] = carry;
+    }
+}
+
+// Exclusive scan of per-row origin counts into row offsets (one workgroup
+// per instance, sequential over rows in chunks).
+__global__ void __launch_bounds__(256)
+k_shape_rowoff(int ninst, const int* const* kcount, int* const* rowoff, const int* nrows, long* total) {
+    const int inst = blockIdx.x;
+    if (inst >= ninst) return;
+    __shared__ long wsum[4];
+    __shared__ long carry;
+    const int n = nrows[inst];
+    const int* cnt = kcount[inst];
+    int* ro = rowoff[inst];
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < n; c0 += 256) {
+        const int i = c0 + threadIdx.x;
+        long v = i < n ? cnt[i] : 0;
+        // inclusive wave scan
+        const int lane = lane_id(), wv = threadIdx.x >> 6;
+        long x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            long y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        long before = carry;
+        for (int q = 0; q < wv; ++q) before += wsum[q];
+        if (i < n) ro[i] = (int)(before + x - v);
+        __syncthreads();
+        if (threadIdx.x == 0) carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ro[n] = (int)carry;
+        total[inst] = carry;
+    }
+}
+
+// Weights W(alpha) = #{ l in L : alpha - l in K }, by run sums over the row
+// prefix of the origin mask.  One workgroup per grid row.
+__global__ void __launch_bounds__(256)
+k_shape_weights(const OpDesc* __restrict__ ops, const Item* __restrict__ items, const Runs* __restrict__ runs,
+                const int* const* kpref, double* const* Wout) {
+    const Item item = items[blockIdx.x];
+    const OpDesc& op = ops[item.inst];
+    const Runs& R = runs[item.inst];
+    const int a = item.idx, B = op.B;
+    const int KA = op.S[1].boxA, KB = op.S[1].boxB;
+    const int* kp = kpref[item.inst];
+    double* W = Wout[item.inst] + (long)a * B;
+    for (int b = threadIdx.x; b < B; b += 256) {
+        long cnt = 0;
+        for (int t = 0; t < R.nrun; ++t) {
+            const int ka = a - R.ra[t];
+            if (ka < 0 || ka >= KA) continue;
+            // k_b in (b - b1, b - b0]  intersected with [0, KB)
+            int lo = b - R.b1[t] + 1, hi = b - R.b0[t] + 1;   // [lo, hi)
+            if (lo < 0) lo = 0;
+            if (hi > KB) hi = KB;
+            if (hi > lo) {
+                const int* pr = kp + (long)ka * (KB + 1);
+                cnt += pr[hi] - pr[lo];
+            }
+        }
+        W[b] = (double)cnt;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Lanczos (FP64): classical Gram-Schmidt applied twice against the basis
+// ------------------------------------------------------------------------
+
+// Deterministic start vector: hash of (seed, index) mapped to [-1, 1); the
+// first step normalises it.
+__device__ __forceinline__ double hash_unit(unsigned long long seed, unsigned long long i) {
+    unsigned long long z = seed * 0x9E3779B97F4A7C15ULL + i + 0x632BE59BD9B4E019ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__global__ void __launch_bounds__(256)
+k_lz_start(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, unsigned long long seed) {
+    __shared__ double red[4];
+    const Item item = items[blockIdx.x];
+    const LzDesc& lz = lzs[item.inst];
+    const long i = (long)item.idx * kLzRows + threadIdx.x;
+    double v = 0.0;
+    if (i < lz.n) {
+        v = hash_unit(seed, (unsigned long long)i);
+        lz.w[i] = v;
+    }
+    const double p = wave_sum(v * v);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = p;
+    __syncthreads();
+    if (threadIdx.x == 0) lz.np[item.idx] = red[0] + red[1] + red[2] + red[3];
+    // clear the projected matrix and the long norms of the previous step
+    if (item.idx == 0) {
+        for (int e = threadIdx.x; e < kMaxBasis * kMaxBasis; e += 256) lz.Bm[e] = 0.0;
+    }
+}
+
+// hp[blk][c] = sum over the block's rows of Q[:, c] * w, c < ncols.
+__device__ __forceinline__ void lz_project_block(const LzDesc& lz, int blk, int ncols, const double* w,
+                                                 double* hp, double (*red)[kMaxBasis + 1]) {
+    const long i = (long)blk * kLzRows + threadIdx.x;
+    const double wi = i < lz.n ? w[i] : 0.0;
+    const int wv = threadIdx.x >> 6;
+    for (int c = 0; c < ncols; ++c) {
+        const double q = i < lz.n ? lz.Q[(long)c * lz.n + i] : 0.0;
+        const double p = wave_sum(q * wi);
+        if (lane_id() == 0) red[wv][c] = p;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < ncols; c += 256)
+        hp[(long)blk * (kMaxBasis + 1) + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+}
+
+__global__ void __launch_bounds__(256)
+k_lz_proj(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int ncols) {
+    __shared__ double red[4][kMaxBasis + 1];
+    const Item item = items[blockIdx.x];
+    const LzDesc& lz = lzs[item.inst];
+    lz_project_block(lz, item.idx, ncols, lz.w, lz.hp1, red);
+}
+
+// Classical Gram-Schmidt, second half of each pass (one-sided: the
+// coefficients are discarded, they are rounding-level terms):
+// pass 1: h = sum of hp1 partials; w -= Q h; hp2 = partial projections of w.
+// pass 2: h = sum of hp2 partials; w -= Q h; np = partial |w|^2.
+__global__ void __launch_bounds__(256)
+k_lz_update(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int ncols, int pass) {
+    __shared__ double h[kMaxBasis + 1];
+    __shared__ double red[4][kMaxBasis + 1];
+    const Item item = items[blockIdx.x];
+    const LzDesc& lz = lzs[item.inst];
+    const double* hp = pass == 1 ? lz.hp1 : lz.hp2;
+    for (int c = threadIdx.x; c < ncols; c += 256) {
+        double s = 0.0;
+        for (int q = 0; q < lz.nblk; ++q) s += hp[(long)q * (kMaxBasis + 1) + c];
+        h[c] = s;
+    }
+    __syncthreads();
+    const long i = (long)item.idx * kLzRows + threadIdx.x;
+    double wi = 0.0;
+    if (i < lz.n) {
+        wi = lz.w[i];
+        double acc = 0.0;
+        for (int c = 0; c < ncols; ++c) acc += lz.Q[(long)c * lz.n + i] * h[c];
+        wi -= acc;
+        lz.w[i] = wi;
+    }
+    if (pass == 1) {
+        __syncthreads();
+        lz_project_block(lz, item.idx, ncols, lz.w, lz.hp2, red);
+        return;
+    }
+    const double p = wave_sum(wi * wi);
+    if (lane_id() == 0) red[threadIdx.x >> 6][0] = p;
+    __syncthreads();
+    if (threadIdx.x == 0) lz.np[item.idx] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+}
+
+// q_m = w / beta into column m of Q; beta -> lz.beta[0].
+__global__ void __launch_bounds__(256)
+k_lz_normalize(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m) {
+    const Item item = items[blockIdx.x];
+    const LzDesc& lz = lzs[item.inst];
+    const double beta = sqrt(sum_parts(lz.np, lz.nblk));
+    const double sc = beta > 1e-300 ? 1.0 / beta : 0.0;
+    const long i = (long)item.idx * kLzRows + threadIdx.x;
+    if (i < lz.n) lz.Q[(long)m * lz.n + i] = lz.w[i] * sc;
+    if (item.idx == 0 && threadIdx.x == 0) lz.beta[0] = beta;
+}
+
+// SVD of the m x m projected matrix by one-sided (Hestenes) Jacobi, one
+// workgroup of 1024 threads per instance: the columns of B are held in LDS
+// and rotated pairwise in round-robin order (16 threads per pair) until all
+// pairs are orthogonal; the right singular vectors accumulate in Yr.  The
+// singular values are the column norms, the left vectors the normalised
+// columns.  Then the values are ranked (descending) and the residual test
+// beta |Yr[m-1, i]| <= tol * sigma_1 is evaluated for the r leading ones.
+__global__ void __launch_bounds__(1024)
+k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, int max_sweeps) {
+    __shared__ double Bs[kMaxBasis * kMaxBasis];
+    __shared__ double cn[kMaxBasis];
+    __shared__ int changed;
+    const Item item = items[blockIdx.x];
+    const LzDesc& lz = lzs[item.inst];
+    const int nt = blockDim.x;
+    for (int e = threadIdx.x; e < m * m; e += nt) {
+        const int i = e % m, c = e / m;
+        Bs[c * m + i] = lz.Bm[(long)c * kMaxBasis + i];
+        lz.Yr[(long)c * kMaxBasis + i] = i == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int nn = m + (m & 1);
+    const int npairs = nn / 2;
+    const int t = threadIdx.x >> 4, g = threadIdx.x & 15;
+    int sweep = 0;
+    for (; sweep < max_sweeps; ++sweep) {
+        if (threadIdx.x == 0) changed = 0;
+        __syncthreads();
+        for (int rd = 0; rd < nn - 1; ++rd) {
+            if (t < npairs) {
+                int a, b;
+                if (t == 0) { a = nn - 1; b = rd % (nn - 1); }
+                else { a = (rd + t) % (nn - 1); b = (rd - t + (nn - 1)) % (nn - 1); }
+                const int p = a < b ? a : b, q = a < b ? b : a;
+                if (q < m) {
+                    double* bp = Bs + p * m;
+                    double* bq = Bs + q * m;
+                    double al = 0.0, be = 0.0, ga = 0.0;
+                    for (int i = g; i < m; i += 16) {
+                        const double x1 = bp[i], x2 = bq[i];
+                        al += x1 * x1; be += x2 * x2; ga += x1 * x2;
+                    }
+#pragma unroll
+                    for (int o = 8; o > 0; o >>= 1) {
+                        al += __shfl_xor(al, o, 16);
+                        be += __shfl_xor(be, o, 16);
+                        ga += __shfl_xor(ga, o, 16);
+                    }
+                    if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+                        const double ze = (be - al) / (2.0 * ga);
+                        const double tt = (ze >= 0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+                        const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+                        for (int i = g; i < m; i += 16) {
+                            const double x1 = bp[i], x2 = bq[i];
+                            bp[i] = c * x1 - s * x2;
+                            bq[i] = s * x1 + c * x2;
+                        }
+                        double* yp = lz.Yr + (long)p * kMaxBasis;
+                        double* yq = lz.Yr + (long)q * kMaxBasis;
+                        for (int i = g; i < m; i += 16) {
+                            const double y1 = yp[i], y2 = yq[i];
+                            yp[i] = c * y1 - s * y2;
+                            yq[i] = s * y1 + c * y2;
+                        }
+                        if (g == 0) changed = 1;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (!changed) break;
+    }
+    for (int c = threadIdx.x; c < m; c += nt) {
+        double s2 = 0.0;
+        for (int i = 0; i < m; ++i) s2 += Bs[c * m + i] * Bs[c * m + i];
+        cn[c] = sqrt(s2);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * m; e += nt) {
+        const int i = e % m, c = e / m;
+        lz.Yl[(long)c * kMaxBasis + i] = cn[c] > 0 ? Bs[c * m + i] / cn[c] : 0.0;
+    }
+    for (int i = threadIdx.x; i < m; i += nt) {
+        const double ti = cn[i];
+        int rank = 0;
+        for (int k = 0; k < m; ++k) {
+            const double tk = cn[k];
+            rank += (tk > ti) || (tk == ti && k < i);
+        }
+        lz.perm[rank] = i;
+        lz.sig[rank] = ti;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double beta = lz.beta[0];
+        const double s1 = lz.sig[0];
+        int ok = 1;
+        double worst = 0.0;
+        for (int i = 0; i < lz.r; ++i) {
+            const double resid = fabs(beta * lz.Yr[(long)lz.perm[i] * kMaxBasis + (m - 1)]);
+            if (!(resid <= lz.tol * s1)) ok = 0;
+            worst = fmax(worst, s1 > 0 ? resid / s1 : 0.0);
+        }
+        lz.flag[0] = ok;
+        lz.flag[1] = sweep;
+        lz.beta[1] = worst;
+    }
+}
+
+// Ritz rotation out[:, 0:k] = Q[:, 0:m] * Yl[:, perm[0:k]] (FP64).
+// Workgroup = 64 rows x 16 output columns (4 per thread).
+__global__ void __launch_bounds__(256)
+k_lz_ritz(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, int k, double* const* outs) {
+    __shared__ double Ys[kMaxBasis][17];
+    const Item item = items[blockIdx.x];
+    const LzDesc& lz = lzs[item.inst];
+    double* out = outs ? outs[item.inst] : lz.Qtmp;
+    const int c0 = item.aux * 16;
+    for (int e = threadIdx.x; e < m * 16; e += 256) {
+        const int i = e / 16, cc = e % 16;
+        const int c = c0 + cc;
+        Ys[i][cc] = c < k ? lz.Yl[(long)lz.perm[c] * kMaxBasis + i] : 0.0;
+    }
+    __syncthreads();
+    const long row = (long)item.idx * 64 + (threadIdx.x & 63);
+    const int cb = (threadIdx.x >> 6) * 4;
+    if (row >= lz.n) return;
+    double acc[4] = {0, 0, 0, 0};
+    for (int i = 0; i < m; ++i) {
+        const double q = lz.Q[(long)i * lz.n + row];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] += q * Ys[i][cb + t];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int c = c0 + cb + t;
+        if (c < k) out[(long)c * lz.n + row] = acc[t];
+    }
+}
+
+// Thick restart keeping k Ritz triplets (u_i = Q Yl_i, sigma_i, and the
+// implicit right vector v_i = X^T u_i / sigma_i):
+//   Q[:, 0:k] = Qtmp, Q[:, k] = q_m,
+//   B = diag(sigma_0..k-1) with row k = rho_i = beta * Yr[m-1, i],
+//   sin = q_m - sum_i (rho_i / sigma_i) u_i, so that X^T sin equals
+//   X^T q_m - sum_i rho_i v_i, the coupling the next step must remove.
+__global__ void __launch_bounds__(256)
+k_lz_restart(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, int k) {
+    __shared__ double coef[kMaxBasis];
+    const Item item = items[blockIdx.x];
+    const LzDesc& lz = lzs[item.inst];
+    const double beta = lz.beta[0];
+    const double s1 = lz.sig[0];
+    for (int c = threadIdx.x; c < k; c += 256) {
+        const double sg = lz.sig[c];
+        const double rho = beta * lz.Yr[(long)lz.perm[c] * kMaxBasis + (m - 1)];
+        coef[c] = sg > 1e-13 * s1 ? rho / sg : 0.0;
+    }
+    __syncthreads();
+    const long i = (long)item.idx * kLzRows + threadIdx.x;
+    if (i < lz.n) {
+        const double qm = lz.Q[(long)m * lz.n + i];
+        double acc = qm;
+        for (int c = 0; c < k; ++c) {
+            const double u = lz.Qtmp[(long)c * lz.n + i];
+            lz.Q[(long)c * lz.n + i] = u;
+            acc -= coef[c] * u;
+        }
+        lz.Q[(long)k * lz.n + i] = qm;
+        lz.sin[i] = acc;
+    }
+    if (item.idx == 0) {
+        for (int e = threadIdx.x; e < kMaxBasis * kMaxBasis; e += 256) {
+            const int a = e % kMaxBasis, b = e / kMaxBasis;   // row a, column b
+            double v = 0.0;
+            if (a == b && a < k) v = lz.sig[a];
+            else if (a == k && b < k) {
+                const double sg = lz.sig[b];
+                v = sg > 1e-13 * s1 ? beta * lz.Yr[(long)lz.perm[b] * kMaxBasis + (m - 1)] : 0.0;
+            }
+            lz.Bm[e] = v;
+        }
+    }
+}
+
+// sigma_i, i < r.
+__global__ void k_lz_sigma(const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
+                           const Item* __restrict__ items) {
+    const int inst = items[blockIdx.x].inst;
+    for (int i = threadIdx.x; i < lzs[inst].r; i += blockDim.x) res[inst].sigma[i] = lzs[inst].sig[i];
+}
+
+// Sign rule: flip (U_i, V_i) so that U_i's entry of largest magnitude is
+// positive (first such entry in the internal order on ties).
+__global__ void __launch_bounds__(256)
+k_sign_fix(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res, const Item* __restrict__ items) {
+    __shared__ double bv[256];
+    __shared__ long bi[256];
+    const Item item = items[blockIdx.x];
+    const OpDesc& op = ops[item.inst];
+    const ResDesc& rs = res[item.inst];
+    const long L = op.S[0].count, K = op.S[1].count;
+    double* u = rs.U + (long)item.comp * L;
+    double* v = rs.V + (long)item.comp * K;
+    double best = -1.0;
+    long arg = 0;
+    for (long i = threadIdx.x; i < L; i += 256) {
+        const double a = fabs(u[i]);
+        if (a > best) { best = a; arg = i; }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = arg;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const double b2 = bv[threadIdx.x + o];
+            const long i2 = bi[threadIdx.x + o];
+            if (b2 > bv[threadIdx.x] || (b2 == bv[threadIdx.x] && i2 < bi[threadIdx.x])) {
+                bv[threadIdx.x] = b2;
+                bi[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    const bool flip = u[bi[0]] < 0;
+    __syncthreads();
+    if (!flip) return;
+    for (long i = threadIdx.x; i < L; i += 256) u[i] = -u[i];
+    for (long i = threadIdx.x; i < K; i += 256) v[i] = -v[i];
+}
+
+// out[c][r] = in[r][c] for nmat consecutive R x C matrices (layout change
+// between the caller's orientation and the internal one).
+__global__ void __launch_bounds__(256) k_transpose(const double* __restrict__ in, double* __restrict__ out,
+                                                   int R, int C) {
+    __shared__ double tile[32][33];
+    const long off = (long)blockIdx.z * R * C;
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        const int r = r0 + k, c = c0 + threadIdx.x;
+        if (r < R && c < C) tile[k][threadIdx.x] = in[off + (long)r * C + c];
+    }
+    __syncthreads();
+    for (int k = threadIdx.y; k < 32; k += 8) {
+        const int c = c0 + k, r = r0 + threadIdx.x;
+        if (r < R && c < C) out[off + (long)c * R + r] = tile[threadIdx.x][k];
+    }
+}
+
+}  // namespace shssa
+
+#include "launch.inc"

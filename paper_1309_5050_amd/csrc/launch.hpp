@@ -1,0 +1,46 @@
+// Declarations of the kernel launch wrappers (defined with the kernels).
+#pragma once
+#include "device.hpp"
+
+namespace shssa {
+
+int row_class(int n, bool f64);
+int row_slots(int cls);
+int col_tile(bool f64);
+
+void launch_row_in(bool f64, int cls, int nitems, hipStream_t st, const OpDesc* ops, const LzDesc* lzs,
+                   const ResDesc* res, const Item* items, RowInArgs a);
+void launch_row_mid(bool f64, int cls, int nitems, hipStream_t st, const OpDesc* ops, const LzDesc* lzs,
+                    const ResDesc* res, const Item* items, RowMidArgs a);
+void launch_row_out(bool f64, int cls, int nitems, hipStream_t st, const OpDesc* ops, const LzDesc* lzs,
+                    const ResDesc* res, const Item* items, RowOutArgs a);
+void launch_rowfam_mid(bool f64, int cls, int nitems, hipStream_t st, const OpDesc* ops, const LzDesc* lzs,
+                       const ResDesc* res, const Item* items, RowFamArgs a);
+void launch_rowfam_out(bool f64, int cls, int nitems, hipStream_t st, const OpDesc* ops, const LzDesc* lzs,
+                       const Item* items, RowOutArgs a);
+void launch_rowfam_recon(bool f64, int cls, int nitems, hipStream_t st, const OpDesc* ops, const ResDesc* res,
+                         const Item* items, double scale);
+void launch_copy_uspec(bool f64, int nitems, hipStream_t st, const OpDesc* ops, const Item* items);
+void launch_col(bool f64, int nitems, hipStream_t st, const OpDesc* ops, const ResDesc* res, const Item* items,
+                ColArgs a);
+void launch_shape_clean(int nitems, hipStream_t st, const OpDesc* ops, const Item* items, const double* const* x,
+                        const uint8_t* const* m, uint8_t* const* nset, double* const* xc, int* const* npref);
+void launch_shape_origins(int nitems, hipStream_t st, const OpDesc* ops, const Item* items, const Runs* runs,
+                          const int* const* npref, uint8_t* const* kmask, int* const* kpref, int* const* kcount);
+void launch_shape_rowoff(int ninst, hipStream_t st, const int* const* kcount, int* const* rowoff, const int* nrows,
+                         long* total);
+void launch_shape_weights(int nitems, hipStream_t st, const OpDesc* ops, const Item* items, const Runs* runs,
+                          const int* const* kpref, double* const* W);
+void launch_lz_start(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, unsigned long long seed);
+void launch_lz_proj(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int ncols);
+void launch_lz_update(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int ncols, int pass);
+void launch_lz_normalize(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int m);
+void launch_lz_svd(int ninst, hipStream_t st, const LzDesc* lzs, const Item* items, int m, int max_sweeps);
+void launch_lz_ritz(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int m, int k,
+                    double* const* outs);
+void launch_lz_restart(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int m, int k);
+void launch_lz_sigma(int ninst, hipStream_t st, const LzDesc* lzs, const ResDesc* res, const Item* items);
+void launch_sign_fix(int nitems, hipStream_t st, const OpDesc* ops, const ResDesc* res, const Item* items);
+void launch_transpose(int nmat, int R, int C, hipStream_t st, const double* in, double* out);
+
+}  // namespace shssa
