@@ -93,6 +93,8 @@ typedef struct ssa_stats {
 /* Context: device, stream (hipStream_t, NULL = the library makes one) and a
  * device-memory budget in bytes (0 = no limit). */
 int  ssa_ctx_create(int device, size_t mem_budget, void* stream, ssa_ctx** out);
+/* Releases the context; if handles made from it are still alive, the release
+ * happens when the last of them is freed. */
 void ssa_ctx_destroy(ssa_ctx* ctx);
 int  ssa_ctx_set_stream(ssa_ctx* ctx, void* stream);
 
@@ -156,6 +158,15 @@ const char* ssa_last_error(void);
 
 /* Blocks until all work queued on the context's stream is complete. */
 int ssa_ctx_sync(ssa_ctx* ctx);
+
+/* Kernel timing with HIP events on the context's stream.  kind names one
+ * kernel class ("col", "row_in", "row_mid", "row_out", "rowfam_mid",
+ * "rowfam_out", "lz_proj", "lz_update"); NULL or "" stops recording.
+ * ssa_ctx_profile_read synchronises the stream, returns the summed event
+ * time of the recorded launches (ms), their number and their algorithmic
+ * bytes (data each launch must read and write), and clears the record. */
+int ssa_ctx_profile(ssa_ctx* ctx, const char* kind);
+int ssa_ctx_profile_read(ssa_ctx* ctx, double* ms, long* launches, double* bytes);
 
 #ifdef __cplusplus
 }

@@ -68,6 +68,7 @@ def lib():
         L.orc_reconstruct_at.argtypes = [C.c_int, _i, _i, C.c_int, C.c_int,
                                          np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS"),
                                          C.c_long, C.c_int, _d, _d, _d, C.c_int, _i, C.c_long, _i, _i, _d]
+        L.orc_gram_rows.argtypes = [C.c_long, C.c_long, _d, C.c_long, C.c_long, _d]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -229,6 +230,15 @@ def svd(X, method: str = "jacobi", tol: float = 1e-14, max_sweeps: int = 100, nv
     U = Ucm.reshape(d, m).T.copy()
     V = Vcm.reshape(d, n).T.copy()
     return sig, U, V
+
+
+def gram_rows(X, r0: int, r1: int) -> np.ndarray:
+    """Rows r0..r1-1 of S = X X^T by explicit sums (used for timing)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    m, n = X.shape
+    out = np.zeros((r1 - r0, m))
+    lib().orc_gram_rows(m, n, X, r0, r1, out)
+    return out
 
 
 def reconstruct(sh: Shapes, sigma, U, V, group) -> np.ndarray:

@@ -542,6 +542,16 @@ void orc_reconstruct_at(int nl, const int *li, const int *lj, int kx, int ky,
     }
 }
 
+/* Rows [r0, r1) of S = X X^T (all columns), X m x n row-major; S_out is
+ * (r1-r0) x m row-major.  Same plain sums as the full Gram formation. */
+void orc_gram_rows(long m, long n, const double *X, long r0, long r1, double *S_out)
+{
+    #pragma omp parallel for schedule(dynamic, 1) collapse(2)
+    for (long i = r0; i < r1; ++i)
+        for (long j = 0; j < m; ++j)
+            S_out[(i - r0) * m + j] = dot(X + i * n, X + j * n, n);
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -125,6 +125,15 @@ class Context:
     def set_stream(self, stream):
         check(lib().ssa_ctx_set_stream(self._h, stream), "ssa_ctx_set_stream")
 
+    def profile(self, kind):
+        """Start (kind = kernel class name) or stop (None) event timing."""
+        check(lib().ssa_ctx_profile(self._h, None if kind is None else kind.encode()), "ssa_ctx_profile")
+
+    def profile_read(self) -> dict:
+        ms, n, b = C.c_double(), C.c_long(), C.c_double()
+        check(lib().ssa_ctx_profile_read(self._h, C.byref(ms), C.byref(n), C.byref(b)), "ssa_ctx_profile_read")
+        return {"ms": ms.value, "launches": n.value, "bytes": b.value}
+
     # ---- decomposition -------------------------------------------------
 
     @staticmethod

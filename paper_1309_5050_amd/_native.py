@@ -36,6 +36,9 @@ _SIGS = {
     "ssa_ctx_destroy": (None, [C.c_void_p]),
     "ssa_ctx_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "ssa_ctx_sync": (C.c_int, [C.c_void_p]),
+    "ssa_ctx_profile": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "ssa_ctx_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_long),
+                                       C.POINTER(C.c_double)]),
     "ssa_decompose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
                                 C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]),
     "ssa_decompose_multi": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p, C.c_int, C.c_int,
@@ -62,9 +65,17 @@ _SIGS = {
 
 
 def lib():
-    """Load libshssa.so (raises if it has not been built)."""
+    """Load libshssa.so (raises if it has not been built).
+
+    PyTorch is imported first when it is installed: its wheel carries its own
+    HIP runtime under the same soname, and the library must bind to that one
+    so that torch's streams and device buffers are valid in its calls."""
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIBPATH):
             raise RuntimeError("libshssa.so is not built: run __graft_entry__.build() "
                                "or python paper_1309_5050_amd/build.py")

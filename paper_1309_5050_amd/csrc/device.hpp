@@ -38,6 +38,7 @@ struct LzDesc {
     int active;
     int r;              // triplets wanted
     double tol;         // stop when beta |q_i[m-1]| <= tol * sigma_1 for i < r
+    double eps;         // breakdown threshold relative to the largest alpha / beta seen
     long n;             // short vector length
     long nl;            // long vector length
     double* Q;          // short basis n x (kMaxBasis+1), column-major (ld n)
@@ -53,8 +54,10 @@ struct LzDesc {
     double* Yr;         // right singular vectors of Bm
     double* sig;        // singular values of Bm, descending
     int* perm;          // column order of the descending singular values
-    double* beta;       // [0] residual norm after the last step, [1] worst residual / sigma_1
-    int* flag;          // [0] converged, [1] sweeps of the last small SVD
+    double* beta;       // [0] residual norm after the last step, [1] worst residual / sigma_1,
+                        // [2], [3] running scale (largest alpha, beta) by step parity
+    int* flag;          // [0] converged, [1] sweeps of the last small SVD, [2] breakdown in
+                        // this cycle, [3] the cycle started from a fresh random vector
     double* Qtmp;       // n x kMaxBasis (Ritz rotation target)
     int nblk;
 };
@@ -116,6 +119,7 @@ struct RowOutArgs {
     double scale;
     int div_sigma;
     int j;            // OUT_LZ: bidiagonalisation step
+    int jstart;       // first step of the current cycle
 };
 
 struct RowFamArgs {

@@ -8,6 +8,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -75,12 +77,77 @@ bool make_plan(int n, FftPlan& pl) {
 
 struct ssa_ctx {
     int device = 0;
+    int refs = 0;            // live decompositions (guarded by mu)
+    bool closing = false;    // ssa_ctx_destroy called; delete when refs drops to 0
     hipStream_t st = nullptr;
     bool own = false;
     size_t budget = 0;
     size_t used = 0;
     std::mutex mu;
     std::map<std::tuple<int, int, int>, void*> tw;   // (n, f64, real split) -> table
+    // kernel timing (see ssa_ctx_profile)
+    std::string prof_kind;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> spans;
+    double prof_bytes = 0.0;
+    long prof_launches = 0;
+
+    int prof_event() {
+        const int k = (int)(spans.size() * 2 + (ev_pending ? 1 : 0));
+        while ((int)ev_pool.size() <= k) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
+            ev_pool.push_back(e);
+        }
+        return k;
+    }
+    bool ev_pending = false;
+
+    // Device memory pool: freed blocks are kept per size class and handed
+    // out again, so steady-state work never calls hipMalloc/hipFree (hipFree
+    // synchronises the device).
+    std::map<size_t, std::vector<void*>> pool;
+    size_t pooled = 0;
+
+    static size_t size_class(size_t b) {
+        if (b <= 4096) return 4096;
+        const int lg = 63 - __builtin_clzll(b);
+        const size_t q = (size_t)1 << (lg - 2);
+        return (b + q - 1) / q * q;
+    }
+    // caller holds mu
+    bool nopool = std::getenv("SHSSA_NO_POOL") != nullptr;
+    void* pool_get(size_t cls) {
+        if (nopool) {
+            void* p = nullptr;
+            return hipMalloc(&p, cls) == hipSuccess ? p : nullptr;
+        }
+        auto it = pool.find(cls);
+        if (it != pool.end() && !it->second.empty()) {
+            void* p = it->second.back();
+            it->second.pop_back();
+            pooled -= cls;
+            return p;
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, cls) != hipSuccess) {
+            // release the pool and try once more
+            for (auto& kv : pool)
+                for (void* q : kv.second) (void)hipFree(q);
+            pool.clear();
+            pooled = 0;
+            if (hipMalloc(&p, cls) != hipSuccess) return nullptr;
+        }
+        return p;
+    }
+    void pool_put(void* p, size_t cls) {
+        if (nopool) {
+            (void)hipFree(p);
+            return;
+        }
+        pool[cls].push_back(p);
+        pooled += cls;
+    }
 
     // twiddles exp(-2 pi i t / N) for t = 0..cnt-1 (N = n, or 2n for the split)
     int twiddles(int n, bool f64, bool split, const void** out) {
@@ -137,8 +204,8 @@ struct ssa_decomp {
     std::vector<int> ra, rb0, rb1;   // window runs (internal)
     std::vector<uint8_t> kmask_h;    // internal KA x KB (fetched on demand)
     std::vector<double> sigma_h;
-    // device memory
-    std::vector<void*> allocs;
+    // device memory (blocks of the context pool, with their size class)
+    std::vector<std::pair<void*, size_t>> allocs;
     size_t bytes = 0;
     double *x = nullptr, *xc = nullptr, *W = nullptr;
     uint8_t *mask = nullptr, *nset = nullptr, *kmask = nullptr, *lmask = nullptr;
@@ -157,31 +224,24 @@ struct ssa_decomp {
     Runs rn{};
     ssa_stats st{};
 
-    ~ssa_decomp() {
-        for (void* p : allocs) (void)hipFree(p);
-        if (ctx) {
-            std::lock_guard<std::mutex> g(ctx->mu);
-            ctx->used -= std::min(ctx->used, bytes);
-        }
+    ~ssa_decomp();
+    void attach(ssa_ctx* c) {
+        ctx = c;
+        std::lock_guard<std::mutex> g(c->mu);
+        c->refs++;
     }
 
     template <typename T>
     int dalloc(T** p, size_t count) {
-        const size_t b = std::max<size_t>(count, 1) * sizeof(T);
-        {
-            std::lock_guard<std::mutex> g(ctx->mu);
-            if (ctx->budget && ctx->used + b > ctx->budget)
-                return fail(SSA_ENOMEM, "device memory budget exhausted");
-            ctx->used += b;
-        }
-        void* q = nullptr;
-        if (hipMalloc(&q, b) != hipSuccess) {
-            std::lock_guard<std::mutex> g(ctx->mu);
-            ctx->used -= b;
-            return fail(SSA_ENOMEM, "hipMalloc failed");
-        }
-        allocs.push_back(q);
-        bytes += b;
+        const size_t cls = ssa_ctx::size_class(std::max<size_t>(count, 1) * sizeof(T));
+        std::lock_guard<std::mutex> g(ctx->mu);
+        if (ctx->budget && ctx->used + cls > ctx->budget)
+            return fail(SSA_ENOMEM, "device memory budget exhausted");
+        void* q = ctx->pool_get(cls);
+        if (!q) return fail(SSA_ENOMEM, "hipMalloc failed");
+        ctx->used += cls;
+        allocs.push_back({q, cls});
+        bytes += cls;
         *p = static_cast<T*>(q);
         return SSA_OK;
     }
@@ -191,12 +251,41 @@ struct ssa_decomp {
 
 namespace {
 
+void ctx_release(ssa_ctx* ctx) {
+    (void)hipStreamSynchronize(ctx->st);
+    for (auto& kv : ctx->tw) (void)hipFree(kv.second);
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (auto& kv : ctx->pool)
+        for (void* q : kv.second) (void)hipFree(q);
+    if (ctx->own) (void)hipStreamDestroy(ctx->st);
+    delete ctx;
+}
+
+}  // namespace
+
+// A handle returns its device blocks to the context pool; the context itself
+// is released with its last handle once ssa_ctx_destroy has been called.
+ssa_decomp::~ssa_decomp() {
+    if (!ctx) return;
+    bool last = false;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        for (auto& a : allocs) ctx->pool_put(a.first, a.second);
+        ctx->used -= std::min(ctx->used, bytes);
+        ctx->refs--;
+        last = ctx->closing && ctx->refs == 0;
+    }
+    if (last) ctx_release(ctx);
+}
+
+namespace {
+
 // Validate a request and compute the internal geometry (host side only).
 int plan_request(ssa_ctx* ctx, const ssa_request& q, ssa_decomp* d) {
     if (q.nx <= 0 || q.ny <= 0 || q.lx <= 0 || q.ly <= 0) return fail(SSA_EINVAL, "sizes must be positive");
     if (!q.x) return fail(SSA_EINVAL, "x is NULL");
     if (q.precision != SSA_FP64 && q.precision != SSA_FP32) return fail(SSA_EINVAL, "unknown precision");
-    d->ctx = ctx;
+    d->attach(ctx);
     d->nx = q.nx;
     d->ny = q.ny;
     d->r = q.r;
@@ -281,29 +370,34 @@ int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStrea
         if (q.mask) {
             if (d->tr && d->nx > 1 && d->ny > 1) {
                 std::vector<uint8_t> hm(n), tm(n);
-                HIPCHK(hipMemcpy(hm.data(), q.mask, n, hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpyAsync(hm.data(), q.mask, n, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
                 for (int i = 0; i < d->nx; ++i)
                     for (int j = 0; j < d->ny; ++j) tm[(size_t)j * d->nx + i] = hm[(size_t)i * d->ny + j];
-                HIPCHK(hipMemcpy(d->mask, tm.data(), n, hipMemcpyHostToDevice));
+                HIPCHK(hipMemcpyAsync(d->mask, tm.data(), n, hipMemcpyHostToDevice, st));
+                HIPCHK(hipStreamSynchronize(st));
             } else {
                 HIPCHK(hipMemcpyAsync(d->mask, q.mask, n, hipMemcpyDeviceToDevice, st));
             }
         }
     } else {
         if (!d->tr) {
-            HIPCHK(hipMemcpy(d->x, q.x, n * 8, hipMemcpyHostToDevice));
-            if (q.mask) HIPCHK(hipMemcpy(d->mask, q.mask, n, hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpyAsync(d->x, q.x, n * 8, hipMemcpyHostToDevice, st));
+            if (q.mask) HIPCHK(hipMemcpyAsync(d->mask, q.mask, n, hipMemcpyHostToDevice, st));
         } else {
             std::vector<double> tx(n);
             for (int i = 0; i < d->nx; ++i)
                 for (int j = 0; j < d->ny; ++j) tx[(size_t)j * d->nx + i] = q.x[(size_t)i * d->ny + j];
-            HIPCHK(hipMemcpy(d->x, tx.data(), n * 8, hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpyAsync(d->x, tx.data(), n * 8, hipMemcpyHostToDevice, st));
+            std::vector<uint8_t> tm;
             if (q.mask) {
-                std::vector<uint8_t> tm(n);
+                tm.resize(n);
                 for (int i = 0; i < d->nx; ++i)
                     for (int j = 0; j < d->ny; ++j) tm[(size_t)j * d->nx + i] = q.mask[(size_t)i * d->ny + j];
-                HIPCHK(hipMemcpy(d->mask, tm.data(), n, hipMemcpyHostToDevice));
+                HIPCHK(hipMemcpyAsync(d->mask, tm.data(), n, hipMemcpyHostToDevice, st));
             }
+            // the host temporaries must outlive the copies
+            HIPCHK(hipStreamSynchronize(st));
         }
     }
     // shape buffers
@@ -320,13 +414,14 @@ int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStrea
     if ((rc = d->dalloc(&d->lrow, d->LA + 1))) return rc;
     const int nrun = (int)d->ra.size();
     if ((rc = d->dalloc(&d->runs, 3 * (long)nrun))) return rc;
-    if (!lfull) HIPCHK(hipMemcpy(d->lmask, d->lmask_h.data(), d->lmask_h.size(), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(d->lrow, d->lrow_h.data(), (d->LA + 1) * sizeof(int), hipMemcpyHostToDevice));
+    if (!lfull) HIPCHK(hipMemcpyAsync(d->lmask, d->lmask_h.data(), d->lmask_h.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d->lrow, d->lrow_h.data(), (d->LA + 1) * sizeof(int), hipMemcpyHostToDevice, st));
     std::vector<int> rr;
     rr.insert(rr.end(), d->ra.begin(), d->ra.end());
     rr.insert(rr.end(), d->rb0.begin(), d->rb0.end());
     rr.insert(rr.end(), d->rb1.begin(), d->rb1.end());
-    HIPCHK(hipMemcpy(d->runs, rr.data(), rr.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(d->runs, rr.data(), rr.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
     d->rn = Runs{d->runs, d->runs + nrun, d->runs + 2 * nrun, nrun, d->L};
     // descriptor (K set filled after the origin count)
     OpDesc& o = d->op;
@@ -344,17 +439,29 @@ int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStrea
 // batches
 // ---------------------------------------------------------------------------
 
+thread_local ssa_ctx* g_tables_ctx = nullptr;   // pool that small batch tables come from
+
+// A small device table filled from the host (descriptor arrays, item lists).
 struct DevVec {
     void* p = nullptr;
     size_t cap = 0;
-    ~DevVec() { if (p) (void)hipFree(p); }
+    ssa_ctx* ctx = g_tables_ctx;
+    ~DevVec() { release(); }
+    void release() {
+        if (!p) return;
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->pool_put(p, cap);
+        p = nullptr;
+        cap = 0;
+    }
     template <typename T>
     int put(const std::vector<T>& v, hipStream_t st) {
-        const size_t b = std::max<size_t>(v.size(), 1) * sizeof(T);
+        const size_t b = ssa_ctx::size_class(std::max<size_t>(v.size(), 1) * sizeof(T));
         if (b > cap) {
-            if (p) (void)hipFree(p);
-            p = nullptr;
-            if (hipMalloc(&p, b) != hipSuccess) return fail(SSA_ENOMEM, "hipMalloc (batch tables)");
+            release();
+            std::lock_guard<std::mutex> g(ctx->mu);
+            p = ctx->pool_get(b);
+            if (!p) return fail(SSA_ENOMEM, "hipMalloc (batch tables)");
             cap = b;
         }
         if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
@@ -407,6 +514,55 @@ struct Batch {
     const ResDesc* res() const { return dres.as<ResDesc>(); }
     const Runs* runs() const { return druns.as<Runs>(); }
 };
+
+// HIP-event span around one launch when its kernel class is being timed.
+struct ProfSpan {
+    ssa_ctx* c;
+    hipStream_t st;
+    bool on = false;
+    int e0 = -1;
+    ProfSpan(ssa_ctx* ctx, const char* kind, hipStream_t s, double bytes) : c(ctx), st(s) {
+        if (c->prof_kind.empty() || c->prof_kind != kind) return;
+        e0 = c->prof_event();
+        if (e0 < 0) return;
+        c->ev_pending = true;
+        (void)hipEventRecord(c->ev_pool[e0], st);
+        c->prof_bytes += bytes;
+        c->prof_launches += 1;
+        on = true;
+    }
+    ~ProfSpan() {
+        if (!on) return;
+        const int e1 = c->prof_event();
+        c->ev_pending = false;
+        if (e1 < 0) return;
+        (void)hipEventRecord(c->ev_pool[e1], st);
+        c->spans.push_back({e0, e1});
+    }
+};
+
+// Algorithmic bytes of one column launch: every tile reads its input rows
+// and the spectrum columns and writes its output rows.
+double col_bytes(const Batch& b, const ItemList& L, int nin, int nout) {
+    double tot = 0.0;
+    for (const Item& it : L.h) {
+        const auto* d = b.ds[it.inst];
+        const int tc = std::min(b.TC, d->P - it.idx * b.TC);
+        tot += (double)tc * (nin + nout + d->MA) * d->celem();
+    }
+    return tot;
+}
+
+// Algorithmic bytes of one row launch: rows x (P complex) in and/or out plus
+// the compact vectors it reads or writes.
+double row_bytes(const Batch& b, const ItemList& L, int cin, int cout, double vec_bytes_per_inst) {
+    double tot = 0.0;
+    for (const Item& it : L.h) tot += (double)b.ds[it.inst]->P * b.ds[it.inst]->celem() * (cin + cout);
+    std::vector<char> seen(b.ds.size(), 0);
+    for (const Item& it : L.h)
+        if (!seen[it.inst]) { seen[it.inst] = 1; tot += vec_bytes_per_inst; }
+    return tot;
+}
 
 // rows [0, nrows) of every listed instance, optional component range
 void rows_items(ItemList& L, const std::vector<int>& inst, std::function<int(int)> nrows, int ncomp = 1,
@@ -500,8 +656,8 @@ int run_alloc_spectrum(Batch& b) {
             (rc = d->dalloc(&d->hp2, (long)nblk * (kMaxBasis + 1))) || (rc = d->dalloc(&d->np, nblk)) ||
             (rc = d->dalloc(&d->lnp, 2 * longrows)) || (rc = d->dalloc(&d->Bm, kMaxBasis * kMaxBasis)) ||
             (rc = d->dalloc(&d->Yl, kMaxBasis * kMaxBasis)) || (rc = d->dalloc(&d->Yr, kMaxBasis * kMaxBasis)) ||
-            (rc = d->dalloc(&d->sig, kMaxBasis)) || (rc = d->dalloc(&d->beta, 2)) ||
-            (rc = d->dalloc(&d->perm, kMaxBasis)) || (rc = d->dalloc(&d->flag, 2)) ||
+            (rc = d->dalloc(&d->sig, kMaxBasis)) || (rc = d->dalloc(&d->beta, 4)) ||
+            (rc = d->dalloc(&d->perm, kMaxBasis)) || (rc = d->dalloc(&d->flag, 4)) ||
             (rc = d->dalloc(&d->Qtmp, n * kMaxBasis)) || (rc = d->dalloc(&d->U, d->L * (long)d->r)) ||
             (rc = d->dalloc(&d->V, d->K * (long)d->r)) || (rc = d->dalloc(&d->sigma, d->r)))
             return rc;
@@ -524,6 +680,7 @@ int run_alloc_spectrum(Batch& b) {
         z.active = 1;
         z.r = d->r;
         z.tol = 0.1 * (d->f64 ? 1e-10 : 1e-5);
+        z.eps = d->f64 ? 1e-12 : 1e-5;
         z.n = n;
         z.nl = d->nlong;
         z.Q = d->Q; z.w = d->w; z.sin = d->sinv; z.hp1 = d->hp1; z.hp2 = d->hp2; z.np = d->np;
@@ -608,28 +765,65 @@ void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode) {
     hipStream_t st = b.st;
     const auto* d0 = b.ds[0];
     const int s = d0->side;
+    const double vs = 8.0 * d0->nshort, vl = (d0->f64 ? 8.0 : 4.0) * d0->nlong;
     if (d0->rowfam) {
-        launch_row_in(b.f64, b.cls, S.rin.n(), st, b.ops(), b.lzs(), b.res(), S.rin.ptr(),
-                      RowInArgs{mode, 0, j, DEST_T1, 1.0, 0, nullptr});
-        launch_rowfam_mid(b.f64, b.cls, S.rmid.n(), st, b.ops(), b.lzs(), b.res(), S.rmid.ptr(),
-                          RowFamArgs{OUT_NONE, 1, 1, j, jstart});
-        launch_rowfam_out(b.f64, b.cls, S.rout.n(), st, b.ops(), b.lzs(), S.rout.ptr(),
-                          RowOutArgs{OUT_LZ, 0, 1.0, 0, j});
+        {
+            ProfSpan p(b.ctx, "row_in", st, row_bytes(b, S.rin, 0, 1, vs));
+            launch_row_in(b.f64, b.cls, S.rin.n(), st, b.ops(), b.lzs(), b.res(), S.rin.ptr(),
+                          RowInArgs{mode, 0, j, DEST_T1, 1.0, 0, nullptr});
+        }
+        {
+            ProfSpan p(b.ctx, "rowfam_mid", st, row_bytes(b, S.rmid, 3, 1, 2 * vl));
+            launch_rowfam_mid(b.f64, b.cls, S.rmid.n(), st, b.ops(), b.lzs(), b.res(), S.rmid.ptr(),
+                              RowFamArgs{OUT_NONE, 1, 1, j, jstart});
+        }
+        {
+            ProfSpan p(b.ctx, "rowfam_out", st, row_bytes(b, S.rout, d0->A, 0, 2 * vs));
+            launch_rowfam_out(b.f64, b.cls, S.rout.n(), st, b.ops(), b.lzs(), S.rout.ptr(),
+                              RowOutArgs{OUT_LZ, 0, 1.0, 0, j, jstart});
+        }
     } else {
         const int nin = d0->op.S[s].boxA, nmid = d0->op.S[1 - s].boxA;
-        launch_row_in(b.f64, b.cls, S.rin.n(), st, b.ops(), b.lzs(), b.res(), S.rin.ptr(),
-                      RowInArgs{mode, s, j, DEST_T1, 1.0, 0, nullptr});
-        launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(), ColArgs{COL_CORR, nin, nmid, 1.0, nullptr});
-        launch_row_mid(b.f64, b.cls, S.rmid.n(), st, b.ops(), b.lzs(), b.res(), S.rmid.ptr(),
-                       RowMidArgs{1 - s, OUT_NONE, 1.0, 0, 1, 1, j, jstart});
-        launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(), ColArgs{COL_CORR, nmid, nin, 1.0, nullptr});
-        launch_row_out(b.f64, b.cls, S.rout.n(), st, b.ops(), b.lzs(), b.res(), S.rout.ptr(),
-                       RowOutArgs{OUT_LZ, s, 1.0, 0, j});
+        {
+            ProfSpan p(b.ctx, "row_in", st, row_bytes(b, S.rin, 0, 1, vs));
+            launch_row_in(b.f64, b.cls, S.rin.n(), st, b.ops(), b.lzs(), b.res(), S.rin.ptr(),
+                          RowInArgs{mode, s, j, DEST_T1, 1.0, 0, nullptr});
+        }
+        {
+            ProfSpan p(b.ctx, "col", st, col_bytes(b, S.cols, nin, nmid));
+            launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(),
+                       ColArgs{COL_CORR, nin, nmid, 1.0, nullptr});
+        }
+        {
+            ProfSpan p(b.ctx, "row_mid", st, row_bytes(b, S.rmid, 1, 1, 2 * vl));
+            launch_row_mid(b.f64, b.cls, S.rmid.n(), st, b.ops(), b.lzs(), b.res(), S.rmid.ptr(),
+                           RowMidArgs{1 - s, OUT_NONE, 1.0, 0, 1, 1, j, jstart});
+        }
+        {
+            ProfSpan p(b.ctx, "col", st, col_bytes(b, S.cols, nmid, nin));
+            launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(),
+                       ColArgs{COL_CORR, nmid, nin, 1.0, nullptr});
+        }
+        {
+            ProfSpan p(b.ctx, "row_out", st, row_bytes(b, S.rout, 1, 0, 2 * vs));
+            launch_row_out(b.f64, b.cls, S.rout.n(), st, b.ops(), b.lzs(), b.res(), S.rout.ptr(),
+                           RowOutArgs{OUT_LZ, s, 1.0, 0, j, jstart});
+        }
     }
     const int ncols = j + 1;
-    launch_lz_proj(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols);
-    launch_lz_update(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 1);
-    launch_lz_update(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 2);
+    const double qb = 8.0 * d0->nshort * ncols * S.inst.n();
+    {
+        ProfSpan p(b.ctx, "lz_proj", st, qb);
+        launch_lz_proj(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols);
+    }
+    {
+        ProfSpan p(b.ctx, "lz_update", st, 2 * qb);
+        launch_lz_update(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 1);
+    }
+    {
+        ProfSpan p(b.ctx, "lz_update", st, qb);
+        launch_lz_update(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 2);
+    }
 }
 
 int basis_size(long nshort, int r) {
@@ -656,8 +850,10 @@ int run_lanczos(Batch& b, int max_steps) {
     if ((rc = upload_step_lists(S, st))) return rc;
     launch_lz_start(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), b.ds[0]->seed);
     int jstart = 0;
-    std::vector<int> flags(2 * ni);
+    std::vector<int> flags(4 * ni);
     std::vector<double> betas(2 * ni);
+    std::vector<int> bdrest(ni, 0);
+    int cycle = 0;
     for (auto* d : b.ds) d->st.basis = m;
     while (!act.empty()) {
         for (int j = jstart; j < m; ++j) {
@@ -668,29 +864,61 @@ int run_lanczos(Batch& b, int max_steps) {
         launch_lz_svd(S.inst.n(), st, b.lzs(), S.inst.ptr(), m, 40);
         HIPCHK(hipGetLastError());
         for (int i : act) {
-            HIPCHK(hipMemcpyAsync(&flags[2 * i], b.ds[i]->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(&flags[4 * i], b.ds[i]->flag, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
             HIPCHK(hipMemcpyAsync(&betas[2 * i], b.ds[i]->beta, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
         }
         HIPCHK(hipStreamSynchronize(st));
-        std::vector<int> done, cont;
+        ++cycle;
+        if (std::getenv("SHSSA_DEBUG")) {
+            for (int i : act) {
+                auto* d = b.ds[i];
+                std::vector<double> Bh(kMaxBasis * kMaxBasis), sg(m), bt(4);
+                (void)hipMemcpy(Bh.data(), d->Bm, Bh.size() * 8, hipMemcpyDeviceToHost);
+                (void)hipMemcpy(sg.data(), d->sig, m * 8, hipMemcpyDeviceToHost);
+                (void)hipMemcpy(bt.data(), d->beta, 4 * 8, hipMemcpyDeviceToHost);
+                std::fprintf(stderr, "cycle %d inst %d flags %d %d %d %d beta %g %g %g %g eps %g\n", cycle, i,
+                             flags[4 * i], flags[4 * i + 1], flags[4 * i + 2], flags[4 * i + 3], bt[0], bt[1], bt[2],
+                             bt[3], d->lz.eps);
+                std::fprintf(stderr, "  diag:");
+                for (int k = 0; k < std::min(m, 8); ++k) std::fprintf(stderr, " %g", Bh[(size_t)k * kMaxBasis + k]);
+                std::fprintf(stderr, "\n  sub:");
+                for (int k = 0; k < std::min(m, 8); ++k) std::fprintf(stderr, " %g", Bh[(size_t)k * kMaxBasis + k + 1]);
+                std::fprintf(stderr, "\n  sig:");
+                for (int k = 0; k < std::min(m, 6); ++k) std::fprintf(stderr, " %g", sg[k]);
+                std::fprintf(stderr, "\n");
+            }
+        }
+        // Per instance: converged -> done; breakdown (the Krylov space of the
+        // start vector is exhausted) -> restart from a random vector orthogonal
+        // to the kept Ritz vectors, at most twice, then done; otherwise a thick
+        // restart, up to the step limit.
+        std::vector<int> done, cont, fresh;
         for (int i : act) {
             steps[i] += m - jstart;
-            const bool ok = flags[2 * i] != 0;
-            if (ok || steps[i] >= max_steps) {
+            const bool ok = flags[4 * i] != 0;
+            const bool bd = flags[4 * i + 2] != 0;
+            auto* d = b.ds[i];
+            if (bd && bdrest[i] < 2 && steps[i] < max_steps) {
+                bdrest[i]++;
+                restarts[i]++;
+                fresh.push_back(i);
+                cont.push_back(i);
+                continue;
+            }
+            if (ok || bd || steps[i] >= max_steps) {
                 done.push_back(i);
-                auto* d = b.ds[i];
-                d->st.converged = ok;
+                d->st.converged = ok || bd;
                 d->st.steps = steps[i];
                 d->st.restarts = restarts[i];
                 d->st.max_resid = betas[2 * i + 1];
-                if (!ok) d->status = fail(SSA_ENOCONV, "bidiagonalisation reached its step limit");
+                if (!(ok || bd)) d->status = fail(SSA_ENOCONV, "bidiagonalisation reached its step limit");
             } else {
                 cont.push_back(i);
                 restarts[i]++;
             }
         }
         if (!done.empty()) {
-            // Ritz vectors of the finished instances into their results
+            // Ritz vectors and singular values of the finished instances
             std::vector<double*> outs(ni, nullptr);
             for (int i : done) outs[i] = b.ds[i]->side == 0 ? b.ds[i]->U : b.ds[i]->V;
             DevVec douts;
@@ -709,16 +937,25 @@ int run_lanczos(Batch& b, int max_steps) {
         }
         if (cont.empty()) break;
         {
-            ItemList R, Z;
+            ItemList R, Z, F;
+            std::vector<char> isfresh(ni, 0);
+            for (int i : fresh) isfresh[i] = 1;
             for (int i : cont) {
                 const long n = b.ds[i]->nshort;
                 for (long rb = 0; rb < (n + 63) / 64; ++rb)
                     for (int cb = 0; cb < (kk + 15) / 16; ++cb) R.h.push_back(Item{i, (int)rb, 0, cb});
-                for (int k = 0; k < b.ds[i]->lz.nblk; ++k) Z.h.push_back(Item{i, k, 0, 0});
+                for (int k = 0; k < b.ds[i]->lz.nblk; ++k)
+                    (isfresh[i] ? F : Z).h.push_back(Item{i, k, 0, 0});
             }
-            if ((rc = R.upload(st)) || (rc = Z.upload(st))) return rc;
+            if ((rc = R.upload(st)) || (rc = Z.upload(st)) || (rc = F.upload(st))) return rc;
             launch_lz_ritz(R.n(), st, b.lzs(), R.ptr(), m, kk, nullptr);
             launch_lz_restart(Z.n(), st, b.lzs(), Z.ptr(), m, kk);
+            if (F.n() > 0) {
+                launch_lz_restart_random(F.n(), st, b.lzs(), F.ptr(), kk, b.ds[0]->seed + 7919ULL * cycle);
+                launch_lz_proj(F.n(), st, b.lzs(), F.ptr(), kk);
+                launch_lz_update(F.n(), st, b.lzs(), F.ptr(), kk, 1);
+                launch_lz_update(F.n(), st, b.lzs(), F.ptr(), kk, 2);
+            }
             HIPCHK(hipStreamSynchronize(st));
         }
         act = cont;
@@ -830,7 +1067,7 @@ int run_reconstruct(Batch& b, const std::vector<int>& gptr, const std::vector<in
                       RowInArgs{IN_VEC, 1, 0, DEST_T1, 1.0, 1, nullptr});
         launch_col(b.f64, c2.n(), st, b.ops(), b.res(), c2.ptr(), ColArgs{COL_ACCUM, d0->KA, d0->A, 1.0, nullptr});
         launch_row_out(b.f64, b.cls, out.n(), st, b.ops(), b.lzs(), b.res(), out.ptr(),
-                       RowOutArgs{OUT_IMAGE, 0, 1.0 / ((double)d0->MA * d0->MB), 0, 0});
+                       RowOutArgs{OUT_IMAGE, 0, 1.0 / ((double)d0->MA * d0->MB), 0, 0, 0});
     }
     HIPCHK(hipGetLastError());
     // keep the item lists alive until the work is done
@@ -847,6 +1084,7 @@ GeoKey geo_key(const ssa_decomp* d) {
 
 int decompose_many(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** out, int* status, bool dev) {
     if (!ctx || n < 0 || (n > 0 && (!reqs || !out))) return fail(SSA_EINVAL, "bad arguments");
+    g_tables_ctx = ctx;
     std::vector<std::unique_ptr<ssa_decomp>> ds(n);
     std::vector<int> st(n, SSA_OK);
     std::map<GeoKey, std::vector<int>> groups;
@@ -934,6 +1172,30 @@ void walk_set(const ssa_decomp* d, int BA, int BB, const uint8_t* mask, F fn) {
 
 extern "C" {
 
+int ssa_ctx_profile(ssa_ctx* ctx, const char* kind) {
+    if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
+    ctx->prof_kind = kind ? kind : "";
+    return SSA_OK;
+}
+
+int ssa_ctx_profile_read(ssa_ctx* ctx, double* ms, long* launches, double* bytes) {
+    if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    double tot = 0.0;
+    for (auto& sp : ctx->spans) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, ctx->ev_pool[sp.first], ctx->ev_pool[sp.second]));
+        tot += t;
+    }
+    if (ms) *ms = tot;
+    if (launches) *launches = ctx->prof_launches;
+    if (bytes) *bytes = ctx->prof_bytes;
+    ctx->spans.clear();
+    ctx->prof_bytes = 0.0;
+    ctx->prof_launches = 0;
+    return SSA_OK;
+}
+
 int ssa_ctx_create(int device, size_t mem_budget, void* stream, ssa_ctx** out) {
     if (!out) return fail(SSA_EINVAL, "out is NULL");
     *out = nullptr;
@@ -959,10 +1221,13 @@ int ssa_ctx_create(int device, size_t mem_budget, void* stream, ssa_ctx** out) {
 
 void ssa_ctx_destroy(ssa_ctx* ctx) {
     if (!ctx) return;
-    (void)hipStreamSynchronize(ctx->st);
-    for (auto& kv : ctx->tw) (void)hipFree(kv.second);
-    if (ctx->own) (void)hipStreamDestroy(ctx->st);
-    delete ctx;
+    bool now = false;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->closing = true;
+        now = ctx->refs == 0;
+    }
+    if (now) ctx_release(ctx);
 }
 
 int ssa_ctx_set_stream(ssa_ctx* ctx, void* stream) {
@@ -1145,6 +1410,7 @@ int ssa_reconstruct(ssa_decomp* d, const int* gp, const int* gi, int ng, double*
     int rc = check_groups(d, gp, gi, ng);
     if (rc) return rc;
     const long n = (long)d->A * d->B;
+    g_tables_ctx = d->ctx;
     double* buf = nullptr;
     HIPCHK(hipMalloc(&buf, n * ng * 8));
     Batch b(d->ctx);
@@ -1180,6 +1446,7 @@ int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* gp, const 
     }
     int rc = check_groups(d[0], gp, gi, ng);
     if (rc) return rc;
+    g_tables_ctx = d[0]->ctx;
     Batch b(d[0]->ctx);
     b.ds.assign(d, d + n);
     b.f64 = d[0]->f64;

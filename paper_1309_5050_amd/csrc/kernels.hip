@@ -145,13 +145,23 @@ k_row_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const R
         double sc = 1.0;
         double* qout = nullptr;
         if (args.mode == IN_LZ_NORM || args.mode == IN_LZ_PLAIN || args.mode == IN_LZ_SIN) {
-            if (args.mode == IN_LZ_NORM) {
+            const bool fresh = args.mode == IN_LZ_SIN && lz.flag[3] != 0;
+            if (args.mode == IN_LZ_NORM || fresh) {
+                // q_j = w / beta_{j-1}.  A beta at rounding level (the short
+                // Krylov space is exhausted) freezes the recurrence for the rest
+                // of the cycle: q_j = 0 and B[j][j-1] = 0.  After a fresh random
+                // restart w is a random vector orthogonal to the basis and has
+                // no coupling to the previous column.
                 const double beta = sqrt(sum_parts(lz.np, lz.nblk));
-                sc = beta > 1e-300 ? 1.0 / beta : 0.0;
+                const double scale = lz.beta[2 + ((args.j - 1) & 1)];
+                const bool bd = !fresh && (lz.flag[2] != 0 || (args.j > 0 && beta <= lz.eps * scale));
+                sc = (!bd && beta > 1e-300) ? 1.0 / beta : 0.0;
                 src = lz.w;
                 qout = lz.Q + (long)args.j * lz.n;
-                if (valid && a == 0 && tid == 0 && args.j > 0)
-                    lz.Bm[(long)(args.j - 1) * kMaxBasis + args.j] = beta;
+                if (valid && a == 0 && tid == 0) {
+                    if (args.j > 0 && !fresh) lz.Bm[(long)(args.j - 1) * kMaxBasis + args.j] = bd ? 0.0 : beta;
+                    if (bd) lz.flag[2] = 1;
+                }
             } else if (args.mode == IN_LZ_SIN) {
                 src = lz.sin;
             } else {
@@ -208,7 +218,7 @@ __device__ __forceinline__ GkLong<T> gk_long(const LzDesc& lz, const CellSet& Sl
     g.lprev = static_cast<const T*>(lz.lbuf[p ^ 1]);
     g.lnp = lz.lnp[p];
     double gm = 0.0;
-    if (j != jstart) {
+    if (j != jstart && lz.flag[2] == 0) {
         const double beta = sqrt(sum_parts(lz.np, lz.nblk));
         const double alpha = sqrt(sum_parts(lz.lnp[p ^ 1], Slong.boxA));
         gm = alpha > 1e-300 ? beta / alpha : 0.0;
@@ -244,7 +254,7 @@ k_row_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     if (args.emit == OUT_VEC && valid) {
         const ResDesc& rs = res[item.inst];
         vout = (args.set == 0 ? rs.U : rs.V) + (long)item.comp * S.count;
-        if (args.div_sigma) sc /= rs.sigma[item.comp];
+        if (args.div_sigma) sc = rs.sigma[item.comp] > 0 ? sc / rs.sigma[item.comp] : 0.0;
     }
     if (args.gk) {
         const GkLong<T> g = gk_long<T>(lzs[item.inst], S, args.j, args.jstart);
@@ -284,12 +294,25 @@ struct GkShort {
     double* w;
 };
 
-__device__ __forceinline__ GkShort gk_short(const LzDesc& lz, const CellSet& Slong, int j) {
+// An alpha at rounding level relative to the running scale (the long Krylov
+// space is exhausted) freezes the recurrence: alpha = 0 and w = 0.
+__device__ __forceinline__ GkShort gk_short(const LzDesc& lz, const CellSet& Slong, int j, int jstart,
+                                            bool writer) {
     GkShort g;
     g.alpha = sqrt(sum_parts(lz.lnp[j & 1], Slong.boxA));
-    g.inv_alpha = g.alpha > 1e-300 ? 1.0 / g.alpha : 0.0;
+    const double prev = lz.beta[2 + ((j - 1) & 1)];
+    const double beta_in = (j > jstart) ? sqrt(sum_parts(lz.np, lz.nblk)) : 0.0;
+    double scale = fmax(prev, beta_in);
+    const bool bd = lz.flag[2] != 0 || (j > 0 && g.alpha <= lz.eps * scale);
+    if (bd) g.alpha = 0.0;
+    g.inv_alpha = (!bd && g.alpha > 1e-300) ? 1.0 / g.alpha : 0.0;
     g.q = lz.Q + (long)j * lz.n;
     g.w = lz.w;
+    if (writer) {
+        lz.beta[2 + (j & 1)] = fmax(scale, g.alpha);
+        lz.Bm[(long)j * kMaxBasis + j] = g.alpha;
+        if (bd) lz.flag[2] = 1;
+    }
     return g;
 }
 
@@ -327,8 +350,7 @@ k_row_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     const CellSet& S = op.S[args.set];
     if (args.mode == OUT_LZ) {
         const LzDesc& lz = lzs[item.inst];
-        const GkShort g = gk_short(lz, op.S[1 - args.set], args.j);
-        if (valid && a == 0 && tid == 0) lz.Bm[(long)args.j * kMaxBasis + args.j] = g.alpha;
+        const GkShort g = gk_short(lz, op.S[1 - args.set], args.j, args.jstart, valid && a == 0 && tid == 0);
         scan_row<G>(S, a, op.MB, tid, wtot, [&](int b, long idx) {
             if (valid && idx >= 0) g.w[idx] = static_cast<double>(sr[b]) * g.inv_alpha - g.alpha * g.q[idx];
         });
@@ -378,7 +400,7 @@ k_rowfam_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, con
     if (args.emit == OUT_VEC && valid) {
         const ResDesc& rs = res[item.inst];
         vout = rs.V + (long)item.comp * S.count;
-        sc = 1.0 / rs.sigma[item.comp];
+        sc = rs.sigma[item.comp] > 0 ? 1.0 / rs.sigma[item.comp] : 0.0;
     }
     if (args.gk) {
         const GkLong<T> g = gk_long<T>(lzs[item.inst], S, args.j, args.jstart);
@@ -435,8 +457,7 @@ k_rowfam_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs,
     __syncthreads();
     rfft_inv<T, NMAX, G>(s, op.prow, tid);
     const LzDesc& lz = lzs[item.inst];
-    const GkShort g = gk_short(lz, op.S[1], args.j);
-    if (valid && tid == 0) lz.Bm[(long)args.j * kMaxBasis + args.j] = g.alpha;
+    const GkShort g = gk_short(lz, op.S[1], args.j, args.jstart, valid && tid == 0);
     scan_row<G>(op.S[0], 0, op.MB, tid, wtot, [&](int b, long idx) {
         if (valid && idx >= 0) g.w[idx] = static_cast<double>(sr[b]) * g.inv_alpha - g.alpha * g.q[idx];
     });
@@ -797,9 +818,15 @@ k_lz_start(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, unsig
     if (lane_id() == 0) red[threadIdx.x >> 6] = p;
     __syncthreads();
     if (threadIdx.x == 0) lz.np[item.idx] = red[0] + red[1] + red[2] + red[3];
-    // clear the projected matrix and the long norms of the previous step
+    // clear the projected matrix, the breakdown flags and the running scale
     if (item.idx == 0) {
         for (int e = threadIdx.x; e < kMaxBasis * kMaxBasis; e += 256) lz.Bm[e] = 0.0;
+        if (threadIdx.x == 0) {
+            lz.flag[2] = 0;
+            lz.flag[3] = 0;
+            lz.beta[2] = 0.0;
+            lz.beta[3] = 0.0;
+        }
     }
 }
 
@@ -1057,6 +1084,43 @@ k_lz_restart(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int
                 v = sg > 1e-13 * s1 ? beta * lz.Yr[(long)lz.perm[b] * kMaxBasis + (m - 1)] : 0.0;
             }
             lz.Bm[e] = v;
+        }
+        if (threadIdx.x == 0) {
+            lz.flag[2] = 0;
+            lz.flag[3] = 0;
+        }
+    }
+}
+
+// Restart after a breakdown: keep the k Ritz triplets (exact for the
+// invariant subspace found), put a fresh random vector in w (to be
+// orthogonalised against the kept vectors by the Gram-Schmidt kernels) and
+// clear the coupling row, so the next cycle explores the complement.
+__global__ void __launch_bounds__(256)
+k_lz_restart_random(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int k,
+                    unsigned long long seed) {
+    __shared__ double red[4];
+    const Item item = items[blockIdx.x];
+    const LzDesc& lz = lzs[item.inst];
+    const long i = (long)item.idx * kLzRows + threadIdx.x;
+    double v = 0.0;
+    if (i < lz.n) {
+        for (int c = 0; c < k; ++c) lz.Q[(long)c * lz.n + i] = lz.Qtmp[(long)c * lz.n + i];
+        v = hash_unit(seed, (unsigned long long)i);
+        lz.w[i] = v;
+    }
+    const double p = wave_sum(v * v);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = p;
+    __syncthreads();
+    if (threadIdx.x == 0) lz.np[item.idx] = red[0] + red[1] + red[2] + red[3];
+    if (item.idx == 0) {
+        for (int e = threadIdx.x; e < kMaxBasis * kMaxBasis; e += 256) {
+            const int a = e % kMaxBasis, b = e / kMaxBasis;
+            lz.Bm[e] = (a == b && a < k) ? lz.sig[a] : 0.0;
+        }
+        if (threadIdx.x == 0) {
+            lz.flag[2] = 0;
+            lz.flag[3] = 1;
         }
     }
 }

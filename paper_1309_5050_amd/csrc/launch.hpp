@@ -39,6 +39,8 @@ void launch_lz_svd(int ninst, hipStream_t st, const LzDesc* lzs, const Item* ite
 void launch_lz_ritz(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int m, int k,
                     double* const* outs);
 void launch_lz_restart(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int m, int k);
+void launch_lz_restart_random(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int k,
+                              unsigned long long seed);
 void launch_lz_sigma(int ninst, hipStream_t st, const LzDesc* lzs, const ResDesc* res, const Item* items);
 void launch_sign_fix(int nitems, hipStream_t st, const OpDesc* ops, const ResDesc* res, const Item* items);
 void launch_transpose(int nmat, int R, int C, hipStream_t st, const double* in, double* out);

@@ -1,0 +1,93 @@
+"""GPU parity at the full workload sizes, against expected values written by
+tests/golden/make_golden.py (oracle only: explicit S = X X^T and Jacobi).
+
+Singular values are compared one by one; left subspaces of gap-stable groups
+against the stored oracle vectors; reconstructions at sampled cells against
+the oracle's explicit averaging evaluated cell by cell, with V_i = X^T U_i /
+sigma_i from the oracle's explicit products.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1309_5050_amd import workloads as W
+
+from helpers import TOL, proj_dist, sigma_err, stable_groups
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+C_SUB = 20.0
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1309_5050_amd as S
+    c = S.Context(0)
+    yield c
+    c.close()
+
+
+def golden(i):
+    return np.load(os.path.join(HERE, "golden", f"config{i}_full.npz"))
+
+
+def run(ctx, w, prec):
+    if w["kind"] == "mssa":
+        return ctx.decompose_multi(w["x"], w["window"], w["r"], precision=prec)
+    return ctx.decompose(w["x"], w["window"], w["r"], mask=w["mask"], wmask=w["wmask"], precision=prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("cfg", [2, 3, 4])
+def test_full_size_sigma_and_subspaces(ctx, cfg, prec):
+    w = W.config(cfg)
+    g = golden(cfg)
+    so, Ug = g["sigma"], g["U"]
+    d = run(ctx, w, prec)
+    tol = TOL[prec]
+    s = d.sigma
+    err = sigma_err(s, so)
+    print(f"config {cfg} {prec}: sigma err {err:.2e} stats {d.stats}")
+    assert d.stats["converged"] == 1
+    assert err <= tol
+    U, _ = d.vectors_lex()
+    nv = Ug.shape[1]
+    for grp, gap in stable_groups(so, nv):
+        dist = proj_dist(U[:, grp], Ug[:, grp])
+        assert dist <= C_SUB * tol * so[0] / gap, (cfg, prec, grp, dist)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_image_reconstruction_sampled(ctx, prec):
+    w = W.config(2)
+    g = golden(2)
+    so, Ug = g["sigma"], g["U"]
+    sh = oracle.shapes(w["x"], window=w["window"])
+    nv = Ug.shape[1]
+    Vg = np.stack([oracle.rmatvec(w["x"], sh, Ug[:, k]) / so[k] for k in range(nv)], axis=1)
+    groups = [[0, 1], [2, 3], [4, 5]]
+    d = run(ctx, w, prec)
+    rec = d.reconstruct(groups)
+    rng = np.random.default_rng(7)
+    cells = np.concatenate([rng.integers(0, 512, (1500, 2)),
+                            np.array([[0, 0], [0, 511], [511, 0], [511, 511], [63, 63], [448, 448]])])
+    gaps = {tuple(gr): gap for gr, gap in stable_groups(so, nv)}
+    rms = np.sqrt(np.mean(w["x"] ** 2))
+    for k, grp in enumerate(groups):
+        ref = oracle.reconstruct_at(sh, so, Ug, Vg, grp, cells)
+        got = rec[k][cells[:, 0], cells[:, 1]]
+        gap = min(gaps[(i,)] for i in grp)
+        e = np.sqrt(np.mean((got - ref) ** 2)) / rms
+        assert e <= C_SUB * TOL[prec] * so[0] / gap, (grp, e)
+
+
+def test_full_size_shaped_covered_set_and_weights(ctx):
+    w = W.config(4)
+    d = run(ctx, w, "fp32")
+    sh = oracle.shapes(w["x"], w["mask"], w["wmask"], w["window"])
+    assert (d.L, d.K) == (sh.L, sh.K)
+    assert np.array_equal(d.weights, sh.W)
+    rec = d.reconstruct([[0, 1, 2, 3]])
+    assert np.array_equal(~np.isnan(rec[0]), sh.covered)

@@ -1,0 +1,270 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: singular values |s_i - s_i^o| <= tol * s_1 (Weyl), spans of
+gap-stable groups |P - P^o|_2 <= C tol s_1 / gap (Wedin), reconstructions
+|x_G - x_G^o| / |x| <= C tol s_1 / gap, with tol = 1e-10 for the FP64 path
+and 1e-5 for the FP32 path (FP32 products, FP64 Lanczos).  Individual
+vectors of clusters closer than 1e-3 s_1 are not unique (only their span
+is); such clusters are compared as a whole.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1309_5050_amd import workloads as W
+
+from helpers import TOL, proj_dist, sigma_err, stable_groups
+
+pytestmark = pytest.mark.gpu
+C_SUB = 20.0
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1309_5050_amd as S
+    c = S.Context(0)
+    yield c
+    c.close()
+
+
+_ORACLE = {}
+
+
+def oracle_case(name, w):
+    if name not in _ORACLE:
+        if w["kind"] == "mssa":
+            s, U, V = oracle.decompose_mssa(w["x"], w["window"])
+            _ORACLE[name] = (None, s, U, V)
+        else:
+            _ORACLE[name] = oracle.decompose(w["x"], w["mask"], w["wmask"], w["window"])
+    return _ORACLE[name]
+
+
+def gpu_case(ctx, w, prec):
+    if w["kind"] == "mssa":
+        return ctx.decompose_multi(w["x"], w["window"], w["r"], precision=prec)
+    return ctx.decompose(w["x"], w["window"], w["r"], mask=w["mask"], wmask=w["wmask"], precision=prec)
+
+
+def packed_mssa(w):
+    ser = w["x"]
+    nmax = max(len(s) for s in ser)
+    arr = np.full((nmax, len(ser)), np.nan)
+    for p, s in enumerate(ser):
+        arr[:len(s), p] = s
+    return arr
+
+
+CASES = {
+    "series_1000": lambda: W.series_1d(),
+    "image_128": lambda: W.config(2, "small"),
+    "mssa_8": lambda: W.config(3, "small"),
+    "disc_160": lambda: W.config(4, "small"),
+    "small_shaped": lambda: W.small_shaped(),
+    "series_ragged": lambda: W.series_1d(n=777, L=301, r=12, seed=9),
+    "image_ragged": lambda: dict(W.image_2d(n=97, lw=13, r=14, seed=21), x=W.image_2d(n=97, r=14, seed=21)["x"][:, :83]),
+}
+
+
+def check_case(ctx, name, prec, groups_too=True):
+    w = CASES[name]()
+    tol = TOL[prec]
+    sh, so, Uo, Vo = oracle_case(name, w)
+    d = gpu_case(ctx, w, prec)
+    r = w["r"]
+    s = d.sigma
+    err = sigma_err(s, so)
+    print(f"{name} {prec}: sigma err {err:.2e} stats {d.stats}")
+    assert d.stats["converged"] == 1
+    assert err <= tol, (name, prec, err)
+    U, V = d.vectors_lex()
+    assert U.shape == (Uo.shape[0], r) and V.shape == (Vo.shape[0], r)
+    for g, gap in stable_groups(so, r):
+        bound = C_SUB * tol * so[0] / gap
+        du = proj_dist(U[:, g], Uo[:, g])
+        dv = proj_dist(V[:, g], Vo[:, g])
+        assert du <= bound and dv <= bound, (name, prec, g, du, dv, bound)
+    # orthonormality of both sides
+    assert np.allclose(U.T @ U, np.eye(r), atol=max(1e-9, 10 * tol))
+    assert np.allclose(V.T @ V, np.eye(r), atol=max(1e-9, 100 * tol))
+    if not groups_too:
+        return d
+    # reconstruction of the gap-stable groups (and of their union)
+    sg = [g for g, _ in stable_groups(so, r)]
+    gaps = [gap for _, gap in stable_groups(so, r)]
+    groups = sg[:4] + [sorted(sum(sg[:4], []))]
+    gaps = gaps[:4] + [min(gaps[:4])]
+    rec = d.reconstruct(groups)
+    if w["kind"] == "mssa":
+        lens = [len(x) for x in w["x"]]
+        for k, g in enumerate(groups):
+            ref = oracle.reconstruct_mssa(lens, w["window"], so, Uo, Vo, g)
+            got = [rec[k][:n, p] for p, n in enumerate(lens)]
+            assert all(np.all(np.isnan(rec[k][n:, p])) for p, n in enumerate(lens))
+            num = np.sqrt(sum(np.sum((a - b) ** 2) for a, b in zip(got, ref)))
+            den = np.sqrt(sum(np.sum(x ** 2) for x in w["x"]))
+            assert num / den <= C_SUB * tol * so[0] / gaps[k], (name, prec, g, num / den)
+    else:
+        x = w["x"] if w["x"].ndim == 2 else w["x"][:, None]
+        for k, g in enumerate(groups):
+            ref = oracle.reconstruct(sh, so, Uo, Vo, g)
+            got = rec[k]
+            assert np.array_equal(np.isnan(got), np.isnan(ref)), (name, "covered set differs")
+            cov = ~np.isnan(ref)
+            num = np.linalg.norm(got[cov] - ref[cov])
+            den = np.linalg.norm(np.nan_to_num(x[cov]))
+            assert num / den <= C_SUB * tol * so[0] / gaps[k], (name, prec, g, num / den)
+        assert np.array_equal(d.weights, sh.W)
+    return d
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_parity(ctx, name, prec):
+    check_case(ctx, name, prec)
+
+
+def test_literal_groups_series(ctx):
+    """The 1D workload's own groups {1-2},{3-4},{5} split near-degenerate
+    sine pairs; their error is bounded by tol * s_1 / gap of each split."""
+    w = W.series_1d()
+    sh, so, Uo, Vo = oracle_case("series_1000", w)
+    d = gpu_case(ctx, w, "fp64")
+    rec = d.reconstruct(w["groups"])
+    for k, g in enumerate(w["groups"]):
+        ref = oracle.reconstruct(sh, so, Uo, Vo, g)
+        gap = min(so[i] - so[i + 1] for i in range(max(g[0] - 1, 0), g[-1] + 1))
+        e = np.linalg.norm(rec[k][:, 0] - ref[:, 0]) / np.linalg.norm(w["x"])
+        assert e <= C_SUB * 1e-10 * so[0] / gap, (g, e)
+
+
+def test_window_set_order_and_nan_pattern(ctx):
+    w = W.small_shaped()
+    sh, so, Uo, Vo = oracle_case("small_shaped", w)
+    d = gpu_case(ctx, w, "fp64")
+    U, V = d.vectors()
+    assert np.array_equal(~np.isnan(U[0]), oracle.grid(sh, np.ones(sh.L), "L") == 1)
+    assert np.array_equal(~np.isnan(V[0]), oracle.grid(sh, np.ones(sh.K), "K") == 1)
+    assert (d.L, d.K) == (sh.L, sh.K)
+
+
+def test_column_window_is_transposed_row_case(ctx):
+    """An Lx x 1 window on an image (runs through the transposed row family)."""
+    g = np.random.default_rng(31)
+    x = g.standard_normal((57, 23)) + np.cos(np.arange(57) / 3.0)[:, None]
+    x[5, 7] = np.nan
+    sh, so, Uo, Vo = oracle.decompose(x, window=(20, 1))
+    d = ctx.decompose(x, (20, 1), 6)
+    assert sigma_err(d.sigma, so) <= 1e-10
+    rec = d.reconstruct([[0], [1, 2]])
+    for k, grp in enumerate([[0], [1, 2]]):
+        ref = oracle.reconstruct(sh, so, Uo, Vo, grp)
+        assert np.array_equal(np.isnan(rec[k]), np.isnan(ref))
+
+
+def test_row_window_on_image(ctx):
+    g = np.random.default_rng(32)
+    x = g.standard_normal((19, 64)) + np.cos(np.arange(64) / 4.0)[None, :]
+    sh, so, Uo, Vo = oracle.decompose(x, window=(1, 25))
+    d = ctx.decompose(x, (1, 25), 5)
+    assert sigma_err(d.sigma, so) <= 1e-10
+
+
+def test_origin_side_basis(ctx):
+    """|K| < |L|: the bidiagonalisation keeps its basis on the origin side."""
+    w = W.image_2d(n=40, lw=28, r=8, seed=12)
+    sh, so, Uo, Vo = oracle.decompose(w["x"], window=(28, 28))
+    d = ctx.decompose(w["x"], (28, 28), 8)
+    assert d.stats["side"] == 1
+    assert sigma_err(d.sigma, so) <= 1e-10
+    rec = d.reconstruct([[0, 1, 2, 3]])
+    ref = oracle.reconstruct(sh, so, Uo, Vo, [0, 1, 2, 3])
+    assert np.allclose(rec[0], ref, atol=1e-8, equal_nan=True)
+
+
+def test_max_rank_and_tiny(ctx):
+    x = np.random.default_rng(5).standard_normal(12)
+    sh, so, Uo, Vo = oracle.decompose(x, window=5)
+    d = ctx.decompose(x, 5, 4)            # r = min(L, K) - 1
+    assert sigma_err(d.sigma, so) <= 1e-10
+
+
+def test_sine_closed_form_degenerate_pair(ctx):
+    """A cos with L w and K w integers: sigma_1 = sigma_2 = A sqrt(LK)/2
+    exactly (a degenerate pair), rank 2."""
+    n, L, A = 959, 480, 1.7
+    t = np.arange(n)
+    x = A * np.cos(2 * np.pi * t / 12 + 0.4)
+    d = ctx.decompose(x, L, 3)
+    K = n - L + 1
+    s = d.sigma
+    ref = A * np.sqrt(L * K) / 2
+    assert abs(s[0] - ref) <= 1e-10 * ref and abs(s[1] - ref) <= 1e-10 * ref
+    assert s[2] <= 1e-9 * ref
+
+
+def test_exponential_rank_one(ctx):
+    n, L, a = 60, 25, 0.93
+    x = a ** np.arange(1, n + 1)
+    d = ctx.decompose(x, L, 2)
+    K = n - L + 1
+    ref = a * np.sqrt(np.sum(a ** (2 * np.arange(L)))) * np.sqrt(np.sum(a ** (2 * np.arange(K))))
+    s = d.sigma
+    assert abs(s[0] - ref) <= 1e-12 * ref
+    assert s[1] <= 1e-10 * ref
+
+
+def test_alone_equals_in_batch(ctx):
+    """A request gives bit-identical results alone and inside a batch."""
+    ws = [W.image_2d(n=100, lw=12, r=8, seed=s) for s in (40, 41, 42)]
+    reqs = [dict(x=w["x"], window=w["window"], r=8) for w in ws]
+    alone = ctx.decompose_batch(reqs[1:2])[0]
+    mix = ctx.decompose_batch(reqs)[1]
+    assert np.array_equal(alone.sigma, mix.sigma)
+    ua, va = alone.vectors()
+    um, vm = mix.vectors()
+    assert np.array_equal(ua, um, equal_nan=True) and np.array_equal(va, vm, equal_nan=True)
+    ra = alone.reconstruct([[0, 1], [2]])
+    rm = mix.reconstruct([[0, 1], [2]])
+    assert np.array_equal(ra, rm, equal_nan=True)
+
+
+def test_errors(ctx):
+    import paper_1309_5050_amd as S
+    x = np.random.default_rng(1).standard_normal((20, 20))
+    with pytest.raises(S.SsaError) as e:
+        ctx.decompose(x, (5, 5), 25)                  # r >= min(L, K)
+    assert e.value.code == -3
+    with pytest.raises(S.SsaError) as e:
+        ctx.decompose(x, (21, 2), 2)                  # window beyond the array
+    assert e.value.code == -1
+    y = x.copy()
+    y[::3, :] = np.nan                                # no 5x5 window fits
+    with pytest.raises(S.SsaError) as e:
+        ctx.decompose(y, (5, 5), 2)
+    assert e.value.code == -2
+    with pytest.raises(S.SsaError) as e:
+        ctx.decompose(np.full((10, 10), np.nan), (3, 3), 1)
+    assert e.value.code == -2
+    with pytest.raises(S.SsaError) as e:
+        ctx.decompose(x, (1, 1), 1)                   # window of one cell
+    assert e.value.code == -1
+    d = ctx.decompose(x, (5, 5), 3)
+    with pytest.raises(S.SsaError):
+        d.reconstruct([[0, 7]])                       # component out of range
+
+
+def test_device_inputs_match_host(ctx):
+    torch = pytest.importorskip("torch")
+    ws = [W.image_2d(n=96, lw=10, r=6, seed=s) for s in (60, 61)]
+    xs = [torch.tensor(w["x"], device="cuda:0") for w in ws]
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    dev = ctx.decompose_batch_dev(xs, (10, 10), 6)
+    host = ctx.decompose_batch([dict(x=w["x"], window=(10, 10), r=6) for w in ws])
+    for a, b in zip(dev, host):
+        assert np.array_equal(a.sigma, b.sigma)
+    outs = [torch.empty((2, 96, 96), dtype=torch.float64, device="cuda:0") for _ in ws]
+    ctx.reconstruct_batch_dev(dev, [[0, 1], [2, 3]], outs)
+    torch.cuda.synchronize()
+    for o, b in zip(outs, host):
+        assert np.array_equal(o.cpu().numpy(), b.reconstruct([[0, 1], [2, 3]]), equal_nan=True)
