@@ -55,6 +55,8 @@ int next_smooth(int n) {
     }
 }
 
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
 bool make_plan(int n, FftPlan& pl) {
     pl.n = n;
     pl.npass = 0;
@@ -483,7 +485,8 @@ struct Batch {
     hipStream_t st;
     std::vector<ssa_decomp*> ds;      // instance i = ds[i]
     bool f64 = true, rowfam = false;
-    int cls = 0, TC = 16;
+    int cls = 0, TC = 16;       // row size class (| 8: radix-2/4/8 plan), column tile
+    bool colp2 = false;         // column plan has radices 2, 4, 8 only
     DevVec dops, dlz, dres, druns;
     std::vector<OpDesc> hops;
     std::vector<LzDesc> hlz;
@@ -715,7 +718,7 @@ int run_alloc_spectrum(Batch& b) {
             for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) cols.h.push_back(Item{i, t, 0, 0});
         if ((rc = cols.upload(st))) return rc;
         ColArgs c{COL_SPEC, d0->A, 0, 1.0 / ((double)d0->MA * d0->MB), nullptr};
-        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c);
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.colp2);
         HIPCHK(hipStreamSynchronize(st));
     }
     HIPCHK(hipStreamSynchronize(st));
@@ -792,7 +795,7 @@ void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode) {
         {
             ProfSpan p(b.ctx, "col", st, col_bytes(b, S.cols, nin, nmid));
             launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(),
-                       ColArgs{COL_CORR, nin, nmid, 1.0, nullptr});
+                       ColArgs{COL_CORR, nin, nmid, 1.0, nullptr}, b.colp2);
         }
         {
             ProfSpan p(b.ctx, "row_mid", st, row_bytes(b, S.rmid, 1, 1, 2 * vl));
@@ -802,7 +805,7 @@ void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode) {
         {
             ProfSpan p(b.ctx, "col", st, col_bytes(b, S.cols, nmid, nin));
             launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(),
-                       ColArgs{COL_CORR, nmid, nin, 1.0, nullptr});
+                       ColArgs{COL_CORR, nmid, nin, 1.0, nullptr}, b.colp2);
         }
         {
             ProfSpan p(b.ctx, "row_out", st, row_bytes(b, S.rout, 1, 0, 2 * vs));
@@ -997,7 +1000,7 @@ int run_finish(Batch& b) {
         const int nin = d0->op.S[s].boxA, nmid = d0->op.S[1 - s].boxA;
         launch_row_in(b.f64, b.cls, rin.n(), st, b.ops(), b.lzs(), b.res(), rin.ptr(),
                       RowInArgs{IN_VEC, s, 0, DEST_T1, 1.0, 0, nullptr});
-        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_CORR, nin, nmid, 1.0, nullptr});
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_CORR, nin, nmid, 1.0, nullptr}, b.colp2);
         launch_row_mid(b.f64, b.cls, rmid.n(), st, b.ops(), b.lzs(), b.res(), rmid.ptr(),
                        RowMidArgs{1 - s, OUT_VEC, 1.0, 1, 0, 0, 0, 0});
     }
@@ -1062,10 +1065,10 @@ int run_reconstruct(Batch& b, const std::vector<int>& gptr, const std::vector<in
             return rc;
         launch_row_in(b.f64, b.cls, a1.n(), st, b.ops(), b.lzs(), b.res(), a1.ptr(),
                       RowInArgs{IN_VEC, 0, 0, DEST_T1, 1.0, 0, nullptr});
-        launch_col(b.f64, c1.n(), st, b.ops(), b.res(), c1.ptr(), ColArgs{COL_STORE, d0->LA, 0, 1.0, nullptr});
+        launch_col(b.f64, c1.n(), st, b.ops(), b.res(), c1.ptr(), ColArgs{COL_STORE, d0->LA, 0, 1.0, nullptr}, b.colp2);
         launch_row_in(b.f64, b.cls, a2.n(), st, b.ops(), b.lzs(), b.res(), a2.ptr(),
                       RowInArgs{IN_VEC, 1, 0, DEST_T1, 1.0, 1, nullptr});
-        launch_col(b.f64, c2.n(), st, b.ops(), b.res(), c2.ptr(), ColArgs{COL_ACCUM, d0->KA, d0->A, 1.0, nullptr});
+        launch_col(b.f64, c2.n(), st, b.ops(), b.res(), c2.ptr(), ColArgs{COL_ACCUM, d0->KA, d0->A, 1.0, nullptr}, b.colp2);
         launch_row_out(b.f64, b.cls, out.n(), st, b.ops(), b.lzs(), b.res(), out.ptr(),
                        RowOutArgs{OUT_IMAGE, 0, 1.0 / ((double)d0->MA * d0->MB), 0, 0, 0});
     }
@@ -1100,7 +1103,8 @@ int decompose_many(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** ou
         for (int i : kv.second) b.ds.push_back(ds[i].get());
         b.f64 = b.ds[0]->f64;
         b.rowfam = b.ds[0]->rowfam;
-        b.cls = row_class(b.ds[0]->nh, b.f64);
+        b.cls = row_class(b.ds[0]->nh, b.f64) | (is_pow2(b.ds[0]->nh) ? 8 : 0);
+        b.colp2 = is_pow2(b.ds[0]->MA);
         b.TC = col_tile(b.f64);
         auto t0 = Clock::now();
         int rc = run_setup(b);
@@ -1417,7 +1421,8 @@ int ssa_reconstruct(ssa_decomp* d, const int* gp, const int* gi, int ng, double*
     b.ds = {d};
     b.f64 = d->f64;
     b.rowfam = d->rowfam;
-    b.cls = row_class(d->nh, d->f64);
+    b.cls = row_class(d->nh, d->f64) | (is_pow2(d->nh) ? 8 : 0);
+    b.colp2 = is_pow2(d->MA);
     b.TC = col_tile(d->f64);
     rc = run_reconstruct(b, std::vector<int>(gp, gp + ng + 1), std::vector<int>(gi, gi + gp[ng]), {buf});
     if (!rc) {
@@ -1451,7 +1456,8 @@ int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* gp, const 
     b.ds.assign(d, d + n);
     b.f64 = d[0]->f64;
     b.rowfam = d[0]->rowfam;
-    b.cls = row_class(d[0]->nh, d[0]->f64);
+    b.cls = row_class(d[0]->nh, d[0]->f64) | (is_pow2(d[0]->nh) ? 8 : 0);
+    b.colp2 = is_pow2(d[0]->MA);
     b.TC = col_tile(d[0]->f64);
     return run_reconstruct(b, std::vector<int>(gp, gp + ng + 1), std::vector<int>(gi, gi + gp[ng]),
                            std::vector<double*>(out_dev, out_dev + n));

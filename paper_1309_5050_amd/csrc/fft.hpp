@@ -178,11 +178,21 @@ __device__ __forceinline__ void fft_pass(cplx<T>* s, int n, int Ns, const cplx<T
 // Complex FFT of length pl.n <= NMAX in LDS, G threads (tid in [0, G)).
 // Starts and ends with the buffer synchronised (caller must have issued a
 // barrier after filling s).
-template <typename T, int NMAX, int G, int DIR>
+// P2: the plan has only radices 2, 4 and 8 (the odd-radix passes are not
+// compiled in, which keeps the register footprint of the kernel small).
+template <typename T, int NMAX, int G, int DIR, bool P2 = false>
 __device__ void fft_lds(cplx<T>* s, const FftPlan& pl, int tid) {
     const cplx<T>* tw = static_cast<const cplx<T>*>(pl.tw);
     int Ns = 1;
     for (int p = 0; p < pl.npass; ++p) {
+        if constexpr (P2) {
+            switch (pl.radix[p]) {
+            case 2: fft_pass<T, 2, cdiv(NMAX, 2 * G), DIR>(s, pl.n, Ns, tw, tid, G); Ns *= 2; break;
+            case 4: fft_pass<T, 4, cdiv(NMAX, 4 * G), DIR>(s, pl.n, Ns, tw, tid, G); Ns *= 4; break;
+            default: fft_pass<T, 8, cdiv(NMAX, 8 * G), DIR>(s, pl.n, Ns, tw, tid, G); Ns *= 8; break;
+            }
+            continue;
+        }
         switch (pl.radix[p]) {
         case 2: fft_pass<T, 2, cdiv(NMAX, 2 * G), DIR>(s, pl.n, Ns, tw, tid, G); Ns *= 2; break;
         case 3: fft_pass<T, 3, cdiv(NMAX, 3 * G), DIR>(s, pl.n, Ns, tw, tid, G); Ns *= 3; break;
@@ -196,9 +206,9 @@ __device__ void fft_lds(cplx<T>* s, const FftPlan& pl, int tid) {
 
 // Real forward transform of length 2n held in s as n complex pairs.
 // On return s[0..n] = X[0..n] (n+1 values).  Ends synchronised.
-template <typename T, int NMAX, int G>
+template <typename T, int NMAX, int G, bool P2 = false>
 __device__ void rfft_fwd(cplx<T>* s, const FftPlan& pl, int tid) {
-    fft_lds<T, NMAX, G, -1>(s, pl, tid);
+    fft_lds<T, NMAX, G, -1, P2>(s, pl, tid);
     const int n = pl.n;
     const cplx<T>* twr = static_cast<const cplx<T>*>(pl.twr);
     for (int k = tid; k <= n / 2; k += G) {
@@ -217,7 +227,7 @@ __device__ void rfft_fwd(cplx<T>* s, const FftPlan& pl, int tid) {
 
 // Inverse of rfft_fwd: from X[0..n] in s, leaves 2n * x (real, as n complex
 // pairs) in s[0..n).  Ends synchronised.
-template <typename T, int NMAX, int G>
+template <typename T, int NMAX, int G, bool P2 = false>
 __device__ void rfft_inv(cplx<T>* s, const FftPlan& pl, int tid) {
     const int n = pl.n;
     const cplx<T>* twr = static_cast<const cplx<T>*>(pl.twr);
@@ -233,7 +243,7 @@ __device__ void rfft_inv(cplx<T>* s, const FftPlan& pl, int tid) {
         if (k != 0 && k != k2) s[k2] = {e.x + o.y, -e.y + o.x};
     }
     __syncthreads();
-    fft_lds<T, NMAX, G, +1>(s, pl, tid);
+    fft_lds<T, NMAX, G, +1, P2>(s, pl, tid);
 }
 
 }  // namespace shssa

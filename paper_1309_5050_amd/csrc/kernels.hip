@@ -107,10 +107,13 @@ __device__ __forceinline__ double slot_sum(double v, double* red) {
     }
 }
 
+// Sum of n partials p[0..n) by one wave: lane l adds p[l], p[l+64], ...,
+// then the lanes combine.  Every lane of every wave gets the same total
+// (the order is fixed, so the result does not depend on the caller).
 __device__ __forceinline__ double sum_parts(const double* p, int n) {
     double s = 0.0;
-    for (int q = 0; q < n; ++q) s += p[q];
-    return s;
+    for (int q = lane_id(); q < n; q += 64) s += p[q];
+    return wave_sum(s);
 }
 
 // ------------------------------------------------------------------------
@@ -119,7 +122,7 @@ __device__ __forceinline__ double sum_parts(const double* p, int n) {
 
 
 
-template <typename T, int NMAX, int G, int SLOTS>
+template <typename T, int NMAX, int G, int SLOTS, bool P2>
 __global__ void __launch_bounds__(G * SLOTS)
 k_row_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
          const Item* __restrict__ items, int nitems, RowInArgs args) {
@@ -184,7 +187,7 @@ k_row_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const R
         });
     }
     __syncthreads();
-    rfft_fwd<T, NMAX, G>(s, op.prow, tid);
+    rfft_fwd<T, NMAX, G, P2>(s, op.prow, tid);
     if (!valid) return;
     const int n1 = op.prow.n + 1;
     cplx<T>* out;
@@ -228,7 +231,7 @@ __device__ __forceinline__ GkLong<T> gk_long(const LzDesc& lz, const CellSet& Sl
 }
 
 // C2R of T2 row a, mask to a set row, optional emission, R2C into T1 row a.
-template <typename T, int NMAX, int G, int SLOTS>
+template <typename T, int NMAX, int G, int SLOTS, bool P2>
 __global__ void __launch_bounds__(G * SLOTS)
 k_row_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
           const Item* __restrict__ items, int nitems, RowMidArgs args) {
@@ -247,7 +250,7 @@ k_row_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     const cplx<T>* in = static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P;
     for (int f = tid; f < n1; f += G) s[f] = in[f];
     __syncthreads();
-    rfft_inv<T, NMAX, G>(s, op.prow, tid);
+    rfft_inv<T, NMAX, G, P2>(s, op.prow, tid);
     const CellSet& S = op.S[args.set];
     double* vout = nullptr;
     double sc = args.scale;
@@ -280,7 +283,7 @@ k_row_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     }
     if (!args.fwd) return;
     __syncthreads();
-    rfft_fwd<T, NMAX, G>(s, op.prow, tid);
+    rfft_fwd<T, NMAX, G, P2>(s, op.prow, tid);
     if (!valid) return;
     cplx<T>* out = static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.P;
     for (int f = tid; f < n1; f += G) out[f] = s[f];
@@ -317,7 +320,7 @@ __device__ __forceinline__ GkShort gk_short(const LzDesc& lz, const CellSet& Slo
 }
 
 // C2R of T2 row a, gathered on a set row (compact output) or written dense.
-template <typename T, int NMAX, int G, int SLOTS>
+template <typename T, int NMAX, int G, int SLOTS, bool P2>
 __global__ void __launch_bounds__(G * SLOTS)
 k_row_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
           const Item* __restrict__ items, int nitems, RowOutArgs args) {
@@ -335,7 +338,7 @@ k_row_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     const cplx<T>* in = static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P;
     for (int f = tid; f < n1; f += G) s[f] = in[f];
     __syncthreads();
-    rfft_inv<T, NMAX, G>(s, op.prow, tid);
+    rfft_inv<T, NMAX, G, P2>(s, op.prow, tid);
     if (args.mode == OUT_IMAGE) {
         if (!valid) return;
         const ResDesc& rs = res[item.inst];
@@ -373,7 +376,7 @@ k_row_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
 // Per (instance, row a, component): v = C2R(Xh_a conj(U^)), mask to the
 // origin row a, then P_a = Xh_a conj(FFT(v)) into T2 slot comp row a.
 // U^ is the spectrum of the window row in T1 slot comp row 0.
-template <typename T, int NMAX, int G, int SLOTS>
+template <typename T, int NMAX, int G, int SLOTS, bool P2>
 __global__ void __launch_bounds__(G * SLOTS)
 k_rowfam_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
              const Item* __restrict__ items, int nitems, RowFamArgs args) {
@@ -393,7 +396,7 @@ k_rowfam_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, con
     const cplx<T>* xh = static_cast<const cplx<T>*>(op.Xh) + (long)a * op.P;
     for (int f = tid; f < n1; f += G) s[f] = cmulc(xh[f], uh[f]);
     __syncthreads();
-    rfft_inv<T, NMAX, G>(s, op.prow, tid);
+    rfft_inv<T, NMAX, G, P2>(s, op.prow, tid);
     const CellSet& S = op.S[1];
     double* vout = nullptr;
     double sc = 1.0;
@@ -426,7 +429,7 @@ k_rowfam_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, con
     }
     if (!args.full) return;
     __syncthreads();
-    rfft_fwd<T, NMAX, G>(s, op.prow, tid);
+    rfft_fwd<T, NMAX, G, P2>(s, op.prow, tid);
     if (!valid) return;
     cplx<T>* out = static_cast<cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P;
     for (int f = tid; f < n1; f += G) out[f] = cmulc(xh[f], s[f]);
@@ -434,7 +437,7 @@ k_rowfam_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, con
 
 // Per (instance, component): sum_a P_a in row order, C2R, gather the window
 // row into the Lanczos w (OUT_LZ) or a result vector.
-template <typename T, int NMAX, int G, int SLOTS>
+template <typename T, int NMAX, int G, int SLOTS, bool P2>
 __global__ void __launch_bounds__(G * SLOTS)
 k_rowfam_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs,
              const Item* __restrict__ items, int nitems, RowOutArgs args) {
@@ -455,7 +458,7 @@ k_rowfam_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs,
         s[f] = acc;
     }
     __syncthreads();
-    rfft_inv<T, NMAX, G>(s, op.prow, tid);
+    rfft_inv<T, NMAX, G, P2>(s, op.prow, tid);
     const LzDesc& lz = lzs[item.inst];
     const GkShort g = gk_short(lz, op.S[1], args.j, args.jstart, valid && tid == 0);
     scan_row<G>(op.S[0], 0, op.MB, tid, wtot, [&](int b, long idx) {
@@ -465,7 +468,7 @@ k_rowfam_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs,
 
 // Row-family reconstruction of group `comp` on row a: for each i in the
 // group, FFT(sigma_i V_i row a) * U^_i summed, one C2R, divided by W.
-template <typename T, int NMAX, int G, int SLOTS>
+template <typename T, int NMAX, int G, int SLOTS, bool P2>
 __global__ void __launch_bounds__(G * SLOTS)
 k_rowfam_recon(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
                const Item* __restrict__ items, int nitems, double scale) {
@@ -495,7 +498,7 @@ k_rowfam_recon(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
             sr[b] = idx >= 0 ? to<T>(sg * v[idx]) : T(0);
         });
         __syncthreads();
-        rfft_fwd<T, NMAX, G>(s, op.prow, tid);
+        rfft_fwd<T, NMAX, G, P2>(s, op.prow, tid);
         const cplx<T>* uh = static_cast<const cplx<T>*>(op.Us) + (long)i * op.uslot;
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
@@ -510,7 +513,7 @@ k_rowfam_recon(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
         if (f < n1) s[f] = acc[p];
     }
     __syncthreads();
-    rfft_inv<T, NMAX, G>(s, op.prow, tid);
+    rfft_inv<T, NMAX, G, P2>(s, op.prow, tid);
     if (!valid) return;
     double* out = rs.recon + (long)item.comp * op.A * op.B + (long)a * op.B;
     const double* W = op.W + (long)a * op.B;
@@ -538,7 +541,7 @@ __global__ void k_copy_uspec(const OpDesc* __restrict__ ops, const Item* __restr
 
 // One workgroup transforms TC adjacent columns f0..f0+TC of a [rows][P]
 // array; each column is an independent length-MA transform on G threads.
-template <typename T, int NMAX, int G, int TC>
+template <typename T, int NMAX, int G, int TC, bool P2>
 __global__ void __launch_bounds__(G * TC)
 k_col(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
       const Item* __restrict__ items, int nitems, ColArgs args) {
@@ -574,7 +577,7 @@ k_col(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
             const int i = rs.gidx[g];
             load_rows(static_cast<const cplx<T>*>(op.T1) + i * op.tslot, args.nin);
             __syncthreads();
-            fft_lds<T, NMAX, G, -1>(s, op.pcol, tid);
+            fft_lds<T, NMAX, G, -1, P2>(s, op.pcol, tid);
             const cplx<T>* uh = static_cast<const cplx<T>*>(op.Us) + (long)i * op.uslot;
 #pragma unroll
             for (int p = 0; p < PER; ++p) {
@@ -590,11 +593,11 @@ k_col(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
             if (a < MA) s[a] = acc[p];
         }
         __syncthreads();
-        fft_lds<T, NMAX, G, +1>(s, op.pcol, tid);
+        fft_lds<T, NMAX, G, +1, P2>(s, op.pcol, tid);
     } else {
         load_rows(static_cast<const cplx<T>*>(op.T1) + item.comp * op.tslot, args.nin);
         __syncthreads();
-        fft_lds<T, NMAX, G, -1>(s, op.pcol, tid);
+        fft_lds<T, NMAX, G, -1, P2>(s, op.pcol, tid);
         if (args.mode == COL_SPEC || args.mode == COL_STORE) {
             cplx<T>* dst = args.mode == COL_SPEC ? static_cast<cplx<T>*>(const_cast<void*>(op.Xh))
                                                  : static_cast<cplx<T>*>(op.Us) + (long)item.comp * op.uslot;
@@ -617,7 +620,7 @@ k_col(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
             if (f < P) buf[cc * LD + a] = cmulc(xh[(long)f * MA + a], buf[cc * LD + a]);
         }
         __syncthreads();
-        fft_lds<T, NMAX, G, +1>(s, op.pcol, tid);
+        fft_lds<T, NMAX, G, +1, P2>(s, op.pcol, tid);
     }
     cplx<T>* out = static_cast<cplx<T>*>(op.T2) + item.comp * op.tslot;
     for (int e = threadIdx.x; e < args.nout * TC; e += nthr) {
@@ -912,16 +915,23 @@ k_lz_normalize(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, i
 // beta |Yr[m-1, i]| <= tol * sigma_1 is evaluated for the r leading ones.
 __global__ void __launch_bounds__(1024)
 k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, int max_sweeps) {
-    __shared__ double Bs[kMaxBasis * kMaxBasis];
+    // B columns and, when they fit next to them (m <= 100), the right vectors
+    // live in LDS; otherwise the right vectors rotate in global memory.
+    constexpr int kLds = 20320;
+    __shared__ double lds[kLds];
     __shared__ double cn[kMaxBasis];
     __shared__ int changed;
     const Item item = items[blockIdx.x];
     const LzDesc& lz = lzs[item.inst];
     const int nt = blockDim.x;
+    double* Bs = lds;
+    const bool ylds = 2 * m * m <= kLds;
+    double* Y = ylds ? lds + m * m : lz.Yr;
+    const int ldy = ylds ? m : kMaxBasis;
     for (int e = threadIdx.x; e < m * m; e += nt) {
         const int i = e % m, c = e / m;
         Bs[c * m + i] = lz.Bm[(long)c * kMaxBasis + i];
-        lz.Yr[(long)c * kMaxBasis + i] = i == c ? 1.0 : 0.0;
+        Y[(long)c * ldy + i] = i == c ? 1.0 : 0.0;
     }
     __syncthreads();
     const int nn = m + (m & 1);
@@ -960,8 +970,8 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
                             bp[i] = c * x1 - s * x2;
                             bq[i] = s * x1 + c * x2;
                         }
-                        double* yp = lz.Yr + (long)p * kMaxBasis;
-                        double* yq = lz.Yr + (long)q * kMaxBasis;
+                        double* yp = Y + (long)p * ldy;
+                        double* yq = Y + (long)q * ldy;
                         for (int i = g; i < m; i += 16) {
                             const double y1 = yp[i], y2 = yq[i];
                             yp[i] = c * y1 - s * y2;
@@ -984,6 +994,7 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
     for (int e = threadIdx.x; e < m * m; e += nt) {
         const int i = e % m, c = e / m;
         lz.Yl[(long)c * kMaxBasis + i] = cn[c] > 0 ? Bs[c * m + i] / cn[c] : 0.0;
+        if (ylds) lz.Yr[(long)c * kMaxBasis + i] = Y[c * m + i];
     }
     for (int i = threadIdx.x; i < m; i += nt) {
         const double ti = cn[i];
@@ -997,12 +1008,14 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        const int r = lz.r;
         const double beta = lz.beta[0];
         const double s1 = lz.sig[0];
         int ok = 1;
         double worst = 0.0;
-        for (int i = 0; i < lz.r; ++i) {
-            const double resid = fabs(beta * lz.Yr[(long)lz.perm[i] * kMaxBasis + (m - 1)]);
+        for (int i = 0; i < r; ++i) {
+            const int c = lz.perm[i];
+            const double resid = fabs(beta * (ylds ? Y[c * m + (m - 1)] : lz.Yr[(long)c * kMaxBasis + (m - 1)]));
             if (!(resid <= lz.tol * s1)) ok = 0;
             worst = fmax(worst, s1 > 0 ? resid / s1 : 0.0);
         }

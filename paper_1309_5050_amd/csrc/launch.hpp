@@ -21,8 +21,9 @@ void launch_rowfam_out(bool f64, int cls, int nitems, hipStream_t st, const OpDe
 void launch_rowfam_recon(bool f64, int cls, int nitems, hipStream_t st, const OpDesc* ops, const ResDesc* res,
                          const Item* items, double scale);
 void launch_copy_uspec(bool f64, int nitems, hipStream_t st, const OpDesc* ops, const Item* items);
+// cls: row size class, plus 8 when the row plan has radices 2, 4, 8 only.
 void launch_col(bool f64, int nitems, hipStream_t st, const OpDesc* ops, const ResDesc* res, const Item* items,
-                ColArgs a);
+                ColArgs a, bool p2);
 void launch_shape_clean(int nitems, hipStream_t st, const OpDesc* ops, const Item* items, const double* const* x,
                         const uint8_t* const* m, uint8_t* const* nset, double* const* xc, int* const* npref);
 void launch_shape_origins(int nitems, hipStream_t st, const OpDesc* ops, const Item* items, const Runs* runs,
