@@ -56,6 +56,7 @@ struct CellSet {
     long count;              // number of cells
     const uint8_t* mask;     // boxA*boxB bytes, row-major; nullptr = full box
     const int* rowoff;       // boxA+1 offsets into the compact order
+    const int* pref;         // boxA x (boxB+1): cells of the row before column b (with mask)
 };
 
 }  // namespace shssa

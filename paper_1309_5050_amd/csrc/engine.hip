@@ -87,6 +87,7 @@ struct ssa_ctx {
     size_t used = 0;
     std::mutex mu;
     std::map<std::tuple<int, int, int>, void*> tw;   // (n, f64, real split) -> table
+    std::map<std::pair<int, int>, int> col_tc;       // (f64, MA) -> tuned column tile
     // kernel timing (see ssa_ctx_profile)
     std::string prof_kind;
     std::vector<hipEvent_t> ev_pool;
@@ -211,7 +212,7 @@ struct ssa_decomp {
     size_t bytes = 0;
     double *x = nullptr, *xc = nullptr, *W = nullptr;
     uint8_t *mask = nullptr, *nset = nullptr, *kmask = nullptr, *lmask = nullptr;
-    int *npref = nullptr, *kpref = nullptr, *kcount = nullptr, *krow = nullptr, *lrow = nullptr, *runs = nullptr;
+    int *npref = nullptr, *kpref = nullptr, *lpref = nullptr, *kcount = nullptr, *krow = nullptr, *lrow = nullptr, *runs = nullptr;
     void *Xh = nullptr, *T1 = nullptr, *T2 = nullptr, *Us = nullptr;
     long tslot = 0, uslot = 0;
     double *Q = nullptr, *w = nullptr, *sinv = nullptr, *hp1 = nullptr, *hp2 = nullptr, *np = nullptr;
@@ -413,10 +414,23 @@ int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStrea
     if ((rc = d->dalloc(&d->W, n))) return rc;
     const bool lfull = d->L == (long)d->LA * d->LB;
     if (!lfull && (rc = d->dalloc(&d->lmask, (long)d->LA * d->LB))) return rc;
+    std::vector<int> lpref_h;
+    if (!lfull) {
+        // per-row exclusive prefix counts of the window mask
+        lpref_h.assign((size_t)d->LA * (d->LB + 1), 0);
+        for (int a = 0; a < d->LA; ++a) {
+            int* pr = lpref_h.data() + (size_t)a * (d->LB + 1);
+            for (int b = 0; b < d->LB; ++b) pr[b + 1] = pr[b] + d->lmask_h[(size_t)a * d->LB + b];
+        }
+        if ((rc = d->dalloc(&d->lpref, (long)lpref_h.size()))) return rc;
+    }
     if ((rc = d->dalloc(&d->lrow, d->LA + 1))) return rc;
     const int nrun = (int)d->ra.size();
     if ((rc = d->dalloc(&d->runs, 3 * (long)nrun))) return rc;
-    if (!lfull) HIPCHK(hipMemcpyAsync(d->lmask, d->lmask_h.data(), d->lmask_h.size(), hipMemcpyHostToDevice, st));
+    if (!lfull) {
+        HIPCHK(hipMemcpyAsync(d->lmask, d->lmask_h.data(), d->lmask_h.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(d->lpref, lpref_h.data(), lpref_h.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    }
     HIPCHK(hipMemcpyAsync(d->lrow, d->lrow_h.data(), (d->LA + 1) * sizeof(int), hipMemcpyHostToDevice, st));
     std::vector<int> rr;
     rr.insert(rr.end(), d->ra.begin(), d->ra.end());
@@ -429,8 +443,8 @@ int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStrea
     OpDesc& o = d->op;
     o.A = d->A; o.B = d->B; o.MA = d->MA; o.MB = d->MB; o.P = d->P;
     o.rowfam = d->rowfam;
-    o.S[0] = CellSet{d->LA, d->LB, d->L, lfull ? nullptr : d->lmask, d->lrow};
-    o.S[1] = CellSet{d->KA, d->KB, 0, d->kmask, d->krow};
+    o.S[0] = CellSet{d->LA, d->LB, d->L, lfull ? nullptr : d->lmask, d->lrow, lfull ? nullptr : d->lpref};
+    o.S[1] = CellSet{d->KA, d->KB, 0, d->kmask, d->krow, d->kpref};
     o.W = d->W;
     o.xc = d->xc;
     o.nset = d->nset;
@@ -624,9 +638,65 @@ int run_setup(Batch& b) {
         auto* d = b.ds[i];
         d->K = tot[i];
         d->op.S[1].count = d->K;
+        // every origin of the box is in K: the row visits skip the mask
+        if (d->K == (long)d->KA * d->KB) d->op.S[1].mask = nullptr;
         if (d->K == 0) d->status = fail(SSA_EEMPTY, "no window position fits inside the array");
         else if (d->r >= std::min(d->L, d->K)) d->status = fail(SSA_ERANK, "r must be < min(L, K)");
     }
+    return SSA_OK;
+}
+
+// Column tile autotuner: the first batch of a (precision, column length)
+// times the spectrum pass (idempotent: it rewrites the spectrum) with every
+// compiled tile width and keeps the fastest for the context.  SHSSA_COL_TILE
+// forces a width.
+int tune_col_tile(Batch& b) {
+    const auto* d0 = b.ds[0];
+    const auto key = std::make_pair((int)b.f64, d0->MA);
+    if (const char* e = std::getenv("SHSSA_COL_TILE")) {
+        const int tc = std::atoi(e);
+        if (col_tile_ok(b.f64, tc)) {
+            b.TC = tc;
+            return SSA_OK;
+        }
+    }
+    auto it = b.ctx->col_tc.find(key);
+    if (it != b.ctx->col_tc.end()) {
+        b.TC = it->second;
+        return SSA_OK;
+    }
+    hipStream_t st = b.st;
+    const int ni = (int)b.ds.size();
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_tc = col_tile(b.f64);
+    const int cands32[] = {4, 8, 16}, cands64[] = {2, 4};
+    const int* cands = b.f64 ? cands64 : cands32;
+    const int nc = b.f64 ? 2 : 3;
+    int rc = SSA_OK;
+    for (int k = 0; k < nc && rc == SSA_OK; ++k) {
+        const int tc = cands[k];
+        ItemList cols;
+        for (int i = 0; i < ni; ++i)
+            for (int t = 0; t < (b.ds[i]->P + tc - 1) / tc; ++t) cols.h.push_back(Item{i, t, 0, 0});
+        if ((rc = cols.upload(st))) break;
+        ColArgs c{COL_SPEC, d0->A, 0, 1.0 / ((double)d0->MA * d0->MB), nullptr};
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.colp2, tc);   // warm-up
+        (void)hipEventRecord(e0, st);
+        for (int rep = 0; rep < 3; ++rep) launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.colp2, tc);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SSA_EDEVICE, "tuning"); break; }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) { best = ms; best_tc = tc; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    b.ctx->col_tc[key] = best_tc;
+    b.TC = best_tc;
     return SSA_OK;
 }
 
@@ -713,12 +783,13 @@ int run_alloc_spectrum(Batch& b) {
     } else {
         RowInArgs a{IN_DENSE, 0, 0, DEST_T1, 1.0, 0, nullptr};
         launch_row_in(b.f64, b.cls, rowsA.n(), st, b.ops(), b.lzs(), b.res(), rowsA.ptr(), a);
+        if ((rc = tune_col_tile(b))) return rc;
         ItemList cols;
         for (int i = 0; i < ni; ++i)
             for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) cols.h.push_back(Item{i, t, 0, 0});
         if ((rc = cols.upload(st))) return rc;
         ColArgs c{COL_SPEC, d0->A, 0, 1.0 / ((double)d0->MA * d0->MB), nullptr};
-        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.colp2);
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.colp2, b.TC);
         HIPCHK(hipStreamSynchronize(st));
     }
     HIPCHK(hipStreamSynchronize(st));
@@ -795,7 +866,7 @@ void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode) {
         {
             ProfSpan p(b.ctx, "col", st, col_bytes(b, S.cols, nin, nmid));
             launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(),
-                       ColArgs{COL_CORR, nin, nmid, 1.0, nullptr}, b.colp2);
+                       ColArgs{COL_CORR, nin, nmid, 1.0, nullptr}, b.colp2, b.TC);
         }
         {
             ProfSpan p(b.ctx, "row_mid", st, row_bytes(b, S.rmid, 1, 1, 2 * vl));
@@ -805,7 +876,7 @@ void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode) {
         {
             ProfSpan p(b.ctx, "col", st, col_bytes(b, S.cols, nmid, nin));
             launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(),
-                       ColArgs{COL_CORR, nmid, nin, 1.0, nullptr}, b.colp2);
+                       ColArgs{COL_CORR, nmid, nin, 1.0, nullptr}, b.colp2, b.TC);
         }
         {
             ProfSpan p(b.ctx, "row_out", st, row_bytes(b, S.rout, 1, 0, 2 * vs));
@@ -1000,7 +1071,7 @@ int run_finish(Batch& b) {
         const int nin = d0->op.S[s].boxA, nmid = d0->op.S[1 - s].boxA;
         launch_row_in(b.f64, b.cls, rin.n(), st, b.ops(), b.lzs(), b.res(), rin.ptr(),
                       RowInArgs{IN_VEC, s, 0, DEST_T1, 1.0, 0, nullptr});
-        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_CORR, nin, nmid, 1.0, nullptr}, b.colp2);
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_CORR, nin, nmid, 1.0, nullptr}, b.colp2, b.TC);
         launch_row_mid(b.f64, b.cls, rmid.n(), st, b.ops(), b.lzs(), b.res(), rmid.ptr(),
                        RowMidArgs{1 - s, OUT_VEC, 1.0, 1, 0, 0, 0, 0});
     }
@@ -1065,10 +1136,10 @@ int run_reconstruct(Batch& b, const std::vector<int>& gptr, const std::vector<in
             return rc;
         launch_row_in(b.f64, b.cls, a1.n(), st, b.ops(), b.lzs(), b.res(), a1.ptr(),
                       RowInArgs{IN_VEC, 0, 0, DEST_T1, 1.0, 0, nullptr});
-        launch_col(b.f64, c1.n(), st, b.ops(), b.res(), c1.ptr(), ColArgs{COL_STORE, d0->LA, 0, 1.0, nullptr}, b.colp2);
+        launch_col(b.f64, c1.n(), st, b.ops(), b.res(), c1.ptr(), ColArgs{COL_STORE, d0->LA, 0, 1.0, nullptr}, b.colp2, b.TC);
         launch_row_in(b.f64, b.cls, a2.n(), st, b.ops(), b.lzs(), b.res(), a2.ptr(),
                       RowInArgs{IN_VEC, 1, 0, DEST_T1, 1.0, 1, nullptr});
-        launch_col(b.f64, c2.n(), st, b.ops(), b.res(), c2.ptr(), ColArgs{COL_ACCUM, d0->KA, d0->A, 1.0, nullptr}, b.colp2);
+        launch_col(b.f64, c2.n(), st, b.ops(), b.res(), c2.ptr(), ColArgs{COL_ACCUM, d0->KA, d0->A, 1.0, nullptr}, b.colp2, b.TC);
         launch_row_out(b.f64, b.cls, out.n(), st, b.ops(), b.lzs(), b.res(), out.ptr(),
                        RowOutArgs{OUT_IMAGE, 0, 1.0 / ((double)d0->MA * d0->MB), 0, 0, 0});
     }
@@ -1106,6 +1177,10 @@ int decompose_many(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** ou
         b.cls = row_class(b.ds[0]->nh, b.f64) | (is_pow2(b.ds[0]->nh) ? 8 : 0);
         b.colp2 = is_pow2(b.ds[0]->MA);
         b.TC = col_tile(b.f64);
+        {
+            auto it = ctx->col_tc.find(std::make_pair((int)b.f64, b.ds[0]->MA));
+            if (it != ctx->col_tc.end()) b.TC = it->second;
+        }
         auto t0 = Clock::now();
         int rc = run_setup(b);
         if (rc) {
@@ -1424,6 +1499,10 @@ int ssa_reconstruct(ssa_decomp* d, const int* gp, const int* gi, int ng, double*
     b.cls = row_class(d->nh, d->f64) | (is_pow2(d->nh) ? 8 : 0);
     b.colp2 = is_pow2(d->MA);
     b.TC = col_tile(d->f64);
+    {
+        auto it = d->ctx->col_tc.find(std::make_pair((int)d->f64, d->MA));
+        if (it != d->ctx->col_tc.end()) b.TC = it->second;
+    }
     rc = run_reconstruct(b, std::vector<int>(gp, gp + ng + 1), std::vector<int>(gi, gi + gp[ng]), {buf});
     if (!rc) {
         if (!d->tr) {
@@ -1459,6 +1538,10 @@ int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* gp, const 
     b.cls = row_class(d[0]->nh, d[0]->f64) | (is_pow2(d[0]->nh) ? 8 : 0);
     b.colp2 = is_pow2(d[0]->MA);
     b.TC = col_tile(d[0]->f64);
+    {
+        auto it = d[0]->ctx->col_tc.find(std::make_pair((int)d[0]->f64, d[0]->MA));
+        if (it != d[0]->ctx->col_tc.end()) b.TC = it->second;
+    }
     return run_reconstruct(b, std::vector<int>(gp, gp + ng + 1), std::vector<int>(gi, gi + gp[ng]),
                            std::vector<double*>(out_dev, out_dev + n));
 }

@@ -180,9 +180,9 @@ __device__ __forceinline__ void fft_pass(cplx<T>* s, int n, int Ns, const cplx<T
 // barrier after filling s).
 // P2: the plan has only radices 2, 4 and 8 (the odd-radix passes are not
 // compiled in, which keeps the register footprint of the kernel small).
+// tw: the plan's twiddle table (global, or a copy staged in LDS).
 template <typename T, int NMAX, int G, int DIR, bool P2 = false>
-__device__ void fft_lds(cplx<T>* s, const FftPlan& pl, int tid) {
-    const cplx<T>* tw = static_cast<const cplx<T>*>(pl.tw);
+__device__ void fft_lds(cplx<T>* s, const FftPlan& pl, const cplx<T>* tw, int tid) {
     int Ns = 1;
     for (int p = 0; p < pl.npass; ++p) {
         if constexpr (P2) {
@@ -207,10 +207,9 @@ __device__ void fft_lds(cplx<T>* s, const FftPlan& pl, int tid) {
 // Real forward transform of length 2n held in s as n complex pairs.
 // On return s[0..n] = X[0..n] (n+1 values).  Ends synchronised.
 template <typename T, int NMAX, int G, bool P2 = false>
-__device__ void rfft_fwd(cplx<T>* s, const FftPlan& pl, int tid) {
-    fft_lds<T, NMAX, G, -1, P2>(s, pl, tid);
+__device__ void rfft_fwd(cplx<T>* s, const FftPlan& pl, const cplx<T>* tw, const cplx<T>* twr, int tid) {
+    fft_lds<T, NMAX, G, -1, P2>(s, pl, tw, tid);
     const int n = pl.n;
-    const cplx<T>* twr = static_cast<const cplx<T>*>(pl.twr);
     for (int k = tid; k <= n / 2; k += G) {
         const int k2 = k == 0 ? 0 : n - k;
         const cplx<T> zk = s[k], zn = s[k2];
@@ -228,9 +227,8 @@ __device__ void rfft_fwd(cplx<T>* s, const FftPlan& pl, int tid) {
 // Inverse of rfft_fwd: from X[0..n] in s, leaves 2n * x (real, as n complex
 // pairs) in s[0..n).  Ends synchronised.
 template <typename T, int NMAX, int G, bool P2 = false>
-__device__ void rfft_inv(cplx<T>* s, const FftPlan& pl, int tid) {
+__device__ void rfft_inv(cplx<T>* s, const FftPlan& pl, const cplx<T>* tw, const cplx<T>* twr, int tid) {
     const int n = pl.n;
-    const cplx<T>* twr = static_cast<const cplx<T>*>(pl.twr);
     for (int k = tid; k <= n / 2; k += G) {
         const int k2 = n - k;
         const cplx<T> xk = s[k], xn = s[k2];
@@ -243,7 +241,7 @@ __device__ void rfft_inv(cplx<T>* s, const FftPlan& pl, int tid) {
         if (k != 0 && k != k2) s[k2] = {e.x + o.y, -e.y + o.x};
     }
     __syncthreads();
-    fft_lds<T, NMAX, G, +1, P2>(s, pl, tid);
+    fft_lds<T, NMAX, G, +1, P2>(s, pl, tw, tid);
 }
 
 }  // namespace shssa

@@ -34,55 +34,41 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
-// Compact index of cell (a, b) of a set row, visiting b = 0..len-1 in chunks
-// of G threads.  fn(b, idx) is called for every b < len with idx = compact
-// index or -1 (b outside the set or beyond the box).  G == 64 slots scan with
-// one ballot per chunk; wider slots (one per workgroup) combine wave counts
-// through LDS, so every thread of the workgroup must call this.
-template <int G, typename F>
-__device__ __forceinline__ void scan_row(const CellSet& S, int a, int len, int tid, int* wtot, F fn) {
-    const int boxB = S.boxB;
-    if (a >= S.boxA) {
-        for (int c0 = 0; c0 < len; c0 += G) {
-            const int b = c0 + tid;
-            if (b < len) fn(b, -1L);
-        }
-        return;
-    }
-    const long base = S.rowoff[a];
-    if (S.mask == nullptr) {
-        for (int c0 = 0; c0 < len; c0 += G) {
-            const int b = c0 + tid;
-            if (b < len) fn(b, b < boxB ? base + b : -1L);
-        }
-        return;
-    }
-    const uint8_t* m = S.mask + (long)a * boxB;
-    long run = base;
-    for (int c0 = 0; c0 < len; c0 += G) {
-        const int b = c0 + tid;
-        const bool in = b < boxB && b < len && m[b] != 0;
-        const unsigned long long bal = __ballot(in);
-        const int lane = lane_id();
-        const int r = __popcll(bal & ((1ULL << lane) - 1ULL));
-        long before = 0;
-        int tot;
-        if constexpr (G == 64) {
-            tot = __popcll(bal);
-        } else {
-            const int wv = tid >> 6;
-            if (lane == 0) wtot[wv] = __popcll(bal);
-            __syncthreads();
-            tot = 0;
-            for (int q = 0; q < G / 64; ++q) {
-                const int c = wtot[q];
-                if (q < wv) before += c;
-                tot += c;
+
+// Visits the cells b = tid + c*G (c < CH, b < len) of set row a, in blocks
+// of up to 8 cells per thread: first every compact index of the block (from
+// the row offset and the row's prefix counts, no serial scan) and every load
+// ld(idx) are issued, then st(b, idx, value) runs for each b < len (idx = -1
+// off the set).  Issuing the loads before any store lets them overlap.
+template <typename V, int G, int CH, typename LD, typename ST>
+__device__ __forceinline__ void row_visit(const CellSet& S, int a, int len, int tid, LD ld, ST st) {
+    constexpr int CB = CH < 8 ? CH : 8;
+    const bool inrow = a < S.boxA;
+    const int base = inrow ? S.rowoff[a] : 0;
+    const uint8_t* m = (inrow && S.mask) ? S.mask + (long)a * S.boxB : nullptr;
+    const int* pf = (inrow && S.mask) ? S.pref + (long)a * (S.boxB + 1) : nullptr;
+    const int lim = inrow ? (len < S.boxB ? len : S.boxB) : 0;
+    for (int c0 = 0; c0 < CH; c0 += CB) {
+        if (tid + c0 * G >= len) break;
+        int idx[CB];
+        V val[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int b = tid + (c0 + c) * G;
+            int v = -1;
+            if (c0 + c < CH && b < lim) {
+                if (!m) v = base + b;
+                else if (m[b]) v = base + pf[b];
             }
-            __syncthreads();
+            idx[c] = v;
         }
-        if (b < len) fn(b, in ? run + before + r : -1L);
-        run += tot;
+#pragma unroll
+        for (int c = 0; c < CB; ++c) val[c] = idx[c] >= 0 ? ld(idx[c]) : V(0);
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int b = tid + (c0 + c) * G;
+            if (c0 + c < CH && b < len) st(b, idx[c], val[c]);
+        }
     }
 }
 
@@ -116,6 +102,39 @@ __device__ __forceinline__ double sum_parts(const double* p, int n) {
     return wave_sum(s);
 }
 
+// Twiddle tables of a transform staged in LDS (one copy per workgroup,
+// shared by its slots), so the butterflies read them from LDS instead of
+// global memory.  Only for the smaller size classes; every thread of the
+// workgroup must call this.
+template <typename T, int NMAX, bool REAL>
+struct TwStage {
+    static constexpr bool kOn = NMAX <= 1024;
+    static constexpr int kSize = kOn ? (REAL ? 2 * NMAX + 1 : NMAX) : 1;
+};
+
+// Twiddle pointers of a plan, staged in LDS when the size class allows.
+template <typename T>
+struct Tw {
+    const cplx<T>* tw;
+    const cplx<T>* twr;
+};
+
+template <typename T, int NMAX, bool REAL>
+__device__ __forceinline__ Tw<T> stage_twiddles(const FftPlan& g, cplx<T>* twl) {
+    Tw<T> t{static_cast<const cplx<T>*>(g.tw), static_cast<const cplx<T>*>(g.twr)};
+    if constexpr (TwStage<T, NMAX, REAL>::kOn) {
+        const int n = g.n;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) twl[i] = t.tw[i];
+        if constexpr (REAL) {
+            for (int i = threadIdx.x; i <= n; i += blockDim.x) twl[NMAX + i] = t.twr[i];
+            t.twr = twl + NMAX;
+        }
+        t.tw = twl;
+        __syncthreads();
+    }
+    return t;
+}
+
 // ------------------------------------------------------------------------
 // row kernels
 // ------------------------------------------------------------------------
@@ -127,12 +146,14 @@ __global__ void __launch_bounds__(G * SLOTS)
 k_row_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
          const Item* __restrict__ items, int nitems, RowInArgs args) {
     __shared__ cplx<T> buf[SLOTS][NMAX + 1];
-    __shared__ int wtot[16];
+    __shared__ cplx<T> twl[TwStage<T, NMAX, true>::kSize];
     const int slot = threadIdx.x / G, tid = threadIdx.x % G;
     const int it = blockIdx.x * SLOTS + slot;
     const bool valid = it < nitems;
     const Item item = items[valid ? it : nitems - 1];
     const OpDesc& op = ops[item.inst];
+    const FftPlan& prow = op.prow;
+    const Tw<T> tw = stage_twiddles<T, NMAX, true>(prow, twl);
     const LzDesc& lz = lzs[item.inst];
     cplx<T>* s = buf[slot];
     T* sr = reinterpret_cast<T*>(s);
@@ -177,19 +198,17 @@ k_row_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const R
             sc = args.scale * (args.use_sigma ? rs.sigma[item.comp] : 1.0);
         }
         const bool wr = valid && qout != nullptr;
-        scan_row<G>(S, a, MB, tid, wtot, [&](int b, long idx) {
-            double v = 0.0;
-            if (idx >= 0) {
-                v = src[idx] * sc;
-                if (wr) qout[idx] = v;
-            }
-            sr[b] = to<T>(v);
-        });
+        row_visit<double, G, cdiv(2 * NMAX, G)>(
+            S, a, MB, tid, [&](int i) { return src[i] * sc; },
+            [&](int b, int i, double v) {
+                if (wr && i >= 0) qout[i] = v;
+                sr[b] = to<T>(v);
+            });
     }
     __syncthreads();
-    rfft_fwd<T, NMAX, G, P2>(s, op.prow, tid);
+    rfft_fwd<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
     if (!valid) return;
-    const int n1 = op.prow.n + 1;
+    const int n1 = prow.n + 1;
     cplx<T>* out;
     if (args.dest == DEST_T1) {
         out = static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.P;
@@ -236,21 +255,23 @@ __global__ void __launch_bounds__(G * SLOTS)
 k_row_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
           const Item* __restrict__ items, int nitems, RowMidArgs args) {
     __shared__ cplx<T> buf[SLOTS][NMAX + 1];
-    __shared__ int wtot[16];
+    __shared__ cplx<T> twl[TwStage<T, NMAX, true>::kSize];
     __shared__ double red[16];
     const int slot = threadIdx.x / G, tid = threadIdx.x % G;
     const int it = blockIdx.x * SLOTS + slot;
     const bool valid = it < nitems;
     const Item item = items[valid ? it : nitems - 1];
     const OpDesc& op = ops[item.inst];
+    const FftPlan& prow = op.prow;
+    const Tw<T> tw = stage_twiddles<T, NMAX, true>(prow, twl);
     cplx<T>* s = buf[slot];
     T* sr = reinterpret_cast<T*>(s);
     const int a = item.idx;
-    const int n1 = op.prow.n + 1;
+    const int n1 = prow.n + 1;
     const cplx<T>* in = static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P;
     for (int f = tid; f < n1; f += G) s[f] = in[f];
     __syncthreads();
-    rfft_inv<T, NMAX, G, P2>(s, op.prow, tid);
+    rfft_inv<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
     const CellSet& S = op.S[args.set];
     double* vout = nullptr;
     double sc = args.scale;
@@ -262,28 +283,32 @@ k_row_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     if (args.gk) {
         const GkLong<T> g = gk_long<T>(lzs[item.inst], S, args.j, args.jstart);
         double part = 0.0;
-        scan_row<G>(S, a, op.MB, tid, wtot, [&](int b, long idx) {
-            T v = T(0);
-            if (idx >= 0) {
-                v = sr[b] - g.gamma * g.lprev[idx];
-                if (valid) g.lcur[idx] = v;
-                part += static_cast<double>(v) * static_cast<double>(v);
-            }
-            sr[b] = v;
-        });
+        row_visit<T, G, cdiv(2 * NMAX, G)>(
+            S, a, op.MB, tid, [&](int i) { return g.lprev[i]; },
+            [&](int b, int i, T p) {
+                T v = T(0);
+                if (i >= 0) {
+                    v = sr[b] - g.gamma * p;
+                    if (valid) g.lcur[i] = v;
+                    part += static_cast<double>(v) * static_cast<double>(v);
+                }
+                sr[b] = v;
+            });
         part = slot_sum<G>(part, red);
         if (valid && tid == 0) g.lnp[a] = part;
     } else {
-        scan_row<G>(S, a, op.MB, tid, wtot, [&](int b, long idx) {
-            T v = sr[b];
-            if (idx < 0) v = T(0);
-            else if (vout) vout[idx] = sc * static_cast<double>(v);
-            sr[b] = v;
-        });
+        row_visit<T, G, cdiv(2 * NMAX, G)>(
+            S, a, op.MB, tid, [&](int) { return T(0); },
+            [&](int b, int i, T) {
+                T v = sr[b];
+                if (i < 0) v = T(0);
+                else if (vout) vout[i] = sc * static_cast<double>(v);
+                sr[b] = v;
+            });
     }
     if (!args.fwd) return;
     __syncthreads();
-    rfft_fwd<T, NMAX, G, P2>(s, op.prow, tid);
+    rfft_fwd<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
     if (!valid) return;
     cplx<T>* out = static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.P;
     for (int f = tid; f < n1; f += G) out[f] = s[f];
@@ -325,20 +350,22 @@ __global__ void __launch_bounds__(G * SLOTS)
 k_row_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
           const Item* __restrict__ items, int nitems, RowOutArgs args) {
     __shared__ cplx<T> buf[SLOTS][NMAX + 1];
-    __shared__ int wtot[16];
+    __shared__ cplx<T> twl[TwStage<T, NMAX, true>::kSize];
     const int slot = threadIdx.x / G, tid = threadIdx.x % G;
     const int it = blockIdx.x * SLOTS + slot;
     const bool valid = it < nitems;
     const Item item = items[valid ? it : nitems - 1];
     const OpDesc& op = ops[item.inst];
+    const FftPlan& prow = op.prow;
+    const Tw<T> tw = stage_twiddles<T, NMAX, true>(prow, twl);
     cplx<T>* s = buf[slot];
     T* sr = reinterpret_cast<T*>(s);
     const int a = item.idx;
-    const int n1 = op.prow.n + 1;
+    const int n1 = prow.n + 1;
     const cplx<T>* in = static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P;
     for (int f = tid; f < n1; f += G) s[f] = in[f];
     __syncthreads();
-    rfft_inv<T, NMAX, G, P2>(s, op.prow, tid);
+    rfft_inv<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
     if (args.mode == OUT_IMAGE) {
         if (!valid) return;
         const ResDesc& rs = res[item.inst];
@@ -354,18 +381,22 @@ k_row_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     if (args.mode == OUT_LZ) {
         const LzDesc& lz = lzs[item.inst];
         const GkShort g = gk_short(lz, op.S[1 - args.set], args.j, args.jstart, valid && a == 0 && tid == 0);
-        scan_row<G>(S, a, op.MB, tid, wtot, [&](int b, long idx) {
-            if (valid && idx >= 0) g.w[idx] = static_cast<double>(sr[b]) * g.inv_alpha - g.alpha * g.q[idx];
-        });
+        row_visit<double, G, cdiv(2 * NMAX, G)>(
+            S, a, op.MB, tid, [&](int i) { return g.q[i]; },
+            [&](int b, int i, double q) {
+                if (valid && i >= 0) g.w[i] = static_cast<double>(sr[b]) * g.inv_alpha - g.alpha * q;
+            });
         return;
     }
     const ResDesc& rs = res[item.inst];
     double* vout = (args.set == 0 ? rs.U : rs.V) + (long)item.comp * S.count;
     double sc = args.scale;
     if (args.div_sigma) sc /= rs.sigma[item.comp];
-    scan_row<G>(S, a, op.MB, tid, wtot, [&](int b, long idx) {
-        if (valid && idx >= 0) vout[idx] = sc * static_cast<double>(sr[b]);
-    });
+    row_visit<double, G, cdiv(2 * NMAX, G)>(
+        S, a, op.MB, tid, [&](int) { return 0.0; },
+        [&](int b, int i, double) {
+            if (valid && i >= 0) vout[i] = sc * static_cast<double>(sr[b]);
+        });
 }
 
 // ------------------------------------------------------------------------
@@ -381,22 +412,24 @@ __global__ void __launch_bounds__(G * SLOTS)
 k_rowfam_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
              const Item* __restrict__ items, int nitems, RowFamArgs args) {
     __shared__ cplx<T> buf[SLOTS][NMAX + 1];
-    __shared__ int wtot[16];
+    __shared__ cplx<T> twl[TwStage<T, NMAX, true>::kSize];
     __shared__ double red[16];
     const int slot = threadIdx.x / G, tid = threadIdx.x % G;
     const int it = blockIdx.x * SLOTS + slot;
     const bool valid = it < nitems;
     const Item item = items[valid ? it : nitems - 1];
     const OpDesc& op = ops[item.inst];
+    const FftPlan& prow = op.prow;
+    const Tw<T> tw = stage_twiddles<T, NMAX, true>(prow, twl);
     cplx<T>* s = buf[slot];
     T* sr = reinterpret_cast<T*>(s);
     const int a = item.idx;
-    const int n1 = op.prow.n + 1;
+    const int n1 = prow.n + 1;
     const cplx<T>* uh = static_cast<const cplx<T>*>(op.T1) + item.comp * op.tslot;
     const cplx<T>* xh = static_cast<const cplx<T>*>(op.Xh) + (long)a * op.P;
     for (int f = tid; f < n1; f += G) s[f] = cmulc(xh[f], uh[f]);
     __syncthreads();
-    rfft_inv<T, NMAX, G, P2>(s, op.prow, tid);
+    rfft_inv<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
     const CellSet& S = op.S[1];
     double* vout = nullptr;
     double sc = 1.0;
@@ -408,28 +441,32 @@ k_rowfam_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, con
     if (args.gk) {
         const GkLong<T> g = gk_long<T>(lzs[item.inst], S, args.j, args.jstart);
         double part = 0.0;
-        scan_row<G>(S, a, op.MB, tid, wtot, [&](int b, long idx) {
-            T v = T(0);
-            if (idx >= 0) {
-                v = sr[b] - g.gamma * g.lprev[idx];
-                if (valid) g.lcur[idx] = v;
-                part += static_cast<double>(v) * static_cast<double>(v);
-            }
-            sr[b] = v;
-        });
+        row_visit<T, G, cdiv(2 * NMAX, G)>(
+            S, a, op.MB, tid, [&](int i) { return g.lprev[i]; },
+            [&](int b, int i, T p) {
+                T v = T(0);
+                if (i >= 0) {
+                    v = sr[b] - g.gamma * p;
+                    if (valid) g.lcur[i] = v;
+                    part += static_cast<double>(v) * static_cast<double>(v);
+                }
+                sr[b] = v;
+            });
         part = slot_sum<G>(part, red);
         if (valid && tid == 0) g.lnp[a] = part;
     } else {
-        scan_row<G>(S, a, op.MB, tid, wtot, [&](int b, long idx) {
-            T v = sr[b];
-            if (idx < 0) v = T(0);
-            else if (vout) vout[idx] = sc * static_cast<double>(v);
-            sr[b] = v;
-        });
+        row_visit<T, G, cdiv(2 * NMAX, G)>(
+            S, a, op.MB, tid, [&](int) { return T(0); },
+            [&](int b, int i, T) {
+                T v = sr[b];
+                if (i < 0) v = T(0);
+                else if (vout) vout[i] = sc * static_cast<double>(v);
+                sr[b] = v;
+            });
     }
     if (!args.full) return;
     __syncthreads();
-    rfft_fwd<T, NMAX, G, P2>(s, op.prow, tid);
+    rfft_fwd<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
     if (!valid) return;
     cplx<T>* out = static_cast<cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P;
     for (int f = tid; f < n1; f += G) out[f] = cmulc(xh[f], s[f]);
@@ -442,15 +479,17 @@ __global__ void __launch_bounds__(G * SLOTS)
 k_rowfam_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs,
              const Item* __restrict__ items, int nitems, RowOutArgs args) {
     __shared__ cplx<T> buf[SLOTS][NMAX + 1];
-    __shared__ int wtot[16];
+    __shared__ cplx<T> twl[TwStage<T, NMAX, true>::kSize];
     const int slot = threadIdx.x / G, tid = threadIdx.x % G;
     const int it = blockIdx.x * SLOTS + slot;
     const bool valid = it < nitems;
     const Item item = items[valid ? it : nitems - 1];
     const OpDesc& op = ops[item.inst];
+    const FftPlan& prow = op.prow;
+    const Tw<T> tw = stage_twiddles<T, NMAX, true>(prow, twl);
     cplx<T>* s = buf[slot];
     T* sr = reinterpret_cast<T*>(s);
-    const int n1 = op.prow.n + 1;
+    const int n1 = prow.n + 1;
     const cplx<T>* pa = static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot;
     for (int f = tid; f < n1; f += G) {
         cplx<T> acc = {T(0), T(0)};
@@ -458,12 +497,14 @@ k_rowfam_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs,
         s[f] = acc;
     }
     __syncthreads();
-    rfft_inv<T, NMAX, G, P2>(s, op.prow, tid);
+    rfft_inv<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
     const LzDesc& lz = lzs[item.inst];
     const GkShort g = gk_short(lz, op.S[1], args.j, args.jstart, valid && tid == 0);
-    scan_row<G>(op.S[0], 0, op.MB, tid, wtot, [&](int b, long idx) {
-        if (valid && idx >= 0) g.w[idx] = static_cast<double>(sr[b]) * g.inv_alpha - g.alpha * g.q[idx];
-    });
+    row_visit<double, G, cdiv(2 * NMAX, G)>(
+        op.S[0], 0, op.MB, tid, [&](int i) { return g.q[i]; },
+        [&](int b, int i, double q) {
+            if (valid && i >= 0) g.w[i] = static_cast<double>(sr[b]) * g.inv_alpha - g.alpha * q;
+        });
 }
 
 // Row-family reconstruction of group `comp` on row a: for each i in the
@@ -473,18 +514,20 @@ __global__ void __launch_bounds__(G * SLOTS)
 k_rowfam_recon(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
                const Item* __restrict__ items, int nitems, double scale) {
     __shared__ cplx<T> buf[SLOTS][NMAX + 1];
-    __shared__ int wtot[16];
+    __shared__ cplx<T> twl[TwStage<T, NMAX, true>::kSize];
     constexpr int PER = cdiv(NMAX + 1, G);
     const int slot = threadIdx.x / G, tid = threadIdx.x % G;
     const int it = blockIdx.x * SLOTS + slot;
     const bool valid = it < nitems;
     const Item item = items[valid ? it : nitems - 1];
     const OpDesc& op = ops[item.inst];
+    const FftPlan& prow = op.prow;
+    const Tw<T> tw = stage_twiddles<T, NMAX, true>(prow, twl);
     const ResDesc& rs = res[item.inst];
     cplx<T>* s = buf[slot];
     T* sr = reinterpret_cast<T*>(s);
     const int a = item.idx;
-    const int n1 = op.prow.n + 1;
+    const int n1 = prow.n + 1;
     cplx<T> acc[PER];
 #pragma unroll
     for (int p = 0; p < PER; ++p) acc[p] = {T(0), T(0)};
@@ -494,11 +537,11 @@ k_rowfam_recon(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
         const int i = rs.gidx[g];
         const double* v = rs.V + (long)i * S.count;
         const double sg = rs.sigma[i];
-        scan_row<G>(S, a, op.MB, tid, wtot, [&](int b, long idx) {
-            sr[b] = idx >= 0 ? to<T>(sg * v[idx]) : T(0);
-        });
+        row_visit<double, G, cdiv(2 * NMAX, G)>(
+            S, a, op.MB, tid, [&](int k) { return v[k]; },
+            [&](int b, int k, double val) { sr[b] = k >= 0 ? to<T>(sg * val) : T(0); });
         __syncthreads();
-        rfft_fwd<T, NMAX, G, P2>(s, op.prow, tid);
+        rfft_fwd<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
         const cplx<T>* uh = static_cast<const cplx<T>*>(op.Us) + (long)i * op.uslot;
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
@@ -513,7 +556,7 @@ k_rowfam_recon(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
         if (f < n1) s[f] = acc[p];
     }
     __syncthreads();
-    rfft_inv<T, NMAX, G, P2>(s, op.prow, tid);
+    rfft_inv<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
     if (!valid) return;
     double* out = rs.recon + (long)item.comp * op.A * op.B + (long)a * op.B;
     const double* W = op.W + (long)a * op.B;
@@ -541,15 +584,18 @@ __global__ void k_copy_uspec(const OpDesc* __restrict__ ops, const Item* __restr
 
 // One workgroup transforms TC adjacent columns f0..f0+TC of a [rows][P]
 // array; each column is an independent length-MA transform on G threads.
-template <typename T, int NMAX, int G, int TC, bool P2>
-__global__ void __launch_bounds__(G * TC)
-k_col(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
-      const Item* __restrict__ items, int nitems, ColArgs args) {
+template <typename T, int NMAX, int G, int TC, bool P2, bool ACC>
+__device__ __forceinline__ void
+col_body(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
+         const Item* __restrict__ items, int nitems, ColArgs args) {
     constexpr int LD = NMAX + 1;
     constexpr int PER = cdiv(NMAX * TC, G * TC);
     __shared__ cplx<T> buf[TC * LD];
+    __shared__ cplx<T> twl[TwStage<T, NMAX, false>::kSize];
     const Item item = items[blockIdx.x];
     const OpDesc& op = ops[item.inst];
+    const FftPlan& pcol = op.pcol;
+    const Tw<T> tw = stage_twiddles<T, NMAX, false>(pcol, twl);
     const int f0 = item.idx * TC;
     const int MA = op.MA, P = op.P;
     const int nthr = G * TC;
@@ -567,7 +613,7 @@ k_col(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
         }
     };
 
-    if (args.mode == COL_ACCUM) {
+    if constexpr (ACC) {
         const ResDesc& rs = res[item.inst];
         const int g0 = rs.gptr[item.comp], g1 = rs.gptr[item.comp + 1];
         cplx<T> acc[PER];
@@ -577,7 +623,7 @@ k_col(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
             const int i = rs.gidx[g];
             load_rows(static_cast<const cplx<T>*>(op.T1) + i * op.tslot, args.nin);
             __syncthreads();
-            fft_lds<T, NMAX, G, -1, P2>(s, op.pcol, tid);
+            fft_lds<T, NMAX, G, -1, P2>(s, pcol, tw.tw, tid);
             const cplx<T>* uh = static_cast<const cplx<T>*>(op.Us) + (long)i * op.uslot;
 #pragma unroll
             for (int p = 0; p < PER; ++p) {
@@ -593,11 +639,11 @@ k_col(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
             if (a < MA) s[a] = acc[p];
         }
         __syncthreads();
-        fft_lds<T, NMAX, G, +1, P2>(s, op.pcol, tid);
+        fft_lds<T, NMAX, G, +1, P2>(s, pcol, tw.tw, tid);
     } else {
         load_rows(static_cast<const cplx<T>*>(op.T1) + item.comp * op.tslot, args.nin);
         __syncthreads();
-        fft_lds<T, NMAX, G, -1, P2>(s, op.pcol, tid);
+        fft_lds<T, NMAX, G, -1, P2>(s, pcol, tw.tw, tid);
         if (args.mode == COL_SPEC || args.mode == COL_STORE) {
             cplx<T>* dst = args.mode == COL_SPEC ? static_cast<cplx<T>*>(const_cast<void*>(op.Xh))
                                                  : static_cast<cplx<T>*>(op.Us) + (long)item.comp * op.uslot;
@@ -620,7 +666,7 @@ k_col(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
             if (f < P) buf[cc * LD + a] = cmulc(xh[(long)f * MA + a], buf[cc * LD + a]);
         }
         __syncthreads();
-        fft_lds<T, NMAX, G, +1, P2>(s, op.pcol, tid);
+        fft_lds<T, NMAX, G, +1, P2>(s, pcol, tw.tw, tid);
     }
     cplx<T>* out = static_cast<cplx<T>*>(op.T2) + item.comp * op.tslot;
     for (int e = threadIdx.x; e < args.nout * TC; e += nthr) {
@@ -628,6 +674,23 @@ k_col(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
         const int f = f0 + cc;
         if (f < P) out[(long)a * P + f] = buf[cc * LD + a];
     }
+}
+
+// Column pass without (k_col) and with (k_col_acc) the group accumulation of
+// the reconstruction; separate kernels keep the accumulator's registers out
+// of the product kernel.
+template <typename T, int NMAX, int G, int TC, bool P2>
+__global__ void __launch_bounds__(G * TC)
+k_col(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res, const Item* __restrict__ items, int nitems,
+      ColArgs args) {
+    col_body<T, NMAX, G, TC, P2, false>(ops, res, items, nitems, args);
+}
+
+template <typename T, int NMAX, int G, int TC, bool P2>
+__global__ void __launch_bounds__(G * TC)
+k_col_acc(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res, const Item* __restrict__ items,
+          int nitems, ColArgs args) {
+    col_body<T, NMAX, G, TC, P2, true>(ops, res, items, nitems, args);
 }
 
 // ------------------------------------------------------------------------
