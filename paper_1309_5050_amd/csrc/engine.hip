@@ -500,7 +500,6 @@ struct Batch {
     std::vector<ssa_decomp*> ds;      // instance i = ds[i]
     bool f64 = true, rowfam = false;
     int cls = 0, TC = 16;       // row size class (| 8: radix-2/4/8 plan), column tile
-    bool colp2 = false;         // column plan has radices 2, 4, 8 only
     DevVec dops, dlz, dres, druns;
     std::vector<OpDesc> hops;
     std::vector<LzDesc> hlz;
@@ -655,7 +654,7 @@ int tune_col_tile(Batch& b) {
     const auto key = std::make_pair((int)b.f64, d0->MA);
     if (const char* e = std::getenv("SHSSA_COL_TILE")) {
         const int tc = std::atoi(e);
-        if (col_tile_ok(b.f64, tc)) {
+        if (col_tile_ok(b.f64, d0->MA, tc)) {
             b.TC = tc;
             return SSA_OK;
         }
@@ -678,14 +677,15 @@ int tune_col_tile(Batch& b) {
     int rc = SSA_OK;
     for (int k = 0; k < nc && rc == SSA_OK; ++k) {
         const int tc = cands[k];
+        if (!col_tile_ok(b.f64, d0->MA, tc)) continue;
         ItemList cols;
         for (int i = 0; i < ni; ++i)
             for (int t = 0; t < (b.ds[i]->P + tc - 1) / tc; ++t) cols.h.push_back(Item{i, t, 0, 0});
         if ((rc = cols.upload(st))) break;
         ColArgs c{COL_SPEC, d0->A, 0, 1.0 / ((double)d0->MA * d0->MB), nullptr};
-        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.colp2, tc);   // warm-up
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.ds[0]->MA, tc);   // warm-up
         (void)hipEventRecord(e0, st);
-        for (int rep = 0; rep < 3; ++rep) launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.colp2, tc);
+        for (int rep = 0; rep < 3; ++rep) launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.ds[0]->MA, tc);
         (void)hipEventRecord(e1, st);
         if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SSA_EDEVICE, "tuning"); break; }
         float ms = 0.f;
@@ -789,7 +789,7 @@ int run_alloc_spectrum(Batch& b) {
             for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) cols.h.push_back(Item{i, t, 0, 0});
         if ((rc = cols.upload(st))) return rc;
         ColArgs c{COL_SPEC, d0->A, 0, 1.0 / ((double)d0->MA * d0->MB), nullptr};
-        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.colp2, b.TC);
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.ds[0]->MA, b.TC);
         HIPCHK(hipStreamSynchronize(st));
     }
     HIPCHK(hipStreamSynchronize(st));
@@ -866,7 +866,7 @@ void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode) {
         {
             ProfSpan p(b.ctx, "col", st, col_bytes(b, S.cols, nin, nmid));
             launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(),
-                       ColArgs{COL_CORR, nin, nmid, 1.0, nullptr}, b.colp2, b.TC);
+                       ColArgs{COL_CORR, nin, nmid, 1.0, nullptr}, b.ds[0]->MA, b.TC);
         }
         {
             ProfSpan p(b.ctx, "row_mid", st, row_bytes(b, S.rmid, 1, 1, 2 * vl));
@@ -876,7 +876,7 @@ void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode) {
         {
             ProfSpan p(b.ctx, "col", st, col_bytes(b, S.cols, nmid, nin));
             launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(),
-                       ColArgs{COL_CORR, nmid, nin, 1.0, nullptr}, b.colp2, b.TC);
+                       ColArgs{COL_CORR, nmid, nin, 1.0, nullptr}, b.ds[0]->MA, b.TC);
         }
         {
             ProfSpan p(b.ctx, "row_out", st, row_bytes(b, S.rout, 1, 0, 2 * vs));
@@ -1071,7 +1071,7 @@ int run_finish(Batch& b) {
         const int nin = d0->op.S[s].boxA, nmid = d0->op.S[1 - s].boxA;
         launch_row_in(b.f64, b.cls, rin.n(), st, b.ops(), b.lzs(), b.res(), rin.ptr(),
                       RowInArgs{IN_VEC, s, 0, DEST_T1, 1.0, 0, nullptr});
-        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_CORR, nin, nmid, 1.0, nullptr}, b.colp2, b.TC);
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_CORR, nin, nmid, 1.0, nullptr}, b.ds[0]->MA, b.TC);
         launch_row_mid(b.f64, b.cls, rmid.n(), st, b.ops(), b.lzs(), b.res(), rmid.ptr(),
                        RowMidArgs{1 - s, OUT_VEC, 1.0, 1, 0, 0, 0, 0});
     }
@@ -1136,10 +1136,10 @@ int run_reconstruct(Batch& b, const std::vector<int>& gptr, const std::vector<in
             return rc;
         launch_row_in(b.f64, b.cls, a1.n(), st, b.ops(), b.lzs(), b.res(), a1.ptr(),
                       RowInArgs{IN_VEC, 0, 0, DEST_T1, 1.0, 0, nullptr});
-        launch_col(b.f64, c1.n(), st, b.ops(), b.res(), c1.ptr(), ColArgs{COL_STORE, d0->LA, 0, 1.0, nullptr}, b.colp2, b.TC);
+        launch_col(b.f64, c1.n(), st, b.ops(), b.res(), c1.ptr(), ColArgs{COL_STORE, d0->LA, 0, 1.0, nullptr}, b.ds[0]->MA, b.TC);
         launch_row_in(b.f64, b.cls, a2.n(), st, b.ops(), b.lzs(), b.res(), a2.ptr(),
                       RowInArgs{IN_VEC, 1, 0, DEST_T1, 1.0, 1, nullptr});
-        launch_col(b.f64, c2.n(), st, b.ops(), b.res(), c2.ptr(), ColArgs{COL_ACCUM, d0->KA, d0->A, 1.0, nullptr}, b.colp2, b.TC);
+        launch_col(b.f64, c2.n(), st, b.ops(), b.res(), c2.ptr(), ColArgs{COL_ACCUM, d0->KA, d0->A, 1.0, nullptr}, b.ds[0]->MA, b.TC);
         launch_row_out(b.f64, b.cls, out.n(), st, b.ops(), b.lzs(), b.res(), out.ptr(),
                        RowOutArgs{OUT_IMAGE, 0, 1.0 / ((double)d0->MA * d0->MB), 0, 0, 0});
     }
@@ -1175,7 +1175,6 @@ int decompose_many(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** ou
         b.f64 = b.ds[0]->f64;
         b.rowfam = b.ds[0]->rowfam;
         b.cls = row_class(b.ds[0]->nh, b.f64) | (is_pow2(b.ds[0]->nh) ? 8 : 0);
-        b.colp2 = is_pow2(b.ds[0]->MA);
         b.TC = col_tile(b.f64);
         {
             auto it = ctx->col_tc.find(std::make_pair((int)b.f64, b.ds[0]->MA));
@@ -1497,7 +1496,6 @@ int ssa_reconstruct(ssa_decomp* d, const int* gp, const int* gi, int ng, double*
     b.f64 = d->f64;
     b.rowfam = d->rowfam;
     b.cls = row_class(d->nh, d->f64) | (is_pow2(d->nh) ? 8 : 0);
-    b.colp2 = is_pow2(d->MA);
     b.TC = col_tile(d->f64);
     {
         auto it = d->ctx->col_tc.find(std::make_pair((int)d->f64, d->MA));
@@ -1536,7 +1534,6 @@ int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* gp, const 
     b.f64 = d[0]->f64;
     b.rowfam = d[0]->rowfam;
     b.cls = row_class(d[0]->nh, d[0]->f64) | (is_pow2(d[0]->nh) ? 8 : 0);
-    b.colp2 = is_pow2(d[0]->MA);
     b.TC = col_tile(d[0]->f64);
     {
         auto it = d[0]->ctx->col_tc.find(std::make_pair((int)d[0]->f64, d[0]->MA));

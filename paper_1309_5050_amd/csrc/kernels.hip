@@ -19,6 +19,7 @@
 #include "common.hpp"
 #include "device.hpp"
 #include "fft.hpp"
+#include "regfft.hpp"
 
 namespace shssa {
 
@@ -673,6 +674,60 @@ col_body(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
         const int a = e / TC, cc = e % TC;
         const int f = f0 + cc;
         if (f < P) out[(long)a * P + f] = buf[cc * LD + a];
+    }
+}
+
+// Column pass for power-of-two column lengths MA = 2^LOGN (64..1024) with
+// the transforms held in registers.  A workgroup takes TC adjacent columns
+// f0..f0+TC of one instance with G = MA/8 threads per column; thread (c, t)
+// is threadIdx.x = c + TC*t, so the lanes of a wave read TC consecutive bins
+// of a row.  The spectrum is stored like T1 and T2: [MA rows][P bins].
+//   SPEC:  Xh = scale * FFT_col(T1 rows < nin)
+//   !SPEC: T2 rows < nout = IFFT_col(Xh * conj(FFT_col(T1 rows < nin)))
+template <typename T, int LOGN, int TC, bool SPEC>
+__global__ void __launch_bounds__(RegPlan<LOGN>::G * TC)
+k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs args) {
+    using RP = RegPlan<LOGN>;
+    constexpr int G = RP::G;
+    __shared__ cplx<T> lds[RP::LROWS * TC];
+    const Item item = items[blockIdx.x];
+    const OpDesc& op = ops[item.inst];
+    const int c = threadIdx.x % TC, t = threadIdx.x / TC;
+    const int P = op.P;
+    const int f = item.idx * TC + c;
+    const bool fok = f < P;
+    cplx<T> w[RP::NTW];
+    reg_twiddles<T, LOGN>(static_cast<const cplx<T>*>(op.pcol.tw), t, w);
+    const cplx<T>* src = static_cast<const cplx<T>*>(op.T1) + item.comp * op.tslot + f;
+    cplx<T>* xh = static_cast<cplx<T>*>(const_cast<void*>(op.Xh)) + f;
+    cplx<T> v[8], x[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int a = t + G * e;
+        v[e] = (fok && a < args.nin) ? src[(long)a * P] : cplx<T>{T(0), T(0)};
+    }
+    if constexpr (!SPEC) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = fok ? xh[(long)(t + G * e) * P] : cplx<T>{T(0), T(0)};
+    }
+    reg_fft<T, LOGN, TC, -1>(v, w, lds, t, c);
+    if constexpr (SPEC) {
+        if (!fok) return;
+        const T sc = to<T>(args.scale);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xh[(long)(t + G * e) * P] = {v[e].x * sc, v[e].y * sc};
+        return;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = cmulc(x[e], v[e]);
+        reg_fft<T, LOGN, TC, +1>(v, w, lds, t, c);
+        if (!fok) return;
+        cplx<T>* dst = static_cast<cplx<T>*>(op.T2) + item.comp * op.tslot + f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int a = t + G * e;
+            if (a < args.nout) dst[(long)a * P] = v[e];
+        }
     }
 }
 

@@ -7,7 +7,8 @@ namespace shssa {
 int row_class(int n, bool f64);
 int row_slots(int cls);
 int col_tile(bool f64);                 // default column tile
-bool col_tile_ok(bool f64, int tc);     // tile widths compiled for the precision
+bool col_tile_ok(bool f64, int MA, int tc);   // tile widths compiled for the precision and length
+int col_fast_logn(int MA);              // log2(MA) when the register column kernel applies, else 0
 
 void launch_row_in(bool f64, int cls, int nitems, hipStream_t st, const OpDesc* ops, const LzDesc* lzs,
                    const ResDesc* res, const Item* items, RowInArgs a);
@@ -24,7 +25,7 @@ void launch_rowfam_recon(bool f64, int cls, int nitems, hipStream_t st, const Op
 void launch_copy_uspec(bool f64, int nitems, hipStream_t st, const OpDesc* ops, const Item* items);
 // cls: row size class, plus 8 when the row plan has radices 2, 4, 8 only.
 void launch_col(bool f64, int nitems, hipStream_t st, const OpDesc* ops, const ResDesc* res, const Item* items,
-                ColArgs a, bool p2, int tc);
+                ColArgs a, int MA, int tc);
 void launch_shape_clean(int nitems, hipStream_t st, const OpDesc* ops, const Item* items, const double* const* x,
                         const uint8_t* const* m, uint8_t* const* nset, double* const* xc, int* const* npref);
 void launch_shape_origins(int nitems, hipStream_t st, const OpDesc* ops, const Item* items, const Runs* runs,

@@ -1,0 +1,116 @@
+// Register-resident radix-8 Stockham FFT for power-of-two lengths (device).
+//
+// A transform of length N = 2^LOGN (64 <= N <= 4096) is spread over
+// G = N/8 threads, each holding 8 elements in registers.  On entry and on
+// exit thread t holds positions t + G*e in slot e (natural order), so a
+// forward transform, a pointwise product and an inverse transform chain
+// without any data movement.  Every radix-8 pass works on one butterfly per
+// thread; a final radix-2 or radix-4 pass (N not a power of 8) works on 4 or
+// 2 butterflies per thread.  Between passes the outputs go through LDS once
+// (write, barrier, read in the next pass's order, barrier).
+//
+// Several transforms share a workgroup: transform c (0 <= c < TC) keeps its
+// exchange rows interleaved in LDS as [position][c], so lanes of consecutive
+// c touch consecutive words; one empty row per 8 positions keeps the
+// stride-8 writes of the first pass off a single bank group.
+//
+// Twiddles are taken once per thread (all passes) from the plan table
+// tw[i] = exp(-2 pi i i/N); the inverse uses their conjugates.
+#pragma once
+#include "fft.hpp"
+
+namespace shssa {
+
+template <int LOGN>
+struct RegPlan {
+    static_assert(LOGN >= 6 && LOGN <= 12, "register FFT lengths 64..4096");
+    static constexpr int N = 1 << LOGN;
+    static constexpr int G = N / 8;
+    static constexpr int P8 = LOGN / 3;                 // radix-8 passes
+    static constexpr int REM = LOGN % 3;                // 1: final radix-2 pass, 2: final radix-4 pass
+    static constexpr int R = REM == 1 ? 2 : (REM == 2 ? 4 : 8);
+    static constexpr int NTW = 7 * (P8 - 1) + (REM ? 8 - 8 / R : 0);   // twiddles per thread
+    static constexpr int LROWS = N + N / 8;             // padded exchange rows
+};
+
+template <int TC>
+__device__ __forceinline__ int rx_addr(int pos, int c) { return (pos + (pos >> 3)) * TC + c; }
+
+// The thread's twiddles of passes 2..: radix-8 pass p uses
+// w^(r k N/(8 Ns)), k = t mod Ns, Ns = 8^p; the final radix-R pass uses
+// w^(r j), j = t + q G for its butterflies q.
+template <typename T, int LOGN>
+__device__ __forceinline__ void reg_twiddles(const cplx<T>* __restrict__ tw, int t,
+                                             cplx<T> (&w)[RegPlan<LOGN>::NTW]) {
+    using RP = RegPlan<LOGN>;
+    int q = 0;
+#pragma unroll
+    for (int p = 1; p < RP::P8; ++p) {
+        const int Ns = 1 << (3 * p);
+        const int k = t & (Ns - 1);
+        const int step = k * (RP::N / (8 * Ns));
+#pragma unroll
+        for (int r = 1; r < 8; ++r) w[q++] = tw[r * step];
+    }
+    if constexpr (RP::REM != 0) {
+        constexpr int B = 8 / RP::R;
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int r = 1; r < RP::R; ++r) w[q++] = tw[r * (t + b * RP::G)];
+    }
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ cplx<T> twiddle(cplx<T> a, cplx<T> w) {
+    return DIR < 0 ? cmul(a, w) : cmulc(a, w);
+}
+
+// In-place transform of the 8 register values of thread t (transform c of
+// the workgroup).  DIR = -1 forward, +1 inverse (unnormalised).  The LDS
+// buffer holds RegPlan<LOGN>::LROWS * TC values; the caller must not touch
+// it concurrently.  Ends with the workgroup synchronised if any exchange
+// took place.
+template <typename T, int LOGN, int TC, int DIR>
+__device__ __forceinline__ void reg_fft(cplx<T> (&v)[8], const cplx<T> (&w)[RegPlan<LOGN>::NTW],
+                                        cplx<T>* lds, int t, int c) {
+    using RP = RegPlan<LOGN>;
+    constexpr int G = RP::G;
+    constexpr int NPASS = RP::P8 + (RP::REM ? 1 : 0);
+#pragma unroll
+    for (int p = 0; p < RP::P8; ++p) {
+        const int Ns = 1 << (3 * p);
+        if (p > 0) {
+#pragma unroll
+            for (int r = 1; r < 8; ++r) v[r] = twiddle<T, DIR>(v[r], w[7 * (p - 1) + r - 1]);
+        }
+        bf8<T, DIR>(v);
+        if (p == NPASS - 1) return;
+        const int k = t & (Ns - 1);
+        const int base = (t - k) * 8 + k;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) lds[rx_addr<TC>(base + r * Ns, c)] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = lds[rx_addr<TC>(t + G * e, c)];
+        __syncthreads();
+    }
+    if constexpr (RP::REM != 0) {
+        constexpr int R = RP::R, B = 8 / R;
+        constexpr int w0 = 7 * (RP::P8 - 1);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            cplx<T> a[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) a[r] = v[b + B * r];
+#pragma unroll
+            for (int r = 1; r < R; ++r) a[r] = twiddle<T, DIR>(a[r], w[w0 + b * (R - 1) + r - 1]);
+            if constexpr (R == 2) bf2<T, DIR>(a);
+            else bf4<T, DIR>(a);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b + B * r] = a[r];
+        }
+    }
+}
+
+}  // namespace shssa
