@@ -46,6 +46,18 @@ double ms_since(Clock::time_point t) {
     return std::chrono::duration<double, std::milli>(Clock::now() - t).count();
 }
 
+// Row kernel selector: size class (bits 0..2), power-of-two plan (bit 3)
+// and, for powers of two, log2 of the half-length (bits 4..7).
+int row_word(int nh, bool f64) {
+    int w = row_class(nh, f64);
+    if (nh > 0 && (nh & (nh - 1)) == 0) {
+        int lg = 0;
+        while ((1 << lg) < nh) ++lg;
+        w |= 8 | (lg << 4);
+    }
+    return w;
+}
+
 int next_smooth(int n) {
     for (int m = std::max(n, 1);; ++m) {
         int t = m;
@@ -1174,7 +1186,7 @@ int decompose_many(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** ou
         for (int i : kv.second) b.ds.push_back(ds[i].get());
         b.f64 = b.ds[0]->f64;
         b.rowfam = b.ds[0]->rowfam;
-        b.cls = row_class(b.ds[0]->nh, b.f64) | (is_pow2(b.ds[0]->nh) ? 8 : 0);
+        b.cls = row_word(b.ds[0]->nh, b.f64);
         b.TC = col_tile(b.f64);
         {
             auto it = ctx->col_tc.find(std::make_pair((int)b.f64, b.ds[0]->MA));
@@ -1495,7 +1507,7 @@ int ssa_reconstruct(ssa_decomp* d, const int* gp, const int* gi, int ng, double*
     b.ds = {d};
     b.f64 = d->f64;
     b.rowfam = d->rowfam;
-    b.cls = row_class(d->nh, d->f64) | (is_pow2(d->nh) ? 8 : 0);
+    b.cls = row_word(d->nh, d->f64);
     b.TC = col_tile(d->f64);
     {
         auto it = d->ctx->col_tc.find(std::make_pair((int)d->f64, d->MA));
@@ -1533,7 +1545,7 @@ int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* gp, const 
     b.ds.assign(d, d + n);
     b.f64 = d[0]->f64;
     b.rowfam = d[0]->rowfam;
-    b.cls = row_class(d[0]->nh, d[0]->f64) | (is_pow2(d[0]->nh) ? 8 : 0);
+    b.cls = row_word(d[0]->nh, d[0]->f64);
     b.TC = col_tile(d[0]->f64);
     {
         auto it = d[0]->ctx->col_tc.find(std::make_pair((int)d[0]->f64, d[0]->MA));

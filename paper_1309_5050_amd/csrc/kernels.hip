@@ -142,6 +142,49 @@ __device__ __forceinline__ Tw<T> stage_twiddles(const FftPlan& g, cplx<T>* twl) 
 
 
 
+// Source of a row-input pass: the compact vector read (src), its scale and
+// the basis column that receives the scaled vector (qout, or nullptr).
+struct RowInSrc {
+    const double* src;
+    double sc;
+    double* qout;
+};
+
+__device__ __forceinline__ RowInSrc row_in_source(const OpDesc& op, const LzDesc& lz, const ResDesc* res,
+                                                  const Item& item, const RowInArgs& args, bool leader) {
+    RowInSrc r{nullptr, 1.0, nullptr};
+    if (args.mode == IN_LZ_NORM || args.mode == IN_LZ_PLAIN || args.mode == IN_LZ_SIN) {
+        const bool fresh = args.mode == IN_LZ_SIN && lz.flag[3] != 0;
+        if (args.mode == IN_LZ_NORM || fresh) {
+            // q_j = w / beta_{j-1}.  A beta at rounding level (the short
+            // Krylov space is exhausted) freezes the recurrence for the rest
+            // of the cycle: q_j = 0 and B[j][j-1] = 0.  After a fresh random
+            // restart w is a random vector orthogonal to the basis and has
+            // no coupling to the previous column.
+            const double beta = sqrt(sum_parts(lz.np, lz.nblk));
+            const double scale = lz.beta[2 + ((args.j - 1) & 1)];
+            const bool bd = !fresh && (lz.flag[2] != 0 || (args.j > 0 && beta <= lz.eps * scale));
+            r.sc = (!bd && beta > 1e-300) ? 1.0 / beta : 0.0;
+            r.src = lz.w;
+            r.qout = lz.Q + (long)args.j * lz.n;
+            if (leader) {
+                if (args.j > 0 && !fresh) lz.Bm[(long)(args.j - 1) * kMaxBasis + args.j] = bd ? 0.0 : beta;
+                if (bd) lz.flag[2] = 1;
+            }
+        } else if (args.mode == IN_LZ_SIN) {
+            r.src = lz.sin;
+        } else {
+            r.src = lz.Q + (long)args.j * lz.n;
+        }
+    } else {
+        const ResDesc& rs = res[item.inst];
+        const long ld = args.set == 0 ? op.S[0].count : op.S[1].count;
+        r.src = (args.set == 0 ? rs.U : rs.V) + (long)item.comp * ld;
+        r.sc = args.scale * (args.use_sigma ? rs.sigma[item.comp] : 1.0);
+    }
+    return r;
+}
+
 template <typename T, int NMAX, int G, int SLOTS, bool P2>
 __global__ void __launch_bounds__(G * SLOTS)
 k_row_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
@@ -166,38 +209,10 @@ k_row_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const R
         for (int b = tid; b < MB; b += G) sr[b] = b < op.B ? to<T>(row[b]) : T(0);
     } else {
         const CellSet& S = op.S[args.set];
-        const double* src;
-        double sc = 1.0;
-        double* qout = nullptr;
-        if (args.mode == IN_LZ_NORM || args.mode == IN_LZ_PLAIN || args.mode == IN_LZ_SIN) {
-            const bool fresh = args.mode == IN_LZ_SIN && lz.flag[3] != 0;
-            if (args.mode == IN_LZ_NORM || fresh) {
-                // q_j = w / beta_{j-1}.  A beta at rounding level (the short
-                // Krylov space is exhausted) freezes the recurrence for the rest
-                // of the cycle: q_j = 0 and B[j][j-1] = 0.  After a fresh random
-                // restart w is a random vector orthogonal to the basis and has
-                // no coupling to the previous column.
-                const double beta = sqrt(sum_parts(lz.np, lz.nblk));
-                const double scale = lz.beta[2 + ((args.j - 1) & 1)];
-                const bool bd = !fresh && (lz.flag[2] != 0 || (args.j > 0 && beta <= lz.eps * scale));
-                sc = (!bd && beta > 1e-300) ? 1.0 / beta : 0.0;
-                src = lz.w;
-                qout = lz.Q + (long)args.j * lz.n;
-                if (valid && a == 0 && tid == 0) {
-                    if (args.j > 0 && !fresh) lz.Bm[(long)(args.j - 1) * kMaxBasis + args.j] = bd ? 0.0 : beta;
-                    if (bd) lz.flag[2] = 1;
-                }
-            } else if (args.mode == IN_LZ_SIN) {
-                src = lz.sin;
-            } else {
-                src = lz.Q + (long)args.j * lz.n;
-            }
-        } else {
-            const ResDesc& rs = res[item.inst];
-            const long ld = args.set == 0 ? op.S[0].count : op.S[1].count;
-            src = (args.set == 0 ? rs.U : rs.V) + (long)item.comp * ld;
-            sc = args.scale * (args.use_sigma ? rs.sigma[item.comp] : 1.0);
-        }
+        const RowInSrc rsrc = row_in_source(op, lz, res, item, args, valid && a == 0 && tid == 0);
+        const double* src = rsrc.src;
+        const double sc = rsrc.sc;
+        double* qout = rsrc.qout;
         const bool wr = valid && qout != nullptr;
         row_visit<double, G, cdiv(2 * NMAX, G)>(
             S, a, MB, tid, [&](int i) { return src[i] * sc; },
@@ -398,6 +413,259 @@ k_row_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
         [&](int b, int i, double) {
             if (valid && i >= 0) vout[i] = sc * static_cast<double>(sr[b]);
         });
+}
+
+// ------------------------------------------------------------------------
+// register row kernels: half-lengths n = 2^LOGN, 64 <= n <= 512
+// ------------------------------------------------------------------------
+// A workgroup of 256 threads takes RPW = 256/G rows, G = n/8 consecutive
+// lanes per row.  Thread t of a row holds the complex pairs
+// z_p = (x_{2p}, x_{2p+1}) at positions p = t + G*e (e = 0..7) and, on the
+// spectral side, the bins k = t + G*e (thread 0 also the bin n).
+
+template <int LOGN>
+struct RowReg {
+    static constexpr int N = 1 << LOGN;
+    static constexpr int G = N / 8;
+    static constexpr int RPW = 256 / G;
+    static_assert(LOGN >= 6 && LOGN <= 9, "register row kernels: n = 64..512");
+};
+
+// Sum over the G consecutive lanes of a row (G divides 64).  All lanes of
+// the row get the same value.
+template <int G>
+__device__ __forceinline__ double lane_group_sum(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Z_k = E'_k + i O'_k for the thread's bins: E'_k = X_k + conj X_{n-k},
+// O'_k = (X_k - conj X_{n-k}) conj(W^k), W = exp(-2 pi i/2n); the inverse
+// complex transform of Z gives 2n x as pairs.
+template <typename T, int LOGN>
+__device__ __forceinline__ void row_unsplit(const cplx<T>* __restrict__ in, const cplx<T> (&wr)[8], int t,
+                                            cplx<T> (&v)[8]) {
+    constexpr int N = RowReg<LOGN>::N, G = RowReg<LOGN>::G;
+    cplx<T> X[8], Y[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = t + G * e;
+        X[e] = in[k];
+        Y[e] = in[N - k];
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const cplx<T> ep = {X[e].x + Y[e].x, X[e].y - Y[e].y};
+        const cplx<T> d = {X[e].x - Y[e].x, X[e].y + Y[e].y};
+        const cplx<T> o = cmulc(d, wr[e]);
+        v[e] = {ep.x - o.y, ep.y + o.x};
+    }
+}
+
+// From Z = FFT(z) (natural positions in v) to the bins of the real
+// transform: X_k = E_k + W^k O_k with E_k = (Z_k + conj Z_{n-k})/2,
+// O_k = (Z_k - conj Z_{n-k})/(2i); X_n = E_0 - O_0.  Z_{n-k} comes from the
+// partner thread through LDS.  Writes out[k] for the thread's bins.
+template <typename T, int LOGN, typename AD>
+__device__ __forceinline__ void row_split_store(const cplx<T> (&v)[8], const cplx<T> (&wr)[8], cplx<T>* lds, AD ad,
+                                                int t, cplx<T>* __restrict__ out, bool write) {
+    constexpr int N = RowReg<LOGN>::N, G = RowReg<LOGN>::G;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) lds[ad(t + G * e)] = v[e];
+    __syncthreads();
+    cplx<T> zn[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) zn[e] = lds[ad((N - (t + G * e)) & (N - 1))];
+    if (!write) return;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const cplx<T> zk = v[e];
+        const cplx<T> E = {T(0.5) * (zk.x + zn[e].x), T(0.5) * (zk.y - zn[e].y)};
+        const cplx<T> O = {T(0.5) * (zk.y + zn[e].y), T(-0.5) * (zk.x - zn[e].x)};
+        const cplx<T> wo = cmul(wr[e], O);
+        out[t + G * e] = cadd(E, wo);
+        if (e == 0 && t == 0) out[N] = csub(E, O);
+    }
+}
+
+// Compact indices of the cells 2p and 2p+1, p = t + G*e, of set row a
+// (-1 off the set or outside the set's box).
+template <int G>
+__device__ __forceinline__ void pair_idx(const CellSet& S, int a, int t, int (&idx)[16]) {
+    const bool inrow = a < S.boxA;
+    const int base = inrow ? S.rowoff[a] : 0;
+    const uint8_t* m = (inrow && S.mask) ? S.mask + (long)a * S.boxB : nullptr;
+    const int* pf = (inrow && S.mask) ? S.pref + (long)a * (S.boxB + 1) : nullptr;
+    const int lim = inrow ? S.boxB : 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int b = 2 * (t + G * (q >> 1)) + (q & 1);
+        int v = -1;
+        if (b < lim) {
+            if (!m) v = base + b;
+            else if (m[b]) v = base + pf[b];
+        }
+        idx[q] = v;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T& pair_part(cplx<T>& z, int h) { return h ? z.y : z.x; }
+
+template <typename T, int LOGN>
+__device__ __forceinline__ void row_reg_setup(const FftPlan& prow, int t, cplx<T> (&w)[RegPlan<LOGN>::NTW],
+                                              cplx<T> (&wr)[8]) {
+    reg_twiddles<T, LOGN>(static_cast<const cplx<T>*>(prow.tw), t, w);
+    const cplx<T>* twr = static_cast<const cplx<T>*>(prow.twr);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) wr[e] = twr[t + RowReg<LOGN>::G * e];
+}
+
+// Row input (all modes but IN_DENSE): gather the compact vector on set row
+// a into the pairs, R2C into T1 row a.
+template <typename T, int LOGN>
+__global__ void __launch_bounds__(256)
+k_rowr_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
+          const Item* __restrict__ items, int nitems, RowInArgs args) {
+    using RR = RowReg<LOGN>;
+    constexpr int G = RR::G;
+    __shared__ cplx<T> lds[RR::RPW * RegPlan<LOGN>::LROWS];
+    const int c = threadIdx.x / G, t = threadIdx.x % G;
+    const int it = blockIdx.x * RR::RPW + c;
+    const bool valid = it < nitems;
+    const Item item = items[valid ? it : nitems - 1];
+    const OpDesc& op = ops[item.inst];
+    const auto ad = [&](int pos) { return rx_addr_row<LOGN>(pos, c); };
+    cplx<T> w[RegPlan<LOGN>::NTW], wr[8], v[8];
+    row_reg_setup<T, LOGN>(op.prow, t, w, wr);
+    const int a = item.idx;
+    const CellSet& S = op.S[args.set];
+    const RowInSrc rs = row_in_source(op, lzs[item.inst], res, item, args, valid && a == 0 && t == 0);
+    int idx[16];
+    pair_idx<G>(S, a, t, idx);
+    double val[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) val[q] = idx[q] >= 0 ? rs.src[idx[q]] * rs.sc : 0.0;
+    const bool wq = valid && rs.qout != nullptr;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        if (wq && idx[q] >= 0) rs.qout[idx[q]] = val[q];
+        pair_part(v[q >> 1], q & 1) = to<T>(val[q]);
+    }
+    reg_fft<T, LOGN, -1>(v, w, lds, t, ad);
+    cplx<T>* out = args.dest == DEST_T1
+                       ? static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.P
+                       : static_cast<cplx<T>*>(const_cast<void*>(op.Xh)) + (long)a * op.P;
+    row_split_store<T, LOGN>(v, wr, lds, ad, t, out, valid);
+}
+
+// C2R of T2 row a, mask to a set row (with the long-vector update or the
+// emission of a result vector), optional R2C into T1 row a.
+template <typename T, int LOGN>
+__global__ void __launch_bounds__(256)
+k_rowr_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
+           const Item* __restrict__ items, int nitems, RowMidArgs args) {
+    using RR = RowReg<LOGN>;
+    constexpr int G = RR::G;
+    __shared__ cplx<T> lds[RR::RPW * RegPlan<LOGN>::LROWS];
+    const int c = threadIdx.x / G, t = threadIdx.x % G;
+    const int it = blockIdx.x * RR::RPW + c;
+    const bool valid = it < nitems;
+    const Item item = items[valid ? it : nitems - 1];
+    const OpDesc& op = ops[item.inst];
+    const auto ad = [&](int pos) { return rx_addr_row<LOGN>(pos, c); };
+    cplx<T> w[RegPlan<LOGN>::NTW], wr[8], v[8];
+    row_reg_setup<T, LOGN>(op.prow, t, w, wr);
+    const int a = item.idx;
+    row_unsplit<T, LOGN>(static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P, wr, t, v);
+    reg_fft<T, LOGN, +1>(v, w, lds, t, ad);
+    const CellSet& S = op.S[args.set];
+    int idx[16];
+    pair_idx<G>(S, a, t, idx);
+    if (args.gk) {
+        const GkLong<T> g = gk_long<T>(lzs[item.inst], S, args.j, args.jstart);
+        T pv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) pv[q] = idx[q] >= 0 ? g.lprev[idx[q]] : T(0);
+        double part = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            T& z = pair_part(v[q >> 1], q & 1);
+            T nv = T(0);
+            if (idx[q] >= 0) {
+                nv = z - g.gamma * pv[q];
+                if (valid) g.lcur[idx[q]] = nv;
+                part += static_cast<double>(nv) * static_cast<double>(nv);
+            }
+            z = nv;
+        }
+        part = lane_group_sum<G>(part);
+        if (valid && t == 0) g.lnp[a] = part;
+    } else {
+        double* vout = nullptr;
+        double sc = args.scale;
+        if (args.emit == OUT_VEC && valid) {
+            const ResDesc& rs = res[item.inst];
+            vout = (args.set == 0 ? rs.U : rs.V) + (long)item.comp * S.count;
+            if (args.div_sigma) sc = rs.sigma[item.comp] > 0 ? sc / rs.sigma[item.comp] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            T& z = pair_part(v[q >> 1], q & 1);
+            if (idx[q] < 0) z = T(0);
+            else if (vout) vout[idx[q]] = sc * static_cast<double>(z);
+        }
+    }
+    if (!args.fwd) return;
+    reg_fft<T, LOGN, -1>(v, w, lds, t, ad);
+    row_split_store<T, LOGN>(v, wr, lds, ad, t,
+                             static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.P, valid);
+}
+
+// C2R of T2 row a gathered on a set row: the short-vector update (OUT_LZ)
+// or a result vector (OUT_VEC).
+template <typename T, int LOGN>
+__global__ void __launch_bounds__(256)
+k_rowr_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res,
+           const Item* __restrict__ items, int nitems, RowOutArgs args) {
+    using RR = RowReg<LOGN>;
+    constexpr int G = RR::G;
+    __shared__ cplx<T> lds[RR::RPW * RegPlan<LOGN>::LROWS];
+    const int c = threadIdx.x / G, t = threadIdx.x % G;
+    const int it = blockIdx.x * RR::RPW + c;
+    const bool valid = it < nitems;
+    const Item item = items[valid ? it : nitems - 1];
+    const OpDesc& op = ops[item.inst];
+    const auto ad = [&](int pos) { return rx_addr_row<LOGN>(pos, c); };
+    cplx<T> w[RegPlan<LOGN>::NTW], wr[8], v[8];
+    row_reg_setup<T, LOGN>(op.prow, t, w, wr);
+    const int a = item.idx;
+    row_unsplit<T, LOGN>(static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P, wr, t, v);
+    reg_fft<T, LOGN, +1>(v, w, lds, t, ad);
+    const CellSet& S = op.S[args.set];
+    int idx[16];
+    pair_idx<G>(S, a, t, idx);
+    if (args.mode == OUT_LZ) {
+        const GkShort g = gk_short(lzs[item.inst], op.S[1 - args.set], args.j, args.jstart, valid && a == 0 && t == 0);
+        double qv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) qv[q] = idx[q] >= 0 ? g.q[idx[q]] : 0.0;
+        if (!valid) return;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (idx[q] >= 0)
+                g.w[idx[q]] = static_cast<double>(pair_part(v[q >> 1], q & 1)) * g.inv_alpha - g.alpha * qv[q];
+        return;
+    }
+    if (!valid) return;
+    const ResDesc& rs = res[item.inst];
+    double* vout = (args.set == 0 ? rs.U : rs.V) + (long)item.comp * S.count;
+    double sc = args.scale;
+    if (args.div_sigma) sc /= rs.sigma[item.comp];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        if (idx[q] >= 0) vout[idx[q]] = sc * static_cast<double>(pair_part(v[q >> 1], q & 1));
 }
 
 // ------------------------------------------------------------------------
@@ -710,7 +978,7 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = fok ? xh[(long)(t + G * e) * P] : cplx<T>{T(0), T(0)};
     }
-    reg_fft<T, LOGN, TC, -1>(v, w, lds, t, c);
+    reg_fft<T, LOGN, -1>(v, w, lds, t, [&](int pos) { return rx_addr<TC>(pos, c); });
     if constexpr (SPEC) {
         if (!fok) return;
         const T sc = to<T>(args.scale);
@@ -720,7 +988,7 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
     } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) v[e] = cmulc(x[e], v[e]);
-        reg_fft<T, LOGN, TC, +1>(v, w, lds, t, c);
+        reg_fft<T, LOGN, +1>(v, w, lds, t, [&](int pos) { return rx_addr<TC>(pos, c); });
         if (!fok) return;
         cplx<T>* dst = static_cast<cplx<T>*>(op.T2) + item.comp * op.tslot + f;
 #pragma unroll

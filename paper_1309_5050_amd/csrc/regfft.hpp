@@ -33,8 +33,12 @@ struct RegPlan {
     static constexpr int LROWS = N + N / 8;             // padded exchange rows
 };
 
+// LDS slot of position pos of transform c when TC transforms interleave
+// ([position][c]) or lie one after the other ([c][position]).
 template <int TC>
 __device__ __forceinline__ int rx_addr(int pos, int c) { return (pos + (pos >> 3)) * TC + c; }
+template <int LOGN>
+__device__ __forceinline__ int rx_addr_row(int pos, int c) { return c * RegPlan<LOGN>::LROWS + pos + (pos >> 3); }
 
 // The thread's twiddles of passes 2..: radix-8 pass p uses
 // w^(r k N/(8 Ns)), k = t mod Ns, Ns = 8^p; the final radix-R pass uses
@@ -66,14 +70,15 @@ __device__ __forceinline__ cplx<T> twiddle(cplx<T> a, cplx<T> w) {
     return DIR < 0 ? cmul(a, w) : cmulc(a, w);
 }
 
-// In-place transform of the 8 register values of thread t (transform c of
-// the workgroup).  DIR = -1 forward, +1 inverse (unnormalised).  The LDS
-// buffer holds RegPlan<LOGN>::LROWS * TC values; the caller must not touch
-// it concurrently.  Ends with the workgroup synchronised if any exchange
-// took place.
-template <typename T, int LOGN, int TC, int DIR>
+// In-place transform of the 8 register values of thread t.  DIR = -1
+// forward, +1 inverse (unnormalised).  ad(pos) maps a position of this
+// thread's transform to its LDS slot (transforms of a workgroup use
+// disjoint slots); the caller must not touch those slots concurrently.
+// Every thread of the workgroup must call it (it contains barriers); it
+// ends with the workgroup synchronised.
+template <typename T, int LOGN, int DIR, typename AD>
 __device__ __forceinline__ void reg_fft(cplx<T> (&v)[8], const cplx<T> (&w)[RegPlan<LOGN>::NTW],
-                                        cplx<T>* lds, int t, int c) {
+                                        cplx<T>* lds, int t, AD ad) {
     using RP = RegPlan<LOGN>;
     constexpr int G = RP::G;
     constexpr int NPASS = RP::P8 + (RP::REM ? 1 : 0);
@@ -89,10 +94,10 @@ __device__ __forceinline__ void reg_fft(cplx<T> (&v)[8], const cplx<T> (&w)[RegP
         const int k = t & (Ns - 1);
         const int base = (t - k) * 8 + k;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) lds[rx_addr<TC>(base + r * Ns, c)] = v[r];
+        for (int r = 0; r < 8; ++r) lds[ad(base + r * Ns)] = v[r];
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = lds[rx_addr<TC>(t + G * e, c)];
+        for (int e = 0; e < 8; ++e) v[e] = lds[ad(t + G * e)];
         __syncthreads();
     }
     if constexpr (RP::REM != 0) {
