@@ -86,6 +86,7 @@ def main():
     t0 = time.perf_counter()
     last = None
     for _ in range(args.steps):
+        last = None          # a step's results are released before the next step
         last = step(args.precision)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -148,6 +149,8 @@ def main():
                         "effective_GBs": bmv * products / (dt / args.steps) / 1e9},
         "lanczos": {"steps": stats["steps"], "restarts": stats["restarts"], "basis": stats["basis"],
                     "max_resid_over_sigma1": stats["max_resid"]},
+        "host_ms_per_batch": {"setup": B * stats["ms_setup"], "lanczos": B * stats["ms_lanczos"],
+                              "finish": B * stats["ms_finish"]},
         "fp64_single_instance": single,
         "speedup_vs_fp64_single": (value / single["decomps_per_s"]) if single else None,
         "cpu_baseline": cpu,

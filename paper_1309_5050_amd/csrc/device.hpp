@@ -47,6 +47,7 @@ struct LzDesc {
     double* hp1;        // partial projections, nblk x (kMaxBasis+1)
     double* hp2;
     double* np;         // partial squared norms of w, nblk
+    double* np0;        // partial squared norms of w before its first projection, nblk
     void* lbuf[2];      // long vectors (operator precision), ping-pong by step parity
     double* lnp[2];     // partial squared norms of the long vectors, per long-set row
     double* Bm;         // projected matrix, kMaxBasis x kMaxBasis column-major (rows: short)

@@ -164,6 +164,80 @@ struct ssa_ctx {
         pooled += cls;
     }
 
+    // Pinned host staging for uploads.  Two halves are filled in turn; a half
+    // is refilled only after the copies issued from it have completed (an
+    // event recorded when it was left), so hipMemcpyAsync from it never
+    // blocks the host and never reads overwritten data.  Caller holds mu.
+    static constexpr size_t kStageHalf = 8u << 20;
+    char* stg = nullptr;
+    size_t stg_head = 0;
+    int stg_cur = 0;
+    hipEvent_t stg_ev[2] = {nullptr, nullptr};
+    bool stg_pending[2] = {false, false};
+    hipStream_t stg_st = nullptr;
+
+    int upload_locked(void* dst, const void* src, size_t n, hipStream_t s) {
+        if (n == 0) return SSA_OK;
+        const size_t need = (n + 255) & ~(size_t)255;
+        if (need > kStageHalf) {
+            // too large to stage: a plain (host-synchronous) copy
+            HIPCHK(hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+            return SSA_OK;
+        }
+        if (!stg) {
+            HIPCHK(hipHostMalloc((void**)&stg, 2 * kStageHalf, hipHostMallocDefault));
+            HIPCHK(hipEventCreateWithFlags(&stg_ev[0], hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&stg_ev[1], hipEventDisableTiming));
+        }
+        if (stg_st && stg_st != s) {
+            // copies of the other stream must be done before its slots are reused
+            HIPCHK(hipStreamSynchronize(stg_st));
+            stg_pending[0] = stg_pending[1] = false;
+        }
+        stg_st = s;
+        if (stg_head + need > kStageHalf) {
+            HIPCHK(hipEventRecord(stg_ev[stg_cur], s));
+            stg_pending[stg_cur] = true;
+            stg_cur ^= 1;
+            stg_head = 0;
+            if (stg_pending[stg_cur]) {
+                HIPCHK(hipEventSynchronize(stg_ev[stg_cur]));
+                stg_pending[stg_cur] = false;
+            }
+        }
+        char* h = stg + (size_t)stg_cur * kStageHalf + stg_head;
+        std::memcpy(h, src, n);
+        stg_head += need;
+        HIPCHK(hipMemcpyAsync(dst, h, n, hipMemcpyHostToDevice, s));
+        return SSA_OK;
+    }
+    int upload(void* dst, const void* src, size_t n, hipStream_t s) {
+        std::lock_guard<std::mutex> g(mu);
+        return upload_locked(dst, src, n, s);
+    }
+    void stage_free() {
+        if (stg) (void)hipHostFree(stg);
+        for (auto e : stg_ev)
+            if (e) (void)hipEventDestroy(e);
+        stg = nullptr;
+    }
+
+    // Pinned host buffer for batched readbacks (grown on demand).
+    void* rb = nullptr;
+    size_t rb_cap = 0;
+    int readback_buf(size_t n, void** out) {
+        if (n > rb_cap) {
+            if (rb) (void)hipHostFree(rb);
+            rb = nullptr;
+            rb_cap = 0;
+            HIPCHK(hipHostMalloc(&rb, n, hipHostMallocDefault));
+            rb_cap = n;
+        }
+        *out = rb;
+        return SSA_OK;
+    }
+
     // twiddles exp(-2 pi i t / N) for t = 0..cnt-1 (N = n, or 2n for the split)
     int twiddles(int n, bool f64, bool split, const void** out) {
         auto key = std::make_tuple(n, (int)f64, (int)split);
@@ -227,7 +301,7 @@ struct ssa_decomp {
     int *npref = nullptr, *kpref = nullptr, *lpref = nullptr, *kcount = nullptr, *krow = nullptr, *lrow = nullptr, *runs = nullptr;
     void *Xh = nullptr, *T1 = nullptr, *T2 = nullptr, *Us = nullptr;
     long tslot = 0, uslot = 0;
-    double *Q = nullptr, *w = nullptr, *sinv = nullptr, *hp1 = nullptr, *hp2 = nullptr, *np = nullptr;
+    double *Q = nullptr, *w = nullptr, *sinv = nullptr, *hp1 = nullptr, *hp2 = nullptr, *np = nullptr, *np0 = nullptr;
     double *lnp = nullptr, *Bm = nullptr, *Yl = nullptr, *Yr = nullptr, *sig = nullptr, *beta = nullptr;
     double* Qtmp = nullptr;
     void* lbuf = nullptr;
@@ -272,6 +346,8 @@ void ctx_release(ssa_ctx* ctx) {
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (auto& kv : ctx->pool)
         for (void* q : kv.second) (void)hipFree(q);
+    ctx->stage_free();
+    if (ctx->rb) (void)hipHostFree(ctx->rb);
     if (ctx->own) (void)hipStreamDestroy(ctx->st);
     delete ctx;
 }
@@ -389,30 +465,27 @@ int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStrea
                 HIPCHK(hipStreamSynchronize(st));
                 for (int i = 0; i < d->nx; ++i)
                     for (int j = 0; j < d->ny; ++j) tm[(size_t)j * d->nx + i] = hm[(size_t)i * d->ny + j];
-                HIPCHK(hipMemcpyAsync(d->mask, tm.data(), n, hipMemcpyHostToDevice, st));
-                HIPCHK(hipStreamSynchronize(st));
+                if ((rc = d->ctx->upload(d->mask, tm.data(), n, st))) return rc;
             } else {
                 HIPCHK(hipMemcpyAsync(d->mask, q.mask, n, hipMemcpyDeviceToDevice, st));
             }
         }
     } else {
         if (!d->tr) {
-            HIPCHK(hipMemcpyAsync(d->x, q.x, n * 8, hipMemcpyHostToDevice, st));
-            if (q.mask) HIPCHK(hipMemcpyAsync(d->mask, q.mask, n, hipMemcpyHostToDevice, st));
+            if ((rc = d->ctx->upload(d->x, q.x, n * 8, st))) return rc;
+            if (q.mask && (rc = d->ctx->upload(d->mask, q.mask, n, st))) return rc;
         } else {
             std::vector<double> tx(n);
             for (int i = 0; i < d->nx; ++i)
                 for (int j = 0; j < d->ny; ++j) tx[(size_t)j * d->nx + i] = q.x[(size_t)i * d->ny + j];
-            HIPCHK(hipMemcpyAsync(d->x, tx.data(), n * 8, hipMemcpyHostToDevice, st));
+            if ((rc = d->ctx->upload(d->x, tx.data(), n * 8, st))) return rc;
             std::vector<uint8_t> tm;
             if (q.mask) {
                 tm.resize(n);
                 for (int i = 0; i < d->nx; ++i)
                     for (int j = 0; j < d->ny; ++j) tm[(size_t)j * d->nx + i] = q.mask[(size_t)i * d->ny + j];
-                HIPCHK(hipMemcpyAsync(d->mask, tm.data(), n, hipMemcpyHostToDevice, st));
+                if ((rc = d->ctx->upload(d->mask, tm.data(), n, st))) return rc;
             }
-            // the host temporaries must outlive the copies
-            HIPCHK(hipStreamSynchronize(st));
         }
     }
     // shape buffers
@@ -440,16 +513,15 @@ int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStrea
     const int nrun = (int)d->ra.size();
     if ((rc = d->dalloc(&d->runs, 3 * (long)nrun))) return rc;
     if (!lfull) {
-        HIPCHK(hipMemcpyAsync(d->lmask, d->lmask_h.data(), d->lmask_h.size(), hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(d->lpref, lpref_h.data(), lpref_h.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        if ((rc = d->ctx->upload(d->lmask, d->lmask_h.data(), d->lmask_h.size(), st))) return rc;
+        if ((rc = d->ctx->upload(d->lpref, lpref_h.data(), lpref_h.size() * sizeof(int), st))) return rc;
     }
-    HIPCHK(hipMemcpyAsync(d->lrow, d->lrow_h.data(), (d->LA + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+    if ((rc = d->ctx->upload(d->lrow, d->lrow_h.data(), (d->LA + 1) * sizeof(int), st))) return rc;
     std::vector<int> rr;
     rr.insert(rr.end(), d->ra.begin(), d->ra.end());
     rr.insert(rr.end(), d->rb0.begin(), d->rb0.end());
     rr.insert(rr.end(), d->rb1.begin(), d->rb1.end());
-    HIPCHK(hipMemcpyAsync(d->runs, rr.data(), rr.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st));
+    if ((rc = d->ctx->upload(d->runs, rr.data(), rr.size() * sizeof(int), st))) return rc;
     d->rn = Runs{d->runs, d->runs + nrun, d->runs + 2 * nrun, nrun, d->L};
     // descriptor (K set filled after the origin count)
     OpDesc& o = d->op;
@@ -492,8 +564,7 @@ struct DevVec {
             if (!p) return fail(SSA_ENOMEM, "hipMalloc (batch tables)");
             cap = b;
         }
-        if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
-        return SSA_OK;
+        return ctx->upload(p, v.data(), v.size() * sizeof(T), st);
     }
     template <typename T> T* as() const { return static_cast<T*>(p); }
 };
@@ -739,6 +810,7 @@ int run_alloc_spectrum(Batch& b) {
         if ((rc = d->dalloc(&d->Q, n * (kMaxBasis + 1))) || (rc = d->dalloc(&d->w, n)) ||
             (rc = d->dalloc(&d->sinv, n)) || (rc = d->dalloc(&d->hp1, (long)nblk * (kMaxBasis + 1))) ||
             (rc = d->dalloc(&d->hp2, (long)nblk * (kMaxBasis + 1))) || (rc = d->dalloc(&d->np, nblk)) ||
+            (rc = d->dalloc(&d->np0, nblk)) ||
             (rc = d->dalloc(&d->lnp, 2 * longrows)) || (rc = d->dalloc(&d->Bm, kMaxBasis * kMaxBasis)) ||
             (rc = d->dalloc(&d->Yl, kMaxBasis * kMaxBasis)) || (rc = d->dalloc(&d->Yr, kMaxBasis * kMaxBasis)) ||
             (rc = d->dalloc(&d->sig, kMaxBasis)) || (rc = d->dalloc(&d->beta, 4)) ||
@@ -768,7 +840,7 @@ int run_alloc_spectrum(Batch& b) {
         z.eps = d->f64 ? 1e-12 : 1e-5;
         z.n = n;
         z.nl = d->nlong;
-        z.Q = d->Q; z.w = d->w; z.sin = d->sinv; z.hp1 = d->hp1; z.hp2 = d->hp2; z.np = d->np;
+        z.Q = d->Q; z.w = d->w; z.sin = d->sinv; z.hp1 = d->hp1; z.hp2 = d->hp2; z.np = d->np; z.np0 = d->np0;
         z.lbuf[0] = d->lbuf;
         z.lbuf[1] = static_cast<char*>(d->lbuf) + d->nlong * (d->f64 ? 8 : 4);
         z.lnp[0] = d->lnp;
@@ -903,13 +975,12 @@ void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode) {
         launch_lz_proj(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols);
     }
     {
-        ProfSpan p(b.ctx, "lz_update", st, 2 * qb);
-        launch_lz_update(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 1);
-    }
-    {
         ProfSpan p(b.ctx, "lz_update", st, qb);
-        launch_lz_update(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 2);
+        launch_lz_update(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 1, 0);
     }
+    // second Gram-Schmidt pass, skipped on the device when not needed
+    launch_lz_proj2(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 0);
+    launch_lz_update(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 2, 0);
 }
 
 int basis_size(long nshort, int r) {
@@ -949,11 +1020,22 @@ int run_lanczos(Batch& b, int max_steps) {
         launch_lz_normalize(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), m);
         launch_lz_svd(S.inst.n(), st, b.lzs(), S.inst.ptr(), m, 40);
         HIPCHK(hipGetLastError());
-        for (int i : act) {
-            HIPCHK(hipMemcpyAsync(&flags[4 * i], b.ds[i]->flag, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipMemcpyAsync(&betas[2 * i], b.ds[i]->beta, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        {
+            // one gather kernel and one copy into pinned memory for the batch
+            const size_t fb = (size_t)ni * 4 * sizeof(int), bb = (size_t)ni * 2 * sizeof(double);
+            if (!b.dflag.p || b.dflag.cap < fb + bb) {
+                std::vector<char> z(fb + bb, 0);
+                if ((rc = b.dflag.put(z, st))) return rc;
+            }
+            char* dv = b.dflag.as<char>();
+            launch_gather_flags(ni, st, b.lzs(), reinterpret_cast<int*>(dv), reinterpret_cast<double*>(dv + fb));
+            void* hb = nullptr;
+            if ((rc = b.ctx->readback_buf(fb + bb, &hb))) return rc;
+            HIPCHK(hipMemcpyAsync(hb, dv, fb + bb, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            std::memcpy(flags.data(), hb, fb);
+            std::memcpy(betas.data(), static_cast<char*>(hb) + fb, bb);
         }
-        HIPCHK(hipStreamSynchronize(st));
         ++cycle;
         if (std::getenv("SHSSA_DEBUG")) {
             for (int i : act) {
@@ -1039,8 +1121,9 @@ int run_lanczos(Batch& b, int max_steps) {
             if (F.n() > 0) {
                 launch_lz_restart_random(F.n(), st, b.lzs(), F.ptr(), kk, b.ds[0]->seed + 7919ULL * cycle);
                 launch_lz_proj(F.n(), st, b.lzs(), F.ptr(), kk);
-                launch_lz_update(F.n(), st, b.lzs(), F.ptr(), kk, 1);
-                launch_lz_update(F.n(), st, b.lzs(), F.ptr(), kk, 2);
+                launch_lz_update(F.n(), st, b.lzs(), F.ptr(), kk, 1, 1);
+                launch_lz_proj2(F.n(), st, b.lzs(), F.ptr(), kk, 1);
+                launch_lz_update(F.n(), st, b.lzs(), F.ptr(), kk, 2, 1);
             }
             HIPCHK(hipStreamSynchronize(st));
         }
@@ -1092,11 +1175,22 @@ int run_finish(Batch& b) {
     if ((rc = sg.upload(st))) return rc;
     launch_sign_fix(sg.n(), st, b.ops(), b.res(), sg.ptr());
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(st));
-    for (auto* d : b.ds) {
-        d->sigma_h.resize(d->r);
-        HIPCHK(hipMemcpy(d->sigma_h.data(), d->sigma, d->r * sizeof(double), hipMemcpyDeviceToHost));
-        d->decomposed = true;
+    {
+        const size_t nb = (size_t)ni * r * sizeof(double);
+        if (!b.dbeta.p || b.dbeta.cap < nb) {
+            std::vector<char> z(nb, 0);
+            if ((rc = b.dbeta.put(z, st))) return rc;
+        }
+        launch_gather_sigma(ni, r, st, b.res(), b.dbeta.as<double>());
+        void* hb = nullptr;
+        if ((rc = b.ctx->readback_buf(nb, &hb))) return rc;
+        HIPCHK(hipMemcpyAsync(hb, b.dbeta.p, nb, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int i = 0; i < ni; ++i) {
+            auto* d = b.ds[i];
+            d->sigma_h.assign(static_cast<double*>(hb) + (size_t)i * r, static_cast<double*>(hb) + (size_t)(i + 1) * r);
+            d->decomposed = true;
+        }
     }
     return SSA_OK;
 }

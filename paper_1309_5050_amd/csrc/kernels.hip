@@ -1219,40 +1219,103 @@ k_lz_start(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, unsig
     }
 }
 
-// hp[blk][c] = sum over the block's rows of Q[:, c] * w, c < ncols.
+// Transposing butterfly over 16 values per lane: each step pairs lanes O
+// apart, each lane keeps half of its values (the lower half when bit O of
+// the lane is clear) and adds the partner's copy of that half.  After the
+// steps O = 8, 4, 2, 1 lane l holds value (l & 15) summed over its 16-lane
+// group; two more steps sum the four groups of the wave.
+template <int O>
+__device__ __forceinline__ void tr_step(double* v, int l) {
+    const bool hi = (l & O) != 0;
+#pragma unroll
+    for (int k = 0; k < O; ++k) {
+        const double send = hi ? v[k] : v[k + O];
+        const double keep = hi ? v[k + O] : v[k];
+        v[k] = keep + __shfl_xor(send, O);
+    }
+}
+
+__device__ __forceinline__ double wave_sum16(double (&v)[16]) {
+    const int l = lane_id();
+    tr_step<8>(v, l);
+    tr_step<4>(v, l);
+    tr_step<2>(v, l);
+    tr_step<1>(v, l);
+    double s = v[0];
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    return s;
+}
+
+// hp[blk][c] = sum over the block's rows of Q[:, c] * w for c < ncols and,
+// when npart is given, npart[blk] = sum over the block's rows of w^2.
 __device__ __forceinline__ void lz_project_block(const LzDesc& lz, int blk, int ncols, const double* w,
-                                                 double* hp, double (*red)[kMaxBasis + 1]) {
+                                                 double* hp, double* npart, double (*red)[kMaxBasis + 1]) {
     const long i = (long)blk * kLzRows + threadIdx.x;
-    const double wi = i < lz.n ? w[i] : 0.0;
-    const int wv = threadIdx.x >> 6;
-    for (int c = 0; c < ncols; ++c) {
-        const double q = i < lz.n ? lz.Q[(long)c * lz.n + i] : 0.0;
-        const double p = wave_sum(q * wi);
-        if (lane_id() == 0) red[wv][c] = p;
+    const bool in = i < lz.n;
+    const double wi = in ? w[i] : 0.0;
+    const int wv = threadIdx.x >> 6, l = lane_id();
+    for (int c0 = 0; c0 < ncols; c0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int c = c0 + k;
+            v[k] = (in && c < ncols) ? lz.Q[(long)c * lz.n + i] * wi : 0.0;
+        }
+        const double sm = wave_sum16(v);
+        if (l < 16 && c0 + l < ncols) red[wv][c0 + l] = sm;
+    }
+    if (npart) {
+        const double p = wave_sum(wi * wi);
+        if (l == 0) red[wv][kMaxBasis] = p;
     }
     __syncthreads();
     for (int c = threadIdx.x; c < ncols; c += 256)
         hp[(long)blk * (kMaxBasis + 1) + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+    if (npart && threadIdx.x == 0)
+        npart[blk] = red[0][kMaxBasis] + red[1][kMaxBasis] + red[2][kMaxBasis] + red[3][kMaxBasis];
 }
 
+// Iterated classical Gram-Schmidt of w against Q[:, 0:ncols] with the
+// Daniel-Gragg-Kaufman-Stewart test: the second pass runs only when the
+// first one shrank |w| below |w_before| / sqrt(2) (or when forced).  Every
+// workgroup takes the decision from the same partial norms in the same
+// order, so all agree.
+__device__ __forceinline__ bool cgs_second_pass(const LzDesc& lz, int force) {
+    if (force) return true;
+    const double after = sum_parts(lz.np, lz.nblk), before = sum_parts(lz.np0, lz.nblk);
+    return after < 0.5 * before;
+}
+
+// First projection: hp1 partials of Q^T w, np0 partials of |w|^2.
 __global__ void __launch_bounds__(256)
 k_lz_proj(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int ncols) {
     __shared__ double red[4][kMaxBasis + 1];
     const Item item = items[blockIdx.x];
     const LzDesc& lz = lzs[item.inst];
-    lz_project_block(lz, item.idx, ncols, lz.w, lz.hp1, red);
+    lz_project_block(lz, item.idx, ncols, lz.w, lz.hp1, lz.np0, red);
 }
 
-// Classical Gram-Schmidt, second half of each pass (one-sided: the
-// coefficients are discarded, they are rounding-level terms):
-// pass 1: h = sum of hp1 partials; w -= Q h; hp2 = partial projections of w.
-// pass 2: h = sum of hp2 partials; w -= Q h; np = partial |w|^2.
+// Second projection (hp2 partials), only when the second pass runs.
 __global__ void __launch_bounds__(256)
-k_lz_update(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int ncols, int pass) {
-    __shared__ double h[kMaxBasis + 1];
+k_lz_proj2(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int ncols, int force) {
     __shared__ double red[4][kMaxBasis + 1];
     const Item item = items[blockIdx.x];
     const LzDesc& lz = lzs[item.inst];
+    if (!cgs_second_pass(lz, force)) return;
+    lz_project_block(lz, item.idx, ncols, lz.w, lz.hp2, nullptr, red);
+}
+
+// Update of each pass (one-sided: the coefficients are discarded, they are
+// rounding-level terms): h = sum of the pass's partials; w -= Q h;
+// np = partial |w|^2.  Pass 2 does nothing unless the second pass runs.
+__global__ void __launch_bounds__(256)
+k_lz_update(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int ncols, int pass, int force) {
+    __shared__ double h[kMaxBasis + 1];
+    __shared__ double red[4];
+    const Item item = items[blockIdx.x];
+    const LzDesc& lz = lzs[item.inst];
+    if (pass == 2 && !cgs_second_pass(lz, force)) return;
     const double* hp = pass == 1 ? lz.hp1 : lz.hp2;
     for (int c = threadIdx.x; c < ncols; c += 256) {
         double s = 0.0;
@@ -1269,15 +1332,10 @@ k_lz_update(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int 
         wi -= acc;
         lz.w[i] = wi;
     }
-    if (pass == 1) {
-        __syncthreads();
-        lz_project_block(lz, item.idx, ncols, lz.w, lz.hp2, red);
-        return;
-    }
     const double p = wave_sum(wi * wi);
-    if (lane_id() == 0) red[threadIdx.x >> 6][0] = p;
+    if (lane_id() == 0) red[threadIdx.x >> 6] = p;
     __syncthreads();
-    if (threadIdx.x == 0) lz.np[item.idx] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+    if (threadIdx.x == 0) lz.np[item.idx] = red[0] + red[1] + red[2] + red[3];
 }
 
 // q_m = w / beta into column m of Q; beta -> lz.beta[0].
@@ -1586,6 +1644,24 @@ __global__ void __launch_bounds__(256) k_transpose(const double* __restrict__ in
         const int c = c0 + k, r = r0 + threadIdx.x;
         if (r < R && c < C) out[off + (long)c * R + r] = tile[threadIdx.x][k];
     }
+}
+
+// Batch readbacks: the Lanczos flags and residual figures of every instance
+// (4 ints + 2 doubles each), or the r singular values of every instance,
+// gathered into one array so the host reads them with a single copy.
+__global__ void k_gather_flags(const LzDesc* __restrict__ lzs, int ninst, int* __restrict__ flags,
+                               double* __restrict__ betas) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst) return;
+    const LzDesc& z = lzs[i];
+    for (int k = 0; k < 4; ++k) flags[4 * i + k] = z.flag[k];
+    for (int k = 0; k < 2; ++k) betas[2 * i + k] = z.beta[k];
+}
+
+__global__ void k_gather_sigma(const ResDesc* __restrict__ res, int ninst, int r, double* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ninst * r) return;
+    out[e] = res[e / r].sigma[e % r];
 }
 
 }  // namespace shssa

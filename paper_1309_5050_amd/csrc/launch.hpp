@@ -36,7 +36,9 @@ void launch_shape_weights(int nitems, hipStream_t st, const OpDesc* ops, const I
                           const int* const* kpref, double* const* W);
 void launch_lz_start(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, unsigned long long seed);
 void launch_lz_proj(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int ncols);
-void launch_lz_update(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int ncols, int pass);
+void launch_lz_update(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int ncols, int pass,
+                      int force);
+void launch_lz_proj2(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int ncols, int force);
 void launch_lz_normalize(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int m);
 void launch_lz_svd(int ninst, hipStream_t st, const LzDesc* lzs, const Item* items, int m, int max_sweeps);
 void launch_lz_ritz(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int m, int k,
@@ -46,6 +48,8 @@ void launch_lz_restart_random(int nitems, hipStream_t st, const LzDesc* lzs, con
                               unsigned long long seed);
 void launch_lz_sigma(int ninst, hipStream_t st, const LzDesc* lzs, const ResDesc* res, const Item* items);
 void launch_sign_fix(int nitems, hipStream_t st, const OpDesc* ops, const ResDesc* res, const Item* items);
+void launch_gather_flags(int ninst, hipStream_t st, const LzDesc* lzs, int* flags, double* betas);
+void launch_gather_sigma(int ninst, int r, hipStream_t st, const ResDesc* res, double* out);
 void launch_transpose(int nmat, int R, int C, hipStream_t st, const double* in, double* out);
 
 }  // namespace shssa
