@@ -13,7 +13,8 @@ constexpr int kLzRows = 256;
 struct OpDesc {
     int A, B;           // grid rows / columns (internal orientation)
     int MA, MB;         // FFT lengths (MA = 1 for the row family)
-    int P;              // complex row pitch of row spectra (MB/2 + 1)
+    int P;              // bins of a row spectrum (MB/2 + 1)
+    int ldp;            // row pitch of the row-major spectra (T1, T2, Xh): P rounded up to 16
     int rowfam;         // 1: window one row high
     CellSet S[2];       // S[0] window cells (L), S[1] origins (K)
     FftPlan prow;       // complex transform of length MB/2 (+ real split twiddles)

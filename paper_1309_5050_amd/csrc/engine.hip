@@ -279,7 +279,7 @@ struct ssa_decomp {
     int nx = 0, ny = 0, lx = 0, ly = 0, kx = 0, ky = 0;
     bool tr = false;                 // internal grid is the transpose
     // internal geometry
-    int A = 0, B = 0, LA = 0, LB = 0, KA = 0, KB = 0, MA = 1, MB = 0, nh = 0, P = 0;
+    int A = 0, B = 0, LA = 0, LB = 0, KA = 0, KB = 0, MA = 1, MB = 0, nh = 0, P = 0, ldp = 0;
     bool rowfam = false, f64 = true;
     int r = 0;
     unsigned long long seed = 0;
@@ -435,6 +435,7 @@ int plan_request(ssa_ctx* ctx, const ssa_request& q, ssa_decomp* d) {
     d->nh = next_smooth((d->B + 1) / 2);
     d->MB = 2 * d->nh;
     d->P = d->nh + 1;
+    d->ldp = (d->P + 15) / 16 * 16;   // 128-byte aligned column tiles
     if (row_class(d->nh, d->f64) < 0) return fail(SSA_EINVAL, "row length beyond the supported transform size");
     if (!d->rowfam) {
         d->MA = next_smooth(d->A);
@@ -525,7 +526,7 @@ int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStrea
     d->rn = Runs{d->runs, d->runs + nrun, d->runs + 2 * nrun, nrun, d->L};
     // descriptor (K set filled after the origin count)
     OpDesc& o = d->op;
-    o.A = d->A; o.B = d->B; o.MA = d->MA; o.MB = d->MB; o.P = d->P;
+    o.A = d->A; o.B = d->B; o.MA = d->MA; o.MB = d->MB; o.P = d->P; o.ldp = d->ldp;
     o.rowfam = d->rowfam;
     o.S[0] = CellSet{d->LA, d->LB, d->L, lfull ? nullptr : d->lmask, d->lrow, lfull ? nullptr : d->lpref};
     o.S[1] = CellSet{d->KA, d->KB, 0, d->kmask, d->krow, d->kpref};
@@ -729,9 +730,10 @@ int run_setup(Batch& b) {
 }
 
 // Column tile autotuner: the first batch of a (precision, column length)
-// times the spectrum pass (idempotent: it rewrites the spectrum) with every
-// compiled tile width and keeps the fastest for the context.  SHSSA_COL_TILE
-// forces a width.
+// times the column product passes of one bidiagonalisation step (on the
+// batch's own spectrum; the buffers they write are scratch at this point)
+// with every compiled tile width and keeps the fastest for the context.  The
+// spectrum pass itself is idempotent.  SHSSA_COL_TILE forces a width.
 int tune_col_tile(Batch& b) {
     const auto* d0 = b.ds[0];
     const auto key = std::make_pair((int)b.f64, d0->MA);
@@ -765,10 +767,17 @@ int tune_col_tile(Batch& b) {
         for (int i = 0; i < ni; ++i)
             for (int t = 0; t < (b.ds[i]->P + tc - 1) / tc; ++t) cols.h.push_back(Item{i, t, 0, 0});
         if ((rc = cols.upload(st))) break;
+        // the spectrum pass (also the warm-up), then the two product passes
+        // of a bidiagonalisation step, timed
         ColArgs c{COL_SPEC, d0->A, 0, 1.0 / ((double)d0->MA * d0->MB), nullptr};
-        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.ds[0]->MA, tc);   // warm-up
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.ds[0]->MA, tc);
+        const int s = d0->side, nin = d0->op.S[s].boxA, nmid = d0->op.S[1 - s].boxA;
+        const ColArgs fw{COL_CORR, nin, nmid, 1.0, nullptr}, bw{COL_CORR, nmid, nin, 1.0, nullptr};
         (void)hipEventRecord(e0, st);
-        for (int rep = 0; rep < 3; ++rep) launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.ds[0]->MA, tc);
+        for (int rep = 0; rep < 2; ++rep) {
+            launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), fw, b.ds[0]->MA, tc);
+            launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), bw, b.ds[0]->MA, tc);
+        }
         (void)hipEventRecord(e1, st);
         if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SSA_EDEVICE, "tuning"); break; }
         float ms = 0.f;
@@ -794,8 +803,8 @@ int run_alloc_spectrum(Batch& b) {
         d->nshort = d->side == 0 ? d->L : d->K;
         d->nlong = d->side == 0 ? d->K : d->L;
         const size_t ce = d->celem();
-        const long xh = d->rowfam ? (long)d->A * d->P : (long)d->P * d->MA;
-        d->tslot = (long)d->A * d->P;
+        const long xh = d->rowfam ? (long)d->A * d->ldp : (long)d->ldp * d->MA;
+        d->tslot = (long)d->A * d->ldp;
         d->uslot = d->rowfam ? (long)d->P : (long)d->P * d->MA;
         const int nslot = std::max(1, d->r);
         char *xh_p, *t1, *t2, *us, *lb;

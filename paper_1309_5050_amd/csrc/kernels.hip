@@ -227,10 +227,10 @@ k_row_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const R
     const int n1 = prow.n + 1;
     cplx<T>* out;
     if (args.dest == DEST_T1) {
-        out = static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.P;
+        out = static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.ldp;
         for (int f = tid; f < n1; f += G) out[f] = s[f];
     } else {
-        out = static_cast<cplx<T>*>(const_cast<void*>(op.Xh)) + (long)a * op.P;
+        out = static_cast<cplx<T>*>(const_cast<void*>(op.Xh)) + (long)a * op.ldp;
         const T scl = to<T>(args.scale);
         for (int f = tid; f < n1; f += G) out[f] = {s[f].x * scl, s[f].y * scl};
     }
@@ -284,7 +284,7 @@ k_row_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     T* sr = reinterpret_cast<T*>(s);
     const int a = item.idx;
     const int n1 = prow.n + 1;
-    const cplx<T>* in = static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P;
+    const cplx<T>* in = static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.ldp;
     for (int f = tid; f < n1; f += G) s[f] = in[f];
     __syncthreads();
     rfft_inv<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
@@ -326,7 +326,7 @@ k_row_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     __syncthreads();
     rfft_fwd<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
     if (!valid) return;
-    cplx<T>* out = static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.P;
+    cplx<T>* out = static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.ldp;
     for (int f = tid; f < n1; f += G) out[f] = s[f];
 }
 
@@ -378,7 +378,7 @@ k_row_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     T* sr = reinterpret_cast<T*>(s);
     const int a = item.idx;
     const int n1 = prow.n + 1;
-    const cplx<T>* in = static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P;
+    const cplx<T>* in = static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.ldp;
     for (int f = tid; f < n1; f += G) s[f] = in[f];
     __syncthreads();
     rfft_inv<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
@@ -471,12 +471,15 @@ template <typename T, int LOGN, typename AD>
 __device__ __forceinline__ void row_split_store(const cplx<T> (&v)[8], const cplx<T> (&wr)[8], cplx<T>* lds, AD ad,
                                                 int t, cplx<T>* __restrict__ out, bool write) {
     constexpr int N = RowReg<LOGN>::N, G = RowReg<LOGN>::G;
+    constexpr int RS = G + G / 8;
+    const int pw = rx_pad(t), pn = t ? rx_pad(G - t) : 0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) lds[ad(t + G * e)] = v[e];
+    for (int e = 0; e < 8; ++e) lds[ad(pw + e * RS)] = v[e];
     __syncthreads();
+    // partner position (n - k) mod n: G (7 - e) + (G - t), or G ((8 - e) mod 8) for t = 0
     cplx<T> zn[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) zn[e] = lds[ad((N - (t + G * e)) & (N - 1))];
+    for (int e = 0; e < 8; ++e) zn[e] = lds[ad(t ? pn + (7 - e) * RS : ((8 - e) & 7) * RS)];
     if (!write) return;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -536,7 +539,7 @@ k_rowr_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     const bool valid = it < nitems;
     const Item item = items[valid ? it : nitems - 1];
     const OpDesc& op = ops[item.inst];
-    const auto ad = [&](int pos) { return rx_addr_row<LOGN>(pos, c); };
+    const auto ad = [&](int pp) { return rx_addr_row<LOGN>(pp, c); };
     cplx<T> w[RegPlan<LOGN>::NTW], wr[8], v[8];
     row_reg_setup<T, LOGN>(op.prow, t, w, wr);
     const int a = item.idx;
@@ -555,8 +558,8 @@ k_rowr_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     }
     reg_fft<T, LOGN, -1>(v, w, lds, t, ad);
     cplx<T>* out = args.dest == DEST_T1
-                       ? static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.P
-                       : static_cast<cplx<T>*>(const_cast<void*>(op.Xh)) + (long)a * op.P;
+                       ? static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.ldp
+                       : static_cast<cplx<T>*>(const_cast<void*>(op.Xh)) + (long)a * op.ldp;
     row_split_store<T, LOGN>(v, wr, lds, ad, t, out, valid);
 }
 
@@ -574,11 +577,11 @@ k_rowr_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
     const bool valid = it < nitems;
     const Item item = items[valid ? it : nitems - 1];
     const OpDesc& op = ops[item.inst];
-    const auto ad = [&](int pos) { return rx_addr_row<LOGN>(pos, c); };
+    const auto ad = [&](int pp) { return rx_addr_row<LOGN>(pp, c); };
     cplx<T> w[RegPlan<LOGN>::NTW], wr[8], v[8];
     row_reg_setup<T, LOGN>(op.prow, t, w, wr);
     const int a = item.idx;
-    row_unsplit<T, LOGN>(static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P, wr, t, v);
+    row_unsplit<T, LOGN>(static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.ldp, wr, t, v);
     reg_fft<T, LOGN, +1>(v, w, lds, t, ad);
     const CellSet& S = op.S[args.set];
     int idx[16];
@@ -620,7 +623,7 @@ k_rowr_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
     if (!args.fwd) return;
     reg_fft<T, LOGN, -1>(v, w, lds, t, ad);
     row_split_store<T, LOGN>(v, wr, lds, ad, t,
-                             static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.P, valid);
+                             static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.ldp, valid);
 }
 
 // C2R of T2 row a gathered on a set row: the short-vector update (OUT_LZ)
@@ -637,11 +640,11 @@ k_rowr_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
     const bool valid = it < nitems;
     const Item item = items[valid ? it : nitems - 1];
     const OpDesc& op = ops[item.inst];
-    const auto ad = [&](int pos) { return rx_addr_row<LOGN>(pos, c); };
+    const auto ad = [&](int pp) { return rx_addr_row<LOGN>(pp, c); };
     cplx<T> w[RegPlan<LOGN>::NTW], wr[8], v[8];
     row_reg_setup<T, LOGN>(op.prow, t, w, wr);
     const int a = item.idx;
-    row_unsplit<T, LOGN>(static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P, wr, t, v);
+    row_unsplit<T, LOGN>(static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.ldp, wr, t, v);
     reg_fft<T, LOGN, +1>(v, w, lds, t, ad);
     const CellSet& S = op.S[args.set];
     int idx[16];
@@ -695,7 +698,7 @@ k_rowfam_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, con
     const int a = item.idx;
     const int n1 = prow.n + 1;
     const cplx<T>* uh = static_cast<const cplx<T>*>(op.T1) + item.comp * op.tslot;
-    const cplx<T>* xh = static_cast<const cplx<T>*>(op.Xh) + (long)a * op.P;
+    const cplx<T>* xh = static_cast<const cplx<T>*>(op.Xh) + (long)a * op.ldp;
     for (int f = tid; f < n1; f += G) s[f] = cmulc(xh[f], uh[f]);
     __syncthreads();
     rfft_inv<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
@@ -737,7 +740,7 @@ k_rowfam_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, con
     __syncthreads();
     rfft_fwd<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
     if (!valid) return;
-    cplx<T>* out = static_cast<cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.P;
+    cplx<T>* out = static_cast<cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.ldp;
     for (int f = tid; f < n1; f += G) out[f] = cmulc(xh[f], s[f]);
 }
 
@@ -762,7 +765,7 @@ k_rowfam_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs,
     const cplx<T>* pa = static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot;
     for (int f = tid; f < n1; f += G) {
         cplx<T> acc = {T(0), T(0)};
-        for (int a = 0; a < op.A; ++a) acc = cadd(acc, pa[(long)a * op.P + f]);
+        for (int a = 0; a < op.A; ++a) acc = cadd(acc, pa[(long)a * op.ldp + f]);
         s[f] = acc;
     }
     __syncthreads();
@@ -877,7 +880,7 @@ col_body(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
             const int a = e / TC, cc = e % TC;
             const int f = f0 + cc;
             cplx<T> v = {T(0), T(0)};
-            if (a < nin && f < P) v = src[(long)a * P + f];
+            if (a < nin && f < P) v = src[(long)a * op.ldp + f];
             buf[cc * LD + a] = v;
         }
     };
@@ -941,7 +944,7 @@ col_body(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
     for (int e = threadIdx.x; e < args.nout * TC; e += nthr) {
         const int a = e / TC, cc = e % TC;
         const int f = f0 + cc;
-        if (f < P) out[(long)a * P + f] = buf[cc * LD + a];
+        if (f < P) out[(long)a * op.ldp + f] = buf[cc * LD + a];
     }
 }
 
@@ -962,6 +965,7 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
     const OpDesc& op = ops[item.inst];
     const int c = threadIdx.x % TC, t = threadIdx.x / TC;
     const int P = op.P;
+    const long ld = op.ldp;
     const int f = item.idx * TC + c;
     const bool fok = f < P;
     cplx<T> w[RP::NTW];
@@ -972,29 +976,39 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int a = t + G * e;
-        v[e] = (fok && a < args.nin) ? src[(long)a * P] : cplx<T>{T(0), T(0)};
+        v[e] = (fok && a < args.nin) ? src[a * ld] : cplx<T>{T(0), T(0)};
     }
     if constexpr (!SPEC) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = fok ? xh[(long)(t + G * e) * P] : cplx<T>{T(0), T(0)};
+        for (int e = 0; e < 8; ++e) x[e] = fok ? xh[(t + G * e) * ld] : cplx<T>{T(0), T(0)};
     }
-    reg_fft<T, LOGN, -1>(v, w, lds, t, [&](int pos) { return rx_addr<TC>(pos, c); });
+    const auto ad = [&](int pp) { return rx_addr<TC>(pp, c); };
+    if (args.nin <= G) reg_fft<T, LOGN, -1, true>(v, w, lds, t, ad);
+    else reg_fft<T, LOGN, -1>(v, w, lds, t, ad);
     if constexpr (SPEC) {
         if (!fok) return;
         const T sc = to<T>(args.scale);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) xh[(long)(t + G * e) * P] = {v[e].x * sc, v[e].y * sc};
+        for (int e = 0; e < 8; ++e) xh[(t + G * e) * ld] = {v[e].x * sc, v[e].y * sc};
         return;
     } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) v[e] = cmulc(x[e], v[e]);
-        reg_fft<T, LOGN, +1>(v, w, lds, t, [&](int pos) { return rx_addr<TC>(pos, c); });
+        if constexpr (RP::REM == 0) {
+            if (args.nout <= G) {
+                reg_fft<T, LOGN, +1, false, true>(v, w, lds, t, ad);
+                if (!fok) return;
+                if (t < args.nout) static_cast<cplx<T>*>(op.T2)[item.comp * op.tslot + f + t * ld] = v[0];
+                return;
+            }
+        }
+        reg_fft<T, LOGN, +1>(v, w, lds, t, ad);
         if (!fok) return;
         cplx<T>* dst = static_cast<cplx<T>*>(op.T2) + item.comp * op.tslot + f;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int a = t + G * e;
-            if (a < args.nout) dst[(long)a * P] = v[e];
+            if (a < args.nout) dst[a * ld] = v[e];
         }
     }
 }

@@ -33,12 +33,18 @@ struct RegPlan {
     static constexpr int LROWS = N + N / 8;             // padded exchange rows
 };
 
-// LDS slot of position pos of transform c when TC transforms interleave
-// ([position][c]) or lie one after the other ([c][position]).
+// Exchange slots.  pad(pos) = pos + pos/8 leaves one empty slot per 8
+// positions (the stride-8 writes of the first pass then spread over the
+// banks).  Every exchange address is pad(base) + r * stride with a
+// compile-time stride, so the per-element offsets become instruction
+// immediates.  A transform's LDS slot of padded index pp is ad(pp): linear in
+// pp, e.g. pp*TC + c for TC interleaved transforms or c*LROWS + pp for
+// transforms one after the other.
+__device__ __forceinline__ int rx_pad(int pos) { return pos + (pos >> 3); }
 template <int TC>
-__device__ __forceinline__ int rx_addr(int pos, int c) { return (pos + (pos >> 3)) * TC + c; }
+__device__ __forceinline__ int rx_addr(int pp, int c) { return pp * TC + c; }
 template <int LOGN>
-__device__ __forceinline__ int rx_addr_row(int pos, int c) { return c * RegPlan<LOGN>::LROWS + pos + (pos >> 3); }
+__device__ __forceinline__ int rx_addr_row(int pp, int c) { return c * RegPlan<LOGN>::LROWS + pp; }
 
 // The thread's twiddles of passes 2..: radix-8 pass p uses
 // w^(r k N/(8 Ns)), k = t mod Ns, Ns = 8^p; the final radix-R pass uses
@@ -71,17 +77,23 @@ __device__ __forceinline__ cplx<T> twiddle(cplx<T> a, cplx<T> w) {
 }
 
 // In-place transform of the 8 register values of thread t.  DIR = -1
-// forward, +1 inverse (unnormalised).  ad(pos) maps a position of this
-// thread's transform to its LDS slot (transforms of a workgroup use
-// disjoint slots); the caller must not touch those slots concurrently.
-// Every thread of the workgroup must call it (it contains barriers); it
-// ends with the workgroup synchronised.
-template <typename T, int LOGN, int DIR, typename AD>
+// forward, +1 inverse (unnormalised).  ad maps a padded position of this
+// thread's transform to its LDS slot (transforms of a workgroup use disjoint
+// slots); the caller must not touch those slots concurrently.  Every thread
+// of the workgroup must call it (it contains barriers); it ends with the
+// workgroup synchronised.
+// SPARSE_IN: only slot 0 of the input is nonzero (the first pass is a
+// broadcast).  FIRST_OUT: only slot 0 of the output is used (the last radix-8
+// pass computes its first output only); valid when LOGN is a multiple of 3.
+template <typename T, int LOGN, int DIR, bool SPARSE_IN = false, bool FIRST_OUT = false, typename AD>
 __device__ __forceinline__ void reg_fft(cplx<T> (&v)[8], const cplx<T> (&w)[RegPlan<LOGN>::NTW],
                                         cplx<T>* lds, int t, AD ad) {
     using RP = RegPlan<LOGN>;
     constexpr int G = RP::G;
     constexpr int NPASS = RP::P8 + (RP::REM ? 1 : 0);
+    constexpr int RS = G + G / 8;        // padded distance of the read slots
+    static_assert(!FIRST_OUT || RP::REM == 0, "FIRST_OUT needs a final radix-8 pass");
+    const int prd = rx_pad(t);
 #pragma unroll
     for (int p = 0; p < RP::P8; ++p) {
         const int Ns = 1 << (3 * p);
@@ -89,15 +101,28 @@ __device__ __forceinline__ void reg_fft(cplx<T> (&v)[8], const cplx<T> (&w)[RegP
 #pragma unroll
             for (int r = 1; r < 8; ++r) v[r] = twiddle<T, DIR>(v[r], w[7 * (p - 1) + r - 1]);
         }
-        bf8<T, DIR>(v);
+        if (p == NPASS - 1 && FIRST_OUT) {
+            cplx<T> s0 = v[0];
+#pragma unroll
+            for (int r = 1; r < 8; ++r) s0 = cadd(s0, v[r]);
+            v[0] = s0;
+            return;
+        }
+        if (p == 0 && SPARSE_IN) {
+#pragma unroll
+            for (int r = 1; r < 8; ++r) v[r] = v[0];
+        } else {
+            bf8<T, DIR>(v);
+        }
         if (p == NPASS - 1) return;
         const int k = t & (Ns - 1);
-        const int base = (t - k) * 8 + k;
+        const int pb = rx_pad((t - k) * 8 + k);
+        const int WS = Ns == 1 ? 1 : Ns + Ns / 8;   // padded distance of the write slots
 #pragma unroll
-        for (int r = 0; r < 8; ++r) lds[ad(base + r * Ns)] = v[r];
+        for (int r = 0; r < 8; ++r) lds[ad(pb + r * WS)] = v[r];
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = lds[ad(t + G * e)];
+        for (int e = 0; e < 8; ++e) v[e] = lds[ad(prd + e * RS)];
         __syncthreads();
     }
     if constexpr (RP::REM != 0) {
