@@ -1365,33 +1365,30 @@ k_lz_normalize(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, i
 }
 
 // SVD of the m x m projected matrix by one-sided (Hestenes) Jacobi, one
-// workgroup of 1024 threads per instance: the columns of B are held in LDS
-// and rotated pairwise in round-robin order (16 threads per pair) until all
-// pairs are orthogonal; the right singular vectors accumulate in Yr.  The
-// singular values are the column norms, the left vectors the normalised
-// columns.  Then the values are ranked (descending) and the residual test
+// workgroup of 1024 threads per instance.  The columns of B live in LDS; in
+// each round of the round-robin ordering every 16-thread group takes one
+// column pair into registers, forms the three inner products, rotates the
+// pair when it is not yet orthogonal and writes it back.  Only the last row
+// of the accumulated right rotations is needed downstream (the residual
+// estimates beta * Yr[m-1, i]), so only that row is rotated.  The singular
+// values are the final column norms, the left vectors the normalised
+// columns; they are ranked (descending) and the residual test
 // beta |Yr[m-1, i]| <= tol * sigma_1 is evaluated for the r leading ones.
 __global__ void __launch_bounds__(1024)
 k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, int max_sweeps) {
-    // B columns and, when they fit next to them (m <= 100), the right vectors
-    // live in LDS; otherwise the right vectors rotate in global memory.
-    constexpr int kLds = 20320;
-    __shared__ double lds[kLds];
+    constexpr int PE = kMaxBasis / 16;          // column entries per thread
+    __shared__ double Bs[kMaxBasis * kMaxBasis];
+    __shared__ double yl[kMaxBasis];
     __shared__ double cn[kMaxBasis];
     __shared__ int changed;
     const Item item = items[blockIdx.x];
     const LzDesc& lz = lzs[item.inst];
     const int nt = blockDim.x;
-    double* Bs = lds;
-    const bool ylds = 2 * m * m <= kLds;
-    double* Y = ylds ? lds + m * m : lz.Yr;
-    const int ldy = ylds ? m : kMaxBasis;
     for (int e = threadIdx.x; e < m * m; e += nt) {
         const int i = e % m, c = e / m;
         Bs[c * m + i] = lz.Bm[(long)c * kMaxBasis + i];
-        Y[(long)c * ldy + i] = i == c ? 1.0 : 0.0;
     }
-    __syncthreads();
+    for (int c = threadIdx.x; c < m; c += nt) yl[c] = c == m - 1 ? 1.0 : 0.0;
     const int nn = m + (m & 1);
     const int npairs = nn / 2;
     const int t = threadIdx.x >> 4, g = threadIdx.x & 15;
@@ -1408,10 +1405,16 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
                 if (q < m) {
                     double* bp = Bs + p * m;
                     double* bq = Bs + q * m;
+                    double x1[PE], x2[PE];
                     double al = 0.0, be = 0.0, ga = 0.0;
-                    for (int i = g; i < m; i += 16) {
-                        const double x1 = bp[i], x2 = bq[i];
-                        al += x1 * x1; be += x2 * x2; ga += x1 * x2;
+#pragma unroll
+                    for (int k = 0; k < PE; ++k) {
+                        const int i = g + 16 * k;
+                        x1[k] = i < m ? bp[i] : 0.0;
+                        x2[k] = i < m ? bq[i] : 0.0;
+                        al += x1[k] * x1[k];
+                        be += x2[k] * x2[k];
+                        ga += x1[k] * x2[k];
                     }
 #pragma unroll
                     for (int o = 8; o > 0; o >>= 1) {
@@ -1422,26 +1425,30 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
                     if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
                         const double ze = (be - al) / (2.0 * ga);
                         const double tt = (ze >= 0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
-                        const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-                        for (int i = g; i < m; i += 16) {
-                            const double x1 = bp[i], x2 = bq[i];
-                            bp[i] = c * x1 - s * x2;
-                            bq[i] = s * x1 + c * x2;
+                        const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+#pragma unroll
+                        for (int k = 0; k < PE; ++k) {
+                            const int i = g + 16 * k;
+                            if (i < m) {
+                                bp[i] = c * x1[k] - sn * x2[k];
+                                bq[i] = sn * x1[k] + c * x2[k];
+                            }
                         }
-                        double* yp = Y + (long)p * ldy;
-                        double* yq = Y + (long)q * ldy;
-                        for (int i = g; i < m; i += 16) {
-                            const double y1 = yp[i], y2 = yq[i];
-                            yp[i] = c * y1 - s * y2;
-                            yq[i] = s * y1 + c * y2;
+                        if (g == 0) {
+                            const double y1 = yl[p], y2 = yl[q];
+                            yl[p] = c * y1 - sn * y2;
+                            yl[q] = sn * y1 + c * y2;
+                            changed = 1;
                         }
-                        if (g == 0) changed = 1;
                     }
                 }
             }
             __syncthreads();
         }
-        if (!changed) break;
+        // read the flag, then let thread 0 reset it only after every thread has
+        const int ch = changed;
+        __syncthreads();
+        if (!ch) break;
     }
     for (int c = threadIdx.x; c < m; c += nt) {
         double s2 = 0.0;
@@ -1452,8 +1459,8 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
     for (int e = threadIdx.x; e < m * m; e += nt) {
         const int i = e % m, c = e / m;
         lz.Yl[(long)c * kMaxBasis + i] = cn[c] > 0 ? Bs[c * m + i] / cn[c] : 0.0;
-        if (ylds) lz.Yr[(long)c * kMaxBasis + i] = Y[c * m + i];
     }
+    for (int c = threadIdx.x; c < m; c += nt) lz.Yr[(long)c * kMaxBasis + (m - 1)] = yl[c];
     for (int i = threadIdx.x; i < m; i += nt) {
         const double ti = cn[i];
         int rank = 0;
@@ -1473,7 +1480,7 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
         double worst = 0.0;
         for (int i = 0; i < r; ++i) {
             const int c = lz.perm[i];
-            const double resid = fabs(beta * (ylds ? Y[c * m + (m - 1)] : lz.Yr[(long)c * kMaxBasis + (m - 1)]));
+            const double resid = fabs(beta * yl[c]);
             if (!(resid <= lz.tol * s1)) ok = 0;
             worst = fmax(worst, s1 > 0 ? resid / s1 : 0.0);
         }
