@@ -20,6 +20,43 @@ namespace shssa {
 
 template <typename T> struct cplx { T x, y; };
 
+// Pointer to device global memory.  Casting the generic pointers held in the
+// descriptors lets the compiler emit global (not flat) loads and stores and
+// use the scalar-base + 32-bit-offset addressing form.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T* p) { return (gptr<T>)p; }
+template <typename T>
+__device__ __forceinline__ gptr<const T> as_global(const T* p) { return (gptr<const T>)p; }
+template <typename T>
+__device__ __forceinline__ T gload(gptr<const T> p) { return *p; }
+template <typename T>
+__device__ __forceinline__ T gload(gptr<T> p) { return *p; }
+template <typename T>
+__device__ __forceinline__ void gstore(gptr<T> p, T v) { *p = v; }
+
+// Complex values move as one two-element vector (one 8- or 16-byte access).
+template <typename T> struct vec2;
+template <> struct vec2<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct vec2<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <typename T>
+__device__ __forceinline__ cplx<T> gload(gptr<const cplx<T>> p) {
+    const typename vec2<T>::type v = *(gptr<const typename vec2<T>::type>)p;
+    return cplx<T>{v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> gload(gptr<cplx<T>> p) {
+    const typename vec2<T>::type v = *(gptr<typename vec2<T>::type>)p;
+    return cplx<T>{v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void gstore(gptr<cplx<T>> p, cplx<T> c) {
+    typename vec2<T>::type v;
+    v.x = c.x;
+    v.y = c.y;
+    *(gptr<typename vec2<T>::type>)p = v;
+}
+
 template <typename T>
 __host__ __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
     return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};

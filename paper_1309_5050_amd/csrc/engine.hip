@@ -657,22 +657,24 @@ double col_bytes(const Batch& b, const ItemList& L, int nin, int nout) {
 // the compact vectors it reads or writes.
 double row_bytes(const Batch& b, const ItemList& L, int cin, int cout, double vec_bytes_per_inst) {
     double tot = 0.0;
-    for (const Item& it : L.h) tot += (double)b.ds[it.inst]->P * b.ds[it.inst]->celem() * (cin + cout);
+    for (const Item& it : L.h)
+        tot += (double)std::max(it.aux, 1) * b.ds[it.inst]->P * b.ds[it.inst]->celem() * (cin + cout);
     std::vector<char> seen(b.ds.size(), 0);
     for (const Item& it : L.h)
         if (!seen[it.inst]) { seen[it.inst] = 1; tot += vec_bytes_per_inst; }
     return tot;
 }
 
-// rows [0, nrows) of every listed instance, optional component range
+// rows [0, nrows) of every listed instance, optional component range; with
+// group > 1 one item per group of rows (first row, row count in aux)
 void rows_items(ItemList& L, const std::vector<int>& inst, std::function<int(int)> nrows, int ncomp = 1,
-                const std::vector<int>* comps = nullptr) {
+                const std::vector<int>* comps = nullptr, int group = 1) {
     L.h.clear();
     for (int c = 0; c < ncomp; ++c)
         for (int i : inst) {
             const int nr = nrows(i);
             const int comp = comps ? (*comps)[c] : c;
-            for (int a = 0; a < nr; ++a) L.h.push_back(Item{i, a, comp, 0});
+            for (int a = 0; a < nr; a += group) L.h.push_back(Item{i, a, comp, std::min(group, nr - a)});
         }
 }
 
@@ -900,14 +902,15 @@ void build_step_lists(Batch& b, const std::vector<int>& act, StepLists& S) {
     const auto* d0 = b.ds[0];
     const int s = d0->side;
     if (d0->rowfam) {
-        rows_items(S.rin, act, [&](int) { return 1; });
+        rows_items(S.rin, act, [&](int) { return 1; }, 1, nullptr, row_group(b.cls, false));
         rows_items(S.rmid, act, [&](int i) { return b.ds[i]->A; });
         rows_items(S.rout, act, [&](int) { return 1; });
         S.cols.h.clear();
     } else {
-        rows_items(S.rin, act, [&](int i) { return b.ds[i]->op.S[s].boxA; });
-        rows_items(S.rmid, act, [&](int i) { return b.ds[i]->op.S[1 - s].boxA; });
-        rows_items(S.rout, act, [&](int i) { return b.ds[i]->op.S[s].boxA; });
+        rows_items(S.rin, act, [&](int i) { return b.ds[i]->op.S[s].boxA; }, 1, nullptr, row_group(b.cls, false));
+        rows_items(S.rmid, act, [&](int i) { return b.ds[i]->op.S[1 - s].boxA; }, 1, nullptr,
+                   row_group(b.cls, false));
+        rows_items(S.rout, act, [&](int i) { return b.ds[i]->op.S[s].boxA; }, 1, nullptr, row_group(b.cls, false));
         S.cols.h.clear();
         for (int i : act)
             for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) S.cols.h.push_back(Item{i, t, 0, 0});
@@ -1158,7 +1161,7 @@ int run_finish(Batch& b) {
     const int s = d0->side;
     ItemList rin, cols, rmid, sg;
     if (d0->rowfam) {
-        rows_items(rin, all, [&](int) { return 1; }, r);
+        rows_items(rin, all, [&](int) { return 1; }, r, nullptr, row_group(b.cls, false));
         rows_items(rmid, all, [&](int i) { return b.ds[i]->A; }, r);
         if ((rc = rin.upload(st)) || (rc = rmid.upload(st))) return rc;
         launch_row_in(b.f64, b.cls, rin.n(), st, b.ops(), b.lzs(), b.res(), rin.ptr(),
@@ -1166,8 +1169,9 @@ int run_finish(Batch& b) {
         launch_rowfam_mid(b.f64, b.cls, rmid.n(), st, b.ops(), b.lzs(), b.res(), rmid.ptr(),
                           RowFamArgs{OUT_VEC, 0, 0, 0, 0});
     } else {
-        rows_items(rin, all, [&](int i) { return b.ds[i]->op.S[s].boxA; }, r);
-        rows_items(rmid, all, [&](int i) { return b.ds[i]->op.S[1 - s].boxA; }, r);
+        rows_items(rin, all, [&](int i) { return b.ds[i]->op.S[s].boxA; }, r, nullptr, row_group(b.cls, false));
+        rows_items(rmid, all, [&](int i) { return b.ds[i]->op.S[1 - s].boxA; }, r, nullptr,
+                   row_group(b.cls, false));
         for (int c = 0; c < r; ++c)
             for (int i : all)
                 for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) cols.h.push_back(Item{i, t, c, 0});
@@ -1229,7 +1233,7 @@ int run_reconstruct(Batch& b, const std::vector<int>& gptr, const std::vector<in
     const auto* d0 = b.ds[0];
     ItemList a1, a2, c1, c2, out;
     if (d0->rowfam) {
-        rows_items(a1, all, [&](int) { return 1; }, nc, &comps);
+        rows_items(a1, all, [&](int) { return 1; }, nc, &comps, row_group(b.cls, false));
         rows_items(out, all, [&](int i) { return b.ds[i]->A; }, ng);
         if ((rc = a1.upload(st)) || (rc = out.upload(st))) return rc;
         launch_row_in(b.f64, b.cls, a1.n(), st, b.ops(), b.lzs(), b.res(), a1.ptr(),
@@ -1237,8 +1241,8 @@ int run_reconstruct(Batch& b, const std::vector<int>& gptr, const std::vector<in
         launch_copy_uspec(b.f64, a1.n(), st, b.ops(), a1.ptr());
         launch_rowfam_recon(b.f64, b.cls, out.n(), st, b.ops(), b.res(), out.ptr(), 1.0 / d0->MB);
     } else {
-        rows_items(a1, all, [&](int i) { return b.ds[i]->LA; }, nc, &comps);
-        rows_items(a2, all, [&](int i) { return b.ds[i]->KA; }, nc, &comps);
+        rows_items(a1, all, [&](int i) { return b.ds[i]->LA; }, nc, &comps, row_group(b.cls, false));
+        rows_items(a2, all, [&](int i) { return b.ds[i]->KA; }, nc, &comps, row_group(b.cls, false));
         rows_items(out, all, [&](int i) { return b.ds[i]->A; }, ng);
         for (int c : comps)
             for (int i : all)

@@ -16,6 +16,8 @@
 // Shapes follow Algorithm 6: an origin belongs to K when every window cell
 // placed there lands on a cell of N.  The window count is taken by exact
 // integer run sums over row prefix counts instead of a rounded FFT product.
+#include <type_traits>
+
 #include "common.hpp"
 #include "device.hpp"
 #include "fft.hpp"
@@ -418,8 +420,9 @@ k_row_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
 // ------------------------------------------------------------------------
 // register row kernels: half-lengths n = 2^LOGN, 64 <= n <= 512
 // ------------------------------------------------------------------------
-// A workgroup of 256 threads takes RPW = 256/G rows, G = n/8 consecutive
-// lanes per row.  Thread t of a row holds the complex pairs
+// A workgroup of 256 threads takes RPW = 256/G consecutive rows of one
+// instance (work item: instance, first row, component, row count), G = n/8
+// consecutive lanes per row.  Thread t of a row holds the complex pairs
 // z_p = (x_{2p}, x_{2p+1}) at positions p = t + G*e (e = 0..7) and, on the
 // spectral side, the bins k = t + G*e (thread 0 also the bin n).
 
@@ -442,17 +445,17 @@ __device__ __forceinline__ double lane_group_sum(double v) {
 
 // Z_k = E'_k + i O'_k for the thread's bins: E'_k = X_k + conj X_{n-k},
 // O'_k = (X_k - conj X_{n-k}) conj(W^k), W = exp(-2 pi i/2n); the inverse
-// complex transform of Z gives 2n x as pairs.
+// complex transform of Z gives 2n x as pairs.  row: bins 0..n of the row.
 template <typename T, int LOGN>
-__device__ __forceinline__ void row_unsplit(const cplx<T>* __restrict__ in, const cplx<T> (&wr)[8], int t,
+__device__ __forceinline__ void row_unsplit(gptr<const cplx<T>> row, const cplx<T> (&wr)[8], int t,
                                             cplx<T> (&v)[8]) {
     constexpr int N = RowReg<LOGN>::N, G = RowReg<LOGN>::G;
+    const gptr<const cplx<T>> lo = row + t, hi = row + (N - t);
     cplx<T> X[8], Y[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-        const int k = t + G * e;
-        X[e] = in[k];
-        Y[e] = in[N - k];
+        X[e] = gload(lo + G * e);
+        Y[e] = gload(hi - G * e);
     }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -466,10 +469,10 @@ __device__ __forceinline__ void row_unsplit(const cplx<T>* __restrict__ in, cons
 // From Z = FFT(z) (natural positions in v) to the bins of the real
 // transform: X_k = E_k + W^k O_k with E_k = (Z_k + conj Z_{n-k})/2,
 // O_k = (Z_k - conj Z_{n-k})/(2i); X_n = E_0 - O_0.  Z_{n-k} comes from the
-// partner thread through LDS.  Writes out[k] for the thread's bins.
+// partner thread through LDS.  Writes the thread's bins of row.
 template <typename T, int LOGN, typename AD>
 __device__ __forceinline__ void row_split_store(const cplx<T> (&v)[8], const cplx<T> (&wr)[8], cplx<T>* lds, AD ad,
-                                                int t, cplx<T>* __restrict__ out, bool write) {
+                                                int t, gptr<cplx<T>> row, bool write) {
     constexpr int N = RowReg<LOGN>::N, G = RowReg<LOGN>::G;
     constexpr int RS = G + G / 8;
     const int pw = rx_pad(t), pn = t ? rx_pad(G - t) : 0;
@@ -481,36 +484,50 @@ __device__ __forceinline__ void row_split_store(const cplx<T> (&v)[8], const cpl
 #pragma unroll
     for (int e = 0; e < 8; ++e) zn[e] = lds[ad(t ? pn + (7 - e) * RS : ((8 - e) & 7) * RS)];
     if (!write) return;
+    const gptr<cplx<T>> out = row + t;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const cplx<T> zk = v[e];
         const cplx<T> E = {T(0.5) * (zk.x + zn[e].x), T(0.5) * (zk.y - zn[e].y)};
         const cplx<T> O = {T(0.5) * (zk.y + zn[e].y), T(-0.5) * (zk.x - zn[e].x)};
         const cplx<T> wo = cmul(wr[e], O);
-        out[t + G * e] = cadd(E, wo);
-        if (e == 0 && t == 0) out[N] = csub(E, O);
+        gstore(out + G * e, cadd(E, wo));
+        if (e == 0 && t == 0) gstore(row + N, csub(E, O));
     }
 }
 
-// Compact indices of the cells 2p and 2p+1, p = t + G*e, of set row a
-// (-1 off the set or outside the set's box).
-template <int G>
+// Compact indices of the cells 2p + h (slot q = 2e + h, p = t + G*e) of set
+// row a; -1 off the set or outside the set's box.  DENSE (no mask): the
+// index is the row offset plus the cell, so accesses through it keep one
+// per-thread address with immediate offsets.
+template <int G, bool DENSE>
 __device__ __forceinline__ void pair_idx(const CellSet& S, int a, int t, int (&idx)[16]) {
     const bool inrow = a < S.boxA;
-    const int base = inrow ? S.rowoff[a] : 0;
-    const uint8_t* m = (inrow && S.mask) ? S.mask + (long)a * S.boxB : nullptr;
-    const int* pf = (inrow && S.mask) ? S.pref + (long)a * (S.boxB + 1) : nullptr;
+    const int base = inrow ? gload(as_global(S.rowoff) + a) : 0;
     const int lim = inrow ? S.boxB : 0;
+    if constexpr (DENSE) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int b = 2 * (t + G * (q >> 1)) + (q & 1);
-        int v = -1;
-        if (b < lim) {
-            if (!m) v = base + b;
-            else if (m[b]) v = base + pf[b];
+        for (int q = 0; q < 16; ++q) {
+            const int b = 2 * (t + G * (q >> 1)) + (q & 1);
+            idx[q] = b < lim ? base + b : -1;
         }
-        idx[q] = v;
+    } else {
+        const gptr<const uint8_t> m = as_global(S.mask) + (long)a * S.boxB;
+        const gptr<const int> pf = as_global(S.pref) + (long)a * (S.boxB + 1);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int b = 2 * (t + G * (q >> 1)) + (q & 1);
+            idx[q] = (b < lim && gload(m + b)) ? base + gload(pf + b) : -1;
+        }
     }
+}
+
+// Runs body(std::true_type) for a set without mask, body(std::false_type)
+// otherwise (the choice is uniform over the workgroup).
+template <typename F>
+__device__ __forceinline__ void dense_or_masked(const CellSet& S, F body) {
+    if (S.mask == nullptr) body(std::true_type{});
+    else body(std::false_type{});
 }
 
 template <typename T>
@@ -520,9 +537,14 @@ template <typename T, int LOGN>
 __device__ __forceinline__ void row_reg_setup(const FftPlan& prow, int t, cplx<T> (&w)[RegPlan<LOGN>::NTW],
                                               cplx<T> (&wr)[8]) {
     reg_twiddles<T, LOGN>(static_cast<const cplx<T>*>(prow.tw), t, w);
-    const cplx<T>* twr = static_cast<const cplx<T>*>(prow.twr);
+    const gptr<const cplx<T>> twr = as_global(static_cast<const cplx<T>*>(prow.twr)) + t;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) wr[e] = twr[t + RowReg<LOGN>::G * e];
+    for (int e = 0; e < 8; ++e) wr[e] = gload(twr + RowReg<LOGN>::G * e);
+}
+
+template <typename T>
+__device__ __forceinline__ gptr<cplx<T>> spec_row(void* base, long slot, int a, int ldp) {
+    return as_global(static_cast<cplx<T>*>(base) + slot + (long)a * ldp);
 }
 
 // Row input (all modes but IN_DENSE): gather the compact vector on set row
@@ -535,31 +557,33 @@ k_rowr_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     constexpr int G = RR::G;
     __shared__ cplx<T> lds[RR::RPW * RegPlan<LOGN>::LROWS];
     const int c = threadIdx.x / G, t = threadIdx.x % G;
-    const int it = blockIdx.x * RR::RPW + c;
-    const bool valid = it < nitems;
-    const Item item = items[valid ? it : nitems - 1];
+    const Item item = items[blockIdx.x];
+    const bool valid = c < item.aux;
+    const int a = item.idx + (valid ? c : 0);
     const OpDesc& op = ops[item.inst];
     const auto ad = [&](int pp) { return rx_addr_row<LOGN>(pp, c); };
     cplx<T> w[RegPlan<LOGN>::NTW], wr[8], v[8];
     row_reg_setup<T, LOGN>(op.prow, t, w, wr);
-    const int a = item.idx;
     const CellSet& S = op.S[args.set];
     const RowInSrc rs = row_in_source(op, lzs[item.inst], res, item, args, valid && a == 0 && t == 0);
-    int idx[16];
-    pair_idx<G>(S, a, t, idx);
-    double val[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) val[q] = idx[q] >= 0 ? rs.src[idx[q]] * rs.sc : 0.0;
+    const gptr<const double> src = as_global(rs.src);
+    const gptr<double> qout = as_global(rs.qout);
     const bool wq = valid && rs.qout != nullptr;
+    dense_or_masked(S, [&](auto dense) {
+        int idx[16];
+        pair_idx<G, decltype(dense)::value>(S, a, t, idx);
+        double val[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        if (wq && idx[q] >= 0) rs.qout[idx[q]] = val[q];
-        pair_part(v[q >> 1], q & 1) = to<T>(val[q]);
-    }
+        for (int q = 0; q < 16; ++q) val[q] = idx[q] >= 0 ? gload(src + idx[q]) * rs.sc : 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (wq && idx[q] >= 0) gstore(qout + idx[q], val[q]);
+            pair_part(v[q >> 1], q & 1) = to<T>(val[q]);
+        }
+    });
     reg_fft<T, LOGN, -1>(v, w, lds, t, ad);
-    cplx<T>* out = args.dest == DEST_T1
-                       ? static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.ldp
-                       : static_cast<cplx<T>*>(const_cast<void*>(op.Xh)) + (long)a * op.ldp;
+    const gptr<cplx<T>> out = args.dest == DEST_T1 ? spec_row<T>(op.T1, item.comp * op.tslot, a, op.ldp)
+                                                   : spec_row<T>(const_cast<void*>(op.Xh), 0, a, op.ldp);
     row_split_store<T, LOGN>(v, wr, lds, ad, t, out, valid);
 }
 
@@ -573,36 +597,39 @@ k_rowr_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
     constexpr int G = RR::G;
     __shared__ cplx<T> lds[RR::RPW * RegPlan<LOGN>::LROWS];
     const int c = threadIdx.x / G, t = threadIdx.x % G;
-    const int it = blockIdx.x * RR::RPW + c;
-    const bool valid = it < nitems;
-    const Item item = items[valid ? it : nitems - 1];
+    const Item item = items[blockIdx.x];
+    const bool valid = c < item.aux;
+    const int a = item.idx + (valid ? c : 0);
     const OpDesc& op = ops[item.inst];
     const auto ad = [&](int pp) { return rx_addr_row<LOGN>(pp, c); };
     cplx<T> w[RegPlan<LOGN>::NTW], wr[8], v[8];
     row_reg_setup<T, LOGN>(op.prow, t, w, wr);
-    const int a = item.idx;
-    row_unsplit<T, LOGN>(static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.ldp, wr, t, v);
+    row_unsplit<T, LOGN>(spec_row<T>(op.T2, item.comp * op.tslot, a, op.ldp), wr, t, v);
     reg_fft<T, LOGN, +1>(v, w, lds, t, ad);
     const CellSet& S = op.S[args.set];
-    int idx[16];
-    pair_idx<G>(S, a, t, idx);
     if (args.gk) {
         const GkLong<T> g = gk_long<T>(lzs[item.inst], S, args.j, args.jstart);
-        T pv[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) pv[q] = idx[q] >= 0 ? g.lprev[idx[q]] : T(0);
+        const gptr<const T> lprev = as_global(g.lprev);
+        const gptr<T> lcur = as_global(g.lcur);
         double part = 0.0;
+        dense_or_masked(S, [&](auto dense) {
+            int idx[16];
+            pair_idx<G, decltype(dense)::value>(S, a, t, idx);
+            T pv[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            T& z = pair_part(v[q >> 1], q & 1);
-            T nv = T(0);
-            if (idx[q] >= 0) {
-                nv = z - g.gamma * pv[q];
-                if (valid) g.lcur[idx[q]] = nv;
-                part += static_cast<double>(nv) * static_cast<double>(nv);
+            for (int q = 0; q < 16; ++q) pv[q] = idx[q] >= 0 ? gload(lprev + idx[q]) : T(0);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                T& z = pair_part(v[q >> 1], q & 1);
+                T nv = T(0);
+                if (idx[q] >= 0) {
+                    nv = z - g.gamma * pv[q];
+                    if (valid) gstore(lcur + idx[q], nv);
+                    part += static_cast<double>(nv) * static_cast<double>(nv);
+                }
+                z = nv;
             }
-            z = nv;
-        }
+        });
         part = lane_group_sum<G>(part);
         if (valid && t == 0) g.lnp[a] = part;
     } else {
@@ -613,17 +640,21 @@ k_rowr_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
             vout = (args.set == 0 ? rs.U : rs.V) + (long)item.comp * S.count;
             if (args.div_sigma) sc = rs.sigma[item.comp] > 0 ? sc / rs.sigma[item.comp] : 0.0;
         }
+        const gptr<double> vo = as_global(vout);
+        dense_or_masked(S, [&](auto dense) {
+            int idx[16];
+            pair_idx<G, decltype(dense)::value>(S, a, t, idx);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            T& z = pair_part(v[q >> 1], q & 1);
-            if (idx[q] < 0) z = T(0);
-            else if (vout) vout[idx[q]] = sc * static_cast<double>(z);
-        }
+            for (int q = 0; q < 16; ++q) {
+                T& z = pair_part(v[q >> 1], q & 1);
+                if (idx[q] < 0) z = T(0);
+                else if (vout) gstore(vo + idx[q], sc * static_cast<double>(z));
+            }
+        });
     }
     if (!args.fwd) return;
     reg_fft<T, LOGN, -1>(v, w, lds, t, ad);
-    row_split_store<T, LOGN>(v, wr, lds, ad, t,
-                             static_cast<cplx<T>*>(op.T1) + item.comp * op.tslot + (long)a * op.ldp, valid);
+    row_split_store<T, LOGN>(v, wr, lds, ad, t, spec_row<T>(op.T1, item.comp * op.tslot, a, op.ldp), valid);
 }
 
 // C2R of T2 row a gathered on a set row: the short-vector update (OUT_LZ)
@@ -636,39 +667,47 @@ k_rowr_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
     constexpr int G = RR::G;
     __shared__ cplx<T> lds[RR::RPW * RegPlan<LOGN>::LROWS];
     const int c = threadIdx.x / G, t = threadIdx.x % G;
-    const int it = blockIdx.x * RR::RPW + c;
-    const bool valid = it < nitems;
-    const Item item = items[valid ? it : nitems - 1];
+    const Item item = items[blockIdx.x];
+    const bool valid = c < item.aux;
+    const int a = item.idx + (valid ? c : 0);
     const OpDesc& op = ops[item.inst];
     const auto ad = [&](int pp) { return rx_addr_row<LOGN>(pp, c); };
     cplx<T> w[RegPlan<LOGN>::NTW], wr[8], v[8];
     row_reg_setup<T, LOGN>(op.prow, t, w, wr);
-    const int a = item.idx;
-    row_unsplit<T, LOGN>(static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot + (long)a * op.ldp, wr, t, v);
+    row_unsplit<T, LOGN>(spec_row<T>(op.T2, item.comp * op.tslot, a, op.ldp), wr, t, v);
     reg_fft<T, LOGN, +1>(v, w, lds, t, ad);
     const CellSet& S = op.S[args.set];
-    int idx[16];
-    pair_idx<G>(S, a, t, idx);
     if (args.mode == OUT_LZ) {
         const GkShort g = gk_short(lzs[item.inst], op.S[1 - args.set], args.j, args.jstart, valid && a == 0 && t == 0);
-        double qv[16];
+        const gptr<const double> qv = as_global(g.q);
+        const gptr<double> wv = as_global(g.w);
+        dense_or_masked(S, [&](auto dense) {
+            int idx[16];
+            pair_idx<G, decltype(dense)::value>(S, a, t, idx);
+            double qq[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) qv[q] = idx[q] >= 0 ? g.q[idx[q]] : 0.0;
-        if (!valid) return;
+            for (int q = 0; q < 16; ++q) qq[q] = idx[q] >= 0 ? gload(qv + idx[q]) : 0.0;
+            if (!valid) return;
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
-            if (idx[q] >= 0)
-                g.w[idx[q]] = static_cast<double>(pair_part(v[q >> 1], q & 1)) * g.inv_alpha - g.alpha * qv[q];
+            for (int q = 0; q < 16; ++q)
+                if (idx[q] >= 0)
+                    gstore(wv + idx[q],
+                           static_cast<double>(pair_part(v[q >> 1], q & 1)) * g.inv_alpha - g.alpha * qq[q]);
+        });
         return;
     }
     if (!valid) return;
     const ResDesc& rs = res[item.inst];
-    double* vout = (args.set == 0 ? rs.U : rs.V) + (long)item.comp * S.count;
+    const gptr<double> vout = as_global((args.set == 0 ? rs.U : rs.V) + (long)item.comp * S.count);
     double sc = args.scale;
     if (args.div_sigma) sc /= rs.sigma[item.comp];
+    dense_or_masked(S, [&](auto dense) {
+        int idx[16];
+        pair_idx<G, decltype(dense)::value>(S, a, t, idx);
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
-        if (idx[q] >= 0) vout[idx[q]] = sc * static_cast<double>(pair_part(v[q >> 1], q & 1));
+        for (int q = 0; q < 16; ++q)
+            if (idx[q] >= 0) gstore(vout + idx[q], sc * static_cast<double>(pair_part(v[q >> 1], q & 1)));
+    });
 }
 
 // ------------------------------------------------------------------------
@@ -970,17 +1009,19 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
     const bool fok = f < P;
     cplx<T> w[RP::NTW];
     reg_twiddles<T, LOGN>(static_cast<const cplx<T>*>(op.pcol.tw), t, w);
-    const cplx<T>* src = static_cast<const cplx<T>*>(op.T1) + item.comp * op.tslot + f;
-    cplx<T>* xh = static_cast<cplx<T>*>(const_cast<void*>(op.Xh)) + f;
+    // tile bases (uniform) and the thread's 32-bit offset within a tile
+    const long tile = item.comp * op.tslot + (long)item.idx * TC;
+    const long estep = (long)G * ld;
+    const int lo = t * (int)ld + c;
+    gptr<const cplx<T>> src = as_global(static_cast<const cplx<T>*>(op.T1) + tile);
+    gptr<cplx<T>> xh = as_global(static_cast<cplx<T>*>(const_cast<void*>(op.Xh)) + (long)item.idx * TC);
     cplx<T> v[8], x[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int a = t + G * e;
-        v[e] = (fok && a < args.nin) ? src[a * ld] : cplx<T>{T(0), T(0)};
-    }
+    for (int e = 0; e < 8; ++e)
+        v[e] = (fok && t + G * e < args.nin) ? gload(src + e * estep + lo) : cplx<T>{T(0), T(0)};
     if constexpr (!SPEC) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = fok ? xh[(t + G * e) * ld] : cplx<T>{T(0), T(0)};
+        for (int e = 0; e < 8; ++e) x[e] = fok ? gload(xh + e * estep + lo) : cplx<T>{T(0), T(0)};
     }
     const auto ad = [&](int pp) { return rx_addr<TC>(pp, c); };
     if (args.nin <= G) reg_fft<T, LOGN, -1, true>(v, w, lds, t, ad);
@@ -989,27 +1030,24 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
         if (!fok) return;
         const T sc = to<T>(args.scale);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) xh[(t + G * e) * ld] = {v[e].x * sc, v[e].y * sc};
+        for (int e = 0; e < 8; ++e) gstore(xh + e * estep + lo, cplx<T>{v[e].x * sc, v[e].y * sc});
         return;
     } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) v[e] = cmulc(x[e], v[e]);
+        gptr<cplx<T>> dst = as_global(static_cast<cplx<T>*>(op.T2) + tile);
         if constexpr (RP::REM == 0) {
             if (args.nout <= G) {
                 reg_fft<T, LOGN, +1, false, true>(v, w, lds, t, ad);
-                if (!fok) return;
-                if (t < args.nout) static_cast<cplx<T>*>(op.T2)[item.comp * op.tslot + f + t * ld] = v[0];
+                if (fok && t < args.nout) gstore(dst + lo, v[0]);
                 return;
             }
         }
         reg_fft<T, LOGN, +1>(v, w, lds, t, ad);
         if (!fok) return;
-        cplx<T>* dst = static_cast<cplx<T>*>(op.T2) + item.comp * op.tslot + f;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int a = t + G * e;
-            if (a < args.nout) dst[a * ld] = v[e];
-        }
+        for (int e = 0; e < 8; ++e)
+            if (t + G * e < args.nout) gstore(dst + e * estep + lo, v[e]);
     }
 }
 

@@ -6,6 +6,10 @@ namespace shssa {
 
 int row_class(int n, bool f64);
 int row_slots(int cls);
+// Rows per work item of the row passes: the register row kernels take one
+// item per group of rows (instance, first row, component, row count); the
+// dense modes and the LDS kernels one item per row.
+int row_group(int cls, bool dense);
 int col_tile(bool f64);                 // default column tile
 bool col_tile_ok(bool f64, int MA, int tc);   // tile widths compiled for the precision and length
 int col_fast_logn(int MA);              // log2(MA) when the register column kernel applies, else 0

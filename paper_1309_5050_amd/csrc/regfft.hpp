@@ -50,9 +50,10 @@ __device__ __forceinline__ int rx_addr_row(int pp, int c) { return c * RegPlan<L
 // w^(r k N/(8 Ns)), k = t mod Ns, Ns = 8^p; the final radix-R pass uses
 // w^(r j), j = t + q G for its butterflies q.
 template <typename T, int LOGN>
-__device__ __forceinline__ void reg_twiddles(const cplx<T>* __restrict__ tw, int t,
+__device__ __forceinline__ void reg_twiddles(const cplx<T>* __restrict__ twp, int t,
                                              cplx<T> (&w)[RegPlan<LOGN>::NTW]) {
     using RP = RegPlan<LOGN>;
+    const gptr<const cplx<T>> tw = as_global(twp);
     int q = 0;
 #pragma unroll
     for (int p = 1; p < RP::P8; ++p) {
@@ -60,14 +61,14 @@ __device__ __forceinline__ void reg_twiddles(const cplx<T>* __restrict__ tw, int
         const int k = t & (Ns - 1);
         const int step = k * (RP::N / (8 * Ns));
 #pragma unroll
-        for (int r = 1; r < 8; ++r) w[q++] = tw[r * step];
+        for (int r = 1; r < 8; ++r) w[q++] = gload(tw + r * step);
     }
     if constexpr (RP::REM != 0) {
         constexpr int B = 8 / RP::R;
 #pragma unroll
         for (int b = 0; b < B; ++b)
 #pragma unroll
-            for (int r = 1; r < RP::R; ++r) w[q++] = tw[r * (t + b * RP::G)];
+            for (int r = 1; r < RP::R; ++r) w[q++] = gload(tw + r * (t + b * RP::G));
     }
 }
 
