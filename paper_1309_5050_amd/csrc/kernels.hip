@@ -1301,18 +1301,22 @@ __device__ __forceinline__ double wave_sum16(double (&v)[16]) {
 
 // hp[blk][c] = sum over the block's rows of Q[:, c] * w for c < ncols and,
 // when npart is given, npart[blk] = sum over the block's rows of w^2.
-__device__ __forceinline__ void lz_project_block(const LzDesc& lz, int blk, int ncols, const double* w,
+// Thread = row; each wave reduces 16 columns at a time with the transposing
+// butterfly, the four waves combine through LDS.
+__device__ __forceinline__ void lz_project_block(const LzDesc& lz, int blk, int ncols, const double* wp,
                                                  double* hp, double* npart, double (*red)[kMaxBasis + 1]) {
     const long i = (long)blk * kLzRows + threadIdx.x;
     const bool in = i < lz.n;
-    const double wi = in ? w[i] : 0.0;
+    const long n = lz.n;
+    const gptr<const double> Q = as_global(static_cast<const double*>(lz.Q)) + (in ? i : 0);
+    const double wi = in ? gload(as_global(wp) + i) : 0.0;
     const int wv = threadIdx.x >> 6, l = lane_id();
     for (int c0 = 0; c0 < ncols; c0 += 16) {
         double v[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             const int c = c0 + k;
-            v[k] = (in && c < ncols) ? lz.Q[(long)c * lz.n + i] * wi : 0.0;
+            v[k] = (in && c < ncols) ? gload(Q + (long)c * n) * wi : 0.0;
         }
         const double sm = wave_sum16(v);
         if (l < 16 && c0 + l < ncols) red[wv][c0 + l] = sm;
@@ -1378,11 +1382,13 @@ k_lz_update(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int 
     const long i = (long)item.idx * kLzRows + threadIdx.x;
     double wi = 0.0;
     if (i < lz.n) {
-        wi = lz.w[i];
+        const gptr<double> w = as_global(lz.w) + i;
+        const gptr<const double> Q = as_global(static_cast<const double*>(lz.Q)) + i;
+        wi = gload(w);
         double acc = 0.0;
-        for (int c = 0; c < ncols; ++c) acc += lz.Q[(long)c * lz.n + i] * h[c];
+        for (int c = 0; c < ncols; ++c) acc += gload(Q + (long)c * lz.n) * h[c];
         wi -= acc;
-        lz.w[i] = wi;
+        gstore(w, wi);
     }
     const double p = wave_sum(wi * wi);
     if (lane_id() == 0) red[threadIdx.x >> 6] = p;
@@ -1403,8 +1409,8 @@ k_lz_normalize(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, i
 }
 
 // SVD of the m x m projected matrix by one-sided (Hestenes) Jacobi, one
-// workgroup of 1024 threads per instance.  The columns of B live in LDS; in
-// each round of the round-robin ordering every 16-thread group takes one
+// workgroup of 512 threads per instance.  The columns of B live in LDS; in
+// each round of the round-robin ordering every 8-thread group takes one
 // column pair into registers, forms the three inner products, rotates the
 // pair when it is not yet orthogonal and writes it back.  Only the last row
 // of the accumulated right rotations is needed downstream (the residual
@@ -1412,9 +1418,10 @@ k_lz_normalize(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, i
 // values are the final column norms, the left vectors the normalised
 // columns; they are ranked (descending) and the residual test
 // beta |Yr[m-1, i]| <= tol * sigma_1 is evaluated for the r leading ones.
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(512)
 k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, int max_sweeps) {
-    constexpr int PE = kMaxBasis / 16;          // column entries per thread
+    constexpr int LP = 8;                       // threads per column pair
+    constexpr int PE = kMaxBasis / LP;          // column entries per thread
     __shared__ double Bs[kMaxBasis * kMaxBasis];
     __shared__ double yl[kMaxBasis];
     __shared__ double cn[kMaxBasis];
@@ -1429,7 +1436,10 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
     for (int c = threadIdx.x; c < m; c += nt) yl[c] = c == m - 1 ? 1.0 : 0.0;
     const int nn = m + (m & 1);
     const int npairs = nn / 2;
-    const int t = threadIdx.x >> 4, g = threadIdx.x & 15;
+    const int t = threadIdx.x / LP, g = threadIdx.x % LP;
+    // rotations stop at |a_p . a_q| <= jt |a_p| |a_q| (far below the
+    // accuracy the operator precision can support)
+    const double jt = lz.eps < 1e-8 ? 1e-15 : 1e-12;
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
         if (threadIdx.x == 0) changed = 0;
@@ -1447,7 +1457,7 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
                     double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
                     for (int k = 0; k < PE; ++k) {
-                        const int i = g + 16 * k;
+                        const int i = g + LP * k;
                         x1[k] = i < m ? bp[i] : 0.0;
                         x2[k] = i < m ? bq[i] : 0.0;
                         al += x1[k] * x1[k];
@@ -1455,18 +1465,18 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
                         ga += x1[k] * x2[k];
                     }
 #pragma unroll
-                    for (int o = 8; o > 0; o >>= 1) {
-                        al += __shfl_xor(al, o, 16);
-                        be += __shfl_xor(be, o, 16);
-                        ga += __shfl_xor(ga, o, 16);
+                    for (int o = LP / 2; o > 0; o >>= 1) {
+                        al += __shfl_xor(al, o, LP);
+                        be += __shfl_xor(be, o, LP);
+                        ga += __shfl_xor(ga, o, LP);
                     }
-                    if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+                    if (ga != 0.0 && fabs(ga) > jt * sqrt(al * be)) {
                         const double ze = (be - al) / (2.0 * ga);
                         const double tt = (ze >= 0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
                         const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
 #pragma unroll
                         for (int k = 0; k < PE; ++k) {
-                            const int i = g + 16 * k;
+                            const int i = g + LP * k;
                             if (i < m) {
                                 bp[i] = c * x1[k] - sn * x2[k];
                                 bq[i] = sn * x1[k] + c * x2[k];
