@@ -75,6 +75,18 @@ __device__ __forceinline__ void row_visit(const CellSet& S, int a, int len, int 
     }
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin in launch order, and
+// each XCD has its own L2.  xcd_block maps launch index b to a work index so
+// that every XCD receives one contiguous range of work items: neighbouring
+// items (which share cache lines) then meet in the same L2.  A bijection on
+// [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    constexpr int kXcd = 8;
+    const int x = b % kXcd, k = b / kXcd;
+    const int q = nb / kXcd, rem = nb % kXcd;
+    return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + k;
+}
+
 template <typename T> __device__ __forceinline__ T to(double v) { return static_cast<T>(v); }
 
 // Sum of v over the G threads of a slot.  G == 64: one wave; otherwise the
@@ -1000,7 +1012,7 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
     using RP = RegPlan<LOGN>;
     constexpr int G = RP::G;
     __shared__ cplx<T> lds[RP::LROWS * TC];
-    const Item item = items[blockIdx.x];
+    const Item item = items[xcd_block(blockIdx.x, gridDim.x)];
     const OpDesc& op = ops[item.inst];
     const int c = threadIdx.x % TC, t = threadIdx.x / TC;
     const int P = op.P;
@@ -1440,16 +1452,19 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
     // rotations stop at |a_p . a_q| <= jt |a_p| |a_q| (far below the
     // accuracy the operator precision can support)
     const double jt = lz.eps < 1e-8 ? 1e-15 : 1e-12;
+    const double jt2 = jt * jt;
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
         if (threadIdx.x == 0) changed = 0;
         __syncthreads();
+        // round-robin pairing: round rd pairs (rd + t, rd - t) mod (nn - 1),
+        // and nn - 1 with rd for t = 0; both indices advance by one per round
+        int a = t == 0 ? nn - 1 : t, b = t == 0 ? 0 : nn - 1 - t;
         for (int rd = 0; rd < nn - 1; ++rd) {
+            const int p = a < b ? a : b, q = a < b ? b : a;
+            if (t != 0) a = a + 1 == nn - 1 ? 0 : a + 1;
+            b = b + 1 == nn - 1 ? 0 : b + 1;
             if (t < npairs) {
-                int a, b;
-                if (t == 0) { a = nn - 1; b = rd % (nn - 1); }
-                else { a = (rd + t) % (nn - 1); b = (rd - t + (nn - 1)) % (nn - 1); }
-                const int p = a < b ? a : b, q = a < b ? b : a;
                 if (q < m) {
                     double* bp = Bs + p * m;
                     double* bq = Bs + q * m;
@@ -1470,7 +1485,7 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
                         be += __shfl_xor(be, o, LP);
                         ga += __shfl_xor(ga, o, LP);
                     }
-                    if (ga != 0.0 && fabs(ga) > jt * sqrt(al * be)) {
+                    if (ga != 0.0 && ga * ga > jt2 * (al * be)) {
                         const double ze = (be - al) / (2.0 * ga);
                         const double tt = (ze >= 0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
                         const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
