@@ -490,7 +490,7 @@ __device__ __forceinline__ void row_split_store(const cplx<T> (&v)[8], const cpl
     const int pw = rx_pad(t), pn = t ? rx_pad(G - t) : 0;
 #pragma unroll
     for (int e = 0; e < 8; ++e) lds[ad(pw + e * RS)] = v[e];
-    __syncthreads();
+    xsync<XS_WAVE>();
     // partner position (n - k) mod n: G (7 - e) + (G - t), or G ((8 - e) mod 8) for t = 0
     cplx<T> zn[8];
 #pragma unroll
@@ -574,6 +574,7 @@ k_rowr_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     const int a = item.idx + (valid ? c : 0);
     const OpDesc& op = ops[item.inst];
     const auto ad = [&](int pp) { return rx_addr_row<LOGN>(pp, c); };
+    int xe = 0;
     cplx<T> w[RegPlan<LOGN>::NTW], wr[8], v[8];
     row_reg_setup<T, LOGN>(op.prow, t, w, wr);
     const CellSet& S = op.S[args.set];
@@ -593,7 +594,7 @@ k_rowr_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
             pair_part(v[q >> 1], q & 1) = to<T>(val[q]);
         }
     });
-    reg_fft<T, LOGN, -1>(v, w, lds, t, ad);
+    reg_fft<T, LOGN, -1, XS_WAVE>(v, w, lds, t, ad, xe);
     const gptr<cplx<T>> out = args.dest == DEST_T1 ? spec_row<T>(op.T1, item.comp * op.tslot, a, op.ldp)
                                                    : spec_row<T>(const_cast<void*>(op.Xh), 0, a, op.ldp);
     row_split_store<T, LOGN>(v, wr, lds, ad, t, out, valid);
@@ -614,10 +615,11 @@ k_rowr_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
     const int a = item.idx + (valid ? c : 0);
     const OpDesc& op = ops[item.inst];
     const auto ad = [&](int pp) { return rx_addr_row<LOGN>(pp, c); };
+    int xe = 0;
     cplx<T> w[RegPlan<LOGN>::NTW], wr[8], v[8];
     row_reg_setup<T, LOGN>(op.prow, t, w, wr);
     row_unsplit<T, LOGN>(spec_row<T>(op.T2, item.comp * op.tslot, a, op.ldp), wr, t, v);
-    reg_fft<T, LOGN, +1>(v, w, lds, t, ad);
+    reg_fft<T, LOGN, +1, XS_WAVE>(v, w, lds, t, ad, xe);
     const CellSet& S = op.S[args.set];
     if (args.gk) {
         const GkLong<T> g = gk_long<T>(lzs[item.inst], S, args.j, args.jstart);
@@ -665,7 +667,7 @@ k_rowr_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
         });
     }
     if (!args.fwd) return;
-    reg_fft<T, LOGN, -1>(v, w, lds, t, ad);
+    reg_fft<T, LOGN, -1, XS_WAVE>(v, w, lds, t, ad, xe);
     row_split_store<T, LOGN>(v, wr, lds, ad, t, spec_row<T>(op.T1, item.comp * op.tslot, a, op.ldp), valid);
 }
 
@@ -684,10 +686,11 @@ k_rowr_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
     const int a = item.idx + (valid ? c : 0);
     const OpDesc& op = ops[item.inst];
     const auto ad = [&](int pp) { return rx_addr_row<LOGN>(pp, c); };
+    int xe = 0;
     cplx<T> w[RegPlan<LOGN>::NTW], wr[8], v[8];
     row_reg_setup<T, LOGN>(op.prow, t, w, wr);
     row_unsplit<T, LOGN>(spec_row<T>(op.T2, item.comp * op.tslot, a, op.ldp), wr, t, v);
-    reg_fft<T, LOGN, +1>(v, w, lds, t, ad);
+    reg_fft<T, LOGN, +1, XS_WAVE>(v, w, lds, t, ad, xe);
     const CellSet& S = op.S[args.set];
     if (args.mode == OUT_LZ) {
         const GkShort g = gk_short(lzs[item.inst], op.S[1 - args.set], args.j, args.jstart, valid && a == 0 && t == 0);
@@ -1011,8 +1014,9 @@ __global__ void __launch_bounds__(RegPlan<LOGN>::G * TC)
 k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs args) {
     using RP = RegPlan<LOGN>;
     constexpr int G = RP::G;
-    __shared__ cplx<T> lds[RP::LROWS * TC];
+    __shared__ cplx<T> lds[2 * RP::LROWS * TC];
     const Item item = items[xcd_block(blockIdx.x, gridDim.x)];
+    int xe = 0;
     const OpDesc& op = ops[item.inst];
     const int c = threadIdx.x % TC, t = threadIdx.x / TC;
     const int P = op.P;
@@ -1036,8 +1040,9 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
         for (int e = 0; e < 8; ++e) x[e] = fok ? gload(xh + e * estep + lo) : cplx<T>{T(0), T(0)};
     }
     const auto ad = [&](int pp) { return rx_addr<TC>(pp, c); };
-    if (args.nin <= G) reg_fft<T, LOGN, -1, true>(v, w, lds, t, ad);
-    else reg_fft<T, LOGN, -1>(v, w, lds, t, ad);
+    constexpr int XB = RP::LROWS * TC;
+    if (args.nin <= G) reg_fft<T, LOGN, -1, XS_WG2, true>(v, w, lds, t, ad, xe, XB);
+    else reg_fft<T, LOGN, -1, XS_WG2>(v, w, lds, t, ad, xe, XB);
     if constexpr (SPEC) {
         if (!fok) return;
         const T sc = to<T>(args.scale);
@@ -1050,12 +1055,12 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
         gptr<cplx<T>> dst = as_global(static_cast<cplx<T>*>(op.T2) + tile);
         if constexpr (RP::REM == 0) {
             if (args.nout <= G) {
-                reg_fft<T, LOGN, +1, false, true>(v, w, lds, t, ad);
+                reg_fft<T, LOGN, +1, XS_WG2, false, true>(v, w, lds, t, ad, xe, XB);
                 if (fok && t < args.nout) gstore(dst + lo, v[0]);
                 return;
             }
         }
-        reg_fft<T, LOGN, +1>(v, w, lds, t, ad);
+        reg_fft<T, LOGN, +1, XS_WG2>(v, w, lds, t, ad, xe, XB);
         if (!fok) return;
 #pragma unroll
         for (int e = 0; e < 8; ++e)

@@ -72,6 +72,27 @@ __device__ __forceinline__ void reg_twiddles(const cplx<T>* __restrict__ twp, in
     }
 }
 
+// Exchange synchronisation.  XS_WG: transforms spread over the waves of a
+// workgroup, one LDS buffer (barrier after the writes and after the reads).
+// XS_WG2: the same with two buffers used in turn (one barrier per exchange:
+// a buffer is rewritten only two exchanges later, after a barrier every
+// reader of its previous contents has passed).  XS_WAVE: every transform
+// lies inside one wave, whose lanes execute each LDS instruction together;
+// a wave-scope fence keeps the compiler from moving LDS accesses across the
+// exchange.
+enum { XS_WG = 0, XS_WG2 = 1, XS_WAVE = 2 };
+
+template <int XS>
+__device__ __forceinline__ void xsync() {
+    if constexpr (XS == XS_WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 template <typename T, int DIR>
 __device__ __forceinline__ cplx<T> twiddle(cplx<T> a, cplx<T> w) {
     return DIR < 0 ? cmul(a, w) : cmulc(a, w);
@@ -81,14 +102,15 @@ __device__ __forceinline__ cplx<T> twiddle(cplx<T> a, cplx<T> w) {
 // forward, +1 inverse (unnormalised).  ad maps a padded position of this
 // thread's transform to its LDS slot (transforms of a workgroup use disjoint
 // slots); the caller must not touch those slots concurrently.  Every thread
-// of the workgroup must call it (it contains barriers); it ends with the
-// workgroup synchronised.
+// of the workgroup must call it (it may contain barriers).  XS selects the
+// exchange synchronisation; with XS_WG2 exchange number xe (counted by the
+// caller across calls) uses buffer lds + (xe & 1) * xbuf.
 // SPARSE_IN: only slot 0 of the input is nonzero (the first pass is a
 // broadcast).  FIRST_OUT: only slot 0 of the output is used (the last radix-8
 // pass computes its first output only); valid when LOGN is a multiple of 3.
-template <typename T, int LOGN, int DIR, bool SPARSE_IN = false, bool FIRST_OUT = false, typename AD>
+template <typename T, int LOGN, int DIR, int XS, bool SPARSE_IN = false, bool FIRST_OUT = false, typename AD>
 __device__ __forceinline__ void reg_fft(cplx<T> (&v)[8], const cplx<T> (&w)[RegPlan<LOGN>::NTW],
-                                        cplx<T>* lds, int t, AD ad) {
+                                        cplx<T>* lds, int t, AD ad, int& xe, int xbuf = 0) {
     using RP = RegPlan<LOGN>;
     constexpr int G = RP::G;
     constexpr int NPASS = RP::P8 + (RP::REM ? 1 : 0);
@@ -116,15 +138,17 @@ __device__ __forceinline__ void reg_fft(cplx<T> (&v)[8], const cplx<T> (&w)[RegP
             bf8<T, DIR>(v);
         }
         if (p == NPASS - 1) return;
+        cplx<T>* buf = XS == XS_WG2 ? lds + (xe & 1) * xbuf : lds;
+        ++xe;
         const int k = t & (Ns - 1);
         const int pb = rx_pad((t - k) * 8 + k);
         const int WS = Ns == 1 ? 1 : Ns + Ns / 8;   // padded distance of the write slots
 #pragma unroll
-        for (int r = 0; r < 8; ++r) lds[ad(pb + r * WS)] = v[r];
-        __syncthreads();
+        for (int r = 0; r < 8; ++r) buf[ad(pb + r * WS)] = v[r];
+        xsync<XS>();
 #pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = lds[ad(prd + e * RS)];
-        __syncthreads();
+        for (int e = 0; e < 8; ++e) v[e] = buf[ad(prd + e * RS)];
+        if constexpr (XS != XS_WG2) xsync<XS>();
     }
     if constexpr (RP::REM != 0) {
         constexpr int R = RP::R, B = 8 / R;
