@@ -52,11 +52,16 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.copy_calibration:
+        # a plain device copy of known size; the source is evicted from the
+        # caches first (512 MiB written after it), so the copy reads HBM
         n = args.copy_calibration * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device=dev)
+        flush = torch.ones(128 << 20, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
+        torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
+        del flush
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
         return
     stream = torch.cuda.current_stream()
@@ -120,6 +125,8 @@ def main():
             lat.append(time.perf_counter() - ta)
         single = {"decomps_per_s": reps / sum(lat), "latency_ms": 1e3 * float(np.median(lat))}
 
+    traffic, traffic_kernel = measured_traffic()
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(imgs[0], lw)
@@ -142,9 +149,9 @@ def main():
                                                              args.precision == "fp32" else ""),
                    "parallelism": "batched on 1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_col (column transform pass)", "ms_per_launch": kern_ms,
-                     "bytes_per_launch": kern_bytes},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_colr (column product pass)", "ms_per_launch": kern_ms,
+                     "bytes_per_launch": kern_bytes, "traffic_counters_on": traffic_kernel},
         "hbh_product": {"bytes_per_product": bmv, "products_per_step": products,
                         "effective_GBs": bmv * products / (dt / args.steps) / 1e9},
         "lanczos": {"steps": stats["steps"], "restarts": stats["restarts"], "basis": stats["basis"],
@@ -156,6 +163,29 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per launch of the column product pass from the committed
+    rocprofv3 counter summary, or None when the kernel sources have changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_colr_image512_batch64_fp32_traffic.md")
+    if not os.path.exists(path):
+        return None, None
+    vals = {}
+    for line in open(path):
+        line = line.strip()
+        for key in ("traffic-bytes-per-launch:", "source-sha256:", "kernel-instance:"):
+            if line.startswith(key):
+                vals[key] = line[len(key):].strip()
+    h = hashlib.sha256()
+    for f in ("common.hpp", "device.hpp", "fft.hpp", "regfft.hpp", "kernels.hip"):
+        with open(os.path.join(ROOT, "paper_1309_5050_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if vals.get("source-sha256:") != h.hexdigest() or "traffic-bytes-per-launch:" not in vals:
+        return None, vals.get("kernel-instance:")
+    return float(vals["traffic-bytes-per-launch:"]), vals.get("kernel-instance:")
 
 
 def cpu_baseline(x, lw):
