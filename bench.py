@@ -34,6 +34,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--no-single", action="store_true", help="skip the single-instance FP64 comparator")
+    ap.add_argument("--serve", type=int, default=300, metavar="N",
+                    help="requests of the mixed serving workload for the latency runs (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (torch) and exit: the reference "
                          "kernel for scaling HBM byte counters")
@@ -127,6 +129,10 @@ def main():
 
     traffic, traffic_kernel = measured_traffic()
 
+    serving = None
+    if args.serve > 0:
+        serving = serve_bench(S, W, args.serve)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(imgs[0], lw)
@@ -161,8 +167,95 @@ def main():
         "fp64_single_instance": single,
         "speedup_vs_fp64_single": (value / single["decomps_per_s"]) if single else None,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
+
+
+def _run_sync(ctx, q, prec):
+    if q["kind"] == "mssa":
+        d = ctx.decompose_multi(q["x"], q["window"], q["r"], precision=prec)
+    else:
+        d = ctx.decompose(q["x"], q["window"], q["r"], mask=q.get("mask"), wmask=q.get("wmask"), precision=prec)
+    d.reconstruct(q["groups"])
+    d.free()
+
+
+def _submit(ctx, q, prec):
+    if q["kind"] == "mssa":
+        return ctx.submit_multi(q["x"], q["window"], q["r"], precision=prec, groups=q["groups"])
+    return ctx.submit(q["x"], q["window"], q["r"], mask=q.get("mask"), wmask=q.get("wmask"), precision=prec,
+                      groups=q["groups"])
+
+
+def _served_run(S, data, prec, rate, seed):
+    """Poisson arrivals at `rate` req/s (rate None: all at once, closed loop);
+    returns latency percentiles (first 5% excluded) and throughput."""
+    import threading
+
+    import numpy as np
+    ctx = S.Context(0)
+    n = len(data)
+    rng = np.random.default_rng(seed)
+    arrive = np.cumsum(rng.exponential(1.0 / rate, n)) if rate else np.zeros(n)
+    tickets = [None] * n
+    lat = [None] * n
+    got = threading.Event()
+
+    def collect():
+        for i in range(n):
+            while tickets[i] is None:
+                got.wait(0.001)
+            ctx.wait(tickets[i])
+            d, _, tm = ctx.take(tickets[i])
+            lat[i] = tm["total_ms"]
+            if hasattr(d, "free"):
+                d.free()
+
+    th = threading.Thread(target=collect)
+    th.start()
+    t0 = time.perf_counter()
+    for i, q in enumerate(data):
+        dt = t0 + arrive[i] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets[i] = _submit(ctx, q, prec)
+        got.set()
+    th.join()
+    t1 = time.perf_counter()
+    ctx.close()
+    warm = max(1, n // 20)
+    ls = np.array(lat[warm:])
+    return {"precision": prec, "offered_rps": rate, "requests": n, "achieved_rps": n / (t1 - t0),
+            "p50_ms": float(np.percentile(ls, 50)), "p99_ms": float(np.percentile(ls, 99)),
+            "mean_ms": float(ls.mean())}
+
+
+def serve_bench(S, W, n_req):
+    """Mixed serving workload (60% 1D, 25% MSSA, 15% 2D, r ~ U{5..40},
+    groups {1..min(r,4)}): capacity of the plain single-instance FP64 path
+    (closed loop), then Poisson arrivals at 0.8 x that capacity through the
+    serving engine in FP32 and FP64, and at 0.8 x the served FP32 capacity."""
+    mix = W.serving_mix(n_req, seed=5)
+    data = [W.materialize(d) for d in mix]
+    ctx = S.Context(0)
+    ncap = min(len(data), 60)
+    for q in data[:3]:
+        _run_sync(ctx, q, "fp64")
+    t0 = time.perf_counter()
+    for q in data[:ncap]:
+        _run_sync(ctx, q, "fp64")
+    cap64 = ncap / (time.perf_counter() - t0)
+    ctx.close()
+    out = {"workload": f"serving mix, {n_req} requests (60% 1D N~U(500,20000), 25% MSSA s~U(4,32), "
+                       f"15% 2D S~U(64,512)), r~U(5,40)",
+           "plain_fp64_capacity_rps": cap64, "runs": []}
+    for prec in ("fp32", "fp64"):
+        out["runs"].append(_served_run(S, data, prec, 0.8 * cap64, seed=11))
+    closed = _served_run(S, data, "fp32", None, seed=12)
+    out["served_fp32_capacity_rps"] = closed["achieved_rps"]
+    out["runs"].append(_served_run(S, data, "fp32", 0.8 * closed["achieved_rps"], seed=13))
+    return out
 
 
 def measured_traffic():

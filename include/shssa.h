@@ -156,6 +156,43 @@ void ssa_free(ssa_decomp* d);
 const char* ssa_strerror(int code);
 const char* ssa_last_error(void);
 
+/* Serving (asynchronous requests).  The paper's ssa() + reconstruct() pair
+ * per request (Section 5 and its reconstruct call), queued instead of run
+ * at once.
+ *
+ * ssa_submit copies the request's host inputs (x, mask, wmask: as for
+ * ssa_decompose; seed unused) and the groups (CSR form: grp_ptr[ngroups+1],
+ * 0-based component ids in grp_idx; ngroups may be 0 for no reconstruction)
+ * and returns a ticket at once.  Library threads, each with its own HIP
+ * stream on the context's device, admit waiting requests in arrival order
+ * while their estimated device memory fits the context's budget beside the
+ * running batches, put every waiting request of the same geometry, rank and
+ * precision into the same batch (up to 64), and run decomposition and
+ * reconstruction.  Errors that the plan shows at once (bad sizes, a request
+ * larger than the whole budget: SSA_ENOMEM) are returned by ssa_submit.
+ *
+ * ssa_poll sets *done = 1 once the request has finished (successfully or
+ * not).  ssa_wait blocks until then.  ssa_take ends the request: it returns
+ * the request's status, hands over the handle (*out, freed by the caller
+ * with ssa_free; NULL if the request failed), copies the reconstruction
+ * (ngroups x nx x ny, NaN off N') into recon if recon is not NULL, and
+ * fills times (ms from submission to start and to completion) if not NULL.
+ * ssa_take of an unfinished request returns SSA_EBUSY and changes nothing.
+ * Requests not taken are released by ssa_ctx_destroy. */
+typedef struct ssa_times {
+    double queue_ms;   /* submission -> start of its batch */
+    double total_ms;   /* submission -> completion */
+} ssa_times;
+
+int ssa_submit(ssa_ctx* ctx, const ssa_request* req, const int* grp_ptr, const int* grp_idx, int ngroups,
+               uint64_t* ticket);
+/* MSSA request (series as for ssa_decompose_multi). */
+int ssa_submit_multi(ssa_ctx* ctx, const double* const* series, const int* len, int s, int L, int r,
+                     int precision, const int* grp_ptr, const int* grp_idx, int ngroups, uint64_t* ticket);
+int ssa_poll(ssa_ctx* ctx, uint64_t ticket, int* done);
+int ssa_wait(ssa_ctx* ctx, uint64_t ticket);
+int ssa_take(ssa_ctx* ctx, uint64_t ticket, ssa_decomp** out, double* recon, ssa_times* times);
+
 /* Blocks until all work queued on the context's stream is complete. */
 int ssa_ctx_sync(ssa_ctx* ctx);
 

@@ -223,3 +223,60 @@ class Context:
         ptrs = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
         check(lib().ssa_reconstruct_batch_dev(n, hs, _ptr(gp), _ptr(gi), len(groups), ptrs),
               "ssa_reconstruct_batch_dev")
+
+    # ---- serving -------------------------------------------------------
+
+    @staticmethod
+    def _groups(groups):
+        if not groups:
+            return None, None, 0
+        gp = np.zeros(len(groups) + 1, np.int32)
+        gp[1:] = np.cumsum([len(g) for g in groups])
+        gi = np.ascontiguousarray(np.concatenate([np.asarray(g, np.int32) for g in groups]))
+        return gp, gi, len(groups)
+
+    def submit(self, x, window=None, r: int = 10, mask=None, wmask=None, precision="fp64", groups=None) -> int:
+        """Queue a decomposition (+ reconstruction of ``groups``); returns a ticket."""
+        x, lx, ly, mask, wmask = self._image_args(x, window, mask, wmask)
+        gp, gi, ng = self._groups(groups)
+        req = _native.Request(x.ctypes.data, x.shape[0], x.shape[1], _ptr(mask), _ptr(wmask), lx, ly, int(r),
+                              _prec(precision), 0x5EED)
+        t = C.c_uint64()
+        check(lib().ssa_submit(self._h, C.byref(req), _ptr(gp), _ptr(gi), ng, C.byref(t)), "ssa_submit")
+        return t.value
+
+    def submit_multi(self, series, L: int, r: int, precision="fp64", groups=None) -> int:
+        """Queue an MSSA request; returns a ticket."""
+        arrs = [np.ascontiguousarray(s, dtype=np.float64) for s in series]
+        ptrs = (C.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+        lens = np.array([len(a) for a in arrs], np.int32)
+        gp, gi, ng = self._groups(groups)
+        t = C.c_uint64()
+        check(lib().ssa_submit_multi(self._h, ptrs, _ptr(lens), len(arrs), int(L), int(r), _prec(precision),
+                                     _ptr(gp), _ptr(gi), ng, C.byref(t)), "ssa_submit_multi")
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        done = C.c_int()
+        check(lib().ssa_poll(self._h, ticket, C.byref(done)), "ssa_poll")
+        return bool(done.value)
+
+    def wait(self, ticket: int):
+        check(lib().ssa_wait(self._h, ticket), "ssa_wait")
+
+    def take(self, ticket: int, shape=None, ngroups: int = 0):
+        """Finish a request: (Decomposition or SsaError, reconstruction or
+        None, {queue_ms, total_ms}).  ``shape`` (nx, ny) and ``ngroups`` size
+        the reconstruction buffer."""
+        h = C.c_void_p()
+        tm = _native.Times()
+        rec = np.zeros((ngroups,) + tuple(shape)) if (ngroups and shape is not None) else None
+        rc = lib().ssa_take(self._h, ticket, C.byref(h), _ptr(rec), C.byref(tm))
+        times = {"queue_ms": tm.queue_ms, "total_ms": tm.total_ms}
+        if rc == _native.SSA_EBUSY:
+            raise SsaError(rc, "request not finished")
+        if h.value:
+            d = Decomposition(self, h.value)
+            d.status = rc
+            return d, rec, times
+        return SsaError(rc, lib().ssa_last_error().decode()), None, times

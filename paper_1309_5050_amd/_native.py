@@ -29,6 +29,10 @@ class Stats(C.Structure):
                 ("ms_lanczos", C.c_double), ("ms_finish", C.c_double), ("device_bytes", C.c_size_t)]
 
 
+class Times(C.Structure):
+    _fields_ = [("queue_ms", C.c_double), ("total_ms", C.c_double)]
+
+
 _lib = None
 
 _SIGS = {
@@ -58,6 +62,13 @@ _SIGS = {
     "ssa_reconstruct_batch_dev": (C.c_int, [C.c_int, C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.c_int,
                                             C.POINTER(C.c_void_p)]),
     "ssa_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
+    "ssa_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.c_void_p, C.c_void_p, C.c_int,
+                             C.POINTER(C.c_uint64)]),
+    "ssa_submit_multi": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p, C.c_int, C.c_int, C.c_int,
+                                   C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_uint64)]),
+    "ssa_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int)]),
+    "ssa_wait": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "ssa_take": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_void_p), C.c_void_p, C.POINTER(Times)]),
     "ssa_free": (None, [C.c_void_p]),
     "ssa_strerror": (C.c_char_p, [C.c_int]),
     "ssa_last_error": (C.c_char_p, []),

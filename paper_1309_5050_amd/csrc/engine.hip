@@ -7,6 +7,8 @@
 // drop out at the next cycle boundary).
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -16,6 +18,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -89,8 +92,11 @@ bool make_plan(int n, FftPlan& pl) {
 // context
 // ---------------------------------------------------------------------------
 
+struct Server;   // serving state (asynchronous requests), created on first submit
+
 struct ssa_ctx {
     int device = 0;
+    Server* srv = nullptr;
     int refs = 0;            // live decompositions (guarded by mu)
     bool closing = false;    // ssa_ctx_destroy called; delete when refs drops to 0
     hipStream_t st = nullptr;
@@ -100,6 +106,13 @@ struct ssa_ctx {
     std::mutex mu;
     std::map<std::tuple<int, int, int>, void*> tw;   // (n, f64, real split) -> table
     std::map<std::pair<int, int>, int> col_tc;       // (f64, MA) -> tuned column tile
+    std::mutex tune_mu;                               // one tuning at a time; guards col_tc
+
+    int tile_for(bool f64, int MA) {
+        std::lock_guard<std::mutex> g(tune_mu);
+        auto it = col_tc.find(std::make_pair((int)f64, MA));
+        return it != col_tc.end() ? it->second : col_tile(f64);
+    }
     // kernel timing (see ssa_ctx_profile)
     std::string prof_kind;
     std::vector<hipEvent_t> ev_pool;
@@ -107,16 +120,18 @@ struct ssa_ctx {
     double prof_bytes = 0.0;
     long prof_launches = 0;
 
+    // next unused event of the pool (caller holds mu); reset by profile_read
+    int ev_next = 0;
     int prof_event() {
-        const int k = (int)(spans.size() * 2 + (ev_pending ? 1 : 0));
+        const int k = ev_next;
         while ((int)ev_pool.size() <= k) {
             hipEvent_t e;
             if (hipEventCreate(&e) != hipSuccess) return -1;
             ev_pool.push_back(e);
         }
+        ++ev_next;
         return k;
     }
-    bool ev_pending = false;
 
     // Device memory pool: freed blocks are kept per size class and handed
     // out again, so steady-state work never calls hipMalloc/hipFree (hipFree
@@ -164,17 +179,19 @@ struct ssa_ctx {
         pooled += cls;
     }
 
-    // Pinned host staging for uploads.  Two halves are filled in turn; a half
-    // is refilled only after the copies issued from it have completed (an
-    // event recorded when it was left), so hipMemcpyAsync from it never
-    // blocks the host and never reads overwritten data.  Caller holds mu.
+    // Pinned host staging for uploads, one per stream.  Two halves are
+    // filled in turn; a half is refilled only after the copies issued from it
+    // have completed (an event recorded when it was left), so hipMemcpyAsync
+    // from it never blocks the host and never reads overwritten data.
     static constexpr size_t kStageHalf = 8u << 20;
-    char* stg = nullptr;
-    size_t stg_head = 0;
-    int stg_cur = 0;
-    hipEvent_t stg_ev[2] = {nullptr, nullptr};
-    bool stg_pending[2] = {false, false};
-    hipStream_t stg_st = nullptr;
+    struct Stage {
+        char* buf = nullptr;
+        size_t head = 0;
+        int cur = 0;
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        bool pending[2] = {false, false};
+    };
+    std::map<hipStream_t, Stage> stages;   // guarded by mu
 
     int upload_locked(void* dst, const void* src, size_t n, hipStream_t s) {
         if (n == 0) return SSA_OK;
@@ -185,30 +202,25 @@ struct ssa_ctx {
             HIPCHK(hipStreamSynchronize(s));
             return SSA_OK;
         }
-        if (!stg) {
-            HIPCHK(hipHostMalloc((void**)&stg, 2 * kStageHalf, hipHostMallocDefault));
-            HIPCHK(hipEventCreateWithFlags(&stg_ev[0], hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&stg_ev[1], hipEventDisableTiming));
+        Stage& g = stages[s];
+        if (!g.buf) {
+            HIPCHK(hipHostMalloc((void**)&g.buf, 2 * kStageHalf, hipHostMallocDefault));
+            HIPCHK(hipEventCreateWithFlags(&g.ev[0], hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&g.ev[1], hipEventDisableTiming));
         }
-        if (stg_st && stg_st != s) {
-            // copies of the other stream must be done before its slots are reused
-            HIPCHK(hipStreamSynchronize(stg_st));
-            stg_pending[0] = stg_pending[1] = false;
-        }
-        stg_st = s;
-        if (stg_head + need > kStageHalf) {
-            HIPCHK(hipEventRecord(stg_ev[stg_cur], s));
-            stg_pending[stg_cur] = true;
-            stg_cur ^= 1;
-            stg_head = 0;
-            if (stg_pending[stg_cur]) {
-                HIPCHK(hipEventSynchronize(stg_ev[stg_cur]));
-                stg_pending[stg_cur] = false;
+        if (g.head + need > kStageHalf) {
+            HIPCHK(hipEventRecord(g.ev[g.cur], s));
+            g.pending[g.cur] = true;
+            g.cur ^= 1;
+            g.head = 0;
+            if (g.pending[g.cur]) {
+                HIPCHK(hipEventSynchronize(g.ev[g.cur]));
+                g.pending[g.cur] = false;
             }
         }
-        char* h = stg + (size_t)stg_cur * kStageHalf + stg_head;
+        char* h = g.buf + (size_t)g.cur * kStageHalf + g.head;
         std::memcpy(h, src, n);
-        stg_head += need;
+        g.head += need;
         HIPCHK(hipMemcpyAsync(dst, h, n, hipMemcpyHostToDevice, s));
         return SSA_OK;
     }
@@ -216,30 +228,51 @@ struct ssa_ctx {
         std::lock_guard<std::mutex> g(mu);
         return upload_locked(dst, src, n, s);
     }
-    void stage_free() {
-        if (stg) (void)hipHostFree(stg);
-        for (auto e : stg_ev)
+    // A stream is about to be destroyed: wait for its copies, drop its stage.
+    void stage_drop(hipStream_t s) {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = stages.find(s);
+        if (it == stages.end()) return;
+        (void)hipStreamSynchronize(s);
+        if (it->second.buf) (void)hipHostFree(it->second.buf);
+        for (auto e : it->second.ev)
             if (e) (void)hipEventDestroy(e);
-        stg = nullptr;
+        stages.erase(it);
+    }
+    void stage_free() {
+        for (auto& kv : stages) {
+            if (kv.second.buf) (void)hipHostFree(kv.second.buf);
+            for (auto e : kv.second.ev)
+                if (e) (void)hipEventDestroy(e);
+        }
+        stages.clear();
     }
 
-    // Pinned host buffer for batched readbacks (grown on demand).
-    void* rb = nullptr;
-    size_t rb_cap = 0;
-    int readback_buf(size_t n, void** out) {
-        if (n > rb_cap) {
-            if (rb) (void)hipHostFree(rb);
-            rb = nullptr;
-            rb_cap = 0;
-            HIPCHK(hipHostMalloc(&rb, n, hipHostMallocDefault));
-            rb_cap = n;
+    // Pinned host buffers for batched readbacks, one per stream (grown on
+    // demand; a stream's readbacks are synchronous, so one buffer suffices).
+    std::map<hipStream_t, std::pair<void*, size_t>> rbs;   // guarded by mu
+    int readback_buf(hipStream_t s, size_t n, void** out) {
+        std::lock_guard<std::mutex> g(mu);
+        auto& rb = rbs[s];
+        if (n > rb.second) {
+            if (rb.first) (void)hipHostFree(rb.first);
+            rb.first = nullptr;
+            rb.second = 0;
+            HIPCHK(hipHostMalloc(&rb.first, n, hipHostMallocDefault));
+            rb.second = n;
         }
-        *out = rb;
+        *out = rb.first;
         return SSA_OK;
+    }
+    void readback_free() {
+        for (auto& kv : rbs)
+            if (kv.second.first) (void)hipHostFree(kv.second.first);
+        rbs.clear();
     }
 
     // twiddles exp(-2 pi i t / N) for t = 0..cnt-1 (N = n, or 2n for the split)
     int twiddles(int n, bool f64, bool split, const void** out) {
+        std::lock_guard<std::mutex> lock(mu);
         auto key = std::make_tuple(n, (int)f64, (int)split);
         auto it = tw.find(key);
         if (it != tw.end()) {
@@ -347,7 +380,7 @@ void ctx_release(ssa_ctx* ctx) {
     for (auto& kv : ctx->pool)
         for (void* q : kv.second) (void)hipFree(q);
     ctx->stage_free();
-    if (ctx->rb) (void)hipHostFree(ctx->rb);
+    ctx->readback_free();
     if (ctx->own) (void)hipStreamDestroy(ctx->st);
     delete ctx;
 }
@@ -541,6 +574,39 @@ int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStrea
 // ---------------------------------------------------------------------------
 
 thread_local ssa_ctx* g_tables_ctx = nullptr;   // pool that small batch tables come from
+// Table blocks released by a serving worker stay with that worker (its
+// stream may still read them) until the worker has synchronised its stream;
+// then flush_table_cache returns them to the context pool.
+thread_local std::vector<std::pair<void*, size_t>>* g_table_cache = nullptr;
+
+void flush_table_cache(ssa_ctx* ctx) {
+    if (!g_table_cache) return;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    for (auto& b : *g_table_cache) ctx->pool_put(b.first, b.second);
+    g_table_cache->clear();
+}
+
+// Scope of a synchronous library call on stream st: table blocks released
+// inside it return to the shared pool only after st has drained (serving
+// workers on other streams share the pool).
+struct TableScope {
+    ssa_ctx* ctx;
+    hipStream_t st;
+    std::vector<std::pair<void*, size_t>> cache;
+    bool owner = false;
+    TableScope(ssa_ctx* c, hipStream_t s) : ctx(c), st(s) {
+        if (!g_table_cache) {
+            g_table_cache = &cache;
+            owner = true;
+        }
+    }
+    ~TableScope() {
+        if (!owner) return;
+        (void)hipStreamSynchronize(st);
+        flush_table_cache(ctx);
+        g_table_cache = nullptr;
+    }
+};
 
 // A small device table filled from the host (descriptor arrays, item lists).
 struct DevVec {
@@ -550,8 +616,12 @@ struct DevVec {
     ~DevVec() { release(); }
     void release() {
         if (!p) return;
-        std::lock_guard<std::mutex> g(ctx->mu);
-        ctx->pool_put(p, cap);
+        if (g_table_cache) {
+            g_table_cache->push_back({p, cap});
+        } else {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            ctx->pool_put(p, cap);
+        }
         p = nullptr;
         cap = 0;
     }
@@ -560,8 +630,18 @@ struct DevVec {
         const size_t b = ssa_ctx::size_class(std::max<size_t>(v.size(), 1) * sizeof(T));
         if (b > cap) {
             release();
-            std::lock_guard<std::mutex> g(ctx->mu);
-            p = ctx->pool_get(b);
+            if (g_table_cache) {
+                for (size_t k = 0; k < g_table_cache->size(); ++k)
+                    if ((*g_table_cache)[k].second == b) {
+                        p = (*g_table_cache)[k].first;
+                        g_table_cache->erase(g_table_cache->begin() + k);
+                        break;
+                    }
+            }
+            if (!p) {
+                std::lock_guard<std::mutex> g(ctx->mu);
+                p = ctx->pool_get(b);
+            }
             if (!p) return fail(SSA_ENOMEM, "hipMalloc (batch tables)");
             cap = b;
         }
@@ -593,6 +673,7 @@ struct Batch {
     DevVec dflag, dbeta;
 
     explicit Batch(ssa_ctx* c) : ctx(c), st(c->st) {}
+    Batch(ssa_ctx* c, hipStream_t s) : ctx(c), st(s) {}
 
     int upload_descs() {
         hops.clear(); hlz.clear(); hres.clear(); hruns.clear();
@@ -621,23 +702,24 @@ struct ProfSpan {
     hipStream_t st;
     bool on = false;
     int e0 = -1;
+    int e1 = -1;
     ProfSpan(ssa_ctx* ctx, const char* kind, hipStream_t s, double bytes) : c(ctx), st(s) {
+        std::lock_guard<std::mutex> g(c->mu);
         if (c->prof_kind.empty() || c->prof_kind != kind) return;
+        // both events are taken now, so spans of concurrent threads never share one
         e0 = c->prof_event();
-        if (e0 < 0) return;
-        c->ev_pending = true;
+        e1 = e0 >= 0 ? c->prof_event() : -1;
+        if (e1 < 0) return;
         (void)hipEventRecord(c->ev_pool[e0], st);
+        c->spans.push_back({e0, e1});
         c->prof_bytes += bytes;
         c->prof_launches += 1;
         on = true;
     }
     ~ProfSpan() {
         if (!on) return;
-        const int e1 = c->prof_event();
-        c->ev_pending = false;
-        if (e1 < 0) return;
+        std::lock_guard<std::mutex> g(c->mu);
         (void)hipEventRecord(c->ev_pool[e1], st);
-        c->spans.push_back({e0, e1});
     }
 };
 
@@ -737,6 +819,7 @@ int run_setup(Batch& b) {
 // with every compiled tile width and keeps the fastest for the context.  The
 // spectrum pass itself is idempotent.  SHSSA_COL_TILE forces a width.
 int tune_col_tile(Batch& b) {
+    std::lock_guard<std::mutex> tune_lock(b.ctx->tune_mu);
     const auto* d0 = b.ds[0];
     const auto key = std::make_pair((int)b.f64, d0->MA);
     if (const char* e = std::getenv("SHSSA_COL_TILE")) {
@@ -1044,7 +1127,7 @@ int run_lanczos(Batch& b, int max_steps) {
             char* dv = b.dflag.as<char>();
             launch_gather_flags(ni, st, b.lzs(), reinterpret_cast<int*>(dv), reinterpret_cast<double*>(dv + fb));
             void* hb = nullptr;
-            if ((rc = b.ctx->readback_buf(fb + bb, &hb))) return rc;
+            if ((rc = b.ctx->readback_buf(st, fb + bb, &hb))) return rc;
             HIPCHK(hipMemcpyAsync(hb, dv, fb + bb, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             std::memcpy(flags.data(), hb, fb);
@@ -1198,7 +1281,7 @@ int run_finish(Batch& b) {
         }
         launch_gather_sigma(ni, r, st, b.res(), b.dbeta.as<double>());
         void* hb = nullptr;
-        if ((rc = b.ctx->readback_buf(nb, &hb))) return rc;
+        if ((rc = b.ctx->readback_buf(st, nb, &hb))) return rc;
         HIPCHK(hipMemcpyAsync(hb, b.dbeta.p, nb, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         for (int i = 0; i < ni; ++i) {
@@ -1277,9 +1360,58 @@ GeoKey geo_key(const ssa_decomp* d) {
                   (int)d->L};
 }
 
+// Decompose planned and uploaded instances of one geometry group on stream
+// st (setup, spectrum, bidiagonalisation, other-side vectors).  st[i]
+// receives each instance's status.
+void run_planned(ssa_ctx* ctx, const std::vector<ssa_decomp*>& grp, hipStream_t stream, std::vector<int>& st) {
+    const int n = (int)grp.size();
+    st.assign(n, SSA_OK);
+    if (n == 0) return;
+    Batch b(ctx, stream);
+    b.ds = grp;
+    b.f64 = b.ds[0]->f64;
+    b.rowfam = b.ds[0]->rowfam;
+    b.cls = row_word(b.ds[0]->nh, b.f64);
+    b.TC = ctx->tile_for(b.f64, b.ds[0]->MA);
+    auto t0 = Clock::now();
+    int rc = run_setup(b);
+    if (rc) {
+        st.assign(n, rc);
+        return;
+    }
+    // drop instances whose shapes failed
+    std::vector<ssa_decomp*> ok;
+    for (int i = 0; i < n; ++i) {
+        if (grp[i]->status != SSA_OK) st[i] = grp[i]->status;
+        else ok.push_back(grp[i]);
+    }
+    if (ok.empty()) return;
+    b.ds = ok;
+    rc = run_alloc_spectrum(b);
+    if (!rc) (void)hipStreamSynchronize(stream);
+    const double t_setup = ms_since(t0);
+    auto t1 = Clock::now();
+    if (!rc) rc = run_lanczos(b, 3000);
+    const double t_lz = ms_since(t1);
+    auto t2 = Clock::now();
+    if (!rc) rc = run_finish(b);
+    const double t_fin = ms_since(t2);
+    for (auto* d : b.ds) {
+        d->st.ms_setup = t_setup / b.ds.size();
+        d->st.ms_lanczos = t_lz / b.ds.size();
+        d->st.ms_finish = t_fin / b.ds.size();
+        d->st.side = d->side;
+    }
+    for (int i = 0; i < n; ++i) {
+        if (rc) st[i] = rc;
+        else if (grp[i]->status != SSA_OK && st[i] == SSA_OK) st[i] = grp[i]->status;
+    }
+}
+
 int decompose_many(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** out, int* status, bool dev) {
     if (!ctx || n < 0 || (n > 0 && (!reqs || !out))) return fail(SSA_EINVAL, "bad arguments");
     g_tables_ctx = ctx;
+    TableScope tables(ctx, ctx->st);
     std::vector<std::unique_ptr<ssa_decomp>> ds(n);
     std::vector<int> st(n, SSA_OK);
     std::map<GeoKey, std::vector<int>> groups;
@@ -1291,49 +1423,11 @@ int decompose_many(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** ou
         if (st[i] == SSA_OK) groups[geo_key(ds[i].get())].push_back(i);
     }
     for (auto& kv : groups) {
-        Batch b(ctx);
-        for (int i : kv.second) b.ds.push_back(ds[i].get());
-        b.f64 = b.ds[0]->f64;
-        b.rowfam = b.ds[0]->rowfam;
-        b.cls = row_word(b.ds[0]->nh, b.f64);
-        b.TC = col_tile(b.f64);
-        {
-            auto it = ctx->col_tc.find(std::make_pair((int)b.f64, b.ds[0]->MA));
-            if (it != ctx->col_tc.end()) b.TC = it->second;
-        }
-        auto t0 = Clock::now();
-        int rc = run_setup(b);
-        if (rc) {
-            for (int i : kv.second) st[i] = rc;
-            continue;
-        }
-        // drop instances whose shapes failed
-        std::vector<ssa_decomp*> ok;
-        for (int i : kv.second) {
-            if (ds[i]->status != SSA_OK) st[i] = ds[i]->status;
-            else ok.push_back(ds[i].get());
-        }
-        if (ok.empty()) continue;
-        b.ds = ok;
-        rc = run_alloc_spectrum(b);
-        if (!rc) (void)hipStreamSynchronize(ctx->st);
-        const double t_setup = ms_since(t0);
-        auto t1 = Clock::now();
-        if (!rc) rc = run_lanczos(b, 3000);
-        const double t_lz = ms_since(t1);
-        auto t2 = Clock::now();
-        if (!rc) rc = run_finish(b);
-        const double t_fin = ms_since(t2);
-        for (auto* d : b.ds) {
-            d->st.ms_setup = t_setup / b.ds.size();
-            d->st.ms_lanczos = t_lz / b.ds.size();
-            d->st.ms_finish = t_fin / b.ds.size();
-            d->st.side = d->side;
-        }
-        for (int i : kv.second) {
-            if (rc) st[i] = rc;
-            else if (ds[i]->status != SSA_OK && st[i] == SSA_OK) st[i] = ds[i]->status;
-        }
+        std::vector<ssa_decomp*> grp;
+        for (int i : kv.second) grp.push_back(ds[i].get());
+        std::vector<int> gst;
+        run_planned(ctx, grp, ctx->st, gst);
+        for (size_t k = 0; k < kv.second.size(); ++k) st[kv.second[k]] = gst[k];
     }
     for (int i = 0; i < n; ++i) {
         if (status) status[i] = st[i];
@@ -1366,6 +1460,240 @@ void walk_set(const ssa_decomp* d, int BA, int BB, const uint8_t* mask, F fn) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// serving: asynchronous requests, admission, batching over several streams
+// ---------------------------------------------------------------------------
+
+// One submitted request.  The inputs are copied at submission; the handle
+// is planned (host-only) at once so that admission and batching know its
+// geometry and size.
+struct ServeReq {
+    uint64_t ticket = 0;
+    std::vector<double> x;
+    std::vector<uint8_t> mask, wmask;
+    ssa_request q{};
+    std::vector<int> gp, gi;
+    std::unique_ptr<ssa_decomp> d;
+    size_t est = 0;
+    GeoKey key;
+    double t_submit = 0.0, t_start = 0.0, t_done = 0.0;   // ms since the server started
+    int status = SSA_EBUSY;   // written by the worker while it runs the request
+    bool done = false;        // set under the server lock once the request has finished
+    std::vector<double> recon;   // ngroups x nx x ny (caller layout) once done
+};
+
+struct Server {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<std::shared_ptr<ServeReq>> pending;
+    std::map<uint64_t, std::shared_ptr<ServeReq>> reqs;   // until taken
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> streams;
+    Clock::time_point t0 = Clock::now();
+    uint64_t next = 1;
+    size_t reserved = 0;      // admitted estimates not yet released
+    int running = 0;          // batches in flight
+    int max_batch = 64;
+    bool stop = false;
+    double now() const { return ms_since(t0); }
+};
+
+// Device bytes one request will hold while it runs (an upper bound: the
+// origin box stands in for the origin set, plus size-class slack).
+size_t estimate_bytes(const ssa_decomp* d, int ngroups) {
+    const double n = (double)d->A * d->B, ce = d->f64 ? 16.0 : 8.0;
+    const double kbox = (double)d->KA * d->KB, L = (double)d->L;
+    const double nshort = std::min(L, kbox), nlong = std::max(L, kbox);
+    const double nslot = std::max(1, d->r);
+    const double xh = d->rowfam ? (double)d->A * d->ldp : (double)d->ldp * d->MA;
+    const double us = d->rowfam ? (double)d->P : (double)d->P * d->MA;
+    double b = 27.0 * n + 5.0 * kbox + 5.0 * d->LA * d->LB;           // x, masks, xc, W, prefix sums
+    b += xh * ce + 2.0 * d->A * d->ldp * ce * nslot + us * ce * nslot;  // spectrum, row/column slots
+    b += 2.0 * nlong * (d->f64 ? 8.0 : 4.0);                            // long vectors
+    b += nshort * (2.0 * kMaxBasis + 4.0) * 8.0;                        // basis, rotation scratch, w
+    b += (L + kbox) * d->r * 8.0;                                       // U, V
+    b += (double)ngroups * n * 8.0;                                     // reconstruction
+    return (size_t)(1.3 * b) + (4u << 20);
+}
+
+Batch make_batch(ssa_ctx* ctx, hipStream_t st, const std::vector<ssa_decomp*>& ds) {
+    Batch b(ctx, st);
+    b.ds = ds;
+    b.f64 = ds[0]->f64;
+    b.rowfam = ds[0]->rowfam;
+    b.cls = row_word(ds[0]->nh, b.f64);
+    b.TC = ctx->tile_for(b.f64, ds[0]->MA);
+    return b;
+}
+
+// Decompose and reconstruct one batch of requests of equal geometry on
+// stream st; results land in the requests.
+void serve_batch(ssa_ctx* ctx, std::vector<std::shared_ptr<ServeReq>>& batch, hipStream_t st) {
+    std::vector<ssa_decomp*> grp;
+    std::vector<ServeReq*> live;
+    for (auto& r : batch) {
+        r->status = upload_request(r->q, r->d.get(), false, st);
+        if (r->status == SSA_OK) {
+            grp.push_back(r->d.get());
+            live.push_back(r.get());
+        }
+    }
+    std::vector<int> gst;
+    run_planned(ctx, grp, st, gst);
+    // reconstructions, one launch sequence per distinct group list
+    std::vector<ServeReq*> ok;
+    for (size_t k = 0; k < live.size(); ++k) {
+        live[k]->status = gst[k];
+        if (gst[k] == SSA_OK && live[k]->gp.size() > 1) ok.push_back(live[k]);
+    }
+    std::vector<char> done(ok.size(), 0);
+    for (size_t a = 0; a < ok.size(); ++a) {
+        if (done[a]) continue;
+        std::vector<ServeReq*> same;
+        for (size_t c = a; c < ok.size(); ++c)
+            if (!done[c] && ok[c]->gp == ok[a]->gp && ok[c]->gi == ok[a]->gi) {
+                same.push_back(ok[c]);
+                done[c] = 1;
+            }
+        const int ng = (int)same[0]->gp.size() - 1;
+        std::vector<ssa_decomp*> ds;
+        std::vector<double*> bufs;
+        int rc = SSA_OK;
+        for (auto* r : same) {
+            double* buf = nullptr;
+            if ((rc = r->d->dalloc(&buf, (long)ng * r->d->A * r->d->B))) break;
+            ds.push_back(r->d.get());
+            bufs.push_back(buf);
+        }
+        if (!rc) {
+            Batch b = make_batch(ctx, st, ds);
+            rc = run_reconstruct(b, same[0]->gp, same[0]->gi, bufs);
+        }
+        for (size_t k = 0; k < same.size(); ++k) {
+            ServeReq* r = same[k];
+            if (rc || k >= bufs.size()) {
+                r->status = rc ? rc : SSA_ENOMEM;
+                continue;
+            }
+            const ssa_decomp* d = r->d.get();
+            const long n = (long)d->A * d->B;
+            std::vector<double> t((size_t)n * ng);
+            if (hipMemcpyAsync(t.data(), bufs[k], t.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                r->status = fail(SSA_EDEVICE, "reconstruction copy");
+                continue;
+            }
+            r->recon.resize(t.size());
+            if (!d->tr) {
+                r->recon.swap(t);
+            } else {
+                for (int g = 0; g < ng; ++g)
+                    for (int a2 = 0; a2 < d->A; ++a2)
+                        for (int b2 = 0; b2 < d->B; ++b2)
+                            r->recon[g * n + (long)b2 * d->A + a2] = t[g * n + (long)a2 * d->B + b2];
+            }
+        }
+    }
+    (void)hipStreamSynchronize(st);
+}
+
+// Admission: the oldest request starts when its estimate fits the budget
+// beside the running batches (a request that cannot fit even alone is
+// refused at submission); compatible waiting requests join its batch.
+bool serve_can_start(const Server& s, size_t budget) {
+    if (s.pending.empty()) return false;
+    return budget == 0 || s.running == 0 || s.reserved + s.pending.front()->est <= budget;
+}
+
+void serve_worker(ssa_ctx* ctx, int w) {
+    Server& S = *ctx->srv;
+    (void)hipSetDevice(ctx->device);
+    g_tables_ctx = ctx;
+    std::vector<std::pair<void*, size_t>> cache;
+    g_table_cache = &cache;
+    const hipStream_t st = S.streams[w];
+    for (;;) {
+        std::vector<std::shared_ptr<ServeReq>> batch;
+        size_t est = 0;
+        {
+            std::unique_lock<std::mutex> lk(S.mu);
+            S.cv.wait(lk, [&] { return S.stop || serve_can_start(S, ctx->budget); });
+            if (S.stop) break;
+            auto r0 = S.pending.front();
+            S.pending.pop_front();
+            batch.push_back(r0);
+            est = r0->est;
+            for (auto it = S.pending.begin(); it != S.pending.end() && (int)batch.size() < S.max_batch;) {
+                if ((*it)->key == r0->key && (ctx->budget == 0 || S.reserved + est + (*it)->est <= ctx->budget)) {
+                    est += (*it)->est;
+                    batch.push_back(*it);
+                    it = S.pending.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+            S.reserved += est;
+            S.running++;
+            const double t = S.now();
+            for (auto& r : batch) r->t_start = t;
+        }
+        serve_batch(ctx, batch, st);
+        flush_table_cache(ctx);
+        {
+            std::lock_guard<std::mutex> lk(S.mu);
+            S.reserved -= est;
+            S.running--;
+            const double t = S.now();
+            for (auto& r : batch) {
+                r->t_done = t;
+                if (r->status == SSA_EBUSY) r->status = SSA_EDEVICE;
+                r->done = true;
+            }
+        }
+        S.cv.notify_all();
+    }
+    flush_table_cache(ctx);
+    g_table_cache = nullptr;
+}
+
+int serve_start(ssa_ctx* ctx) {
+    if (ctx->srv) return SSA_OK;
+    auto* S = new Server();
+    int nw = 3;
+    if (const char* e = std::getenv("SHSSA_SERVE_WORKERS")) nw = std::max(1, std::min(8, std::atoi(e)));
+    for (int w = 0; w < nw; ++w) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            for (auto x : S->streams) (void)hipStreamDestroy(x);
+            delete S;
+            return fail(SSA_EDEVICE, "stream creation failed");
+        }
+        S->streams.push_back(s);
+    }
+    ctx->srv = S;
+    for (int w = 0; w < nw; ++w) S->workers.emplace_back(serve_worker, ctx, w);
+    return SSA_OK;
+}
+
+void serve_stop(ssa_ctx* ctx) {
+    Server* S = ctx->srv;
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    for (auto& t : S->workers) t.join();
+    S->pending.clear();
+    S->reqs.clear();   // frees the handles of requests never taken
+    for (auto s : S->streams) {
+        ctx->stage_drop(s);
+        (void)hipStreamDestroy(s);
+    }
+    ctx->srv = nullptr;
+    delete S;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 
@@ -1373,6 +1701,7 @@ extern "C" {
 
 int ssa_ctx_profile(ssa_ctx* ctx, const char* kind) {
     if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> g(ctx->mu);
     ctx->prof_kind = kind ? kind : "";
     return SSA_OK;
 }
@@ -1380,9 +1709,11 @@ int ssa_ctx_profile(ssa_ctx* ctx, const char* kind) {
 int ssa_ctx_profile_read(ssa_ctx* ctx, double* ms, long* launches, double* bytes) {
     if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
     HIPCHK(hipStreamSynchronize(ctx->st));
+    std::lock_guard<std::mutex> g(ctx->mu);
     double tot = 0.0;
     for (auto& sp : ctx->spans) {
         float t = 0.f;
+        HIPCHK(hipEventSynchronize(ctx->ev_pool[sp.second]));
         HIPCHK(hipEventElapsedTime(&t, ctx->ev_pool[sp.first], ctx->ev_pool[sp.second]));
         tot += t;
     }
@@ -1390,6 +1721,7 @@ int ssa_ctx_profile_read(ssa_ctx* ctx, double* ms, long* launches, double* bytes
     if (launches) *launches = ctx->prof_launches;
     if (bytes) *bytes = ctx->prof_bytes;
     ctx->spans.clear();
+    ctx->ev_next = 0;
     ctx->prof_bytes = 0.0;
     ctx->prof_launches = 0;
     return SSA_OK;
@@ -1420,6 +1752,7 @@ int ssa_ctx_create(int device, size_t mem_budget, void* stream, ssa_ctx** out) {
 
 void ssa_ctx_destroy(ssa_ctx* ctx) {
     if (!ctx) return;
+    serve_stop(ctx);
     bool now = false;
     {
         std::lock_guard<std::mutex> g(ctx->mu);
@@ -1610,6 +1943,7 @@ int ssa_reconstruct(ssa_decomp* d, const int* gp, const int* gi, int ng, double*
     if (rc) return rc;
     const long n = (long)d->A * d->B;
     g_tables_ctx = d->ctx;
+    TableScope tables(d->ctx, d->ctx->st);
     double* buf = nullptr;
     HIPCHK(hipMalloc(&buf, n * ng * 8));
     Batch b(d->ctx);
@@ -1617,11 +1951,7 @@ int ssa_reconstruct(ssa_decomp* d, const int* gp, const int* gi, int ng, double*
     b.f64 = d->f64;
     b.rowfam = d->rowfam;
     b.cls = row_word(d->nh, d->f64);
-    b.TC = col_tile(d->f64);
-    {
-        auto it = d->ctx->col_tc.find(std::make_pair((int)d->f64, d->MA));
-        if (it != d->ctx->col_tc.end()) b.TC = it->second;
-    }
+    b.TC = d->ctx->tile_for(d->f64, d->MA);
     rc = run_reconstruct(b, std::vector<int>(gp, gp + ng + 1), std::vector<int>(gi, gi + gp[ng]), {buf});
     if (!rc) {
         if (!d->tr) {
@@ -1650,16 +1980,13 @@ int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* gp, const 
     int rc = check_groups(d[0], gp, gi, ng);
     if (rc) return rc;
     g_tables_ctx = d[0]->ctx;
+    TableScope tables(d[0]->ctx, d[0]->ctx->st);
     Batch b(d[0]->ctx);
     b.ds.assign(d, d + n);
     b.f64 = d[0]->f64;
     b.rowfam = d[0]->rowfam;
     b.cls = row_word(d[0]->nh, d[0]->f64);
-    b.TC = col_tile(d[0]->f64);
-    {
-        auto it = d[0]->ctx->col_tc.find(std::make_pair((int)d[0]->f64, d[0]->MA));
-        if (it != d[0]->ctx->col_tc.end()) b.TC = it->second;
-    }
+    b.TC = d[0]->ctx->tile_for(d[0]->f64, d[0]->MA);
     return run_reconstruct(b, std::vector<int>(gp, gp + ng + 1), std::vector<int>(gi, gi + gp[ng]),
                            std::vector<double*>(out_dev, out_dev + n));
 }
@@ -1672,6 +1999,115 @@ int ssa_get_stats(const ssa_decomp* d, ssa_stats* st) {
 }
 
 void ssa_free(ssa_decomp* d) { delete d; }
+
+int ssa_submit(ssa_ctx* ctx, const ssa_request* req, const int* grp_ptr, const int* grp_idx, int ngroups,
+               uint64_t* ticket) {
+    if (!ctx || !req || !ticket) return fail(SSA_EINVAL, "NULL argument");
+    if (!req->x || req->nx <= 0 || req->ny <= 0) return fail(SSA_EINVAL, "sizes must be positive");
+    if (ngroups < 0 || (ngroups > 0 && (!grp_ptr || !grp_idx))) return fail(SSA_EINVAL, "bad groups");
+    auto r = std::make_shared<ServeReq>();
+    const size_t n = (size_t)req->nx * req->ny;
+    r->x.assign(req->x, req->x + n);
+    r->q = *req;
+    r->q.x = r->x.data();
+    if (req->mask) {
+        r->mask.assign(req->mask, req->mask + n);
+        r->q.mask = r->mask.data();
+    }
+    if (req->wmask) {
+        r->wmask.assign(req->wmask, req->wmask + (size_t)req->lx * req->ly);
+        r->q.wmask = r->wmask.data();
+    }
+    if (ngroups > 0) {
+        r->gp.assign(grp_ptr, grp_ptr + ngroups + 1);
+        r->gi.assign(grp_idx, grp_idx + grp_ptr[ngroups]);
+    }
+    r->d.reset(new ssa_decomp());
+    int rc = plan_request(ctx, r->q, r->d.get());
+    if (rc) return rc;
+    if (ngroups > 0 && (rc = check_groups(r->d.get(), r->gp.data(), r->gi.data(), ngroups))) return rc;
+    r->key = geo_key(r->d.get());
+    r->est = estimate_bytes(r->d.get(), ngroups);
+    if (ctx->budget && r->est > ctx->budget)
+        return fail(SSA_ENOMEM, "request larger than the context's memory budget");
+    if ((rc = serve_start(ctx))) return rc;
+    Server& S = *ctx->srv;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        r->ticket = S.next++;
+        r->t_submit = S.now();
+        S.reqs[r->ticket] = r;
+        S.pending.push_back(r);
+        *ticket = r->ticket;
+    }
+    S.cv.notify_all();
+    return SSA_OK;
+}
+
+int ssa_submit_multi(ssa_ctx* ctx, const double* const* series, const int* len, int s, int L, int r,
+                     int precision, const int* grp_ptr, const int* grp_idx, int ngroups, uint64_t* ticket) {
+    if (!series || !len || s <= 0) return fail(SSA_EINVAL, "no series");
+    int nmax = 0, nmin = 1 << 30;
+    for (int p = 0; p < s; ++p) {
+        if (len[p] <= 0 || !series[p]) return fail(SSA_EINVAL, "empty series");
+        nmax = std::max(nmax, len[p]);
+        nmin = std::min(nmin, len[p]);
+    }
+    if (!(L > 1 && L < nmin)) return fail(SSA_EINVAL, "window must satisfy 1 < L < min N_p");
+    std::vector<double> x((size_t)nmax * s, std::nan(""));
+    for (int p = 0; p < s; ++p)
+        for (int t = 0; t < len[p]; ++t) x[(size_t)t * s + p] = series[p][t];
+    ssa_request q{x.data(), nmax, s, nullptr, nullptr, L, 1, r, precision, 0x5eedULL};
+    return ssa_submit(ctx, &q, grp_ptr, grp_idx, ngroups, ticket);
+}
+
+int ssa_poll(ssa_ctx* ctx, uint64_t ticket, int* done) {
+    if (!ctx || !done) return fail(SSA_EINVAL, "NULL argument");
+    if (!ctx->srv) return fail(SSA_EINVAL, "unknown ticket");
+    Server& S = *ctx->srv;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.reqs.find(ticket);
+    if (it == S.reqs.end()) return fail(SSA_EINVAL, "unknown ticket");
+    *done = it->second->done;
+    return SSA_OK;
+}
+
+int ssa_wait(ssa_ctx* ctx, uint64_t ticket) {
+    if (!ctx || !ctx->srv) return fail(SSA_EINVAL, "unknown ticket");
+    Server& S = *ctx->srv;
+    std::unique_lock<std::mutex> lk(S.mu);
+    auto it = S.reqs.find(ticket);
+    if (it == S.reqs.end()) return fail(SSA_EINVAL, "unknown ticket");
+    auto r = it->second;
+    S.cv.wait(lk, [&] { return r->done; });
+    return SSA_OK;
+}
+
+int ssa_take(ssa_ctx* ctx, uint64_t ticket, ssa_decomp** out, double* recon, ssa_times* times) {
+    if (!ctx || !out) return fail(SSA_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (!ctx->srv) return fail(SSA_EINVAL, "unknown ticket");
+    Server& S = *ctx->srv;
+    std::shared_ptr<ServeReq> r;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        auto it = S.reqs.find(ticket);
+        if (it == S.reqs.end()) return fail(SSA_EINVAL, "unknown ticket");
+        if (!it->second->done) return SSA_EBUSY;
+        r = it->second;
+        S.reqs.erase(it);
+    }
+    if (times) {
+        times->queue_ms = r->t_start - r->t_submit;
+        times->total_ms = r->t_done - r->t_submit;
+    }
+    const int st = r->status;
+    if (st == SSA_OK || st == SSA_ENOCONV) {
+        if (recon && !r->recon.empty()) std::memcpy(recon, r->recon.data(), r->recon.size() * sizeof(double));
+        *out = r->d.release();
+    }
+    return st == SSA_OK ? SSA_OK : fail(st, "request failed");
+}
 
 const char* ssa_strerror(int code) {
     switch (code) {
