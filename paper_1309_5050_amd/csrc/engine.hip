@@ -1082,6 +1082,7 @@ void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode) {
 
 int basis_size(long nshort, int r) {
     int m = std::max(2 * r + 20, 3 * r);
+    if (const char* e = std::getenv("SHSSA_BASIS")) m = std::max(r + 2, std::atoi(e));   // experiments
     m = std::min(m, kMaxBasis);
     if (nshort <= m) m = (int)nshort;
     return m;

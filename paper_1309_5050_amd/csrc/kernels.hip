@@ -575,8 +575,7 @@ k_rowr_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     const OpDesc& op = ops[item.inst];
     const auto ad = [&](int pp) { return rx_addr_row<LOGN>(pp, c); };
     int xe = 0;
-    cplx<T> w[RegPlan<LOGN>::NTW], wr[8], v[8];
-    row_reg_setup<T, LOGN>(op.prow, t, w, wr);
+    cplx<T> v[8];
     const CellSet& S = op.S[args.set];
     const RowInSrc rs = row_in_source(op, lzs[item.inst], res, item, args, valid && a == 0 && t == 0);
     const gptr<const double> src = as_global(rs.src);
@@ -594,6 +593,8 @@ k_rowr_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
             pair_part(v[q >> 1], q & 1) = to<T>(val[q]);
         }
     });
+    cplx<T> w[RegPlan<LOGN>::NTW], wr[8];   // loaded after the gather: shorter live ranges
+    row_reg_setup<T, LOGN>(op.prow, t, w, wr);
     reg_fft<T, LOGN, -1, XS_WAVE>(v, w, lds, t, ad, xe);
     const gptr<cplx<T>> out = args.dest == DEST_T1 ? spec_row<T>(op.T1, item.comp * op.tslot, a, op.ldp)
                                                    : spec_row<T>(const_cast<void*>(op.Xh), 0, a, op.ldp);
@@ -616,10 +617,15 @@ k_rowr_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
     const OpDesc& op = ops[item.inst];
     const auto ad = [&](int pp) { return rx_addr_row<LOGN>(pp, c); };
     int xe = 0;
-    cplx<T> w[RegPlan<LOGN>::NTW], wr[8], v[8];
-    row_reg_setup<T, LOGN>(op.prow, t, w, wr);
-    row_unsplit<T, LOGN>(spec_row<T>(op.T2, item.comp * op.tslot, a, op.ldp), wr, t, v);
-    reg_fft<T, LOGN, +1, XS_WAVE>(v, w, lds, t, ad, xe);
+    cplx<T> v[8];
+    {
+        // twiddles are loaded again for the forward half: short live ranges
+        // keep the kernel's register count (and so its occupancy) down
+        cplx<T> w[RegPlan<LOGN>::NTW], wr[8];
+        row_reg_setup<T, LOGN>(op.prow, t, w, wr);
+        row_unsplit<T, LOGN>(spec_row<T>(op.T2, item.comp * op.tslot, a, op.ldp), wr, t, v);
+        reg_fft<T, LOGN, +1, XS_WAVE>(v, w, lds, t, ad, xe);
+    }
     const CellSet& S = op.S[args.set];
     if (args.gk) {
         const GkLong<T> g = gk_long<T>(lzs[item.inst], S, args.j, args.jstart);
@@ -667,6 +673,8 @@ k_rowr_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
         });
     }
     if (!args.fwd) return;
+    cplx<T> w[RegPlan<LOGN>::NTW], wr[8];
+    row_reg_setup<T, LOGN>(op.prow, t, w, wr);
     reg_fft<T, LOGN, -1, XS_WAVE>(v, w, lds, t, ad, xe);
     row_split_store<T, LOGN>(v, wr, lds, ad, t, spec_row<T>(op.T1, item.comp * op.tslot, a, op.ldp), valid);
 }
