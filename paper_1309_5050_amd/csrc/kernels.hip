@@ -512,10 +512,14 @@ __device__ __forceinline__ void row_split_store(const cplx<T> (&v)[8], const cpl
 // row a; -1 off the set or outside the set's box.  DENSE (no mask): the
 // index is the row offset plus the cell, so accesses through it keep one
 // per-thread address with immediate offsets.
+// All loads are unconditional (clamped to valid addresses, results masked):
+// a load under a lane condition becomes a branch with a wait of its own, and
+// the loads of a row would no longer overlap.
 template <int G, bool DENSE>
 __device__ __forceinline__ void pair_idx(const CellSet& S, int a, int t, int (&idx)[16]) {
     const bool inrow = a < S.boxA;
-    const int base = inrow ? gload(as_global(S.rowoff) + a) : 0;
+    const int ar = inrow ? a : 0;
+    const int base = gload(as_global(S.rowoff) + ar);
     const int lim = inrow ? S.boxB : 0;
     if constexpr (DENSE) {
 #pragma unroll
@@ -524,14 +528,30 @@ __device__ __forceinline__ void pair_idx(const CellSet& S, int a, int t, int (&i
             idx[q] = b < lim ? base + b : -1;
         }
     } else {
-        const gptr<const uint8_t> m = as_global(S.mask) + (long)a * S.boxB;
-        const gptr<const int> pf = as_global(S.pref) + (long)a * (S.boxB + 1);
+        const gptr<const uint8_t> m = as_global(S.mask) + (long)ar * S.boxB;
+        const gptr<const int> pf = as_global(S.pref) + (long)ar * (S.boxB + 1);
+        uint8_t mv[16];
+        int pv[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int b = 2 * (t + G * (q >> 1)) + (q & 1);
-            idx[q] = (b < lim && gload(m + b)) ? base + gload(pf + b) : -1;
+            const int bb = b < S.boxB ? b : S.boxB - 1;
+            mv[q] = gload(m + bb);
+            pv[q] = gload(pf + bb);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int b = 2 * (t + G * (q >> 1)) + (q & 1);
+            idx[q] = (b < lim && mv[q]) ? base + pv[q] : -1;
         }
     }
+}
+
+// Unconditional load of p[i] (p[0] when i < 0), zero when i < 0.
+template <typename V>
+__device__ __forceinline__ V load_or_zero(gptr<const V> p, int i) {
+    const V v = gload(p + (i >= 0 ? i : 0));
+    return i >= 0 ? v : V(0);
 }
 
 // Runs body(std::true_type) for a set without mask, body(std::false_type)
@@ -586,7 +606,7 @@ k_rowr_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
         pair_idx<G, decltype(dense)::value>(S, a, t, idx);
         double val[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) val[q] = idx[q] >= 0 ? gload(src + idx[q]) * rs.sc : 0.0;
+        for (int q = 0; q < 16; ++q) val[q] = load_or_zero(src, idx[q]) * rs.sc;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             if (wq && idx[q] >= 0) gstore(qout + idx[q], val[q]);
@@ -637,7 +657,7 @@ k_rowr_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
             pair_idx<G, decltype(dense)::value>(S, a, t, idx);
             T pv[16];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) pv[q] = idx[q] >= 0 ? gload(lprev + idx[q]) : T(0);
+            for (int q = 0; q < 16; ++q) pv[q] = load_or_zero(lprev, idx[q]);
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 T& z = pair_part(v[q >> 1], q & 1);
@@ -709,7 +729,7 @@ k_rowr_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
             pair_idx<G, decltype(dense)::value>(S, a, t, idx);
             double qq[16];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) qq[q] = idx[q] >= 0 ? gload(qv + idx[q]) : 0.0;
+            for (int q = 0; q < 16; ++q) qq[q] = load_or_zero(qv, idx[q]);
             if (!valid) return;
 #pragma unroll
             for (int q = 0; q < 16; ++q)
@@ -1341,7 +1361,8 @@ __device__ __forceinline__ void lz_project_block(const LzDesc& lz, int blk, int 
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             const int c = c0 + k;
-            v[k] = (in && c < ncols) ? gload(Q + (long)c * n) * wi : 0.0;
+            const double qv = gload(Q + (long)(c < ncols ? c : 0) * n);   // unconditional: loads overlap
+            v[k] = c < ncols ? qv * wi : 0.0;
         }
         const double sm = wave_sum16(v);
         if (l < 16 && c0 + l < ncols) red[wv][c0 + l] = sm;
@@ -1397,11 +1418,17 @@ k_lz_update(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int 
     const Item item = items[blockIdx.x];
     const LzDesc& lz = lzs[item.inst];
     if (pass == 2 && !cgs_second_pass(lz, force)) return;
-    const double* hp = pass == 1 ? lz.hp1 : lz.hp2;
+    const gptr<const double> hp = as_global(static_cast<const double*>(pass == 1 ? lz.hp1 : lz.hp2));
     for (int c = threadIdx.x; c < ncols; c += 256) {
-        double s = 0.0;
-        for (int q = 0; q < lz.nblk; ++q) s += hp[(long)q * (kMaxBasis + 1) + c];
-        h[c] = s;
+        // four independent partial sums: the block partials load in parallel
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+        int q = 0;
+        for (; q + 4 <= lz.nblk; q += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s4[u] += gload(hp + (long)(q + u) * (kMaxBasis + 1) + c);
+        }
+        for (; q < lz.nblk; ++q) s4[0] += gload(hp + (long)q * (kMaxBasis + 1) + c);
+        h[c] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     }
     __syncthreads();
     const long i = (long)item.idx * kLzRows + threadIdx.x;
@@ -1411,6 +1438,7 @@ k_lz_update(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int 
         const gptr<const double> Q = as_global(static_cast<const double*>(lz.Q)) + i;
         wi = gload(w);
         double acc = 0.0;
+#pragma unroll 8
         for (int c = 0; c < ncols; ++c) acc += gload(Q + (long)c * lz.n) * h[c];
         wi -= acc;
         gstore(w, wi);
