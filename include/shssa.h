@@ -196,15 +196,17 @@ int ssa_take(ssa_ctx* ctx, uint64_t ticket, ssa_decomp** out, double* recon, ssa
 /* Blocks until all work queued on the context's stream is complete. */
 int ssa_ctx_sync(ssa_ctx* ctx);
 
-/* Kernel timing with HIP events.  kind names one kernel class ("col",
- * "row_in", "row_mid", "row_out", "rowfam_mid", "rowfam_out", "lz_proj",
- * "lz_update"); NULL or "" stops recording.  ssa_ctx_profile_read waits for
- * the recorded launches and returns the time during which at least one of
- * them was running (ms: the union of their intervals, so launches of
- * concurrent sub-batch streams are not counted twice), their number and
- * their algorithmic bytes (data each launch must read and write), and
- * clears the record. */
+/* Kernel timing with HIP events.  kind is a comma-separated list of kernel
+ * classes ("col", "row_in", "row_mid", "row_out", "rowfam_mid",
+ * "rowfam_out", "lz_proj", "lz_update"); NULL or "" stops recording.
+ * ssa_ctx_profile_read_kind waits for the recorded launches of one class and
+ * returns the time during which at least one of them was running (ms: the
+ * union of their intervals, so launches of concurrent sub-batch streams are
+ * not counted twice), their number and their algorithmic bytes (data each
+ * launch must read and write).  ssa_ctx_profile_read returns the same over
+ * all recorded classes and clears the record. */
 int ssa_ctx_profile(ssa_ctx* ctx, const char* kind);
+int ssa_ctx_profile_read_kind(ssa_ctx* ctx, const char* kind, double* ms, long* launches, double* bytes);
 int ssa_ctx_profile_read(ssa_ctx* ctx, double* ms, long* launches, double* bytes);
 
 #ifdef __cplusplus

@@ -129,10 +129,20 @@ class Context:
         """Start (kind = kernel class name) or stop (None) event timing."""
         check(lib().ssa_ctx_profile(self._h, None if kind is None else kind.encode()), "ssa_ctx_profile")
 
-    def profile_read(self) -> dict:
+    def profile_read(self, kinds=None) -> dict:
+        """Totals of the recorded launches; with ``kinds`` (a list of kernel
+        classes) a dict of per-class totals.  Clears the record."""
+        per = None
+        if kinds:
+            per = {}
+            for k in kinds:
+                ms, n, b = C.c_double(), C.c_long(), C.c_double()
+                check(lib().ssa_ctx_profile_read_kind(self._h, k.encode(), C.byref(ms), C.byref(n), C.byref(b)),
+                      "ssa_ctx_profile_read_kind")
+                per[k] = {"ms": ms.value, "launches": n.value, "bytes": b.value}
         ms, n, b = C.c_double(), C.c_long(), C.c_double()
         check(lib().ssa_ctx_profile_read(self._h, C.byref(ms), C.byref(n), C.byref(b)), "ssa_ctx_profile_read")
-        return {"ms": ms.value, "launches": n.value, "bytes": b.value}
+        return per if per is not None else {"ms": ms.value, "launches": n.value, "bytes": b.value}
 
     # ---- decomposition -------------------------------------------------
 

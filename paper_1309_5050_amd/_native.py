@@ -43,6 +43,8 @@ _SIGS = {
     "ssa_ctx_profile": (C.c_int, [C.c_void_p, C.c_char_p]),
     "ssa_ctx_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_long),
                                        C.POINTER(C.c_double)]),
+    "ssa_ctx_profile_read_kind": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_long),
+                                            C.POINTER(C.c_double)]),
     "ssa_decompose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
                                 C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]),
     "ssa_decompose_multi": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p, C.c_int, C.c_int,

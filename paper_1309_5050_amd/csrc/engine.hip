@@ -115,11 +115,18 @@ struct ssa_ctx {
         return it != col_tc.end() ? it->second : col_tile(f64);
     }
     // kernel timing (see ssa_ctx_profile)
-    std::string prof_kind;
+    std::vector<std::string> prof_kinds;   // kernel classes being timed
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, int>> spans;
-    double prof_bytes = 0.0;
-    long prof_launches = 0;
+    struct Span {
+        int e0, e1, kind;
+        double bytes;
+    };
+    std::vector<Span> spans;
+    int prof_index(const char* kind) const {
+        for (size_t k = 0; k < prof_kinds.size(); ++k)
+            if (prof_kinds[k] == kind) return (int)k;
+        return -1;
+    }
 
     // next unused event of the pool (caller holds mu); reset by profile_read
     int ev_next = 0;
@@ -710,15 +717,14 @@ struct ProfSpan {
     int e1 = -1;
     ProfSpan(ssa_ctx* ctx, const char* kind, hipStream_t s, double bytes) : c(ctx), st(s) {
         std::lock_guard<std::mutex> g(c->mu);
-        if (c->prof_kind.empty() || c->prof_kind != kind) return;
+        const int k = c->prof_index(kind);
+        if (k < 0) return;
         // both events are taken now, so spans of concurrent threads never share one
         e0 = c->prof_event();
         e1 = e0 >= 0 ? c->prof_event() : -1;
         if (e1 < 0) return;
         (void)hipEventRecord(c->ev_pool[e0], st);
-        c->spans.push_back({e0, e1});
-        c->prof_bytes += bytes;
-        c->prof_launches += 1;
+        c->spans.push_back({e0, e1, k, bytes});
         on = true;
     }
     ~ProfSpan() {
@@ -1758,27 +1764,44 @@ extern "C" {
 int ssa_ctx_profile(ssa_ctx* ctx, const char* kind) {
     if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
     std::lock_guard<std::mutex> g(ctx->mu);
-    ctx->prof_kind = kind ? kind : "";
-    if (!ctx->prof_kind.empty()) {
+    ctx->prof_kinds.clear();
+    if (kind) {
+        std::string all(kind), cur;
+        for (char ch : all + ",") {
+            if (ch == ',') {
+                if (!cur.empty()) ctx->prof_kinds.push_back(cur);
+                cur.clear();
+            } else {
+                cur += ch;
+            }
+        }
+    }
+    if (!ctx->prof_kinds.empty()) {
         if (!ctx->prof_ref) HIPCHK(hipEventCreate(&ctx->prof_ref));
         HIPCHK(hipEventRecord(ctx->prof_ref, ctx->st));
     }
     return SSA_OK;
 }
 
-int ssa_ctx_profile_read(ssa_ctx* ctx, double* ms, long* launches, double* bytes) {
-    if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
-    HIPCHK(hipStreamSynchronize(ctx->st));
-    std::lock_guard<std::mutex> g(ctx->mu);
+// Time during which at least one recorded launch of class kind (all classes
+// for kind = NULL) was running, with the launch count and algorithmic bytes.
+static int profile_sum(ssa_ctx* ctx, const char* kind, double* ms, long* launches, double* bytes) {
+    const int want = kind ? ctx->prof_index(kind) : -1;
+    if (kind && want < 0) return fail(SSA_EINVAL, "kernel class not recorded");
     // launches of concurrent streams may overlap: the time is the length of
     // the union of the recorded [start, end] intervals
     std::vector<std::pair<double, double>> iv;
+    long n = 0;
+    double by = 0.0;
     for (auto& sp : ctx->spans) {
+        if (kind && sp.kind != want) continue;
         float a = 0.f, b = 0.f;
-        HIPCHK(hipEventSynchronize(ctx->ev_pool[sp.second]));
-        HIPCHK(hipEventElapsedTime(&a, ctx->prof_ref, ctx->ev_pool[sp.first]));
-        HIPCHK(hipEventElapsedTime(&b, ctx->prof_ref, ctx->ev_pool[sp.second]));
+        HIPCHK(hipEventSynchronize(ctx->ev_pool[sp.e1]));
+        HIPCHK(hipEventElapsedTime(&a, ctx->prof_ref, ctx->ev_pool[sp.e0]));
+        HIPCHK(hipEventElapsedTime(&b, ctx->prof_ref, ctx->ev_pool[sp.e1]));
         iv.push_back({a, b});
+        ++n;
+        by += sp.bytes;
     }
     std::sort(iv.begin(), iv.end());
     double tot = 0.0, cs = 0.0, ce = -1e300;
@@ -1793,13 +1816,26 @@ int ssa_ctx_profile_read(ssa_ctx* ctx, double* ms, long* launches, double* bytes
     }
     if (ce > cs && !iv.empty()) tot += ce - cs;
     if (ms) *ms = tot;
-    if (launches) *launches = ctx->prof_launches;
-    if (bytes) *bytes = ctx->prof_bytes;
+    if (launches) *launches = n;
+    if (bytes) *bytes = by;
+    return SSA_OK;
+}
+
+int ssa_ctx_profile_read(ssa_ctx* ctx, double* ms, long* launches, double* bytes) {
+    if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    std::lock_guard<std::mutex> g(ctx->mu);
+    int rc = profile_sum(ctx, nullptr, ms, launches, bytes);
     ctx->spans.clear();
     ctx->ev_next = 0;
-    ctx->prof_bytes = 0.0;
-    ctx->prof_launches = 0;
-    return SSA_OK;
+    return rc;
+}
+
+int ssa_ctx_profile_read_kind(ssa_ctx* ctx, const char* kind, double* ms, long* launches, double* bytes) {
+    if (!ctx || !kind) return fail(SSA_EINVAL, "NULL argument");
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    std::lock_guard<std::mutex> g(ctx->mu);
+    return profile_sum(ctx, kind, ms, launches, bytes);
 }
 
 int ssa_ctx_create(int device, size_t mem_budget, void* stream, ssa_ctx** out) {
