@@ -85,6 +85,7 @@ typedef struct ssa_stats {
     int basis;              /* projected matrix size m */
     int converged;          /* 1 if every triplet met the residual test */
     int side;               /* 0: basis on the window side, 1: origin side */
+    int batch;              /* decompositions that advanced together in its batch */
     double max_resid;       /* largest residual bound |X v - s u| / sigma_1 */
     double ms_setup, ms_lanczos, ms_finish;
     size_t device_bytes;    /* device memory held by the handle */
@@ -112,10 +113,15 @@ int ssa_decompose(ssa_ctx* ctx, const double* x, int nx, int ny, const uint8_t* 
 int ssa_decompose_multi(ssa_ctx* ctx, const double* const* series, const int* len, int s, int L,
                         int r, int precision, ssa_decomp** out);
 
-/* Decompose n requests together: requests of equal geometry, rank and
- * precision advance in one batch through the same kernels.  out[i] and
- * status[i] receive each request's handle (or NULL) and code.  Returns
- * SSA_OK if the batch ran (individual failures are in status). */
+/* Decompose n requests together.  Requests of one kernel class advance in
+ * one batch through the same kernels whatever their sizes and shapes; the
+ * class is the operator family (window one row high or not), precision,
+ * short side (window or origin set), the row and column transform variants
+ * and the bidiagonalisation's basis and restart sizes (which follow from r).
+ * Each request's results do not depend on the others in its batch (its own
+ * seed starts its Krylov space).  out[i] and status[i] receive each
+ * request's handle (or NULL) and code.  Returns SSA_OK if the batch ran
+ * (individual failures are in status). */
 int ssa_decompose_batch(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** out, int* status);
 
 /* As ssa_decompose_batch with x (and mask) as device pointers. */
@@ -144,7 +150,8 @@ int ssa_get_weights(const ssa_decomp* d, double* w);
  * ids < r).  out: ngroups arrays of nx*ny, NaN outside N'. */
 int ssa_reconstruct(ssa_decomp* d, const int* grp_ptr, const int* grp_idx, int ngroups, double* out);
 
-/* Reconstruct the same groups for n handles of equal geometry in one batch.
+/* Reconstruct the same groups for n handles of one kernel class (as for
+ * ssa_decompose_batch) in one batch; the group ids must be < r of every handle.
  * out_dev[i] is a device buffer of ngroups*nx*ny doubles with the layout of
  * ssa_reconstruct.  Queued on the context's stream; returns without waiting. */
 int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* grp_ptr, const int* grp_idx,
@@ -161,14 +168,14 @@ const char* ssa_last_error(void);
  * at once.
  *
  * ssa_submit copies the request's host inputs (x, mask, wmask: as for
- * ssa_decompose; seed unused) and the groups (CSR form: grp_ptr[ngroups+1],
+ * ssa_decompose) and the groups (CSR form: grp_ptr[ngroups+1],
  * 0-based component ids in grp_idx; ngroups may be 0 for no reconstruction)
  * and returns a ticket at once.  Library threads, each with its own HIP
  * stream on the context's device, admit waiting requests in arrival order
  * while their estimated device memory fits the context's budget beside the
- * running batches, put every waiting request of the same geometry, rank and
- * precision into the same batch (up to 64), and run decomposition and
- * reconstruction.  Errors that the plan shows at once (bad sizes, a request
+ * running batches, put every waiting request of the same kernel class (as
+ * for ssa_decompose_batch: sizes may differ) into the same batch (up to
+ * 64), and run decomposition and reconstruction.  Errors that the plan shows at once (bad sizes, a request
  * larger than the whole budget: SSA_ENOMEM) are returned by ssa_submit.
  *
  * ssa_poll sets *done = 1 once the request has finished (successfully or

@@ -16,6 +16,7 @@ struct OpDesc {
     int P;              // bins of a row spectrum (MB/2 + 1)
     int ldp;            // row pitch of the row-major spectra (T1, T2, Xh): P rounded up to 16
     int rowfam;         // 1: window one row high
+    double spec_scale;  // 1 / (MA MB) (grid family) or 1 / MB (row family): the spectrum's scale
     CellSet S[2];       // S[0] window cells (L), S[1] origins (K)
     FftPlan prow;       // complex transform of length MB/2 (+ real split twiddles)
     FftPlan pcol;       // complex transform of length MA (grid family)
@@ -35,6 +36,7 @@ struct OpDesc {
 // with classical Gram-Schmidt applied twice; the long side keeps only the
 // last two (unnormalised) vectors, in the precision of the operator.
 struct LzDesc {
+    unsigned long long seed;   // start and restart vectors of this decomposition
     int side;           // short side: 0 = window set, 1 = origin set
     int active;
     int r;              // triplets wanted
@@ -66,6 +68,7 @@ struct LzDesc {
 
 // Final results of one decomposition (compact FP64 vectors).
 struct ResDesc {
+    int r;              // triplets of this decomposition
     double* U;          // L x r column-major (ld = L)
     double* V;          // K x r column-major (ld = K)
     double* sigma;      // r
@@ -93,9 +96,8 @@ enum RowDest : int {
 
 struct RowInArgs {
     int mode, set, j, dest;
-    double scale;     // IN_VEC: multiply by scale * sigma[comp] if use_sigma
+    double scale;     // IN_VEC: multiply by scale * sigma[comp] if use_sigma; DEST_XH: < 0 = spec_scale
     int use_sigma;
-    void* xh_out;     // DEST_XH target
 };
 
 enum OutMode : int {
@@ -138,13 +140,19 @@ enum ColMode : int {
     COL_ACCUM = 3,    // for i in group comp: fwd of T1 slot i, * Us_i, summed; inverse
 };
 
+// Row counts of the column pass, per instance: a count >= 0, or one of
+// ROWS_ALL (A), ROWS_S0 (window box rows), ROWS_S1 (origin box rows).
+enum { ROWS_ALL = -1, ROWS_S0 = -2, ROWS_S1 = -3 };
+
 struct ColArgs {
     int mode;
-    int nin;          // nonzero input rows
-    int nout;         // output rows written to T2
-    double scale;
-    void* xh_out;     // COL_SPEC target
+    int nin;          // nonzero input rows (count or ROWS_*)
+    int nout;         // output rows written to T2 (count or ROWS_*)
 };
+
+__host__ __device__ inline int col_rows(const OpDesc& op, int code) {
+    return code >= 0 ? code : code == ROWS_ALL ? op.A : code == ROWS_S0 ? op.S[0].boxA : op.S[1].boxA;
+}
 
 // Window rows as runs: run t covers window row ra[t], columns [b0[t], b1[t]).
 struct Runs { const int* ra; const int* b0; const int* b1; int nrun; long total; };

@@ -573,6 +573,7 @@ int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStrea
     OpDesc& o = d->op;
     o.A = d->A; o.B = d->B; o.MA = d->MA; o.MB = d->MB; o.P = d->P; o.ldp = d->ldp;
     o.rowfam = d->rowfam;
+    o.spec_scale = d->rowfam ? 1.0 / d->MB : 1.0 / ((double)d->MA * d->MB);
     o.S[0] = CellSet{d->LA, d->LB, d->L, lfull ? nullptr : d->lmask, d->lrow, lfull ? nullptr : d->lpref};
     o.S[1] = CellSet{d->KA, d->KB, 0, d->kmask, d->krow, d->kpref};
     o.W = d->W;
@@ -741,34 +742,87 @@ double col_bytes(const Batch& b, const ItemList& L, int nin, int nout) {
     for (const Item& it : L.h) {
         const auto* d = b.ds[it.inst];
         const int tc = std::min(b.TC, d->P - it.idx * b.TC);
-        tot += (double)tc * (nin + nout + d->MA) * d->celem();
+        tot += (double)tc * (col_rows(d->op, nin) + col_rows(d->op, nout) + d->MA) * d->celem();
     }
     return tot;
 }
 
 // Algorithmic bytes of one row launch: rows x (P complex) in and/or out plus
-// the compact vectors it reads or writes.
-double row_bytes(const Batch& b, const ItemList& L, int cin, int cout, double vec_bytes_per_inst) {
+// the compact vectors it reads or writes (vec(d) bytes per instance).  cin =
+// -1: every item reads all A rows of its instance.
+template <typename F>
+double row_bytes(const Batch& b, const ItemList& L, int cin, int cout, F vec) {
     double tot = 0.0;
-    for (const Item& it : L.h)
-        tot += (double)std::max(it.aux, 1) * b.ds[it.inst]->P * b.ds[it.inst]->celem() * (cin + cout);
+    for (const Item& it : L.h) {
+        if (it.aux < 0) continue;   // padding
+        const auto* d = b.ds[it.inst];
+        const int ci = cin < 0 ? d->A : cin;
+        tot += (double)std::max(it.aux, 1) * d->P * d->celem() * (ci + cout);
+    }
     std::vector<char> seen(b.ds.size(), 0);
     for (const Item& it : L.h)
-        if (!seen[it.inst]) { seen[it.inst] = 1; tot += vec_bytes_per_inst; }
+        if (!seen[it.inst]) { seen[it.inst] = 1; tot += vec(b.ds[it.inst]); }
     return tot;
 }
 
+// The LDS row kernels of the smallest size class run several items per
+// workgroup and stage one twiddle table per workgroup.  In a batch whose row
+// transform lengths differ, every (instance, component) run of a row item
+// list is padded to a whole number of workgroups with copies of its last
+// item marked aux = -1 (computed, never written), so no workgroup mixes
+// lengths.
+bool mixed_rows(const Batch& b) {
+    if (row_slots(b.cls) <= 1) return false;
+    for (auto* d : b.ds)
+        if (d->nh != b.ds[0]->nh) return true;
+    return false;
+}
+
+void slot_pad(const Batch& b, ItemList& L) {
+    if (!mixed_rows(b)) return;
+    const size_t s = (size_t)row_slots(b.cls);
+    std::vector<Item> out;
+    out.reserve(L.h.size() + L.h.size() / 4 + s);
+    for (size_t k = 0; k < L.h.size();) {
+        size_t e = k;
+        while (e < L.h.size() && L.h[e].inst == L.h[k].inst && L.h[e].comp == L.h[k].comp) ++e;
+        out.insert(out.end(), L.h.begin() + k, L.h.begin() + e);
+        Item pad = L.h[e - 1];
+        pad.aux = -1;
+        while (out.size() % s) out.push_back(pad);
+        k = e;
+    }
+    L.h.swap(out);
+}
+
+// Column-pass row code of a side's set (0: window box rows, 1: origin box rows).
+inline int side_rows(int side) { return side == 0 ? ROWS_S0 : ROWS_S1; }
+
 // rows [0, nrows) of every listed instance, optional component range; with
-// group > 1 one item per group of rows (first row, row count in aux)
+// group > 1 one item per group of rows (first row, row count in aux); with
+// keep, only the (instance, component) pairs it accepts
 void rows_items(ItemList& L, const std::vector<int>& inst, std::function<int(int)> nrows, int ncomp = 1,
-                const std::vector<int>* comps = nullptr, int group = 1) {
+                const std::vector<int>* comps = nullptr, int group = 1,
+                std::function<bool(int, int)> keep = nullptr) {
     L.h.clear();
     for (int c = 0; c < ncomp; ++c)
         for (int i : inst) {
             const int nr = nrows(i);
             const int comp = comps ? (*comps)[c] : c;
+            if (keep && !keep(i, comp)) continue;
             for (int a = 0; a < nr; a += group) L.h.push_back(Item{i, a, comp, std::min(group, nr - a)});
         }
+}
+
+// Short side of the bidiagonalisation: the window set unless the origin box
+// is smaller (the row family always works on the window side).  It depends
+// on sizes known before the origin count, so batching can use it.
+int plan_side(const ssa_decomp* d) { return d->rowfam || d->L <= (long)d->KA * d->KB ? 0 : 1; }
+
+void choose_side(ssa_decomp* d) {
+    d->side = plan_side(d);
+    d->nshort = d->side == 0 ? d->L : d->K;
+    d->nlong = d->side == 0 ? d->K : d->L;
 }
 
 // Shape setup, origin counts, weights and the image spectrum.
@@ -865,10 +919,9 @@ int tune_col_tile(Batch& b) {
         if ((rc = cols.upload(st))) break;
         // the spectrum pass (also the warm-up), then the two product passes
         // of a bidiagonalisation step, timed
-        ColArgs c{COL_SPEC, d0->A, 0, 1.0 / ((double)d0->MA * d0->MB), nullptr};
-        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.ds[0]->MA, tc);
-        const int s = d0->side, nin = d0->op.S[s].boxA, nmid = d0->op.S[1 - s].boxA;
-        const ColArgs fw{COL_CORR, nin, nmid, 1.0, nullptr}, bw{COL_CORR, nmid, nin, 1.0, nullptr};
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_SPEC, ROWS_ALL, 0}, d0->MA, tc);
+        const ColArgs fw{COL_CORR, side_rows(d0->side), side_rows(1 - d0->side)};
+        const ColArgs bw{COL_CORR, side_rows(1 - d0->side), side_rows(d0->side)};
         (void)hipEventRecord(e0, st);
         for (int rep = 0; rep < 4; ++rep) {
             launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), fw, b.ds[0]->MA, tc);
@@ -896,10 +949,6 @@ int run_alloc_spectrum(Batch& b) {
     hipStream_t st = b.st;
     int rc;
     for (auto* d : b.ds) {
-        const bool fullbox_short = d->L <= (long)d->KA * d->KB;
-        d->side = d->rowfam ? 0 : (fullbox_short ? 0 : 1);
-        d->nshort = d->side == 0 ? d->L : d->K;
-        d->nlong = d->side == 0 ? d->K : d->L;
         const size_t ce = d->celem();
         const long xh = d->rowfam ? (long)d->A * d->ldp : (long)d->ldp * d->MA;
         d->tslot = (long)d->A * d->ldp;
@@ -940,6 +989,7 @@ int run_alloc_spectrum(Batch& b) {
             o.pcol.twr = nullptr;
         }
         LzDesc& z = d->lz;
+        z.seed = d->seed;
         z.side = d->side;
         z.active = 1;
         z.r = d->r;
@@ -956,6 +1006,7 @@ int run_alloc_spectrum(Batch& b) {
         z.beta = d->beta; z.flag = d->flag; z.Qtmp = d->Qtmp;
         z.nblk = nblk;
         ResDesc& s = d->rs;
+        s.r = d->r;
         s.U = d->U; s.V = d->V; s.sigma = d->sigma;
     }
     if ((rc = b.upload_descs())) return rc;
@@ -965,22 +1016,22 @@ int run_alloc_spectrum(Batch& b) {
     for (int i = 0; i < ni; ++i) all[i] = i;
     ItemList rowsA;
     rows_items(rowsA, all, [&](int i) { return b.ds[i]->A; });
+    slot_pad(b, rowsA);
     if ((rc = rowsA.upload(st))) return rc;
     const auto* d0 = b.ds[0];
     if (d0->rowfam) {
         // row spectra scaled by 1/MB straight into each instance's Xh
-        RowInArgs a{IN_DENSE, 0, 0, DEST_XH, 1.0 / d0->MB, 0, nullptr};
+        RowInArgs a{IN_DENSE, 0, 0, DEST_XH, -1.0, 0};   // each instance's spec_scale
         launch_row_in(b.f64, b.cls, rowsA.n(), st, b.ops(), b.lzs(), b.res(), rowsA.ptr(), a);
     } else {
-        RowInArgs a{IN_DENSE, 0, 0, DEST_T1, 1.0, 0, nullptr};
+        RowInArgs a{IN_DENSE, 0, 0, DEST_T1, 1.0, 0};
         launch_row_in(b.f64, b.cls, rowsA.n(), st, b.ops(), b.lzs(), b.res(), rowsA.ptr(), a);
         if ((rc = tune_col_tile(b))) return rc;
         ItemList cols;
         for (int i = 0; i < ni; ++i)
             for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) cols.h.push_back(Item{i, t, 0, 0});
         if ((rc = cols.upload(st))) return rc;
-        ColArgs c{COL_SPEC, d0->A, 0, 1.0 / ((double)d0->MA * d0->MB), nullptr};
-        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), c, b.ds[0]->MA, b.TC);
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_SPEC, ROWS_ALL, 0}, d0->MA, b.TC);
         HIPCHK(hipStreamSynchronize(st));
     }
     HIPCHK(hipStreamSynchronize(st));
@@ -1011,6 +1062,9 @@ void build_step_lists(Batch& b, const std::vector<int>& act, StepLists& S) {
         for (int i : act)
             for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) S.cols.h.push_back(Item{i, t, 0, 0});
     }
+    slot_pad(b, S.rin);
+    slot_pad(b, S.rmid);
+    slot_pad(b, S.rout);
     S.lzb.h.clear();
     S.inst.h.clear();
     for (int i : act) {
@@ -1031,53 +1085,57 @@ void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode) {
     hipStream_t st = b.st;
     const auto* d0 = b.ds[0];
     const int s = d0->side;
-    const double vs = 8.0 * d0->nshort, vl = (d0->f64 ? 8.0 : 4.0) * d0->nlong;
+    // compact vector bytes per instance: short side FP64, long side in the operator precision
+    const auto vs = [&](const ssa_decomp* d) { return 8.0 * d->nshort; };
+    const auto vl2 = [&](const ssa_decomp* d) { return 2.0 * (d->f64 ? 8.0 : 4.0) * d->nlong; };
+    const auto vs2 = [&](const ssa_decomp* d) { return 16.0 * d->nshort; };
     if (d0->rowfam) {
         {
             ProfSpan p(b.ctx, "row_in", st, row_bytes(b, S.rin, 0, 1, vs));
             launch_row_in(b.f64, b.cls, S.rin.n(), st, b.ops(), b.lzs(), b.res(), S.rin.ptr(),
-                          RowInArgs{mode, 0, j, DEST_T1, 1.0, 0, nullptr});
+                          RowInArgs{mode, 0, j, DEST_T1, 1.0, 0});
         }
         {
-            ProfSpan p(b.ctx, "rowfam_mid", st, row_bytes(b, S.rmid, 3, 1, 2 * vl));
+            ProfSpan p(b.ctx, "rowfam_mid", st, row_bytes(b, S.rmid, 3, 1, vl2));
             launch_rowfam_mid(b.f64, b.cls, S.rmid.n(), st, b.ops(), b.lzs(), b.res(), S.rmid.ptr(),
                               RowFamArgs{OUT_NONE, 1, 1, j, jstart});
         }
         {
-            ProfSpan p(b.ctx, "rowfam_out", st, row_bytes(b, S.rout, d0->A, 0, 2 * vs));
+            ProfSpan p(b.ctx, "rowfam_out", st, row_bytes(b, S.rout, -1, 0, vs2));
             launch_rowfam_out(b.f64, b.cls, S.rout.n(), st, b.ops(), b.lzs(), S.rout.ptr(),
                               RowOutArgs{OUT_LZ, 0, 1.0, 0, j, jstart});
         }
     } else {
-        const int nin = d0->op.S[s].boxA, nmid = d0->op.S[1 - s].boxA;
+        const int nin = side_rows(s), nmid = side_rows(1 - s);
         {
             ProfSpan p(b.ctx, "row_in", st, row_bytes(b, S.rin, 0, 1, vs));
             launch_row_in(b.f64, b.cls, S.rin.n(), st, b.ops(), b.lzs(), b.res(), S.rin.ptr(),
-                          RowInArgs{mode, s, j, DEST_T1, 1.0, 0, nullptr});
+                          RowInArgs{mode, s, j, DEST_T1, 1.0, 0});
         }
         {
             ProfSpan p(b.ctx, "col", st, col_bytes(b, S.cols, nin, nmid));
             launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(),
-                       ColArgs{COL_CORR, nin, nmid, 1.0, nullptr}, b.ds[0]->MA, b.TC);
+                       ColArgs{COL_CORR, nin, nmid}, d0->MA, b.TC);
         }
         {
-            ProfSpan p(b.ctx, "row_mid", st, row_bytes(b, S.rmid, 1, 1, 2 * vl));
+            ProfSpan p(b.ctx, "row_mid", st, row_bytes(b, S.rmid, 1, 1, vl2));
             launch_row_mid(b.f64, b.cls, S.rmid.n(), st, b.ops(), b.lzs(), b.res(), S.rmid.ptr(),
                            RowMidArgs{1 - s, OUT_NONE, 1.0, 0, 1, 1, j, jstart});
         }
         {
             ProfSpan p(b.ctx, "col", st, col_bytes(b, S.cols, nmid, nin));
             launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(),
-                       ColArgs{COL_CORR, nmid, nin, 1.0, nullptr}, b.ds[0]->MA, b.TC);
+                       ColArgs{COL_CORR, nmid, nin}, d0->MA, b.TC);
         }
         {
-            ProfSpan p(b.ctx, "row_out", st, row_bytes(b, S.rout, 1, 0, 2 * vs));
+            ProfSpan p(b.ctx, "row_out", st, row_bytes(b, S.rout, 1, 0, vs2));
             launch_row_out(b.f64, b.cls, S.rout.n(), st, b.ops(), b.lzs(), b.res(), S.rout.ptr(),
                            RowOutArgs{OUT_LZ, s, 1.0, 0, j, jstart});
         }
     }
     const int ncols = j + 1;
-    const double qb = 8.0 * d0->nshort * ncols * S.inst.n();
+    double qb = 0.0;
+    for (const Item& it : S.inst.h) qb += 8.0 * b.ds[it.inst]->nshort * ncols;
     {
         ProfSpan p(b.ctx, "lz_proj", st, qb);
         launch_lz_proj(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols);
@@ -1099,22 +1157,26 @@ int basis_size(long nshort, int r) {
     return m;
 }
 
+// Ritz vectors kept by a thick restart of a basis of size m.
+int restart_keep(int m, int r) { return std::min(m - 1, r + (m - r) / 2); }
+
 int run_lanczos(Batch& b, int max_steps) {
     hipStream_t st = b.st;
     const int ni = (int)b.ds.size();
     int rc;
-    long nmin = b.ds[0]->nshort;
-    for (auto* d : b.ds) nmin = std::min(nmin, d->nshort);
-    const int r = b.ds[0]->r;
-    const int m = basis_size(nmin, r);
-    const int kk = std::min(m - 1, r + (m - r) / 2);
+    // every instance of a batch has the same basis size and restart size
+    // (they differ in r only where the basis is clipped)
+    const int m = basis_size(b.ds[0]->nshort, b.ds[0]->r);
+    const int kk = restart_keep(m, b.ds[0]->r);
+    int rmax = 0;
+    for (auto* d : b.ds) rmax = std::max(rmax, d->r);
     std::vector<int> act(ni);
     for (int i = 0; i < ni; ++i) act[i] = i;
     std::vector<int> steps(ni, 0), restarts(ni, 0);
     StepLists S;
     build_step_lists(b, act, S);
     if ((rc = upload_step_lists(S, st))) return rc;
-    launch_lz_start(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), b.ds[0]->seed);
+    launch_lz_start(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), 0ULL);   // each instance's own seed
     int jstart = 0;
     std::vector<int> flags(4 * ni);
     std::vector<double> betas(2 * ni);
@@ -1204,11 +1266,11 @@ int run_lanczos(Batch& b, int max_steps) {
             for (int i : done) {
                 const long n = b.ds[i]->nshort;
                 for (long rb = 0; rb < (n + 63) / 64; ++rb)
-                    for (int cb = 0; cb < (r + 15) / 16; ++cb) R.h.push_back(Item{i, (int)rb, 0, cb});
+                    for (int cb = 0; cb < (b.ds[i]->r + 15) / 16; ++cb) R.h.push_back(Item{i, (int)rb, 0, cb});
                 I.h.push_back(Item{i, 0, 0, 0});
             }
             if ((rc = R.upload(st)) || (rc = I.upload(st))) return rc;
-            launch_lz_ritz(R.n(), st, b.lzs(), R.ptr(), m, r, douts.as<double*>());
+            launch_lz_ritz(R.n(), st, b.lzs(), R.ptr(), m, rmax, douts.as<double*>());
             launch_lz_sigma(I.n(), st, b.lzs(), b.res(), I.ptr());
             HIPCHK(hipStreamSynchronize(st));
         }
@@ -1228,7 +1290,7 @@ int run_lanczos(Batch& b, int max_steps) {
             launch_lz_ritz(R.n(), st, b.lzs(), R.ptr(), m, kk, nullptr);
             launch_lz_restart(Z.n(), st, b.lzs(), Z.ptr(), m, kk);
             if (F.n() > 0) {
-                launch_lz_restart_random(F.n(), st, b.lzs(), F.ptr(), kk, b.ds[0]->seed + 7919ULL * cycle);
+                launch_lz_restart_random(F.n(), st, b.lzs(), F.ptr(), kk, 7919ULL * cycle);   // ^ own seed
                 launch_lz_proj(F.n(), st, b.lzs(), F.ptr(), kk);
                 launch_lz_update(F.n(), st, b.lzs(), F.ptr(), kk, 1, 1);
                 launch_lz_proj2(F.n(), st, b.lzs(), F.ptr(), kk, 1);
@@ -1254,34 +1316,44 @@ int run_finish(Batch& b) {
     std::vector<int> all(ni);
     for (int i = 0; i < ni; ++i) all[i] = i;
     const auto* d0 = b.ds[0];
-    const int r = d0->r;
+    int r = 0;   // components of the batch (instances may have fewer)
+    for (auto* d : b.ds) r = std::max(r, d->r);
     const int s = d0->side;
+    // component c of the instances with r > c
+    const auto has = [&](int i, int c) { return c < b.ds[i]->r; };
     ItemList rin, cols, rmid, sg;
     if (d0->rowfam) {
-        rows_items(rin, all, [&](int) { return 1; }, r, nullptr, row_group(b.cls, false));
-        rows_items(rmid, all, [&](int i) { return b.ds[i]->A; }, r);
+        rows_items(rin, all, [&](int) { return 1; }, r, nullptr, row_group(b.cls, false), has);
+        rows_items(rmid, all, [&](int i) { return b.ds[i]->A; }, r, nullptr, 1, has);
+        slot_pad(b, rin);
+        slot_pad(b, rmid);
         if ((rc = rin.upload(st)) || (rc = rmid.upload(st))) return rc;
         launch_row_in(b.f64, b.cls, rin.n(), st, b.ops(), b.lzs(), b.res(), rin.ptr(),
-                      RowInArgs{IN_VEC, 0, 0, DEST_T1, 1.0, 0, nullptr});
+                      RowInArgs{IN_VEC, 0, 0, DEST_T1, 1.0, 0});
         launch_rowfam_mid(b.f64, b.cls, rmid.n(), st, b.ops(), b.lzs(), b.res(), rmid.ptr(),
                           RowFamArgs{OUT_VEC, 0, 0, 0, 0});
     } else {
-        rows_items(rin, all, [&](int i) { return b.ds[i]->op.S[s].boxA; }, r, nullptr, row_group(b.cls, false));
+        rows_items(rin, all, [&](int i) { return b.ds[i]->op.S[s].boxA; }, r, nullptr, row_group(b.cls, false),
+                   has);
         rows_items(rmid, all, [&](int i) { return b.ds[i]->op.S[1 - s].boxA; }, r, nullptr,
-                   row_group(b.cls, false));
+                   row_group(b.cls, false), has);
         for (int c = 0; c < r; ++c)
             for (int i : all)
-                for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) cols.h.push_back(Item{i, t, c, 0});
+                if (has(i, c))
+                    for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) cols.h.push_back(Item{i, t, c, 0});
+        slot_pad(b, rin);
+        slot_pad(b, rmid);
         if ((rc = rin.upload(st)) || (rc = rmid.upload(st)) || (rc = cols.upload(st))) return rc;
-        const int nin = d0->op.S[s].boxA, nmid = d0->op.S[1 - s].boxA;
         launch_row_in(b.f64, b.cls, rin.n(), st, b.ops(), b.lzs(), b.res(), rin.ptr(),
-                      RowInArgs{IN_VEC, s, 0, DEST_T1, 1.0, 0, nullptr});
-        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_CORR, nin, nmid, 1.0, nullptr}, b.ds[0]->MA, b.TC);
+                      RowInArgs{IN_VEC, s, 0, DEST_T1, 1.0, 0});
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_CORR, side_rows(s), side_rows(1 - s)},
+                   d0->MA, b.TC);
         launch_row_mid(b.f64, b.cls, rmid.n(), st, b.ops(), b.lzs(), b.res(), rmid.ptr(),
                        RowMidArgs{1 - s, OUT_VEC, 1.0, 1, 0, 0, 0, 0});
     }
     for (int c = 0; c < r; ++c)
-        for (int i : all) sg.h.push_back(Item{i, 0, c, 0});
+        for (int i : all)
+            if (has(i, c)) sg.h.push_back(Item{i, 0, c, 0});
     if ((rc = sg.upload(st))) return rc;
     launch_sign_fix(sg.n(), st, b.ops(), b.res(), sg.ptr());
     HIPCHK(hipGetLastError());
@@ -1298,7 +1370,8 @@ int run_finish(Batch& b) {
         HIPCHK(hipStreamSynchronize(st));
         for (int i = 0; i < ni; ++i) {
             auto* d = b.ds[i];
-            d->sigma_h.assign(static_cast<double*>(hb) + (size_t)i * r, static_cast<double*>(hb) + (size_t)(i + 1) * r);
+            const double* row = static_cast<double*>(hb) + (size_t)i * r;
+            d->sigma_h.assign(row, row + d->r);
             d->decomposed = true;
         }
     }
@@ -1332,11 +1405,13 @@ int run_reconstruct(Batch& b, const std::vector<int>& gptr, const std::vector<in
     if (d0->rowfam) {
         rows_items(a1, all, [&](int) { return 1; }, nc, &comps, row_group(b.cls, false));
         rows_items(out, all, [&](int i) { return b.ds[i]->A; }, ng);
+        slot_pad(b, a1);
+        slot_pad(b, out);
         if ((rc = a1.upload(st)) || (rc = out.upload(st))) return rc;
         launch_row_in(b.f64, b.cls, a1.n(), st, b.ops(), b.lzs(), b.res(), a1.ptr(),
-                      RowInArgs{IN_VEC, 0, 0, DEST_T1, 1.0, 0, nullptr});
+                      RowInArgs{IN_VEC, 0, 0, DEST_T1, 1.0, 0});
         launch_copy_uspec(b.f64, a1.n(), st, b.ops(), a1.ptr());
-        launch_rowfam_recon(b.f64, b.cls, out.n(), st, b.ops(), b.res(), out.ptr(), 1.0 / d0->MB);
+        launch_rowfam_recon(b.f64, b.cls, out.n(), st, b.ops(), b.res(), out.ptr(), -1.0);   // spec_scale
     } else {
         rows_items(a1, all, [&](int i) { return b.ds[i]->LA; }, nc, &comps, row_group(b.cls, false));
         rows_items(a2, all, [&](int i) { return b.ds[i]->KA; }, nc, &comps, row_group(b.cls, false));
@@ -1347,17 +1422,21 @@ int run_reconstruct(Batch& b, const std::vector<int>& gptr, const std::vector<in
         for (int g = 0; g < ng; ++g)
             for (int i : all)
                 for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) c2.h.push_back(Item{i, t, g, 0});
+        slot_pad(b, a1);
+        slot_pad(b, a2);
+        slot_pad(b, out);
         if ((rc = a1.upload(st)) || (rc = a2.upload(st)) || (rc = c1.upload(st)) || (rc = c2.upload(st)) ||
             (rc = out.upload(st)))
             return rc;
         launch_row_in(b.f64, b.cls, a1.n(), st, b.ops(), b.lzs(), b.res(), a1.ptr(),
-                      RowInArgs{IN_VEC, 0, 0, DEST_T1, 1.0, 0, nullptr});
-        launch_col(b.f64, c1.n(), st, b.ops(), b.res(), c1.ptr(), ColArgs{COL_STORE, d0->LA, 0, 1.0, nullptr}, b.ds[0]->MA, b.TC);
+                      RowInArgs{IN_VEC, 0, 0, DEST_T1, 1.0, 0});
+        launch_col(b.f64, c1.n(), st, b.ops(), b.res(), c1.ptr(), ColArgs{COL_STORE, ROWS_S0, 0}, d0->MA, b.TC);
         launch_row_in(b.f64, b.cls, a2.n(), st, b.ops(), b.lzs(), b.res(), a2.ptr(),
-                      RowInArgs{IN_VEC, 1, 0, DEST_T1, 1.0, 1, nullptr});
-        launch_col(b.f64, c2.n(), st, b.ops(), b.res(), c2.ptr(), ColArgs{COL_ACCUM, d0->KA, d0->A, 1.0, nullptr}, b.ds[0]->MA, b.TC);
+                      RowInArgs{IN_VEC, 1, 0, DEST_T1, 1.0, 1});
+        launch_col(b.f64, c2.n(), st, b.ops(), b.res(), c2.ptr(), ColArgs{COL_ACCUM, ROWS_S1, ROWS_ALL}, d0->MA,
+                   b.TC);
         launch_row_out(b.f64, b.cls, out.n(), st, b.ops(), b.lzs(), b.res(), out.ptr(),
-                       RowOutArgs{OUT_IMAGE, 0, 1.0 / ((double)d0->MA * d0->MB), 0, 0, 0});
+                       RowOutArgs{OUT_IMAGE, 0, -1.0, 0, 0, 0});   // each instance's spec_scale
     }
     HIPCHK(hipGetLastError());
     // keep the item lists alive until the work is done
@@ -1365,11 +1444,25 @@ int run_reconstruct(Batch& b, const std::vector<int>& gptr, const std::vector<in
     return SSA_OK;
 }
 
-// key of a batch: instances must share geometry, rank and precision
-using GeoKey = std::tuple<int, int, int, int, int, int, int, int, int, int, int>;
+// Kernel class of a request.  Requests of one class advance together
+// through the same kernels whatever their sizes and shapes (the descriptors
+// carry each instance's geometry): operator family, precision, short side,
+// row transform variant (row_word), column transform variant, and the basis
+// and restart sizes of the bidiagonalisation.  The origin count can only
+// shrink the basis of small problems; run_planned splits a batch again on
+// the sizes that hold after the count.
+using GeoKey = std::tuple<int, int, int, int, int, int, int>;
+int col_key(int MA) {
+    if (MA <= 1) return 0;                            // row family: no column pass
+    if (col_fast_logn(MA)) return MA;                 // register kernel of that length
+    return (MA & (MA - 1)) == 0 ? -2 : -1;            // LDS kernel, radix-2 or mixed plan
+}
 GeoKey geo_key(const ssa_decomp* d) {
-    return GeoKey{d->A, d->B, d->LA, d->LB, d->MA, d->MB, (int)d->tr, d->r, (int)d->f64, (int)d->rowfam,
-                  (int)d->L};
+    const int side = plan_side(d);
+    const long nshort = side == 0 ? d->L : (long)d->KA * d->KB;   // the origin box bounds |K|
+    const int m = basis_size(nshort, d->r);
+    return GeoKey{(int)d->rowfam, (int)d->f64, side, row_word(d->nh, d->f64), col_key(d->MA), m,
+                  restart_keep(m, d->r)};
 }
 
 int ensure_sub_streams(ssa_ctx* ctx, int n) {
@@ -1408,26 +1501,39 @@ void run_planned(ssa_ctx* ctx, const std::vector<ssa_decomp*>& grp, hipStream_t 
         else ok.push_back(grp[i]);
     }
     if (ok.empty()) return;
-    b.ds = ok;
-    rc = run_alloc_spectrum(b);
-    if (!rc) (void)hipStreamSynchronize(stream);
-    const double t_setup = ms_since(t0);
-    auto t1 = Clock::now();
-    if (!rc) rc = run_lanczos(b, 3000);
-    const double t_lz = ms_since(t1);
-    auto t2 = Clock::now();
-    if (!rc) rc = run_finish(b);
-    const double t_fin = ms_since(t2);
-    for (auto* d : b.ds) {
-        d->st.ms_setup = t_setup / b.ds.size();
-        d->st.ms_lanczos = t_lz / b.ds.size();
-        d->st.ms_finish = t_fin / b.ds.size();
-        d->st.side = d->side;
+    // sub-batches of equal basis and restart size (the origin count fixes
+    // the short side's size)
+    std::map<std::pair<int, int>, std::vector<ssa_decomp*>> parts;
+    for (auto* d : ok) {
+        choose_side(d);
+        const int m = basis_size(d->nshort, d->r);
+        parts[{m, restart_keep(m, d->r)}].push_back(d);
     }
-    for (int i = 0; i < n; ++i) {
-        if (rc) st[i] = rc;
-        else if (grp[i]->status != SSA_OK && st[i] == SSA_OK) st[i] = grp[i]->status;
+    double t_setup = ms_since(t0);
+    for (auto& kv : parts) {
+        b.ds = kv.second;
+        auto t1 = Clock::now();
+        rc = run_alloc_spectrum(b);
+        if (!rc) (void)hipStreamSynchronize(stream);
+        const double t_spec = ms_since(t1);
+        auto t2 = Clock::now();
+        if (!rc) rc = run_lanczos(b, 3000);
+        const double t_lz = ms_since(t2);
+        auto t3 = Clock::now();
+        if (!rc) rc = run_finish(b);
+        const double t_fin = ms_since(t3);
+        const double nb = (double)b.ds.size();
+        for (auto* d : b.ds) {
+            d->st.ms_setup = (t_setup + t_spec) / nb;
+            d->st.ms_lanczos = t_lz / nb;
+            d->st.ms_finish = t_fin / nb;
+            d->st.side = d->side;
+            d->st.batch = (int)b.ds.size();
+            if (rc) d->status = rc;
+        }
     }
+    for (int i = 0; i < n; ++i)
+        if (grp[i]->status != SSA_OK && st[i] == SSA_OK) st[i] = grp[i]->status;
 }
 
 int decompose_many(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** out, int* status, bool dev) {
@@ -2085,10 +2191,11 @@ int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* gp, const 
     if (n <= 0 || !d || !out_dev) return fail(SSA_EINVAL, "bad arguments");
     for (int i = 0; i < n; ++i) {
         if (!d[i] || !d[i]->decomposed) return fail(SSA_ESTATE, "not decomposed");
-        if (geo_key(d[i]) != geo_key(d[0])) return fail(SSA_EINVAL, "handles differ in geometry");
+        if (geo_key(d[i]) != geo_key(d[0])) return fail(SSA_EINVAL, "handles differ in kernel class");
         if (d[i]->tr) return fail(SSA_EINVAL, "device reconstruction needs a window more than one column wide");
     }
-    int rc = check_groups(d[0], gp, gi, ng);
+    int rc = SSA_OK;
+    for (int i = 0; i < n && !rc; ++i) rc = check_groups(d[i], gp, gi, ng);
     if (rc) return rc;
     g_tables_ctx = d[0]->ctx;
     TableScope tables(d[0]->ctx, d[0]->ctx->st);

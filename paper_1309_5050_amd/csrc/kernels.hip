@@ -207,8 +207,8 @@ k_row_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const R
     __shared__ cplx<T> twl[TwStage<T, NMAX, true>::kSize];
     const int slot = threadIdx.x / G, tid = threadIdx.x % G;
     const int it = blockIdx.x * SLOTS + slot;
-    const bool valid = it < nitems;
-    const Item item = items[valid ? it : nitems - 1];
+    const Item item = items[it < nitems ? it : nitems - 1];
+    const bool valid = it < nitems && item.aux >= 0;   // aux < 0: padding slot (no writes)
     const OpDesc& op = ops[item.inst];
     const FftPlan& prow = op.prow;
     const Tw<T> tw = stage_twiddles<T, NMAX, true>(prow, twl);
@@ -245,7 +245,7 @@ k_row_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const R
         for (int f = tid; f < n1; f += G) out[f] = s[f];
     } else {
         out = static_cast<cplx<T>*>(const_cast<void*>(op.Xh)) + (long)a * op.ldp;
-        const T scl = to<T>(args.scale);
+        const T scl = to<T>(args.scale < 0 ? op.spec_scale : args.scale);
         for (int f = tid; f < n1; f += G) out[f] = {s[f].x * scl, s[f].y * scl};
     }
 }
@@ -289,8 +289,8 @@ k_row_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     __shared__ double red[16];
     const int slot = threadIdx.x / G, tid = threadIdx.x % G;
     const int it = blockIdx.x * SLOTS + slot;
-    const bool valid = it < nitems;
-    const Item item = items[valid ? it : nitems - 1];
+    const Item item = items[it < nitems ? it : nitems - 1];
+    const bool valid = it < nitems && item.aux >= 0;   // aux < 0: padding slot (no writes)
     const OpDesc& op = ops[item.inst];
     const FftPlan& prow = op.prow;
     const Tw<T> tw = stage_twiddles<T, NMAX, true>(prow, twl);
@@ -383,8 +383,8 @@ k_row_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     __shared__ cplx<T> twl[TwStage<T, NMAX, true>::kSize];
     const int slot = threadIdx.x / G, tid = threadIdx.x % G;
     const int it = blockIdx.x * SLOTS + slot;
-    const bool valid = it < nitems;
-    const Item item = items[valid ? it : nitems - 1];
+    const Item item = items[it < nitems ? it : nitems - 1];
+    const bool valid = it < nitems && item.aux >= 0;   // aux < 0: padding slot (no writes)
     const OpDesc& op = ops[item.inst];
     const FftPlan& prow = op.prow;
     const Tw<T> tw = stage_twiddles<T, NMAX, true>(prow, twl);
@@ -398,12 +398,13 @@ k_row_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     rfft_inv<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
     if (args.mode == OUT_IMAGE) {
         if (!valid) return;
+        const double sc_img = args.scale < 0 ? op.spec_scale : args.scale;
         const ResDesc& rs = res[item.inst];
         double* out = rs.recon + (long)item.comp * op.A * op.B + (long)a * op.B;
         const double* W = op.W + (long)a * op.B;
         for (int b = tid; b < op.B; b += G) {
             const double w = W[b];
-            out[b] = w > 0 ? args.scale * static_cast<double>(sr[b]) / w : __builtin_nan("");
+            out[b] = w > 0 ? sc_img * static_cast<double>(sr[b]) / w : __builtin_nan("");
         }
         return;
     }
@@ -770,8 +771,8 @@ k_rowfam_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, con
     __shared__ double red[16];
     const int slot = threadIdx.x / G, tid = threadIdx.x % G;
     const int it = blockIdx.x * SLOTS + slot;
-    const bool valid = it < nitems;
-    const Item item = items[valid ? it : nitems - 1];
+    const Item item = items[it < nitems ? it : nitems - 1];
+    const bool valid = it < nitems && item.aux >= 0;   // aux < 0: padding slot (no writes)
     const OpDesc& op = ops[item.inst];
     const FftPlan& prow = op.prow;
     const Tw<T> tw = stage_twiddles<T, NMAX, true>(prow, twl);
@@ -836,8 +837,8 @@ k_rowfam_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs,
     __shared__ cplx<T> twl[TwStage<T, NMAX, true>::kSize];
     const int slot = threadIdx.x / G, tid = threadIdx.x % G;
     const int it = blockIdx.x * SLOTS + slot;
-    const bool valid = it < nitems;
-    const Item item = items[valid ? it : nitems - 1];
+    const Item item = items[it < nitems ? it : nitems - 1];
+    const bool valid = it < nitems && item.aux >= 0;   // aux < 0: padding slot (no writes)
     const OpDesc& op = ops[item.inst];
     const FftPlan& prow = op.prow;
     const Tw<T> tw = stage_twiddles<T, NMAX, true>(prow, twl);
@@ -872,8 +873,8 @@ k_rowfam_recon(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
     constexpr int PER = cdiv(NMAX + 1, G);
     const int slot = threadIdx.x / G, tid = threadIdx.x % G;
     const int it = blockIdx.x * SLOTS + slot;
-    const bool valid = it < nitems;
-    const Item item = items[valid ? it : nitems - 1];
+    const Item item = items[it < nitems ? it : nitems - 1];
+    const bool valid = it < nitems && item.aux >= 0;   // aux < 0: padding slot (no writes)
     const OpDesc& op = ops[item.inst];
     const FftPlan& prow = op.prow;
     const Tw<T> tw = stage_twiddles<T, NMAX, true>(prow, twl);
@@ -912,11 +913,12 @@ k_rowfam_recon(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
     __syncthreads();
     rfft_inv<T, NMAX, G, P2>(s, prow, tw.tw, tw.twr, tid);
     if (!valid) return;
+    const double sc_img = scale < 0 ? op.spec_scale : scale;
     double* out = rs.recon + (long)item.comp * op.A * op.B + (long)a * op.B;
     const double* W = op.W + (long)a * op.B;
     for (int b = tid; b < op.B; b += G) {
         const double w = W[b];
-        out[b] = w > 0 ? scale * static_cast<double>(sr[b]) / w : __builtin_nan("");
+        out[b] = w > 0 ? sc_img * static_cast<double>(sr[b]) / w : __builtin_nan("");
     }
 }
 
@@ -924,6 +926,7 @@ k_rowfam_recon(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
 template <typename T>
 __global__ void k_copy_uspec(const OpDesc* __restrict__ ops, const Item* __restrict__ items, int nitems) {
     const Item item = items[blockIdx.x];
+    if (item.aux < 0) return;   // padding item
     const OpDesc& op = ops[item.inst];
     const cplx<T>* src = static_cast<const cplx<T>*>(op.T1) + item.comp * op.tslot;
     cplx<T>* dst = static_cast<cplx<T>*>(op.Us) + item.comp * op.uslot;
@@ -975,7 +978,7 @@ col_body(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
         for (int p = 0; p < PER; ++p) acc[p] = {T(0), T(0)};
         for (int g = g0; g < g1; ++g) {
             const int i = rs.gidx[g];
-            load_rows(static_cast<const cplx<T>*>(op.T1) + i * op.tslot, args.nin);
+            load_rows(static_cast<const cplx<T>*>(op.T1) + i * op.tslot, col_rows(op, args.nin));
             __syncthreads();
             fft_lds<T, NMAX, G, -1, P2>(s, pcol, tw.tw, tid);
             const cplx<T>* uh = static_cast<const cplx<T>*>(op.Us) + (long)i * op.uslot;
@@ -995,13 +998,13 @@ col_body(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
         __syncthreads();
         fft_lds<T, NMAX, G, +1, P2>(s, pcol, tw.tw, tid);
     } else {
-        load_rows(static_cast<const cplx<T>*>(op.T1) + item.comp * op.tslot, args.nin);
+        load_rows(static_cast<const cplx<T>*>(op.T1) + item.comp * op.tslot, col_rows(op, args.nin));
         __syncthreads();
         fft_lds<T, NMAX, G, -1, P2>(s, pcol, tw.tw, tid);
         if (args.mode == COL_SPEC || args.mode == COL_STORE) {
             cplx<T>* dst = args.mode == COL_SPEC ? static_cast<cplx<T>*>(const_cast<void*>(op.Xh))
                                                  : static_cast<cplx<T>*>(op.Us) + (long)item.comp * op.uslot;
-            const T scl = to<T>(args.mode == COL_SPEC ? args.scale : 1.0);
+            const T scl = to<T>(args.mode == COL_SPEC ? op.spec_scale : 1.0);
             for (int e = threadIdx.x; e < MA * TC; e += nthr) {
                 const int cc = e / MA, a = e % MA;
                 const int f = f0 + cc;
@@ -1023,7 +1026,8 @@ col_body(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
         fft_lds<T, NMAX, G, +1, P2>(s, pcol, tw.tw, tid);
     }
     cplx<T>* out = static_cast<cplx<T>*>(op.T2) + item.comp * op.tslot;
-    for (int e = threadIdx.x; e < args.nout * TC; e += nthr) {
+    const int nout = col_rows(op, args.nout);
+    for (int e = threadIdx.x; e < nout * TC; e += nthr) {
         const int a = e / TC, cc = e % TC;
         const int f = f0 + cc;
         if (f < P) out[(long)a * op.ldp + f] = buf[cc * LD + a];
@@ -1051,6 +1055,7 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
     const long ld = op.ldp;
     const int f = item.idx * TC + c;
     const bool fok = f < P;
+    const int nin = col_rows(op, args.nin), nout = col_rows(op, args.nout);
     cplx<T> w[RP::NTW];
     reg_twiddles<T, LOGN>(static_cast<const cplx<T>*>(op.pcol.tw), t, w);
     // tile bases (uniform) and the thread's 32-bit offset within a tile
@@ -1062,18 +1067,18 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
     cplx<T> v[8], x[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e)
-        v[e] = (fok && t + G * e < args.nin) ? gload(src + e * estep + lo) : cplx<T>{T(0), T(0)};
+        v[e] = (fok && t + G * e < nin) ? gload(src + e * estep + lo) : cplx<T>{T(0), T(0)};
     if constexpr (!SPEC) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = fok ? gload(xh + e * estep + lo) : cplx<T>{T(0), T(0)};
     }
     const auto ad = [&](int pp) { return rx_addr<TC>(pp, c); };
     constexpr int XB = RP::LROWS * TC;
-    if (args.nin <= G) reg_fft<T, LOGN, -1, XS_WG2, true>(v, w, lds, t, ad, xe, XB);
+    if (nin <= G) reg_fft<T, LOGN, -1, XS_WG2, true>(v, w, lds, t, ad, xe, XB);
     else reg_fft<T, LOGN, -1, XS_WG2>(v, w, lds, t, ad, xe, XB);
     if constexpr (SPEC) {
         if (!fok) return;
-        const T sc = to<T>(args.scale);
+        const T sc = to<T>(op.spec_scale);
 #pragma unroll
         for (int e = 0; e < 8; ++e) gstore(xh + e * estep + lo, cplx<T>{v[e].x * sc, v[e].y * sc});
         return;
@@ -1082,9 +1087,9 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
         for (int e = 0; e < 8; ++e) v[e] = cmulc(x[e], v[e]);
         gptr<cplx<T>> dst = as_global(static_cast<cplx<T>*>(op.T2) + tile);
         if constexpr (RP::REM == 0) {
-            if (args.nout <= G) {
+            if (nout <= G) {
                 reg_fft<T, LOGN, +1, XS_WG2, false, true>(v, w, lds, t, ad, xe, XB);
-                if (fok && t < args.nout) gstore(dst + lo, v[0]);
+                if (fok && t < nout) gstore(dst + lo, v[0]);
                 return;
             }
         }
@@ -1092,7 +1097,7 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
         if (!fok) return;
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-            if (t + G * e < args.nout) gstore(dst + e * estep + lo, v[e]);
+            if (t + G * e < nout) gstore(dst + e * estep + lo, v[e]);
     }
 }
 
@@ -1294,6 +1299,7 @@ k_lz_start(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, unsig
     __shared__ double red[4];
     const Item item = items[blockIdx.x];
     const LzDesc& lz = lzs[item.inst];
+    seed ^= lz.seed;   // the decomposition's own seed: a result does not depend on its batch
     const long i = (long)item.idx * kLzRows + threadIdx.x;
     double v = 0.0;
     if (i < lz.n) {
@@ -1602,6 +1608,7 @@ k_lz_ritz(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m,
     const Item item = items[blockIdx.x];
     const LzDesc& lz = lzs[item.inst];
     double* out = outs ? outs[item.inst] : lz.Qtmp;
+    if (outs) k = k < lz.r ? k : lz.r;   // final vectors: this decomposition's r
     const int c0 = item.aux * 16;
     for (int e = threadIdx.x; e < m * 16; e += 256) {
         const int i = e / 16, cc = e % 16;
@@ -1684,6 +1691,7 @@ k_lz_restart_random(const LzDesc* __restrict__ lzs, const Item* __restrict__ ite
     __shared__ double red[4];
     const Item item = items[blockIdx.x];
     const LzDesc& lz = lzs[item.inst];
+    seed ^= lz.seed;
     const long i = (long)item.idx * kLzRows + threadIdx.x;
     double v = 0.0;
     if (i < lz.n) {
@@ -1786,7 +1794,8 @@ __global__ void k_gather_flags(const LzDesc* __restrict__ lzs, int ninst, int* _
 __global__ void k_gather_sigma(const ResDesc* __restrict__ res, int ninst, int r, double* __restrict__ out) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ninst * r) return;
-    out[e] = res[e / r].sigma[e % r];
+    const ResDesc& rs = res[e / r];
+    out[e] = e % r < rs.r ? rs.sigma[e % r] : 0.0;
 }
 
 }  // namespace shssa

@@ -229,6 +229,44 @@ def test_alone_equals_in_batch(ctx):
     assert np.array_equal(ra, rm, equal_nan=True)
 
 
+def _mixed_requests():
+    """Requests of different sizes and shapes in two kernel classes: four
+    images (square, oblong, transposed window box, shaped with holes and a
+    disc window) with r = 8 and three series of different lengths with
+    r = 6."""
+    big = W.image_2d(n=128, lw=12, r=8, seed=70)["x"]
+    rng = np.random.default_rng(71)
+    imgs = [big[:96, :96], big[:100, :112], big[:120, :90], big[5:95, 10:110].copy()]
+    imgs[3][rng.random(imgs[3].shape) < 0.02] = np.nan
+    wi, wj = np.mgrid[0:13, 0:13]
+    disc = ((wi - 6) ** 2 + (wj - 6) ** 2 <= 36).astype(np.uint8)
+    reqs = [dict(x=imgs[0], window=(12, 12), r=8), dict(x=imgs[1], window=(12, 12), r=8),
+            dict(x=imgs[2], window=(10, 14), r=8), dict(x=imgs[3], window=(13, 13), wmask=disc, r=8)]
+    for n in (700, 800, 900):
+        reqs.append(dict(x=W.series_1d(n=n, L=n // 3, r=6, seed=n)["x"], window=n // 3, r=6))
+    return reqs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mixed_sizes_alone_equal_in_batch(ctx, prec):
+    """Requests of different sizes share one batch per kernel class; each
+    result is bit-identical to the request decomposed alone, and matches the
+    oracle."""
+    reqs = _mixed_requests()
+    mix = ctx.decompose_batch(reqs, precision=prec)
+    assert [d.stats["batch"] for d in mix] == [4, 4, 4, 4, 3, 3, 3]
+    for q, m in zip(reqs, mix):
+        a = ctx.decompose_batch([q], precision=prec)[0]
+        assert a.stats["batch"] == 1
+        assert np.array_equal(a.sigma, m.sigma)
+        ua, va = a.vectors()
+        um, vm = m.vectors()
+        assert np.array_equal(ua, um, equal_nan=True) and np.array_equal(va, vm, equal_nan=True)
+        assert np.array_equal(a.reconstruct([[0, 1], [2]]), m.reconstruct([[0, 1], [2]]), equal_nan=True)
+        _, so, _, _ = oracle.decompose(q["x"], None, q.get("wmask"), q["window"])
+        assert sigma_err(m.sigma, so) <= TOL[prec]
+
+
 def test_errors(ctx):
     import paper_1309_5050_amd as S
     x = np.random.default_rng(1).standard_normal((20, 20))
