@@ -213,6 +213,12 @@ int ssa_ctx_sync(ssa_ctx* ctx);
  * launch must read and write).  ssa_ctx_profile_read returns the same over
  * all recorded classes and clears the record. */
 int ssa_ctx_profile(ssa_ctx* ctx, const char* kind);
+/* Time only one launch in every `every` (>= 1, default 1) of each class,
+ * counted from the last ssa_ctx_profile call: each timed launch costs a pair
+ * of event records on the stream (a few microseconds of idle device each),
+ * and a sample keeps that cost out of the work being measured.  An odd
+ * period samples both directions of the alternating column passes. */
+int ssa_ctx_profile_every(ssa_ctx* ctx, int every);
 int ssa_ctx_profile_read_kind(ssa_ctx* ctx, const char* kind, double* ms, long* launches, double* bytes);
 int ssa_ctx_profile_read(ssa_ctx* ctx, double* ms, long* launches, double* bytes);
 

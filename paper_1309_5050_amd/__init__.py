@@ -44,7 +44,10 @@ class Decomposition:
         self.shape = (nx.value, ny.value)
 
     def __del__(self):
-        self.free()
+        try:
+            self.free()
+        except TypeError:   # interpreter shutdown: the module's globals are already gone
+            pass
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -108,7 +111,10 @@ class Context:
         self._h = h
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except TypeError:   # interpreter shutdown: the module's globals are already gone
+            pass
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -125,8 +131,11 @@ class Context:
     def set_stream(self, stream):
         check(lib().ssa_ctx_set_stream(self._h, stream), "ssa_ctx_set_stream")
 
-    def profile(self, kind):
-        """Start (kind = kernel class name) or stop (None) event timing."""
+    def profile(self, kind, every: int = 1):
+        """Start (kind = comma-separated kernel classes) or stop (None) event
+        timing; with every > 1 only one launch in `every` of each class is
+        timed."""
+        check(lib().ssa_ctx_profile_every(self._h, int(every)), "ssa_ctx_profile_every")
         check(lib().ssa_ctx_profile(self._h, None if kind is None else kind.encode()), "ssa_ctx_profile")
 
     def profile_read(self, kinds=None) -> dict:

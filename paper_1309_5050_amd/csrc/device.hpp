@@ -53,6 +53,8 @@ struct LzDesc {
     double* np0;        // partial squared norms of w before its first projection, nblk
     void* lbuf[2];      // long vectors (operator precision), ping-pong by step parity
     double* lnp[2];     // partial squared norms of the long vectors, per long-set row
+    long lwords;        // 32-bit words of lbuf[0] and lbuf[1] together (contiguous)
+    int lrows;          // rows of lnp[0] and of lnp[1] (lnp[1] = lnp[0] + lrows)
     double* Bm;         // projected matrix, kMaxBasis x kMaxBasis column-major (rows: short)
     double* Yl;         // left singular vectors of Bm (kMaxBasis ld)
     double* Yr;         // right singular vectors of Bm

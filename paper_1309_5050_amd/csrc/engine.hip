@@ -116,6 +116,8 @@ struct ssa_ctx {
     }
     // kernel timing (see ssa_ctx_profile)
     std::vector<std::string> prof_kinds;   // kernel classes being timed
+    std::vector<long> prof_seen;           // launches of each class since timing started
+    int prof_every = 1;                    // time one launch in every prof_every of a class
     std::vector<hipEvent_t> ev_pool;
     struct Span {
         int e0, e1, kind;
@@ -666,9 +668,46 @@ struct DevVec {
 struct ItemList {
     std::vector<Item> h;
     DevVec d;
+    const Item* dp = nullptr;   // device copy inside another list's table (upload_lists)
     int n() const { return (int)h.size(); }
-    const Item* ptr() const { return d.as<Item>(); }
+    const Item* ptr() const { return dp ? dp : d.as<Item>(); }
+    int upload(hipStream_t st) {
+        dp = nullptr;
+        return d.put(h, st);
+    }
+};
+
+// Several item lists in one host-to-device copy: the first list's table
+// holds them all, the others point into it (valid while the first lives and
+// is not uploaded again).
+int upload_lists(std::initializer_list<ItemList*> ls, hipStream_t st) {
+    ItemList* own = *ls.begin();
+    std::vector<Item> all;
+    std::vector<size_t> off;
+    for (ItemList* L : ls) {
+        off.push_back(all.size());
+        all.insert(all.end(), L->h.begin(), L->h.end());
+    }
+    const int rc = own->d.put(all, st);
+    if (rc) return rc;
+    size_t k = 0;
+    for (ItemList* L : ls) L->dp = own->d.as<Item>() + off[k++];
+    return SSA_OK;
+}
+
+// Host tables of mixed types packed into one device block (one copy).
+struct TablePack {
+    std::vector<char> h;
+    DevVec d;
+    template <typename T>
+    size_t add(const std::vector<T>& v) {
+        const size_t off = (h.size() + 15) & ~size_t(15);
+        h.resize(off + std::max<size_t>(v.size(), 1) * sizeof(T));
+        if (!v.empty()) std::memcpy(h.data() + off, v.data(), v.size() * sizeof(T));
+        return off;
+    }
     int upload(hipStream_t st) { return d.put(h, st); }
+    template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(static_cast<char*>(d.p) + off); }
 };
 
 struct Batch {
@@ -720,6 +759,7 @@ struct ProfSpan {
         std::lock_guard<std::mutex> g(c->mu);
         const int k = c->prof_index(kind);
         if (k < 0) return;
+        if (c->prof_seen[k]++ % c->prof_every) return;   // not in the sample
         // both events are taken now, so spans of concurrent threads never share one
         e0 = c->prof_event();
         e1 = e0 >= 0 ? c->prof_event() : -1;
@@ -846,25 +886,25 @@ int run_setup(Batch& b) {
         pxc[i] = d->xc; pw[i] = d->W; pnp[i] = d->npref; pkp[i] = d->kpref;
         pkc[i] = d->kcount; pkr[i] = d->krow; nr[i] = d->KA;
     }
-    DevVec dpx, dpm, dpn, dpk, dpxc, dpw, dpnp, dpkp, dpkc, dpkr, dnr, dtot;
-    if ((rc = dpx.put(px, st)) || (rc = dpm.put(pm, st)) || (rc = dpn.put(pn, st)) || (rc = dpk.put(pk, st)) ||
-        (rc = dpxc.put(pxc, st)) || (rc = dpw.put(pw, st)) || (rc = dpnp.put(pnp, st)) ||
-        (rc = dpkp.put(pkp, st)) || (rc = dpkc.put(pkc, st)) || (rc = dpkr.put(pkr, st)) || (rc = dnr.put(nr, st)))
-        return rc;
     std::vector<long> tot(ni, 0);
-    if ((rc = dtot.put(tot, st))) return rc;
     ItemList rowsA, rowsK;
     rows_items(rowsA, all, [&](int i) { return b.ds[i]->A; });
     rows_items(rowsK, all, [&](int i) { return b.ds[i]->KA; });
-    if ((rc = rowsA.upload(st)) || (rc = rowsK.upload(st))) return rc;
-    launch_shape_clean(rowsA.n(), st, b.ops(), rowsA.ptr(), dpx.as<const double*>(), dpm.as<const uint8_t*>(),
-                       dpn.as<uint8_t*>(), dpxc.as<double*>(), dpnp.as<int*>());
-    launch_shape_origins(rowsK.n(), st, b.ops(), rowsK.ptr(), b.runs(), dpnp.as<const int*>(), dpk.as<uint8_t*>(),
-                         dpkp.as<int*>(), dpkc.as<int*>());
-    launch_shape_rowoff(ni, st, dpkc.as<const int*>(), dpkr.as<int*>(), dnr.as<int>(), dtot.as<long>());
-    launch_shape_weights(rowsA.n(), st, b.ops(), rowsA.ptr(), b.runs(), dpkp.as<const int*>(), dpw.as<double*>());
+    TablePack tp;
+    const size_t opx = tp.add(px), opm = tp.add(pm), opn = tp.add(pn), opk = tp.add(pk), opxc = tp.add(pxc),
+                 opw = tp.add(pw), opnp = tp.add(pnp), opkp = tp.add(pkp), opkc = tp.add(pkc), opkr = tp.add(pkr),
+                 onr = tp.add(nr), otot = tp.add(tot), oa = tp.add(rowsA.h), ok = tp.add(rowsK.h);
+    if ((rc = tp.upload(st))) return rc;
+    const Item* ia = tp.at<Item>(oa);
+    const Item* ik = tp.at<Item>(ok);
+    launch_shape_clean(rowsA.n(), st, b.ops(), ia, tp.at<const double*>(opx), tp.at<const uint8_t*>(opm),
+                       tp.at<uint8_t*>(opn), tp.at<double*>(opxc), tp.at<int*>(opnp));
+    launch_shape_origins(rowsK.n(), st, b.ops(), ik, b.runs(), tp.at<const int*>(opnp), tp.at<uint8_t*>(opk),
+                         tp.at<int*>(opkp), tp.at<int*>(opkc));
+    launch_shape_rowoff(ni, st, tp.at<const int*>(opkc), tp.at<int*>(opkr), tp.at<int>(onr), tp.at<long>(otot));
+    launch_shape_weights(rowsA.n(), st, b.ops(), ia, b.runs(), tp.at<const int*>(opkp), tp.at<double*>(opw));
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(tot.data(), dtot.p, ni * sizeof(long), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(tot.data(), tp.at<long>(otot), ni * sizeof(long), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int i = 0; i < ni; ++i) {
         auto* d = b.ds[i];
@@ -974,8 +1014,6 @@ int run_alloc_spectrum(Batch& b) {
             (rc = d->dalloc(&d->Qtmp, n * kMaxBasis)) || (rc = d->dalloc(&d->U, d->L * (long)d->r)) ||
             (rc = d->dalloc(&d->V, d->K * (long)d->r)) || (rc = d->dalloc(&d->sigma, d->r)))
             return rc;
-        HIPCHK(hipMemsetAsync(d->lnp, 0, 2 * longrows * sizeof(double), st));
-        HIPCHK(hipMemsetAsync(d->lbuf, 0, 2 * d->nlong * (d->f64 ? 8 : 4), st));
         // descriptors
         OpDesc& o = d->op;
         o.Xh = d->Xh; o.T1 = d->T1; o.T2 = d->T2; o.Us = d->Us;
@@ -1002,6 +1040,8 @@ int run_alloc_spectrum(Batch& b) {
         z.lbuf[1] = static_cast<char*>(d->lbuf) + d->nlong * (d->f64 ? 8 : 4);
         z.lnp[0] = d->lnp;
         z.lnp[1] = d->lnp + longrows;
+        z.lwords = 2 * d->nlong * (d->f64 ? 2 : 1);   // zeroed by the start kernel
+        z.lrows = (int)longrows;
         z.Bm = d->Bm; z.Yl = d->Yl; z.Yr = d->Yr; z.sig = d->sig; z.perm = d->perm;
         z.beta = d->beta; z.flag = d->flag; z.Qtmp = d->Qtmp;
         z.nblk = nblk;
@@ -1032,7 +1072,6 @@ int run_alloc_spectrum(Batch& b) {
             for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) cols.h.push_back(Item{i, t, 0, 0});
         if ((rc = cols.upload(st))) return rc;
         launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_SPEC, ROWS_ALL, 0}, d0->MA, b.TC);
-        HIPCHK(hipStreamSynchronize(st));
     }
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipGetLastError());
@@ -1074,11 +1113,7 @@ void build_step_lists(Batch& b, const std::vector<int>& act, StepLists& S) {
 }
 
 int upload_step_lists(StepLists& S, hipStream_t st) {
-    int rc;
-    if ((rc = S.rin.upload(st)) || (rc = S.cols.upload(st)) || (rc = S.rmid.upload(st)) ||
-        (rc = S.rout.upload(st)) || (rc = S.lzb.upload(st)) || (rc = S.inst.upload(st)))
-        return rc;
-    return SSA_OK;
+    return upload_lists({&S.rin, &S.cols, &S.rmid, &S.rout, &S.lzb, &S.inst}, st);
 }
 
 void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode) {
@@ -1269,10 +1304,11 @@ int run_lanczos(Batch& b, int max_steps) {
                     for (int cb = 0; cb < (b.ds[i]->r + 15) / 16; ++cb) R.h.push_back(Item{i, (int)rb, 0, cb});
                 I.h.push_back(Item{i, 0, 0, 0});
             }
-            if ((rc = R.upload(st)) || (rc = I.upload(st))) return rc;
+            if ((rc = upload_lists({&R, &I}, st))) return rc;
             launch_lz_ritz(R.n(), st, b.lzs(), R.ptr(), m, rmax, douts.as<double*>());
             launch_lz_sigma(I.n(), st, b.lzs(), b.res(), I.ptr());
-            HIPCHK(hipStreamSynchronize(st));
+            // no wait: the tables are released into the call's table cache,
+            // which returns them to the pool only after the stream drains
         }
         if (cont.empty()) break;
         {
@@ -1286,7 +1322,7 @@ int run_lanczos(Batch& b, int max_steps) {
                 for (int k = 0; k < b.ds[i]->lz.nblk; ++k)
                     (isfresh[i] ? F : Z).h.push_back(Item{i, k, 0, 0});
             }
-            if ((rc = R.upload(st)) || (rc = Z.upload(st)) || (rc = F.upload(st))) return rc;
+            if ((rc = upload_lists({&R, &Z, &F}, st))) return rc;
             launch_lz_ritz(R.n(), st, b.lzs(), R.ptr(), m, kk, nullptr);
             launch_lz_restart(Z.n(), st, b.lzs(), Z.ptr(), m, kk);
             if (F.n() > 0) {
@@ -1296,7 +1332,6 @@ int run_lanczos(Batch& b, int max_steps) {
                 launch_lz_proj2(F.n(), st, b.lzs(), F.ptr(), kk, 1);
                 launch_lz_update(F.n(), st, b.lzs(), F.ptr(), kk, 2, 1);
             }
-            HIPCHK(hipStreamSynchronize(st));
         }
         act = cont;
         build_step_lists(b, act, S);
@@ -1882,10 +1917,19 @@ int ssa_ctx_profile(ssa_ctx* ctx, const char* kind) {
             }
         }
     }
+    ctx->prof_seen.assign(ctx->prof_kinds.size(), 0);
     if (!ctx->prof_kinds.empty()) {
         if (!ctx->prof_ref) HIPCHK(hipEventCreate(&ctx->prof_ref));
         HIPCHK(hipEventRecord(ctx->prof_ref, ctx->st));
     }
+    return SSA_OK;
+}
+
+int ssa_ctx_profile_every(ssa_ctx* ctx, int every) {
+    if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
+    if (every < 1) return fail(SSA_EINVAL, "every must be >= 1");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->prof_every = every;
     return SSA_OK;
 }
 

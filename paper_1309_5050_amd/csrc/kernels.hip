@@ -1310,6 +1310,16 @@ k_lz_start(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, unsig
     if (lane_id() == 0) red[threadIdx.x >> 6] = p;
     __syncthreads();
     if (threadIdx.x == 0) lz.np[item.idx] = red[0] + red[1] + red[2] + red[3];
+    // clear this block's share of the long vectors and their row norms
+    {
+        const long wc = (lz.lwords + lz.nblk - 1) / lz.nblk;
+        const long w0 = (long)item.idx * wc, w1 = min(lz.lwords, w0 + wc);
+        uint32_t* lw = static_cast<uint32_t*>(lz.lbuf[0]);
+        for (long e = w0 + threadIdx.x; e < w1; e += 256) lw[e] = 0u;
+        const int rc = (2 * lz.lrows + lz.nblk - 1) / lz.nblk;
+        const int r0 = item.idx * rc, r1 = min(2 * lz.lrows, r0 + rc);
+        for (int e = r0 + threadIdx.x; e < r1; e += 256) lz.lnp[0][e] = 0.0;
+    }
     // clear the projected matrix, the breakdown flags and the running scale
     if (item.idx == 0) {
         for (int e = threadIdx.x; e < kMaxBasis * kMaxBasis; e += 256) lz.Bm[e] = 0.0;
