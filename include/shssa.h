@@ -30,7 +30,16 @@
  * Handles are owned by the library and released with ssa_free /
  * ssa_ctx_destroy.  Functions ending in _dev take device pointers on the
  * context's device and work on the context's stream; all others take host
- * pointers and return after the work is complete.
+ * pointers.
+ *
+ * Completion.  A decomposition call returns once the bidiagonalisation has
+ * converged (it waits for each restart's convergence test) with the last
+ * kernels of the decomposition (the other-side vectors and the sign rule)
+ * still queued on the stream; ssa_reconstruct_batch_dev returns with all of
+ * its work queued.  The getters (ssa_get_sigma, ssa_get_vectors,
+ * ssa_get_weights) and ssa_reconstruct wait for the handle's queued work.
+ * A handle may be freed at any time: its device memory is reused only after
+ * the work queued on it has completed.
  *
  * Errors.  Every int-returning function returns SSA_OK (0) or a negative
  * code; ssa_strerror gives a message, ssa_last_error the detail of the last
@@ -86,6 +95,7 @@ typedef struct ssa_stats {
     int converged;          /* 1 if every triplet met the residual test */
     int side;               /* 0: basis on the window side, 1: origin side */
     int batch;              /* decompositions that advanced together in its batch */
+    int svd_sweeps;         /* Jacobi sweeps of the projected-matrix SVDs, summed over cycles */
     double max_resid;       /* largest residual bound |X v - s u| / sigma_1 */
     double ms_setup, ms_lanczos, ms_finish;
     size_t device_bytes;    /* device memory held by the handle */

@@ -25,7 +25,7 @@ class Request(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("steps", C.c_int), ("restarts", C.c_int), ("basis", C.c_int), ("converged", C.c_int),
-                ("side", C.c_int), ("batch", C.c_int), ("max_resid", C.c_double), ("ms_setup", C.c_double),
+                ("side", C.c_int), ("batch", C.c_int), ("svd_sweeps", C.c_int), ("max_resid", C.c_double), ("ms_setup", C.c_double),
                 ("ms_lanczos", C.c_double), ("ms_finish", C.c_double), ("device_bytes", C.c_size_t)]
 
 

@@ -164,6 +164,10 @@ struct ssa_ctx {
             return hipMalloc(&p, cls) == hipSuccess ? p : nullptr;
         }
         auto it = pool.find(cls);
+        if ((it == pool.end() || it->second.empty()) && !deferred.empty()) {
+            reclaim();
+            it = pool.find(cls);
+        }
         if (it != pool.end() && !it->second.empty()) {
             void* p = it->second.back();
             it->second.pop_back();
@@ -188,6 +192,49 @@ struct ssa_ctx {
         }
         pool[cls].push_back(p);
         pooled += cls;
+    }
+
+    // Blocks whose last users may still be queued on a stream go back to
+    // the pool once an event recorded after those users has completed, so
+    // library calls return without waiting for their work (caller holds mu).
+    struct Deferred {
+        hipEvent_t ev;
+        std::vector<std::pair<void*, size_t>> blocks;
+    };
+    std::vector<Deferred> deferred;
+    std::vector<hipEvent_t> spare_ev;
+    void defer(std::vector<std::pair<void*, size_t>>& blocks, hipStream_t s) {
+        if (blocks.empty()) return;
+        hipEvent_t e = nullptr;
+        if (!spare_ev.empty()) {
+            e = spare_ev.back();
+            spare_ev.pop_back();
+        } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            e = nullptr;
+        }
+        if (!e || hipEventRecord(e, s) != hipSuccess) {
+            // no event: wait for the stream instead
+            (void)hipStreamSynchronize(s);
+            for (auto& b : blocks) pool_put(b.first, b.second);
+            if (e) spare_ev.push_back(e);
+        } else {
+            deferred.push_back(Deferred{e, {}});
+            deferred.back().blocks.swap(blocks);
+        }
+        blocks.clear();
+    }
+    void reclaim() {
+        size_t k = 0;
+        for (size_t i = 0; i < deferred.size(); ++i) {
+            if (hipEventQuery(deferred[i].ev) == hipSuccess) {
+                for (auto& b : deferred[i].blocks) pool_put(b.first, b.second);
+                spare_ev.push_back(deferred[i].ev);
+            } else {
+                if (k != i) deferred[k] = std::move(deferred[i]);
+                ++k;
+            }
+        }
+        deferred.resize(k);
     }
 
     // Pinned host staging for uploads, one per stream.  Two halves are
@@ -336,7 +383,9 @@ struct ssa_decomp {
     std::vector<int> lrow_h;         // LA + 1
     std::vector<int> ra, rb0, rb1;   // window runs (internal)
     std::vector<uint8_t> kmask_h;    // internal KA x KB (fetched on demand)
-    std::vector<double> sigma_h;
+    std::vector<double> sigma_h;     // filled from the device on first request
+    bool sigma_ready = false;
+    hipStream_t last_st = nullptr;   // stream of the last work queued on this handle
     // device memory (blocks of the context pool, with their size class)
     std::vector<std::pair<void*, size_t>> allocs;
     size_t bytes = 0;
@@ -386,6 +435,13 @@ namespace {
 
 void ctx_release(ssa_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->st);
+    for (auto x : ctx->sub_st) (void)hipStreamSynchronize(x);
+    for (auto& df : ctx->deferred) {
+        (void)hipEventSynchronize(df.ev);
+        for (auto& b : df.blocks) (void)hipFree(b.first);
+        (void)hipEventDestroy(df.ev);
+    }
+    for (auto e : ctx->spare_ev) (void)hipEventDestroy(e);
     for (auto& kv : ctx->tw) (void)hipFree(kv.second);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->prof_ref) (void)hipEventDestroy(ctx->prof_ref);
@@ -408,7 +464,11 @@ ssa_decomp::~ssa_decomp() {
     bool last = false;
     {
         std::lock_guard<std::mutex> g(ctx->mu);
-        for (auto& a : allocs) ctx->pool_put(a.first, a.second);
+        if (last_st) {
+            ctx->defer(allocs, last_st);   // queued work may still use the blocks
+        } else {
+            for (auto& a : allocs) ctx->pool_put(a.first, a.second);
+        }
         ctx->used -= std::min(ctx->used, bytes);
         ctx->refs--;
         last = ctx->closing && ctx->refs == 0;
@@ -498,6 +558,7 @@ int plan_request(ssa_ctx* ctx, const ssa_request& q, ssa_decomp* d) {
 int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStream_t st) {
     const long n = (long)d->A * d->B;
     int rc;
+    d->last_st = st;
     if ((rc = d->dalloc(&d->x, n))) return rc;
     if (q.mask && (rc = d->dalloc(&d->mask, n))) return rc;
     if (dev_input) {
@@ -601,9 +662,10 @@ void flush_table_cache(ssa_ctx* ctx) {
     g_table_cache->clear();
 }
 
-// Scope of a synchronous library call on stream st: table blocks released
-// inside it return to the shared pool only after st has drained (serving
-// workers on other streams share the pool).
+// Scope of a library call on stream st: table blocks released inside it
+// return to the shared pool only after the work queued on st so far has
+// completed (serving workers on other streams share the pool); the call
+// itself does not wait.
 struct TableScope {
     ssa_ctx* ctx;
     hipStream_t st;
@@ -617,8 +679,10 @@ struct TableScope {
     }
     ~TableScope() {
         if (!owner) return;
-        (void)hipStreamSynchronize(st);
-        flush_table_cache(ctx);
+        {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            ctx->defer(cache, st);
+        }
         g_table_cache = nullptr;
     }
 };
@@ -715,16 +779,21 @@ struct Batch {
     hipStream_t st;
     std::vector<ssa_decomp*> ds;      // instance i = ds[i]
     bool f64 = true, rowfam = false;
-    int cls = 0, TC = 16;       // row size class (| 8: radix-2/4/8 plan), column tile
+    int cls = 0, TC = 16, CV = 0;   // row size class (| 8: radix-2/4/8 plan), column tile and variant
     DevVec dops, dlz, dres, druns;
     std::vector<OpDesc> hops;
     std::vector<LzDesc> hlz;
     std::vector<ResDesc> hres;
     std::vector<Runs> hruns;
-    // per-batch scratch for flags and stats
-    DevVec dflag, dbeta;
+    // per-batch scratch for the convergence flags
+    DevVec dflag;
 
     explicit Batch(ssa_ctx* c) : ctx(c), st(c->st) {}
+    int colcfg() const { return TC | CV << 8; }
+    void set_col(int cfg) {
+        TC = cfg & 0xff;
+        CV = cfg >> 8;
+    }
     Batch(ssa_ctx* c, hipStream_t s) : ctx(c), st(s) {}
 
     int upload_descs() {
@@ -918,25 +987,27 @@ int run_setup(Batch& b) {
     return SSA_OK;
 }
 
-// Column tile autotuner: the first batch of a (precision, column length)
-// times the column product passes of one bidiagonalisation step (on the
-// batch's own spectrum; the buffers they write are scratch at this point)
-// with every compiled tile width and keeps the fastest for the context.  The
-// spectrum pass itself is idempotent.  SHSSA_COL_TILE forces a width.
+// Column autotuner: the first batch of a (precision, column length) times
+// the column product passes of one bidiagonalisation step (on the batch's
+// own spectrum; the buffers they write are scratch at this point) with every
+// compiled configuration (tile width x kernel variant) and keeps the fastest
+// for the context.  The spectrum pass itself is idempotent.  SHSSA_COL_TILE
+// forces a configuration (tile + 256 * variant); SHSSA_TUNE_LOG prints the
+// timings.
 int tune_col_tile(Batch& b) {
     std::lock_guard<std::mutex> tune_lock(b.ctx->tune_mu);
     const auto* d0 = b.ds[0];
     const auto key = std::make_pair((int)b.f64, d0->MA);
     if (const char* e = std::getenv("SHSSA_COL_TILE")) {
-        const int tc = std::atoi(e);
-        if (col_tile_ok(b.f64, d0->MA, tc)) {
-            b.TC = tc;
+        const int cfg = std::atoi(e);
+        if (col_tile_ok(b.f64, d0->MA, cfg)) {
+            b.set_col(cfg);
             return SSA_OK;
         }
     }
     auto it = b.ctx->col_tc.find(key);
     if (it != b.ctx->col_tc.end()) {
-        b.TC = it->second;
+        b.set_col(it->second);
         return SSA_OK;
     }
     hipStream_t st = b.st;
@@ -946,40 +1017,43 @@ int tune_col_tile(Batch& b) {
     HIPCHK(hipEventCreate(&e1));
     float best = 1e30f;
     int best_tc = col_tile(b.f64);
-    const int cands32[] = {4, 8, 16}, cands64[] = {2, 4};
+    const int cands32[] = {4, 8, 16, 4 | 256, 8 | 256, 16 | 256}, cands64[] = {2, 4, 2 | 256, 4 | 256};
     const int* cands = b.f64 ? cands64 : cands32;
-    const int nc = b.f64 ? 2 : 3;
+    const int nc = b.f64 ? 4 : 6;
     int rc = SSA_OK;
     for (int k = 0; k < nc && rc == SSA_OK; ++k) {
-        const int tc = cands[k];
-        if (!col_tile_ok(b.f64, d0->MA, tc)) continue;
+        const int cfg = cands[k], tc = cfg & 0xff;
+        if (!col_tile_ok(b.f64, d0->MA, cfg)) continue;
         ItemList cols;
         for (int i = 0; i < ni; ++i)
             for (int t = 0; t < (b.ds[i]->P + tc - 1) / tc; ++t) cols.h.push_back(Item{i, t, 0, 0});
         if ((rc = cols.upload(st))) break;
         // the spectrum pass (also the warm-up), then the two product passes
         // of a bidiagonalisation step, timed
-        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_SPEC, ROWS_ALL, 0}, d0->MA, tc);
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_SPEC, ROWS_ALL, 0}, d0->MA, cfg);
         const ColArgs fw{COL_CORR, side_rows(d0->side), side_rows(1 - d0->side)};
         const ColArgs bw{COL_CORR, side_rows(1 - d0->side), side_rows(d0->side)};
         (void)hipEventRecord(e0, st);
         for (int rep = 0; rep < 4; ++rep) {
-            launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), fw, b.ds[0]->MA, tc);
-            launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), bw, b.ds[0]->MA, tc);
+            launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), fw, b.ds[0]->MA, cfg);
+            launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), bw, b.ds[0]->MA, cfg);
         }
         (void)hipEventRecord(e1, st);
         if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SSA_EDEVICE, "tuning"); break; }
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        // the default tile is kept unless another is clearly (5%) faster
-        if (tc == col_tile(b.f64)) ms *= 0.95f;
-        if (ms < best) { best = ms; best_tc = tc; }
+        if (std::getenv("SHSSA_TUNE_LOG"))
+            std::fprintf(stderr, "column tuner: MA %d f64 %d tile %d variant %d: %.3f ms\n", d0->MA, (int)b.f64, tc,
+                         cfg >> 8, ms / 8);
+        // the default is kept unless another configuration is clearly (5%) faster
+        if (cfg == col_tile(b.f64)) ms *= 0.95f;
+        if (ms < best) { best = ms; best_tc = cfg; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     b.ctx->col_tc[key] = best_tc;
-    b.TC = best_tc;
+    b.set_col(best_tc);
     return SSA_OK;
 }
 
@@ -1071,7 +1145,7 @@ int run_alloc_spectrum(Batch& b) {
         for (int i = 0; i < ni; ++i)
             for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) cols.h.push_back(Item{i, t, 0, 0});
         if ((rc = cols.upload(st))) return rc;
-        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_SPEC, ROWS_ALL, 0}, d0->MA, b.TC);
+        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_SPEC, ROWS_ALL, 0}, d0->MA, b.colcfg());
     }
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipGetLastError());
@@ -1150,7 +1224,7 @@ void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode) {
         {
             ProfSpan p(b.ctx, "col", st, col_bytes(b, S.cols, nin, nmid));
             launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(),
-                       ColArgs{COL_CORR, nin, nmid}, d0->MA, b.TC);
+                       ColArgs{COL_CORR, nin, nmid}, d0->MA, b.colcfg());
         }
         {
             ProfSpan p(b.ctx, "row_mid", st, row_bytes(b, S.rmid, 1, 1, vl2));
@@ -1160,7 +1234,7 @@ void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode) {
         {
             ProfSpan p(b.ctx, "col", st, col_bytes(b, S.cols, nmid, nin));
             launch_col(b.f64, S.cols.n(), st, b.ops(), b.res(), S.cols.ptr(),
-                       ColArgs{COL_CORR, nmid, nin}, d0->MA, b.TC);
+                       ColArgs{COL_CORR, nmid, nin}, d0->MA, b.colcfg());
         }
         {
             ProfSpan p(b.ctx, "row_out", st, row_bytes(b, S.rout, 1, 0, vs2));
@@ -1195,7 +1269,7 @@ int basis_size(long nshort, int r) {
 // Ritz vectors kept by a thick restart of a basis of size m.
 int restart_keep(int m, int r) { return std::min(m - 1, r + (m - r) / 2); }
 
-int run_lanczos(Batch& b, int max_steps) {
+int run_lanczos(Batch& b, int max_steps, const std::function<int()>& overlap = nullptr) {
     hipStream_t st = b.st;
     const int ni = (int)b.ds.size();
     int rc;
@@ -1226,6 +1300,7 @@ int run_lanczos(Batch& b, int max_steps) {
         launch_lz_normalize(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), m);
         launch_lz_svd(S.inst.n(), st, b.lzs(), S.inst.ptr(), m, 40);
         HIPCHK(hipGetLastError());
+        if (cycle == 0 && overlap && (rc = overlap())) return rc;   // host work while the cycle runs
         {
             // one gather kernel and one copy into pinned memory for the batch
             const size_t fb = (size_t)ni * 4 * sizeof(int), bb = (size_t)ni * 2 * sizeof(double);
@@ -1269,6 +1344,7 @@ int run_lanczos(Batch& b, int max_steps) {
         std::vector<int> done, cont, fresh;
         for (int i : act) {
             steps[i] += m - jstart;
+            b.ds[i]->st.svd_sweeps += flags[4 * i + 1];
             const bool ok = flags[4 * i] != 0;
             const bool bd = flags[4 * i + 2] != 0;
             auto* d = b.ds[i];
@@ -1342,12 +1418,15 @@ int run_lanczos(Batch& b, int max_steps) {
     return SSA_OK;
 }
 
-// Long-side vectors of the final triplets (V = X^T U / sigma or
-// U = X V / sigma), then the sign rule.
-int run_finish(Batch& b) {
-    hipStream_t st = b.st;
+// Item lists of the final pass (built and uploaded while the first
+// bidiagonalisation cycle runs on the device).
+struct FinishLists {
+    ItemList rin, cols, rmid, sg;
+    bool ready = false;
+};
+
+int finish_lists(Batch& b, FinishLists& F) {
     const int ni = (int)b.ds.size();
-    int rc;
     std::vector<int> all(ni);
     for (int i = 0; i < ni; ++i) all[i] = i;
     const auto* d0 = b.ds[0];
@@ -1356,59 +1435,60 @@ int run_finish(Batch& b) {
     const int s = d0->side;
     // component c of the instances with r > c
     const auto has = [&](int i, int c) { return c < b.ds[i]->r; };
-    ItemList rin, cols, rmid, sg;
     if (d0->rowfam) {
-        rows_items(rin, all, [&](int) { return 1; }, r, nullptr, row_group(b.cls, false), has);
-        rows_items(rmid, all, [&](int i) { return b.ds[i]->A; }, r, nullptr, 1, has);
-        slot_pad(b, rin);
-        slot_pad(b, rmid);
-        if ((rc = rin.upload(st)) || (rc = rmid.upload(st))) return rc;
-        launch_row_in(b.f64, b.cls, rin.n(), st, b.ops(), b.lzs(), b.res(), rin.ptr(),
-                      RowInArgs{IN_VEC, 0, 0, DEST_T1, 1.0, 0});
-        launch_rowfam_mid(b.f64, b.cls, rmid.n(), st, b.ops(), b.lzs(), b.res(), rmid.ptr(),
-                          RowFamArgs{OUT_VEC, 0, 0, 0, 0});
+        rows_items(F.rin, all, [&](int) { return 1; }, r, nullptr, row_group(b.cls, false), has);
+        rows_items(F.rmid, all, [&](int i) { return b.ds[i]->A; }, r, nullptr, 1, has);
+        F.cols.h.clear();
     } else {
-        rows_items(rin, all, [&](int i) { return b.ds[i]->op.S[s].boxA; }, r, nullptr, row_group(b.cls, false),
+        rows_items(F.rin, all, [&](int i) { return b.ds[i]->op.S[s].boxA; }, r, nullptr, row_group(b.cls, false),
                    has);
-        rows_items(rmid, all, [&](int i) { return b.ds[i]->op.S[1 - s].boxA; }, r, nullptr,
+        rows_items(F.rmid, all, [&](int i) { return b.ds[i]->op.S[1 - s].boxA; }, r, nullptr,
                    row_group(b.cls, false), has);
+        F.cols.h.clear();
         for (int c = 0; c < r; ++c)
             for (int i : all)
                 if (has(i, c))
-                    for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) cols.h.push_back(Item{i, t, c, 0});
-        slot_pad(b, rin);
-        slot_pad(b, rmid);
-        if ((rc = rin.upload(st)) || (rc = rmid.upload(st)) || (rc = cols.upload(st))) return rc;
-        launch_row_in(b.f64, b.cls, rin.n(), st, b.ops(), b.lzs(), b.res(), rin.ptr(),
-                      RowInArgs{IN_VEC, s, 0, DEST_T1, 1.0, 0});
-        launch_col(b.f64, cols.n(), st, b.ops(), b.res(), cols.ptr(), ColArgs{COL_CORR, side_rows(s), side_rows(1 - s)},
-                   d0->MA, b.TC);
-        launch_row_mid(b.f64, b.cls, rmid.n(), st, b.ops(), b.lzs(), b.res(), rmid.ptr(),
-                       RowMidArgs{1 - s, OUT_VEC, 1.0, 1, 0, 0, 0, 0});
+                    for (int t = 0; t < (b.ds[i]->P + b.TC - 1) / b.TC; ++t) F.cols.h.push_back(Item{i, t, c, 0});
     }
+    slot_pad(b, F.rin);
+    slot_pad(b, F.rmid);
+    F.sg.h.clear();
     for (int c = 0; c < r; ++c)
         for (int i : all)
-            if (has(i, c)) sg.h.push_back(Item{i, 0, c, 0});
-    if ((rc = sg.upload(st))) return rc;
-    launch_sign_fix(sg.n(), st, b.ops(), b.res(), sg.ptr());
+            if (has(i, c)) F.sg.h.push_back(Item{i, 0, c, 0});
+    const int rc = upload_lists({&F.rin, &F.cols, &F.rmid, &F.sg}, b.st);
+    F.ready = rc == SSA_OK;
+    return rc;
+}
+
+// Long-side vectors of the final triplets (V = X^T U / sigma or
+// U = X V / sigma), then the sign rule.
+int run_finish(Batch& b, FinishLists& F) {
+    hipStream_t st = b.st;
+    int rc;
+    if (!F.ready && (rc = finish_lists(b, F))) return rc;
+    const auto* d0 = b.ds[0];
+    const int s = d0->side;
+    if (d0->rowfam) {
+        launch_row_in(b.f64, b.cls, F.rin.n(), st, b.ops(), b.lzs(), b.res(), F.rin.ptr(),
+                      RowInArgs{IN_VEC, 0, 0, DEST_T1, 1.0, 0});
+        launch_rowfam_mid(b.f64, b.cls, F.rmid.n(), st, b.ops(), b.lzs(), b.res(), F.rmid.ptr(),
+                          RowFamArgs{OUT_VEC, 0, 0, 0, 0});
+    } else {
+        launch_row_in(b.f64, b.cls, F.rin.n(), st, b.ops(), b.lzs(), b.res(), F.rin.ptr(),
+                      RowInArgs{IN_VEC, s, 0, DEST_T1, 1.0, 0});
+        launch_col(b.f64, F.cols.n(), st, b.ops(), b.res(), F.cols.ptr(),
+                   ColArgs{COL_CORR, side_rows(s), side_rows(1 - s)}, d0->MA, b.colcfg());
+        launch_row_mid(b.f64, b.cls, F.rmid.n(), st, b.ops(), b.lzs(), b.res(), F.rmid.ptr(),
+                       RowMidArgs{1 - s, OUT_VEC, 1.0, 1, 0, 0, 0, 0});
+    }
+    launch_sign_fix(F.sg.n(), st, b.ops(), b.res(), F.sg.ptr());
     HIPCHK(hipGetLastError());
-    {
-        const size_t nb = (size_t)ni * r * sizeof(double);
-        if (!b.dbeta.p || b.dbeta.cap < nb) {
-            std::vector<char> z(nb, 0);
-            if ((rc = b.dbeta.put(z, st))) return rc;
-        }
-        launch_gather_sigma(ni, r, st, b.res(), b.dbeta.as<double>());
-        void* hb = nullptr;
-        if ((rc = b.ctx->readback_buf(st, nb, &hb))) return rc;
-        HIPCHK(hipMemcpyAsync(hb, b.dbeta.p, nb, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        for (int i = 0; i < ni; ++i) {
-            auto* d = b.ds[i];
-            const double* row = static_cast<double*>(hb) + (size_t)i * r;
-            d->sigma_h.assign(row, row + d->r);
-            d->decomposed = true;
-        }
+    // the singular values are read back when first asked for
+    for (auto* d : b.ds) {
+        d->decomposed = true;
+        d->sigma_ready = false;
+        d->last_st = st;
     }
     return SSA_OK;
 }
@@ -1465,17 +1545,16 @@ int run_reconstruct(Batch& b, const std::vector<int>& gptr, const std::vector<in
             return rc;
         launch_row_in(b.f64, b.cls, a1.n(), st, b.ops(), b.lzs(), b.res(), a1.ptr(),
                       RowInArgs{IN_VEC, 0, 0, DEST_T1, 1.0, 0});
-        launch_col(b.f64, c1.n(), st, b.ops(), b.res(), c1.ptr(), ColArgs{COL_STORE, ROWS_S0, 0}, d0->MA, b.TC);
+        launch_col(b.f64, c1.n(), st, b.ops(), b.res(), c1.ptr(), ColArgs{COL_STORE, ROWS_S0, 0}, d0->MA, b.colcfg());
         launch_row_in(b.f64, b.cls, a2.n(), st, b.ops(), b.lzs(), b.res(), a2.ptr(),
                       RowInArgs{IN_VEC, 1, 0, DEST_T1, 1.0, 1});
         launch_col(b.f64, c2.n(), st, b.ops(), b.res(), c2.ptr(), ColArgs{COL_ACCUM, ROWS_S1, ROWS_ALL}, d0->MA,
-                   b.TC);
+                   b.colcfg());
         launch_row_out(b.f64, b.cls, out.n(), st, b.ops(), b.lzs(), b.res(), out.ptr(),
                        RowOutArgs{OUT_IMAGE, 0, -1.0, 0, 0, 0});   // each instance's spec_scale
     }
     HIPCHK(hipGetLastError());
-    // keep the item lists alive until the work is done
-    HIPCHK(hipStreamSynchronize(st));
+    for (auto* d : b.ds) d->last_st = st;
     return SSA_OK;
 }
 
@@ -1517,12 +1596,13 @@ void run_planned(ssa_ctx* ctx, const std::vector<ssa_decomp*>& grp, hipStream_t 
     const int n = (int)grp.size();
     st.assign(n, SSA_OK);
     if (n == 0) return;
+    for (auto* d : grp) d->last_st = stream;
     Batch b(ctx, stream);
     b.ds = grp;
     b.f64 = b.ds[0]->f64;
     b.rowfam = b.ds[0]->rowfam;
     b.cls = row_word(b.ds[0]->nh, b.f64);
-    b.TC = ctx->tile_for(b.f64, b.ds[0]->MA);
+    b.set_col(ctx->tile_for(b.f64, b.ds[0]->MA));
     auto t0 = Clock::now();
     int rc = run_setup(b);
     if (rc) {
@@ -1552,10 +1632,11 @@ void run_planned(ssa_ctx* ctx, const std::vector<ssa_decomp*>& grp, hipStream_t 
         if (!rc) (void)hipStreamSynchronize(stream);
         const double t_spec = ms_since(t1);
         auto t2 = Clock::now();
-        if (!rc) rc = run_lanczos(b, 3000);
+        FinishLists F;
+        if (!rc) rc = run_lanczos(b, 3000, [&] { return finish_lists(b, F); });
         const double t_lz = ms_since(t2);
         auto t3 = Clock::now();
-        if (!rc) rc = run_finish(b);
+        if (!rc) rc = run_finish(b, F);
         const double t_fin = ms_since(t3);
         const double nb = (double)b.ds.size();
         for (auto* d : b.ds) {
@@ -1623,11 +1704,16 @@ int decompose_many(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** ou
                 auto* prev = g_table_cache;
                 g_table_cache = &cache;
                 run_planned(ctx, parts[0], ctx->sub_st[0], pst[0]);
-                (void)hipStreamSynchronize(ctx->sub_st[0]);
-                flush_table_cache(ctx);
+                {
+                    std::lock_guard<std::mutex> g(ctx->mu);
+                    ctx->defer(cache, ctx->sub_st[0]);
+                }
                 g_table_cache = prev;
             }
             for (auto& t : th) t.join();
+            // the handles leave the sub-batch streams complete
+            for (int q = 0; q < ns; ++q) HIPCHK(hipStreamSynchronize(ctx->sub_st[q]));
+            for (auto* d : grp) d->last_st = nullptr;
             for (int q = 0; q < ns; ++q) gst.insert(gst.end(), pst[q].begin(), pst[q].end());
         }
         for (size_t k = 0; k < kv.second.size(); ++k) st[kv.second[k]] = gst[k];
@@ -1636,6 +1722,13 @@ int decompose_many(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** ou
         if (status) status[i] = st[i];
         if (st[i] == SSA_OK || st[i] == SSA_ENOCONV) out[i] = ds[i].release();
     }
+    return SSA_OK;
+}
+
+// Wait for the work queued on a handle (library calls return before it
+// completes); its device results are then final.
+int wait_handle(ssa_decomp* d) {
+    if (d->last_st) HIPCHK(hipStreamSynchronize(d->last_st));
     return SSA_OK;
 }
 
@@ -1724,7 +1817,7 @@ Batch make_batch(ssa_ctx* ctx, hipStream_t st, const std::vector<ssa_decomp*>& d
     b.f64 = ds[0]->f64;
     b.rowfam = ds[0]->rowfam;
     b.cls = row_word(ds[0]->nh, b.f64);
-    b.TC = ctx->tile_for(b.f64, ds[0]->MA);
+    b.set_col(ctx->tile_for(b.f64, ds[0]->MA));
     return b;
 }
 
@@ -1797,6 +1890,9 @@ void serve_batch(ssa_ctx* ctx, std::vector<std::shared_ptr<ServeReq>>& batch, hi
         }
     }
     (void)hipStreamSynchronize(st);
+    // handed to the caller complete: nothing refers to the worker's stream
+    for (auto& r : batch)
+        if (r->d) r->d->last_st = nullptr;
 }
 
 // Admission: the oldest request starts when its estimate fits the budget
@@ -2092,9 +2188,17 @@ int ssa_get_dims(const ssa_decomp* d, int* lx, int* ly, int* kx, int* ky, long* 
     return SSA_OK;
 }
 
-int ssa_get_sigma(const ssa_decomp* d, double* sigma) {
+int ssa_get_sigma(const ssa_decomp* dc, double* sigma) {
+    auto* d = const_cast<ssa_decomp*>(dc);
     if (!d || !sigma) return fail(SSA_EINVAL, "NULL argument");
     if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
+    if (!d->sigma_ready) {
+        int rc;
+        if ((rc = wait_handle(d))) return rc;
+        d->sigma_h.resize(d->r);
+        HIPCHK(hipMemcpy(d->sigma_h.data(), d->sigma, d->r * sizeof(double), hipMemcpyDeviceToHost));
+        d->sigma_ready = true;
+    }
     std::memcpy(sigma, d->sigma_h.data(), d->r * sizeof(double));
     return SSA_OK;
 }
@@ -2104,6 +2208,7 @@ int ssa_get_vectors(const ssa_decomp* dc, double* U, double* V) {
     if (!d) return fail(SSA_EINVAL, "handle is NULL");
     if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
     int rc;
+    if ((rc = wait_handle(d))) return rc;
     if (U) {
         std::vector<double> u((size_t)d->L * d->r);
         HIPCHK(hipMemcpy(u.data(), d->U, u.size() * 8, hipMemcpyDeviceToHost));
@@ -2172,8 +2277,11 @@ int ssa_get_vectors_lex(const ssa_decomp* dc, double* U, double* V) {
     return SSA_OK;
 }
 
-int ssa_get_weights(const ssa_decomp* d, double* w) {
+int ssa_get_weights(const ssa_decomp* dc, double* w) {
+    auto* d = const_cast<ssa_decomp*>(dc);
     if (!d || !w) return fail(SSA_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = wait_handle(d))) return rc;
     const long n = (long)d->A * d->B;
     if (!d->tr) {
         HIPCHK(hipMemcpy(w, d->W, n * 8, hipMemcpyDeviceToHost));
@@ -2212,8 +2320,9 @@ int ssa_reconstruct(ssa_decomp* d, const int* gp, const int* gi, int ng, double*
     b.f64 = d->f64;
     b.rowfam = d->rowfam;
     b.cls = row_word(d->nh, d->f64);
-    b.TC = d->ctx->tile_for(d->f64, d->MA);
+    b.set_col(d->ctx->tile_for(d->f64, d->MA));
     rc = run_reconstruct(b, std::vector<int>(gp, gp + ng + 1), std::vector<int>(gi, gi + gp[ng]), {buf});
+    if (!rc && hipStreamSynchronize(b.st) != hipSuccess) rc = fail(SSA_EDEVICE, "reconstruction");
     if (!rc) {
         if (!d->tr) {
             if (hipMemcpy(out, buf, n * ng * 8, hipMemcpyDeviceToHost) != hipSuccess) rc = fail(SSA_EDEVICE, "copy");
@@ -2248,7 +2357,7 @@ int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* gp, const 
     b.f64 = d[0]->f64;
     b.rowfam = d[0]->rowfam;
     b.cls = row_word(d[0]->nh, d[0]->f64);
-    b.TC = d[0]->ctx->tile_for(d[0]->f64, d[0]->MA);
+    b.set_col(d[0]->ctx->tile_for(d[0]->f64, d[0]->MA));
     return run_reconstruct(b, std::vector<int>(gp, gp + ng + 1), std::vector<int>(gi, gi + gp[ng]),
                            std::vector<double*>(out_dev, out_dev + n));
 }

@@ -1041,12 +1041,18 @@ col_body(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
 // of a row.  The spectrum is stored like T1 and T2: [MA rows][P bins].
 //   SPEC:  Xh = scale * FFT_col(T1 rows < nin)
 //   !SPEC: T2 rows < nout = IFFT_col(Xh * conj(FFT_col(T1 rows < nin)))
-template <typename T, int LOGN, int TC, bool SPEC>
+// LTW: twiddles from a table in LDS and one exchange buffer (two barriers
+// per exchange): fewer registers and less LDS per workgroup, so more
+// workgroups per compute unit; otherwise twiddles in registers and two
+// exchange buffers used in turn.
+template <typename T, int LOGN, int TC, bool SPEC, bool LTW>
 __global__ void __launch_bounds__(RegPlan<LOGN>::G * TC)
 k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs args) {
     using RP = RegPlan<LOGN>;
     constexpr int G = RP::G;
-    __shared__ cplx<T> lds[2 * RP::LROWS * TC];
+    constexpr int XB = RP::LROWS * TC;
+    constexpr int XSM = LTW ? XS_WG : XS_WG2;
+    __shared__ cplx<T> lds[(LTW ? 1 : 2) * XB + (LTW ? RP::N : 0)];
     const Item item = items[xcd_block(blockIdx.x, gridDim.x)];
     int xe = 0;
     const OpDesc& op = ops[item.inst];
@@ -1056,8 +1062,19 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
     const int f = item.idx * TC + c;
     const bool fok = f < P;
     const int nin = col_rows(op, args.nin), nout = col_rows(op, args.nout);
-    cplx<T> w[RP::NTW];
-    reg_twiddles<T, LOGN>(static_cast<const cplx<T>*>(op.pcol.tw), t, w);
+    cplx<T> w[LTW ? 1 : RP::NTW];
+    cplx<T>* tab = lds + XB;
+    if constexpr (LTW) {
+        // read first after an exchange barrier (the first pass has no twiddles)
+        const gptr<const cplx<T>> tw = as_global(static_cast<const cplx<T>*>(op.pcol.tw));
+        for (int i = threadIdx.x; i < RP::N; i += G * TC) tab[i] = gload(tw + i);
+    } else {
+        reg_twiddles<T, LOGN>(static_cast<const cplx<T>*>(op.pcol.tw), t, w);
+    }
+    const auto W = [&](int q) -> cplx<T> {
+        if constexpr (LTW) return TwTable<T, LOGN>{tab, t}(q);
+        else return w[q];
+    };
     // tile bases (uniform) and the thread's 32-bit offset within a tile
     const long tile = item.comp * op.tslot + (long)item.idx * TC;
     const long estep = (long)G * ld;
@@ -1073,9 +1090,8 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
         for (int e = 0; e < 8; ++e) x[e] = fok ? gload(xh + e * estep + lo) : cplx<T>{T(0), T(0)};
     }
     const auto ad = [&](int pp) { return rx_addr<TC>(pp, c); };
-    constexpr int XB = RP::LROWS * TC;
-    if (nin <= G) reg_fft<T, LOGN, -1, XS_WG2, true>(v, w, lds, t, ad, xe, XB);
-    else reg_fft<T, LOGN, -1, XS_WG2>(v, w, lds, t, ad, xe, XB);
+    if (nin <= G) reg_fft_tw<T, LOGN, -1, XSM, true>(v, W, lds, t, ad, xe, XB);
+    else reg_fft_tw<T, LOGN, -1, XSM>(v, W, lds, t, ad, xe, XB);
     if constexpr (SPEC) {
         if (!fok) return;
         const T sc = to<T>(op.spec_scale);
@@ -1088,12 +1104,12 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
         gptr<cplx<T>> dst = as_global(static_cast<cplx<T>*>(op.T2) + tile);
         if constexpr (RP::REM == 0) {
             if (nout <= G) {
-                reg_fft<T, LOGN, +1, XS_WG2, false, true>(v, w, lds, t, ad, xe, XB);
+                reg_fft_tw<T, LOGN, +1, XSM, false, true>(v, W, lds, t, ad, xe, XB);
                 if (fok && t < nout) gstore(dst + lo, v[0]);
                 return;
             }
         }
-        reg_fft<T, LOGN, +1, XS_WG2>(v, w, lds, t, ad, xe, XB);
+        reg_fft_tw<T, LOGN, +1, XSM>(v, W, lds, t, ad, xe, XB);
         if (!fok) return;
 #pragma unroll
         for (int e = 0; e < 8; ++e)
@@ -1799,13 +1815,6 @@ __global__ void k_gather_flags(const LzDesc* __restrict__ lzs, int ninst, int* _
     const LzDesc& z = lzs[i];
     for (int k = 0; k < 4; ++k) flags[4 * i + k] = z.flag[k];
     for (int k = 0; k < 2; ++k) betas[2 * i + k] = z.beta[k];
-}
-
-__global__ void k_gather_sigma(const ResDesc* __restrict__ res, int ninst, int r, double* __restrict__ out) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= ninst * r) return;
-    const ResDesc& rs = res[e / r];
-    out[e] = e % r < rs.r ? rs.sigma[e % r] : 0.0;
 }
 
 }  // namespace shssa

@@ -10,8 +10,8 @@ int row_slots(int cls);
 // item per group of rows (instance, first row, component, row count); the
 // dense modes and the LDS kernels one item per row.
 int row_group(int cls, bool dense);
-int col_tile(bool f64);                 // default column tile
-bool col_tile_ok(bool f64, int MA, int tc);   // tile widths compiled for the precision and length
+int col_tile(bool f64);                 // default column configuration (tile width, variant 0)
+bool col_tile_ok(bool f64, int MA, int cfg);  // configurations compiled for the precision and length
 int col_fast_logn(int MA);              // log2(MA) when the register column kernel applies, else 0
 
 void launch_row_in(bool f64, int cls, int nitems, hipStream_t st, const OpDesc* ops, const LzDesc* lzs,
@@ -29,7 +29,7 @@ void launch_rowfam_recon(bool f64, int cls, int nitems, hipStream_t st, const Op
 void launch_copy_uspec(bool f64, int nitems, hipStream_t st, const OpDesc* ops, const Item* items);
 // cls: row size class, plus 8 when the row plan has radices 2, 4, 8 only.
 void launch_col(bool f64, int nitems, hipStream_t st, const OpDesc* ops, const ResDesc* res, const Item* items,
-                ColArgs a, int MA, int tc);
+                ColArgs a, int MA, int cfg);   // cfg: tile | variant << 8
 void launch_shape_clean(int nitems, hipStream_t st, const OpDesc* ops, const Item* items, const double* const* x,
                         const uint8_t* const* m, uint8_t* const* nset, double* const* xc, int* const* npref);
 void launch_shape_origins(int nitems, hipStream_t st, const OpDesc* ops, const Item* items, const Runs* runs,
@@ -53,7 +53,6 @@ void launch_lz_restart_random(int nitems, hipStream_t st, const LzDesc* lzs, con
 void launch_lz_sigma(int ninst, hipStream_t st, const LzDesc* lzs, const ResDesc* res, const Item* items);
 void launch_sign_fix(int nitems, hipStream_t st, const OpDesc* ops, const ResDesc* res, const Item* items);
 void launch_gather_flags(int ninst, hipStream_t st, const LzDesc* lzs, int* flags, double* betas);
-void launch_gather_sigma(int ninst, int r, hipStream_t st, const ResDesc* res, double* out);
 void launch_transpose(int nmat, int R, int C, hipStream_t st, const double* in, double* out);
 
 }  // namespace shssa

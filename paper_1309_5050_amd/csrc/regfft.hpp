@@ -72,6 +72,26 @@ __device__ __forceinline__ void reg_twiddles(const cplx<T>* __restrict__ twp, in
     }
 }
 
+// The same twiddles looked up in a table of all N values w^k staged in LDS
+// (shared by the workgroup): twiddle q of thread t, numbered as in
+// reg_twiddles.  Costs an LDS read per use instead of NTW registers.
+template <typename T, int LOGN>
+struct TwTable {
+    const cplx<T>* tab;
+    int t;
+    __device__ __forceinline__ cplx<T> operator()(int q) const {
+        using RP = RegPlan<LOGN>;
+        if (q < 7 * (RP::P8 - 1)) {
+            const int p = q / 7 + 1, r = q % 7 + 1;
+            const int Ns = 1 << (3 * p);
+            return tab[r * ((t & (Ns - 1)) * (RP::N / (8 * Ns)))];
+        }
+        const int q2 = q - 7 * (RP::P8 - 1);
+        const int b = q2 / (RP::R - 1), r = q2 % (RP::R - 1) + 1;
+        return tab[r * (t + b * RP::G)];
+    }
+};
+
 // Exchange synchronisation.  XS_WG: transforms spread over the waves of a
 // workgroup, one LDS buffer (barrier after the writes and after the reads).
 // XS_WG2: the same with two buffers used in turn (one barrier per exchange:
@@ -108,9 +128,11 @@ __device__ __forceinline__ cplx<T> twiddle(cplx<T> a, cplx<T> w) {
 // SPARSE_IN: only slot 0 of the input is nonzero (the first pass is a
 // broadcast).  FIRST_OUT: only slot 0 of the output is used (the last radix-8
 // pass computes its first output only); valid when LOGN is a multiple of 3.
-template <typename T, int LOGN, int DIR, int XS, bool SPARSE_IN = false, bool FIRST_OUT = false, typename AD>
-__device__ __forceinline__ void reg_fft(cplx<T> (&v)[8], const cplx<T> (&w)[RegPlan<LOGN>::NTW],
-                                        cplx<T>* lds, int t, AD ad, int& xe, int xbuf = 0) {
+// W(q) gives twiddle q of the thread (registers or TwTable).
+template <typename T, int LOGN, int DIR, int XS, bool SPARSE_IN = false, bool FIRST_OUT = false, typename TW,
+          typename AD>
+__device__ __forceinline__ void reg_fft_tw(cplx<T> (&v)[8], TW W, cplx<T>* lds, int t, AD ad, int& xe,
+                                           int xbuf = 0) {
     using RP = RegPlan<LOGN>;
     constexpr int G = RP::G;
     constexpr int NPASS = RP::P8 + (RP::REM ? 1 : 0);
@@ -122,7 +144,7 @@ __device__ __forceinline__ void reg_fft(cplx<T> (&v)[8], const cplx<T> (&w)[RegP
         const int Ns = 1 << (3 * p);
         if (p > 0) {
 #pragma unroll
-            for (int r = 1; r < 8; ++r) v[r] = twiddle<T, DIR>(v[r], w[7 * (p - 1) + r - 1]);
+            for (int r = 1; r < 8; ++r) v[r] = twiddle<T, DIR>(v[r], W(7 * (p - 1) + r - 1));
         }
         if (p == NPASS - 1 && FIRST_OUT) {
             cplx<T> s0 = v[0];
@@ -159,13 +181,19 @@ __device__ __forceinline__ void reg_fft(cplx<T> (&v)[8], const cplx<T> (&w)[RegP
 #pragma unroll
             for (int r = 0; r < R; ++r) a[r] = v[b + B * r];
 #pragma unroll
-            for (int r = 1; r < R; ++r) a[r] = twiddle<T, DIR>(a[r], w[w0 + b * (R - 1) + r - 1]);
+            for (int r = 1; r < R; ++r) a[r] = twiddle<T, DIR>(a[r], W(w0 + b * (R - 1) + r - 1));
             if constexpr (R == 2) bf2<T, DIR>(a);
             else bf4<T, DIR>(a);
 #pragma unroll
             for (int r = 0; r < R; ++r) v[b + B * r] = a[r];
         }
     }
+}
+
+template <typename T, int LOGN, int DIR, int XS, bool SPARSE_IN = false, bool FIRST_OUT = false, typename AD>
+__device__ __forceinline__ void reg_fft(cplx<T> (&v)[8], const cplx<T> (&w)[RegPlan<LOGN>::NTW],
+                                        cplx<T>* lds, int t, AD ad, int& xe, int xbuf = 0) {
+    reg_fft_tw<T, LOGN, DIR, XS, SPARSE_IN, FIRST_OUT>(v, [&](int q) { return w[q]; }, lds, t, ad, xe, xbuf);
 }
 
 }  // namespace shssa

@@ -267,6 +267,37 @@ def test_mixed_sizes_alone_equal_in_batch(ctx, prec):
         assert sigma_err(m.sigma, so) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_column_configurations_agree(prec, monkeypatch):
+    """Every column configuration the tuner can pick (tile width x kernel
+    variant) computes the same column transforms: the results match the
+    oracle and each other (the variants differ only in where twiddles and
+    exchanges live, so only the compiler's choice of fused multiply-adds can
+    differ: agreement to rounding, not bit for bit)."""
+    import paper_1309_5050_amd as S
+    w = W.image_2d(n=128, lw=16, r=6, seed=90)       # column transforms of length 128
+    _, so, _, _ = oracle.decompose(w["x"], None, None, (16, 16))
+    cfgs = [2, 4, 2 + 256, 4 + 256] if prec == "fp64" else [4, 8, 16, 4 + 256, 8 + 256, 16 + 256]
+    ref = None
+    for cfg in cfgs:
+        monkeypatch.setenv("SHSSA_COL_TILE", str(cfg))
+        c = S.Context(0)
+        try:
+            d = c.decompose(w["x"], (16, 16), 6, precision=prec)
+            sig, rec = d.sigma, d.reconstruct([[0, 1]])
+            d.free()
+        finally:
+            c.close()
+        assert sigma_err(sig, so) <= TOL[prec], cfg
+        if ref is None:
+            ref = (sig, rec)
+        else:
+            assert sigma_err(sig, ref[0]) <= TOL[prec], cfg
+            assert np.array_equal(np.isnan(rec), np.isnan(ref[1])), cfg
+            scale = np.linalg.norm(np.nan_to_num(w["x"]))
+            assert np.linalg.norm(np.nan_to_num(rec - ref[1])) <= 20 * TOL[prec] * scale, cfg
+
+
 def test_errors(ctx):
     import paper_1309_5050_amd as S
     x = np.random.default_rng(1).standard_normal((20, 20))
