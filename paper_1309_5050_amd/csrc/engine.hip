@@ -1377,7 +1377,7 @@ int run_lanczos(Batch& b, int max_steps, const std::function<int()>& overlap = n
             for (int i : done) {
                 const long n = b.ds[i]->nshort;
                 for (long rb = 0; rb < (n + 63) / 64; ++rb)
-                    for (int cb = 0; cb < (b.ds[i]->r + 15) / 16; ++cb) R.h.push_back(Item{i, (int)rb, 0, cb});
+                    for (int cb = 0; cb < (b.ds[i]->r + 31) / 32; ++cb) R.h.push_back(Item{i, (int)rb, 0, cb});
                 I.h.push_back(Item{i, 0, 0, 0});
             }
             if ((rc = upload_lists({&R, &I}, st))) return rc;
@@ -1394,7 +1394,7 @@ int run_lanczos(Batch& b, int max_steps, const std::function<int()>& overlap = n
             for (int i : cont) {
                 const long n = b.ds[i]->nshort;
                 for (long rb = 0; rb < (n + 63) / 64; ++rb)
-                    for (int cb = 0; cb < (kk + 15) / 16; ++cb) R.h.push_back(Item{i, (int)rb, 0, cb});
+                    for (int cb = 0; cb < (kk + 31) / 32; ++cb) R.h.push_back(Item{i, (int)rb, 0, cb});
                 for (int k = 0; k < b.ds[i]->lz.nblk; ++k)
                     (isfresh[i] ? F : Z).h.push_back(Item{i, k, 0, 0});
             }

@@ -459,9 +459,8 @@ __device__ __forceinline__ double lane_group_sum(double v) {
 // Z_k = E'_k + i O'_k for the thread's bins: E'_k = X_k + conj X_{n-k},
 // O'_k = (X_k - conj X_{n-k}) conj(W^k), W = exp(-2 pi i/2n); the inverse
 // complex transform of Z gives 2n x as pairs.  row: bins 0..n of the row.
-template <typename T, int LOGN>
-__device__ __forceinline__ void row_unsplit(gptr<const cplx<T>> row, const cplx<T> (&wr)[8], int t,
-                                            cplx<T> (&v)[8]) {
+template <typename T, int LOGN, typename WRF>
+__device__ __forceinline__ void row_unsplit(gptr<const cplx<T>> row, WRF wr, int t, cplx<T> (&v)[8]) {
     constexpr int N = RowReg<LOGN>::N, G = RowReg<LOGN>::G;
     const gptr<const cplx<T>> lo = row + t, hi = row + (N - t);
     cplx<T> X[8], Y[8];
@@ -474,7 +473,7 @@ __device__ __forceinline__ void row_unsplit(gptr<const cplx<T>> row, const cplx<
     for (int e = 0; e < 8; ++e) {
         const cplx<T> ep = {X[e].x + Y[e].x, X[e].y - Y[e].y};
         const cplx<T> d = {X[e].x - Y[e].x, X[e].y + Y[e].y};
-        const cplx<T> o = cmulc(d, wr[e]);
+        const cplx<T> o = cmulc(d, wr(e));
         v[e] = {ep.x - o.y, ep.y + o.x};
     }
 }
@@ -483,9 +482,9 @@ __device__ __forceinline__ void row_unsplit(gptr<const cplx<T>> row, const cplx<
 // transform: X_k = E_k + W^k O_k with E_k = (Z_k + conj Z_{n-k})/2,
 // O_k = (Z_k - conj Z_{n-k})/(2i); X_n = E_0 - O_0.  Z_{n-k} comes from the
 // partner thread through LDS.  Writes the thread's bins of row.
-template <typename T, int LOGN, typename AD>
-__device__ __forceinline__ void row_split_store(const cplx<T> (&v)[8], const cplx<T> (&wr)[8], cplx<T>* lds, AD ad,
-                                                int t, gptr<cplx<T>> row, bool write) {
+template <typename T, int LOGN, typename WRF, typename AD>
+__device__ __forceinline__ void row_split_store(const cplx<T> (&v)[8], WRF wr, cplx<T>* lds, AD ad, int t,
+                                                gptr<cplx<T>> row, bool write) {
     constexpr int N = RowReg<LOGN>::N, G = RowReg<LOGN>::G;
     constexpr int RS = G + G / 8;
     const int pw = rx_pad(t), pn = t ? rx_pad(G - t) : 0;
@@ -503,7 +502,7 @@ __device__ __forceinline__ void row_split_store(const cplx<T> (&v)[8], const cpl
         const cplx<T> zk = v[e];
         const cplx<T> E = {T(0.5) * (zk.x + zn[e].x), T(0.5) * (zk.y - zn[e].y)};
         const cplx<T> O = {T(0.5) * (zk.y + zn[e].y), T(-0.5) * (zk.x - zn[e].x)};
-        const cplx<T> wo = cmul(wr[e], O);
+        const cplx<T> wo = cmul(wr(e), O);
         gstore(out + G * e, cadd(E, wo));
         if (e == 0 && t == 0) gstore(row + N, csub(E, O));
     }
@@ -566,14 +565,34 @@ __device__ __forceinline__ void dense_or_masked(const CellSet& S, F body) {
 template <typename T>
 __device__ __forceinline__ T& pair_part(cplx<T>& z, int h) { return h ? z.y : z.x; }
 
+// Twiddles of the register row kernels: the complex transform's (W) and the
+// real split's (WR, w^k of length 2n at the thread's bins k = t + G e), both
+// tables (2n values) staged once in LDS for the workgroup by stage() (which
+// has a barrier).  Reading them from LDS at each use keeps them off the
+// registers and off the global-load latency of every transform.
 template <typename T, int LOGN>
-__device__ __forceinline__ void row_reg_setup(const FftPlan& prow, int t, cplx<T> (&w)[RegPlan<LOGN>::NTW],
-                                              cplx<T> (&wr)[8]) {
-    reg_twiddles<T, LOGN>(static_cast<const cplx<T>*>(prow.tw), t, w);
-    const gptr<const cplx<T>> twr = as_global(static_cast<const cplx<T>*>(prow.twr)) + t;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) wr[e] = gload(twr + RowReg<LOGN>::G * e);
-}
+struct RowTw {
+    static constexpr int N = RowReg<LOGN>::N, G = RowReg<LOGN>::G;
+    static constexpr int LDS = 2 * N;   // LDS values
+    cplx<T>* tab;
+    int t;
+    __device__ __forceinline__ RowTw(cplx<T>* table, int tt) : tab(table), t(tt) {}
+    __device__ __forceinline__ void stage(const FftPlan& prow) {
+        const gptr<const cplx<T>> tw = as_global(static_cast<const cplx<T>*>(prow.tw));
+        const gptr<const cplx<T>> twr = as_global(static_cast<const cplx<T>*>(prow.twr));
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            tab[i] = gload(tw + i);
+            tab[N + i] = gload(twr + i);
+        }
+        __syncthreads();
+    }
+    __device__ __forceinline__ auto W() const {
+        return [this](int q) -> cplx<T> { return TwTable<T, LOGN>{tab, t}(q); };
+    }
+    __device__ __forceinline__ auto WR() const {
+        return [this](int e) -> cplx<T> { return tab[N + t + G * e]; };
+    }
+};
 
 template <typename T>
 __device__ __forceinline__ gptr<cplx<T>> spec_row(void* base, long slot, int a, int ldp) {
@@ -588,12 +607,15 @@ k_rowr_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
           const Item* __restrict__ items, int nitems, RowInArgs args) {
     using RR = RowReg<LOGN>;
     constexpr int G = RR::G;
-    __shared__ cplx<T> lds[RR::RPW * RegPlan<LOGN>::LROWS];
+    constexpr int XB = RR::RPW * RegPlan<LOGN>::LROWS;
+    __shared__ cplx<T> lds[XB + RowTw<T, LOGN>::LDS];
     const int c = threadIdx.x / G, t = threadIdx.x % G;
     const Item item = items[blockIdx.x];
     const bool valid = c < item.aux;
     const int a = item.idx + (valid ? c : 0);
     const OpDesc& op = ops[item.inst];
+    RowTw<T, LOGN> tw(lds + XB, t);
+    tw.stage(op.prow);
     const auto ad = [&](int pp) { return rx_addr_row<LOGN>(pp, c); };
     int xe = 0;
     cplx<T> v[8];
@@ -614,12 +636,10 @@ k_rowr_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
             pair_part(v[q >> 1], q & 1) = to<T>(val[q]);
         }
     });
-    cplx<T> w[RegPlan<LOGN>::NTW], wr[8];   // loaded after the gather: shorter live ranges
-    row_reg_setup<T, LOGN>(op.prow, t, w, wr);
-    reg_fft<T, LOGN, -1, XS_WAVE>(v, w, lds, t, ad, xe);
+    reg_fft_tw<T, LOGN, -1, XS_WAVE>(v, tw.W(), lds, t, ad, xe);
     const gptr<cplx<T>> out = args.dest == DEST_T1 ? spec_row<T>(op.T1, item.comp * op.tslot, a, op.ldp)
                                                    : spec_row<T>(const_cast<void*>(op.Xh), 0, a, op.ldp);
-    row_split_store<T, LOGN>(v, wr, lds, ad, t, out, valid);
+    row_split_store<T, LOGN>(v, tw.WR(), lds, ad, t, out, valid);
 }
 
 // C2R of T2 row a, mask to a set row (with the long-vector update or the
@@ -630,7 +650,8 @@ k_rowr_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
            const Item* __restrict__ items, int nitems, RowMidArgs args) {
     using RR = RowReg<LOGN>;
     constexpr int G = RR::G;
-    __shared__ cplx<T> lds[RR::RPW * RegPlan<LOGN>::LROWS];
+    constexpr int XB = RR::RPW * RegPlan<LOGN>::LROWS;
+    __shared__ cplx<T> lds[XB + RowTw<T, LOGN>::LDS];
     const int c = threadIdx.x / G, t = threadIdx.x % G;
     const Item item = items[blockIdx.x];
     const bool valid = c < item.aux;
@@ -639,13 +660,11 @@ k_rowr_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
     const auto ad = [&](int pp) { return rx_addr_row<LOGN>(pp, c); };
     int xe = 0;
     cplx<T> v[8];
+    RowTw<T, LOGN> tw(lds + XB, t);
+    tw.stage(op.prow);
     {
-        // twiddles are loaded again for the forward half: short live ranges
-        // keep the kernel's register count (and so its occupancy) down
-        cplx<T> w[RegPlan<LOGN>::NTW], wr[8];
-        row_reg_setup<T, LOGN>(op.prow, t, w, wr);
-        row_unsplit<T, LOGN>(spec_row<T>(op.T2, item.comp * op.tslot, a, op.ldp), wr, t, v);
-        reg_fft<T, LOGN, +1, XS_WAVE>(v, w, lds, t, ad, xe);
+        row_unsplit<T, LOGN>(spec_row<T>(op.T2, item.comp * op.tslot, a, op.ldp), tw.WR(), t, v);
+        reg_fft_tw<T, LOGN, +1, XS_WAVE>(v, tw.W(), lds, t, ad, xe);
     }
     const CellSet& S = op.S[args.set];
     if (args.gk) {
@@ -694,10 +713,8 @@ k_rowr_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
         });
     }
     if (!args.fwd) return;
-    cplx<T> w[RegPlan<LOGN>::NTW], wr[8];
-    row_reg_setup<T, LOGN>(op.prow, t, w, wr);
-    reg_fft<T, LOGN, -1, XS_WAVE>(v, w, lds, t, ad, xe);
-    row_split_store<T, LOGN>(v, wr, lds, ad, t, spec_row<T>(op.T1, item.comp * op.tslot, a, op.ldp), valid);
+    reg_fft_tw<T, LOGN, -1, XS_WAVE>(v, tw.W(), lds, t, ad, xe);
+    row_split_store<T, LOGN>(v, tw.WR(), lds, ad, t, spec_row<T>(op.T1, item.comp * op.tslot, a, op.ldp), valid);
 }
 
 // C2R of T2 row a gathered on a set row: the short-vector update (OUT_LZ)
@@ -708,7 +725,8 @@ k_rowr_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
            const Item* __restrict__ items, int nitems, RowOutArgs args) {
     using RR = RowReg<LOGN>;
     constexpr int G = RR::G;
-    __shared__ cplx<T> lds[RR::RPW * RegPlan<LOGN>::LROWS];
+    constexpr int XB = RR::RPW * RegPlan<LOGN>::LROWS;
+    __shared__ cplx<T> lds[XB + RowTw<T, LOGN>::LDS];
     const int c = threadIdx.x / G, t = threadIdx.x % G;
     const Item item = items[blockIdx.x];
     const bool valid = c < item.aux;
@@ -716,10 +734,11 @@ k_rowr_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
     const OpDesc& op = ops[item.inst];
     const auto ad = [&](int pp) { return rx_addr_row<LOGN>(pp, c); };
     int xe = 0;
-    cplx<T> w[RegPlan<LOGN>::NTW], wr[8], v[8];
-    row_reg_setup<T, LOGN>(op.prow, t, w, wr);
-    row_unsplit<T, LOGN>(spec_row<T>(op.T2, item.comp * op.tslot, a, op.ldp), wr, t, v);
-    reg_fft<T, LOGN, +1, XS_WAVE>(v, w, lds, t, ad, xe);
+    cplx<T> v[8];
+    RowTw<T, LOGN> tw(lds + XB, t);
+    tw.stage(op.prow);
+    row_unsplit<T, LOGN>(spec_row<T>(op.T2, item.comp * op.tslot, a, op.ldp), tw.WR(), t, v);
+    reg_fft_tw<T, LOGN, +1, XS_WAVE>(v, tw.W(), lds, t, ad, xe);
     const CellSet& S = op.S[args.set];
     if (args.mode == OUT_LZ) {
         const GkShort g = gk_short(lzs[item.inst], op.S[1 - args.set], args.j, args.jstart, valid && a == 0 && t == 0);
@@ -1493,6 +1512,25 @@ k_lz_normalize(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, i
     if (item.idx == 0 && threadIdx.x == 0) lz.beta[0] = beta;
 }
 
+// 1/x (x nonzero, finite) and 1/sqrt(x) (x > 0, finite) from the hardware
+// approximations (about 23 correct bits) refined by Newton steps, which
+// double the correct bits each: one step for 1/x (used for the rotation
+// angle, which only needs to be close), two for 1/sqrt(x) (the cosine, which
+// must make c^2 + s^2 = 1 to rounding so that rotations stay orthogonal).
+__device__ __forceinline__ double rcp_nr(double x) {
+    const double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double h = 0.5 * x * y;
+        y = fma(y, fma(-h, y, 0.5), y);
+    }
+    return y;
+}
+
 // SVD of the m x m projected matrix by one-sided (Hestenes) Jacobi, one
 // workgroup of 512 threads per instance.  The columns of B live in LDS; in
 // each round of the round-robin ordering every 8-thread group takes one
@@ -1542,16 +1580,18 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
                     double* bp = Bs + p * m;
                     double* bq = Bs + q * m;
                     double x1[PE], x2[PE];
-                    double al = 0.0, be = 0.0, ga = 0.0;
+                    // two partial sums per product: shorter dependent chains
+                    double al2[2] = {0.0, 0.0}, be2[2] = {0.0, 0.0}, ga2[2] = {0.0, 0.0};
 #pragma unroll
                     for (int k = 0; k < PE; ++k) {
                         const int i = g + LP * k;
                         x1[k] = i < m ? bp[i] : 0.0;
                         x2[k] = i < m ? bq[i] : 0.0;
-                        al += x1[k] * x1[k];
-                        be += x2[k] * x2[k];
-                        ga += x1[k] * x2[k];
+                        al2[k & 1] += x1[k] * x1[k];
+                        be2[k & 1] += x2[k] * x2[k];
+                        ga2[k & 1] += x1[k] * x2[k];
                     }
+                    double al = al2[0] + al2[1], be = be2[0] + be2[1], ga = ga2[0] + ga2[1];
 #pragma unroll
                     for (int o = LP / 2; o > 0; o >>= 1) {
                         al += __shfl_xor(al, o, LP);
@@ -1559,9 +1599,16 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
                         ga += __shfl_xor(ga, o, LP);
                     }
                     if (ga != 0.0 && ga * ga > jt2 * (al * be)) {
-                        const double ze = (be - al) / (2.0 * ga);
-                        const double tt = (ze >= 0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
-                        const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+                        const double ze = (be - al) * rcp_nr(2.0 * ga);
+                        const double az = fabs(ze);
+                        double tt;
+                        if (az < 1e100) {
+                            const double q1 = 1.0 + ze * ze;
+                            tt = copysign(rcp_nr(az + q1 * rsqrt_nr(q1)), ze);
+                        } else {
+                            tt = 0.5 / ze;   // angle below rounding of 1 + ze^2
+                        }
+                        const double c = rsqrt_nr(1.0 + tt * tt), sn = c * tt;
 #pragma unroll
                         for (int k = 0; k < PE; ++k) {
                             const int i = g + LP * k;
@@ -1626,36 +1673,73 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
     }
 }
 
-// Ritz rotation out[:, 0:k] = Q[:, 0:m] * Yl[:, perm[0:k]] (FP64).
-// Workgroup = 64 rows x 16 output columns (4 per thread).
+// Ritz rotation out[:, 0:k] = Q[:, 0:m] * Yl[:, perm[0:k]] (FP64) on the
+// matrix cores.  Workgroup = 64 rows x up to 32 output columns; each wave
+// takes 16 rows and accumulates the transposed
+// tiles out^T (16 columns x 16 rows) = Y^T Q^T with v_mfma_f64_16x16x4f64,
+// 4 basis vectors per instruction.  Operand lanes: A (16 x 4) element (i, k)
+// in lane i + 16 k, B (4 x 16) element (k, j) in lane j + 16 k; the
+// accumulator holds element (4 v + lane / 16, lane % 16) in its value v.  So
+// the lanes of a wave read 16 consecutive rows of 4 basis vectors
+// (coalesced) and write 16 consecutive rows of 4 output columns.  The loads
+// of 8 instructions' operands are issued together (memory-level parallelism).
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
 __global__ void __launch_bounds__(256)
 k_lz_ritz(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, int k, double* const* outs) {
-    __shared__ double Ys[kMaxBasis][17];
+    constexpr int CB = 2;   // 16-column blocks per workgroup
+    __shared__ double Ys[kMaxBasis][16 * CB];
     const Item item = items[blockIdx.x];
     const LzDesc& lz = lzs[item.inst];
     double* out = outs ? outs[item.inst] : lz.Qtmp;
     if (outs) k = k < lz.r ? k : lz.r;   // final vectors: this decomposition's r
-    const int c0 = item.aux * 16;
-    for (int e = threadIdx.x; e < m * 16; e += 256) {
-        const int i = e / 16, cc = e % 16;
+    const int c0 = item.aux * 16 * CB;
+    const int m4 = (m + 3) & ~3;
+    for (int e = threadIdx.x; e < m4 * 16 * CB; e += 256) {
+        const int i = e / (16 * CB), cc = e % (16 * CB);
         const int c = c0 + cc;
-        Ys[i][cc] = c < k ? lz.Yl[(long)lz.perm[c] * kMaxBasis + i] : 0.0;
+        Ys[i][cc] = (i < m && c < k) ? lz.Yl[(long)lz.perm[c] * kMaxBasis + i] : 0.0;
     }
     __syncthreads();
-    const long row = (long)item.idx * 64 + (threadIdx.x & 63);
-    const int cb = (threadIdx.x >> 6) * 4;
-    if (row >= lz.n) return;
-    double acc[4] = {0, 0, 0, 0};
-    for (int i = 0; i < m; ++i) {
-        const double q = lz.Q[(long)i * lz.n + row];
+    const int nb = min(CB, (k - c0 + 15) / 16);   // column blocks with output
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lo = lane & 15, hi = lane >> 4;
+    const long n = lz.n;
+    const long r0 = (long)item.idx * 64 + wave * 16;
+    if (r0 >= n || nb <= 0) return;
+    const long row = r0 + lo;
+    const bool rok = row < n;
+    const gptr<const double> Q = as_global(lz.Q) + (rok ? row : 0);
+    dvec4 acc[CB];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] += q * Ys[i][cb + t];
-    }
+    for (int cb = 0; cb < CB; ++cb) acc[cb] = dvec4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < m4; k0 += 32) {
+        double b[8];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int c = c0 + cb + t;
-        if (c < k) out[(long)c * lz.n + row] = acc[t];
+        for (int s = 0; s < 8; ++s) {
+            const int col = k0 + 4 * s + hi;
+            b[s] = (rok && col < m) ? gload(Q + (long)col * n) : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int col = k0 + 4 * s + hi;
+            if (k0 + 4 * s < m4) {
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+                    if (cb < nb)
+                        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ys[col][16 * cb + lo], b[s], acc[cb], 0, 0, 0);
+            }
+        }
     }
+    if (!rok) return;
+    const gptr<double> o = as_global(out) + row;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int c = c0 + 16 * cb + 4 * v + hi;
+            if (cb < nb && c < k) gstore(o + (long)c * n, acc[cb][v]);
+        }
 }
 
 // Thick restart keeping k Ritz triplets (u_i = Q Yl_i, sigma_i, and the
