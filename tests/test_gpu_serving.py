@@ -27,6 +27,11 @@ def _requests():
     for i in range(3):   # three images of one geometry: one batch
         w = W.image_2d(n=96, lw=12, r=8, seed=300 + i)
         reqs.append(dict(kind="image", x=w["x"], window=w["window"], r=8, groups=[[0, 1], [2, 3]]))
+    # images of other sizes and window shapes in the same kernel class: they
+    # join the batch of the images above when they wait together
+    big = W.image_2d(n=128, lw=12, r=8, seed=310)["x"]
+    reqs.append(dict(kind="image", x=big[:100, :112], window=(12, 12), r=8, groups=[[0, 1], [2, 3]]))
+    reqs.append(dict(kind="image", x=big[:120, :90], window=(10, 14), r=8, groups=[[0], [1, 2]]))
     for n in (700, 1234):
         w = W.series_1d(n=n, L=n // 2, r=6, seed=n)
         reqs.append(dict(kind="image", x=w["x"], window=w["window"], r=6, groups=[[0, 1]]))
@@ -55,6 +60,8 @@ def _submit(ctx, q, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_served_equals_synchronous(ctx, prec):
+    """Each request decomposed alone (synchronous call) and served inside
+    the mix of requests submitted together gives the same results."""
     reqs = _requests()
     ref = [_sync(ctx, q, prec) for q in reqs]
     tickets = [_submit(ctx, q, prec) for q in reqs]
