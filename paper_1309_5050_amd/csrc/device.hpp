@@ -37,6 +37,7 @@ struct OpDesc {
 // last two (unnormalised) vectors, in the precision of the operator.
 struct LzDesc {
     unsigned long long seed;   // start and restart vectors of this decomposition
+    const int* step;    // [j, jstart] of the batch's current step (device; see kStepDev)
     int side;           // short side: 0 = window set, 1 = origin set
     int active;
     int r;              // triplets wanted
@@ -89,7 +90,14 @@ enum InMode : int {
     IN_VEC = 2,       // src = result vector (U or V) component `comp`, times scale
     IN_DENSE = 3,     // src = dense image row (spectrum creation)
     IN_LZ_SIN = 4,    // src = modified input of the first step after a restart
+    IN_LZ_STEP = 5,   // IN_LZ_SIN on the first step of a restarted cycle, else IN_LZ_NORM
+                      // (step from the batch's step counter)
 };
+
+// A step index j of kStepDev in launch arguments: the step (and the cycle's
+// first step) is read from the batch's step counter in device memory
+// (LzDesc::step), so one captured step can be replayed for every j.
+constexpr int kStepDev = -1;
 
 enum RowDest : int {
     DEST_T1 = 0,      // scratch slot `comp` of T1

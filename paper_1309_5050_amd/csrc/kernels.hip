@@ -165,8 +165,14 @@ struct RowInSrc {
 };
 
 __device__ __forceinline__ RowInSrc row_in_source(const OpDesc& op, const LzDesc& lz, const ResDesc* res,
-                                                  const Item& item, const RowInArgs& args, bool leader) {
+                                                  const Item& item, const RowInArgs& a0, bool leader) {
     RowInSrc r{nullptr, 1.0, nullptr};
+    RowInArgs args = a0;
+    if (args.mode == IN_LZ_STEP) {
+        const int j = lz.step[0], js = lz.step[1];
+        args.j = j;
+        args.mode = (j == js && js > 0) ? IN_LZ_SIN : IN_LZ_NORM;
+    }
     if (args.mode == IN_LZ_NORM || args.mode == IN_LZ_PLAIN || args.mode == IN_LZ_SIN) {
         const bool fresh = args.mode == IN_LZ_SIN && lz.flag[3] != 0;
         if (args.mode == IN_LZ_NORM || fresh) {
@@ -264,6 +270,10 @@ struct GkLong {
 
 template <typename T>
 __device__ __forceinline__ GkLong<T> gk_long(const LzDesc& lz, const CellSet& Slong, int j, int jstart) {
+    if (j == kStepDev) {
+        j = lz.step[0];
+        jstart = lz.step[1];
+    }
     GkLong<T> g;
     const int p = j & 1;
     g.lcur = static_cast<T*>(lz.lbuf[p]);
@@ -356,6 +366,10 @@ struct GkShort {
 // space is exhausted) freezes the recurrence: alpha = 0 and w = 0.
 __device__ __forceinline__ GkShort gk_short(const LzDesc& lz, const CellSet& Slong, int j, int jstart,
                                             bool writer) {
+    if (j == kStepDev) {
+        j = lz.step[0];
+        jstart = lz.step[1];
+    }
     GkShort g;
     g.alpha = sqrt(sum_parts(lz.lnp[j & 1], Slong.boxA));
     const double prev = lz.beta[2 + ((j - 1) & 1)];
@@ -1446,6 +1460,7 @@ k_lz_proj(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int nc
     __shared__ double red[4][kMaxBasis + 1];
     const Item item = items[blockIdx.x];
     const LzDesc& lz = lzs[item.inst];
+    if (ncols < 0) ncols = lz.step[0] + 1;   // step from the counter
     lz_project_block(lz, item.idx, ncols, lz.w, lz.hp1, lz.np0, red);
 }
 
@@ -1455,6 +1470,7 @@ k_lz_proj2(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int n
     __shared__ double red[4][kMaxBasis + 1];
     const Item item = items[blockIdx.x];
     const LzDesc& lz = lzs[item.inst];
+    if (ncols < 0) ncols = lz.step[0] + 1;
     if (!cgs_second_pass(lz, force)) return;
     lz_project_block(lz, item.idx, ncols, lz.w, lz.hp2, nullptr, red);
 }
@@ -1468,6 +1484,7 @@ k_lz_update(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int 
     __shared__ double red[4];
     const Item item = items[blockIdx.x];
     const LzDesc& lz = lzs[item.inst];
+    if (ncols < 0) ncols = lz.step[0] + 1;
     if (pass == 2 && !cgs_second_pass(lz, force)) return;
     const gptr<const double> hp = as_global(static_cast<const double*>(pass == 1 ? lz.hp1 : lz.hp2));
     for (int c = threadIdx.x; c < ncols; c += 256) {
@@ -1833,9 +1850,12 @@ __global__ void k_lz_sigma(const LzDesc* __restrict__ lzs, const ResDesc* __rest
 }
 
 // Sign rule: flip (U_i, V_i) so that U_i's entry of largest magnitude is
-// positive (first such entry in the internal order on ties).
+// positive (first such entry in the internal order on ties).  with_v = 0
+// flips U_i only: used before V = X^T U / sigma is formed, which then
+// inherits the sign.
 __global__ void __launch_bounds__(256)
-k_sign_fix(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res, const Item* __restrict__ items) {
+k_sign_fix(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res, const Item* __restrict__ items,
+           int with_v) {
     __shared__ double bv[256];
     __shared__ long bi[256];
     const Item item = items[blockIdx.x];
@@ -1868,7 +1888,8 @@ k_sign_fix(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res, cons
     __syncthreads();
     if (!flip) return;
     for (long i = threadIdx.x; i < L; i += 256) u[i] = -u[i];
-    for (long i = threadIdx.x; i < K; i += 256) v[i] = -v[i];
+    if (with_v)
+        for (long i = threadIdx.x; i < K; i += 256) v[i] = -v[i];
 }
 
 // out[c][r] = in[r][c] for nmat consecutive R x C matrices (layout change
@@ -1892,6 +1913,11 @@ __global__ void __launch_bounds__(256) k_transpose(const double* __restrict__ in
 // Batch readbacks: the Lanczos flags and residual figures of every instance
 // (4 ints + 2 doubles each), or the r singular values of every instance,
 // gathered into one array so the host reads them with a single copy.
+// Advance the batch's step counter (end of a replayed step).
+__global__ void k_step_next(int* step) {
+    if (threadIdx.x == 0) step[0] += 1;
+}
+
 __global__ void k_gather_flags(const LzDesc* __restrict__ lzs, int ninst, int* __restrict__ flags,
                                double* __restrict__ betas) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -51,8 +51,10 @@ void launch_lz_restart(int nitems, hipStream_t st, const LzDesc* lzs, const Item
 void launch_lz_restart_random(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int k,
                               unsigned long long seed);
 void launch_lz_sigma(int ninst, hipStream_t st, const LzDesc* lzs, const ResDesc* res, const Item* items);
-void launch_sign_fix(int nitems, hipStream_t st, const OpDesc* ops, const ResDesc* res, const Item* items);
+void launch_sign_fix(int nitems, hipStream_t st, const OpDesc* ops, const ResDesc* res, const Item* items,
+                     int with_v);
 void launch_gather_flags(int ninst, hipStream_t st, const LzDesc* lzs, int* flags, double* betas);
+void launch_step_next(hipStream_t st, int* step);
 void launch_transpose(int nmat, int R, int C, hipStream_t st, const double* in, double* out);
 
 }  // namespace shssa
