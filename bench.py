@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
 def main():
@@ -91,7 +92,7 @@ def main():
     # HIP events bracket one launch in every PROFILE_EVERY of each timed class
     # (an odd period samples both directions of the column pass); each
     # bracketed launch costs the stream two event records
-    ctx.profile(",".join(KERNELS), every=PROFILE_EVERY)
+    ctx.profile(",".join(list(KERNELS) + ["lz_ritz"]), every=PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     last = None
@@ -100,7 +101,7 @@ def main():
         last = step(args.precision)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = ctx.profile_read(list(KERNELS))
+    prof = ctx.profile_read(list(KERNELS) + ["lz_ritz"])
     ctx.profile(None)
     stats = last[0].stats
     dt = t1 - t0
@@ -120,6 +121,15 @@ def main():
                       "ms_per_launch": kern_ms, "bytes_per_launch": kern_bytes, "launches": p["launches"],
                       "ms_total": p["ms"], "timed_every": PROFILE_EVERY, "traffic_counters_on": traffic_kernel}
     dominant = max(roofs, key=lambda c: roofs[c]["ms_total"])
+    # the matrix-core kernel (FP64 Ritz rotation): its timing class counts
+    # floating-point operations
+    pr = prof["lz_ritz"]
+    mfma = None
+    if pr["launches"] > 0 and pr["ms"] > 0:
+        tf = pr["bytes"] / (pr["ms"] * 1e-3) / 1e12
+        mfma = {"kernel": "k_lz_ritz", "dtype": "f64", "achieved": tf, "peak": FP64_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": tf / FP64_MFMA_PEAK_TFLOPS, "launches": pr["launches"],
+                "ms_per_launch": pr["ms"] / pr["launches"], "flop_per_launch": pr["bytes"] / pr["launches"]}
     # HbH product rate over the whole product (algorithmic bytes per product)
     L, K = lw * lw, (n - lw + 1) ** 2
     b = 4 if args.precision == "fp32" else 8
@@ -168,6 +178,7 @@ def main():
                    "parallelism": "batched on 1 GPU"},
         "roofline": roofs[dominant],
         "roofline_kernels": roofs,
+        "mfma": mfma,
         "hbh_product": {"bytes_per_product": bmv, "products_per_step": products,
                         "effective_GBs": bmv * products / (dt / args.steps) / 1e9},
         "lanczos": {"steps": stats["steps"], "restarts": stats["restarts"], "basis": stats["basis"],

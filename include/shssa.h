@@ -215,7 +215,9 @@ int ssa_ctx_sync(ssa_ctx* ctx);
 
 /* Kernel timing with HIP events.  kind is a comma-separated list of kernel
  * classes ("col", "row_in", "row_mid", "row_out", "rowfam_mid",
- * "rowfam_out", "lz_proj", "lz_update"); NULL or "" stops recording.
+ * "rowfam_out", "lz_proj", "lz_update", and "lz_ritz", the matrix-core Ritz
+ * rotation, whose "bytes" are floating-point operations); NULL or "" stops
+ * recording.
  * ssa_ctx_profile_read_kind waits for the recorded launches of one class and
  * returns the time during which at least one of them was running (ms: the
  * union of their intervals, so launches of concurrent sub-batch streams are

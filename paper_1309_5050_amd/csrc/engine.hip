@@ -1489,7 +1489,15 @@ int run_lanczos(Batch& b, int max_steps, const std::function<int()>& overlap = n
                 I.h.push_back(Item{i, 0, 0, 0});
             }
             if ((rc = upload_lists({&R, &I}, st))) return rc;
-            launch_lz_ritz(R.n(), st, b.lzs(), R.ptr(), m, rmax, douts.as<double*>());
+            {
+                // timing class "lz_ritz" counts floating-point operations, 2 n m k per instance
+                ProfSpan p(b.ctx, "lz_ritz", st, [&] {
+                    double f = 0.0;
+                    for (int i : done) f += 2.0 * b.ds[i]->nshort * m * b.ds[i]->r;
+                    return f;
+                });
+                launch_lz_ritz(R.n(), st, b.lzs(), R.ptr(), m, rmax, douts.as<double*>());
+            }
             launch_lz_sigma(I.n(), st, b.lzs(), b.res(), I.ptr());
             // no wait: the tables are released into the call's table cache,
             // which returns them to the pool only after the stream drains
@@ -1507,7 +1515,14 @@ int run_lanczos(Batch& b, int max_steps, const std::function<int()>& overlap = n
                     (isfresh[i] ? F : Z).h.push_back(Item{i, k, 0, 0});
             }
             if ((rc = upload_lists({&R, &Z, &F}, st))) return rc;
-            launch_lz_ritz(R.n(), st, b.lzs(), R.ptr(), m, kk, nullptr);
+            {
+                ProfSpan p(b.ctx, "lz_ritz", st, [&] {
+                    double f = 0.0;
+                    for (int i : cont) f += 2.0 * b.ds[i]->nshort * m * kk;
+                    return f;
+                });
+                launch_lz_ritz(R.n(), st, b.lzs(), R.ptr(), m, kk, nullptr);
+            }
             launch_lz_restart(Z.n(), st, b.lzs(), Z.ptr(), m, kk);
             if (F.n() > 0) {
                 launch_lz_restart_random(F.n(), st, b.lzs(), F.ptr(), kk, 7919ULL * cycle);   // ^ own seed
