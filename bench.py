@@ -247,16 +247,57 @@ def _served_run(S, data, prec, rate, seed):
     ctx.close()
     warm = max(1, n // 20)
     ls = np.array(lat[warm:])
+    third = max(1, len(ls) // 3)
     return {"precision": prec, "offered_rps": rate, "requests": n, "achieved_rps": n / (t1 - t0),
             "p50_ms": float(np.percentile(ls, 50)), "p99_ms": float(np.percentile(ls, 99)),
+            "mean_ms": float(ls.mean()),
+            # queue trend: median latency of the first and last third of the arrivals
+            "p50_first_third_ms": float(np.median(ls[:third])), "p50_last_third_ms": float(np.median(ls[-third:]))}
+
+
+def _plain_run(S, data, rate, seed):
+    """The plain single-instance FP64 path as a server: requests arrive as in
+    _served_run and are decomposed and reconstructed one at a time, in
+    arrival order, with the synchronous calls; latency = completion minus
+    arrival."""
+    import numpy as np
+    ctx = S.Context(0)
+    n = len(data)
+    rng = np.random.default_rng(seed)
+    arrive = np.cumsum(rng.exponential(1.0 / rate, n))
+    lat = []
+    t0 = time.perf_counter()
+    for i, q in enumerate(data):
+        dt = t0 + arrive[i] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        _run_sync(ctx, q, "fp64")
+        lat.append(1e3 * (time.perf_counter() - t0 - arrive[i]))
+    t1 = time.perf_counter()
+    ctx.close()
+    warm = max(1, n // 20)
+    ls = np.array(lat[warm:])
+    return {"precision": "fp64 plain", "offered_rps": rate, "requests": n, "achieved_rps": n / (t1 - t0),
+            "p50_ms": float(np.percentile(ls, 50)), "p99_ms": float(np.percentile(ls, 99)),
             "mean_ms": float(ls.mean())}
+
+
+def _keeps_up(run):
+    """A Poisson run the server sustained: it completed at the offered rate and
+    the latency did not grow over the run (no queue build-up)."""
+    return (run["achieved_rps"] >= 0.95 * run["offered_rps"]
+            and run["p50_last_third_ms"] <= 2.0 * max(run["p50_first_third_ms"], 1.0))
 
 
 def serve_bench(S, W, n_req):
     """Mixed serving workload (60% 1D, 25% MSSA, 15% 2D, r ~ U{5..40},
     groups {1..min(r,4)}): capacity of the plain single-instance FP64 path
     (closed loop), then Poisson arrivals at 0.8 x that capacity through the
-    serving engine in FP32 and FP64, and at 0.8 x the served FP32 capacity."""
+    plain path (one request at a time) and the serving engine in FP32 and
+    FP64.  The served FP32 capacity is the highest
+    Poisson rate it sustains (a ladder of rates below the closed-loop
+    throughput, where all requests wait at once and form the largest
+    batches); the last run is at 0.8 x that sustained capacity."""
     mix = W.serving_mix(n_req, seed=5)
     data = [W.materialize(d) for d in mix]
     ctx = S.Context(0)
@@ -271,11 +312,27 @@ def serve_bench(S, W, n_req):
     out = {"workload": f"serving mix, {n_req} requests (60% 1D N~U(500,20000), 25% MSSA s~U(4,32), "
                        f"15% 2D S~U(64,512)), r~U(5,40)",
            "plain_fp64_capacity_rps": cap64, "runs": []}
+    # the same arrivals (seed 11) through the plain path and the serving engine
+    out["runs"].append(_plain_run(S, data, 0.8 * cap64, seed=11))
     for prec in ("fp32", "fp64"):
         out["runs"].append(_served_run(S, data, prec, 0.8 * cap64, seed=11))
     closed = _served_run(S, data, "fp32", None, seed=12)
-    out["served_fp32_capacity_rps"] = closed["achieved_rps"]
-    out["runs"].append(_served_run(S, data, "fp32", 0.8 * closed["achieved_rps"], seed=13))
+    out["served_fp32_closed_loop_rps"] = closed["achieved_rps"]
+    sustained, ladder = None, []
+    for f in (0.8, 0.65, 0.5, 0.4, 0.3, 0.2):
+        rate = f * closed["achieved_rps"]
+        if rate <= cap64:
+            break
+        run = _served_run(S, data, "fp32", rate, seed=14)
+        ladder.append({"offered_rps": rate, "achieved_rps": run["achieved_rps"], "p50_ms": run["p50_ms"],
+                       "p99_ms": run["p99_ms"], "kept_up": _keeps_up(run)})
+        if _keeps_up(run):
+            sustained = rate
+            break
+    out["served_fp32_ladder"] = ladder
+    out["served_fp32_capacity_rps"] = sustained
+    if sustained:
+        out["runs"].append(_served_run(S, data, "fp32", 0.8 * sustained, seed=13))
     return out
 
 
