@@ -1079,7 +1079,7 @@ col_body(const OpDesc* __restrict__ ops, const ResDesc* __restrict__ res,
 // workgroups per compute unit; otherwise twiddles in registers and two
 // exchange buffers used in turn.
 template <typename T, int LOGN, int TC, bool SPEC, bool LTW>
-__global__ void __launch_bounds__(RegPlan<LOGN>::G * TC)
+__global__ void __launch_bounds__(RegPlan<LOGN>::G * TC, LTW ? 8 : 1)
 k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs args) {
     using RP = RegPlan<LOGN>;
     constexpr int G = RP::G;
