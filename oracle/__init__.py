@@ -264,6 +264,29 @@ def reconstruct_mssa(series_lens, L, sigma, U, V, group) -> list:
     return np.split(out, np.cumsum(lens)[:-1])
 
 
+def wcor(x, sh: Shapes, sigma, U, V, groups):
+    """w-correlations and contributions of reconstructed groups (Section 2.1,
+    separability paragraph): the weighted inner product (Y, Z)_w =
+    sum_k w_k y_k z_k with w_k = |A_k| (the number of trajectory-matrix
+    entries holding element k), rho_w(Y, Z) = (Y, Z)_w / (|Y|_w |Z|_w)
+    without subtracting means, and the contribution of a component Y,
+    |Y|_w^2 / |X|_w^2.  Sums run over the covered cells N' (w > 0).
+    Returns (rho, contrib): (ng, ng) and (ng,)."""
+    cov = sh.W > 0
+    w = sh.W[cov]
+    comps = [reconstruct(sh, sigma, U, V, g)[cov] for g in groups]
+    xc = clean(x, sh)[cov]
+    ng = len(groups)
+    G = np.zeros((ng, ng))
+    for i in range(ng):
+        for j in range(ng):
+            G[i, j] = np.sum(w * comps[i] * comps[j])
+    d = np.sqrt(np.diag(G))
+    rho = G / np.outer(d, d)
+    contrib = np.diag(G) / np.sum(w * xc * xc)
+    return rho, contrib
+
+
 # --------------------------------------------------------------------------
 # whole decompositions
 # --------------------------------------------------------------------------

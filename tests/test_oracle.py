@@ -411,3 +411,59 @@ def test_table3_reconstruction_mse():
         v = np.array(res[key])
         se = v.std() / np.sqrt(reps)
         assert abs(v.mean() - ref) < 5 * se + 0.005, (key, v.mean(), ref, se)
+
+
+# --------------------------------------------------------------------------
+# w-correlations and contributions
+# --------------------------------------------------------------------------
+
+def test_wcor_is_frobenius_correlation_of_trajectory_matrices():
+    """rho_w of two reconstructed components equals the normalised Frobenius
+    inner product of their trajectory matrices (the paper's definition via
+    rho(X~_1, X~_2)), and the contribution equals |T(X~_j)|_F^2 / |X|_F^2."""
+    w = W.small_shaped()
+    sh, s, U, V = oracle.decompose(w["x"], w["mask"], w["wmask"])
+    groups = [[0, 1], [2], [3, 4, 5]]
+    rho, contrib = oracle.wcor(w["x"], sh, s, U, V, groups)
+    T = [oracle.trajectory(oracle.reconstruct(sh, s, U, V, g), sh) for g in groups]
+    X = oracle.trajectory(w["x"], sh)
+    for i in range(3):
+        assert np.isclose(contrib[i], np.sum(T[i] ** 2) / np.sum(X ** 2), rtol=1e-12)
+        for j in range(3):
+            ref = np.sum(T[i] * T[j]) / np.sqrt(np.sum(T[i] ** 2) * np.sum(T[j] ** 2))
+            assert abs(rho[i, j] - ref) <= 1e-12
+    assert np.allclose(rho, rho.T) and np.allclose(np.diag(rho), 1.0)
+    assert np.all(np.abs(rho) <= 1 + 1e-12)
+
+
+def test_wcor_of_a_complete_grouping_recovers_the_norm():
+    """The groups of a complete grouping sum to x on N', so the weighted
+    inner products of all pairs add up to |X|_w^2: sum_ij rho_ij
+    sqrt(c_i c_j) = 1."""
+    x = W.series_1d(n=120, L=40, r=6, seed=8)["x"]
+    sh, s, U, V = oracle.decompose(x, None, None, 40)
+    groups = [[0], [1, 2], [3, 4], list(range(5, len(s)))]
+    rho, c = oracle.wcor(x, sh, s, U, V, groups)
+    assert abs(np.sum(rho * np.sqrt(np.outer(c, c))) - 1.0) <= 1e-11
+
+
+def test_wcor_of_exactly_separable_components():
+    """x_t = a + b(-1)^t with L and K even: the constant and the alternating
+    series have orthogonal row and column trajectory spaces and distinct
+    singular values a sqrt(LK) and |b| sqrt(LK), so the two elementary
+    reconstructions are exactly a and b(-1)^t.  Their w-correlation and
+    contributions then follow from the 1D weights w_k = min(k, L, K, N-k+1)
+    and the known signals."""
+    N, L, a, b = 31, 10, 1.5, -0.7
+    K = N - L + 1
+    t = np.arange(N)
+    x = a + b * (-1.0) ** t
+    # rank 2 (the other singular values vanish): the Gram route of the SVD step
+    sh, s, U, V = oracle.decompose(x, None, None, L, method="gram")
+    assert np.isclose(s[0], a * np.sqrt(L * K)) and np.isclose(s[1], abs(b) * np.sqrt(L * K))
+    rho, c = oracle.wcor(x, sh, s, U, V, [[0], [1]])
+    wk = np.minimum.reduce([t + 1, np.full(N, L), np.full(N, K), N - t])
+    f1, f2 = np.full(N, a), b * (-1.0) ** t
+    ip = lambda p, q: np.sum(wk * p * q)
+    assert abs(rho[0, 1] - ip(f1, f2) / np.sqrt(ip(f1, f1) * ip(f2, f2))) <= 1e-12
+    assert np.allclose(c, [ip(f1, f1) / ip(x, x), ip(f2, f2) / ip(x, x)], rtol=1e-12)
