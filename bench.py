@@ -136,6 +136,21 @@ def main():
     bmv = b * (K + L) + 2 * b * n * (n // 2 + 1)
     products = 2 * sum(d.stats["steps"] for d in last)
 
+    # w-correlation matrix of the r elementary components of one decomposition
+    # (reconstruction of r singleton groups + the weighted Gram kernel)
+    ctx.profile("wgram")
+    torch.cuda.synchronize()
+    tw0 = time.perf_counter()
+    rho, _ = last[0].wcor([[i] for i in range(r)])
+    tw1 = time.perf_counter()
+    pw = ctx.profile_read(["wgram"])["wgram"]
+    ctx.profile(None)
+    wgram_gbs = pw["bytes"] / (pw["ms"] * 1e-3) / 1e9 if pw["ms"] > 0 else 0.0
+    wcor = {"groups": r, "ms_total": 1e3 * (tw1 - tw0), "gram_kernel_ms": pw["ms"],
+            "gram_roofline": {"bound": "hbm", "achieved": wgram_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": wgram_gbs / HBM_PEAK_GBS, "bytes": pw["bytes"]},
+            "max_offdiag_abs_rho": float(np.max(np.abs(rho - np.diag(np.diag(rho)))))}
+
     # plain single-instance FP64 path (same kernels, batch of one)
     single = None
     if not args.no_single:
@@ -179,6 +194,7 @@ def main():
         "roofline": roofs[dominant],
         "roofline_kernels": roofs,
         "mfma": mfma,
+        "wcor": wcor,
         "hbh_product": {"bytes_per_product": bmv, "products_per_step": products,
                         "effective_GBs": bmv * products / (dt / args.steps) / 1e9},
         "lanczos": {"steps": stats["steps"], "restarts": stats["restarts"], "basis": stats["basis"],

@@ -167,6 +167,16 @@ int ssa_reconstruct(ssa_decomp* d, const int* grp_ptr, const int* grp_idx, int n
 int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* grp_ptr, const int* grp_idx,
                               int ngroups, double* const* out_dev);
 
+/* w-correlations and contributions of the reconstructed groups (Section
+ * 2.1, separability paragraph).  With the weights w = |A_k| of
+ * ssa_get_weights and the weighted inner product (Y, Z)_w = sum_k w_k y_k
+ * z_k over the covered cells N': rho[a*ngroups + b] = (Y_a, Y_b)_w /
+ * (|Y_a|_w |Y_b|_w) (means not subtracted; 0 if a component is zero) and
+ * contrib[a] = |Y_a|_w^2 / |X|_w^2 (contrib may be NULL).  Groups as for
+ * ssa_reconstruct (singletons give the w-correlation matrix of the
+ * elementary components).  Synchronous. */
+int ssa_wcor(ssa_decomp* d, const int* grp_ptr, const int* grp_idx, int ngroups, double* rho, double* contrib);
+
 int  ssa_get_stats(const ssa_decomp* d, ssa_stats* st);
 void ssa_free(ssa_decomp* d);
 
@@ -215,9 +225,9 @@ int ssa_ctx_sync(ssa_ctx* ctx);
 
 /* Kernel timing with HIP events.  kind is a comma-separated list of kernel
  * classes ("col", "row_in", "row_mid", "row_out", "rowfam_mid",
- * "rowfam_out", "lz_proj", "lz_update", and "lz_ritz", the matrix-core Ritz
- * rotation, whose "bytes" are floating-point operations); NULL or "" stops
- * recording.
+ * "rowfam_out", "lz_proj", "lz_update", "wgram" (the w-correlation Gram),
+ * and "lz_ritz", the matrix-core Ritz rotation, whose "bytes" are
+ * floating-point operations); NULL or "" stops recording.
  * ssa_ctx_profile_read_kind waits for the recorded launches of one class and
  * returns the time during which at least one of them was running (ms: the
  * union of their intervals, so launches of concurrent sub-batch streams are

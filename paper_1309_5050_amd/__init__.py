@@ -101,6 +101,17 @@ class Decomposition:
         check(lib().ssa_reconstruct(self._h, _ptr(gp), _ptr(gi), len(groups), _ptr(out)), "ssa_reconstruct")
         return out
 
+    def wcor(self, groups):
+        """w-correlation matrix (ngroups, ngroups) and contributions
+        (ngroups,) of the reconstructed groups."""
+        gp = np.zeros(len(groups) + 1, np.int32)
+        gp[1:] = np.cumsum([len(g) for g in groups])
+        gi = np.ascontiguousarray(np.concatenate([np.asarray(g, np.int32) for g in groups]))
+        rho = np.zeros((len(groups), len(groups)))
+        contrib = np.zeros(len(groups))
+        check(lib().ssa_wcor(self._h, _ptr(gp), _ptr(gi), len(groups), _ptr(rho), _ptr(contrib)), "ssa_wcor")
+        return rho, contrib
+
 
 class Context:
     """A device, a stream and a memory budget for decompositions."""

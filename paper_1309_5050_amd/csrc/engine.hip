@@ -747,6 +747,19 @@ struct DevVec {
         return ctx->upload(p, v.data(), v.size() * sizeof(T), st);
     }
     template <typename T> T* as() const { return static_cast<T*>(p); }
+    // device space without contents (from the pool)
+    int reserve(size_t bytes) {
+        const size_t b = ssa_ctx::size_class(std::max<size_t>(bytes, 1));
+        if (b <= cap) return SSA_OK;
+        release();
+        {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            p = ctx->pool_get(b);
+        }
+        if (!p) return fail(SSA_ENOMEM, "device memory (work buffer)");
+        cap = b;
+        return SSA_OK;
+    }
 };
 
 struct ItemList {
@@ -2468,6 +2481,72 @@ int ssa_reconstruct(ssa_decomp* d, const int* gp, const int* gi, int ng, double*
     }
     (void)hipFree(buf);
     return rc;
+}
+
+int ssa_wcor(ssa_decomp* d, const int* gp, const int* gi, int ng, double* rho, double* contrib) {
+    if (!d || !rho) return fail(SSA_EINVAL, "NULL argument");
+    if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
+    int rc = check_groups(d, gp, gi, ng);
+    if (rc) return rc;
+    g_tables_ctx = d->ctx;
+    TableScope tables(d->ctx, d->ctx->st);
+    Batch b(d->ctx);
+    b.ds = {d};
+    b.f64 = d->f64;
+    b.rowfam = d->rowfam;
+    b.cls = row_word(d->nh, d->f64);
+    b.set_col(d->ctx->tile_for(d->f64, d->MA));
+    const long n = (long)d->A * d->B;
+    // the groups' reconstructions (internal orientation) and the cleaned
+    // input (equal to x on the covered set) are the arrays of the Gram
+    DevVec rec, part, out;
+    if ((rc = rec.reserve((size_t)ng * n * sizeof(double)))) return rc;
+    if ((rc = run_reconstruct(b, std::vector<int>(gp, gp + ng + 1), std::vector<int>(gi, gi + gp[ng]),
+                              {rec.as<double>()})))
+        return rc;
+    const int narr = ng + 1;
+    std::vector<const double*> arr;
+    for (int g = 0; g < ng; ++g) arr.push_back(rec.as<double>() + (long)g * n);
+    arr.push_back(d->xc);
+    DevVec darr;
+    if ((rc = darr.put(arr, b.st))) return rc;
+    const int tiles = wgram_tiles(narr);
+    // about 1024 workgroups in all, each with at least 512 cells
+    const int nchunk = (int)std::max<long>(1, std::min<long>(1024 / tiles + 1, n / 512));
+    if ((rc = part.reserve((size_t)tiles * 256 * nchunk * sizeof(double))) ||
+        (rc = out.reserve((size_t)tiles * 256 * sizeof(double))))
+        return rc;
+    {
+        // algorithmic bytes: every array and the weights read once
+        ProfSpan p(b.ctx, "wgram", b.st, [&] { return (double)(narr + 1) * n * sizeof(double); });
+        launch_wgram(b.st, darr.as<const double*>(), narr, d->W, n, nchunk, part.as<double>(), out.as<double>());
+    }
+    HIPCHK(hipGetLastError());
+    std::vector<double> t((size_t)tiles * 256);
+    HIPCHK(hipMemcpyAsync(t.data(), out.p, t.size() * sizeof(double), hipMemcpyDeviceToHost, b.st));
+    HIPCHK(hipStreamSynchronize(b.st));
+    // Gram matrix from the tiles (the entry with i <= j on diagonal tiles)
+    std::vector<double> G((size_t)narr * narr, 0.0);
+    const int nb = (narr + 15) / 16;
+    int k = 0;
+    for (int ib = 0; ib < nb; ++ib)
+        for (int jb = ib; jb < nb; ++jb, ++k)
+            for (int i = 0; i < 16; ++i)
+                for (int j = 0; j < 16; ++j) {
+                    const int a = 16 * ib + i, c = 16 * jb + j;
+                    if (a >= narr || c >= narr || (ib == jb && j < i)) continue;
+                    const double v = t[(size_t)k * 256 + 16 * i + j];
+                    G[(size_t)a * narr + c] = G[(size_t)c * narr + a] = v;
+                }
+    const double xx = G[(size_t)ng * narr + ng];
+    for (int a = 0; a < ng; ++a) {
+        for (int c = 0; c < ng; ++c) {
+            const double den = std::sqrt(G[(size_t)a * narr + a] * G[(size_t)c * narr + c]);
+            rho[(size_t)a * ng + c] = den > 0 ? G[(size_t)a * narr + c] / den : 0.0;
+        }
+        if (contrib) contrib[a] = xx > 0 ? G[(size_t)a * narr + a] / xx : 0.0;
+    }
+    return SSA_OK;
 }
 
 int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* gp, const int* gi, int ng,

@@ -1913,6 +1913,80 @@ __global__ void __launch_bounds__(256) k_transpose(const double* __restrict__ in
 // Batch readbacks: the Lanczos flags and residual figures of every instance
 // (4 ints + 2 doubles each), or the r singular values of every instance,
 // gathered into one array so the host reads them with a single copy.
+// ------------------------------------------------------------------------
+// w-correlations: weighted Gram matrix of reconstructed components
+// ------------------------------------------------------------------------
+
+// Partial weighted inner products sum_c W[c] y_a[c] y_b[c] over one chunk of
+// cells, for a 16 x 16 tile of array pairs (a in block ib, b in block jb,
+// ib <= jb; tiles numbered along the rows of the upper triangle), on the
+// matrix cores: the Gram R^T diag(W) R is a dense contraction over the
+// cells.  Each v_mfma_f64_16x16x4f64 takes 4 cells: A = the 16 arrays of
+// block ib (element (i, k) in lane i + 16 k), B = W times the 16 arrays of
+// block jb (element (k, j) in lane j + 16 k), so both operands of a lane are
+// the same cell of two arrays.  Only cells with W > 0 enter (the
+// reconstructions are NaN off the covered set).  Grid (chunks, tiles), 4
+// waves per workgroup; part[(tile * 256 + 16 i + j) * nchunk + chunk].
+__global__ void __launch_bounds__(256)
+k_wgram(const double* const* __restrict__ arr, int narr, const double* __restrict__ W, long ncell, int nchunk,
+        double* __restrict__ part) {
+    __shared__ double red[4][256];
+    const int nb = (narr + 15) / 16;
+    int k = blockIdx.y, ib = 0;
+    while (k >= nb - ib) {
+        k -= nb - ib;
+        ++ib;
+    }
+    const int jb = ib + k;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lo = lane & 15, hi = lane >> 4;
+    const int ai = ib * 16 + lo, aj = jb * 16 + lo;
+    const gptr<const double> pi = as_global(ai < narr ? arr[ai] : W);   // unused rows read W (finite)
+    const gptr<const double> pj = as_global(aj < narr ? arr[aj] : W);
+    const gptr<const double> pw = as_global(W);
+    constexpr int U = 8;   // 4-cell steps whose operands are loaded together
+    const long csz = ((ncell + nchunk - 1) / nchunk + 16 * U - 1) / (16 * U) * (16 * U);
+    const long c0 = (long)blockIdx.x * csz;
+    const long c1 = min(ncell, c0 + csz);
+    dvec4 acc = {0.0, 0.0, 0.0, 0.0};
+    // the waves take interleaved 4-cell steps of the chunk, U at a time
+    for (long cb = c0 + 4 * wave; cb < c1; cb += 16 * U) {
+        double w[U], yi[U], yj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long c = cb + 16 * u + hi;
+            const bool in = c < c1;
+            w[u] = in ? gload(pw + c) : 0.0;
+            yi[u] = gload(pi + (in ? c : c0));
+            yj[u] = gload(pj + (in ? c : c0));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool on = w[u] > 0;
+            const double a = (on && ai < narr) ? yi[u] : 0.0;
+            const double b = (on && aj < narr) ? w[u] * yj[u] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave][(4 * v + hi) * 16 + lo] = acc[v];
+    __syncthreads();
+    const int e = threadIdx.x;   // 256 entries of the tile
+    part[((long)blockIdx.y * 256 + e) * nchunk + blockIdx.x] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+}
+
+// out[e] = sum over the chunks of part[e * nchunk + chunk]: one wave per
+// entry, lanes over the chunks, then a fixed-order wave sum.
+__global__ void __launch_bounds__(256)
+k_wgram_sum(const double* __restrict__ part, int nent, int nchunk, double* __restrict__ out) {
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= nent) return;
+    double s = 0.0;
+    for (int q = lane_id(); q < nchunk; q += 64) s += part[(long)e * nchunk + q];
+    s = wave_sum(s);
+    if (lane_id() == 0) out[e] = s;
+}
+
 // Advance the batch's step counter (end of a replayed step).
 __global__ void k_step_next(int* step) {
     if (threadIdx.x == 0) step[0] += 1;

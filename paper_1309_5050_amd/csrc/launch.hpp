@@ -55,6 +55,13 @@ void launch_sign_fix(int nitems, hipStream_t st, const OpDesc* ops, const ResDes
                      int with_v);
 void launch_gather_flags(int ninst, hipStream_t st, const LzDesc* lzs, int* flags, double* betas);
 void launch_step_next(hipStream_t st, int* step);
+// Weighted Gram of narr arrays of ncell values over the cells with W > 0:
+// 16 x 16 tiles of the upper triangle (wgram_tiles of them), entry
+// (16 ib + i, 16 jb + j) of tile t at out[256 t + 16 i + j]; part holds
+// tiles*256*nchunk values.
+int wgram_tiles(int narr);
+void launch_wgram(hipStream_t st, const double* const* arr, int narr, const double* W, long ncell, int nchunk,
+                  double* part, double* out);
 void launch_transpose(int nmat, int R, int C, hipStream_t st, const double* in, double* out);
 
 }  // namespace shssa

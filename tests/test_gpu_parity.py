@@ -124,6 +124,32 @@ def test_parity(ctx, name, prec):
     check_case(ctx, name, prec)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["series_1000", "image_128", "disc_160", "small_shaped", "image_ragged"])
+def test_wcor_parity(ctx, name, prec):
+    """w-correlations and contributions of the gap-stable groups against the
+    oracle's.  A group's reconstruction is within d = 20 tol s_1 / gap of
+    the oracle's (relative to |x|), so a correlation moves by at most about
+    d (c_a^-1/2 + c_b^-1/2) and a contribution by about 2 d c_a^1/2 (+ d^2),
+    c = contribution; the bounds below allow 4x that."""
+    w = CASES[name]()
+    tol = TOL[prec]
+    sh, so, Uo, Vo = oracle_case(name, w)
+    d = gpu_case(ctx, w, prec)
+    st = stable_groups(so, w["r"])
+    groups = [g for g, _ in st][:5]
+    gap = min(gp for _, gp in st[:5])
+    rho, c = d.wcor(groups)
+    rho_o, c_o = oracle.wcor(w["x"], sh, so, Uo, Vo, groups)
+    dd = 20 * tol * so[0] / gap
+    assert np.allclose(rho, rho.T) and np.allclose(np.diag(rho), 1.0)
+    for a in range(len(groups)):
+        assert abs(c[a] - c_o[a]) <= 4 * (2 * dd * np.sqrt(c_o[a]) + dd * dd), (name, prec, a, c[a], c_o[a])
+        for b in range(len(groups)):
+            bound = 4 * dd * (1 / np.sqrt(c_o[a]) + 1 / np.sqrt(c_o[b]))
+            assert abs(rho[a, b] - rho_o[a, b]) <= bound, (name, prec, a, b, rho[a, b], rho_o[a, b], bound)
+
+
 def test_literal_groups_series(ctx):
     """The 1D workload's own groups {1-2},{3-4},{5} split near-degenerate
     sine pairs; their error is bounded by tol * s_1 / gap of each split."""
