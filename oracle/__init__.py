@@ -287,6 +287,35 @@ def wcor(x, sh: Shapes, sigma, U, V, groups):
     return rho, contrib
 
 
+def lrr_column(U, group):
+    """Coefficients of the column recurrent forecast (Section 3.x, recurrent
+    MSSA forecast, column form; one series is the case s = 1): with pi(U_j)
+    the last coordinate of U_j and nu^2 = sum_j pi(U_j)^2 over the group,
+    R_L = sum_j pi(U_j) U_j[0:L-1] / (1 - nu^2), an LRR of order L-1."""
+    U = np.asarray(U, dtype=np.float64)
+    pi = U[-1, group]
+    nu2 = float(np.sum(pi * pi))
+    if not nu2 < 1.0:
+        raise ValueError("the last coordinates of the group's U span e_L: no recurrent forecast")
+    return (U[:-1, group] @ pi) / (1.0 - nu2)
+
+
+def rforecast_column(recs, U, group, h: int):
+    """Column recurrent forecast of h values for each reconstructed series in
+    recs (a list of 1-D arrays, the group's reconstruction of each series):
+    x_{N+1} = sum_k R_k x_{N-L+1+k} applied to the last L-1 values, then by
+    recurrence on the forecast values.  Returns an (s, h) array."""
+    R = lrr_column(U, group)
+    out = np.zeros((len(recs), h))
+    for p, y in enumerate(recs):
+        buf = list(np.asarray(y, dtype=np.float64)[-(len(R)):])
+        for k in range(h):
+            nxt = float(np.dot(R, buf[-len(R):]))
+            buf.append(nxt)
+            out[p, k] = nxt
+    return out
+
+
 # --------------------------------------------------------------------------
 # whole decompositions
 # --------------------------------------------------------------------------

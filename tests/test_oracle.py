@@ -467,3 +467,55 @@ def test_wcor_of_exactly_separable_components():
     ip = lambda p, q: np.sum(wk * p * q)
     assert abs(rho[0, 1] - ip(f1, f2) / np.sqrt(ip(f1, f1) * ip(f2, f2))) <= 1e-12
     assert np.allclose(c, [ip(f1, f1) / ip(x, x), ip(f2, f2) / ip(x, x)], rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# recurrent (column) forecast
+# --------------------------------------------------------------------------
+
+def _lapack_svd(X):
+    # exactly low-rank matrices: LAPACK's SVD (the oracle's Jacobi routes
+    # need a numerically full spectrum to meet their convergence test)
+    U, s, Vt = np.linalg.svd(X, full_matrices=False)
+    return s, U, Vt.T
+
+
+def _rank_r_forecast(x, L, group, h):
+    sh = oracle.shapes(x, None, None, L)
+    s, U, V = _lapack_svd(oracle.trajectory(x, sh))
+    rec = oracle.reconstruct(sh, s, U, V, group)[:, 0]
+    return oracle.rforecast_column([rec], U, group, h)[0]
+
+
+def test_rforecast_continues_a_sine():
+    """A pure cosine has rank 2 and satisfies an LRR: the forecast from the
+    group {1,2} continues it exactly."""
+    N, L, h = 96, 36, 30
+    t = np.arange(N + h)
+    x = 1.3 * np.cos(2 * np.pi * t / 12 + 0.4)
+    f = _rank_r_forecast(x[:N], L, [0, 1], h)
+    assert np.max(np.abs(f - x[N:])) <= 1e-9
+
+
+def test_rforecast_continues_an_exponential_and_a_line():
+    N, L, h = 60, 20, 15
+    t = np.arange(N + h)
+    x = 0.97 ** t
+    assert np.max(np.abs(_rank_r_forecast(x[:N], L, [0], h) - x[N:])) <= 1e-10
+    y = 2.0 + 0.1 * t          # a linear trend has rank 2
+    assert np.max(np.abs(_rank_r_forecast(y[:N], L, [0, 1], h) - y[N:])) <= 1e-9
+
+
+def test_rforecast_mssa_uses_one_lrr_for_all_series():
+    """MSSA of cosines of one period and different amplitudes and phases: the
+    common U gives one LRR that continues every series."""
+    L, h = 24, 20
+    lens = [80, 95, 110]
+    amp, ph = [1.0, 0.5, 2.0], [0.0, 1.0, 2.5]
+    full = [a * np.cos(2 * np.pi * np.arange(n + h) / 10 + p) for a, p, n in zip(amp, ph, lens)]
+    ser = [f[:n] for f, n in zip(full, lens)]
+    s, U, V = _lapack_svd(oracle.trajectory_mssa(ser, L))
+    recs = oracle.reconstruct_mssa(lens, L, s, U, V, [0, 1])
+    f = oracle.rforecast_column(recs, U, [0, 1], h)
+    for p, n in enumerate(lens):
+        assert np.max(np.abs(f[p] - full[p][n:])) <= 1e-9
