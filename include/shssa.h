@@ -167,8 +167,9 @@ int ssa_reconstruct(ssa_decomp* d, const int* grp_ptr, const int* grp_idx, int n
 int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* grp_ptr, const int* grp_idx,
                               int ngroups, double* const* out_dev);
 
-/* w-correlations and contributions of the reconstructed groups (Section
- * 2.1, separability paragraph).  With the weights w = |A_k| of
+/* w-correlations and contributions of the reconstructed groups (the
+ * general-notions subsection, separability and w-correlation paragraphs).
+ * With the weights w = |A_k| of
  * ssa_get_weights and the weighted inner product (Y, Z)_w = sum_k w_k y_k
  * z_k over the covered cells N': rho[a*ngroups + b] = (Y_a, Y_b)_w /
  * (|Y_a|_w |Y_b|_w) (means not subtracted; 0 if a component is zero) and
@@ -176,6 +177,19 @@ int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* grp_ptr, c
  * ssa_reconstruct (singletons give the w-correlation matrix of the
  * elementary components).  Synchronous. */
 int ssa_wcor(ssa_decomp* d, const int* grp_ptr, const int* grp_idx, int ngroups, double* rho, double* contrib);
+
+/* Column recurrent forecast (the MSSA forecasting subsection: recurrent
+ * column forecast, equation Forec:ContMSSAL; a single series is the case
+ * s = 1) of h values for each series of
+ * a decomposition whose window is one row or one column wide without mask
+ * (1D SSA, MSSA): the group's eigenvectors give the LRR
+ * R_L = sum_j pi(U_j) U_j[0:L-1] / (1 - nu^2), pi = last coordinate,
+ * nu^2 = sum_j pi(U_j)^2 (< 1 required), applied to the last L-1 values of
+ * the group's reconstruction of each series and then by recurrence.  grp:
+ * ng 0-based component ids.  out: nseries x h (series in the order of the
+ * caller's columns for a window one column high, rows otherwise).
+ * With out = NULL only *nseries is set.  Synchronous. */
+int ssa_rforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries);
 
 int  ssa_get_stats(const ssa_decomp* d, ssa_stats* st);
 void ssa_free(ssa_decomp* d);

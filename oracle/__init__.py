@@ -265,8 +265,9 @@ def reconstruct_mssa(series_lens, L, sigma, U, V, group) -> list:
 
 
 def wcor(x, sh: Shapes, sigma, U, V, groups):
-    """w-correlations and contributions of reconstructed groups (Section 2.1,
-    separability paragraph): the weighted inner product (Y, Z)_w =
+    """w-correlations and contributions of reconstructed groups (general-
+    notions subsection, separability and w-correlation paragraphs): the
+    weighted inner product (Y, Z)_w =
     sum_k w_k y_k z_k with w_k = |A_k| (the number of trajectory-matrix
     entries holding element k), rho_w(Y, Z) = (Y, Z)_w / (|Y|_w |Z|_w)
     without subtracting means, and the contribution of a component Y,
@@ -288,8 +289,9 @@ def wcor(x, sh: Shapes, sigma, U, V, groups):
 
 
 def lrr_column(U, group):
-    """Coefficients of the column recurrent forecast (Section 3.x, recurrent
-    MSSA forecast, column form; one series is the case s = 1): with pi(U_j)
+    """Coefficients of the column recurrent forecast (MSSA forecasting
+    subsection, recurrent column forecast, equation Forec:ContMSSAL; one
+    series is the case s = 1): with pi(U_j)
     the last coordinate of U_j and nu^2 = sum_j pi(U_j)^2 over the group,
     R_L = sum_j pi(U_j) U_j[0:L-1] / (1 - nu^2), an LRR of order L-1."""
     U = np.asarray(U, dtype=np.float64)

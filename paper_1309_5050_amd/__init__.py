@@ -101,6 +101,16 @@ class Decomposition:
         check(lib().ssa_reconstruct(self._h, _ptr(gp), _ptr(gi), len(groups), _ptr(out)), "ssa_reconstruct")
         return out
 
+    def rforecast(self, group, h: int) -> np.ndarray:
+        """Column recurrent forecast of h values from the group's
+        reconstruction: (series, h)."""
+        g = np.ascontiguousarray(group, dtype=np.int32)
+        ns = C.c_int()
+        check(lib().ssa_rforecast(self._h, _ptr(g), len(g), int(h), None, C.byref(ns)), "ssa_rforecast")
+        out = np.zeros((ns.value, int(h)))
+        check(lib().ssa_rforecast(self._h, _ptr(g), len(g), int(h), _ptr(out), C.byref(ns)), "ssa_rforecast")
+        return out
+
     def wcor(self, groups):
         """w-correlation matrix (ngroups, ngroups) and contributions
         (ngroups,) of the reconstructed groups."""

@@ -2549,6 +2549,47 @@ int ssa_wcor(ssa_decomp* d, const int* gp, const int* gi, int ng, double* rho, d
     return SSA_OK;
 }
 
+int ssa_rforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries) {
+    if (!d) return fail(SSA_EINVAL, "handle is NULL");
+    if (!d->rowfam) return fail(SSA_EINVAL, "recurrent forecast needs a window one row or column wide");
+    if (d->L != (long)d->LB) return fail(SSA_EINVAL, "recurrent forecast needs a window without mask");
+    if (nseries) *nseries = d->A;
+    if (!out) return SSA_OK;
+    if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
+    if (!grp || ng < 1 || h < 1) return fail(SSA_EINVAL, "bad group or horizon");
+    for (int k = 0; k < ng; ++k)
+        if (grp[k] < 0 || grp[k] >= d->r) return fail(SSA_EINVAL, "component id out of range");
+    g_tables_ctx = d->ctx;
+    TableScope tables(d->ctx, d->ctx->st);
+    Batch b(d->ctx);
+    b.ds = {d};
+    b.f64 = d->f64;
+    b.rowfam = d->rowfam;
+    b.cls = row_word(d->nh, d->f64);
+    b.set_col(d->ctx->tile_for(d->f64, d->MA));
+    const long n = (long)d->A * d->B;
+    const long L1 = d->L - 1;
+    int rc;
+    std::vector<int> g(grp, grp + ng);
+    DevVec rec, R, flag, buf, outd, dg;
+    if ((rc = rec.reserve((size_t)n * sizeof(double))) ||
+        (rc = run_reconstruct(b, std::vector<int>{0, ng}, g, {rec.as<double>()})))
+        return rc;
+    if ((rc = dg.put(g, b.st)) || (rc = R.reserve((size_t)std::max<long>(L1, 1) * sizeof(double))) ||
+        (rc = flag.reserve(sizeof(int))) || (rc = buf.reserve((size_t)d->A * (L1 + h) * sizeof(double))) ||
+        (rc = outd.reserve((size_t)d->A * h * sizeof(double))))
+        return rc;
+    launch_rforecast(b.st, d->U, d->L, dg.as<int>(), ng, R.as<double>(), flag.as<int>(), rec.as<double>(), d->W,
+                     d->A, d->B, h, buf.as<double>(), outd.as<double>());
+    HIPCHK(hipGetLastError());
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, flag.p, sizeof(int), hipMemcpyDeviceToHost, b.st));
+    HIPCHK(hipMemcpyAsync(out, outd.p, (size_t)d->A * h * sizeof(double), hipMemcpyDeviceToHost, b.st));
+    HIPCHK(hipStreamSynchronize(b.st));
+    if (bad) return fail(SSA_EINVAL, "no recurrent forecast: the group's last coordinates have nu^2 >= 1");
+    return SSA_OK;
+}
+
 int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* gp, const int* gi, int ng,
                               double* const* out_dev) {
     if (n <= 0 || !d || !out_dev) return fail(SSA_EINVAL, "bad arguments");

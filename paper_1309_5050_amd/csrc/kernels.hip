@@ -1987,6 +1987,78 @@ k_wgram_sum(const double* __restrict__ part, int nent, int nchunk, double* __res
     if (lane_id() == 0) out[e] = s;
 }
 
+// ------------------------------------------------------------------------
+// recurrent forecast (column form)
+// ------------------------------------------------------------------------
+
+// Sum of v over the 256 threads of the workgroup in a fixed order; every
+// thread gets the total.
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// LRR coefficients R[k] = sum_j pi_j U_j[k] / (1 - nu^2), k < L - 1, with
+// pi_j = U_j[L - 1] the last coordinate of group component j and nu^2 =
+// sum_j pi_j^2.  U: L x r column-major.  One workgroup; flag[0] = 1 when
+// nu^2 >= 1 (no forecast).
+__global__ void __launch_bounds__(256)
+k_lrr(const double* __restrict__ U, long L, const int* __restrict__ grp, int ng, double* __restrict__ R,
+      int* __restrict__ flag) {
+    __shared__ double red[4];
+    double p2 = 0.0;
+    for (int j = threadIdx.x; j < ng; j += 256) {
+        const double pj = U[(long)grp[j] * L + (L - 1)];
+        p2 += pj * pj;
+    }
+    const double nu2 = block_sum256(p2, red);
+    if (threadIdx.x == 0) flag[0] = nu2 < 1.0 ? 0 : 1;
+    const double sc = nu2 < 1.0 ? 1.0 / (1.0 - nu2) : 0.0;
+    for (long k = threadIdx.x; k < L - 1; k += 256) {
+        double s = 0.0;
+        for (int j = 0; j < ng; ++j) s += U[(long)grp[j] * L + (L - 1)] * U[(long)grp[j] * L + k];
+        R[k] = s * sc;
+    }
+}
+
+// Forecast of h values of series a (internal row a of the reconstruction
+// rec, A x B): n_a = the covered cells of the row (a prefix), then x_{n+1} =
+// sum_k R_k x_{n-L+1+k} over the last L - 1 values, by recurrence.  One
+// workgroup per row; buf (per row, L - 1 + h values) holds the running
+// window; out[a * h + k].
+__global__ void __launch_bounds__(256)
+k_rforecast(const double* __restrict__ rec, const double* __restrict__ W, int B, const double* __restrict__ R,
+            long L, int h, double* __restrict__ buf, double* __restrict__ out) {
+    __shared__ double red[4];
+    __shared__ int nmax[4];
+    const int a = blockIdx.x;
+    const long L1 = L - 1;
+    // covered length of the row: one past its last cell with W > 0
+    int last = 0;
+    for (int b = threadIdx.x; b < B; b += 256)
+        if (W[(long)a * B + b] > 0) last = max(last, b + 1);
+    for (int o = 32; o > 0; o >>= 1) last = max(last, __shfl_xor(last, o));
+    if (lane_id() == 0) nmax[threadIdx.x >> 6] = last;
+    __syncthreads();
+    const int n = max(max(nmax[0], nmax[1]), max(nmax[2], nmax[3]));
+    double* bw = buf + (long)a * (L1 + h);
+    for (long k = threadIdx.x; k < L1; k += 256) bw[k] = n - L1 + k >= 0 ? rec[(long)a * B + n - L1 + k] : 0.0;
+    __syncthreads();
+    for (int s = 0; s < h; ++s) {
+        double p = 0.0;
+        for (long k = threadIdx.x; k < L1; k += 256) p += R[k] * bw[s + k];
+        const double v = block_sum256(p, red);
+        if (threadIdx.x == 0) {
+            bw[L1 + s] = v;
+            out[(long)a * h + s] = v;
+        }
+        __syncthreads();
+    }
+}
+
 // Advance the batch's step counter (end of a replayed step).
 __global__ void k_step_next(int* step) {
     if (threadIdx.x == 0) step[0] += 1;

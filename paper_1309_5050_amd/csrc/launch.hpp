@@ -60,6 +60,11 @@ void launch_step_next(hipStream_t st, int* step);
 // (16 ib + i, 16 jb + j) of tile t at out[256 t + 16 i + j]; part holds
 // tiles*256*nchunk values.
 int wgram_tiles(int narr);
+// Column recurrent forecast: LRR R (L-1) from the group's U columns (flag[0]
+// = 1 if undefined), then h values per row of rec (A x B) into out (A x h);
+// buf holds A * (L-1+h) values.
+void launch_rforecast(hipStream_t st, const double* U, long L, const int* grp, int ng, double* R, int* flag,
+                      const double* rec, const double* W, int A, int B, int h, double* buf, double* out);
 void launch_wgram(hipStream_t st, const double* const* arr, int narr, const double* W, long ncell, int nchunk,
                   double* part, double* out);
 void launch_transpose(int nmat, int R, int C, hipStream_t st, const double* in, double* out);

@@ -150,6 +150,62 @@ def test_wcor_parity(ctx, name, prec):
             assert abs(rho[a, b] - rho_o[a, b]) <= bound, (name, prec, a, b, rho[a, b], rho_o[a, b], bound)
 
 
+def _rforecast_oracle(name, w, group, h):
+    sh, so, Uo, Vo = oracle_case(name, w)
+    if w["kind"] == "mssa":
+        lens = [len(x) for x in w["x"]]
+        recs = oracle.reconstruct_mssa(lens, w["window"], so, Uo, Vo, group)
+    else:
+        recs = [oracle.reconstruct(sh, so, Uo, Vo, group)[:, 0]]
+    return oracle.rforecast_column(recs, Uo, group, h), so
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,group", [("series_1000", [0, 1, 2, 3, 4, 5]), ("mssa_8", [0, 1, 2, 3])])
+def test_rforecast_parity(ctx, name, group, prec):
+    """Column recurrent forecast (24 values) from the GPU decomposition and
+    reconstruction against the oracle's.  The group is a union of gap-stable
+    groups whose span (and reconstruction) is within 20 tol s_1 / gap of the
+    oracle's, relative; the bound allows that relative to the largest
+    forecast value (the recurrence over 24 steps of these damped signals
+    does not amplify it)."""
+    w = CASES[name]()
+    tol = TOL[prec]
+    h = 24
+    ref, so = _rforecast_oracle(name, w, group, h)
+    d = gpu_case(ctx, w, prec)
+    got = d.rforecast(group, h)
+    if w["kind"] == "mssa":
+        assert got.shape == (len(w["x"]), h)
+    gap = so[group[-1]] - so[group[-1] + 1]
+    bound = 20 * tol * so[0] / gap * np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref))
+    print(f"{name} {prec}: forecast error {err:.3e} bound {bound:.3e}")
+    assert err <= bound, (name, prec, err, bound)
+
+
+def test_rforecast_continues_a_cosine(ctx):
+    """A pure cosine (rank 2) is continued exactly by its LRR."""
+    N, L, h = 300, 120, 40
+    t = np.arange(N + h)
+    x = 2.0 * np.cos(2 * np.pi * t / 15 + 0.3)
+    d = ctx.decompose(x[:N], L, 2)
+    f = d.rforecast([0, 1], h)[0]
+    assert np.max(np.abs(f - x[N:])) <= 1e-8
+
+
+def test_rforecast_errors(ctx):
+    import paper_1309_5050_amd as S
+    x = np.random.default_rng(3).standard_normal((30, 30))
+    d = ctx.decompose(x, (5, 5), 3)
+    with pytest.raises(S.SsaError):
+        d.rforecast([0], 5)            # a 2D window: no recurrent forecast
+    y = np.random.default_rng(4).standard_normal(200)
+    e = ctx.decompose(y, 50, 3)
+    with pytest.raises(S.SsaError):
+        e.rforecast([0, 5], 5)         # component beyond r
+
+
 def test_literal_groups_series(ctx):
     """The 1D workload's own groups {1-2},{3-4},{5} split near-degenerate
     sine pairs; their error is bounded by tol * s_1 / gap of each split."""
