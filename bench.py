@@ -151,6 +151,19 @@ def main():
                               "frac": wgram_gbs / HBM_PEAK_GBS, "bytes": pw["bytes"]},
             "max_offdiag_abs_rho": float(np.max(np.abs(rho - np.diag(np.diag(rho)))))}
 
+    # column recurrent forecast: 100 values of each of the 50 series of the
+    # MSSA workload (N_p ~ U(1000, 3000), L = 500, r = 20) from the group of
+    # the two shared sines, on an FP32 decomposition
+    wm = W.config(3)
+    dm = ctx.decompose_multi(wm["x"], wm["window"], wm["r"], precision="fp32")
+    torch.cuda.synchronize()
+    tf0 = time.perf_counter()
+    fc = dm.rforecast([0, 1, 2, 3], 100)
+    tf1 = time.perf_counter()
+    rforecast = {"workload": "MSSA 50 series N~U(1000,3000), L=500, r=20, fp32; group {1..4}, 100 steps",
+                 "series": int(fc.shape[0]), "steps": int(fc.shape[1]), "ms": 1e3 * (tf1 - tf0)}
+    dm.free()
+
     # plain single-instance FP64 path (same kernels, batch of one)
     single = None
     if not args.no_single:
@@ -195,6 +208,7 @@ def main():
         "roofline_kernels": roofs,
         "mfma": mfma,
         "wcor": wcor,
+        "rforecast": rforecast,
         "hbh_product": {"bytes_per_product": bmv, "products_per_step": products,
                         "effective_GBs": bmv * products / (dt / args.steps) / 1e9},
         "lanczos": {"steps": stats["steps"], "restarts": stats["restarts"], "basis": stats["basis"],
