@@ -448,3 +448,25 @@ def test_device_inputs_match_host(ctx):
     torch.cuda.synchronize()
     for o, b in zip(outs, host):
         assert np.array_equal(o.cpu().numpy(), b.reconstruct([[0, 1], [2, 3]]), equal_nan=True)
+
+
+def test_handle_outlives_its_stream():
+    """A handle whose work went to the context's own stream stays usable and
+    can be freed after set_stream has replaced (and destroyed) that stream:
+    a call leaves an event behind its work, not the stream."""
+    torch = pytest.importorskip("torch")
+    import paper_1309_5050_amd as S
+    c = S.Context(0)
+    try:
+        w = W.image_2d(n=96, lw=12, r=6, seed=77)
+        d = c.decompose(w["x"], (12, 12), 6)
+        s = torch.cuda.Stream()
+        c.set_stream(s.cuda_stream)          # the library's own stream is destroyed here
+        sig = d.sigma                        # waits on the handle's event
+        assert np.all(np.diff(sig) <= 0)
+        rec = d.reconstruct([[0, 1]])
+        assert np.isfinite(np.nanmax(rec))
+        d.free()
+        torch.cuda.synchronize()
+    finally:
+        c.close()
