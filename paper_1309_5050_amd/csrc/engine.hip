@@ -243,6 +243,21 @@ struct ssa_ctx {
         }
         blocks.clear();
     }
+    // as defer, behind an event the caller recorded (ownership moves here)
+    void defer_ev(std::vector<std::pair<void*, size_t>>& blocks, hipEvent_t e) {
+        deferred.push_back(Deferred{e, {}});
+        deferred.back().blocks.swap(blocks);
+        blocks.clear();
+    }
+    hipEvent_t take_event() {
+        if (!spare_ev.empty()) {
+            hipEvent_t e = spare_ev.back();
+            spare_ev.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        return hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess ? e : nullptr;
+    }
     void reclaim() {
         size_t k = 0;
         for (size_t i = 0; i < deferred.size(); ++i) {
@@ -405,7 +420,11 @@ struct ssa_decomp {
     std::vector<uint8_t> kmask_h;    // internal KA x KB (fetched on demand)
     std::vector<double> sigma_h;     // filled from the device on first request
     bool sigma_ready = false;
-    hipStream_t last_st = nullptr;   // stream of the last work queued on this handle
+    // Work queued on this handle: inside a library call the stream it went
+    // to (last_st); when a call returns, an event recorded behind it
+    // (last_ev), which stays valid whatever happens to the stream later.
+    hipStream_t last_st = nullptr;
+    hipEvent_t last_ev = nullptr;
     // device memory (blocks of the context pool, with their size class)
     std::vector<std::pair<void*, size_t>> allocs;
     size_t bytes = 0;
@@ -484,8 +503,11 @@ ssa_decomp::~ssa_decomp() {
     bool last = false;
     {
         std::lock_guard<std::mutex> g(ctx->mu);
-        if (last_st) {
-            ctx->defer(allocs, last_st);   // queued work may still use the blocks
+        if (last_ev) {
+            ctx->defer_ev(allocs, last_ev);   // queued work may still use the blocks
+            last_ev = nullptr;
+        } else if (last_st) {
+            ctx->defer(allocs, last_st);
         } else {
             for (auto& a : allocs) ctx->pool_put(a.first, a.second);
         }
@@ -1637,6 +1659,8 @@ int run_finish(Batch& b, FinishLists& F) {
     return SSA_OK;
 }
 
+int seal_handle(ssa_decomp* d);
+
 // Reconstruction of the same groups for every instance of the batch into
 // internal-orientation device buffers recon[i] (ngroups x A x B).
 int run_reconstruct(Batch& b, const std::vector<int>& gptr, const std::vector<int>& gidx,
@@ -1698,7 +1722,10 @@ int run_reconstruct(Batch& b, const std::vector<int>& gptr, const std::vector<in
                        RowOutArgs{OUT_IMAGE, 0, -1.0, 0, 0, 0});   // each instance's spec_scale
     }
     HIPCHK(hipGetLastError());
-    for (auto* d : b.ds) d->last_st = st;
+    for (auto* d : b.ds) {
+        d->last_st = st;
+        (void)seal_handle(d);
+    }
     return SSA_OK;
 }
 
@@ -1864,7 +1891,10 @@ int decompose_many(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** ou
     }
     for (int i = 0; i < n; ++i) {
         if (status) status[i] = st[i];
-        if (st[i] == SSA_OK || st[i] == SSA_ENOCONV) out[i] = ds[i].release();
+        if (st[i] == SSA_OK || st[i] == SSA_ENOCONV) {
+            (void)seal_handle(ds[i].get());
+            out[i] = ds[i].release();
+        }
     }
     return SSA_OK;
 }
@@ -1873,6 +1903,23 @@ int decompose_many(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** ou
 // completes); its device results are then final.
 int wait_handle(ssa_decomp* d) {
     if (d->last_st) HIPCHK(hipStreamSynchronize(d->last_st));
+    if (d->last_ev) HIPCHK(hipEventSynchronize(d->last_ev));
+    return SSA_OK;
+}
+
+// End of a library call that queued work on d: replace the stream by an
+// event recorded behind the work (the caller may destroy or replace the
+// stream afterwards).
+int seal_handle(ssa_decomp* d) {
+    if (!d->last_st) return SSA_OK;
+    if (!d->last_ev) {
+        std::lock_guard<std::mutex> g(d->ctx->mu);
+        d->last_ev = d->ctx->take_event();
+    }
+    if (!d->last_ev || hipEventRecord(d->last_ev, d->last_st) != hipSuccess) {
+        HIPCHK(hipStreamSynchronize(d->last_st));   // no event: wait instead
+    }
+    d->last_st = nullptr;
     return SSA_OK;
 }
 
