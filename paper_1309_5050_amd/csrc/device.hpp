@@ -54,6 +54,8 @@ struct LzDesc {
     double* np0;        // partial squared norms of w before its first projection, nblk
     void* lbuf[2];      // long vectors (operator precision), ping-pong by step parity
     double* lnp[2];     // partial squared norms of the long vectors, per long-set row
+    double* gam;        // [2] gamma_j = beta_{j-1} / alpha_{j-1} of the long update, by step parity
+                        // (written by the input pass of step j, read by its long update)
     long lwords;        // 32-bit words of lbuf[0] and lbuf[1] together (contiguous)
     int lrows;          // rows of lnp[0] and of lnp[1] (lnp[1] = lnp[0] + lrows)
     double* Bm;         // projected matrix, kMaxBasis x kMaxBasis column-major (rows: short)

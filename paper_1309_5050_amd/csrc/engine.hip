@@ -434,7 +434,7 @@ struct ssa_decomp {
     void *Xh = nullptr, *T1 = nullptr, *T2 = nullptr, *Us = nullptr;
     long tslot = 0, uslot = 0;
     double *Q = nullptr, *w = nullptr, *sinv = nullptr, *hp1 = nullptr, *hp2 = nullptr, *np = nullptr, *np0 = nullptr;
-    double *lnp = nullptr, *Bm = nullptr, *Yl = nullptr, *Yr = nullptr, *sig = nullptr, *beta = nullptr;
+    double *lnp = nullptr, *gam = nullptr, *Bm = nullptr, *Yl = nullptr, *Yr = nullptr, *sig = nullptr, *beta = nullptr;
     double* Qtmp = nullptr;
     void* lbuf = nullptr;
     int *perm = nullptr, *flag = nullptr;
@@ -1142,7 +1142,7 @@ int run_alloc_spectrum(Batch& b) {
         if ((rc = d->dalloc(&d->Q, n * (kMaxBasis + 1))) || (rc = d->dalloc(&d->w, n)) ||
             (rc = d->dalloc(&d->sinv, n)) || (rc = d->dalloc(&d->hp1, (long)nblk * (kMaxBasis + 1))) ||
             (rc = d->dalloc(&d->hp2, (long)nblk * (kMaxBasis + 1))) || (rc = d->dalloc(&d->np, nblk)) ||
-            (rc = d->dalloc(&d->np0, nblk)) ||
+            (rc = d->dalloc(&d->np0, nblk)) || (rc = d->dalloc(&d->gam, 2)) ||
             (rc = d->dalloc(&d->lnp, 2 * longrows)) || (rc = d->dalloc(&d->Bm, kMaxBasis * kMaxBasis)) ||
             (rc = d->dalloc(&d->Yl, kMaxBasis * kMaxBasis)) || (rc = d->dalloc(&d->Yr, kMaxBasis * kMaxBasis)) ||
             (rc = d->dalloc(&d->sig, kMaxBasis)) || (rc = d->dalloc(&d->beta, 4)) ||
@@ -1177,6 +1177,7 @@ int run_alloc_spectrum(Batch& b) {
         z.lbuf[1] = static_cast<char*>(d->lbuf) + d->nlong * (d->f64 ? 8 : 4);
         z.lnp[0] = d->lnp;
         z.lnp[1] = d->lnp + longrows;
+        z.gam = d->gam;
         z.lwords = 2 * d->nlong * (d->f64 ? 2 : 1);   // zeroed by the start kernel
         z.lrows = (int)longrows;
         z.Bm = d->Bm; z.Yl = d->Yl; z.Yr = d->Yr; z.sig = d->sig; z.perm = d->perm;

@@ -191,6 +191,16 @@ __device__ __forceinline__ RowInSrc row_in_source(const OpDesc& op, const LzDesc
                 if (args.j > 0 && !fresh) lz.Bm[(long)(args.j - 1) * kMaxBasis + args.j] = bd ? 0.0 : beta;
                 if (bd) lz.flag[2] = 1;
             }
+            // gamma_j of this step's long update (beta_{j-1} / alpha_{j-1}),
+            // formed once here by the work item holding set row 0 instead of
+            // by every work item of the long-side pass.  The first step of a
+            // cycle has none.
+            if (args.mode == IN_LZ_NORM && item.idx == 0 && args.j > 0) {
+                const int p = args.j & 1;
+                const double alpha = sqrt(sum_parts(lz.lnp[p ^ 1], op.S[1 - args.set].boxA));
+                const double gm = (!bd && alpha > 1e-300) ? beta / alpha : 0.0;
+                if (leader) lz.gam[p] = gm;
+            }
         } else if (args.mode == IN_LZ_SIN) {
             r.src = lz.sin;
         } else {
@@ -279,13 +289,11 @@ __device__ __forceinline__ GkLong<T> gk_long(const LzDesc& lz, const CellSet& Sl
     g.lcur = static_cast<T*>(lz.lbuf[p]);
     g.lprev = static_cast<const T*>(lz.lbuf[p ^ 1]);
     g.lnp = lz.lnp[p];
-    double gm = 0.0;
-    if (j != jstart && lz.flag[2] == 0) {
-        const double beta = sqrt(sum_parts(lz.np, lz.nblk));
-        const double alpha = sqrt(sum_parts(lz.lnp[p ^ 1], Slong.boxA));
-        gm = alpha > 1e-300 ? beta / alpha : 0.0;
-    }
+    // gamma_j was formed by this step's input pass (0 on the first step of
+    // a cycle and after a breakdown)
+    const double gm = j != jstart ? lz.gam[p] : 0.0;
     g.gamma = static_cast<T>(gm);
+    (void)Slong;
     return g;
 }
 
