@@ -318,6 +318,46 @@ def rforecast_column(recs, U, group, h: int):
     return out
 
 
+def vforecast_column(series_lens, L: int, sigma, U, V, group, h: int):
+    """Column vector forecast (MSSA forecasting subsection, vector MSSA
+    forecasting, column forecast; one series is the case s = 1), from its
+    definition.  Series p owns the K_p = N_p - L + 1 columns of the stacked
+    trajectory matrix (in series order in V).  Its lagged vectors start as
+    the columns of the group's reconstructed matrix, Z_k = sum_j sigma_j U_j
+    V_j[k]; each next vector is P(Z_{k-1}), where P maps z to (Pi zbar,
+    R_L . zbar) with zbar the last L-1 coordinates of z, Pi the orthogonal
+    projector onto the span of the group's U_j without their last coordinate
+    and R_L the column LRR (equation Forec:ContMSSAL).  After h + L - 1 new
+    vectors, the diagonal average of [Z_1 : ... ] holds the forecast at
+    positions N_p .. N_p + h - 1.  Returns an (s, h) array."""
+    U = np.asarray(U, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    g = list(group)
+    R = lrr_column(U, g)                 # raises when nu^2 >= 1
+    Qb, _ = np.linalg.qr(U[:-1, g])      # orthonormal basis of the projected span
+    lens = [int(n) for n in series_lens]
+    out = np.zeros((len(lens), h))
+    off = 0
+    for p, n in enumerate(lens):
+        K = n - L + 1
+        Xh = (U[:, g] * sigma[g]) @ V[off:off + K, g].T      # L x K_p
+        off += K
+        Z = [Xh[:, k] for k in range(K)]
+        for _ in range(h + L - 1):
+            zbar = Z[-1][1:]
+            Z.append(np.concatenate([Qb @ (Qb.T @ zbar), [float(R @ zbar)]]))
+        Zm = np.stack(Z, axis=1)
+        ncol = Zm.shape[1]
+        acc = np.zeros(L + ncol - 1)
+        cnt = np.zeros(L + ncol - 1)
+        for i in range(L):
+            acc[i:i + ncol] += Zm[i]
+            cnt[i:i + ncol] += 1.0
+        out[p] = (acc / cnt)[n:n + h]
+    return out
+
+
 # --------------------------------------------------------------------------
 # whole decompositions
 # --------------------------------------------------------------------------

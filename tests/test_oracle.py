@@ -519,3 +519,90 @@ def test_rforecast_mssa_uses_one_lrr_for_all_series():
     f = oracle.rforecast_column(recs, U, [0, 1], h)
     for p, n in enumerate(lens):
         assert np.max(np.abs(f[p] - full[p][n:])) <= 1e-9
+
+
+# --------------------------------------------------------------------------
+# vector (column) forecast
+# --------------------------------------------------------------------------
+
+def _rank_r_vforecast(x, L, group, h):
+    sh = oracle.shapes(x, None, None, L)
+    s, U, V = _lapack_svd(oracle.trajectory(x, sh))
+    return oracle.vforecast_column([len(x)], L, s, U, V, group, h)[0]
+
+
+def test_vforecast_continues_finite_rank_series():
+    """Series of finite rank lie in their signal subspace: every lagged
+    vector of the continuation is the true one, so the forecast is exact."""
+    N, L, h = 90, 30, 25
+    t = np.arange(N + h)
+    x = 1.3 * np.cos(2 * np.pi * t / 12 + 0.4)
+    assert np.max(np.abs(_rank_r_vforecast(x[:N], L, [0, 1], h) - x[N:])) <= 1e-9
+    y = 0.97 ** t
+    assert np.max(np.abs(_rank_r_vforecast(y[:N], L, [0], h) - y[N:])) <= 1e-10
+    z = 2.0 + 0.1 * t
+    assert np.max(np.abs(_rank_r_vforecast(z[:N], L, [0, 1], h) - z[N:])) <= 1e-9
+
+
+def test_vforecast_mssa_continues_every_series():
+    L, h = 24, 20
+    lens = [80, 95, 110]
+    amp, ph = [1.0, 0.5, 2.0], [0.0, 1.0, 2.5]
+    full = [a * np.cos(2 * np.pi * np.arange(n + h) / 10 + p) for a, p, n in zip(amp, ph, lens)]
+    ser = [f[:n] for f, n in zip(full, lens)]
+    s, U, V = _lapack_svd(oracle.trajectory_mssa(ser, L))
+    f = oracle.vforecast_column(lens, L, s, U, V, [0, 1], h)
+    for p, n in enumerate(lens):
+        assert np.max(np.abs(f[p] - full[p][n:])) <= 1e-9
+
+
+def _noisy_case():
+    g = np.random.default_rng(17)
+    N, L = 140, 40
+    t = np.arange(N)
+    x = np.cos(2 * np.pi * t / 11) + 0.02 * t + 0.3 * g.standard_normal(N)
+    sh = oracle.shapes(x, None, None, L)
+    s, U, V = _lapack_svd(oracle.trajectory(x, sh))
+    return x, L, s, U, V
+
+
+def test_vforecast_does_not_redraw():
+    """A longer horizon extends a shorter one without changing it (the
+    number of new lagged vectors grows with the horizon for that reason)."""
+    x, L, s, U, V = _noisy_case()
+    a = oracle.vforecast_column([len(x)], L, s, U, V, [0, 1, 2], 10)
+    b = oracle.vforecast_column([len(x)], L, s, U, V, [0, 1, 2], 17)
+    assert np.max(np.abs(a - b[:, :10])) <= 1e-12
+
+
+def test_vforecast_matches_the_shift_matrix_route():
+    """The fast algorithm of the forecast implementation section carries the
+    coefficient vectors W_k = D W_{k-1} with D the pseudo-inverse of the
+    group's U without its last row times U without its first row; the
+    forecast is then an anti-diagonal average of U W.  It must agree with
+    the definition on a noisy series whose group is no exact signal."""
+    x, L, s, U, V = _noisy_case()
+    grp, h = [0, 1, 2], 15
+    N = len(x)
+    K = N - L + 1
+    Ug = U[:, grp]
+    D = np.linalg.lstsq(Ug[:-1], Ug[1:], rcond=None)[0]
+    w = s[grp] * V[K - 1, grp]
+    Ws = []
+    for _ in range(h + L - 1):
+        w = D @ w
+        Ws.append(w)
+    Ws = np.array(Ws)                            # row e: column K + e (0-based)
+    fast = np.array([np.mean([Ug[i] @ Ws[L - 1 + t - i] for i in range(L)]) for t in range(h)])
+    ref = oracle.vforecast_column([N], L, s, U, V, grp, h)[0]
+    assert np.max(np.abs(fast - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_vforecast_rejects_a_group_spanning_the_last_axis():
+    L = 10
+    U = np.eye(L)[:, :2]                     # e_1, e_2: fine
+    V = np.eye(20)[:, :2]
+    oracle.vforecast_column([L + 19], L, np.ones(2), U, V, [0, 1], 3)
+    U2 = np.eye(L)[:, [0, L - 1]]            # e_L in the span: nu^2 = 1
+    with pytest.raises(ValueError):
+        oracle.vforecast_column([L + 19], L, np.ones(2), U2, V, [0, 1], 3)
