@@ -160,8 +160,11 @@ def main():
     tf0 = time.perf_counter()
     fc = dm.rforecast([0, 1, 2, 3], 100)
     tf1 = time.perf_counter()
+    fv = dm.vforecast([0, 1, 2, 3], 100)
+    tf2 = time.perf_counter()
     rforecast = {"workload": "MSSA 50 series N~U(1000,3000), L=500, r=20, fp32; group {1..4}, 100 steps",
-                 "series": int(fc.shape[0]), "steps": int(fc.shape[1]), "ms": 1e3 * (tf1 - tf0)}
+                 "series": int(fc.shape[0]), "steps": int(fc.shape[1]), "ms": 1e3 * (tf1 - tf0),
+                 "vector_ms": 1e3 * (tf2 - tf1), "vector_series": int(fv.shape[0])}
     dm.free()
 
     # plain single-instance FP64 path (same kernels, batch of one)

@@ -191,6 +191,24 @@ int ssa_wcor(ssa_decomp* d, const int* grp_ptr, const int* grp_idx, int ngroups,
  * With out = NULL only *nseries is set.  Synchronous. */
 int ssa_rforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries);
 
+/* Column vector forecast (the MSSA forecasting subsection: vector MSSA
+ * forecasting, column forecast; a single series is the case s = 1),
+ * computed by the fast algorithm of the forecast implementation section,
+ * for the same decompositions as ssa_rforecast.  Each series' lagged
+ * vectors are continued inside the group's span: starting from its last
+ * column of the group's reconstructed matrix, each new vector keeps the
+ * projection of the previous one's last L-1 coordinates onto the group's
+ * U_j without their last coordinate and takes R_L of that for its last;
+ * after h + L - 1 new vectors the diagonal average of the extended matrix
+ * gives the h values that follow each series.  Only coefficient vectors in
+ * the group's basis are carried: w_k = D w_{k-1}, with D the pseudo-inverse
+ * of the basis without its last row times the basis without its first row.
+ * grp: ng (<= 64) 0-based component ids, nu^2 < 1 required.  Each series'
+ * last lagged vector must end at its last covered value.  out: nseries x h,
+ * series ordered as for ssa_rforecast.  With out = NULL only *nseries is
+ * set.  Synchronous. */
+int ssa_vforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries);
+
 int  ssa_get_stats(const ssa_decomp* d, ssa_stats* st);
 void ssa_free(ssa_decomp* d);
 

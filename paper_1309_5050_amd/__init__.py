@@ -111,6 +111,15 @@ class Decomposition:
         check(lib().ssa_rforecast(self._h, _ptr(g), len(g), int(h), _ptr(out), C.byref(ns)), "ssa_rforecast")
         return out
 
+    def vforecast(self, group, h: int) -> np.ndarray:
+        """Column vector forecast of h values after each series: (series, h)."""
+        g = np.ascontiguousarray(group, dtype=np.int32)
+        ns = C.c_int()
+        check(lib().ssa_vforecast(self._h, _ptr(g), len(g), int(h), None, C.byref(ns)), "ssa_vforecast")
+        out = np.zeros((ns.value, int(h)))
+        check(lib().ssa_vforecast(self._h, _ptr(g), len(g), int(h), _ptr(out), C.byref(ns)), "ssa_vforecast")
+        return out
+
     def wcor(self, groups):
         """w-correlation matrix (ngroups, ngroups) and contributions
         (ngroups,) of the reconstructed groups."""

@@ -101,6 +101,10 @@ enum InMode : int {
 // (LzDesc::step), so one captured step can be replayed for every j.
 constexpr int kStepDev = -1;
 
+// Largest group of a vector forecast (one lane of a wave per coordinate of
+// the carried coefficient vectors).
+constexpr int kVfMaxGroup = 64;
+
 enum RowDest : int {
     DEST_T1 = 0,      // scratch slot `comp` of T1
     DEST_XH = 1,      // spectrum rows (row family), times the spectrum scale

@@ -2638,6 +2638,49 @@ int ssa_rforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int
     return SSA_OK;
 }
 
+int ssa_vforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries) {
+    if (!d) return fail(SSA_EINVAL, "handle is NULL");
+    if (!d->rowfam) return fail(SSA_EINVAL, "vector forecast needs a window one row or column wide");
+    if (d->L != (long)d->LB) return fail(SSA_EINVAL, "vector forecast needs a window without mask");
+    if (nseries) *nseries = d->A;
+    if (!out) return SSA_OK;
+    if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
+    if (!grp || ng < 1 || h < 1) return fail(SSA_EINVAL, "bad group or horizon");
+    if (ng > kVfMaxGroup) return fail(SSA_EINVAL, "vector forecast group larger than 64 components");
+    for (int k = 0; k < ng; ++k)
+        if (grp[k] < 0 || grp[k] >= d->r) return fail(SSA_EINVAL, "component id out of range");
+    int rc;
+    if ((rc = wait_handle(d))) return rc;
+    g_tables_ctx = d->ctx;
+    TableScope tables(d->ctx, d->ctx->st);
+    hipStream_t st = d->ctx->st;
+    const long E = (long)h + d->L - 1;
+    std::vector<int> g(grp, grp + ng);
+    DevVec dg, M, flag, wbuf, outd;
+    if ((rc = dg.put(g, st)) || (rc = flag.put(std::vector<int>{0, 0}, st)) ||
+        (rc = M.reserve((size_t)ng * ng * sizeof(double))) ||
+        (rc = wbuf.reserve((size_t)d->A * E * ng * sizeof(double))) ||
+        (rc = outd.reserve((size_t)d->A * h * sizeof(double))))
+        return rc;
+    {
+        // algorithmic bytes: the group's U columns and the coefficient vectors
+        // written and read once per row, the forecasts written
+        ProfSpan p(d->ctx, "vforecast", st, [&] {
+            return 8.0 * ((double)ng * d->L + 2.0 * d->A * E * ng + (double)d->A * h);
+        });
+        launch_vforecast(st, d->U, d->L, d->V, d->K, d->sigma, dg.as<int>(), ng, M.as<double>(), d->krow, d->kmask,
+                         d->KB, d->W, d->A, d->B, h, wbuf.as<double>(), outd.as<double>(), flag.as<int>());
+    }
+    HIPCHK(hipGetLastError());
+    int bad[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(bad, flag.p, sizeof(bad), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(out, outd.p, (size_t)d->A * h * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (bad[1]) return fail(SSA_EINVAL, "no vector forecast: the group's last coordinates have nu^2 >= 1");
+    if (bad[0]) return fail(SSA_EINVAL, "no vector forecast: a series' last lagged vector misses its last value");
+    return SSA_OK;
+}
+
 int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* gp, const int* gi, int ng,
                               double* const* out_dev) {
     if (n <= 0 || !d || !out_dev) return fail(SSA_EINVAL, "bad arguments");

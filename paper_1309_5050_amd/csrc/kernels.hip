@@ -2067,6 +2067,116 @@ k_rforecast(const double* __restrict__ rec, const double* __restrict__ W, int B,
     }
 }
 
+// Broadcast of lane j's value to the whole wave (j wave-uniform).
+__device__ __forceinline__ double lane_bcast(double v, int j) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b), j));
+    const long long hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), j);
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// Vector forecast, shift part: M[i * ng + j] = sum_{l < L-1} U_{g_i}[l]
+// U_{g_j}[l + 1], the group's window vectors without their last coordinate
+// against the same vectors without their first.  One wave per entry.
+__global__ void __launch_bounds__(256)
+k_vf_shift(const double* __restrict__ U, long L, const int* __restrict__ grp, int ng, double* __restrict__ M) {
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= ng * ng) return;   // whole waves
+    const double* ui = U + (long)grp[e / ng] * L;
+    const double* uj = U + (long)grp[e % ng] * L + 1;
+    double s = 0.0;
+    for (long l = lane_id(); l < L - 1; l += 64) s += ui[l] * uj[l];
+    s = wave_sum(s);
+    if (lane_id() == 0) M[e] = s;
+}
+
+// Column vector forecast of series a (internal row a), by the fast
+// algorithm of the forecast implementation section: the lagged vectors of
+// the continuation stay in the group's span, so only their coefficient
+// vectors are carried, w_k = D w_{k-1} with
+// D = (I + pi pi^T / (1 - nu^2)) M.  For an orthonormal basis that is the
+// pseudo-inverse of the basis without its last row times the basis without
+// its first row (pi: the last row, nu^2 = |pi|^2).  w_0 = sigma_j V_j at
+// the row's last origin cell; forecast t is the mean over i < L of
+// (U w_{L-1+t-i})_i, the anti-diagonal of the extended matrix through
+// position n + t.  wbuf: per row (h + L - 1) x ng.  flag[0] = 1: a row
+// whose last lagged vector does not end at its covered end; flag[1] = 1:
+// nu^2 >= 1.  Such rows get NaN.
+__global__ void __launch_bounds__(256)
+k_vforecast(const double* __restrict__ U, long L, const double* __restrict__ V, long K,
+            const double* __restrict__ sigma, const int* __restrict__ grp, int ng, const double* __restrict__ M,
+            const int* __restrict__ krow, const uint8_t* __restrict__ kmask, int KB, const double* __restrict__ W,
+            int B, int h, double* __restrict__ wbuf, double* __restrict__ out, int* __restrict__ flag) {
+    constexpr int LD = kVfMaxGroup + 1;
+    __shared__ double Ds[kVfMaxGroup * LD];
+    __shared__ double pis[kVfMaxGroup], cs[kVfMaxGroup];
+    __shared__ int ext[2][4];
+    const int a = blockIdx.x, tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
+    const long E = (long)h + L - 1;
+    // covered length n of the row and its last origin column
+    int last = 0, klast = -1;
+    for (int b = tid; b < B; b += 256)
+        if (W[(long)a * B + b] > 0) last = b + 1;
+    for (int b = tid; b < KB; b += 256)
+        if (kmask[(long)a * KB + b]) klast = b;
+    for (int o = 32; o > 0; o >>= 1) {
+        last = max(last, __shfl_xor(last, o));
+        klast = max(klast, __shfl_xor(klast, o));
+    }
+    if (lane == 0) {
+        ext[0][wv] = last;
+        ext[1][wv] = klast;
+    }
+    if (tid < ng) pis[tid] = U[(long)grp[tid] * L + (L - 1)];
+    __syncthreads();
+    const int n = max(max(ext[0][0], ext[0][1]), max(ext[0][2], ext[0][3]));
+    const int kl = max(max(ext[1][0], ext[1][1]), max(ext[1][2], ext[1][3]));
+    double nu2 = 0.0;
+    for (int j = 0; j < ng; ++j) nu2 += pis[j] * pis[j];
+    const bool row_ok = kl >= 0 && kl + L == n;
+    if (!row_ok || !(nu2 < 1.0)) {
+        if (tid == 0) flag[row_ok ? 1 : 0] = 1;
+        for (int t = tid; t < h; t += 256) out[(long)a * h + t] = __builtin_nan("");
+        return;
+    }
+    if (tid < ng) {
+        double c = 0.0;
+        for (int i = 0; i < ng; ++i) c += pis[i] * M[i * ng + tid];
+        cs[tid] = c;
+    }
+    __syncthreads();
+    const double sc = 1.0 / (1.0 - nu2);
+    for (int e = tid; e < ng * ng; e += 256) {
+        const int i = e / ng, j = e % ng;
+        Ds[i * LD + j] = M[e] + pis[i] * cs[j] * sc;
+    }
+    __syncthreads();
+    double* wb = wbuf + (long)a * E * ng;
+    if (wv == 0) {
+        // the recursion: lane i holds coordinate i of w
+        const long kidx = krow[a + 1] - 1;
+        double w = lane < ng ? sigma[grp[lane]] * V[(long)grp[lane] * K + kidx] : 0.0;
+        const double* drow = Ds + (lane < ng ? lane : 0) * LD;
+        for (long e = 0; e < E; ++e) {
+            double s = 0.0;
+            for (int j = 0; j < ng; ++j) s += drow[j] * lane_bcast(w, j);
+            w = s;
+            if (lane < ng) wb[e * ng + lane] = w;
+        }
+    }
+    __syncthreads();
+    // forecasts: one wave per value, lanes over the window coordinates
+    for (int t = wv; t < h; t += 4) {
+        double s = 0.0;
+        for (long i = lane; i < L; i += 64) {
+            const double* we = wb + (L - 1 + t - i) * ng;
+            for (int j = 0; j < ng; ++j) s += U[(long)grp[j] * L + i] * we[j];
+        }
+        s = wave_sum(s);
+        if (lane == 0) out[(long)a * h + t] = s / (double)L;
+    }
+}
+
 // Advance the batch's step counter (end of a replayed step).
 __global__ void k_step_next(int* step) {
     if (threadIdx.x == 0) step[0] += 1;

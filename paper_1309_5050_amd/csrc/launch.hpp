@@ -65,6 +65,13 @@ int wgram_tiles(int narr);
 // buf holds A * (L-1+h) values.
 void launch_rforecast(hipStream_t st, const double* U, long L, const int* grp, int ng, double* R, int* flag,
                       const double* rec, const double* W, int A, int B, int h, double* buf, double* out);
+// Column vector forecast: shift matrix M (ng x ng) of the group's U columns,
+// then h values per row into out (A x h); wbuf holds A * (h+L-1) * ng
+// values; flag[0..1] (zeroed by the caller) report rows or a group without
+// a forecast.  ng <= kVfMaxGroup.
+void launch_vforecast(hipStream_t st, const double* U, long L, const double* V, long K, const double* sigma,
+                      const int* grp, int ng, double* M, const int* krow, const uint8_t* kmask, int KB,
+                      const double* W, int A, int B, int h, double* wbuf, double* out, int* flag);
 void launch_wgram(hipStream_t st, const double* const* arr, int narr, const double* W, long ncell, int nchunk,
                   double* part, double* out);
 void launch_transpose(int nmat, int R, int C, hipStream_t st, const double* in, double* out);

@@ -470,3 +470,76 @@ def test_handle_outlives_its_stream():
         torch.cuda.synchronize()
     finally:
         c.close()
+
+
+def _vforecast_oracle(name, w, group, h):
+    sh, so, Uo, Vo = oracle_case(name, w)
+    lens = [len(x) for x in w["x"]] if w["kind"] == "mssa" else [len(w["x"])]
+    return oracle.vforecast_column(lens, w["window"], so, Uo, Vo, group, h), so
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,group", [("series_1000", [0, 1, 2, 3, 4, 5]), ("mssa_8", [0, 1, 2, 3])])
+def test_vforecast_parity(ctx, name, group, prec):
+    """Column vector forecast (24 values) from the GPU decomposition against
+    the oracle's (its projector definition on the oracle's triplets), with
+    the bound of the recurrent forecast: the group's span and coefficients
+    are within 20 tol s_1 / gap of the oracle's, relative to the largest
+    forecast value."""
+    w = CASES[name]()
+    tol = TOL[prec]
+    h = 24
+    ref, so = _vforecast_oracle(name, w, group, h)
+    d = gpu_case(ctx, w, prec)
+    got = d.vforecast(group, h)
+    assert got.shape == ref.shape
+    gap = so[group[-1]] - so[group[-1] + 1]
+    bound = 20 * tol * so[0] / gap * np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref))
+    print(f"{name} {prec}: vector forecast error {err:.3e} bound {bound:.3e}")
+    assert err <= bound, (name, prec, err, bound)
+
+
+def test_vforecast_continues_a_cosine(ctx):
+    """A pure cosine (rank 2) lies in its signal subspace: the vector
+    forecast continues it exactly, as the recurrent one does."""
+    N, L, h = 300, 120, 40
+    t = np.arange(N + h)
+    x = 2.0 * np.cos(2 * np.pi * t / 15 + 0.3)
+    d = ctx.decompose(x[:N], L, 2)
+    f = d.vforecast([0, 1], h)[0]
+    assert np.max(np.abs(f - x[N:])) <= 1e-8
+    assert np.max(np.abs(f - d.rforecast([0, 1], h)[0])) <= 1e-8
+
+
+def test_vforecast_longer_horizon_extends_shorter(ctx):
+    w = CASES["mssa_8"]()
+    d = gpu_case(ctx, w, "fp64")
+    a = d.vforecast([0, 1, 2], 10)
+    b = d.vforecast([0, 1, 2], 31)
+    assert np.max(np.abs(a - b[:, :10])) <= 1e-12 * np.max(np.abs(b))
+
+
+def test_vforecast_errors(ctx):
+    import paper_1309_5050_amd as S
+    x = np.random.default_rng(3).standard_normal((30, 30))
+    d = ctx.decompose(x, (5, 5), 3)
+    with pytest.raises(S.SsaError):
+        d.vforecast([0], 5)            # a 2D window: no vector forecast
+    y = np.random.default_rng(4).standard_normal(200)
+    e = ctx.decompose(y, 50, 3)
+    with pytest.raises(S.SsaError):
+        e.vforecast([0, 5], 5)         # component beyond r
+
+
+def test_vforecast_starts_after_the_last_covered_value(ctx):
+    """Values after a gap too short for a window are outside every lagged
+    vector: the forecast follows the last covered value, as for the series
+    cut there."""
+    t = np.arange(200)
+    y = 3.0 * np.cos(2 * np.pi * t / 17) + 0.1 * np.random.default_rng(8).standard_normal(200)
+    y2 = y.copy()
+    y2[197] = np.nan
+    a = ctx.decompose(y[:197], 50, 4).vforecast([0, 1], 6)
+    b = ctx.decompose(y2, 50, 4).vforecast([0, 1], 6)
+    assert np.max(np.abs(a - b)) <= 1e-8 * np.max(np.abs(a))
