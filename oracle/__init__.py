@@ -358,6 +358,99 @@ def vforecast_column(series_lens, L: int, sigma, U, V, group, h: int):
     return out
 
 
+def _row_blocks(series_lens, L):
+    """Start and end (exclusive) of each series' block of K_p = N_p - L + 1
+    columns in the stacked trajectory matrix."""
+    ks = [int(n) - L + 1 for n in series_lens]
+    ends = np.cumsum(ks)
+    return [(int(e - k), int(e)) for k, e in zip(ks, ends)]
+
+
+def lrr_row(series_lens, L, V, group):
+    """Coefficients of the recurrent row forecast (MSSA forecasting
+    subsection, recurrent row forecast, equation Forec:ContMSSAK):
+    R_K = (I_s - S S^T)^{-1} S Vlow^T, an s x (K - s) matrix, where S holds
+    the last coordinate of each series' block of the group's V_j (s x ng) and
+    Vlow the group's V_j without those coordinates (blocks in series order).
+    Row p applied to the stacked last K_q - 1 values of every series q gives
+    the next value of series p."""
+    V = np.asarray(V, dtype=np.float64)[:, list(group)]
+    blocks = _row_blocks(series_lens, L)
+    S = np.array([V[e - 1] for _, e in blocks])
+    Vlow = np.concatenate([V[b:e - 1] for b, e in blocks])
+    Ms = np.eye(len(blocks)) - S @ S.T
+    if np.linalg.cond(Ms) > 1e12:
+        raise ValueError("I - S S^T is singular: no row forecast")
+    return np.linalg.solve(Ms, S @ Vlow.T)
+
+
+def rforecast_row(recs, L, V, group, h: int):
+    """Recurrent row forecast of h values for each reconstructed series in
+    recs (the group's reconstruction of each series): the next values of
+    all series are R_K times the stacked last K_p - 1 values of every
+    series, then by recurrence on the extended series.  Returns (s, h)."""
+    lens = [len(y) for y in recs]
+    R = lrr_row(lens, L, V, group)
+    ext = [list(np.asarray(y, dtype=np.float64)) for y in recs]
+    out = np.zeros((len(recs), h))
+    for m in range(h):
+        Z = np.concatenate([np.asarray(e[len(e) - (n - L):]) for e, n in zip(ext, lens)])
+        nxt = R @ Z
+        for p in range(len(recs)):
+            ext[p].append(float(nxt[p]))
+        out[:, m] = nxt
+    return out
+
+
+def vforecast_row(series_lens, L: int, sigma, U, V, group, h: int):
+    """Row vector forecast (MSSA forecasting subsection, vector MSSA
+    forecasting, row forecast), from its definition.  The rows Y_i of the
+    group's reconstructed matrix (K-vectors, i < L) are continued by the map
+    that takes the first-dropped part of each block of the previous row
+    (all but the first coordinate of each block), projects it onto the span
+    of the group's V_j without the last coordinate of each block for the
+    new row's leading coordinates, and takes R_K of it for the new row's
+    last coordinate of each block.  After h + K* - 1 new rows (K* the
+    largest K_p), each series is the diagonal average of its block of
+    columns; positions N_p .. N_p + h - 1 are its forecast.  Returns (s, h)."""
+    U = np.asarray(U, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    g = list(group)
+    lens = [int(n) for n in series_lens]
+    blocks = _row_blocks(lens, L)
+    R = lrr_row(lens, L, V, g)
+    Vg = V[:, g]
+    Qb, _ = np.linalg.qr(np.concatenate([Vg[b:e - 1] for b, e in blocks]))
+    Xh = (U[:, g] * sigma[g]) @ Vg.T                     # L x K
+    rows = [Xh[i] for i in range(L)]
+    kstar = max(e - b for b, e in blocks)
+    for _ in range(h + kstar - 1):
+        prev = rows[-1]
+        zf = np.concatenate([prev[b + 1:e] for b, e in blocks])    # each block without its first
+        low = Qb @ (Qb.T @ zf)
+        last = R @ zf
+        new = np.zeros_like(prev)
+        o = 0
+        for p, (b, e) in enumerate(blocks):
+            new[b:e - 1] = low[o:o + (e - 1 - b)]
+            new[e - 1] = last[p]
+            o += e - 1 - b
+        rows.append(new)
+    Zm = np.stack(rows)                                  # (L + h + K* - 1) x K
+    out = np.zeros((len(lens), h))
+    for p, (b, e) in enumerate(blocks):
+        blk = Zm[:, b:e]
+        nr, kp = blk.shape
+        acc = np.zeros(nr + kp - 1)
+        cnt = np.zeros(nr + kp - 1)
+        for k in range(kp):
+            acc[k:k + nr] += blk[:, k]
+            cnt[k:k + nr] += 1.0
+        out[p] = (acc / cnt)[lens[p]:lens[p] + h]
+    return out
+
+
 # --------------------------------------------------------------------------
 # whole decompositions
 # --------------------------------------------------------------------------

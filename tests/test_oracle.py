@@ -606,3 +606,110 @@ def test_vforecast_rejects_a_group_spanning_the_last_axis():
     U2 = np.eye(L)[:, [0, L - 1]]            # e_L in the span: nu^2 = 1
     with pytest.raises(ValueError):
         oracle.vforecast_column([L + 19], L, np.ones(2), U2, V, [0, 1], 3)
+
+
+# --------------------------------------------------------------------------
+# row forecasts (recurrent and vector)
+# --------------------------------------------------------------------------
+
+def _noisy_system(lens=(70, 85, 60), L=20, seed=23):
+    g = np.random.default_rng(seed)
+    ser = [1.5 * np.cos(2 * np.pi * np.arange(n) / 9 + p) + 0.01 * np.arange(n)
+           + 0.4 * g.standard_normal(n) for p, n in enumerate(lens)]
+    s, U, V = _lapack_svd(oracle.trajectory_mssa(ser, L))
+    return ser, list(lens), L, s, U, V
+
+
+def test_row_forecasts_of_one_series_are_column_forecasts_of_the_transpose():
+    """For one series the trajectory matrix with window K is the transpose
+    of the one with window L: the row forecasts with window L are the column
+    forecasts with window K (U and V swapped, same reconstruction)."""
+    g = np.random.default_rng(5)
+    N, L, h = 100, 30, 12
+    x = np.sin(np.arange(N) / 4.0) + 0.3 * g.standard_normal(N)
+    s, U, V = _lapack_svd(oracle.trajectory_mssa([x], L))
+    grp = [0, 1, 2]
+    rec = oracle.reconstruct_mssa([N], L, s, U, V, grp)
+    K = N - L + 1
+    a = oracle.rforecast_row(rec, L, V, grp, h)
+    b = oracle.rforecast_column(rec, V, grp, h)
+    assert np.max(np.abs(a - b)) <= 1e-10 * np.max(np.abs(b))
+    c = oracle.vforecast_row([N], L, s, U, V, grp, h)
+    d = oracle.vforecast_column([N], K, s, V, U, grp, h)
+    assert np.max(np.abs(c - d)) <= 1e-10 * np.max(np.abs(d))
+
+
+def test_row_forecasts_continue_a_finite_rank_system():
+    L, h = 24, 20
+    lens = [80, 95, 110]
+    amp, ph = [1.0, 0.5, 2.0], [0.0, 1.0, 2.5]
+    full = [a * np.cos(2 * np.pi * np.arange(n + h) / 10 + p) for a, p, n in zip(amp, ph, lens)]
+    ser = [f[:n] for f, n in zip(full, lens)]
+    s, U, V = _lapack_svd(oracle.trajectory_mssa(ser, L))
+    recs = oracle.reconstruct_mssa(lens, L, s, U, V, [0, 1])
+    fr = oracle.rforecast_row(recs, L, V, [0, 1], h)
+    fv = oracle.vforecast_row(lens, L, s, U, V, [0, 1], h)
+    for p, n in enumerate(lens):
+        assert np.max(np.abs(fr[p] - full[p][n:])) <= 1e-9
+        assert np.max(np.abs(fv[p] - full[p][n:])) <= 1e-9
+
+
+def test_recurrent_row_forecast_is_the_least_squares_completion():
+    """The next value of every series completes the next row of the
+    trajectory matrix (known: each series' last K_p - 1 values; unknown: one
+    value per series) to the vector closest to the group's row space."""
+    ser, lens, L, s, U, V = _noisy_system()
+    grp = [0, 1, 2, 3]
+    recs = oracle.reconstruct_mssa(lens, L, s, U, V, grp)
+    got = oracle.rforecast_row(recs, L, V, grp, 1)[:, 0]
+    Vg = V[:, grp]
+    Pc = np.eye(Vg.shape[0]) - Vg @ Vg.T
+    ks = [n - L + 1 for n in lens]
+    ends = np.cumsum(ks)
+    unknown = ends - 1
+    known = np.setdiff1d(np.arange(Vg.shape[0]), unknown)
+    z = np.concatenate([r[len(r) - (k - 1):] for r, k in zip(recs, ks)])
+    ref = np.linalg.lstsq(Pc[:, unknown], -Pc[:, known] @ z, rcond=None)[0]
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_vector_row_forecast_matches_the_shift_matrix_route():
+    """Algorithm of the fast row forecast: W_i = D W_{i-1} with D the
+    pseudo-inverse of V's blocks without their last coordinate times V's
+    blocks without their first; forecast = block-wise anti-diagonal mean."""
+    ser, lens, L, s, U, V = _noisy_system()
+    grp, h = [0, 1, 2, 3], 9
+    Vg = V[:, grp]
+    ks = [n - L + 1 for n in lens]
+    ends = np.cumsum(ks)
+    starts = ends - ks
+    lo = np.concatenate([Vg[b:e - 1] for b, e in zip(starts, ends)])
+    hi = np.concatenate([Vg[b + 1:e] for b, e in zip(starts, ends)])
+    D = np.linalg.lstsq(lo, hi, rcond=None)[0]
+    w = s[grp] * U[L - 1, grp]
+    Ws = []
+    for _ in range(h + max(ks) - 1):
+        w = D @ w
+        Ws.append(w)
+    Ws = np.array(Ws)                       # row e: trajectory row L + e (0-based)
+    ref = oracle.vforecast_row(lens, L, s, U, V, grp, h)
+    for p, (b, kp) in enumerate(zip(starts, ks)):
+        fast = [np.mean([Vg[b + k] @ Ws[kp - 1 + m - k] for k in range(kp)]) for m in range(h)]
+        assert np.max(np.abs(np.array(fast) - ref[p])) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_vector_row_forecast_does_not_redraw():
+    ser, lens, L, s, U, V = _noisy_system()
+    a = oracle.vforecast_row(lens, L, s, U, V, [0, 1, 2], 6)
+    b = oracle.vforecast_row(lens, L, s, U, V, [0, 1, 2], 11)
+    assert np.max(np.abs(a - b[:, :6])) <= 1e-12 * np.max(np.abs(b))
+
+
+def test_row_forecast_rejects_a_singular_system():
+    L = 4
+    lens = [L + 2, L + 2]                  # K_1 = K_2 = 3, K = 6
+    V = np.zeros((6, 2))
+    V[2, 0] = 1.0                          # V_1 = e_3: the last coordinate of block 1
+    V[0, 1] = 1.0
+    with pytest.raises(ValueError):
+        oracle.lrr_row(lens, L, V, [0, 1])
