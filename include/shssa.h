@@ -209,6 +209,27 @@ int ssa_rforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int
  * set.  Synchronous. */
 int ssa_vforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries);
 
+/* Row forecasts (the MSSA forecasting subsection: recurrent row forecast,
+ * equation Forec:ContMSSAK, and vector row forecast, computed by the fast
+ * row algorithm of the forecast implementation section) for the same
+ * decompositions as ssa_rforecast, whose series have no gaps.  The row
+ * space of the group is spanned by its V_j, split in blocks of K_p
+ * coordinates by series; S (s x ng) holds each block's last coordinate.
+ * Recurrent: the next value of every series is
+ * R_K Z = (I_s - S S^T)^{-1} S Vlow^T Z, Z the stacked last K_p - 1 values
+ * of each series' reconstruction (Vlow: the blocks without their last
+ * coordinate), then by recurrence; the forecast of one series uses the
+ * values of all of them.  Vector: the rows of the group's reconstructed
+ * matrix are continued inside the row space by the map of that subsection
+ * and each series' columns are diagonally averaged; only coefficient
+ * vectors w_i = D w_{i-1} are carried, D = (I - S^T S)^{-1} times the
+ * blocks without their last coordinate against the blocks without their
+ * first.  (I - S S^T) must be invertible (SSA_EINVAL otherwise).  grp: ng
+ * (<= 64) 0-based component ids; out: nseries x h as for ssa_rforecast;
+ * with out = NULL only *nseries is set.  Synchronous. */
+int ssa_rforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries);
+int ssa_vforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries);
+
 int  ssa_get_stats(const ssa_decomp* d, ssa_stats* st);
 void ssa_free(ssa_decomp* d);
 

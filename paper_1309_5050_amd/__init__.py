@@ -101,24 +101,28 @@ class Decomposition:
         check(lib().ssa_reconstruct(self._h, _ptr(gp), _ptr(gi), len(groups), _ptr(out)), "ssa_reconstruct")
         return out
 
-    def rforecast(self, group, h: int) -> np.ndarray:
-        """Column recurrent forecast of h values from the group's
-        reconstruction: (series, h)."""
+    def _forecast(self, fn, group, h):
         g = np.ascontiguousarray(group, dtype=np.int32)
         ns = C.c_int()
-        check(lib().ssa_rforecast(self._h, _ptr(g), len(g), int(h), None, C.byref(ns)), "ssa_rforecast")
+        f = getattr(lib(), fn)
+        check(f(self._h, _ptr(g), len(g), int(h), None, C.byref(ns)), fn)
         out = np.zeros((ns.value, int(h)))
-        check(lib().ssa_rforecast(self._h, _ptr(g), len(g), int(h), _ptr(out), C.byref(ns)), "ssa_rforecast")
+        check(f(self._h, _ptr(g), len(g), int(h), _ptr(out), C.byref(ns)), fn)
         return out
 
-    def vforecast(self, group, h: int) -> np.ndarray:
-        """Column vector forecast of h values after each series: (series, h)."""
-        g = np.ascontiguousarray(group, dtype=np.int32)
-        ns = C.c_int()
-        check(lib().ssa_vforecast(self._h, _ptr(g), len(g), int(h), None, C.byref(ns)), "ssa_vforecast")
-        out = np.zeros((ns.value, int(h)))
-        check(lib().ssa_vforecast(self._h, _ptr(g), len(g), int(h), _ptr(out), C.byref(ns)), "ssa_vforecast")
-        return out
+    def rforecast(self, group, h: int, direction: str = "column") -> np.ndarray:
+        """Recurrent forecast of h values after each series from the group:
+        (series, h).  direction "column" (one LRR from the U_j) or "row"
+        (from the V_j; each series' next value uses all series)."""
+        fn = {"column": "ssa_rforecast", "row": "ssa_rforecast_row"}[direction]
+        return self._forecast(fn, group, h)
+
+    def vforecast(self, group, h: int, direction: str = "column") -> np.ndarray:
+        """Vector forecast of h values after each series: (series, h);
+        direction "column" (lagged vectors in the span of the U_j) or "row"
+        (trajectory rows in the span of the V_j)."""
+        fn = {"column": "ssa_vforecast", "row": "ssa_vforecast_row"}[direction]
+        return self._forecast(fn, group, h)
 
     def wcor(self, groups):
         """w-correlation matrix (ngroups, ngroups) and contributions

@@ -2535,7 +2535,7 @@ int ssa_wcor(ssa_decomp* d, const int* gp, const int* gi, int ng, double* rho, d
     if (!d || !rho) return fail(SSA_EINVAL, "NULL argument");
     if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
     int rc = check_groups(d, gp, gi, ng);
-    if (rc) return rc;
+    if (rc || (rc = wait_handle(d))) return rc;
     g_tables_ctx = d->ctx;
     TableScope tables(d->ctx, d->ctx->st);
     Batch b(d->ctx);
@@ -2607,6 +2607,8 @@ int ssa_rforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int
     if (!grp || ng < 1 || h < 1) return fail(SSA_EINVAL, "bad group or horizon");
     for (int k = 0; k < ng; ++k)
         if (grp[k] < 0 || grp[k] >= d->r) return fail(SSA_EINVAL, "component id out of range");
+    int rc;
+    if ((rc = wait_handle(d))) return rc;
     g_tables_ctx = d->ctx;
     TableScope tables(d->ctx, d->ctx->st);
     Batch b(d->ctx);
@@ -2617,7 +2619,6 @@ int ssa_rforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int
     b.set_col(d->ctx->tile_for(d->f64, d->MA));
     const long n = (long)d->A * d->B;
     const long L1 = d->L - 1;
-    int rc;
     std::vector<int> g(grp, grp + ng);
     DevVec rec, R, flag, buf, outd, dg;
     if ((rc = rec.reserve((size_t)n * sizeof(double))) ||
@@ -2679,6 +2680,86 @@ int ssa_vforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int
     if (bad[1]) return fail(SSA_EINVAL, "no vector forecast: the group's last coordinates have nu^2 >= 1");
     if (bad[0]) return fail(SSA_EINVAL, "no vector forecast: a series' last lagged vector misses its last value");
     return SSA_OK;
+}
+
+namespace {
+
+int check_forecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries, const char* what) {
+    if (!d) return fail(SSA_EINVAL, "handle is NULL");
+    if (!d->rowfam) return fail(SSA_EINVAL, (std::string(what) + " needs a window one row or column wide").c_str());
+    if (d->L != (long)d->LB) return fail(SSA_EINVAL, (std::string(what) + " needs a window without mask").c_str());
+    if (nseries) *nseries = d->A;
+    if (!out) return SSA_OK;
+    if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
+    if (!grp || ng < 1 || h < 1) return fail(SSA_EINVAL, "bad group or horizon");
+    if (ng > kVfMaxGroup) return fail(SSA_EINVAL, "forecast group larger than 64 components");
+    for (int k = 0; k < ng; ++k)
+        if (grp[k] < 0 || grp[k] >= d->r) return fail(SSA_EINVAL, "component id out of range");
+    return SSA_OK;
+}
+
+// The row forecasts: shift matrix and (I - S^T S)^{-1} of the group's V
+// blocks, then the vector (vec = true) or recurrent forecast.
+int row_forecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, bool vec) {
+    int rc;
+    if ((rc = wait_handle(d))) return rc;
+    g_tables_ctx = d->ctx;
+    TableScope tables(d->ctx, d->ctx->st);
+    Batch b(d->ctx);
+    b.ds = {d};
+    b.f64 = d->f64;
+    b.rowfam = d->rowfam;
+    b.cls = row_word(d->nh, d->f64);
+    b.set_col(d->ctx->tile_for(d->f64, d->MA));
+    hipStream_t st = b.st;
+    std::vector<int> g(grp, grp + ng);
+    const size_t nn = (size_t)ng * ng * sizeof(double);
+    DevVec dg, flag, Mr, StS, T, D, G, outd;
+    if ((rc = dg.put(g, st)) || (rc = flag.put(std::vector<int>{0, 0}, st)) || (rc = Mr.reserve(nn)) ||
+        (rc = StS.reserve(nn)) || (rc = T.reserve(3 * nn)) || (rc = D.reserve(nn)) || (rc = G.reserve(nn)) ||
+        (rc = outd.reserve((size_t)d->A * h * sizeof(double))))
+        return rc;
+    launch_rowf_prep(st, d->kmask, d->KB, d->krow, d->A, d->V, d->K, dg.as<int>(), ng, Mr.as<double>(),
+                     StS.as<double>(), T.as<double>(), D.as<double>(), G.as<double>(), flag.as<int>());
+    HIPCHK(hipGetLastError());
+    DevVec wbuf, rec, yk;
+    if (vec) {
+        const long E = (long)h + d->KB - 1;   // KB = the longest series' K_p
+        if ((rc = wbuf.reserve((size_t)E * ng * sizeof(double)))) return rc;
+        ProfSpan p(d->ctx, "vforecast_row", st, [&] { return 8.0 * (2.0 * E * ng + (double)ng * d->K); });
+        launch_vrow(st, d->U, d->L, d->sigma, dg.as<int>(), ng, D.as<double>(), E, wbuf.as<double>(), d->V, d->K,
+                    d->krow, d->A, h, outd.as<double>());
+    } else {
+        if ((rc = rec.reserve((size_t)d->A * d->B * sizeof(double))) ||
+            (rc = run_reconstruct(b, std::vector<int>{0, ng}, g, {rec.as<double>()})) ||
+            (rc = yk.reserve((size_t)h * ng * sizeof(double))))
+            return rc;
+        ProfSpan p(d->ctx, "rforecast_row", st, [&] { return 8.0 * ((double)ng * d->K + (double)d->A * d->B); });
+        launch_rrow(st, d->V, d->K, d->krow, d->A, dg.as<int>(), ng, G.as<double>(), rec.as<double>(), d->B, d->L,
+                    h, yk.as<double>(), outd.as<double>());
+    }
+    HIPCHK(hipGetLastError());
+    int bad[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(bad, flag.p, sizeof(bad), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(out, outd.p, (size_t)d->A * h * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (bad[0]) return fail(SSA_EINVAL, "row forecast needs series without gaps");
+    if (bad[1]) return fail(SSA_EINVAL, "no row forecast: I - S S^T is singular for the group");
+    return SSA_OK;
+}
+
+}  // namespace
+
+int ssa_rforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries) {
+    int rc = check_forecast(d, grp, ng, h, out, nseries, "row forecast");
+    if (rc || !out) return rc;
+    return row_forecast(d, grp, ng, h, out, false);
+}
+
+int ssa_vforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries) {
+    int rc = check_forecast(d, grp, ng, h, out, nseries, "row forecast");
+    if (rc || !out) return rc;
+    return row_forecast(d, grp, ng, h, out, true);
 }
 
 int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* gp, const int* gi, int ng,

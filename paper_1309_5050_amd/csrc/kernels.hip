@@ -2177,6 +2177,212 @@ k_vforecast(const double* __restrict__ U, long L, const double* __restrict__ V, 
     }
 }
 
+// ---- row forecasts (MSSA): V's blocks are the series' origin rows ------
+
+// Row forecasts need every series' origin set to be a prefix [0, K_p) of
+// its row (no gaps; then its covered cells are [0, K_p + L - 1)).
+// flag[0] = 1 otherwise.  One workgroup per row.
+__global__ void __launch_bounds__(256)
+k_rowf_check(const uint8_t* __restrict__ kmask, int KB, const int* __restrict__ krow, int* __restrict__ flag) {
+    __shared__ int ext[4];
+    const int a = blockIdx.x, tid = threadIdx.x;
+    int klast = -1;
+    for (int b = tid; b < KB; b += 256)
+        if (kmask[(long)a * KB + b]) klast = b;
+    for (int o = 32; o > 0; o >>= 1) klast = max(klast, __shfl_xor(klast, o));
+    if (lane_id() == 0) ext[tid >> 6] = klast;
+    __syncthreads();
+    const int kl = max(max(ext[0], ext[1]), max(ext[2], ext[3]));
+    const int kp = krow[a + 1] - krow[a];
+    if (tid == 0 && kl != kp - 1) flag[0] = 1;
+}
+
+// Gram terms of the group's row-space basis Q (the V_j, blocks by series):
+// e < ng^2:  Mr[i][j] = sum over blocks of sum_{k < K_p - 1} Q_i[k] Q_j[k+1]
+//            (blocks without their last coordinate against blocks without
+//            their first), as the sum over all adjacent pairs minus the
+//            pairs that cross from one block into the next;
+// e >= ng^2: StS[i][j] = sum_p Q_i[end_p] Q_j[end_p] over the blocks' last
+//            coordinates.  One wave per entry.
+__global__ void __launch_bounds__(256)
+k_rowf_gram(const double* __restrict__ V, long K, const int* __restrict__ krow, int A, const int* __restrict__ grp,
+            int ng, double* __restrict__ Mr, double* __restrict__ StS) {
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = lane_id();
+    if (e >= 2 * ng * ng) return;   // whole waves
+    const int q = e < ng * ng ? e : e - ng * ng;
+    const double* vi = V + (long)grp[q / ng] * K;
+    const double* vj = V + (long)grp[q % ng] * K;
+    double s = 0.0;
+    if (e < ng * ng) {
+        for (long c = lane; c < K - 1; c += 64) s += vi[c] * vj[c + 1];
+        for (int p = lane; p < A; p += 64) {
+            const int b = krow[p], en = krow[p + 1];
+            if (en > b && en < K) s -= vi[en - 1] * vj[en];
+        }
+        s = wave_sum(s);
+        if (lane == 0) Mr[q] = s;
+    } else {
+        for (int p = lane; p < A; p += 64) {
+            const int b = krow[p], en = krow[p + 1];
+            if (en > b) s += vi[en - 1] * vj[en - 1];
+        }
+        s = wave_sum(s);
+        if (lane == 0) StS[q] = s;
+    }
+}
+
+// Solves (I - StS) [D | G] = [Mr | I] by Gauss-Jordan elimination without
+// pivoting (I - StS is symmetric positive definite when the forecast
+// exists; a pivot below 1e-12 sets flag[1]).  T: ng x 3ng work array.
+// D = (I - S^T S)^{-1} Mr is the row shift matrix (pseudo-inverse of the
+// blocks without their last coordinate times the blocks without their
+// first, for an orthonormal basis); G = (I - S^T S)^{-1}.  One workgroup.
+__global__ void __launch_bounds__(256)
+k_rowf_solve(const double* __restrict__ StS, const double* __restrict__ Mr, int ng, double* __restrict__ T,
+             double* __restrict__ D, double* __restrict__ G, int* __restrict__ flag) {
+    __shared__ double fac[kVfMaxGroup];
+    __shared__ int bad;
+    const int tid = threadIdx.x, nc = 3 * ng;
+    if (tid == 0) bad = 0;
+    for (int e = tid; e < ng * nc; e += 256) {
+        const int i = e / nc, c = e % nc;
+        double v;
+        if (c < ng) v = (i == c ? 1.0 : 0.0) - StS[i * ng + c];
+        else if (c < 2 * ng) v = Mr[i * ng + (c - ng)];
+        else v = (i == c - 2 * ng) ? 1.0 : 0.0;
+        T[e] = v;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < ng; ++kk) {
+        const double piv = T[kk * nc + kk];
+        if (!(piv > 1e-12)) {
+            if (tid == 0) bad = 1;
+            break;   // uniform: every thread read the same pivot
+        }
+        if (tid < ng) fac[tid] = T[tid * nc + kk];
+        __syncthreads();
+        for (int c = tid; c < nc; c += 256) T[kk * nc + c] /= piv;
+        __syncthreads();
+        for (int e = tid; e < ng * nc; e += 256) {
+            const int i = e / nc, c = e % nc;
+            if (i != kk) T[e] -= fac[i] * T[kk * nc + c];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (bad) {
+        if (tid == 0) flag[1] = 1;
+        return;
+    }
+    for (int e = tid; e < ng * ng; e += 256) {
+        const int i = e / ng, j = e % ng;
+        D[e] = T[i * nc + ng + j];
+        G[e] = T[i * nc + 2 * ng + j];
+    }
+}
+
+// Vector row forecast, the recursion shared by all series: the coefficient
+// vectors of the trajectory rows in the group's basis, w_L = D w_{L-1},
+// ... from w_{L-1} = sigma_j U_j[L-1] (the last row of the reconstructed
+// matrix); wbuf[e * ng + j] holds w_{L+e}, e < E.  One wave.
+__global__ void __launch_bounds__(64)
+k_vrow_recur(const double* __restrict__ U, long L, const double* __restrict__ sigma, const int* __restrict__ grp,
+             int ng, const double* __restrict__ D, long E, double* __restrict__ wbuf) {
+    constexpr int LD = kVfMaxGroup + 1;
+    __shared__ double Ds[kVfMaxGroup * LD];
+    const int lane = threadIdx.x;
+    for (int e = lane; e < ng * ng; e += 64) Ds[(e / ng) * LD + e % ng] = D[e];
+    __syncthreads();
+    double w = lane < ng ? sigma[grp[lane]] * U[(long)grp[lane] * L + (L - 1)] : 0.0;
+    const double* drow = Ds + (lane < ng ? lane : 0) * LD;
+    for (long e = 0; e < E; ++e) {
+        double s = 0.0;
+        for (int j = 0; j < ng; ++j) s += drow[j] * lane_bcast(w, j);
+        w = s;
+        if (lane < ng) wbuf[e * ng + lane] = w;
+    }
+}
+
+// Vector row forecast of series a: position N_p + m is the mean over the
+// block's K_p columns k of (Q^(p) w_{L+K_p-1+m-k})_k, all rows past the
+// reconstructed ones.  One workgroup per series, one wave per value.
+__global__ void __launch_bounds__(256)
+k_vrow_out(const double* __restrict__ V, long K, const int* __restrict__ krow, const int* __restrict__ grp, int ng,
+           const double* __restrict__ wbuf, int h, double* __restrict__ out) {
+    const int a = blockIdx.x, wv = threadIdx.x >> 6, lane = lane_id();
+    const int b0 = krow[a], kp = krow[a + 1] - b0;
+    for (int m = wv; m < h; m += 4) {
+        double s = 0.0;
+        for (int k = lane; k < kp; k += 64) {
+            const double* we = wbuf + (long)(kp - 1 + m - k) * ng;
+            for (int j = 0; j < ng; ++j) s += V[(long)grp[j] * K + b0 + k] * we[j];
+        }
+        s = wave_sum(s);
+        if (lane == 0) out[(long)a * h + m] = kp > 0 ? s / kp : __builtin_nan("");
+    }
+}
+
+// Recurrent row forecast, the part from reconstructed values: for step m
+// (next values N_p + m) and component j, the sum over series of
+// Q_j^(p)[k] x^(p)[L + m + k] over the k < K_p - 1 - m whose value lies in
+// the reconstruction rec (A x B).  One wave per (m, j).
+__global__ void __launch_bounds__(256)
+k_rrow_known(const double* __restrict__ V, long K, const int* __restrict__ krow, int A, const int* __restrict__ grp,
+             int ng, const double* __restrict__ rec, int B, long L, int h, double* __restrict__ yk) {
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = lane_id();
+    if (e >= h * ng) return;   // whole waves
+    const int m = e / ng, j = e % ng;
+    const double* vj = V + (long)grp[j] * K;
+    double s = 0.0;
+    for (int p = 0; p < A; ++p) {
+        const int b0 = krow[p], kn = krow[p + 1] - b0 - 1 - m;
+        for (int k = lane; k < kn; k += 64) s += vj[b0 + k] * rec[(long)p * B + L + m + k];
+    }
+    s = wave_sum(s);
+    if (lane == 0) yk[e] = s;
+}
+
+// Recurrent row forecast by recurrence: step m adds to yk[m] the terms whose
+// values are earlier forecasts, y = Vlow^T Z; then the next value of every
+// series is (S G y)_p with S the blocks' last coordinates.  out (A x h)
+// doubles as the store of the forecasts.  One workgroup.
+__global__ void __launch_bounds__(256)
+k_rrow_recur(const double* __restrict__ V, long K, const int* __restrict__ krow, int A, const int* __restrict__ grp,
+             int ng, const double* __restrict__ G, const double* __restrict__ yk, int h, double* __restrict__ out) {
+    __shared__ double ys[kVfMaxGroup], gs[kVfMaxGroup];
+    const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
+    for (int m = 0; m < h; ++m) {
+        for (int j = wv; j < ng; j += 4) {
+            const double* vj = V + (long)grp[j] * K;
+            double s = 0.0;
+            for (int p = lane; p < A; p += 64) {
+                const int b0 = krow[p], kp = krow[p + 1] - b0;
+                // forecasts i = 0 .. m-1 sit at block positions k = K_p - 1 - m + i >= 0
+                for (int i = max(0, m - kp + 1); i < m; ++i)
+                    s += vj[b0 + kp - 1 - m + i] * out[(long)p * h + i];
+            }
+            s = wave_sum(s);
+            if (lane == 0) ys[j] = yk[(long)m * ng + j] + s;
+        }
+        __syncthreads();
+        if (tid < ng) {
+            double g = 0.0;
+            for (int l = 0; l < ng; ++l) g += G[tid * ng + l] * ys[l];
+            gs[tid] = g;
+        }
+        __syncthreads();
+        for (int p = tid; p < A; p += 256) {
+            const int kp = krow[p + 1] - krow[p];
+            double r = 0.0;
+            for (int j = 0; j < ng; ++j) r += V[(long)grp[j] * K + krow[p + 1] - 1] * gs[j];
+            out[(long)p * h + m] = kp > 0 ? r : __builtin_nan("");
+        }
+        __syncthreads();
+    }
+}
+
 // Advance the batch's step counter (end of a replayed step).
 __global__ void k_step_next(int* step) {
     if (threadIdx.x == 0) step[0] += 1;

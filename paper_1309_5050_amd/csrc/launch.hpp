@@ -72,6 +72,21 @@ void launch_rforecast(hipStream_t st, const double* U, long L, const int* grp, i
 void launch_vforecast(hipStream_t st, const double* U, long L, const double* V, long K, const double* sigma,
                       const int* grp, int ng, double* M, const int* krow, const uint8_t* kmask, int KB,
                       const double* W, int A, int B, int h, double* wbuf, double* out, int* flag);
+// Row forecasts (the group's V blocks by series, A series): structure
+// check (flag[0]: an origin row that is not a prefix), Gram terms Mr and
+// StS (ng x ng), and D = (I - StS)^{-1} Mr, G = (I - StS)^{-1} (flag[1]:
+// singular); T holds 3 ng^2 values.  flag zeroed by the caller.
+void launch_rowf_prep(hipStream_t st, const uint8_t* kmask, int KB, const int* krow, int A, const double* V, long K,
+                      const int* grp, int ng, double* Mr, double* StS, double* T, double* D, double* G, int* flag);
+// Vector row forecast: E coefficient vectors (wbuf, E x ng, E = h + KB - 1)
+// then h values per series into out (A x h).
+void launch_vrow(hipStream_t st, const double* U, long L, const double* sigma, const int* grp, int ng,
+                 const double* D, long E, double* wbuf, const double* V, long K, const int* krow, int A, int h,
+                 double* out);
+// Recurrent row forecast from the group's reconstruction rec (A x B): yk
+// (h x ng) then h values per series into out (A x h).
+void launch_rrow(hipStream_t st, const double* V, long K, const int* krow, int A, const int* grp, int ng,
+                 const double* G, const double* rec, int B, long L, int h, double* yk, double* out);
 void launch_wgram(hipStream_t st, const double* const* arr, int narr, const double* W, long ncell, int nchunk,
                   double* part, double* out);
 void launch_transpose(int nmat, int R, int C, hipStream_t st, const double* in, double* out);

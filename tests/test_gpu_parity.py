@@ -543,3 +543,62 @@ def test_vforecast_starts_after_the_last_covered_value(ctx):
     a = ctx.decompose(y[:197], 50, 4).vforecast([0, 1], 6)
     b = ctx.decompose(y2, 50, 4).vforecast([0, 1], 6)
     assert np.max(np.abs(a - b)) <= 1e-8 * np.max(np.abs(a))
+
+
+def _row_forecast_oracle(name, w, group, h, kind):
+    sh, so, Uo, Vo = oracle_case(name, w)
+    L = w["window"]
+    lens = [len(x) for x in w["x"]] if w["kind"] == "mssa" else [len(w["x"])]
+    if kind == "vector":
+        return oracle.vforecast_row(lens, L, so, Uo, Vo, group, h), so
+    recs = oracle.reconstruct_mssa(lens, L, so, Uo, Vo, group)
+    return oracle.rforecast_row(recs, L, Vo, group, h), so
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", ["recurrent", "vector"])
+@pytest.mark.parametrize("name,group", [("series_1000", [0, 1, 2, 3, 4, 5]), ("mssa_8", [0, 1, 2, 3])])
+def test_row_forecast_parity(ctx, name, group, kind, prec):
+    """Row forecasts (24 values) from the GPU decomposition against the
+    oracle's definitions on its own triplets, with the bound of the column
+    forecasts (the group's row space is as close to the oracle's as its
+    column space)."""
+    w = CASES[name]()
+    tol = TOL[prec]
+    h = 24
+    ref, so = _row_forecast_oracle(name, w, group, h, kind)
+    d = gpu_case(ctx, w, prec)
+    got = (d.vforecast if kind == "vector" else d.rforecast)(group, h, direction="row")
+    assert got.shape == ref.shape
+    gap = so[group[-1]] - so[group[-1] + 1]
+    bound = 20 * tol * so[0] / gap * np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref))
+    print(f"{name} {kind} {prec}: row forecast error {err:.3e} bound {bound:.3e}")
+    assert err <= bound, (name, kind, prec, err, bound)
+
+
+def test_row_forecasts_continue_a_cosine_system(ctx):
+    L, h = 40, 30
+    lens = [150, 190, 230]
+    amp, ph = [1.0, 0.5, 2.0], [0.0, 1.0, 2.5]
+    full = [a * np.cos(2 * np.pi * np.arange(n + h) / 13 + p) for a, p, n in zip(amp, ph, lens)]
+    d = ctx.decompose_multi([f[:n] for f, n in zip(full, lens)], L, 2)
+    for f in (d.rforecast([0, 1], h, direction="row"), d.vforecast([0, 1], h, direction="row")):
+        for p, n in enumerate(lens):
+            assert np.max(np.abs(f[p] - full[p][n:])) <= 1e-8
+
+
+def test_row_forecast_errors(ctx):
+    import paper_1309_5050_amd as S
+    x = np.random.default_rng(3).standard_normal((30, 30))
+    d = ctx.decompose(x, (5, 5), 3)
+    with pytest.raises(S.SsaError):
+        d.rforecast([0], 5, direction="row")
+    y = np.cos(np.arange(300) / 5.0) + 0.1 * np.random.default_rng(4).standard_normal(300)
+    y[150] = np.nan                    # a gap: the trajectory rows are no longer Hankel blocks
+    e = ctx.decompose(y, 40, 3)
+    with pytest.raises(S.SsaError):
+        e.vforecast([0, 1], 5, direction="row")
+    with pytest.raises(S.SsaError):
+        e.rforecast([0, 1], 5, direction="row")
+    e.vforecast([0, 1], 5)             # the column forecasts need no Hankel rows
