@@ -162,9 +162,14 @@ def main():
     tf1 = time.perf_counter()
     fv = dm.vforecast([0, 1, 2, 3], 100)
     tf2 = time.perf_counter()
+    fr = dm.rforecast([0, 1, 2, 3], 100, direction="row")
+    tf3 = time.perf_counter()
+    fw = dm.vforecast([0, 1, 2, 3], 100, direction="row")
+    tf4 = time.perf_counter()
     rforecast = {"workload": "MSSA 50 series N~U(1000,3000), L=500, r=20, fp32; group {1..4}, 100 steps",
                  "series": int(fc.shape[0]), "steps": int(fc.shape[1]), "ms": 1e3 * (tf1 - tf0),
-                 "vector_ms": 1e3 * (tf2 - tf1), "vector_series": int(fv.shape[0])}
+                 "vector_ms": 1e3 * (tf2 - tf1), "row_ms": 1e3 * (tf3 - tf2), "vector_row_ms": 1e3 * (tf4 - tf3),
+                 "finite": bool(np.isfinite(fv).all() and np.isfinite(fr).all() and np.isfinite(fw).all())}
     dm.free()
 
     # plain single-instance FP64 path (same kernels, batch of one)
