@@ -595,24 +595,23 @@ __device__ __forceinline__ T& pair_part(cplx<T>& z, int h) { return h ? z.y : z.
 template <typename T, int LOGN>
 struct RowTw {
     static constexpr int N = RowReg<LOGN>::N, G = RowReg<LOGN>::G;
-    static constexpr int LDS = 2 * N;   // LDS values
+    static constexpr int TW = TwTable<T, LOGN>::SIZE;   // complex transform's table
+    static constexpr int LDS = TW + N;                   // LDS values
     cplx<T>* tab;
     int t;
     __device__ __forceinline__ RowTw(cplx<T>* table, int tt) : tab(table), t(tt) {}
     __device__ __forceinline__ void stage(const FftPlan& prow) {
         const gptr<const cplx<T>> tw = as_global(static_cast<const cplx<T>*>(prow.tw));
         const gptr<const cplx<T>> twr = as_global(static_cast<const cplx<T>*>(prow.twr));
-        for (int i = threadIdx.x; i < N; i += blockDim.x) {
-            tab[i] = gload(tw + i);
-            tab[N + i] = gload(twr + i);
-        }
+        TwTable<T, LOGN>::stage(tab, tw, threadIdx.x, blockDim.x);
+        for (int i = threadIdx.x; i < N; i += blockDim.x) tab[TW + i] = gload(twr + i);
         __syncthreads();
     }
     __device__ __forceinline__ auto W() const {
         return [this](int q) -> cplx<T> { return TwTable<T, LOGN>{tab, t}(q); };
     }
     __device__ __forceinline__ auto WR() const {
-        return [this](int e) -> cplx<T> { return tab[N + t + G * e]; };
+        return [this](int e) -> cplx<T> { return tab[TW + t + G * e]; };
     }
 };
 
@@ -1093,7 +1092,7 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
     constexpr int G = RP::G;
     constexpr int XB = RP::LROWS * TC;
     constexpr int XSM = LTW ? XS_WG : XS_WG2;
-    __shared__ cplx<T> lds[(LTW ? 1 : 2) * XB + (LTW ? RP::N : 0)];
+    __shared__ cplx<T> lds[(LTW ? 1 : 2) * XB + (LTW ? TwTable<T, LOGN>::SIZE : 0)];
     const Item item = items[xcd_block(blockIdx.x, gridDim.x)];
     int xe = 0;
     const OpDesc& op = ops[item.inst];
@@ -1107,8 +1106,7 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
     cplx<T>* tab = lds + XB;
     if constexpr (LTW) {
         // read first after an exchange barrier (the first pass has no twiddles)
-        const gptr<const cplx<T>> tw = as_global(static_cast<const cplx<T>*>(op.pcol.tw));
-        for (int i = threadIdx.x; i < RP::N; i += G * TC) tab[i] = gload(tw + i);
+        TwTable<T, LOGN>::stage(tab, as_global(static_cast<const cplx<T>*>(op.pcol.tw)), threadIdx.x, G * TC);
     } else {
         reg_twiddles<T, LOGN>(static_cast<const cplx<T>*>(op.pcol.tw), t, w);
     }

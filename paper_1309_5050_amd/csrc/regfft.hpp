@@ -72,23 +72,48 @@ __device__ __forceinline__ void reg_twiddles(const cplx<T>* __restrict__ twp, in
     }
 }
 
-// The same twiddles looked up in a table of all N values w^k staged in LDS
-// (shared by the workgroup): twiddle q of thread t, numbered as in
-// reg_twiddles.  Costs an LDS read per use instead of NTW registers.
+// The same twiddles looked up in a table staged in LDS (shared by the
+// workgroup), laid out pass by pass so that the lanes of a transform read
+// consecutive entries: radix-8 pass p (Ns = 8^p) holds w^(r k N/(8 Ns)) at
+// r Ns - 8 + k (r = 1..7, k < Ns); the final radix-R pass holds w^(r j),
+// j = t + b G, at 8^P8 - 8 + (b (R-1) + r - 1) G + t.  A table indexed by
+// the exponent would put the 8 distinct twiddles of a pass Ns = 8 on
+// addresses 8 r words apart (several lanes per bank).  Costs an LDS read per
+// use instead of NTW registers.
 template <typename T, int LOGN>
 struct TwTable {
+    using RP = RegPlan<LOGN>;
+    static constexpr int OFF_R = (1 << (3 * RP::P8)) - 8;   // start of the final pass's entries
+    static constexpr int SIZE = OFF_R + (RP::REM ? (8 / RP::R) * (RP::R - 1) * RP::G : 0);
     const cplx<T>* tab;
     int t;
     __device__ __forceinline__ cplx<T> operator()(int q) const {
-        using RP = RegPlan<LOGN>;
         if (q < 7 * (RP::P8 - 1)) {
             const int p = q / 7 + 1, r = q % 7 + 1;
             const int Ns = 1 << (3 * p);
-            return tab[r * ((t & (Ns - 1)) * (RP::N / (8 * Ns)))];
+            return tab[r * Ns - 8 + (t & (Ns - 1))];
         }
         const int q2 = q - 7 * (RP::P8 - 1);
+        return tab[OFF_R + q2 * RP::G + t];
+    }
+    // Exponent of entry i (the table holds w^src(i), w = exp(-2 pi i / N)).
+    __device__ __forceinline__ static int src(int i) {
+        if (i < OFF_R) {
+            int Ns = 8;
+            while (i >= 8 * Ns - 8) Ns *= 8;
+            const int j = i - (Ns - 8);
+            const int r = j / Ns + 1, k = j % Ns;
+            return r * k * (RP::N / (8 * Ns));
+        }
+        const int j = i - OFF_R;
+        const int q2 = j / RP::G, tt = j % RP::G;
         const int b = q2 / (RP::R - 1), r = q2 % (RP::R - 1) + 1;
-        return tab[r * (t + b * RP::G)];
+        return r * (tt + b * RP::G);
+    }
+    // Fills the table from the N values w^k (global memory); threads
+    // tid, tid + nthr, ... of the workgroup.
+    __device__ __forceinline__ static void stage(cplx<T>* dst, gptr<const cplx<T>> tw, int tid, int nthr) {
+        for (int i = tid; i < SIZE; i += nthr) dst[i] = gload(tw + src(i));
     }
 };
 
