@@ -160,6 +160,19 @@ int ssa_get_weights(const ssa_decomp* d, double* w);
  * ids < r).  out: ngroups arrays of nx*ny, NaN outside N'. */
 int ssa_reconstruct(ssa_decomp* d, const int* grp_ptr, const int* grp_idx, int ngroups, double* out);
 
+/* Continuation of a decomposition to r_new > r triplets (the paper's
+ * automatic continuation: a reconstruction that asks for more components
+ * than were computed continues the decomposition).  The handle's spectrum
+ * and bidiagonalisation state stay resident after ssa_decompose*: the
+ * bidiagonalisation is thick-restarted from its last Ritz vectors with the
+ * basis and convergence test of r_new, and all r_new triplets (and the
+ * other side's vectors) are recomputed; the first r change only within the
+ * tolerance.  r_new <= r: no-op.  r_new >= min(L, K): SSA_ERANK.  The
+ * per-component buffers are reallocated (SSA_ENOMEM beyond the context's
+ * budget; the handle is then unusable).  Returns when the new triplets are
+ * computed, with the last kernels queued, like ssa_decompose. */
+int ssa_extend(ssa_decomp* d, int r_new);
+
 /* Reconstruct the same groups for n handles of one kernel class (as for
  * ssa_decompose_batch) in one batch; the group ids must be < r of every handle.
  * out_dev[i] is a device buffer of ngroups*nx*ny doubles with the layout of

@@ -91,9 +91,18 @@ class Decomposition:
         check(lib().ssa_get_stats(self._h, C.byref(st)), "ssa_get_stats")
         return {k: getattr(st, k) for k, _ in st._fields_}
 
+    def extend(self, r: int):
+        """Continue the decomposition to r triplets (no-op if r <= self.r)."""
+        check(lib().ssa_extend(self._h, int(r)), "ssa_extend")
+        self.r = max(self.r, int(r))
+
     def reconstruct(self, groups) -> np.ndarray:
         """Reconstruct each group (list of 0-based component ids); returns
-        (ngroups, nx, ny) with NaN outside the covered cells."""
+        (ngroups, nx, ny) with NaN outside the covered cells.  Components
+        beyond r continue the decomposition first."""
+        need = max((max(g) for g in groups if len(g)), default=-1) + 1
+        if need > self.r:
+            self.extend(need)
         gp = np.zeros(len(groups) + 1, np.int32)
         gp[1:] = np.cumsum([len(g) for g in groups])
         gi = np.ascontiguousarray(np.concatenate([np.asarray(g, np.int32) for g in groups]))

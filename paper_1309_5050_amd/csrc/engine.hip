@@ -467,6 +467,22 @@ struct ssa_decomp {
         return SSA_OK;
     }
 
+    // Returns block p of the handle to the pool once the work queued on s
+    // has completed.
+    void dfree(void* p, hipStream_t s) {
+        if (!p) return;
+        std::lock_guard<std::mutex> g(ctx->mu);
+        for (size_t i = 0; i < allocs.size(); ++i) {
+            if (allocs[i].first != p) continue;
+            std::vector<std::pair<void*, size_t>> one{allocs[i]};
+            bytes -= allocs[i].second;
+            ctx->used -= std::min(ctx->used, allocs[i].second);
+            allocs.erase(allocs.begin() + (long)i);
+            ctx->defer(one, s);
+            return;
+        }
+    }
+
     size_t celem() const { return f64 ? 16 : 8; }
 };
 
@@ -1400,7 +1416,51 @@ std::vector<std::pair<const char*, int>> step_classes(bool rowfam) {
     return {{"row_in", 1}, {"col", 2}, {"row_mid", 1}, {"row_out", 1}, {"lz_proj", 1}, {"lz_update", 1}};
 }
 
-int run_lanczos(Batch& b, int max_steps, const std::function<int()>& overlap = nullptr) {
+// Thick restart of the instances in cont from the last cycle (basis m):
+// the k leading Ritz vectors are kept; the instances in fresh restart from
+// a random vector orthogonal to them instead of the residual.
+int launch_restart(Batch& b, const std::vector<int>& cont, const std::vector<int>& fresh, int m, int kk,
+                   int cycle) {
+    hipStream_t st = b.st;
+    int rc;
+    ItemList R, Z, F;
+    std::vector<char> isfresh(b.ds.size(), 0);
+    for (int i : fresh) isfresh[i] = 1;
+    for (int i : cont) {
+        const long n = b.ds[i]->nshort;
+        for (long rb = 0; rb < (n + 63) / 64; ++rb)
+            for (int cb = 0; cb < (kk + 31) / 32; ++cb) R.h.push_back(Item{i, (int)rb, 0, cb});
+        for (int k = 0; k < b.ds[i]->lz.nblk; ++k) (isfresh[i] ? F : Z).h.push_back(Item{i, k, 0, 0});
+    }
+    if ((rc = upload_lists({&R, &Z, &F}, st))) return rc;
+    {
+        ProfSpan p(b.ctx, "lz_ritz", st, [&] {
+            double f = 0.0;
+            for (int i : cont) f += 2.0 * b.ds[i]->nshort * m * kk;
+            return f;
+        });
+        launch_lz_ritz(R.n(), st, b.lzs(), R.ptr(), m, kk, nullptr);
+    }
+    launch_lz_restart(Z.n(), st, b.lzs(), Z.ptr(), m, kk);
+    if (F.n() > 0) {
+        launch_lz_restart_random(F.n(), st, b.lzs(), F.ptr(), kk, 7919ULL * cycle);   // ^ own seed
+        launch_lz_proj(F.n(), st, b.lzs(), F.ptr(), kk);
+        launch_lz_update(F.n(), st, b.lzs(), F.ptr(), kk, 1, 1);
+        launch_lz_proj2(F.n(), st, b.lzs(), F.ptr(), kk, 1);
+        launch_lz_update(F.n(), st, b.lzs(), F.ptr(), kk, 2, 1);
+    }
+    return SSA_OK;
+}
+
+// resume_m > 0: continue a finished bidiagonalisation whose last cycle had
+// a basis of resume_m vectors (its Ritz vectors and residual are still in
+// the instances' state): a thick restart keeps its leading Ritz vectors and
+// the cycles go on with the basis and restart size of the instances' r.
+// resume_fresh: the last cycle's residual is no direction to continue in
+// (the Krylov space was exhausted, or the basis was the whole short side):
+// a random vector orthogonal to the kept Ritz vectors replaces it.
+int run_lanczos(Batch& b, int max_steps, const std::function<int()>& overlap = nullptr, int resume_m = 0,
+                bool resume_fresh = false) {
     hipStream_t st = b.st;
     const int ni = (int)b.ds.size();
     int rc;
@@ -1416,8 +1476,14 @@ int run_lanczos(Batch& b, int max_steps, const std::function<int()>& overlap = n
     StepLists S;
     build_step_lists(b, act, S);
     if ((rc = upload_step_lists(S, st))) return rc;
-    launch_lz_start(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), 0ULL);   // each instance's own seed
     int jstart = 0;
+    if (resume_m > 0) {
+        const int k0 = std::min(kk, resume_m);
+        if ((rc = launch_restart(b, act, resume_fresh ? act : std::vector<int>{}, resume_m, k0, 0))) return rc;
+        jstart = k0;
+    } else {
+        launch_lz_start(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), 0ULL);   // each instance's own seed
+    }
     std::vector<int> flags(4 * ni);
     std::vector<double> betas(2 * ni);
     std::vector<int> bdrest(ni, 0);
@@ -1539,35 +1605,7 @@ int run_lanczos(Batch& b, int max_steps, const std::function<int()>& overlap = n
             // which returns them to the pool only after the stream drains
         }
         if (cont.empty()) break;
-        {
-            ItemList R, Z, F;
-            std::vector<char> isfresh(ni, 0);
-            for (int i : fresh) isfresh[i] = 1;
-            for (int i : cont) {
-                const long n = b.ds[i]->nshort;
-                for (long rb = 0; rb < (n + 63) / 64; ++rb)
-                    for (int cb = 0; cb < (kk + 31) / 32; ++cb) R.h.push_back(Item{i, (int)rb, 0, cb});
-                for (int k = 0; k < b.ds[i]->lz.nblk; ++k)
-                    (isfresh[i] ? F : Z).h.push_back(Item{i, k, 0, 0});
-            }
-            if ((rc = upload_lists({&R, &Z, &F}, st))) return rc;
-            {
-                ProfSpan p(b.ctx, "lz_ritz", st, [&] {
-                    double f = 0.0;
-                    for (int i : cont) f += 2.0 * b.ds[i]->nshort * m * kk;
-                    return f;
-                });
-                launch_lz_ritz(R.n(), st, b.lzs(), R.ptr(), m, kk, nullptr);
-            }
-            launch_lz_restart(Z.n(), st, b.lzs(), Z.ptr(), m, kk);
-            if (F.n() > 0) {
-                launch_lz_restart_random(F.n(), st, b.lzs(), F.ptr(), kk, 7919ULL * cycle);   // ^ own seed
-                launch_lz_proj(F.n(), st, b.lzs(), F.ptr(), kk);
-                launch_lz_update(F.n(), st, b.lzs(), F.ptr(), kk, 1, 1);
-                launch_lz_proj2(F.n(), st, b.lzs(), F.ptr(), kk, 1);
-                launch_lz_update(F.n(), st, b.lzs(), F.ptr(), kk, 2, 1);
-            }
-        }
+        if ((rc = launch_restart(b, cont, fresh, m, kk, cycle))) return rc;
         if (cont.size() != act.size()) {
             // the item lists change: the captured step is rebuilt (the
             // stream has been waited for at the convergence test)
@@ -2680,6 +2718,71 @@ int ssa_vforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int
     if (bad[1]) return fail(SSA_EINVAL, "no vector forecast: the group's last coordinates have nu^2 >= 1");
     if (bad[0]) return fail(SSA_EINVAL, "no vector forecast: a series' last lagged vector misses its last value");
     return SSA_OK;
+}
+
+int ssa_extend(ssa_decomp* d, int r_new) {
+    if (!d) return fail(SSA_EINVAL, "handle is NULL");
+    if (!d->decomposed || d->status != SSA_OK) return fail(SSA_ESTATE, "not decomposed");
+    if (r_new <= d->r) return SSA_OK;
+    if (r_new >= std::min(d->L, d->K)) return fail(SSA_ERANK, "r must be < min(L, K)");
+    int rc;
+    if ((rc = wait_handle(d))) return rc;
+    g_tables_ctx = d->ctx;
+    TableScope tables(d->ctx, d->ctx->st);
+    Batch b(d->ctx);
+    b.ds = {d};
+    b.f64 = d->f64;
+    b.rowfam = d->rowfam;
+    b.cls = row_word(d->nh, d->f64);
+    b.set_col(d->ctx->tile_for(d->f64, d->MA));
+    hipStream_t st = b.st;
+    const int m_old = d->st.basis;
+    if (m_old < 1) return fail(SSA_ESTATE, "no bidiagonalisation state to continue");
+    int fl[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpy(fl, d->flag, sizeof(fl), hipMemcpyDeviceToHost));
+    const bool fresh = fl[2] != 0 || m_old >= d->nshort;
+    // per-component buffers for r_new components (the spectrum, the cell
+    // sets and the bidiagonalisation state stay)
+    for (void* p : {d->T1, d->T2, d->Us, static_cast<void*>(d->U), static_cast<void*>(d->V),
+                    static_cast<void*>(d->sigma)})
+        d->dfree(p, st);
+    d->T1 = d->T2 = d->Us = nullptr;
+    d->U = d->V = d->sigma = nullptr;
+    const size_t ce = d->celem();
+    char *t1, *t2, *us;
+    if ((rc = d->dalloc(&t1, d->tslot * ce * r_new)) || (rc = d->dalloc(&t2, d->tslot * ce * r_new)) ||
+        (rc = d->dalloc(&us, d->uslot * ce * r_new)) || (rc = d->dalloc(&d->U, d->L * (long)r_new)) ||
+        (rc = d->dalloc(&d->V, d->K * (long)r_new)) || (rc = d->dalloc(&d->sigma, r_new))) {
+        d->status = rc;
+        d->decomposed = false;
+        return rc;
+    }
+    d->T1 = t1; d->T2 = t2; d->Us = us;
+    d->op.T1 = d->T1; d->op.T2 = d->T2; d->op.Us = d->Us;
+    d->r = r_new;
+    d->rs.r = r_new;
+    d->rs.U = d->U; d->rs.V = d->V; d->rs.sigma = d->sigma;
+    d->lz.r = r_new;
+    if ((rc = b.dstep.put(std::vector<int>{0, 0}, st))) return rc;
+    d->lz.step = b.dstep.as<int>();
+    if ((rc = b.upload_descs())) return rc;
+    d->last_st = st;
+    const ssa_stats before = d->st;
+    auto t0 = Clock::now();
+    FinishLists F;
+    rc = run_lanczos(b, 3000, [&] { return finish_lists(b, F); }, m_old, fresh);
+    if (!rc) rc = run_finish(b, F);
+    d->st.steps += before.steps;
+    d->st.restarts += before.restarts + 1;
+    d->st.ms_lanczos = before.ms_lanczos + ms_since(t0);
+    d->sigma_ready = false;
+    d->sigma_h.clear();
+    if (rc) {
+        d->status = rc;
+        d->decomposed = false;
+    }
+    (void)seal_handle(d);
+    return rc ? rc : d->status;
 }
 
 namespace {

@@ -430,8 +430,15 @@ def test_errors(ctx):
         ctx.decompose(x, (1, 1), 1)                   # window of one cell
     assert e.value.code == -1
     d = ctx.decompose(x, (5, 5), 3)
-    with pytest.raises(S.SsaError):
-        d.reconstruct([[0, 7]])                       # component out of range
+    with pytest.raises(S.SsaError) as e:
+        d.reconstruct([[0, 25]])                      # beyond min(L, K): no continuation
+    assert e.value.code == -3
+    import ctypes as C
+    from paper_1309_5050_amd import _native
+    gp, gi = np.array([0, 2], np.int32), np.array([0, 7], np.int32)
+    out = np.zeros((1, 20, 20))
+    rc = _native.lib().ssa_reconstruct(d.handle, gp.ctypes.data, gi.ctypes.data, 1, out.ctypes.data)
+    assert rc == -1                                   # the C call does not continue by itself
 
 
 def test_device_inputs_match_host(ctx):
@@ -602,3 +609,69 @@ def test_row_forecast_errors(ctx):
     with pytest.raises(S.SsaError):
         e.rforecast([0, 1], 5, direction="row")
     e.vforecast([0, 1], 5)             # the column forecasts need no Hankel rows
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,r0,r1", [("image_128", 4, 10), ("series_1000", 3, 8), ("mssa_8", 2, 6),
+                                        ("small_shaped", 3, 7)])
+def test_extend_matches_oracle(ctx, name, r0, r1, prec):
+    """A decomposition with r0 triplets continued to r1 (thick restart from
+    its resident state) against the oracle's first r1 triplets: sigma within
+    tol sigma_1, and the reconstruction of every gap-stable prefix group
+    within 20 tol sigma_1 / gap."""
+    w = dict(CASES[name]())
+    tol = TOL[prec]
+    sh, so, Uo, Vo = oracle_case(name, w)
+    w["r"] = r0
+    d = gpu_case(ctx, w, prec)
+    d.extend(r1)
+    assert d.r == r1
+    s = d.sigma
+    assert s.shape == (r1,)
+    assert sigma_err(s, so) <= tol, (name, prec, sigma_err(s, so))
+    st = d.stats
+    assert st["converged"]
+    for k in range(2, r1 + 1):
+        gap = so[k - 1] - so[k]
+        if gap < 1e-3 * so[0]:
+            continue
+        g = list(range(k))
+        got = d.reconstruct([g])[0]
+        if w["kind"] == "mssa":
+            lens = [len(x) for x in w["x"]]
+            ref = oracle.reconstruct_mssa(lens, w["window"], so, Uo, Vo, g)
+            num = np.sqrt(sum(np.sum((got[:n, p] - ref[p]) ** 2) for p, n in enumerate(lens)))
+            den = np.sqrt(sum(np.sum(x ** 2) for x in w["x"]))
+        else:
+            x = w["x"] if w["x"].ndim == 2 else w["x"][:, None]
+            ref = oracle.reconstruct(sh, so, Uo, Vo, g)
+            cov = ~np.isnan(ref)
+            num = np.linalg.norm(got[cov] - ref[cov])
+            den = np.linalg.norm(np.nan_to_num(x[cov]))
+        assert num / den <= C_SUB * tol * so[0] / gap, (name, prec, k, num / den)
+
+
+def test_reconstruct_continues_the_decomposition(ctx):
+    """Asking for components beyond r continues the decomposition (the
+    result equals that of a decomposition made with enough triplets)."""
+    w = W.series_1d()
+    a = ctx.decompose(w["x"], w["window"], 3)
+    ra = a.reconstruct([[0, 1, 2, 3, 4, 5]])[0]
+    assert a.r == 6
+    b = ctx.decompose(w["x"], w["window"], 6)
+    rb = b.reconstruct([[0, 1, 2, 3, 4, 5]])[0]
+    sh, so, Uo, Vo = oracle_case("series_1000", w)
+    gap = so[5] - so[6]
+    assert np.max(np.abs(ra - rb)) <= 40 * 1e-10 * so[0] / gap * np.max(np.abs(w["x"]))
+    np.testing.assert_allclose(a.sigma, b.sigma, rtol=0, atol=2e-10 * so[0])
+
+
+def test_extend_twice_and_noop(ctx):
+    w = W.image_2d(n=96, lw=10, r=4, seed=70)
+    d = ctx.decompose(w["x"], w["window"], 2)
+    d.extend(2)                                       # no-op
+    assert d.r == 2
+    d.extend(5)
+    d.extend(9)
+    e = ctx.decompose(w["x"], w["window"], 9)
+    np.testing.assert_allclose(d.sigma, e.sigma, rtol=0, atol=1e-9 * e.sigma[0])
