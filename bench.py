@@ -172,6 +172,28 @@ def main():
                  "finite": bool(np.isfinite(fv).all() and np.isfinite(fr).all() and np.isfinite(fw).all())}
     dm.free()
 
+    # continuation: one decomposition of the workload (FP32) extended by
+    # r/5 triplets, against decomposing it afresh with that many
+    r2 = r + max(1, r // 5)
+    torch.cuda.synchronize()
+    te0 = time.perf_counter()
+    prec = args.precision
+    de = ctx.decompose_batch_dev(xs[:1], (lw, lw), r, precision=prec)[0]
+    _ = de.sigma
+    te1 = time.perf_counter()
+    de.extend(r2)
+    _ = de.sigma
+    te2 = time.perf_counter()
+    df = ctx.decompose_batch_dev(xs[:1], (lw, lw), r2, precision=prec)[0]
+    _ = df.sigma
+    te3 = time.perf_counter()
+    extend = {"workload": f"one {n}x{n} image, {lw}x{lw} window, {prec}", "r_from": r, "r_to": r2,
+              "decompose_ms": 1e3 * (te1 - te0), "extend_ms": 1e3 * (te2 - te1),
+              "fresh_decompose_ms": 1e3 * (te3 - te2),
+              "max_sigma_diff_over_s1": float(np.max(np.abs(de.sigma - df.sigma)) / df.sigma[0])}
+    de.free()
+    df.free()
+
     # plain single-instance FP64 path (same kernels, batch of one)
     single = None
     if not args.no_single:
@@ -217,6 +239,7 @@ def main():
         "mfma": mfma,
         "wcor": wcor,
         "rforecast": rforecast,
+        "extend": extend,
         "hbh_product": {"bytes_per_product": bmv, "products_per_step": products,
                         "effective_GBs": bmv * products / (dt / args.steps) / 1e9},
         "lanczos": {"steps": stats["steps"], "restarts": stats["restarts"], "basis": stats["basis"],
