@@ -115,6 +115,20 @@ int  ssa_ctx_set_stream(ssa_ctx* ctx, void* stream);
 int ssa_decompose(ssa_ctx* ctx, const double* x, int nx, int ny, const uint8_t* mask,
                   const uint8_t* wmask, int lx, int ly, int r, int precision, ssa_decomp** out);
 
+/* The eigen method for small windows (the paper's alternative to the
+ * truncated SVD when L is small: S = X X^T and its full eigendecomposition,
+ * O(L N log N + L^3)).  Same arguments as ssa_decompose, always FP64; the
+ * window may hold at most 128 cells (SSA_EINVAL otherwise).  S is formed on
+ * the matrix cores straight from the cleaned array (the trajectory matrix
+ * is never stored), its eigenpairs by one-sided Jacobi; sigma_i =
+ * sqrt(lambda_i), U_i the eigenvectors, V_i = X^T U_i / sigma_i.  Squaring
+ * the matrix limits the absolute accuracy of sigma_i to about
+ * eps sigma_1^2 / sigma_i (sqrt(eps) sigma_1 for vanishing ones).  The
+ * handle serves every call on decompositions; ssa_extend takes further
+ * eigenpairs of the resident S. */
+int ssa_decompose_eigen(ssa_ctx* ctx, const double* x, int nx, int ny, const uint8_t* mask,
+                        const uint8_t* wmask, int lx, int ly, int r, ssa_decomp** out);
+
 /* MSSA (Section 3.1, equation mssa_embedding) of s series of lengths len[p]
  * with window L (1 < L < min len).  Internally the 2D packing of Section
  * 5.3: a max(len) x s array, window L x 1.  Outputs use that packing:

@@ -216,10 +216,19 @@ class Context:
             mask = np.ascontiguousarray(mask, dtype=np.uint8).reshape(x.shape)
         return x, lx, ly, mask, wmask
 
-    def decompose(self, x, window=None, r: int = 10, mask=None, wmask=None, precision="fp64") -> Decomposition:
-        """Shaped decomposition of an image (or a series given as 1-D)."""
+    def decompose(self, x, window=None, r: int = 10, mask=None, wmask=None, precision="fp64",
+                  method: str = "lanczos") -> Decomposition:
+        """Shaped decomposition of an image (or a series given as 1-D).
+        method "eigen": S = X X^T and its eigenpairs (windows of at most 128
+        cells, FP64 whatever the precision)."""
         x, lx, ly, mask, wmask = self._image_args(x, window, mask, wmask)
         h = C.c_void_p()
+        if method == "eigen":
+            check(lib().ssa_decompose_eigen(self._h, _ptr(x), x.shape[0], x.shape[1], _ptr(mask), _ptr(wmask), lx,
+                                            ly, r, C.byref(h)), "ssa_decompose_eigen")
+            return Decomposition(self, h.value)
+        if method != "lanczos":
+            raise ValueError("method must be 'lanczos' or 'eigen'")
         check(lib().ssa_decompose(self._h, _ptr(x), x.shape[0], x.shape[1], _ptr(mask), _ptr(wmask), lx, ly, r,
                                   _prec(precision), C.byref(h)), "ssa_decompose")
         return Decomposition(self, h.value)

@@ -407,6 +407,7 @@ struct ssa_decomp {
     // internal geometry
     int A = 0, B = 0, LA = 0, LB = 0, KA = 0, KB = 0, MA = 1, MB = 0, nh = 0, P = 0, ldp = 0;
     bool rowfam = false, f64 = true;
+    bool eigen = false;              // eigen method: S = X X^T and its eigenpairs (small L)
     int r = 0;
     unsigned long long seed = 0;
     long L = 0, K = 0;
@@ -1698,6 +1699,68 @@ int run_finish(Batch& b, FinishLists& F) {
     return SSA_OK;
 }
 
+int fetch_kmask(ssa_decomp* d);
+
+// The eigen method (the paper's alternative for small windows): S = X X^T
+// on the matrix cores straight from the cleaned grid, its eigenpairs by the
+// one-sided Jacobi SVD of the projected-matrix kernel (S is symmetric
+// positive semi-definite, so its left singular vectors are eigenvectors and
+// its singular values the eigenvalues), U and sigma = sqrt(lambda) of the r
+// leading ones.  The other side's vectors come from the finish pass.
+int run_eigen(Batch& b, FinishLists& F) {
+    hipStream_t st = b.st;
+    int rc;
+    ItemList I;
+    for (size_t q = 0; q < b.ds.size(); ++q) {
+        auto* d = b.ds[q];
+        if ((rc = fetch_kmask(d))) return rc;
+        std::vector<int> offL, offK;
+        offL.reserve(d->L);
+        offK.reserve(d->K);
+        for (int a = 0; a < d->LA; ++a)
+            for (int c = 0; c < d->LB; ++c)
+                if (d->lmask_h[(size_t)a * d->LB + c]) offL.push_back(a * d->B + c);
+        for (int a = 0; a < d->KA; ++a)
+            for (int c = 0; c < d->KB; ++c)
+                if (d->kmask_h[(size_t)a * d->KB + c]) offK.push_back(a * d->B + c);
+        if ((long)offL.size() != d->L || (long)offK.size() != d->K || d->L > kMaxBasis)
+            return fail(SSA_EINVAL, "eigen method: inconsistent cell sets");
+        const int L = (int)d->L;
+        const int nb = (L + 15) / 16, ntile = nb * (nb + 1) / 2;
+        // about 2048 workgroups, each chunk at least 128 origins
+        const int nchunk = (int)std::max<long>(1, std::min<long>(2048 / ntile + 1, (d->K + 127) / 128));
+        DevVec dl, dk, part, out;
+        if ((rc = dl.put(offL, st)) || (rc = dk.put(offK, st)) ||
+            (rc = part.reserve((size_t)ntile * 256 * nchunk * sizeof(double))) ||
+            (rc = out.reserve((size_t)ntile * 256 * sizeof(double))))
+            return rc;
+        {
+            // flops of the Gram (upper-triangle tiles, 2 per multiply-add)
+            ProfSpan p(b.ctx, "xgram", st, [&] { return 2.0 * ntile * 256.0 * (double)d->K; });
+            launch_xgram(st, d->xc, dl.as<int>(), L, dk.as<int>(), d->K, nchunk, part.as<double>(),
+                         out.as<double>(), d->Bm);
+        }
+        HIPCHK(hipGetLastError());
+        // the DevVecs go back to the call's table cache, reused after the stream drains
+        I.h.push_back(Item{(int)q, 0, 0, 0});
+    }
+    if ((rc = upload_lists({&I}, st))) return rc;
+    const int L = (int)b.ds[0]->L;
+    launch_lz_svd(I.n(), st, b.lzs(), I.ptr(), L, 100);
+    int rmax = 0;
+    for (auto* d : b.ds) rmax = std::max(rmax, d->r);
+    launch_eig_take(I.n(), st, b.lzs(), b.res(), I.ptr(), L, rmax);
+    HIPCHK(hipGetLastError());
+    for (auto* d : b.ds) {
+        d->st.steps = 0;
+        d->st.restarts = 0;
+        d->st.basis = 0;
+        d->st.converged = 1;
+        d->st.max_resid = 0.0;
+    }
+    return F.ready ? SSA_OK : finish_lists(b, F);
+}
+
 int seal_handle(ssa_decomp* d);
 
 // Reconstruction of the same groups for every instance of the batch into
@@ -1831,6 +1894,14 @@ void run_planned(ssa_ctx* ctx, const std::vector<ssa_decomp*>& grp, hipStream_t 
     std::map<std::pair<int, int>, std::vector<ssa_decomp*>> parts;
     for (auto* d : ok) {
         choose_side(d);
+        if (d->eigen) {
+            // S lives on the window side
+            d->side = 0;
+            d->nshort = d->L;
+            d->nlong = d->K;
+            parts[{0, 0}].push_back(d);
+            continue;
+        }
         const int m = basis_size(d->nshort, d->r);
         parts[{m, restart_keep(m, d->r)}].push_back(d);
     }
@@ -1843,7 +1914,7 @@ void run_planned(ssa_ctx* ctx, const std::vector<ssa_decomp*>& grp, hipStream_t 
         const double t_spec = ms_since(t1);
         auto t2 = Clock::now();
         FinishLists F;
-        if (!rc) rc = run_lanczos(b, 3000, [&] { return finish_lists(b, F); });
+        if (!rc) rc = b.ds[0]->eigen ? run_eigen(b, F) : run_lanczos(b, 3000, [&] { return finish_lists(b, F); });
         const double t_lz = ms_since(t2);
         auto t3 = Clock::now();
         if (!rc) rc = run_finish(b, F);
@@ -2381,6 +2452,28 @@ int ssa_decompose(ssa_ctx* ctx, const double* x, int nx, int ny, const uint8_t* 
     return rc ? rc : st;
 }
 
+int ssa_decompose_eigen(ssa_ctx* ctx, const double* x, int nx, int ny, const uint8_t* mask, const uint8_t* wmask,
+                        int lx, int ly, int r, ssa_decomp** out) {
+    if (!out) return fail(SSA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctx) return fail(SSA_EINVAL, "context is NULL");
+    ssa_request q{x, nx, ny, mask, wmask, lx, ly, r, SSA_FP64, 0x5eedULL};
+    g_tables_ctx = ctx;
+    TableScope tables(ctx, ctx->st);
+    std::unique_ptr<ssa_decomp> d(new ssa_decomp());
+    int rc = plan_request(ctx, q, d.get());
+    if (rc) return rc;
+    if (d->L > kMaxBasis) return fail(SSA_EINVAL, "eigen method needs a window of at most 128 cells");
+    if ((rc = upload_request(q, d.get(), false, ctx->st))) return rc;
+    d->eigen = true;
+    std::vector<int> st;
+    run_planned(ctx, {d.get()}, ctx->st, st);
+    if (st.empty() || st[0] != SSA_OK) return st.empty() ? fail(SSA_EINVAL, "no decomposition") : st[0];
+    (void)seal_handle(d.get());
+    *out = d.release();
+    return SSA_OK;
+}
+
 int ssa_decompose_multi(ssa_ctx* ctx, const double* const* series, const int* len, int s, int L, int r,
                         int precision, ssa_decomp** out) {
     if (!out) return fail(SSA_EINVAL, "out is NULL");
@@ -2737,7 +2830,7 @@ int ssa_extend(ssa_decomp* d, int r_new) {
     b.set_col(d->ctx->tile_for(d->f64, d->MA));
     hipStream_t st = b.st;
     const int m_old = d->st.basis;
-    if (m_old < 1) return fail(SSA_ESTATE, "no bidiagonalisation state to continue");
+    if (m_old < 1 && !d->eigen) return fail(SSA_ESTATE, "no bidiagonalisation state to continue");
     int fl[4] = {0, 0, 0, 0};
     HIPCHK(hipMemcpy(fl, d->flag, sizeof(fl), hipMemcpyDeviceToHost));
     const bool fresh = fl[2] != 0 || m_old >= d->nshort;
@@ -2770,7 +2863,15 @@ int ssa_extend(ssa_decomp* d, int r_new) {
     const ssa_stats before = d->st;
     auto t0 = Clock::now();
     FinishLists F;
-    rc = run_lanczos(b, 3000, [&] { return finish_lists(b, F); }, m_old, fresh);
+    if (d->eigen) {
+        // every eigenpair of S is still resident: take r_new of them
+        ItemList I;
+        I.h.push_back(Item{0, 0, 0, 0});
+        rc = upload_lists({&I}, st);
+        if (!rc) launch_eig_take(I.n(), st, b.lzs(), b.res(), I.ptr(), (int)d->L, r_new);
+    } else {
+        rc = run_lanczos(b, 3000, [&] { return finish_lists(b, F); }, m_old, fresh);
+    }
     if (!rc) rc = run_finish(b, F);
     d->st.steps += before.steps;
     d->st.restarts += before.restarts + 1;

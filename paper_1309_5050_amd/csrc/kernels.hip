@@ -1981,6 +1981,106 @@ k_wgram(const double* const* __restrict__ arr, int narr, const double* __restric
     part[((long)blockIdx.y * 256 + e) * nchunk + blockIdx.x] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
 }
 
+// ------------------------------------------------------------------------
+// eigen method: S = X X^T for a small window, then its eigenpairs
+// ------------------------------------------------------------------------
+
+// Partial sums of S = X X^T over one chunk of origins for a 16 x 16 tile of
+// window-cell pairs (i in block ib, j in block jb, ib <= jb; tiles numbered
+// along the rows of the upper triangle), on the matrix cores.  The
+// trajectory matrix is never stored: X[i, k] = xc[offL[i] + offK[k]], the
+// cleaned grid (zero off N) at the cell of window cell i seen from origin
+// k.  Each v_mfma_f64_16x16x4f64 takes 4 origins: A = X[block ib, 4
+// origins] (element (i, k) in lane i + 16 k), B = X[block jb, the same
+// origins]^T (element (k, j) in lane j + 16 k).  Grid (chunks, tiles), 4
+// waves per workgroup; part[(tile * 256 + 16 i + j) * nchunk + chunk] as
+// for the weighted Gram.
+__global__ void __launch_bounds__(256)
+k_xgram(const double* __restrict__ xc, const int* __restrict__ offL, int L, const int* __restrict__ offK, long K,
+        int nchunk, double* __restrict__ part) {
+    __shared__ double red[4][256];
+    const int nb = (L + 15) / 16;
+    int k = blockIdx.y, ib = 0;
+    while (k >= nb - ib) {
+        k -= nb - ib;
+        ++ib;
+    }
+    const int jb = ib + k;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lo = lane & 15, hi = lane >> 4;
+    const int ai = ib * 16 + lo, aj = jb * 16 + lo;
+    const long oi = ai < L ? offL[ai] : 0, oj = aj < L ? offL[aj] : 0;   // unused rows read a valid cell
+    const gptr<const double> px = as_global(xc);
+    const gptr<const int> pk = as_global(offK);
+    constexpr int U = 8;   // 4-origin steps whose operands are loaded together
+    const long csz = ((K + nchunk - 1) / nchunk + 16 * U - 1) / (16 * U) * (16 * U);
+    const long c0 = (long)blockIdx.x * csz;
+    const long c1 = min(K, c0 + csz);
+    dvec4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (long cb = c0 + 4 * wave; cb < c1; cb += 16 * U) {
+        int ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long c = cb + 16 * u + hi;
+            ok[u] = gload(pk + (c < c1 ? c : c0));
+        }
+        double yi[U], yj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            yi[u] = gload(px + oi + ok[u]);
+            yj[u] = gload(px + oj + ok[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool in = cb + 16 * u + hi < c1;
+            const double a = (in && ai < L) ? yi[u] : 0.0;
+            const double b = (in && aj < L) ? yj[u] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave][(4 * v + hi) * 16 + lo] = acc[v];
+    __syncthreads();
+    const int e = threadIdx.x;
+    part[((long)blockIdx.y * 256 + e) * nchunk + blockIdx.x] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+}
+
+// Places the summed tiles of S (out[tile * 256 + 16 i + j]) into the
+// projected-matrix buffer (column-major, leading dimension kMaxBasis),
+// mirroring the off-diagonal tiles.  One workgroup per tile.
+__global__ void __launch_bounds__(256)
+k_xgram_place(const double* __restrict__ out, int L, double* __restrict__ Bm) {
+    const int nb = (L + 15) / 16;
+    int k = blockIdx.x, ib = 0;
+    while (k >= nb - ib) {
+        k -= nb - ib;
+        ++ib;
+    }
+    const int jb = ib + k;
+    const int e = threadIdx.x, i = ib * 16 + e / 16, j = jb * 16 + e % 16;
+    if (i >= L || j >= L) return;
+    const double v = out[(long)blockIdx.x * 256 + e];
+    Bm[(long)j * kMaxBasis + i] = v;
+    if (ib != jb) Bm[(long)i * kMaxBasis + j] = v;
+}
+
+// After the SVD of the symmetric positive semi-definite S (its left singular
+// vectors are eigenvectors, its singular values the eigenvalues):
+// U_c = eigenvector of the c-th largest eigenvalue, sigma_c = sqrt(lambda_c)
+// (rounding can leave a vanishing eigenvalue slightly negative: 0).
+__global__ void __launch_bounds__(256)
+k_eig_take(const LzDesc* __restrict__ lzs, const ResDesc* __restrict__ res, const Item* __restrict__ items, int L,
+           int r) {
+    const int inst = items[blockIdx.x].inst;
+    const LzDesc& lz = lzs[inst];
+    const ResDesc& rs = res[inst];
+    for (int e = threadIdx.x; e < L * r; e += 256) {
+        const int c = e / L, i = e % L;
+        rs.U[(long)c * L + i] = lz.Yl[(long)lz.perm[c] * kMaxBasis + i];
+    }
+    for (int c = threadIdx.x; c < r; c += 256) rs.sigma[c] = sqrt(fmax(lz.sig[c], 0.0));
+}
+
 // out[e] = sum over the chunks of part[e * nchunk + chunk]: one wave per
 // entry, lanes over the chunks, then a fixed-order wave sum.
 __global__ void __launch_bounds__(256)

@@ -87,6 +87,15 @@ void launch_vrow(hipStream_t st, const double* U, long L, const double* sigma, c
 // (h x ng) then h values per series into out (A x h).
 void launch_rrow(hipStream_t st, const double* V, long K, const int* krow, int A, const int* grp, int ng,
                  const double* G, const double* rec, int B, long L, int h, double* yk, double* out);
+// Eigen method: S = X X^T (L x L, L <= kMaxBasis) into Bm from the cleaned
+// grid xc and the window-cell and origin offsets; part holds
+// ntile * 256 * nchunk values and out ntile * 256, ntile = nb (nb + 1) / 2,
+// nb = ceil(L / 16).  Then U and sigma of the r leading eigenpairs from the
+// small SVD's output.
+void launch_xgram(hipStream_t st, const double* xc, const int* offL, int L, const int* offK, long K, int nchunk,
+                  double* part, double* out, double* Bm);
+void launch_eig_take(int nitems, hipStream_t st, const LzDesc* lzs, const ResDesc* res, const Item* items, int L,
+                     int r);
 void launch_wgram(hipStream_t st, const double* const* arr, int narr, const double* W, long ncell, int nchunk,
                   double* part, double* out);
 void launch_transpose(int nmat, int R, int C, hipStream_t st, const double* in, double* out);

@@ -675,3 +675,62 @@ def test_extend_twice_and_noop(ctx):
     d.extend(9)
     e = ctx.decompose(w["x"], w["window"], 9)
     np.testing.assert_allclose(d.sigma, e.sigma, rtol=0, atol=1e-9 * e.sigma[0])
+
+
+EIGEN_CASES = {
+    "small_shaped": lambda: W.small_shaped(),
+    "series_400_L100": lambda: W.series_1d(n=400, L=100, r=8),
+    "image_64_w8": lambda: W.image_2d(n=64, lw=8, r=6, seed=41),
+    "disc_48_w10x12": lambda: dict(W.shaped_disc(n=48, radius=20.0, lw=10, r=6, hole_r=(1, 2)), window=(10, 12)),
+}
+
+
+@pytest.mark.parametrize("name", list(EIGEN_CASES))
+def test_eigen_method_matches_oracle(ctx, name):
+    """The eigen method (S = X X^T on the matrix cores, eigenpairs by
+    Jacobi) against the oracle: sigma within tol sigma_1 wherever sigma_i is
+    large enough for the squared matrix to resolve it (sigma_i >= 1e-3
+    sigma_1), reconstructions of gap-stable prefix groups within
+    20 tol sigma_1 / gap."""
+    w = EIGEN_CASES[name]()
+    tol = 1e-10
+    sh, so, Uo, Vo = oracle.decompose(w["x"], w["mask"], w["wmask"], w["window"])
+    r = min(w["r"], sh.L - 1)
+    d = ctx.decompose(w["x"], w["window"], r, mask=w["mask"], wmask=w["wmask"], method="eigen")
+    s = d.sigma
+    big = so[:r] >= 1e-3 * so[0]
+    assert np.max(np.abs(s - so[:r])[big]) <= tol * so[0], (name, s, so[:r])
+    x = w["x"] if w["x"].ndim == 2 else w["x"][:, None]
+    for k in range(1, r):
+        gap = so[k - 1] - so[k]
+        if gap < 1e-3 * so[0] or not big[k - 1]:
+            continue
+        g = list(range(k))
+        ref = oracle.reconstruct(sh, so, Uo, Vo, g)
+        got = d.reconstruct([g])[0]
+        assert np.array_equal(np.isnan(got), np.isnan(ref))
+        cov = ~np.isnan(ref)
+        e = np.linalg.norm(got[cov] - ref[cov]) / np.linalg.norm(np.nan_to_num(x[cov]))
+        assert e <= C_SUB * tol * so[0] / gap, (name, k, e)
+
+
+def test_eigen_method_agrees_with_lanczos_and_extends(ctx):
+    w = W.image_2d(n=80, lw=9, r=5, seed=43)
+    a = ctx.decompose(w["x"], w["window"], 5, method="eigen")
+    b = ctx.decompose(w["x"], w["window"], 5)
+    np.testing.assert_allclose(a.sigma, b.sigma, rtol=0, atol=1e-9 * b.sigma[0])
+    a.extend(9)
+    c = ctx.decompose(w["x"], w["window"], 9, method="eigen")
+    assert np.array_equal(a.sigma, c.sigma)          # the same eigenpairs of the same S
+    Ua, Va = a.vectors()
+    Uc, Vc = c.vectors()
+    assert np.allclose(Ua, Uc, atol=1e-12, equal_nan=True)
+
+
+def test_eigen_method_limits(ctx):
+    import paper_1309_5050_amd as S
+    x = np.random.default_rng(2).standard_normal((40, 40))
+    with pytest.raises(S.SsaError):
+        ctx.decompose(x, (12, 12), 3, method="eigen")    # 144 cells > 128
+    with pytest.raises(ValueError):
+        ctx.decompose(x, (5, 5), 3, method="svd")
