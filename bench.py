@@ -194,6 +194,31 @@ def main():
     de.free()
     df.free()
 
+    # eigen method against the truncated SVD on a small window: a 1D series
+    # of 10000 values with L = 100, r = 10 (FP64 both)
+    xe = W.series_1d(n=10000, L=100, r=10)["x"]
+    ctx.profile("xgram")
+    torch.cuda.synchronize()
+    tq0 = time.perf_counter()
+    dq = ctx.decompose(xe, 100, 10, method="eigen")
+    _ = dq.sigma
+    tq1 = time.perf_counter()
+    dl = ctx.decompose(xe, 100, 10)
+    _ = dl.sigma
+    tq2 = time.perf_counter()
+    pg = ctx.profile_read(["xgram"])["xgram"]
+    ctx.profile(None)
+    # the "bytes" of the xgram class count floating-point operations
+    xg_tf = pg["bytes"] / (pg["ms"] * 1e-3) / 1e12 if pg["launches"] and pg["ms"] > 0 else None
+    eigen = {"workload": "1D series N=10000, L=100, r=10, fp64", "eigen_ms": 1e3 * (tq1 - tq0),
+             "lanczos_ms": 1e3 * (tq2 - tq1),
+             "max_sigma_diff_over_s1": float(np.max(np.abs(dq.sigma - dl.sigma)) / dl.sigma[0]),
+             "xgram_kernel_ms": pg["ms"] / pg["launches"] if pg["launches"] else None,
+             "xgram_tflops": xg_tf,
+             "xgram_mfma_frac": xg_tf / FP64_MFMA_PEAK_TFLOPS if xg_tf else None}
+    dq.free()
+    dl.free()
+
     # plain single-instance FP64 path (same kernels, batch of one)
     single = None
     if not args.no_single:
@@ -240,6 +265,7 @@ def main():
         "wcor": wcor,
         "rforecast": rforecast,
         "extend": extend,
+        "eigen": eigen,
         "hbh_product": {"bytes_per_product": bmv, "products_per_step": products,
                         "effective_GBs": bmv * products / (dt / args.steps) / 1e9},
         "lanczos": {"steps": stats["steps"], "restarts": stats["restarts"], "basis": stats["basis"],
