@@ -35,6 +35,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--no-single", action="store_true", help="skip the single-instance FP64 comparator")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the w-correlation, forecast, continuation and eigen-method timings")
     ap.add_argument("--serve", type=int, default=300, metavar="N",
                     help="requests of the mixed serving workload for the latency runs (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -136,88 +138,96 @@ def main():
     bmv = b * (K + L) + 2 * b * n * (n // 2 + 1)
     products = 2 * sum(d.stats["steps"] for d in last)
 
-    # w-correlation matrix of the r elementary components of one decomposition
-    # (reconstruction of r singleton groups + the weighted Gram kernel)
-    ctx.profile("wgram")
-    torch.cuda.synchronize()
-    tw0 = time.perf_counter()
-    rho, _ = last[0].wcor([[i] for i in range(r)])
-    tw1 = time.perf_counter()
-    pw = ctx.profile_read(["wgram"])["wgram"]
-    ctx.profile(None)
-    wgram_gbs = pw["bytes"] / (pw["ms"] * 1e-3) / 1e9 if pw["ms"] > 0 else 0.0
-    wcor = {"groups": r, "ms_total": 1e3 * (tw1 - tw0), "gram_kernel_ms": pw["ms"],
-            "gram_roofline": {"bound": "hbm", "achieved": wgram_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": wgram_gbs / HBM_PEAK_GBS, "bytes": pw["bytes"]},
-            "max_offdiag_abs_rho": float(np.max(np.abs(rho - np.diag(np.diag(rho)))))}
+    def run_extras():
+        """The calls outside the timed batches (w-correlations, forecasts,
+        continuation, eigen method), each timed on its own."""
+        # w-correlation matrix of the r elementary components of one decomposition
+        # (reconstruction of r singleton groups + the weighted Gram kernel)
+        ctx.profile("wgram")
+        torch.cuda.synchronize()
+        tw0 = time.perf_counter()
+        rho, _ = last[0].wcor([[i] for i in range(r)])
+        tw1 = time.perf_counter()
+        pw = ctx.profile_read(["wgram"])["wgram"]
+        ctx.profile(None)
+        wgram_gbs = pw["bytes"] / (pw["ms"] * 1e-3) / 1e9 if pw["ms"] > 0 else 0.0
+        wcor = {"groups": r, "ms_total": 1e3 * (tw1 - tw0), "gram_kernel_ms": pw["ms"],
+                "gram_roofline": {"bound": "hbm", "achieved": wgram_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": wgram_gbs / HBM_PEAK_GBS, "bytes": pw["bytes"]},
+                "max_offdiag_abs_rho": float(np.max(np.abs(rho - np.diag(np.diag(rho)))))}
 
-    # column recurrent forecast: 100 values of each of the 50 series of the
-    # MSSA workload (N_p ~ U(1000, 3000), L = 500, r = 20) from the group of
-    # the two shared sines, on an FP32 decomposition
-    wm = W.config(3)
-    dm = ctx.decompose_multi(wm["x"], wm["window"], wm["r"], precision="fp32")
-    torch.cuda.synchronize()
-    tf0 = time.perf_counter()
-    fc = dm.rforecast([0, 1, 2, 3], 100)
-    tf1 = time.perf_counter()
-    fv = dm.vforecast([0, 1, 2, 3], 100)
-    tf2 = time.perf_counter()
-    fr = dm.rforecast([0, 1, 2, 3], 100, direction="row")
-    tf3 = time.perf_counter()
-    fw = dm.vforecast([0, 1, 2, 3], 100, direction="row")
-    tf4 = time.perf_counter()
-    rforecast = {"workload": "MSSA 50 series N~U(1000,3000), L=500, r=20, fp32; group {1..4}, 100 steps",
-                 "series": int(fc.shape[0]), "steps": int(fc.shape[1]), "ms": 1e3 * (tf1 - tf0),
-                 "vector_ms": 1e3 * (tf2 - tf1), "row_ms": 1e3 * (tf3 - tf2), "vector_row_ms": 1e3 * (tf4 - tf3),
-                 "finite": bool(np.isfinite(fv).all() and np.isfinite(fr).all() and np.isfinite(fw).all())}
-    dm.free()
+        # column recurrent forecast: 100 values of each of the 50 series of the
+        # MSSA workload (N_p ~ U(1000, 3000), L = 500, r = 20) from the group of
+        # the two shared sines, on an FP32 decomposition
+        wm = W.config(3)
+        dm = ctx.decompose_multi(wm["x"], wm["window"], wm["r"], precision="fp32")
+        torch.cuda.synchronize()
+        tf0 = time.perf_counter()
+        fc = dm.rforecast([0, 1, 2, 3], 100)
+        tf1 = time.perf_counter()
+        fv = dm.vforecast([0, 1, 2, 3], 100)
+        tf2 = time.perf_counter()
+        fr = dm.rforecast([0, 1, 2, 3], 100, direction="row")
+        tf3 = time.perf_counter()
+        fw = dm.vforecast([0, 1, 2, 3], 100, direction="row")
+        tf4 = time.perf_counter()
+        rforecast = {"workload": "MSSA 50 series N~U(1000,3000), L=500, r=20, fp32; group {1..4}, 100 steps",
+                     "series": int(fc.shape[0]), "steps": int(fc.shape[1]), "ms": 1e3 * (tf1 - tf0),
+                     "vector_ms": 1e3 * (tf2 - tf1), "row_ms": 1e3 * (tf3 - tf2), "vector_row_ms": 1e3 * (tf4 - tf3),
+                     "finite": bool(np.isfinite(fv).all() and np.isfinite(fr).all() and np.isfinite(fw).all())}
+        dm.free()
 
-    # continuation: one decomposition of the workload (FP32) extended by
-    # r/5 triplets, against decomposing it afresh with that many
-    r2 = r + max(1, r // 5)
-    torch.cuda.synchronize()
-    te0 = time.perf_counter()
-    prec = args.precision
-    de = ctx.decompose_batch_dev(xs[:1], (lw, lw), r, precision=prec)[0]
-    _ = de.sigma
-    te1 = time.perf_counter()
-    de.extend(r2)
-    _ = de.sigma
-    te2 = time.perf_counter()
-    df = ctx.decompose_batch_dev(xs[:1], (lw, lw), r2, precision=prec)[0]
-    _ = df.sigma
-    te3 = time.perf_counter()
-    extend = {"workload": f"one {n}x{n} image, {lw}x{lw} window, {prec}", "r_from": r, "r_to": r2,
-              "decompose_ms": 1e3 * (te1 - te0), "extend_ms": 1e3 * (te2 - te1),
-              "fresh_decompose_ms": 1e3 * (te3 - te2),
-              "max_sigma_diff_over_s1": float(np.max(np.abs(de.sigma - df.sigma)) / df.sigma[0])}
-    de.free()
-    df.free()
+        # continuation: one decomposition of the workload (FP32) extended by
+        # r/5 triplets, against decomposing it afresh with that many
+        r2 = r + max(1, r // 5)
+        torch.cuda.synchronize()
+        te0 = time.perf_counter()
+        prec = args.precision
+        de = ctx.decompose_batch_dev(xs[:1], (lw, lw), r, precision=prec)[0]
+        _ = de.sigma
+        te1 = time.perf_counter()
+        de.extend(r2)
+        _ = de.sigma
+        te2 = time.perf_counter()
+        df = ctx.decompose_batch_dev(xs[:1], (lw, lw), r2, precision=prec)[0]
+        _ = df.sigma
+        te3 = time.perf_counter()
+        extend = {"workload": f"one {n}x{n} image, {lw}x{lw} window, {prec}", "r_from": r, "r_to": r2,
+                  "decompose_ms": 1e3 * (te1 - te0), "extend_ms": 1e3 * (te2 - te1),
+                  "fresh_decompose_ms": 1e3 * (te3 - te2),
+                  "max_sigma_diff_over_s1": float(np.max(np.abs(de.sigma - df.sigma)) / df.sigma[0])}
+        de.free()
+        df.free()
 
-    # eigen method against the truncated SVD on a small window: a 1D series
-    # of 10000 values with L = 100, r = 10 (FP64 both)
-    xe = W.series_1d(n=10000, L=100, r=10)["x"]
-    ctx.profile("xgram")
-    torch.cuda.synchronize()
-    tq0 = time.perf_counter()
-    dq = ctx.decompose(xe, 100, 10, method="eigen")
-    _ = dq.sigma
-    tq1 = time.perf_counter()
-    dl = ctx.decompose(xe, 100, 10)
-    _ = dl.sigma
-    tq2 = time.perf_counter()
-    pg = ctx.profile_read(["xgram"])["xgram"]
-    ctx.profile(None)
-    # the "bytes" of the xgram class count floating-point operations
-    xg_tf = pg["bytes"] / (pg["ms"] * 1e-3) / 1e12 if pg["launches"] and pg["ms"] > 0 else None
-    eigen = {"workload": "1D series N=10000, L=100, r=10, fp64", "eigen_ms": 1e3 * (tq1 - tq0),
-             "lanczos_ms": 1e3 * (tq2 - tq1),
-             "max_sigma_diff_over_s1": float(np.max(np.abs(dq.sigma - dl.sigma)) / dl.sigma[0]),
-             "xgram_kernel_ms": pg["ms"] / pg["launches"] if pg["launches"] else None,
-             "xgram_tflops": xg_tf,
-             "xgram_mfma_frac": xg_tf / FP64_MFMA_PEAK_TFLOPS if xg_tf else None}
-    dq.free()
-    dl.free()
+        # eigen method against the truncated SVD on a small window: a 1D series
+        # of 10000 values with L = 100, r = 10 (FP64 both)
+        xe = W.series_1d(n=10000, L=100, r=10)["x"]
+        ctx.profile("xgram")
+        torch.cuda.synchronize()
+        tq0 = time.perf_counter()
+        dq = ctx.decompose(xe, 100, 10, method="eigen")
+        _ = dq.sigma
+        tq1 = time.perf_counter()
+        dl = ctx.decompose(xe, 100, 10)
+        _ = dl.sigma
+        tq2 = time.perf_counter()
+        pg = ctx.profile_read(["xgram"])["xgram"]
+        ctx.profile(None)
+        # the "bytes" of the xgram class count floating-point operations
+        xg_tf = pg["bytes"] / (pg["ms"] * 1e-3) / 1e12 if pg["launches"] and pg["ms"] > 0 else None
+        eigen = {"workload": "1D series N=10000, L=100, r=10, fp64", "eigen_ms": 1e3 * (tq1 - tq0),
+                 "lanczos_ms": 1e3 * (tq2 - tq1),
+                 "max_sigma_diff_over_s1": float(np.max(np.abs(dq.sigma - dl.sigma)) / dl.sigma[0]),
+                 "xgram_kernel_ms": pg["ms"] / pg["launches"] if pg["launches"] else None,
+                 "xgram_tflops": xg_tf,
+                 "xgram_mfma_frac": xg_tf / FP64_MFMA_PEAK_TFLOPS if xg_tf else None}
+        dq.free()
+        dl.free()
+        return wcor, rforecast, extend, eigen
+
+    wcor = rforecast = extend = eigen = None
+    if not args.no_extras:
+        wcor, rforecast, extend, eigen = run_extras()
 
     # plain single-instance FP64 path (same kernels, batch of one)
     single = None
