@@ -489,6 +489,32 @@ def decompose_mssa(series, L: int, method: str = "jacobi", nvec: int = -1):
     return svd(X, method, nvec=nvec)
 
 
+def trajectory_m2d(images, window, wmask=None) -> np.ndarray:
+    """M-2D-SSA trajectory matrix (the shaped-variants section, equation
+    embedding_m2dssa): the 2D-SSA trajectory matrices of the images side by
+    side, [T(X_1) : ... : T(X_s)], each with the same (shaped) window."""
+    return np.hstack([trajectory(x, shapes(x, None, wmask, window)) for x in images])
+
+
+def pack_m2d(images, window, wmask=None) -> np.ndarray:
+    """The packing of the same section: the images side by side in one
+    array (rows = the tallest image), NaN below shorter images and in the
+    separator columns between them, so that no window fits across two
+    images.  One separator column, as printed, for a full window; ly - 1
+    columns for a shaped window, which may have holes where a separator
+    would fall."""
+    lx, ly = (window, 1) if np.isscalar(window) else window
+    sep = 1 if wmask is None else max(1, ly - 1)
+    nx = max(x.shape[0] for x in images)
+    ny = sum(x.shape[1] for x in images) + sep * (len(images) - 1)
+    out = np.full((nx, ny), np.nan)
+    c = 0
+    for x in images:
+        out[:x.shape[0], c:c + x.shape[1]] = x
+        c += x.shape[1] + sep
+    return out
+
+
 def grid(sh: Shapes, vec, which: str) -> np.ndarray:
     """Place a compact vector on its (Lx, Ly) or (Kx, Ky) box, NaN elsewhere."""
     if which == "L":

@@ -713,3 +713,42 @@ def test_row_forecast_rejects_a_singular_system():
     V[0, 1] = 1.0
     with pytest.raises(ValueError):
         oracle.lrr_row(lens, L, V, [0, 1])
+
+
+# --------------------------------------------------------------------------
+# M-2D-SSA packing
+# --------------------------------------------------------------------------
+
+def _m2d_images(seed=29):
+    g = np.random.default_rng(seed)
+    sizes = [(14, 11), (12, 15), (16, 9)]
+    imgs = []
+    for nx, ny in sizes:
+        i, j = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+        imgs.append(np.cos(0.7 * i + 0.3 * j) + 0.5 * g.standard_normal((nx, ny)))
+    return imgs
+
+
+def test_m2d_packing_gives_the_stacked_trajectory_matrix():
+    """The packed array's shaped trajectory matrix has the columns of
+    [T(X_1) : ... : T(X_s)] (ordered differently): same Gram X X^T, same
+    singular values."""
+    imgs = _m2d_images()
+    for window, wmask in (((4, 3), None), ((4, 4), np.array([[1, 1, 1, 1], [1, 0, 0, 1], [1, 0, 0, 1], [1, 1, 1, 1]]))):
+        Xs = oracle.trajectory_m2d(imgs, window, wmask)
+        packed = oracle.pack_m2d(imgs, window, wmask)
+        Xp = oracle.trajectory(packed, oracle.shapes(packed, None, wmask, window))
+        assert Xp.shape == Xs.shape
+        np.testing.assert_allclose(Xp @ Xp.T, Xs @ Xs.T, rtol=0, atol=1e-10 * np.abs(Xs @ Xs.T).max())
+        s1 = np.linalg.svd(Xs, compute_uv=False)
+        s2 = np.linalg.svd(Xp, compute_uv=False)
+        np.testing.assert_allclose(s1, s2, rtol=0, atol=1e-12 * s1[0])
+
+
+def test_m2d_of_copies_scales_the_singular_values():
+    """s copies of one image: X X^T grows s times, so sigma = sqrt(s) times
+    the 2D-SSA singular values of the image."""
+    img = _m2d_images()[0]
+    s1 = np.linalg.svd(oracle.trajectory(img, oracle.shapes(img, None, None, (4, 3))), compute_uv=False)
+    s3 = np.linalg.svd(oracle.trajectory_m2d([img, img, img], (4, 3)), compute_uv=False)
+    np.testing.assert_allclose(s3[:len(s1)], np.sqrt(3.0) * s1, rtol=0, atol=1e-12 * s3[0])
