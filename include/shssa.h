@@ -134,6 +134,21 @@ int ssa_decompose_eigen(ssa_ctx* ctx, const double* x, int nx, int ny, const uin
  * 5.3: a max(len) x s array, window L x 1.  Outputs use that packing:
  * V is (max(len) - L + 1) x s with NaN beyond K_p, reconstructions
  * max(len) x s with NaN beyond len[p]. */
+/* M-2D-SSA (the shaped-variants section, equation embedding_m2dssa): one
+ * common decomposition of s images X_p (nx[p] x ny[p], row-major, NaN =
+ * missing) whose trajectory matrix is [T(X_1) : ... : T(X_s)] with the same
+ * lx x ly window (wmask as for ssa_decompose, NULL = full box).  Internally
+ * the packing of that section: the images side by side in one array of
+ * max nx rows, image p from column col_off[p] (col_off[0] = 0,
+ * col_off[p+1] = col_off[p] + ny[p] + sep), NaN below shorter images and in
+ * sep separator columns (1 for a full window, max(1, ly - 1) for a shaped
+ * one), so that no window fits across two images.  Outputs (V,
+ * reconstructions, weights) refer to the packed array; col_off (s ints,
+ * may be NULL) receives the offsets. */
+int ssa_decompose_m2d(ssa_ctx* ctx, const double* const* images, const int* nx, const int* ny, int s,
+                      const uint8_t* wmask, int lx, int ly, int r, int precision, int* col_off,
+                      ssa_decomp** out);
+
 int ssa_decompose_multi(ssa_ctx* ctx, const double* const* series, const int* len, int s, int L,
                         int r, int precision, ssa_decomp** out);
 

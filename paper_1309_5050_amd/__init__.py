@@ -91,6 +91,11 @@ class Decomposition:
         check(lib().ssa_get_stats(self._h, C.byref(st)), "ssa_get_stats")
         return {k: getattr(st, k) for k, _ in st._fields_}
 
+    def unpack(self, rec):
+        """Cut arrays over the packed M-2D-SSA array (..., nx, ny) into the
+        images: a list of (..., nx_p, ny_p) views."""
+        return [rec[..., :a, c:c + b] for a, c, b in self.m2d_layout]
+
     def extend(self, r: int):
         """Continue the decomposition to r triplets (no-op if r <= self.r)."""
         check(lib().ssa_extend(self._h, int(r)), "ssa_extend")
@@ -232,6 +237,24 @@ class Context:
         check(lib().ssa_decompose(self._h, _ptr(x), x.shape[0], x.shape[1], _ptr(mask), _ptr(wmask), lx, ly, r,
                                   _prec(precision), C.byref(h)), "ssa_decompose")
         return Decomposition(self, h.value)
+
+    def decompose_m2d(self, images, window, r: int, wmask=None, precision="fp64") -> Decomposition:
+        """M-2D-SSA of several images with one window (common basis).  The
+        handle refers to the packed array; ``unpack(rec)`` of the returned
+        handle cuts a reconstruction back into the images."""
+        arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in images]
+        ptrs = (C.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+        nx = np.array([a.shape[0] for a in arrs], np.int32)
+        ny = np.array([a.shape[1] for a in arrs], np.int32)
+        lx, ly = window
+        wm = None if wmask is None else np.ascontiguousarray(wmask, dtype=np.uint8)
+        off = np.zeros(len(arrs), np.int32)
+        h = C.c_void_p()
+        check(lib().ssa_decompose_m2d(self._h, ptrs, _ptr(nx), _ptr(ny), len(arrs), _ptr(wm), lx, ly, r,
+                                      _prec(precision), _ptr(off), C.byref(h)), "ssa_decompose_m2d")
+        d = Decomposition(self, h.value)
+        d.m2d_layout = [(int(a), int(c), int(b)) for a, b, c in zip(nx, ny, off)]   # (rows, col offset, cols)
+        return d
 
     def decompose_multi(self, series, L: int, r: int, precision="fp64") -> Decomposition:
         """MSSA of uneven series (2D packing: outputs are max N_p x s arrays)."""

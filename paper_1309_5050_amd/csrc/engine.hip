@@ -2496,6 +2496,37 @@ int ssa_decompose_multi(ssa_ctx* ctx, const double* const* series, const int* le
     return rc ? rc : st;
 }
 
+int ssa_decompose_m2d(ssa_ctx* ctx, const double* const* images, const int* nx, const int* ny, int s,
+                      const uint8_t* wmask, int lx, int ly, int r, int precision, int* col_off, ssa_decomp** out) {
+    if (!out) return fail(SSA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!images || !nx || !ny || s <= 0) return fail(SSA_EINVAL, "no images");
+    if (lx <= 0 || ly <= 0) return fail(SSA_EINVAL, "sizes must be positive");
+    // one separator column for a full window; ly - 1 for a shaped one, whose
+    // holes could otherwise let a window reach across a single column
+    const int sep = wmask ? std::max(1, ly - 1) : 1;
+    int nxmax = 0;
+    long width = (long)sep * (s - 1);
+    for (int p = 0; p < s; ++p) {
+        if (nx[p] <= 0 || ny[p] <= 0 || !images[p]) return fail(SSA_EINVAL, "empty image");
+        nxmax = std::max(nxmax, nx[p]);
+        width += ny[p];
+    }
+    if ((double)nxmax * (double)width > 2e9) return fail(SSA_EINVAL, "packed array too large");
+    std::vector<double> x((size_t)nxmax * width, std::nan(""));
+    long c = 0;
+    for (int p = 0; p < s; ++p) {
+        if (col_off) col_off[p] = (int)c;
+        for (int i = 0; i < nx[p]; ++i)
+            std::memcpy(&x[(size_t)i * width + c], images[p] + (size_t)i * ny[p], (size_t)ny[p] * sizeof(double));
+        c += ny[p] + sep;
+    }
+    ssa_request q{x.data(), nxmax, (int)width, nullptr, wmask, lx, ly, r, precision, 0x5eedULL};
+    int st = SSA_OK;
+    int rc = decompose_many(ctx, 1, &q, out, &st, false);
+    return rc ? rc : st;
+}
+
 int ssa_get_dims(const ssa_decomp* d, int* lx, int* ly, int* kx, int* ky, long* L, long* K, int* r, int* nx,
                  int* ny) {
     if (!d) return fail(SSA_EINVAL, "handle is NULL");

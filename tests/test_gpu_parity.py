@@ -734,3 +734,49 @@ def test_eigen_method_limits(ctx):
         ctx.decompose(x, (12, 12), 3, method="eigen")    # 144 cells > 128
     with pytest.raises(ValueError):
         ctx.decompose(x, (5, 5), 3, method="svd")
+
+
+def _m2d_case(seed=53):
+    g = np.random.default_rng(seed)
+    imgs = []
+    for nx, ny in [(40, 33), (36, 45), (48, 27)]:
+        i, j = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+        imgs.append(2.0 * np.cos(0.5 * i + 0.2 * j) + np.cos(0.9 * j) + 0.3 * g.standard_normal((nx, ny)))
+    return imgs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("hollow", [False, True])
+def test_m2d_matches_oracle(ctx, prec, hollow):
+    """M-2D-SSA of three images of different sizes: sigma against the SVD of
+    the stacked trajectory matrix [T(X_1) : T(X_2) : T(X_3)] (the oracle's
+    definition), reconstructions against the oracle's on its own packing."""
+    imgs = _m2d_case()
+    tol = TOL[prec]
+    window = (6, 5)
+    wmask = None
+    if hollow:
+        wmask = np.ones(window, np.uint8)
+        wmask[2:4, 1:4] = 0
+    r = 6
+    X = oracle.trajectory_m2d(imgs, window, wmask)
+    so = oracle.svd(X)[0]
+    d = ctx.decompose_m2d(imgs, window, r, wmask=wmask, precision=prec)
+    assert sigma_err(d.sigma, so) <= tol, (prec, hollow, sigma_err(d.sigma, so))
+    packed = oracle.pack_m2d(imgs, window, wmask)
+    sh, so2, Uo, Vo = oracle.decompose(packed, None, wmask, window)
+    np.testing.assert_allclose(so2[:r], so[:r], rtol=0, atol=1e-12 * so[0])
+    for k in range(1, r):
+        gap = so2[k - 1] - so2[k]
+        if gap < 1e-3 * so2[0]:
+            continue
+        g = list(range(k))
+        ref = oracle.reconstruct(sh, so2, Uo, Vo, g)
+        got = d.reconstruct([g])[0]
+        assert got.shape == packed.shape
+        assert np.array_equal(np.isnan(got), np.isnan(ref))
+        cov = ~np.isnan(ref)
+        e = np.linalg.norm(got[cov] - ref[cov]) / np.linalg.norm(np.nan_to_num(packed[cov]))
+        assert e <= C_SUB * tol * so2[0] / gap, (prec, hollow, k, e)
+    parts = d.unpack(d.reconstruct([[0, 1]]))
+    assert [p.shape[-2:] for p in parts] == [x.shape for x in imgs]
