@@ -358,6 +358,20 @@ def vforecast_column(series_lens, L: int, sigma, U, V, group, h: int):
     return out
 
 
+def esprit(U, group):
+    """LS-ESPRIT roots (the 1D parameter-estimation paragraph; the remark on
+    the fast column forecast names its shift matrix): the eigenvalues of
+    D = U_low^+ U_high, U_low the group's U without its last row, U_high
+    without its first (least squares).  A series term c rho^t cos(omega t +
+    phi) contributes the roots rho e^{+-i omega}.  Returns complex roots
+    sorted by decreasing modulus, then decreasing imaginary part."""
+    Ug = np.asarray(U, dtype=np.float64)[:, list(group)]
+    D = np.linalg.lstsq(Ug[:-1], Ug[1:], rcond=None)[0]
+    z = np.linalg.eigvals(D)
+    order = sorted(range(len(z)), key=lambda k: (-abs(z[k]), -z[k].imag))
+    return z[order]
+
+
 def _row_blocks(series_lens, L):
     """Start and end (exclusive) of each series' block of K_p = N_p - L + 1
     columns in the stacked trajectory matrix."""

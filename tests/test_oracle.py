@@ -752,3 +752,53 @@ def test_m2d_of_copies_scales_the_singular_values():
     s1 = np.linalg.svd(oracle.trajectory(img, oracle.shapes(img, None, None, (4, 3))), compute_uv=False)
     s3 = np.linalg.svd(oracle.trajectory_m2d([img, img, img], (4, 3)), compute_uv=False)
     np.testing.assert_allclose(s3[:len(s1)], np.sqrt(3.0) * s1, rtol=0, atol=1e-12 * s3[0])
+
+
+# --------------------------------------------------------------------------
+# LS-ESPRIT roots
+# --------------------------------------------------------------------------
+
+def _match_roots(a, b):
+    """Largest distance after pairing each root of a with its nearest unused root of b."""
+    b = list(b)
+    worst = 0.0
+    for z in a:
+        k = int(np.argmin([abs(z - w) for w in b]))
+        worst = max(worst, abs(z - b[k]))
+        b.pop(k)
+    return worst
+
+
+def test_esprit_recovers_damped_cosines_and_exponentials():
+    """A noiseless sum of a damped cosine, an undamped one and an
+    exponential has rank 5; the roots of the five-component group are
+    rho e^{+-i omega} of each cosine and the exponential's base."""
+    N, L = 120, 40
+    t = np.arange(N)
+    x = 2.0 * 0.98 ** t * np.cos(2 * np.pi * t / 10 + 0.3) + np.cos(2 * np.pi * t / 23) + 0.5 * 1.01 ** t
+    sh = oracle.shapes(x, None, None, L)
+    s, U, V = _lapack_svd(oracle.trajectory(x, sh))
+    z = oracle.esprit(U, [0, 1, 2, 3, 4])
+    true = [0.98 * np.exp(2j * np.pi / 10), 0.98 * np.exp(-2j * np.pi / 10), np.exp(2j * np.pi / 23),
+            np.exp(-2j * np.pi / 23), 1.01]
+    assert _match_roots(z, true) <= 1e-9
+    assert [abs(a) >= abs(b) - 1e-15 for a, b in zip(z, z[1:])] == [True] * 4
+
+
+def test_esprit_roots_do_not_depend_on_the_basis_of_the_span():
+    """The roots are the eigenvalues of the shift operator on the span: any
+    other basis of the same span (here a rotation of the group's vectors)
+    gives the same roots, a different span does not."""
+    g = np.random.default_rng(9)
+    N, L = 90, 30
+    t = np.arange(N)
+    x = np.cos(2 * np.pi * t / 7) + 0.7 * np.cos(2 * np.pi * t / 13 + 1) + 0.05 * g.standard_normal(N)
+    sh = oracle.shapes(x, None, None, L)
+    s, U, V = _lapack_svd(oracle.trajectory(x, sh))
+    Q, _ = np.linalg.qr(g.standard_normal((4, 4)))
+    U2 = U.copy()
+    U2[:, :4] = U[:, :4] @ Q
+    a, b = oracle.esprit(U, [0, 1, 2, 3]), oracle.esprit(U2, [0, 1, 2, 3])
+    assert _match_roots(a, b) <= 1e-10
+    periods = sorted(2 * np.pi / abs(np.angle(z)) for z in a if z.imag > 0)
+    np.testing.assert_allclose(periods, [7.0, 13.0], rtol=2e-2)
