@@ -270,6 +270,18 @@ int ssa_vforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int
  * (<= 64) 0-based component ids; out: nseries x h as for ssa_rforecast;
  * with out = NULL only *nseries is set.  Synchronous. */
 int ssa_rforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries);
+
+/* LS-ESPRIT parameter estimation (the 1D parameter-estimation paragraph of
+ * the 2D-SSA examples; the remark after the fast column forecast names the
+ * shift matrix) for the same decompositions as ssa_rforecast: the ng roots
+ * z_k, the eigenvalues of D = pinv(U_low) U_high of the group (U_low / U_high:
+ * its U_j without the last / first coordinate).  A term c rho^t
+ * cos(omega t + phi) of the series gives rho e^{+-i omega}: period
+ * 2 pi / |arg z|, damping |z|.  re, im: ng values each, ordered by
+ * decreasing |z|, then decreasing imaginary part.  nu^2 < 1 required
+ * (SSA_EINVAL); SSA_ENOCONV if the eigenvalue iteration fails.
+ * Synchronous. */
+int ssa_esprit(ssa_decomp* d, const int* grp, int ng, double* re, double* im);
 int ssa_vforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries);
 
 int  ssa_get_stats(const ssa_decomp* d, ssa_stats* st);

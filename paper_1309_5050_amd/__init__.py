@@ -138,6 +138,13 @@ class Decomposition:
         fn = {"column": "ssa_vforecast", "row": "ssa_vforecast_row"}[direction]
         return self._forecast(fn, group, h)
 
+    def esprit(self, group) -> np.ndarray:
+        """LS-ESPRIT roots of the group (complex, by decreasing modulus)."""
+        g = np.ascontiguousarray(group, dtype=np.int32)
+        re, im = np.zeros(len(g)), np.zeros(len(g))
+        check(lib().ssa_esprit(self._h, _ptr(g), len(g), _ptr(re), _ptr(im)), "ssa_esprit")
+        return re + 1j * im
+
     def wcor(self, groups):
         """w-correlation matrix (ngroups, ngroups) and contributions
         (ngroups,) of the reconstructed groups."""

@@ -2985,6 +2985,33 @@ int row_forecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, bool
 
 }  // namespace
 
+int ssa_esprit(ssa_decomp* d, const int* grp, int ng, double* re, double* im) {
+    if (!re || !im) return fail(SSA_EINVAL, "NULL argument");
+    int rc = check_forecast(d, grp, ng, 1, re, nullptr, "ESPRIT");
+    if (rc) return rc;
+    if ((rc = wait_handle(d))) return rc;
+    g_tables_ctx = d->ctx;
+    TableScope tables(d->ctx, d->ctx->st);
+    hipStream_t st = d->ctx->st;
+    std::vector<int> g(grp, grp + ng);
+    DevVec dg, flag, M, dre, dim;
+    if ((rc = dg.put(g, st)) || (rc = flag.put(std::vector<int>{0, 0}, st)) ||
+        (rc = M.reserve((size_t)ng * ng * sizeof(double))) || (rc = dre.reserve((size_t)ng * sizeof(double))) ||
+        (rc = dim.reserve((size_t)ng * sizeof(double))))
+        return rc;
+    launch_esprit(st, d->U, d->L, dg.as<int>(), ng, M.as<double>(), dre.as<double>(), dim.as<double>(),
+                  flag.as<int>());
+    HIPCHK(hipGetLastError());
+    int bad[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(bad, flag.p, sizeof(bad), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(re, dre.p, (size_t)ng * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(im, dim.p, (size_t)ng * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (bad[0]) return fail(SSA_EINVAL, "no ESPRIT roots: the group's last coordinates have nu^2 >= 1");
+    if (bad[1]) return fail(SSA_ENOCONV, "ESPRIT: the eigenvalue iteration did not converge");
+    return SSA_OK;
+}
+
 int ssa_rforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries) {
     int rc = check_forecast(d, grp, ng, h, out, nseries, "row forecast");
     if (rc || !out) return rc;

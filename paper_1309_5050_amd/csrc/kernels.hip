@@ -22,6 +22,7 @@
 #include "device.hpp"
 #include "fft.hpp"
 #include "regfft.hpp"
+#include "hqr.hpp"
 
 namespace shssa {
 
@@ -2272,6 +2273,61 @@ k_vforecast(const double* __restrict__ U, long L, const double* __restrict__ V, 
         }
         s = wave_sum(s);
         if (lane == 0) out[(long)a * h + t] = s / (double)L;
+    }
+}
+
+// LS-ESPRIT roots of a group: the eigenvalues of its shift matrix
+// D = (I + pi pi^T / (1 - nu^2)) M (as for the vector forecast: the
+// pseudo-inverse of the group's U without its last row times U without its
+// first), sorted by decreasing modulus, then decreasing imaginary part.
+// One wave builds D in LDS; its first lane runs the sequential eigenvalue
+// iteration (the matrix has at most 64 rows).  flag[0] = 1: nu^2 >= 1;
+// flag[1] = 1: the iteration did not converge.
+__global__ void __launch_bounds__(64)
+k_esprit(const double* __restrict__ U, long L, const int* __restrict__ grp, int ng, const double* __restrict__ M,
+         double* __restrict__ re, double* __restrict__ im, int* __restrict__ flag) {
+    constexpr int LD = kVfMaxGroup + 1;
+    __shared__ double Ds[kVfMaxGroup * LD];
+    __shared__ double pis[kVfMaxGroup], cs[kVfMaxGroup], work[kVfMaxGroup], wr[kVfMaxGroup], wi[kVfMaxGroup];
+    const int lane = threadIdx.x;
+    if (lane < ng) pis[lane] = U[(long)grp[lane] * L + (L - 1)];
+    __syncthreads();
+    double nu2 = 0.0;
+    for (int j = 0; j < ng; ++j) nu2 += pis[j] * pis[j];
+    if (!(nu2 < 1.0)) {
+        if (lane == 0) flag[0] = 1;
+        return;
+    }
+    if (lane < ng) {
+        double c = 0.0;
+        for (int i = 0; i < ng; ++i) c += pis[i] * M[i * ng + lane];
+        cs[lane] = c;
+    }
+    __syncthreads();
+    const double sc = 1.0 / (1.0 - nu2);
+    for (int e = lane; e < ng * ng; e += 64) {
+        const int i = e / ng, j = e % ng;
+        Ds[i * LD + j] = M[e] + pis[i] * cs[j] * sc;
+    }
+    __syncthreads();
+    if (lane != 0) return;
+    if (eig_real<double>(Ds, ng, LD, work, wr, wi) != 0) flag[1] = 1;
+    // order: selection by (modulus, imaginary part), work[] marks the taken
+    for (int k = 0; k < ng; ++k) work[k] = 0.0;
+    for (int p = 0; p < ng; ++p) {
+        int best = -1;
+        double bm = 0.0;
+        for (int k = 0; k < ng; ++k) {
+            if (work[k] != 0.0) continue;
+            const double mk = sqrt(wr[k] * wr[k] + wi[k] * wi[k]);
+            if (best < 0 || mk > bm || (mk == bm && wi[k] > wi[best])) {
+                best = k;
+                bm = mk;
+            }
+        }
+        work[best] = 1.0;
+        re[p] = wr[best];
+        im[p] = wi[best];
     }
 }
 

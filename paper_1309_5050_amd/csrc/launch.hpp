@@ -96,6 +96,10 @@ void launch_xgram(hipStream_t st, const double* xc, const int* offL, int L, cons
                   double* part, double* out, double* Bm);
 void launch_eig_take(int nitems, hipStream_t st, const LzDesc* lzs, const ResDesc* res, const Item* items, int L,
                      int r);
+// LS-ESPRIT roots (ng <= kVfMaxGroup) into re/im; M holds ng^2 values;
+// flag[0..1] (zeroed by the caller) as for k_esprit.
+void launch_esprit(hipStream_t st, const double* U, long L, const int* grp, int ng, double* M, double* re,
+                   double* im, int* flag);
 void launch_wgram(hipStream_t st, const double* const* arr, int narr, const double* W, long ncell, int nchunk,
                   double* part, double* out);
 void launch_transpose(int nmat, int R, int C, hipStream_t st, const double* in, double* out);

@@ -780,3 +780,59 @@ def test_m2d_matches_oracle(ctx, prec, hollow):
         assert e <= C_SUB * tol * so2[0] / gap, (prec, hollow, k, e)
     parts = d.unpack(d.reconstruct([[0, 1]]))
     assert [p.shape[-2:] for p in parts] == [x.shape for x in imgs]
+
+
+def _nearest_match(a, b):
+    b = list(b)
+    worst = 0.0
+    for z in a:
+        k = int(np.argmin([abs(z - w) for w in b]))
+        worst = max(worst, abs(z - b[k]))
+        b.pop(k)
+    return worst
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,group", [("series_1000", [0, 1, 2, 3, 4, 5]), ("mssa_8", [0, 1, 2, 3])])
+def test_esprit_parity(ctx, name, group, prec):
+    """LS-ESPRIT roots from the GPU decomposition against the oracle's roots
+    of its own triplets, within the bound on the group's span, 20 tol s_1 /
+    gap (the roots of these well-conditioned shift matrices move no more
+    than their span)."""
+    w = CASES[name]()
+    tol = TOL[prec]
+    sh, so, Uo, Vo = oracle_case(name, w)
+    ref = oracle.esprit(Uo, group)
+    d = gpu_case(ctx, w, prec)
+    got = d.esprit(group)
+    assert got.shape == ref.shape
+    gap = so[group[-1]] - so[group[-1] + 1]
+    err = _nearest_match(got, ref)
+    bound = 20 * tol * so[0] / gap
+    print(f"{name} {prec}: ESPRIT root error {err:.3e} bound {bound:.3e}")
+    assert err <= bound, (name, prec, err, bound)
+    mods = np.abs(got)
+    assert np.all(mods[:-1] >= mods[1:] - 1e-15)
+
+
+def test_esprit_recovers_damped_cosines(ctx):
+    N, L = 240, 80
+    t = np.arange(N)
+    x = 2.0 * 0.99 ** t * np.cos(2 * np.pi * t / 10 + 0.3) + np.cos(2 * np.pi * t / 23) + 0.5 * 1.005 ** t
+    d = ctx.decompose(x, L, 5)
+    z = d.esprit([0, 1, 2, 3, 4])
+    true = [0.99 * np.exp(2j * np.pi / 10), 0.99 * np.exp(-2j * np.pi / 10), np.exp(2j * np.pi / 23),
+            np.exp(-2j * np.pi / 23), 1.005]
+    assert _nearest_match(z, true) <= 1e-8
+
+
+def test_esprit_errors(ctx):
+    import paper_1309_5050_amd as S
+    x = np.random.default_rng(3).standard_normal((30, 30))
+    d = ctx.decompose(x, (5, 5), 3)
+    with pytest.raises(S.SsaError):
+        d.esprit([0, 1])               # a 2D window
+    y = np.random.default_rng(4).standard_normal(200)
+    e = ctx.decompose(y, 50, 3)
+    with pytest.raises(S.SsaError):
+        e.esprit([0, 7])               # component beyond r
