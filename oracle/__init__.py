@@ -372,6 +372,37 @@ def esprit(U, group):
     return z[order]
 
 
+ESPRIT2D_GAMMA = 0.6180339887498949   # weight of the y shift in the combination whose eigenvectors pair the roots
+
+
+def esprit2d(sh: Shapes, U, group, gamma: float = ESPRIT2D_GAMMA):
+    """2D-ESPRIT (the parameter-estimation subsection of the 2D-SSA
+    examples: a pair of shift matrices for the x and y directions and their
+    joint diagonalisation).  For the window cells c whose neighbour one step
+    down (x) is also in the window, Phi_x = U_a^+ U_b with U_a the group's U
+    on those cells and U_b on their neighbours (least squares); Phi_y the
+    same for the neighbour one step right.  The eigenvectors T of
+    Phi_x + gamma Phi_y diagonalise both (they commute for a signal of
+    finite rank); lambda_k and mu_k are the diagonals of T^-1 Phi_x T and
+    T^-1 Phi_y T.  A term rho^m tau^n cos(2 pi (m f + n g) + phi) gives the
+    pairs (rho e^{+-2 pi i f}, tau e^{+-2 pi i g}).  Returns (lambda, mu)
+    sorted by decreasing |lambda|, then decreasing Im lambda."""
+    Ug = np.asarray(U, dtype=np.float64)[:, list(group)]
+    pos = {(int(a), int(b)): c for c, (a, b) in enumerate(zip(sh.li, sh.lj))}
+    phis = []
+    for da, db in ((1, 0), (0, 1)):
+        src = [c for (a, b), c in pos.items() if (a + da, b + db) in pos]
+        dst = [pos[(int(sh.li[c]) + da, int(sh.lj[c]) + db)] for c in src]
+        phis.append(np.linalg.lstsq(Ug[src], Ug[dst], rcond=None)[0])
+    px, py = phis
+    _, T = np.linalg.eig(px + gamma * py)
+    Ti = np.linalg.inv(T)
+    lam = np.diag(Ti @ px @ T)
+    mu = np.diag(Ti @ py @ T)
+    order = sorted(range(len(lam)), key=lambda k: (-abs(lam[k]), -lam[k].imag))
+    return lam[order], mu[order]
+
+
 def _row_blocks(series_lens, L):
     """Start and end (exclusive) of each series' block of K_p = N_p - L + 1
     columns in the stacked trajectory matrix."""

@@ -802,3 +802,48 @@ def test_esprit_roots_do_not_depend_on_the_basis_of_the_span():
     assert _match_roots(a, b) <= 1e-10
     periods = sorted(2 * np.pi / abs(np.angle(z)) for z in a if z.imag > 0)
     np.testing.assert_allclose(periods, [7.0, 13.0], rtol=2e-2)
+
+
+def _pairs_match(l1, m1, l2, m2):
+    """Largest distance after pairing each (lambda, mu) of one set with its nearest unused pair of the other."""
+    b = list(zip(l2, m2))
+    worst = 0.0
+    for a in zip(l1, m1):
+        d = [max(abs(a[0] - c[0]), abs(a[1] - c[1])) for c in b]
+        k = int(np.argmin(d))
+        worst = max(worst, d[k])
+        b.pop(k)
+    return worst
+
+
+def test_esprit2d_recovers_planar_waves():
+    """A noiseless sum of two planar cosines, one of them damped in both
+    directions, has rank 4; the pairs of the group's joint eigenvalues are
+    (rho e^{+-2 pi i f}, tau e^{+-2 pi i g}) of each term, also for a
+    window with a hole."""
+    nx, ny = 40, 36
+    m, n = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    f1, g1, f2, g2 = 0.11, 0.07, 0.04, 0.19
+    x = np.cos(2 * np.pi * (f1 * m + g1 * n) + 0.4) + 0.97 ** m * 0.99 ** n * 2 * np.cos(2 * np.pi * (f2 * m + g2 * n))
+    true_l = [np.exp(2j * np.pi * f1), np.exp(-2j * np.pi * f1), 0.97 * np.exp(2j * np.pi * f2), 0.97 * np.exp(-2j * np.pi * f2)]
+    true_m = [np.exp(2j * np.pi * g1), np.exp(-2j * np.pi * g1), 0.99 * np.exp(2j * np.pi * g2), 0.99 * np.exp(-2j * np.pi * g2)]
+    wm = np.ones((8, 7), np.uint8)
+    wm[3:5, 2:4] = 0
+    for window, wmask in (((8, 7), None), ((8, 7), wm)):
+        sh = oracle.shapes(x, None, wmask, window)
+        s, U, V = _lapack_svd(oracle.trajectory(x, sh))
+        lam, mu = oracle.esprit2d(sh, U, [0, 1, 2, 3])
+        assert _pairs_match(lam, mu, true_l, true_m) <= 1e-9
+
+
+def test_esprit2d_pairs_do_not_depend_on_the_combination_weight():
+    """For a signal of finite rank the shift matrices commute, so any
+    combination weight gives the same pairs."""
+    nx, ny = 30, 30
+    m, n = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    x = np.cos(2 * np.pi * (0.13 * m + 0.05 * n)) + 0.5 * np.cos(2 * np.pi * (0.03 * m - 0.21 * n) + 1.0)
+    sh = oracle.shapes(x, None, None, (6, 6))
+    s, U, V = _lapack_svd(oracle.trajectory(x, sh))
+    a = oracle.esprit2d(sh, U, [0, 1, 2, 3])
+    b = oracle.esprit2d(sh, U, [0, 1, 2, 3], gamma=2.3)
+    assert _pairs_match(a[0], a[1], b[0], b[1]) <= 1e-9
