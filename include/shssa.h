@@ -282,6 +282,21 @@ int ssa_rforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out,
  * (SSA_EINVAL); SSA_ENOCONV if the eigenvalue iteration fails.
  * Synchronous. */
 int ssa_esprit(ssa_decomp* d, const int* grp, int ng, double* re, double* im);
+
+/* 2D-ESPRIT (the parameter-estimation subsection of the 2D-SSA examples:
+ * shift matrices for the x and y directions and their joint
+ * diagonalisation) for a decomposition whose window is at least 2 x 2.  For
+ * the window cells whose neighbour one step down (x) is also in the window,
+ * Phi_x = pinv(U_a) U_b, U_a the group's U on those cells and U_b on the
+ * neighbours; Phi_y the same one step right.  The eigenvectors of
+ * Phi_x + gamma Phi_y (gamma = 0.618...) pair the roots: lambda_k =
+ * t_k^H Phi_x t_k, mu_k = t_k^H Phi_y t_k for unit eigenvectors t_k.  A
+ * term rho^m tau^n cos(2 pi (m f + n g) + phi) gives the pairs
+ * (rho e^{+-2 pi i f}, tau e^{+-2 pi i g}).  lre, lim, mre, mim: ng values
+ * each, ordered by decreasing |lambda|, then decreasing Im lambda.
+ * SSA_EINVAL for a 1D window or a singular shift equation, SSA_ENOCONV if
+ * the eigenvalue iteration fails.  Synchronous. */
+int ssa_esprit2d(ssa_decomp* d, const int* grp, int ng, double* lre, double* lim, double* mre, double* mim);
 int ssa_vforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries);
 
 int  ssa_get_stats(const ssa_decomp* d, ssa_stats* st);

@@ -145,6 +145,13 @@ class Decomposition:
         check(lib().ssa_esprit(self._h, _ptr(g), len(g), _ptr(re), _ptr(im)), "ssa_esprit")
         return re + 1j * im
 
+    def esprit2d(self, group):
+        """2D-ESPRIT pairs of the group: (lambda, mu) complex arrays (x and y roots)."""
+        g = np.ascontiguousarray(group, dtype=np.int32)
+        a, b, c, e = (np.zeros(len(g)) for _ in range(4))
+        check(lib().ssa_esprit2d(self._h, _ptr(g), len(g), _ptr(a), _ptr(b), _ptr(c), _ptr(e)), "ssa_esprit2d")
+        return a + 1j * b, c + 1j * e
+
     def wcor(self, groups):
         """w-correlation matrix (ngroups, ngroups) and contributions
         (ngroups,) of the reconstructed groups."""

@@ -105,6 +105,12 @@ constexpr int kStepDev = -1;
 // the carried coefficient vectors).
 constexpr int kVfMaxGroup = 64;
 
+// Weight of the y shift matrix in the combination whose eigenvectors pair
+// the x and y roots of 2D-ESPRIT (any weight works when the shift matrices
+// commute; an irrational one avoids chance coincidences of the combined
+// eigenvalues).
+constexpr double kEsprit2dGamma = 0.6180339887498949;
+
 enum RowDest : int {
     DEST_T1 = 0,      // scratch slot `comp` of T1
     DEST_XH = 1,      // spectrum rows (row family), times the spectrum scale

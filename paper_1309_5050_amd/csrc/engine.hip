@@ -3012,6 +3012,80 @@ int ssa_esprit(ssa_decomp* d, const int* grp, int ng, double* re, double* im) {
     return SSA_OK;
 }
 
+int ssa_esprit2d(ssa_decomp* d, const int* grp, int ng, double* lre, double* lim, double* mre, double* mim) {
+    if (!d || !grp || !lre || !lim || !mre || !mim) return fail(SSA_EINVAL, "NULL argument");
+    if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
+    if (d->rowfam || d->LA < 2 || d->LB < 2) return fail(SSA_EINVAL, "2D-ESPRIT needs a window at least 2 x 2");
+    if (ng < 1 || ng > kVfMaxGroup) return fail(SSA_EINVAL, "group of 1..64 components");
+    for (int k = 0; k < ng; ++k)
+        if (grp[k] < 0 || grp[k] >= d->r) return fail(SSA_EINVAL, "component id out of range");
+    int rc;
+    if ((rc = wait_handle(d))) return rc;
+    // index pairs in the window's compact order (row-major over its box):
+    // per axis the cells whose neighbour one step along it is in the window
+    // (with that neighbour), then the cells without such a neighbour
+    const int LA = d->LA, LB = d->LB;
+    std::vector<int> idx((size_t)LA * LB, -1);
+    int c = 0;
+    for (int a = 0; a < LA; ++a)
+        for (int b = 0; b < LB; ++b)
+            if (d->lmask_h[(size_t)a * LB + b]) idx[(size_t)a * LB + b] = c++;
+    std::vector<int> lists[4][2];
+    for (int ax = 0; ax < 2; ++ax)
+        for (int a = 0; a < LA; ++a)
+            for (int b = 0; b < LB; ++b) {
+                const int i = idx[(size_t)a * LB + b];
+                if (i < 0) continue;
+                const int a2 = a + (ax == 0), b2 = b + (ax == 1);
+                const int j = (a2 < LA && b2 < LB) ? idx[(size_t)a2 * LB + b2] : -1;
+                if (j >= 0) {
+                    lists[2 * ax][0].push_back(i);
+                    lists[2 * ax][1].push_back(j);
+                } else {
+                    lists[2 * ax + 1][0].push_back(i);
+                    lists[2 * ax + 1][1].push_back(i);
+                }
+            }
+    if (lists[0][0].empty() || lists[2][0].empty()) return fail(SSA_EINVAL, "window has no neighbouring cells");
+    g_tables_ctx = d->ctx;
+    TableScope tables(d->ctx, d->ctx->st);
+    hipStream_t st = d->ctx->st;
+    std::vector<int> g(grp, grp + ng);
+    DevVec dg, flag, dl[4][2], ptrs, gram, T, phi, G, scr, out;
+    const size_t nn = (size_t)ng * ng;
+    if ((rc = dg.put(g, st)) || (rc = flag.put(std::vector<int>{0, 0, 0}, st))) return rc;
+    for (int q = 0; q < 4; ++q)
+        for (int h = 0; h < 2; ++h)
+            if ((rc = dl[q][h].put(lists[q][h], st))) return rc;
+    if ((rc = gram.reserve(2 * nn * sizeof(double))) || (rc = T.reserve(3 * nn * sizeof(double))) ||
+        (rc = phi.reserve(2 * nn * sizeof(double))) || (rc = G.reserve(nn * sizeof(double))) ||
+        (rc = scr.reserve((3 * nn + 14 * (size_t)ng) * sizeof(double))) ||
+        (rc = out.reserve(4 * (size_t)ng * sizeof(double))))
+        return rc;
+    const int* pa[4] = {dl[0][0].as<int>(), dl[1][0].as<int>(), dl[2][0].as<int>(), dl[3][0].as<int>()};
+    const int* pb[4] = {dl[0][1].as<int>(), dl[1][1].as<int>(), dl[2][1].as<int>(), dl[3][1].as<int>()};
+    const int np[4] = {(int)lists[0][0].size(), (int)lists[1][0].size(), (int)lists[2][0].size(),
+                       (int)lists[3][0].size()};
+    launch_esprit2d(st, d->U, d->L, dg.as<int>(), ng, pa, pb, np, gram.as<double>(), T.as<double>(),
+                    phi.as<double>(), G.as<double>(), kEsprit2dGamma, scr.as<double>(), out.as<double>(),
+                    flag.as<int>());
+    HIPCHK(hipGetLastError());
+    int bad[3] = {0, 0, 0};
+    std::vector<double> h(4 * (size_t)ng);
+    HIPCHK(hipMemcpyAsync(bad, flag.p, sizeof(bad), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h.data(), out.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (bad[1]) return fail(SSA_EINVAL, "2D-ESPRIT: a shift equation is singular for the group");
+    if (bad[2]) return fail(SSA_ENOCONV, "2D-ESPRIT: the eigenvalue iteration did not converge");
+    for (int k = 0; k < ng; ++k) {
+        lre[k] = h[k];
+        lim[k] = h[ng + k];
+        mre[k] = h[2 * ng + k];
+        mim[k] = h[3 * ng + k];
+    }
+    return SSA_OK;
+}
+
 int ssa_rforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries) {
     int rc = check_forecast(d, grp, ng, h, out, nseries, "row forecast");
     if (rc || !out) return rc;

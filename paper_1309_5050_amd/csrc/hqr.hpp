@@ -154,4 +154,147 @@ __host__ __device__ inline int eig_real(Real* a, int n, int lda, Real* work, Rea
     return 0;
 }
 
+// Joint eigenvalues of two real n x n matrices px and py (row-major,
+// leading dimension ld) that commute up to noise, as a joint
+// diagonalisation: with C = px + gamma py = T diag(z) T^-1, lambda_k =
+// (T^-1 px T)_kk and mu_k = (T^-1 py T)_kk.  Column k of T is a right
+// eigenvector t_k of C and row k of T^-1 a left eigenvector w_k (C^T w_k =
+// z_k w_k) scaled to w_k^T t_k = 1, so lambda_k = w_k^T px t_k / w_k^T t_k.
+// Both come from two steps of inverse iteration at each eigenvalue of C
+// (complex Gaussian elimination with partial pivoting on C - z I and on
+// C^T - z I; the shift is moved off the eigenvalue by a rounding-level
+// amount so that the systems stay solvable).  Scratch: c (n * ld), work
+// (n), piv (n), lu (2 n n), v, y and t (2 n each).  Returns 0, or -1 if C's
+// eigenvalue iteration failed.
+template <typename Real>
+__host__ __device__ inline int joint_eig(const Real* px, const Real* py, int n, int ld, Real gamma, Real* c,
+                                         Real* work, int* piv, Real* lu, Real* v, Real* y, Real* t, Real* wr,
+                                         Real* wi, Real* lre, Real* lim, Real* mre, Real* mim) {
+    Real cnorm = 0;
+    for (int i = 0; i < n; ++i) {
+        Real rs = 0;
+        for (int j = 0; j < n; ++j) {
+            c[i * ld + j] = px[i * ld + j] + gamma * py[i * ld + j];
+            rs += std::fabs(c[i * ld + j]);
+        }
+        cnorm = rs > cnorm ? rs : cnorm;
+    }
+    if (eig_real(c, n, ld, work, wr, wi) != 0) return -1;
+    const Real eps = sizeof(Real) == 8 ? Real(2.220446049250313e-16) : Real(1.1920929e-7);
+    const Real tiny = (cnorm > 0 ? cnorm : Real(1)) * eps;
+    const auto LR = [&](int i, int j) -> Real& { return lu[2 * (i * n + j)]; };
+    const auto LI = [&](int i, int j) -> Real& { return lu[2 * (i * n + j) + 1]; };
+    const auto C = [&](int i, int j) -> Real { return px[i * ld + j] + gamma * py[i * ld + j]; };
+    // v <- unit vector in the null direction of (C or C^T) - (zr + i zi) I
+    const auto inverse_iteration = [&](bool transposed, Real zr, Real zi) {
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                LR(i, j) = (transposed ? C(j, i) : C(i, j)) - (i == j ? zr : Real(0));
+                LI(i, j) = i == j ? -zi : Real(0);
+            }
+        for (int p = 0; p < n; ++p) {
+            int best = p;
+            Real bm = -1;
+            for (int i = p; i < n; ++i) {
+                const Real m = std::fabs(LR(i, p)) + std::fabs(LI(i, p));
+                if (m > bm) {
+                    bm = m;
+                    best = i;
+                }
+            }
+            piv[p] = best;
+            if (best != p)
+                for (int j = 0; j < n; ++j) {
+                    const Real tr = LR(p, j), ti = LI(p, j);
+                    LR(p, j) = LR(best, j);
+                    LI(p, j) = LI(best, j);
+                    LR(best, j) = tr;
+                    LI(best, j) = ti;
+                }
+            if (std::fabs(LR(p, p)) + std::fabs(LI(p, p)) == 0) LR(p, p) = tiny;
+            const Real dr = LR(p, p), di = LI(p, p), dd = dr * dr + di * di;
+            for (int i = p + 1; i < n; ++i) {
+                const Real fr = (LR(i, p) * dr + LI(i, p) * di) / dd;
+                const Real fi = (LI(i, p) * dr - LR(i, p) * di) / dd;
+                LR(i, p) = fr;
+                LI(i, p) = fi;
+                for (int j = p + 1; j < n; ++j) {
+                    LR(i, j) -= fr * LR(p, j) - fi * LI(p, j);
+                    LI(i, j) -= fr * LI(p, j) + fi * LR(p, j);
+                }
+            }
+        }
+        for (int i = 0; i < n; ++i) {
+            v[2 * i] = 1;
+            v[2 * i + 1] = 0;
+        }
+        for (int it = 0; it < 2; ++it) {
+            for (int i = 0; i < 2 * n; ++i) y[i] = v[i];
+            for (int p = 0; p < n; ++p)
+                if (piv[p] != p) {
+                    const int q = piv[p];
+                    const Real tr = y[2 * p], ti = y[2 * p + 1];
+                    y[2 * p] = y[2 * q];
+                    y[2 * p + 1] = y[2 * q + 1];
+                    y[2 * q] = tr;
+                    y[2 * q + 1] = ti;
+                }
+            for (int i = 1; i < n; ++i)
+                for (int j = 0; j < i; ++j) {
+                    y[2 * i] -= LR(i, j) * y[2 * j] - LI(i, j) * y[2 * j + 1];
+                    y[2 * i + 1] -= LR(i, j) * y[2 * j + 1] + LI(i, j) * y[2 * j];
+                }
+            for (int i = n - 1; i >= 0; --i) {
+                Real sr = y[2 * i], si = y[2 * i + 1];
+                for (int j = i + 1; j < n; ++j) {
+                    sr -= LR(i, j) * y[2 * j] - LI(i, j) * y[2 * j + 1];
+                    si -= LR(i, j) * y[2 * j + 1] + LI(i, j) * y[2 * j];
+                }
+                const Real dr = LR(i, i), di = LI(i, i), dd = dr * dr + di * di;
+                y[2 * i] = (sr * dr + si * di) / dd;
+                y[2 * i + 1] = (si * dr - sr * di) / dd;
+            }
+            Real mx = 0;
+            for (int i = 0; i < 2 * n; ++i) mx = std::fabs(y[i]) > mx ? std::fabs(y[i]) : mx;
+            if (mx == 0) mx = 1;
+            Real nn = 0;
+            for (int i = 0; i < 2 * n; ++i) {
+                v[i] = y[i] / mx;
+                nn += v[i] * v[i];
+            }
+            nn = std::sqrt(nn);
+            for (int i = 0; i < 2 * n; ++i) v[i] /= nn;
+        }
+    };
+    for (int k = 0; k < n; ++k) {
+        inverse_iteration(false, wr[k] + tiny, wi[k]);
+        for (int i = 0; i < 2 * n; ++i) t[i] = v[i];
+        inverse_iteration(true, wr[k] + tiny, wi[k]);   // v = w_k
+        // w^T t, w^T px t and w^T py t (no conjugation: rows of T^-1)
+        Real sr = 0, si = 0, ar = 0, ai = 0, br = 0, bi = 0;
+        for (int i = 0; i < n; ++i) {
+            Real xr = 0, xi = 0, qr = 0, qi = 0;
+            for (int j = 0; j < n; ++j) {
+                xr += px[i * ld + j] * t[2 * j];
+                xi += px[i * ld + j] * t[2 * j + 1];
+                qr += py[i * ld + j] * t[2 * j];
+                qi += py[i * ld + j] * t[2 * j + 1];
+            }
+            const Real wr_ = v[2 * i], wi_ = v[2 * i + 1];
+            sr += wr_ * t[2 * i] - wi_ * t[2 * i + 1];
+            si += wr_ * t[2 * i + 1] + wi_ * t[2 * i];
+            ar += wr_ * xr - wi_ * xi;
+            ai += wr_ * xi + wi_ * xr;
+            br += wr_ * qr - wi_ * qi;
+            bi += wr_ * qi + wi_ * qr;
+        }
+        const Real dd = sr * sr + si * si;
+        lre[k] = (ar * sr + ai * si) / dd;
+        lim[k] = (ai * sr - ar * si) / dd;
+        mre[k] = (br * sr + bi * si) / dd;
+        mim[k] = (bi * sr - br * si) / dd;
+    }
+    return 0;
+}
+
 }  // namespace shssa

@@ -2331,6 +2331,70 @@ k_esprit(const double* __restrict__ U, long L, const int* __restrict__ grp, int 
     }
 }
 
+// 2D-ESPRIT, Gram terms over index pairs: out[i * ng + j] = sum_p
+// U_{g_i}[pa[p]] U_{g_j}[pb[p]] (window cells and their neighbours one step
+// along an axis, or the cells without one paired with themselves).  One
+// wave per entry.
+__global__ void __launch_bounds__(256)
+k_pairgram(const double* __restrict__ U, long L, const int* __restrict__ grp, int ng, const int* __restrict__ pa,
+           const int* __restrict__ pb, int np, double* __restrict__ out) {
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= ng * ng) return;   // whole waves
+    const double* ui = U + (long)grp[e / ng] * L;
+    const double* uj = U + (long)grp[e % ng] * L;
+    double s = 0.0;
+    for (int p = lane_id(); p < np; p += 64) s += ui[pa[p]] * uj[pb[p]];
+    s = wave_sum(s);
+    if (lane_id() == 0) out[e] = s;
+}
+
+// 2D-ESPRIT pairing: the joint eigenvalues (lambda_k, mu_k) of the x and y
+// shift matrices px, py (ng x ng, leading dimension ng), through the
+// eigenvectors of px + gamma py, ordered by decreasing |lambda|, then
+// decreasing Im lambda.  One thread (the matrices have at most 64 rows);
+// scr: scratch of 3 ng^2 + 14 ng values.  flag[2] = 1: the eigenvalue
+// iteration failed.
+__global__ void __launch_bounds__(64)
+k_esprit2d(const double* __restrict__ px, const double* __restrict__ py, int ng, double gamma,
+           double* __restrict__ scr, double* __restrict__ out, int* __restrict__ flag) {
+    if (threadIdx.x != 0) return;
+    double* c = scr;
+    double* lu = c + ng * ng;
+    double* work = lu + 2 * ng * ng;
+    double* v = work + ng;
+    double* y = v + 2 * ng;
+    double* t = y + 2 * ng;
+    double* wr = t + 2 * ng;
+    double* wi = wr + ng;
+    double* lre = wi + ng;
+    double* lim = lre + ng;
+    double* mre = lim + ng;
+    double* mim = mre + ng;
+    int* piv = reinterpret_cast<int*>(mim + ng);
+    if (joint_eig<double>(px, py, ng, ng, gamma, c, work, piv, lu, v, y, t, wr, wi, lre, lim, mre, mim) != 0) {
+        flag[2] = 1;
+        return;
+    }
+    for (int k = 0; k < ng; ++k) work[k] = 0.0;
+    for (int p = 0; p < ng; ++p) {
+        int best = -1;
+        double bm = 0.0;
+        for (int k = 0; k < ng; ++k) {
+            if (work[k] != 0.0) continue;
+            const double mk = sqrt(lre[k] * lre[k] + lim[k] * lim[k]);
+            if (best < 0 || mk > bm || (mk == bm && lim[k] > lim[best])) {
+                best = k;
+                bm = mk;
+            }
+        }
+        work[best] = 1.0;
+        out[p] = lre[best];
+        out[ng + p] = lim[best];
+        out[2 * ng + p] = mre[best];
+        out[3 * ng + p] = mim[best];
+    }
+}
+
 // ---- row forecasts (MSSA): V's blocks are the series' origin rows ------
 
 // Row forecasts need every series' origin set to be a prefix [0, K_p) of

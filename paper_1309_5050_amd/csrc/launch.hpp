@@ -100,6 +100,15 @@ void launch_eig_take(int nitems, hipStream_t st, const LzDesc* lzs, const ResDes
 // flag[0..1] (zeroed by the caller) as for k_esprit.
 void launch_esprit(hipStream_t st, const double* U, long L, const int* grp, int ng, double* M, double* re,
                    double* im, int* flag);
+// 2D-ESPRIT: for each axis the Gram terms over the index pairs (pa[2 ax],
+// pb[2 ax]: cells and their neighbour; pa/pb[2 ax + 1]: the cells without
+// one, with themselves) give phi_ax = (I - S^T S)^{-1} M; then the joint
+// eigenvalues into out (lambda re, lambda im, mu re, mu im; ng each).
+// gram: 2 ng^2, T: 3 ng^2, phi: 2 ng^2, G: ng^2, scr: 3 ng^2 + 14 ng values;
+// flag[1]: singular system, flag[2]: eigenvalue iteration failed.
+void launch_esprit2d(hipStream_t st, const double* U, long L, const int* grp, int ng, const int* const* pa,
+                     const int* const* pb, const int* np, double* gram, double* T, double* phi, double* G,
+                     double gamma, double* scr, double* out, int* flag);
 void launch_wgram(hipStream_t st, const double* const* arr, int narr, const double* W, long ncell, int nchunk,
                   double* part, double* out);
 void launch_transpose(int nmat, int R, int C, hipStream_t st, const double* in, double* out);

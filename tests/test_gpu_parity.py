@@ -836,3 +836,73 @@ def test_esprit_errors(ctx):
     e = ctx.decompose(y, 50, 3)
     with pytest.raises(S.SsaError):
         e.esprit([0, 7])               # component beyond r
+
+
+def _pairs_nearest(l1, m1, l2, m2):
+    b = list(zip(l2, m2))
+    worst = 0.0
+    for a in zip(l1, m1):
+        d = [max(abs(a[0] - c[0]), abs(a[1] - c[1])) for c in b]
+        k = int(np.argmin(d))
+        worst = max(worst, d[k])
+        b.pop(k)
+    return worst
+
+
+def _planar_waves(noise, seed=2):
+    nx, ny = 40, 36
+    m, n = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    x = (np.cos(2 * np.pi * (0.11 * m + 0.07 * n) + 0.4)
+         + 0.97 ** m * 0.99 ** n * 2 * np.cos(2 * np.pi * (0.04 * m + 0.19 * n)))
+    return x + noise * np.random.default_rng(seed).standard_normal((nx, ny))
+
+
+def _hollow_window():
+    wm = np.ones((8, 7), np.uint8)
+    wm[3:5, 2:4] = 0
+    return wm
+
+
+@pytest.mark.parametrize("hollow", [False, True])
+def test_esprit2d_recovers_planar_waves(ctx, hollow):
+    x = _planar_waves(0.0)
+    wm = _hollow_window() if hollow else None
+    d = ctx.decompose(x, (8, 7), 4, wmask=wm)
+    lam, mu = d.esprit2d([0, 1, 2, 3])
+    true_l = [np.exp(2j * np.pi * 0.11), np.exp(-2j * np.pi * 0.11), 0.97 * np.exp(2j * np.pi * 0.04),
+              0.97 * np.exp(-2j * np.pi * 0.04)]
+    true_m = [np.exp(2j * np.pi * 0.07), np.exp(-2j * np.pi * 0.07), 0.99 * np.exp(2j * np.pi * 0.19),
+              0.99 * np.exp(-2j * np.pi * 0.19)]
+    assert _pairs_nearest(lam, mu, true_l, true_m) <= 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("hollow", [False, True])
+def test_esprit2d_parity(ctx, prec, hollow):
+    """2D-ESPRIT pairs from the GPU decomposition of a noisy image against
+    the oracle's pairs of its own triplets, within the bound on the group's
+    span, 20 tol s_1 / gap."""
+    x = _planar_waves(0.05)
+    wm = _hollow_window() if hollow else None
+    tol = TOL[prec]
+    sh, so, Uo, Vo = oracle.decompose(x, None, wm, (8, 7))
+    lam_o, mu_o = oracle.esprit2d(sh, Uo, [0, 1, 2, 3])
+    d = ctx.decompose(x, (8, 7), 6, wmask=wm, precision=prec)
+    lam, mu = d.esprit2d([0, 1, 2, 3])
+    gap = so[3] - so[4]
+    err = _pairs_nearest(lam, mu, lam_o, mu_o)
+    bound = 20 * tol * so[0] / gap
+    print(f"hollow={hollow} {prec}: 2D-ESPRIT pair error {err:.3e} bound {bound:.3e}")
+    assert err <= bound, (hollow, prec, err, bound)
+
+
+def test_esprit2d_errors(ctx):
+    import paper_1309_5050_amd as S
+    y = np.random.default_rng(4).standard_normal(200)
+    e = ctx.decompose(y, 50, 3)
+    with pytest.raises(S.SsaError):
+        e.esprit2d([0, 1])             # a 1D window
+    x = _planar_waves(0.05)
+    d = ctx.decompose(x, (8, 7), 4)
+    with pytest.raises(S.SsaError):
+        d.esprit2d([0, 9])             # component beyond r
