@@ -46,6 +46,8 @@ struct LzDesc {
     long n;             // short vector length
     long nl;            // long vector length
     double* Q;          // short basis n x (kMaxBasis+1), column-major (ld n)
+    float* Q32;         // FP32 copy of Q that the reorthogonalisation reads (instances with
+                        // FP32 products: half the basis traffic; nullptr otherwise)
     double* w;          // short work vector
     double* sin;        // modified input vector of the first step after a restart
     double* hp1;        // partial projections, nblk x (kMaxBasis+1)

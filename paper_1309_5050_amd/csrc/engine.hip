@@ -437,6 +437,7 @@ struct ssa_decomp {
     double *Q = nullptr, *w = nullptr, *sinv = nullptr, *hp1 = nullptr, *hp2 = nullptr, *np = nullptr, *np0 = nullptr;
     double *lnp = nullptr, *gam = nullptr, *Bm = nullptr, *Yl = nullptr, *Yr = nullptr, *sig = nullptr, *beta = nullptr;
     double* Qtmp = nullptr;
+    float* Q32 = nullptr;            // FP32 copy of Q for the reorthogonalisation (FP32 products)
     void* lbuf = nullptr;
     int *perm = nullptr, *flag = nullptr;
     double *U = nullptr, *V = nullptr, *sigma = nullptr;
@@ -1165,7 +1166,8 @@ int run_alloc_spectrum(Batch& b) {
             (rc = d->dalloc(&d->sig, kMaxBasis)) || (rc = d->dalloc(&d->beta, 4)) ||
             (rc = d->dalloc(&d->perm, kMaxBasis)) || (rc = d->dalloc(&d->flag, 4)) ||
             (rc = d->dalloc(&d->Qtmp, n * kMaxBasis)) || (rc = d->dalloc(&d->U, d->L * (long)d->r)) ||
-            (rc = d->dalloc(&d->V, d->K * (long)d->r)) || (rc = d->dalloc(&d->sigma, d->r)))
+            (rc = d->dalloc(&d->V, d->K * (long)d->r)) || (rc = d->dalloc(&d->sigma, d->r)) ||
+            (!d->f64 && (rc = d->dalloc(&d->Q32, n * (kMaxBasis + 1)))))
             return rc;
         // descriptors
         OpDesc& o = d->op;
@@ -1199,6 +1201,7 @@ int run_alloc_spectrum(Batch& b) {
         z.lrows = (int)longrows;
         z.Bm = d->Bm; z.Yl = d->Yl; z.Yr = d->Yr; z.sig = d->sig; z.perm = d->perm;
         z.beta = d->beta; z.flag = d->flag; z.Qtmp = d->Qtmp;
+        z.Q32 = d->f64 ? nullptr : d->Q32;
         z.nblk = nblk;
         ResDesc& s = d->rs;
         s.r = d->r;

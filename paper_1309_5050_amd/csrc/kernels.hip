@@ -163,11 +163,12 @@ struct RowInSrc {
     const double* src;
     double sc;
     double* qout;
+    float* qout32;   // the FP32 copy of the basis column (or nullptr)
 };
 
 __device__ __forceinline__ RowInSrc row_in_source(const OpDesc& op, const LzDesc& lz, const ResDesc* res,
                                                   const Item& item, const RowInArgs& a0, bool leader) {
-    RowInSrc r{nullptr, 1.0, nullptr};
+    RowInSrc r{nullptr, 1.0, nullptr, nullptr};
     RowInArgs args = a0;
     if (args.mode == IN_LZ_STEP) {
         const int j = lz.step[0], js = lz.step[1];
@@ -188,6 +189,7 @@ __device__ __forceinline__ RowInSrc row_in_source(const OpDesc& op, const LzDesc
             r.sc = (!bd && beta > 1e-300) ? 1.0 / beta : 0.0;
             r.src = lz.w;
             r.qout = lz.Q + (long)args.j * lz.n;
+            r.qout32 = lz.Q32 ? lz.Q32 + (long)args.j * lz.n : nullptr;
             if (leader) {
                 if (args.j > 0 && !fresh) lz.Bm[(long)(args.j - 1) * kMaxBasis + args.j] = bd ? 0.0 : beta;
                 if (bd) lz.flag[2] = 1;
@@ -244,11 +246,15 @@ k_row_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const R
         const double* src = rsrc.src;
         const double sc = rsrc.sc;
         double* qout = rsrc.qout;
+        float* q32 = rsrc.qout32;
         const bool wr = valid && qout != nullptr;
         row_visit<double, G, cdiv(2 * NMAX, G)>(
             S, a, MB, tid, [&](int i) { return src[i] * sc; },
             [&](int b, int i, double v) {
-                if (wr && i >= 0) qout[i] = v;
+                if (wr && i >= 0) {
+                    qout[i] = v;
+                    if (q32) q32[i] = static_cast<float>(v);
+                }
                 sr[b] = to<T>(v);
             });
     }
@@ -645,7 +651,9 @@ k_rowr_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     const RowInSrc rs = row_in_source(op, lzs[item.inst], res, item, args, valid && a == 0 && t == 0);
     const gptr<const double> src = as_global(rs.src);
     const gptr<double> qout = as_global(rs.qout);
+    const gptr<float> q32 = as_global(rs.qout32);
     const bool wq = valid && rs.qout != nullptr;
+    const bool wq32 = wq && rs.qout32 != nullptr;
     dense_or_masked(S, [&](auto dense) {
         int idx[16];
         pair_idx<G, decltype(dense)::value>(S, a, t, idx);
@@ -655,6 +663,7 @@ k_rowr_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             if (wq && idx[q] >= 0) gstore(qout + idx[q], val[q]);
+            if (wq32 && idx[q] >= 0) gstore(q32 + idx[q], static_cast<float>(val[q]));
             pair_part(v[q >> 1], q & 1) = to<T>(val[q]);
         }
     });
@@ -1420,12 +1429,15 @@ __device__ __forceinline__ double wave_sum16(double (&v)[16]) {
 // when npart is given, npart[blk] = sum over the block's rows of w^2.
 // Thread = row; each wave reduces 16 columns at a time with the transposing
 // butterfly, the four waves combine through LDS.
-__device__ __forceinline__ void lz_project_block(const LzDesc& lz, int blk, int ncols, const double* wp,
-                                                 double* hp, double* npart, double (*red)[kMaxBasis + 1]) {
+// QT: the type of the basis copy read (double, or float for the FP32 copy).
+template <typename QT>
+__device__ __forceinline__ void lz_project_block_t(const LzDesc& lz, const QT* Qb, int blk, int ncols,
+                                                   const double* wp, double* hp, double* npart,
+                                                   double (*red)[kMaxBasis + 1]) {
     const long i = (long)blk * kLzRows + threadIdx.x;
     const bool in = i < lz.n;
     const long n = lz.n;
-    const gptr<const double> Q = as_global(static_cast<const double*>(lz.Q)) + (in ? i : 0);
+    const gptr<const QT> Q = as_global(Qb) + (in ? i : 0);
     const double wi = in ? gload(as_global(wp) + i) : 0.0;
     const int wv = threadIdx.x >> 6, l = lane_id();
     for (int c0 = 0; c0 < ncols; c0 += 16) {
@@ -1433,7 +1445,7 @@ __device__ __forceinline__ void lz_project_block(const LzDesc& lz, int blk, int 
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             const int c = c0 + k;
-            const double qv = gload(Q + (long)(c < ncols ? c : 0) * n);   // unconditional: loads overlap
+            const double qv = static_cast<double>(gload(Q + (long)(c < ncols ? c : 0) * n));   // unconditional: loads overlap
             v[k] = c < ncols ? qv * wi : 0.0;
         }
         const double sm = wave_sum16(v);
@@ -1448,6 +1460,12 @@ __device__ __forceinline__ void lz_project_block(const LzDesc& lz, int blk, int 
         hp[(long)blk * (kMaxBasis + 1) + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
     if (npart && threadIdx.x == 0)
         npart[blk] = red[0][kMaxBasis] + red[1][kMaxBasis] + red[2][kMaxBasis] + red[3][kMaxBasis];
+}
+
+__device__ __forceinline__ void lz_project_block(const LzDesc& lz, int blk, int ncols, const double* wp,
+                                                 double* hp, double* npart, double (*red)[kMaxBasis + 1]) {
+    if (lz.Q32) lz_project_block_t<float>(lz, lz.Q32, blk, ncols, wp, hp, npart, red);
+    else lz_project_block_t<double>(lz, lz.Q, blk, ncols, wp, hp, npart, red);
 }
 
 // Iterated classical Gram-Schmidt of w against Q[:, 0:ncols] with the
@@ -1510,11 +1528,17 @@ k_lz_update(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int 
     double wi = 0.0;
     if (i < lz.n) {
         const gptr<double> w = as_global(lz.w) + i;
-        const gptr<const double> Q = as_global(static_cast<const double*>(lz.Q)) + i;
         wi = gload(w);
         double acc = 0.0;
+        if (lz.Q32) {
+            const gptr<const float> Q = as_global(static_cast<const float*>(lz.Q32)) + i;
 #pragma unroll 8
-        for (int c = 0; c < ncols; ++c) acc += gload(Q + (long)c * lz.n) * h[c];
+            for (int c = 0; c < ncols; ++c) acc += static_cast<double>(gload(Q + (long)c * lz.n)) * h[c];
+        } else {
+            const gptr<const double> Q = as_global(static_cast<const double*>(lz.Q)) + i;
+#pragma unroll 8
+            for (int c = 0; c < ncols; ++c) acc += gload(Q + (long)c * lz.n) * h[c];
+        }
         wi -= acc;
         gstore(w, wi);
     }
@@ -1532,7 +1556,11 @@ k_lz_normalize(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, i
     const double beta = sqrt(sum_parts(lz.np, lz.nblk));
     const double sc = beta > 1e-300 ? 1.0 / beta : 0.0;
     const long i = (long)item.idx * kLzRows + threadIdx.x;
-    if (i < lz.n) lz.Q[(long)m * lz.n + i] = lz.w[i] * sc;
+    if (i < lz.n) {
+        const double q = lz.w[i] * sc;
+        lz.Q[(long)m * lz.n + i] = q;
+        if (lz.Q32) lz.Q32[(long)m * lz.n + i] = static_cast<float>(q);
+    }
     if (item.idx == 0 && threadIdx.x == 0) lz.beta[0] = beta;
 }
 
@@ -1792,9 +1820,11 @@ k_lz_restart(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int
         for (int c = 0; c < k; ++c) {
             const double u = lz.Qtmp[(long)c * lz.n + i];
             lz.Q[(long)c * lz.n + i] = u;
+            if (lz.Q32) lz.Q32[(long)c * lz.n + i] = static_cast<float>(u);
             acc -= coef[c] * u;
         }
         lz.Q[(long)k * lz.n + i] = qm;
+        if (lz.Q32) lz.Q32[(long)k * lz.n + i] = static_cast<float>(qm);
         lz.sin[i] = acc;
     }
     if (item.idx == 0) {
@@ -1829,7 +1859,11 @@ k_lz_restart_random(const LzDesc* __restrict__ lzs, const Item* __restrict__ ite
     const long i = (long)item.idx * kLzRows + threadIdx.x;
     double v = 0.0;
     if (i < lz.n) {
-        for (int c = 0; c < k; ++c) lz.Q[(long)c * lz.n + i] = lz.Qtmp[(long)c * lz.n + i];
+        for (int c = 0; c < k; ++c) {
+            const double u = lz.Qtmp[(long)c * lz.n + i];
+            lz.Q[(long)c * lz.n + i] = u;
+            if (lz.Q32) lz.Q32[(long)c * lz.n + i] = static_cast<float>(u);
+        }
         v = hash_unit(seed, (unsigned long long)i);
         lz.w[i] = v;
     }
