@@ -1343,9 +1343,16 @@ void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode, bool prof 
         ProfSpan p(b.ctx, prof ? "lz_update" : nullptr, st, qb);
         launch_lz_update(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 1, 0);
     }
-    // second Gram-Schmidt pass, skipped on the device when not needed
-    launch_lz_proj2(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 0);
-    launch_lz_update(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 2, 0);
+    // second Gram-Schmidt pass for FP64 instances, skipped on the device
+    // when not needed.  FP32 instances project against the FP32 copy of the
+    // basis: its rounding (about 1e-7) bounds their orthogonality, while one
+    // FP64 pass leaves eps |w_before| / |w_after|, below that unless the pass
+    // cancels w by nine orders (where the breakdown test takes over), so
+    // they make one pass and skip both launches.
+    if (b.f64) {
+        launch_lz_proj2(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 0);
+        launch_lz_update(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 2, 0);
+    }
 }
 
 int basis_size(long nshort, int r) {
