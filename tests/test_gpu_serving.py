@@ -11,7 +11,13 @@ import pytest
 
 from paper_1309_5050_amd import workloads as W
 
-pytestmark = pytest.mark.gpu
+pytestmark = [
+    pytest.mark.gpu,
+    pytest.mark.skip(reason="a full serving benchmark (300 mixed requests, FP32 and FP64 batches on the "
+                            "library's worker threads) ended with a GPU memory fault on the build that adds the "
+                            "FP32 basis copy; these tests passed in the same run, but the fault's cause is not "
+                            "found, so the served path stays off the GPU until it is"),
+]
 
 
 @pytest.fixture(scope="module")
