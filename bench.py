@@ -321,17 +321,23 @@ def _served_run(S, data, prec, rate, seed):
     arrive = np.cumsum(rng.exponential(1.0 / rate, n)) if rate else np.zeros(n)
     tickets = [None] * n
     lat = [None] * n
+    errors = []
     got = threading.Event()
 
     def collect():
-        for i in range(n):
-            while tickets[i] is None:
-                got.wait(0.001)
-            ctx.wait(tickets[i])
-            d, _, tm = ctx.take(tickets[i])
-            lat[i] = tm["total_ms"]
-            if hasattr(d, "free"):
-                d.free()
+        try:
+            for i in range(n):
+                while tickets[i] is None:
+                    got.wait(0.001)
+                ctx.wait(tickets[i])
+                d, _, tm = ctx.take(tickets[i])
+                lat[i] = tm["total_ms"]
+                if hasattr(d, "free"):
+                    d.free()
+                else:
+                    errors.append(f"request {i}: {d!r}")   # a failed request's error
+        except Exception as e:   # reported by the main thread
+            errors.append(f"collector: {e!r}")
 
     th = threading.Thread(target=collect)
     th.start()
@@ -345,6 +351,8 @@ def _served_run(S, data, prec, rate, seed):
     th.join()
     t1 = time.perf_counter()
     ctx.close()
+    if errors:
+        raise RuntimeError(f"{len(errors)} served requests failed ({prec}); first: {errors[0]}")
     warm = max(1, n // 20)
     ls = np.array(lat[warm:])
     third = max(1, len(ls) // 3)
