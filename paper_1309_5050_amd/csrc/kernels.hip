@@ -276,7 +276,8 @@ k_row_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const R
 
 
 // Long-vector update of step j inside the row pass: gamma = beta_{j-1} /
-// alpha_{j-1} (0 on the first step of a cycle), lcur/lprev by parity.
+// alpha_{j-1} (formed by the step's input pass; 0 on the first step of a
+// cycle), lcur/lprev by parity.
 template <typename T>
 struct GkLong {
     T* lcur;
@@ -286,7 +287,7 @@ struct GkLong {
 };
 
 template <typename T>
-__device__ __forceinline__ GkLong<T> gk_long(const LzDesc& lz, const CellSet& Slong, int j, int jstart) {
+__device__ __forceinline__ GkLong<T> gk_long(const LzDesc& lz, int j, int jstart) {
     if (j == kStepDev) {
         j = lz.step[0];
         jstart = lz.step[1];
@@ -300,7 +301,6 @@ __device__ __forceinline__ GkLong<T> gk_long(const LzDesc& lz, const CellSet& Sl
     // a cycle and after a breakdown)
     const double gm = j != jstart ? lz.gam[p] : 0.0;
     g.gamma = static_cast<T>(gm);
-    (void)Slong;
     return g;
 }
 
@@ -336,7 +336,7 @@ k_row_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
         if (args.div_sigma) sc = rs.sigma[item.comp] > 0 ? sc / rs.sigma[item.comp] : 0.0;
     }
     if (args.gk) {
-        const GkLong<T> g = gk_long<T>(lzs[item.inst], S, args.j, args.jstart);
+        const GkLong<T> g = gk_long<T>(lzs[item.inst], args.j, args.jstart);
         double part = 0.0;
         row_visit<T, G, cdiv(2 * NMAX, G)>(
             S, a, op.MB, tid, [&](int i) { return g.lprev[i]; },
@@ -699,7 +699,7 @@ k_rowr_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
     }
     const CellSet& S = op.S[args.set];
     if (args.gk) {
-        const GkLong<T> g = gk_long<T>(lzs[item.inst], S, args.j, args.jstart);
+        const GkLong<T> g = gk_long<T>(lzs[item.inst], args.j, args.jstart);
         const gptr<const T> lprev = as_global(g.lprev);
         const gptr<T> lcur = as_global(g.lcur);
         double part = 0.0;
@@ -844,7 +844,7 @@ k_rowfam_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, con
         sc = rs.sigma[item.comp] > 0 ? 1.0 / rs.sigma[item.comp] : 0.0;
     }
     if (args.gk) {
-        const GkLong<T> g = gk_long<T>(lzs[item.inst], S, args.j, args.jstart);
+        const GkLong<T> g = gk_long<T>(lzs[item.inst], args.j, args.jstart);
         double part = 0.0;
         row_visit<T, G, cdiv(2 * NMAX, G)>(
             S, a, op.MB, tid, [&](int i) { return g.lprev[i]; },
