@@ -367,7 +367,26 @@ def esprit(U, group):
     sorted by decreasing modulus, then decreasing imaginary part."""
     Ug = np.asarray(U, dtype=np.float64)[:, list(group)]
     D = np.linalg.lstsq(Ug[:-1], Ug[1:], rcond=None)[0]
-    z = np.linalg.eigvals(D)
+    return _sorted_roots(np.linalg.eigvals(D))
+
+
+def esprit_tls(U, group):
+    """TLS-ESPRIT roots (the same paragraph; Roy and Kailath's total least
+    squares variant): with Z = [U_low : U_high] ((L-1) x 2r) and its right
+    singular vectors V = [[V11, V12], [V21, V22]] (r x r blocks, columns by
+    decreasing singular value), the shift matrix is -V12 V22^{-1}; its
+    eigenvalues are the roots, sorted as for esprit."""
+    Ug = np.asarray(U, dtype=np.float64)[:, list(group)]
+    r = Ug.shape[1]
+    Z = np.hstack([Ug[:-1], Ug[1:]])
+    _, _, Vt = np.linalg.svd(Z, full_matrices=False)
+    V = Vt.T
+    V12, V22 = V[:r, r:], V[r:, r:]
+    return _sorted_roots(np.linalg.eigvals(-V12 @ np.linalg.inv(V22)))
+
+
+def _sorted_roots(z):
+    """Roots by decreasing modulus, then decreasing imaginary part."""
     order = sorted(range(len(z)), key=lambda k: (-abs(z[k]), -z[k].imag))
     return z[order]
 

@@ -847,3 +847,34 @@ def test_esprit2d_pairs_do_not_depend_on_the_combination_weight():
     a = oracle.esprit2d(sh, U, [0, 1, 2, 3])
     b = oracle.esprit2d(sh, U, [0, 1, 2, 3], gamma=2.3)
     assert _pairs_match(a[0], a[1], b[0], b[1]) <= 1e-9
+
+
+def test_tls_esprit_recovers_damped_cosines_and_agrees_with_ls():
+    """Noiseless finite-rank series: TLS-ESPRIT gives the exact roots, like
+    LS-ESPRIT; on a noisy one both stay close to the true roots."""
+    N, L = 120, 40
+    t = np.arange(N)
+    x = 2.0 * 0.98 ** t * np.cos(2 * np.pi * t / 10 + 0.3) + np.cos(2 * np.pi * t / 23) + 0.5 * 1.01 ** t
+    true = [0.98 * np.exp(2j * np.pi / 10), 0.98 * np.exp(-2j * np.pi / 10), np.exp(2j * np.pi / 23),
+            np.exp(-2j * np.pi / 23), 1.01]
+    sh = oracle.shapes(x, None, None, L)
+    s, U, V = _lapack_svd(oracle.trajectory(x, sh))
+    assert _match_roots(oracle.esprit_tls(U, [0, 1, 2, 3, 4]), true) <= 1e-9
+    g = np.random.default_rng(12)
+    y = x + 0.05 * g.standard_normal(N)
+    s, U, V = _lapack_svd(oracle.trajectory(y, oracle.shapes(y, None, None, L)))
+    a, b = oracle.esprit_tls(U, [0, 1, 2, 3, 4]), oracle.esprit(U, [0, 1, 2, 3, 4])
+    assert _match_roots(a, true) <= 2e-2 and _match_roots(b, true) <= 2e-2
+    assert _match_roots(a, b) > 1e-12                  # the two estimators differ on noisy data
+
+
+def test_tls_esprit_roots_do_not_depend_on_the_basis_of_the_span():
+    g = np.random.default_rng(9)
+    N, L = 90, 30
+    t = np.arange(N)
+    x = np.cos(2 * np.pi * t / 7) + 0.7 * np.cos(2 * np.pi * t / 13 + 1) + 0.05 * g.standard_normal(N)
+    s, U, V = _lapack_svd(oracle.trajectory(x, oracle.shapes(x, None, None, L)))
+    Q, _ = np.linalg.qr(g.standard_normal((4, 4)))
+    U2 = U.copy()
+    U2[:, :4] = U[:, :4] @ Q
+    assert _match_roots(oracle.esprit_tls(U, [0, 1, 2, 3]), oracle.esprit_tls(U2, [0, 1, 2, 3])) <= 1e-10
