@@ -270,6 +270,7 @@ int ssa_vforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int
  * (<= 64) 0-based component ids; out: nseries x h as for ssa_rforecast;
  * with out = NULL only *nseries is set.  Synchronous. */
 int ssa_rforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries);
+int ssa_vforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries);
 
 /* LS-ESPRIT parameter estimation (the 1D parameter-estimation paragraph of
  * the 2D-SSA examples; the remark after the fast column forecast names the
@@ -282,6 +283,16 @@ int ssa_rforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out,
  * (SSA_EINVAL); SSA_ENOCONV if the eigenvalue iteration fails.
  * Synchronous. */
 int ssa_esprit(ssa_decomp* d, const int* grp, int ng, double* re, double* im);
+
+/* TLS-ESPRIT roots (the same paragraph, with the total-least-squares shift
+ * matrix of Roy and Kailath): for Z = [U_low : U_high], the group's U
+ * without its last row beside it without its first, and Z's right singular
+ * vectors V = [[V11, V12], [V21, V22]] (ng x ng blocks, by decreasing
+ * singular value), the roots are the eigenvalues of -V12 V22^{-1}.  Same
+ * window, arguments and output order as ssa_esprit, with 1 <= ng <= 24;
+ * SSA_EINVAL if V22 is singular, SSA_ENOCONV if an eigenvalue iteration
+ * fails.  Synchronous. */
+int ssa_esprit_tls(ssa_decomp* d, const int* grp, int ng, double* re, double* im);
 
 /* 2D-ESPRIT (the parameter-estimation subsection of the 2D-SSA examples:
  * shift matrices for the x and y directions and their joint
@@ -297,7 +308,6 @@ int ssa_esprit(ssa_decomp* d, const int* grp, int ng, double* re, double* im);
  * SSA_EINVAL for a 1D window or a singular shift equation, SSA_ENOCONV if
  * the eigenvalue iteration fails.  Synchronous. */
 int ssa_esprit2d(ssa_decomp* d, const int* grp, int ng, double* lre, double* lim, double* mre, double* mim);
-int ssa_vforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries);
 
 int  ssa_get_stats(const ssa_decomp* d, ssa_stats* st);
 void ssa_free(ssa_decomp* d);

@@ -138,11 +138,13 @@ class Decomposition:
         fn = {"column": "ssa_vforecast", "row": "ssa_vforecast_row"}[direction]
         return self._forecast(fn, group, h)
 
-    def esprit(self, group) -> np.ndarray:
-        """LS-ESPRIT roots of the group (complex, by decreasing modulus)."""
+    def esprit(self, group, method: str = "ls") -> np.ndarray:
+        """ESPRIT roots of the group (complex, by decreasing modulus);
+        method "ls" (least squares) or "tls" (total least squares)."""
+        fn = {"ls": "ssa_esprit", "tls": "ssa_esprit_tls"}[method]
         g = np.ascontiguousarray(group, dtype=np.int32)
         re, im = np.zeros(len(g)), np.zeros(len(g))
-        check(lib().ssa_esprit(self._h, _ptr(g), len(g), _ptr(re), _ptr(im)), "ssa_esprit")
+        check(getattr(lib(), fn)(self._h, _ptr(g), len(g), _ptr(re), _ptr(im)), fn)
         return re + 1j * im
 
     def esprit2d(self, group):

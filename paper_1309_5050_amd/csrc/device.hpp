@@ -106,6 +106,8 @@ constexpr int kStepDev = -1;
 // Largest group of a vector forecast (one lane of a wave per coordinate of
 // the carried coefficient vectors).
 constexpr int kVfMaxGroup = 64;
+// TLS-ESPRIT: the 2 ng x 2 ng eigenproblem is solved in one workgroup's LDS.
+constexpr int kTlsMaxGroup = 24;
 
 // Weight of the y shift matrix in the combination whose eigenvectors pair
 // the x and y roots of 2D-ESPRIT (any weight works when the shift matrices

@@ -3022,6 +3022,32 @@ int ssa_esprit(ssa_decomp* d, const int* grp, int ng, double* re, double* im) {
     return SSA_OK;
 }
 
+int ssa_esprit_tls(ssa_decomp* d, const int* grp, int ng, double* re, double* im) {
+    if (!re || !im) return fail(SSA_EINVAL, "NULL argument");
+    int rc = check_forecast(d, grp, ng, 1, re, nullptr, "ESPRIT");
+    if (rc) return rc;
+    if (ng > kTlsMaxGroup) return fail(SSA_EINVAL, "TLS-ESPRIT group larger than 24 components");
+    if ((rc = wait_handle(d))) return rc;
+    hipStream_t st = d->ctx->st;
+    std::vector<int> g(grp, grp + ng);
+    DevVec dg, flag, G, dre, dim;
+    if ((rc = dg.put(g, st)) || (rc = flag.put(std::vector<int>{0, 0}, st)) ||
+        (rc = G.reserve((size_t)4 * ng * ng * sizeof(double))) || (rc = dre.reserve((size_t)ng * sizeof(double))) ||
+        (rc = dim.reserve((size_t)ng * sizeof(double))))
+        return rc;
+    launch_esprit_tls(st, d->U, d->L, dg.as<int>(), ng, G.as<double>(), dre.as<double>(), dim.as<double>(),
+                      flag.as<int>());
+    HIPCHK(hipGetLastError());
+    int bad[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(bad, flag.p, sizeof(bad), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(re, dre.p, (size_t)ng * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(im, dim.p, (size_t)ng * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (bad[0]) return fail(SSA_EINVAL, "no TLS-ESPRIT roots: V22 is singular for the group");
+    if (bad[1]) return fail(SSA_ENOCONV, "TLS-ESPRIT: an eigenvalue iteration did not converge");
+    return SSA_OK;
+}
+
 int ssa_esprit2d(ssa_decomp* d, const int* grp, int ng, double* lre, double* lim, double* mre, double* mim) {
     if (!d || !grp || !lre || !lim || !mre || !mim) return fail(SSA_EINVAL, "NULL argument");
     if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");

@@ -297,4 +297,109 @@ __host__ __device__ inline int joint_eig(const Real* px, const Real* py, int n, 
     return 0;
 }
 
+// Eigenpairs of a symmetric n x n matrix (row-major, leading dimension lda,
+// overwritten) by the cyclic Jacobi method: rotations zero each
+// off-diagonal entry in turn until the off-diagonal mass falls below
+// rounding.  vec (n x n, leading dimension ldv) receives the eigenvectors as
+// columns, w the eigenvalues.  Returns the sweeps used, or -1 if 60 did not
+// suffice.
+template <typename Real>
+__host__ __device__ inline int sym_eig(Real* a, int n, int lda, Real* vec, int ldv, Real* w) {
+    const auto A = [&](int i, int j) -> Real& { return a[i * lda + j]; };
+    const auto Vv = [&](int i, int j) -> Real& { return vec[i * ldv + j]; };
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Vv(i, j) = i == j ? Real(1) : Real(0);
+    const Real eps = sizeof(Real) == 8 ? Real(2.220446049250313e-16) : Real(1.1920929e-7);
+    Real nrm = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) nrm += A(i, j) * A(i, j);
+    int sweep = 0;
+    for (; sweep < 60; ++sweep) {
+        Real off = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) off += A(i, j) * A(i, j);
+        if (off <= eps * eps * nrm) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const Real apq = A(p, q);
+                if (apq == 0) continue;
+                const Real th = (A(q, q) - A(p, p)) / (2 * apq);
+                const Real t = std::copysign(Real(1), th) / (std::fabs(th) + std::sqrt(th * th + 1));
+                const Real c = 1 / std::sqrt(t * t + 1), sn = t * c;
+                for (int k = 0; k < n; ++k) {   // columns p, q
+                    const Real akp = A(k, p), akq = A(k, q);
+                    A(k, p) = c * akp - sn * akq;
+                    A(k, q) = sn * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {   // rows p, q
+                    const Real apk = A(p, k), aqk = A(q, k);
+                    A(p, k) = c * apk - sn * aqk;
+                    A(q, k) = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const Real vkp = Vv(k, p), vkq = Vv(k, q);
+                    Vv(k, p) = c * vkp - sn * vkq;
+                    Vv(k, q) = sn * vkp + c * vkq;
+                }
+            }
+    }
+    for (int i = 0; i < n; ++i) w[i] = A(i, i);
+    return sweep < 60 ? sweep : -1;
+}
+
+// TLS-ESPRIT shift matrix of r components from the Gram matrix
+// g = Z^T Z (2r x 2r, row-major, leading dimension 2r, overwritten) of
+// Z = [U_low : U_high]: with the eigenvectors of g ordered by decreasing
+// eigenvalue (the right singular vectors of Z), V = [[V11, V12], [V21, V22]],
+// phi = -V12 V22^{-1} (r x r, row-major, leading dimension r).  Scratch:
+// vec (4 r^2), w and order (2r each), lu (2 r^2: V22^T and the right-hand
+// sides).  Returns 0, or -1 (no convergence) / -2 (V22 singular).
+template <typename Real>
+__host__ __device__ inline int tls_shift(Real* g, int r, Real* vec, Real* w, int* order, Real* lu, Real* phi) {
+    const int n = 2 * r;
+    if (sym_eig(g, n, n, vec, n, w) < 0) return -1;
+    for (int i = 0; i < n; ++i) order[i] = i;
+    for (int i = 1; i < n; ++i) {   // insertion sort by decreasing eigenvalue
+        const int o = order[i];
+        int k = i - 1;
+        while (k >= 0 && w[order[k]] < w[o]) {
+            order[k + 1] = order[k];
+            --k;
+        }
+        order[k + 1] = o;
+    }
+    // solve V22^T X^T = -V12^T by Gauss-Jordan with partial pivoting:
+    // M = [V22^T | -V12^T], V12(i, j) = vec(i, order[r + j]), V22(i, j) = vec(r + i, order[r + j])
+    Real* m = lu;   // r x 2r
+    for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) {
+            m[i * n + j] = vec[(r + j) * n + order[r + i]];   // V22^T(i, j) = V22(j, i)
+            m[i * n + r + j] = -vec[j * n + order[r + i]];    // -V12^T(i, j) = -V12(j, i)
+        }
+    for (int p = 0; p < r; ++p) {
+        int best = p;
+        for (int i = p + 1; i < r; ++i)
+            if (std::fabs(m[i * n + p]) > std::fabs(m[best * n + p])) best = i;
+        if (m[best * n + p] == 0) return -2;
+        if (best != p)
+            for (int j = 0; j < n; ++j) {
+                const Real t = m[p * n + j];
+                m[p * n + j] = m[best * n + j];
+                m[best * n + j] = t;
+            }
+        const Real piv = m[p * n + p];
+        for (int j = 0; j < n; ++j) m[p * n + j] /= piv;
+        for (int i = 0; i < r; ++i) {
+            if (i == p) continue;
+            const Real f = m[i * n + p];
+            if (f == 0) continue;
+            for (int j = 0; j < n; ++j) m[i * n + j] -= f * m[p * n + j];
+        }
+    }
+    // X^T = right half; phi = X
+    for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) phi[i * r + j] = m[j * n + r + i];
+    return 0;
+}
+
 }  // namespace shssa

@@ -2310,6 +2310,28 @@ k_vforecast(const double* __restrict__ U, long L, const double* __restrict__ V, 
     }
 }
 
+// Roots (wr, wi; n values) into re/im by decreasing modulus, then
+// decreasing imaginary part (selection; taken: n values of scratch).
+__device__ inline void order_roots(const double* wr, const double* wi, int n, double* taken, double* re,
+                                   double* im) {
+    for (int k = 0; k < n; ++k) taken[k] = 0.0;
+    for (int p = 0; p < n; ++p) {
+        int best = -1;
+        double bm = 0.0;
+        for (int k = 0; k < n; ++k) {
+            if (taken[k] != 0.0) continue;
+            const double mk = sqrt(wr[k] * wr[k] + wi[k] * wi[k]);
+            if (best < 0 || mk > bm || (mk == bm && wi[k] > wi[best])) {
+                best = k;
+                bm = mk;
+            }
+        }
+        taken[best] = 1.0;
+        re[p] = wr[best];
+        im[p] = wi[best];
+    }
+}
+
 // LS-ESPRIT roots of a group: the eigenvalues of its shift matrix
 // D = (I + pi pi^T / (1 - nu^2)) M (as for the vector forecast: the
 // pseudo-inverse of the group's U without its last row times U without its
@@ -2346,23 +2368,62 @@ k_esprit(const double* __restrict__ U, long L, const int* __restrict__ grp, int 
     __syncthreads();
     if (lane != 0) return;
     if (eig_real<double>(Ds, ng, LD, work, wr, wi) != 0) flag[1] = 1;
-    // order: selection by (modulus, imaginary part), work[] marks the taken
-    for (int k = 0; k < ng; ++k) work[k] = 0.0;
-    for (int p = 0; p < ng; ++p) {
-        int best = -1;
-        double bm = 0.0;
-        for (int k = 0; k < ng; ++k) {
-            if (work[k] != 0.0) continue;
-            const double mk = sqrt(wr[k] * wr[k] + wi[k] * wi[k]);
-            if (best < 0 || mk > bm || (mk == bm && wi[k] > wi[best])) {
-                best = k;
-                bm = mk;
-            }
-        }
-        work[best] = 1.0;
-        re[p] = wr[best];
-        im[p] = wi[best];
+    order_roots(wr, wi, ng, work, re, im);
+}
+
+// TLS-ESPRIT Gram matrix of Z = [U_low : U_high] (U_low: the group's U
+// without its last row, U_high without its first): g (2 ng x 2 ng,
+// row-major) = [[U_low^T U_low, U_low^T U_high], [U_high^T U_low,
+// U_high^T U_high]], summed explicitly (the blocks are I - pi pi^T, M and
+// I - rho rho^T only for an exactly orthonormal U).  One wave per (i, j).
+__global__ void __launch_bounds__(256)
+k_tls_gram(const double* __restrict__ U, long L, const int* __restrict__ grp, int ng, double* __restrict__ g) {
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= ng * ng) return;   // whole waves
+    const int i = e / ng, j = e % ng, n = 2 * ng;
+    const double* ui = U + (long)grp[i] * L;
+    const double* uj = U + (long)grp[j] * L;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (long l = lane_id(); l < L - 1; l += 64) {
+        const double a = ui[l], b = ui[l + 1], c = uj[l], d = uj[l + 1];
+        s0 += a * c;
+        s1 += a * d;
+        s2 += b * d;
     }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if (lane_id() == 0) {
+        g[i * n + j] = s0;
+        g[i * n + ng + j] = s1;
+        g[(ng + j) * n + i] = s1;
+        g[(ng + i) * n + ng + j] = s2;
+    }
+}
+
+// TLS-ESPRIT roots from that Gram matrix: its eigenvectors by decreasing
+// eigenvalue are Z's right singular vectors, the shift matrix is
+// -V12 V22^{-1}, its eigenvalues the roots, ordered as for k_esprit.  The
+// first lane works in LDS (ng <= kTlsMaxGroup).  flag[0] = 1: V22 singular;
+// flag[1] = 1: an eigenvalue iteration did not converge.
+__global__ void __launch_bounds__(64)
+k_esprit_tls(const double* __restrict__ g, int ng, double* __restrict__ re, double* __restrict__ im,
+             int* __restrict__ flag) {
+    constexpr int NM = 2 * kTlsMaxGroup;
+    __shared__ double gs[NM * NM], vec[NM * NM], lu[kTlsMaxGroup * NM], phi[kTlsMaxGroup * kTlsMaxGroup];
+    __shared__ double w[NM], work[kTlsMaxGroup], wr[kTlsMaxGroup], wi[kTlsMaxGroup];
+    __shared__ int order[NM];
+    const int n = 2 * ng;
+    for (int e = threadIdx.x; e < n * n; e += 64) gs[e] = g[e];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int rc = tls_shift<double>(gs, ng, vec, w, order, lu, phi);
+    if (rc != 0) {
+        flag[rc == -2 ? 0 : 1] = 1;
+        return;
+    }
+    if (eig_real<double>(phi, ng, ng, work, wr, wi) != 0) flag[1] = 1;
+    order_roots(wr, wi, ng, work, re, im);
 }
 
 // 2D-ESPRIT, Gram terms over index pairs: out[i * ng + j] = sum_p

@@ -100,6 +100,10 @@ void launch_eig_take(int nitems, hipStream_t st, const LzDesc* lzs, const ResDes
 // flag[0..1] (zeroed by the caller) as for k_esprit.
 void launch_esprit(hipStream_t st, const double* U, long L, const int* grp, int ng, double* M, double* re,
                    double* im, int* flag);
+// TLS-ESPRIT roots (ng <= kTlsMaxGroup) into re/im; g holds 4 ng^2 values;
+// flag[0] (V22 singular) and flag[1] (no convergence), zeroed by the caller.
+void launch_esprit_tls(hipStream_t st, const double* U, long L, const int* grp, int ng, double* g, double* re,
+                       double* im, int* flag);
 // 2D-ESPRIT: for each axis the Gram terms over the index pairs (pa[2 ax],
 // pb[2 ax]: cells and their neighbour; pa/pb[2 ax + 1]: the cells without
 // one, with themselves) give phi_ax = (I - S^T S)^{-1} M; then the joint

@@ -830,12 +830,71 @@ def test_esprit_errors(ctx):
     import paper_1309_5050_amd as S
     x = np.random.default_rng(3).standard_normal((30, 30))
     d = ctx.decompose(x, (5, 5), 3)
-    with pytest.raises(S.SsaError):
-        d.esprit([0, 1])               # a 2D window
     y = np.random.default_rng(4).standard_normal(200)
     e = ctx.decompose(y, 50, 3)
+    for method in ("ls", "tls"):
+        with pytest.raises(S.SsaError):
+            d.esprit([0, 1], method)   # a 2D window
+        with pytest.raises(S.SsaError):
+            e.esprit([0, 7], method)   # component beyond r
+    f = ctx.decompose(y, 60, 30)
     with pytest.raises(S.SsaError):
-        e.esprit([0, 7])               # component beyond r
+        f.esprit(list(range(25)), "tls")   # beyond the 24 roots TLS solves
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,group", [("series_1000", [0, 1, 2, 3, 4, 5]), ("mssa_8", [0, 1, 2, 3]),
+                                        ("series_1000", [1, 2])])
+def test_esprit_tls_parity(ctx, name, group, prec):
+    """TLS-ESPRIT roots from the GPU decomposition against the oracle's
+    TLS roots of its own triplets, within the same span bound as LS-ESPRIT
+    (20 tol s_1 / gap, the gap after the group's last component)."""
+    w = CASES[name]()
+    tol = TOL[prec]
+    sh, so, Uo, Vo = oracle_case(name, w)
+    ref = oracle.esprit_tls(Uo, group)
+    d = gpu_case(ctx, w, prec)
+    got = d.esprit(group, "tls")
+    assert got.shape == ref.shape
+    gap = min(so[group[-1]] - so[group[-1] + 1], so[group[0] - 1] - so[group[0]] if group[0] > 0 else np.inf)
+    err = _nearest_match(got, ref)
+    bound = 20 * tol * so[0] / gap
+    print(f"{name} {group} {prec}: TLS-ESPRIT root error {err:.3e} bound {bound:.3e}")
+    assert err <= bound, (name, prec, err, bound)
+    mods = np.abs(got)
+    assert np.all(mods[:-1] >= mods[1:] - 1e-15)
+
+
+def test_esprit_tls_recovers_damped_cosines(ctx):
+    """On an exact rank-5 series TLS and LS agree with the true roots."""
+    N, L = 240, 80
+    t = np.arange(N)
+    x = 2.0 * 0.99 ** t * np.cos(2 * np.pi * t / 10 + 0.3) + np.cos(2 * np.pi * t / 23) + 0.5 * 1.005 ** t
+    d = ctx.decompose(x, L, 5)
+    z = d.esprit([0, 1, 2, 3, 4], "tls")
+    true = [0.99 * np.exp(2j * np.pi / 10), 0.99 * np.exp(-2j * np.pi / 10), np.exp(2j * np.pi / 23),
+            np.exp(-2j * np.pi / 23), 1.005]
+    assert _nearest_match(z, true) <= 1e-8
+    assert _nearest_match(z, d.esprit([0, 1, 2, 3, 4])) <= 1e-8
+
+
+def test_esprit_tls_largest_group(ctx):
+    """24 roots (the largest TLS group) from a noisy series against the
+    oracle's TLS roots of the GPU's own basis, so that only the small
+    eigenproblems are compared."""
+    g = np.random.default_rng(11)
+    N, L = 600, 150
+    t = np.arange(N)
+    x = sum(g.uniform(0.5, 2) * np.cos(2 * np.pi * t / g.uniform(2.5, 60) + g.uniform(0, 6)) for _ in range(12))
+    x = x + 0.05 * g.standard_normal(N)
+    d = ctx.decompose(x, L, 30)
+    U, _ = d.vectors_lex()
+    grp = list(range(24))
+    ref = oracle.esprit_tls(U, grp)
+    got = d.esprit(grp, "tls")
+    err = _nearest_match(got, ref)
+    print(f"24-root TLS-ESPRIT: {err:.3e}")
+    assert err <= 1e-9, err
 
 
 def _pairs_nearest(l1, m1, l2, m2):
@@ -906,3 +965,18 @@ def test_esprit2d_errors(ctx):
     d = ctx.decompose(x, (8, 7), 4)
     with pytest.raises(S.SsaError):
         d.esprit2d([0, 9])             # component beyond r
+
+
+@pytest.mark.parametrize("name", ["image_128", "series_1000", "disc_160"])
+def test_fp32_vectors_stay_orthonormal(ctx, name):
+    """FP32-product decompositions reorthogonalise once against an FP32 copy
+    of the basis: their Lanczos-side vectors stay orthonormal to about 1e-7,
+    far inside the 1e-5 tolerance."""
+    w = CASES[name]()
+    d = gpu_case(ctx, w, "fp32")
+    U, V = d.vectors_lex()
+    side = d.stats["side"]
+    B = U if side == 0 else V
+    err = np.max(np.abs(B.T @ B - np.eye(B.shape[1])))
+    print(f"{name}: |B^T B - I| = {err:.2e} (side {side})")
+    assert err <= 1e-6, (name, err)
