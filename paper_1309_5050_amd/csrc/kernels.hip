@@ -1593,10 +1593,13 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // values are the final column norms, the left vectors the normalised
 // columns; they are ranked (descending) and the residual test
 // beta |Yr[m-1, i]| <= tol * sigma_1 is evaluated for the r leading ones.
+// PE: column entries per thread, 8 PE >= m (the entries past m are zeros
+// and only cost issue slots, so the launch picks the smallest PE that fits).
+template <int PE>
 __global__ void __launch_bounds__(512)
 k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, int max_sweeps) {
     constexpr int LP = 8;                       // threads per column pair
-    constexpr int PE = kMaxBasis / LP;          // column entries per thread
+    static_assert(PE * LP <= kMaxBasis, "column entries beyond the basis");
     __shared__ double Bs[kMaxBasis * kMaxBasis];
     __shared__ double yl[kMaxBasis];
     __shared__ double cn[kMaxBasis];
