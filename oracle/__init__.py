@@ -579,6 +579,80 @@ def pack_m2d(images, window, wmask=None) -> np.ndarray:
     return out
 
 
+def mosaic_hankel(series, Ls, Ks) -> np.ndarray:
+    """Mosaic Hankel matrix (the mosaic Hankel subsection): block (i, j) is
+    the L_i x K_j Hankel matrix of series[i][j] (length L_i + K_j - 1),
+    entry (b, k) = series[i][j][b + k]; block rows of L_i rows, block
+    columns of K_j columns."""
+    rows = []
+    for i, L in enumerate(Ls):
+        blocks = []
+        for j, K in enumerate(Ks):
+            x = np.asarray(series[i][j], dtype=np.float64)
+            if len(x) != L + K - 1:
+                raise ValueError("series (%d, %d) needs length L_i + K_j - 1" % (i, j))
+            H = np.empty((L, K))
+            for b in range(L):
+                for k in range(K):
+                    H[b, k] = x[b + k]
+            blocks.append(H)
+        rows.append(np.hstack(blocks))
+    return np.vstack(rows)
+
+
+def pack_mosaic(series, Ls, Ks):
+    """Shaped packing of a mosaic Hankel matrix (the same subsection: stacked
+    shapes with separators): (array, window, wmask).  Row i of an s-row
+    array holds series[i][j] from column c_j on; the block columns follow
+    each other with one NaN column after the longest series of the block
+    (c_{j+1} = c_j + max L + K_j).  The window has s rows, row i its first
+    L_i cells; its positions that fit are exactly the K_j origins of each
+    block column, so the shaped trajectory matrix is the mosaic matrix."""
+    s, t = len(Ls), len(Ks)
+    Lm = max(Ls)
+    offs = [0]
+    for K in Ks[:-1]:
+        offs.append(offs[-1] + Lm + K)
+    width = offs[-1] + Lm + Ks[-1] - 1
+    out = np.full((s, width), np.nan)
+    for i, L in enumerate(Ls):
+        for j, K in enumerate(Ks):
+            out[i, offs[j]:offs[j] + L + K - 1] = series[i][j]
+    wmask = np.zeros((s, Lm), np.uint8)
+    for i, L in enumerate(Ls):
+        wmask[i, :L] = 1
+    return out, (s, Lm), wmask
+
+
+def reconstruct_mosaic(series, Ls, Ks, group):
+    """The group's reconstruction of every series of a mosaic Hankel matrix
+    (the embedding, grouping and diagonal averaging steps on the mosaic
+    matrix): the sum of sigma_k U_k V_k^T over the group, each block averaged
+    along its anti-diagonals.  Returns the nested list of series."""
+    M = mosaic_hankel(series, Ls, Ks)
+    U, s, Vt = np.linalg.svd(M, full_matrices=False)
+    g = list(group)
+    Mg = (U[:, g] * s[g]) @ Vt[g]
+    out = []
+    r0 = 0
+    for L in Ls:
+        row = []
+        c0 = 0
+        for K in Ks:
+            blk = Mg[r0:r0 + L, c0:c0 + K]
+            acc = np.zeros(L + K - 1)
+            cnt = np.zeros(L + K - 1)
+            for b in range(L):
+                for k in range(K):
+                    acc[b + k] += blk[b, k]
+                    cnt[b + k] += 1
+            row.append(acc / cnt)
+            c0 += K
+        out.append(row)
+        r0 += L
+    return out
+
+
 def grid(sh: Shapes, vec, which: str) -> np.ndarray:
     """Place a compact vector on its (Lx, Ly) or (Kx, Ky) box, NaN elsewhere."""
     if which == "L":

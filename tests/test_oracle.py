@@ -878,3 +878,72 @@ def test_tls_esprit_roots_do_not_depend_on_the_basis_of_the_span():
     U2 = U.copy()
     U2[:, :4] = U[:, :4] @ Q
     assert _match_roots(oracle.esprit_tls(U, [0, 1, 2, 3]), oracle.esprit_tls(U2, [0, 1, 2, 3])) <= 1e-10
+
+
+# --------------------------------------------------------------------------
+# Mosaic Hankel matrices
+# --------------------------------------------------------------------------
+
+def _mosaic_series(Ls, Ks, seed=7):
+    g = np.random.default_rng(seed)
+    return [[g.standard_normal(L + K - 1) for K in Ks] for L in Ls]
+
+
+def test_mosaic_of_one_block_is_the_hankel_matrix():
+    from scipy.linalg import hankel
+    x = np.random.default_rng(2).standard_normal(20)
+    M = oracle.mosaic_hankel([[x]], [6], [15])
+    np.testing.assert_array_equal(M, hankel(x[:6], x[5:]))
+
+
+def test_mosaic_reduces_to_mssa_and_its_transpose():
+    """One block row is the MSSA trajectory matrix with window L_1; one
+    block column is the transposed MSSA matrix of its series with window
+    K_1."""
+    row = _mosaic_series([7], [5, 9, 4])
+    np.testing.assert_array_equal(oracle.mosaic_hankel(row, [7], [5, 9, 4]),
+                                  oracle.trajectory_mssa(row[0], 7))
+    col = _mosaic_series([3, 8, 5], [6])
+    np.testing.assert_array_equal(oracle.mosaic_hankel(col, [3, 8, 5], [6]),
+                                  oracle.trajectory_mssa([c[0] for c in col], 6).T)
+
+
+@pytest.mark.parametrize("Ls,Ks", [([5, 3, 7], [9, 4]), ([4], [6, 3]), ([2, 6], [7]), ([1, 4], [3, 1, 5])])
+def test_mosaic_packing_gives_the_mosaic_matrix(Ls, Ks):
+    """The shaped trajectory matrix of the packing is the mosaic matrix,
+    its rows in the window's lexicographic cell order (down the window's
+    columns) and its columns block after block."""
+    ser = _mosaic_series(Ls, Ks)
+    M = oracle.mosaic_hankel(ser, Ls, Ks)
+    x, window, wmask = oracle.pack_mosaic(ser, Ls, Ks)
+    sh = oracle.shapes(x, None, wmask, window)
+    X = oracle.trajectory(x, sh)
+    r0 = np.concatenate([[0], np.cumsum(Ls)[:-1]])
+    rows = r0[sh.li] + sh.lj
+    assert sorted(rows) == list(range(sum(Ls)))
+    np.testing.assert_array_equal(X, M[rows])
+
+
+def test_mosaic_reconstruction_is_exact_for_a_rank_two_mosaic_and_complete():
+    """Series (i, j) = a_i b_j cos(w n + p_i + q_j): entry (b, k) of block
+    (i, j) is the real part of (a_i e^{i(w b + p_i)}) (b_j e^{i(w k + q_j)}),
+    so the whole mosaic matrix has rank 2 and the first two components
+    reconstruct every series exactly; and the reconstructions of all
+    components sum to the input."""
+    Ls, Ks = [5, 8, 3], [6, 10]
+    g = np.random.default_rng(5)
+    a, p = g.uniform(0.5, 2, len(Ls)), g.uniform(0, 6, len(Ls))
+    b, q = g.uniform(0.5, 2, len(Ks)), g.uniform(0, 6, len(Ks))
+    ser = [[a[i] * b[j] * np.cos(0.7 * np.arange(L + K - 1) + p[i] + q[j]) for j, K in enumerate(Ks)]
+           for i, L in enumerate(Ls)]
+    assert np.linalg.matrix_rank(oracle.mosaic_hankel(ser, Ls, Ks), tol=1e-9) == 2
+    rec = oracle.reconstruct_mosaic(ser, Ls, Ks, [0, 1])
+    for i in range(len(Ls)):
+        for j in range(len(Ks)):
+            np.testing.assert_allclose(rec[i][j], ser[i][j], rtol=0, atol=1e-12)
+    noisy = _mosaic_series(Ls, Ks, seed=9)
+    n = min(sum(Ls), sum(Ks))
+    parts = [oracle.reconstruct_mosaic(noisy, Ls, Ks, [k]) for k in range(n)]
+    for i in range(len(Ls)):
+        for j in range(len(Ks)):
+            np.testing.assert_allclose(sum(p[i][j] for p in parts), noisy[i][j], rtol=0, atol=1e-12)
