@@ -129,11 +129,6 @@ int ssa_decompose(ssa_ctx* ctx, const double* x, int nx, int ny, const uint8_t* 
 int ssa_decompose_eigen(ssa_ctx* ctx, const double* x, int nx, int ny, const uint8_t* mask,
                         const uint8_t* wmask, int lx, int ly, int r, ssa_decomp** out);
 
-/* MSSA (Section 3.1, equation mssa_embedding) of s series of lengths len[p]
- * with window L (1 < L < min len).  Internally the 2D packing of Section
- * 5.3: a max(len) x s array, window L x 1.  Outputs use that packing:
- * V is (max(len) - L + 1) x s with NaN beyond K_p, reconstructions
- * max(len) x s with NaN beyond len[p]. */
 /* M-2D-SSA (the shaped-variants section, equation embedding_m2dssa): one
  * common decomposition of s images X_p (nx[p] x ny[p], row-major, NaN =
  * missing) whose trajectory matrix is [T(X_1) : ... : T(X_s)] with the same
@@ -149,6 +144,28 @@ int ssa_decompose_m2d(ssa_ctx* ctx, const double* const* images, const int* nx, 
                       const uint8_t* wmask, int lx, int ly, int r, int precision, int* col_off,
                       ssa_decomp** out);
 
+/* Mosaic Hankel SSA (the mosaic Hankel subsection): the decomposition of
+ * the block matrix whose block (i, j), 0 <= i < s, 0 <= j < t, is the
+ * L_i x K_j Hankel matrix of series[i * t + j] (L_i + K_j - 1 values each,
+ * NaN = missing; the caller guarantees the lengths).  Internally the
+ * shaped packing of that subsection: an s-row array where row i holds the
+ * series of block row i, block column j from column col_off[j]
+ * (col_off[0] = 0, col_off[j+1] = col_off[j] + max L + K_j), NaN between
+ * them, and a window of s rows whose row i has its first L_i cells.  The
+ * only window positions that fit are the K_j origins of each block column,
+ * so the trajectory matrix is the mosaic matrix (rows in the window's
+ * lexicographic cell order).  Outputs (U, V, reconstructions, weights)
+ * refer to the packing: series (i, j) is reconstructed in row i, columns
+ * col_off[j] .. col_off[j] + L_i + K_j - 2.  col_off: t ints, may be
+ * NULL.  precision as for ssa_decompose. */
+int ssa_decompose_mosaic(ssa_ctx* ctx, const double* const* series, int s, int t, const int* Ls, const int* Ks,
+                         int r, int precision, int* col_off, ssa_decomp** out);
+
+/* MSSA (Section 3.1, equation mssa_embedding) of s series of lengths len[p]
+ * with window L (1 < L < min len).  Internally the 2D packing of Section
+ * 5.3: a max(len) x s array, window L x 1.  Outputs use that packing:
+ * V is (max(len) - L + 1) x s with NaN beyond K_p, reconstructions
+ * max(len) x s with NaN beyond len[p]. */
 int ssa_decompose_multi(ssa_ctx* ctx, const double* const* series, const int* len, int s, int L,
                         int r, int precision, ssa_decomp** out);
 

@@ -92,8 +92,12 @@ class Decomposition:
         return {k: getattr(st, k) for k, _ in st._fields_}
 
     def unpack(self, rec):
-        """Cut arrays over the packed M-2D-SSA array (..., nx, ny) into the
-        images: a list of (..., nx_p, ny_p) views."""
+        """Cut arrays over a packed array (..., nx, ny) into its parts: for
+        M-2D-SSA a list of (..., nx_p, ny_p) image views, for a mosaic
+        Hankel decomposition the nested list (block rows, block columns) of
+        (..., L_i + K_j - 1) series views."""
+        if getattr(self, "mosaic_layout", None) is not None:
+            return [[rec[..., i, c:c + n] for i, c, n in row] for row in self.mosaic_layout]
         return [rec[..., :a, c:c + b] for a, c, b in self.m2d_layout]
 
     def extend(self, r: int):
@@ -270,6 +274,33 @@ class Context:
                                       _prec(precision), _ptr(off), C.byref(h)), "ssa_decompose_m2d")
         d = Decomposition(self, h.value)
         d.m2d_layout = [(int(a), int(c), int(b)) for a, b, c in zip(nx, ny, off)]   # (rows, col offset, cols)
+        return d
+
+    def decompose_mosaic(self, series, Ls, Ks, r: int, precision="fp64") -> Decomposition:
+        """Mosaic Hankel SSA: series[i][j] (length Ls[i] + Ks[j] - 1) gives
+        block (i, j), the Ls[i] x Ks[j] Hankel matrix.  The handle refers to
+        the packed array; ``unpack(rec)`` of the returned handle cuts a
+        reconstruction back into the nested list of series."""
+        Ls = [int(v) for v in Ls]
+        Ks = [int(v) for v in Ks]
+        if len(series) != len(Ls) or any(len(row) != len(Ks) for row in series):
+            raise ValueError("series must be a len(Ls) x len(Ks) nested list")
+        arrs = []
+        for i, L in enumerate(Ls):
+            for j, K in enumerate(Ks):
+                a = np.ascontiguousarray(series[i][j], dtype=np.float64)
+                if a.ndim != 1 or len(a) != L + K - 1:
+                    raise ValueError("series (%d, %d) needs Ls[i] + Ks[j] - 1 = %d values" % (i, j, L + K - 1))
+                arrs.append(a)
+        ptrs = (C.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+        ls = np.array(Ls, np.int32)
+        ks = np.array(Ks, np.int32)
+        off = np.zeros(len(Ks), np.int32)
+        h = C.c_void_p()
+        check(lib().ssa_decompose_mosaic(self._h, ptrs, len(Ls), len(Ks), _ptr(ls), _ptr(ks), r, _prec(precision),
+                                         _ptr(off), C.byref(h)), "ssa_decompose_mosaic")
+        d = Decomposition(self, h.value)
+        d.mosaic_layout = [[(i, int(off[j]), L + K - 1) for j, K in enumerate(Ks)] for i, L in enumerate(Ls)]
         return d
 
     def decompose_multi(self, series, L: int, r: int, precision="fp64") -> Decomposition:

@@ -2537,6 +2537,46 @@ int ssa_decompose_m2d(ssa_ctx* ctx, const double* const* images, const int* nx, 
     return rc ? rc : st;
 }
 
+int ssa_decompose_mosaic(ssa_ctx* ctx, const double* const* series, int s, int t, const int* Ls, const int* Ks,
+                         int r, int precision, int* col_off, ssa_decomp** out) {
+    if (!out) return fail(SSA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!series || !Ls || !Ks || s <= 0 || t <= 0) return fail(SSA_EINVAL, "no blocks");
+    int Lm = 0;
+    for (int i = 0; i < s; ++i) {
+        if (Ls[i] <= 0) return fail(SSA_EINVAL, "block row sizes L_i must be positive");
+        Lm = std::max(Lm, Ls[i]);
+    }
+    for (int j = 0; j < t; ++j)
+        if (Ks[j] <= 0) return fail(SSA_EINVAL, "block column sizes K_j must be positive");
+    for (int e = 0; e < s * t; ++e)
+        if (!series[e]) return fail(SSA_EINVAL, "NULL series");
+    // block column j from column off[j]: Lm + K_j - 1 columns, then one NaN
+    // column (none after the last)
+    std::vector<long> off(t);
+    long width = 0;
+    for (int j = 0; j < t; ++j) {
+        off[j] = width;
+        width += (long)Lm + Ks[j];
+    }
+    width -= 1;
+    if ((double)s * (double)width > 2e9) return fail(SSA_EINVAL, "packed array too large");
+    std::vector<double> x((size_t)s * width, std::nan(""));
+    for (int i = 0; i < s; ++i)
+        for (int j = 0; j < t; ++j)
+            std::memcpy(&x[(size_t)i * width + off[j]], series[(size_t)i * t + j],
+                        (size_t)(Ls[i] + Ks[j] - 1) * sizeof(double));
+    // window: s rows, row i its first L_i cells
+    std::vector<uint8_t> wm((size_t)s * Lm, 0);
+    for (int i = 0; i < s; ++i) std::memset(&wm[(size_t)i * Lm], 1, (size_t)Ls[i]);
+    if (col_off)
+        for (int j = 0; j < t; ++j) col_off[j] = (int)off[j];
+    ssa_request q{x.data(), s, (int)width, nullptr, wm.data(), s, Lm, r, precision, 0x5eedULL};
+    int st = SSA_OK;
+    int rc = decompose_many(ctx, 1, &q, out, &st, false);
+    return rc ? rc : st;
+}
+
 int ssa_get_dims(const ssa_decomp* d, int* lx, int* ly, int* kx, int* ky, long* L, long* K, int* r, int* nx,
                  int* ny) {
     if (!d) return fail(SSA_EINVAL, "handle is NULL");

@@ -980,3 +980,62 @@ def test_fp32_vectors_stay_orthonormal(ctx, name):
     err = np.max(np.abs(B.T @ B - np.eye(B.shape[1])))
     print(f"{name}: |B^T B - I| = {err:.2e} (side {side})")
     assert err <= 1e-6, (name, err)
+
+
+def _mosaic_case(Ls, Ks, seed=61):
+    """Series (i, j): a rank-2 mosaic component a_i b_j cos(0.3 n + p_i + q_j),
+    a weaker one of frequency 1.1 and noise."""
+    g = np.random.default_rng(seed)
+    a, p, a2, p2 = (g.uniform(0.5, 2, len(Ls)), g.uniform(0, 6, len(Ls)), g.uniform(0.2, 0.6, len(Ls)),
+                    g.uniform(0, 6, len(Ls)))
+    b, q = g.uniform(0.5, 2, len(Ks)), g.uniform(0, 6, len(Ks))
+    out = []
+    for i, L in enumerate(Ls):
+        row = []
+        for j, K in enumerate(Ks):
+            n = np.arange(L + K - 1)
+            row.append(a[i] * b[j] * np.cos(0.3 * n + p[i] + q[j]) + a2[i] * np.cos(1.1 * n + p2[i] + q[j])
+                       + 0.1 * g.standard_normal(len(n)))
+        out.append(row)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("Ls,Ks", [([12, 7, 15], [40, 25, 33]), ([30], [60]), ([9], [50, 41, 70]), ([6, 14, 9, 11], [45])])
+def test_mosaic_matches_oracle(ctx, prec, Ls, Ks):
+    """Mosaic Hankel SSA: sigma against the SVD of the explicit mosaic matrix
+    (the oracle's definition), each series' reconstruction against the
+    oracle's block-wise anti-diagonal averages of the same group."""
+    ser = _mosaic_case(Ls, Ks)
+    tol = TOL[prec]
+    r = 6
+    M = oracle.mosaic_hankel(ser, Ls, Ks)
+    so = np.linalg.svd(M, compute_uv=False)
+    d = ctx.decompose_mosaic(ser, Ls, Ks, r, precision=prec)
+    assert d.L == sum(Ls) and d.K == sum(Ks)
+    assert sigma_err(d.sigma, so) <= tol, (prec, Ls, Ks, sigma_err(d.sigma, so))
+    xnorm = np.sqrt(sum(np.sum(x ** 2) for row in ser for x in row))
+    checked = 0
+    for k in range(1, r):
+        gap = so[k - 1] - so[k]
+        if gap < 1e-3 * so[0]:
+            continue
+        g = list(range(k))
+        ref = oracle.reconstruct_mosaic(ser, Ls, Ks, g)
+        got = d.unpack(d.reconstruct([g])[0])
+        e = np.sqrt(sum(np.sum((got[i][j] - ref[i][j]) ** 2) for i in range(len(Ls)) for j in range(len(Ks))))
+        assert e / xnorm <= C_SUB * tol * so[0] / gap, (prec, Ls, Ks, k, e / xnorm)
+        checked += 1
+    assert checked > 0
+
+
+def test_mosaic_errors(ctx):
+    import paper_1309_5050_amd as S
+    ser = _mosaic_case([5, 6], [9, 8])
+    with pytest.raises(ValueError):
+        ctx.decompose_mosaic(ser, [5, 6], [9, 7], 2)       # lengths do not match the sizes
+    with pytest.raises(ValueError):
+        ctx.decompose_mosaic(ser[:1], [5, 6], [9, 8], 2)   # one block row missing
+    bad = [[np.zeros(4 + K - 1) for K in (9, 8)], [np.zeros(0 + K - 1) for K in (9, 8)]]
+    with pytest.raises(S.SsaError):
+        ctx.decompose_mosaic(bad, [4, 0], [9, 8], 2)       # an empty block row
