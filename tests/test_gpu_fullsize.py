@@ -91,3 +91,50 @@ def test_full_size_shaped_covered_set_and_weights(ctx):
     assert np.array_equal(d.weights, sh.W)
     rec = d.reconstruct([[0, 1, 2, 3]])
     assert np.array_equal(~np.isnan(rec[0]), sh.covered)
+
+
+def test_full_size_batched_as_timed(ctx):
+    """The timed configuration: a batch of device-resident 512 x 512 images
+    (64 x 64 window, r = 30, FP32 products) through decompose_batch_dev and
+    reconstruct_batch_dev into device outputs.  The batch's first image is
+    the stored oracle case: sigma, stable subspaces and reconstructions at
+    sampled cells against the oracle; the others against single-image
+    decompositions of the same images (a result must not depend on the
+    batch it runs in)."""
+    import torch
+    dev = torch.device("cuda:0")
+    w = W.config(2)
+    g = golden(2)
+    so, Ug = g["sigma"], g["U"]
+    tol = TOL["fp32"]
+    imgs = [w["x"]] + [W.image_2d(seed=1000 + i)["x"] for i in range(7)]
+    xs = [torch.tensor(x, device=dev) for x in imgs]
+    groups = [[0, 1], [2, 3], [4, 5]]
+    outs = [torch.empty((len(groups), 512, 512), dtype=torch.float64, device=dev) for _ in imgs]
+    ds = ctx.decompose_batch_dev(xs, w["window"], w["r"], precision="fp32")
+    assert not any(isinstance(d, Exception) for d in ds)
+    type(ctx).reconstruct_batch_dev(ds, groups, outs)
+    torch.cuda.synchronize()
+    d0 = ds[0]
+    assert d0.stats["converged"] == 1
+    assert sigma_err(d0.sigma, so) <= tol
+    U, _ = d0.vectors_lex()
+    nv = Ug.shape[1]
+    for grp, gap in stable_groups(so, nv):
+        assert proj_dist(U[:, grp], Ug[:, grp]) <= C_SUB * tol * so[0] / gap, grp
+    sh = oracle.shapes(w["x"], window=w["window"])
+    Vg = np.stack([oracle.rmatvec(w["x"], sh, Ug[:, k]) / so[k] for k in range(nv)], axis=1)
+    rng = np.random.default_rng(11)
+    cells = rng.integers(0, 512, (800, 2))
+    gaps = {tuple(gr): gap for gr, gap in stable_groups(so, nv)}
+    rms = np.sqrt(np.mean(w["x"] ** 2))
+    rec0 = outs[0].cpu().numpy()
+    for k, grp in enumerate(groups):
+        ref = oracle.reconstruct_at(sh, so, Ug, Vg, grp, cells)
+        e = np.sqrt(np.mean((rec0[k][cells[:, 0], cells[:, 1]] - ref) ** 2)) / rms
+        assert e <= C_SUB * tol * so[0] / min(gaps[(i,)] for i in grp), (grp, e)
+    for i in range(1, len(imgs)):
+        single = ctx.decompose(imgs[i], w["window"], w["r"], precision="fp32")
+        s1 = single.sigma
+        assert ds[i].stats["converged"] == 1
+        assert np.max(np.abs(ds[i].sigma - s1)) <= 2 * tol * s1[0], i
