@@ -60,8 +60,8 @@ def lib():
         L.orc_rmatvec.argtypes = L.orc_matvec.argtypes
         L.orc_svd_jacobi.argtypes = [C.c_long, C.c_long, _d, C.c_double, C.c_int, _d, _d, _d]
         L.orc_svd_jacobi.restype = C.c_int
-        L.orc_svd_gram.argtypes = [C.c_long, C.c_long, _d, C.c_double, C.c_int, C.c_int, _d, _d, _d]
-        L.orc_svd_gram.restype = C.c_int
+        L.orc_eig_gram.argtypes = [C.c_long, _d, C.c_double, C.c_int, _d, _d]
+        L.orc_eig_gram.restype = C.c_int
         L.orc_reconstruct.argtypes = [C.c_int, C.c_int, C.c_int, _i, _i, C.c_long, _i, _i, C.c_int,
                                       _d, _d, _d, C.c_int, _i, _d]
         L.orc_reconstruct_mssa.argtypes = [C.c_int, _i, C.c_int, C.c_int, _d, _d, _d, C.c_int, _i, _d]
@@ -207,29 +207,50 @@ def svd(X, method: str = "jacobi", tol: float = 1e-14, max_sweeps: int = 100, nv
     X = np.ascontiguousarray(X, dtype=np.float64)
     m, n = X.shape
     d = min(m, n)
+    if method == "gram":
+        if m > n:
+            # S = X X^T is the larger Gram; decompose X^T and swap roles
+            s, V, U = svd(X.T, "gram", tol, max_sweeps)
+            return s, U, _sign_rule(U, V)
+        # S = X X^T by a library matrix product, its eigenpairs by cyclic
+        # Jacobi, V_j = X^T U_j / sigma_j by a library matrix product
+        S = np.ascontiguousarray(X @ X.T)
+        S = 0.5 * (S + S.T)
+        lam = np.zeros(m)
+        Ucm = np.zeros(m * m)
+        sweeps = lib().orc_eig_gram(m, S, tol, max_sweeps, lam, Ucm)
+        if sweeps < 0:
+            raise RuntimeError("Jacobi iteration did not converge")
+        U = Ucm.reshape(m, m).T[:, :d].copy()
+        sig = np.sqrt(np.maximum(lam[:d], 0.0))
+        nv = d if nvec < 0 or nvec > d else nvec
+        V = np.zeros((n, d))
+        pos = sig[:nv] > 0
+        if nv:
+            V[:, :nv] = X.T @ U[:, :nv]
+            V[:, :nv][:, pos] /= sig[:nv][pos]
+            V[:, :nv][:, ~pos] = 0.0
+        return sig, U, _sign_rule(U, V)
     sig = np.zeros(d)
     Ucm = np.zeros(m * d)
     Vcm = np.zeros(n * d)
-    fn = lib().orc_svd_jacobi if method == "jacobi" else lib().orc_svd_gram
-    if method == "gram" and m > n:
-        # S = X X^T is the larger Gram; decompose X^T and swap roles
-        s, V, U = svd(X.T, "gram", tol, max_sweeps)
-        # keep the sign rule on U
-        for k in range(d):
-            a = int(np.argmax(np.abs(U[:, k])))
-            if U[a, k] < 0:
-                U[:, k] *= -1
-                V[:, k] *= -1
-        return s, U, V
-    if method == "gram":
-        sweeps = fn(m, n, X, tol, max_sweeps, nvec, sig, Ucm, Vcm)
-    else:
-        sweeps = fn(m, n, X, tol, max_sweeps, sig, Ucm, Vcm)
+    sweeps = lib().orc_svd_jacobi(m, n, X, tol, max_sweeps, sig, Ucm, Vcm)
     if sweeps < 0:
         raise RuntimeError("Jacobi iteration did not converge")
     U = Ucm.reshape(d, m).T.copy()
     V = Vcm.reshape(d, n).T.copy()
     return sig, U, V
+
+
+def _sign_rule(U, V):
+    """Flips (U_k, V_k) in place so that the entry of largest magnitude of
+    U_k is positive (lowest index on ties); returns V."""
+    for k in range(U.shape[1]):
+        a = int(np.argmax(np.abs(U[:, k])))
+        if U[a, k] < 0:
+            U[:, k] *= -1
+            V[:, k] *= -1
+    return V
 
 
 def gram_rows(X, r0: int, r1: int) -> np.ndarray:

@@ -388,63 +388,31 @@ static int jacobi_eig(int n, double *S, double *lam, double *Z, double tol, int 
 }
 
 /* The SVD step exactly as the paper defines it (Section 2.1, Step 2):
- * S = X X^T, lambda_j and U_j its eigenpairs, V_j = X^T U_j / sqrt(lambda_j).
- * X is m x n row-major.  Returns the d = min(m, n) leading triplets (those
- * with lambda_j > 0; trailing ones are zero).  Used for the large workloads,
- * where the one-sided iteration over the long columns is too slow. */
-int orc_svd_gram(long m, long n, const double *X, double tol, int max_sweeps,
-                 int nvec, double *sig, double *U, double *V)
+ * lambda_j and U_j are the eigenpairs of S = X X^T, and the caller forms
+ * V_j = X^T U_j / sqrt(lambda_j).  S (m x m, row-major, overwritten) is
+ * formed by the caller with a library matrix product.  Outputs the
+ * eigenvalues in decreasing order in lam and the matching eigenvectors as
+ * the columns of U (column-major, column k at U + k*m).  Used for the large
+ * workloads, where the one-sided iteration over the long columns is too
+ * slow.  Returns the sweep count or -1. */
+int orc_eig_gram(long m, double *S, double tol, int max_sweeps, double *lam, double *U)
 {
     int mm = (int)m;
-    double *S = (double *)calloc((size_t)m * m, sizeof(double));
-    /* S = X X^T, summed over column chunks so that a block of rows stays in
-     * cache; every entry is still the plain sum over all columns. */
-    const int RB = 32;
-    const long CB = 2048;
-    int nb = (mm + RB - 1) / RB;
-    #pragma omp parallel for schedule(dynamic, 1)
-    for (int t = 0; t < nb * nb; ++t) {
-        int bi = t / nb, bj = t % nb;
-        if (bj > bi) continue;
-        for (long c0 = 0; c0 < n; c0 += CB) {
-            long c1 = c0 + CB < n ? c0 + CB : n;
-            for (int i = bi * RB; i < (bi + 1) * RB && i < mm; ++i)
-                for (int j = bj * RB; j < (bj + 1) * RB && j <= i; ++j)
-                    S[(long)i * m + j] += dot(X + (long)i * n + c0, X + (long)j * n + c0, c1 - c0);
-        }
-    }
-    for (int i = 0; i < mm; ++i)
-        for (int j = 0; j < i; ++j) S[(long)j * m + i] = S[(long)i * m + j];
-    double *lam = (double *)malloc(sizeof(double) * m);
+    double *ev = (double *)malloc(sizeof(double) * m);
     double *Z = (double *)malloc(sizeof(double) * m * m);
-    int sw = jacobi_eig(mm, S, lam, Z, tol, max_sweeps);
-    int d = (int)(m < n ? m : n);
-    if (nvec < 0 || nvec > d) nvec = d;
-    /* order by eigenvalue, keep d */
+    int sw = jacobi_eig(mm, S, ev, Z, tol, max_sweeps);
     int *perm = (int *)malloc(sizeof(int) * m);
     for (int k = 0; k < mm; ++k) perm[k] = k;
-    for (int a = 1; a < mm; ++a) {
+    for (int a = 1; a < mm; ++a) {                /* insertion sort, stable */
         int p = perm[a], b = a - 1;
-        while (b >= 0 && lam[perm[b]] < lam[p]) { perm[b + 1] = perm[b]; --b; }
+        while (b >= 0 && ev[perm[b]] < ev[p]) { perm[b + 1] = perm[b]; --b; }
         perm[b + 1] = p;
     }
-    for (int k = 0; k < d; ++k) {
-        int p = perm[k];
-        double l = lam[p] > 0 ? lam[p] : 0.0;
-        sig[k] = sqrt(l);
-        memcpy(U + (long)k * m, Z + (long)p * m, sizeof(double) * m);
+    for (int k = 0; k < mm; ++k) {
+        lam[k] = ev[perm[k]];
+        memcpy(U + (long)k * m, Z + (long)perm[k] * m, sizeof(double) * m);
     }
-    /* V_j = X^T U_j / sigma_j for the first nvec triplets (zero after) */
-    memset(V, 0, sizeof(double) * (size_t)n * d);
-    #pragma omp parallel for schedule(static)
-    for (long j = 0; j < n; ++j)
-        for (int k = 0; k < nvec; ++k) {
-            double acc = 0.0;
-            for (long i = 0; i < m; ++i) acc += X[i * n + j] * U[(long)k * m + i];
-            V[(long)k * n + j] = sig[k] > 0 ? acc / sig[k] : 0.0;
-        }
-    sort_and_sign(m, n, d, sig, U, V);
-    free(S); free(lam); free(Z); free(perm);
+    free(ev); free(Z); free(perm);
     return sw;
 }
 

@@ -257,6 +257,41 @@ def test_elementary_components_sum_to_input():
     assert np.allclose(g1[cov] + g2[cov], w["x"][cov], atol=1e-11)
 
 
+def _reconstruct_at_cases():
+    """A shaped case, a holed non-square 2D case with a holed window, and 1D
+    series in both orientations: reconstruct_at must equal reconstruct."""
+    cases = []
+    w = W.small_shaped()
+    cases.append((w["x"], w["mask"], w["wmask"], w["window"]))
+    g = np.random.default_rng(41)
+    x = g.standard_normal((17, 11))
+    x[3:5, 6:8] = np.nan
+    x[12, 2] = np.nan
+    wm = np.ones((5, 3), np.uint8)
+    wm[2, 1] = 0
+    cases.append((x, None, wm, (5, 3)))
+    t = np.arange(1, 61)
+    y = np.cos(2 * np.pi * t / 7) + 0.05 * g.standard_normal(60)
+    cases.append((y.reshape(60, 1), None, None, (18, 1)))
+    cases.append((y.reshape(1, 60), None, None, (1, 18)))
+    return cases
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_reconstruct_at_equals_reconstruct_everywhere(case):
+    x, mask, wmask, window = _reconstruct_at_cases()[case]
+    sh, s, U, V = oracle.decompose(x, mask, wmask, window)
+    nx, ny = sh.nx, sh.ny
+    cells = np.array([(i, j) for i in range(nx) for j in range(ny)], np.int32)
+    for group in ([0], [0, 1, 2], list(range(len(s)))):
+        ref = oracle.reconstruct(sh, s, U, V, group)
+        got = oracle.reconstruct_at(sh, s, U, V, group, cells).reshape(nx, ny)
+        assert np.array_equal(np.isnan(got), np.isnan(ref))
+        assert np.array_equal(~np.isnan(ref), sh.covered)
+        cov = sh.covered
+        assert np.allclose(got[cov], ref[cov], rtol=1e-12, atol=1e-12 * np.nanmax(np.abs(ref)))
+
+
 def test_hankelization_is_least_squares():
     # The averaging is the Frobenius-optimal structured approximation
     # (Section 2.1, Step 4): solve min_y |T(y) - Y|_F densely.
