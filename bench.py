@@ -1,6 +1,6 @@
 """Benchmark: batched Shaped 2D-SSA decompositions + reconstructions per second.
 
-Workload (default): the 2D-SSA image workload -- 512x512 images, each a sum of
+Headline workload: the 2D-SSA image workload -- 512x512 images, each a sum of
 three planar cosines (periods 8..64 px, random directions) plus N(0, 0.2^2)
 noise, window 64x64, r = 30 eigentriples, reconstruction of the groups
 {1,2}, {3,4}, {5,6} (0-based {0,1}, {2,3}, {4,5}).  A step decomposes and
@@ -8,14 +8,23 @@ reconstructs one batch of B images already resident in device memory.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--batch 64] [--precision fp32]
 
-Prints one JSON line.  Besides the headline rate it reports the plain
-single-instance FP64 path on the same GPU, the roofline of the dominant
-kernel (HIP-event timing of its launches inside the timed region) and the
-CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line.  Besides the headline rate it reports:
+
+* ``roofline``: the whole FFT product (X v and X^T u) against the HBM peak,
+  with the algorithmic bytes per product B_mv = b (K + L) + 2 b M_A (M_B/2 + 1)
+  (vector in, vector out, spectrum read once; b = 4 for FP32 products, 8 for
+  FP64) times the products of the timed batches, over the summed HIP-event
+  time of the product kernels in the timed region (one launch in seven of
+  each class timed, scaled by the class's launch count).  ``roofline_kernels``
+  splits it by kernel class, each with the part of B_mv it moves.
+* the same batched measurement in FP64 and for the 1D, MSSA and shaped
+  workloads, the plain single-instance FP64 path, the paper's own timing
+  experiments on a Mars-like stand-in, and the CPU oracle timed on the host.
 """
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -24,6 +33,280 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
+PROFILE_EVERY = 7
+# kernel classes of the FFT product (the library's timing classes) and the
+# kernels behind them on the register (power-of-two) path
+GRID_CLASSES = ["row_in", "col", "row_mid", "row_out"]
+ROWFAM_CLASSES = ["row_in", "rowfam_mid", "rowfam_out"]
+KERNEL_OF = {"row_in": "k_rowr_in", "col": "k_colr", "row_mid": "k_rowr_mid", "row_out": "k_rowr_out",
+             "rowfam_mid": "k_row_mid", "rowfam_out": "k_row_out"}
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fft_product_image512_batch64_fp32_traffic.md")
+# the paper's decomposition timings (R, Rssa 0.10 with FFTW; hardware not
+# stated), elapsed seconds, for the three settings on its 258 x 275 image
+PAPER_SECONDS = {"eigen_25x25": 3.843, "lanczos_25x25": 0.519, "lanczos_160x80_r50": 0.587,
+                 "shaped_circle15_mask": 0.684}
+
+
+def _prec_bytes(prec):
+    return 8 if prec == "fp64" else 4
+
+
+def bmv_of(d, prec):
+    """Algorithmic bytes of one product of decomposition d."""
+    st = d.stats
+    b = _prec_bytes(prec)
+    return b * (d.K + d.L) + 2 * b * st["fft_rows"] * (st["fft_cols"] // 2 + 1)
+
+
+def class_bytes(ds, prec, rowfam):
+    """Part of the timed products' algorithmic bytes each kernel class moves.
+    Per step (two products): the input pass reads the short-side vector, the
+    column passes read the spectrum once per product, the middle pass writes
+    the long-side result of the first product and reads the long-side input
+    of the second, the output pass writes the short-side result."""
+    b = _prec_bytes(prec)
+    out = {}
+    for d in ds:
+        st = d.stats
+        steps = st["steps"]
+        nshort, nlong = (d.L, d.K) if st["side"] == 0 else (d.K, d.L)
+        xh = 2 * b * st["fft_rows"] * (st["fft_cols"] // 2 + 1)
+        if rowfam:
+            parts = {"row_in": b * nshort, "rowfam_mid": 2 * b * nlong + xh, "rowfam_out": b * nshort + xh}
+        else:
+            parts = {"row_in": b * nshort, "col": 2 * xh, "row_mid": 2 * b * nlong, "row_out": b * nshort}
+        for k, v in parts.items():
+            out[k] = out.get(k, 0.0) + steps * v
+    return out
+
+
+def measured_traffic():
+    """Counter bytes per dispatch of each product kernel from the committed
+    rocprofv3 summary, or None when the kernel sources have changed since
+    the counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    per, sha = {}, None
+    for line in open(TRAFFIC_SUMMARY):
+        f = line.split()
+        if len(f) >= 2 and f[0] == "source-sha256:":
+            sha = f[1]
+        if len(f) == 4 and f[0] == "traffic:":
+            per[f[1]] = (float(f[2]), float(f[3]))   # class -> (bytes per dispatch, dispatches counted)
+    h = hashlib.sha256()
+    for f in ("common.hpp", "device.hpp", "fft.hpp", "regfft.hpp", "kernels.hip"):
+        with open(os.path.join(ROOT, "paper_1309_5050_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return per if sha == h.hexdigest() and per else None
+
+
+def product_roofline(prof, ds, prec, rowfam, nbatch, traffic=None):
+    """Whole-product roofline and per-class entries from a profile record of
+    nbatch timed batches, all like the batch ds (the same inputs each time,
+    so the same steps)."""
+    classes = ROWFAM_CLASSES if rowfam else GRID_CLASSES
+    cb = {k: nbatch * v for k, v in class_bytes(ds, prec, rowfam).items()}
+    products = nbatch * 2 * sum(d.stats["steps"] for d in ds)
+    bmv_total = nbatch * sum(2 * d.stats["steps"] * bmv_of(d, prec) for d in ds)
+    kern, t_total = {}, 0.0
+    for c in classes:
+        p = prof[c]
+        if p["launches"] == 0:
+            continue
+        per_launch = p["ms"] / p["launches"]
+        ms = per_launch * p["all_launches"]
+        t_total += ms
+        gbs = cb[c] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        kern[c] = {"kernel": KERNEL_OF[c], "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": gbs / HBM_PEAK_GBS, "ms_per_launch": per_launch, "launches": p["all_launches"],
+                   "launches_timed": p["launches"], "ms_total": ms,
+                   "bytes_per_launch": cb[c] / max(p["all_launches"], 1)}
+    ach = bmv_total / (t_total * 1e-3) / 1e9 if t_total > 0 else 0.0
+    tr = None
+    if traffic:
+        counted = sum(traffic[c][0] * kern[c]["launches"] for c in kern if c in traffic)
+        if all(c in traffic for c in kern):
+            tr = counted / products
+    bmv_mean = bmv_total / max(products, 1)
+    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": tr,
+            "kernel": "FFT product: " + " + ".join(KERNEL_OF[c] for c in classes),
+            "unit_of_work": "one product X v or X^T u", "bytes_per_product": bmv_mean, "products": products,
+            "ms_total": t_total, "us_per_product": 1e3 * t_total / max(products, 1),
+            "traffic_over_bmv": (tr / bmv_mean) if tr else None, "timed_every": PROFILE_EVERY}
+    return roof, kern
+
+
+def run_batched(S, ctx, torch, xs, window, r, groups, prec, steps, warmup, masks=None, extra_classes=()):
+    """Time `steps` batches (decompose + reconstruct, inputs on the device)
+    after `warmup` untimed ones; returns (decomps/s, ms per step, the last
+    batch's handles, the profile record)."""
+    dev = xs[0].device
+    outs = [torch.empty((len(groups),) + tuple(x.shape), dtype=torch.float64, device=dev) for x in xs]
+
+    def step():
+        ds = ctx.decompose_batch_dev(xs, window, r, precision=prec, masks=masks)
+        bad = [d for d in ds if isinstance(d, Exception)]
+        if bad:
+            raise bad[0]
+        S.Context.reconstruct_batch_dev(ds, groups, outs)
+        return ds
+
+    for _ in range(warmup):
+        ds = step()
+        del ds
+    torch.cuda.synchronize()
+    rowfam = None
+    kinds = GRID_CLASSES + ROWFAM_CLASSES[1:] + list(extra_classes)
+    ctx.profile(",".join(kinds), every=PROFILE_EVERY)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(steps):
+        last = None          # a step's results are released before the next step
+        last = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read(kinds)
+    ctx.profile(None)
+    rowfam = prof["col"]["all_launches"] == 0
+    dt = t1 - t0
+    return len(xs) * steps / dt, 1e3 * dt / steps, last, prof, rowfam
+
+
+def note(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def config_line(S, W, ctx, torch, which, prec, steps, warmup):
+    """Batched rate and product roofline of one of the other workloads."""
+    import numpy as np
+    note(f"workload {which} ({prec})")
+    dev = torch.device("cuda:0")
+    if which == 1:
+        B, groups = 64, [[0, 1], [2, 3], [4]]
+        ws = [W.series_1d(seed=1 + i) for i in range(B)]
+        # a series as a one-row array with a one-row window (the same
+        # trajectory matrix as the column orientation)
+        xs = [torch.tensor(w["x"][None, :], device=dev) for w in ws]
+        masks, window, r = None, (1, ws[0]["window"]), ws[0]["r"]
+        name = "1D SSA N=1000, L=500, r=10, groups {1,2},{3,4},{5}"
+    elif which == 3:
+        B, groups = 8, [[0, 1], [2, 3]]
+        ws = [W.mssa_series(seed=3 + i) for i in range(B)]
+        xs = []
+        for w in ws:
+            nmax = max(len(s) for s in w["x"])
+            arr = np.full((len(w["x"]), nmax), np.nan)      # one series per row, NaN after each end
+            for p, s in enumerate(w["x"]):
+                arr[p, :len(s)] = s
+            xs.append(torch.tensor(arr, device=dev))
+        masks, window, r = None, (1, ws[0]["window"]), ws[0]["r"]
+        name = "MSSA 50 series N~U(1000,3000), L=500, r=20, groups {1,2},{3,4}"
+    else:
+        B, groups = 8, [[0, 1, 2, 3]]
+        ws = [W.shaped_disc(seed=4 + i) for i in range(B)]
+        xs = [torch.tensor(w["x"], device=dev) for w in ws]
+        masks = [torch.tensor(w["mask"], device=dev) for w in ws]
+        window, r = ws[0]["window"], ws[0]["r"]
+        name = "shaped 1024x1024 disc r=480 with 10% NaN holes, 32x32 window, r=50, group {1..4}"
+    rate, ms, last, prof, rowfam = run_batched(S, ctx, torch, xs, window, r, groups, prec, steps, warmup,
+                                               masks=masks)
+    roof, kern = product_roofline(prof, last, prec, rowfam, steps)
+    return {"workload": name, "batch": B, "precision": prec, "decomps_per_s": rate, "ms_per_step": ms,
+            "roofline": roof, "roofline_kernels": kern,
+            "lanczos_steps_mean": float(np.mean([d.stats["steps"] for d in last]))}
+
+
+def paper_context(S, W, torch):
+    """The paper's decomposition timings re-run on a synthetic Mars-like
+    stand-in (258 x 275, bright disc on a zero = NA background, planar sines
+    of periods near 5 and 10 px), single decompositions in FP64 from host
+    inputs, r = 50 (the package's default number of eigentriples)."""
+    import numpy as np
+    w = W.mars_like()
+    x, mask = w["x"], w["mask"]
+    full = np.nan_to_num(x)          # the plain 2D-SSA runs decompose the whole array
+    ctx = S.Context(0)
+    out = {"workload": "Mars-like 258x275 stand-in, FP64, r=50, single decomposition from host memory",
+           "paper_seconds_hardware": "not stated (R, Rssa 0.10, FFTW)", "runs": {}}
+
+    def timed(fn, reps=3):
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            d = fn()
+            _ = d.sigma
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            d.free()
+            best = t if best is None else min(best, t)
+        return best
+
+    cases = {
+        "lanczos_25x25": lambda: ctx.decompose(full, (25, 25), 50),
+        "lanczos_160x80_r50": lambda: ctx.decompose(full, (160, 80), 50),
+        "shaped_circle15_mask": lambda: ctx.decompose(x, w["window"], 50, mask=mask, wmask=w["wmask"]),
+        "eigen_25x25": lambda: ctx.decompose(full, (25, 25), 50, method="eigen"),
+    }
+    for k, fn in cases.items():
+        try:
+            t = timed(fn)
+            out["runs"][k] = {"seconds": t, "paper_seconds": PAPER_SECONDS[k], "paper_over_ours": PAPER_SECONDS[k] / t}
+        except S.SsaError as e:
+            out["runs"][k] = {"seconds": None, "paper_seconds": PAPER_SECONDS[k], "error": str(e)}
+    ctx.close()
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(W):
+    """The CPU oracle (explicit trajectory matrix, one-sided Jacobi SVD,
+    averaging by explicit summation) timed on the host: complete
+    decompositions + reconstructions of the reduced 2D workload (128x128
+    image, 16x16 window, r = 30, groups {1,2},{3,4},{5,6}) and of the 1D
+    workload, with every host thread and with one."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+
+    def one(w, groups):
+        t0 = time.perf_counter()
+        sh, s, U, V = oracle.decompose(w["x"], window=w["window"])
+        for g in groups:
+            oracle.reconstruct(sh, s, U, V, g)
+        return time.perf_counter() - t0
+
+    w2 = W.config(2, "small")
+    w1 = W.config(1)
+    g2, g1 = [[0, 1], [2, 3], [4, 5]], [[0, 1], [2, 3], [4]]
+    allc = oracle.num_threads()
+    t2 = one(w2, g2)
+    t1 = one(w1, g1)
+    oracle.set_threads(1)
+    with threadpool_limits(limits=1):
+        t2s = one(w2, g2)
+        t1s = one(w1, g1)
+    oracle.set_threads(allc)
+    return {"value": 1.0 / t2, "unit": "decomps/s", "cores": allc, "kind": "oracle",
+            "sample": "complete oracle decomposition + reconstruction of the reduced 2D workload "
+                      "(128x128 image, 16x16 window: X is 256 x 12769; r=30, 3 groups), all host threads",
+            "cpu_model": cpu_model(), "single_thread_decomps_per_s": 1.0 / t2s,
+            "seconds": {"reduced_2d_all_threads": t2, "reduced_2d_one_thread": t2s,
+                        "series_1000_all_threads": t1, "series_1000_one_thread": t1s},
+            "recorded_full_512x512": {"seconds": 660.0, "threads": 8, "route": "S = X X^T + Jacobi eigenpairs",
+                                      "note": "one run of tests/golden/make_golden.py 2 on the 8-core "
+                                              "build host (Xeon, 2.70 GHz), not re-timed here"}}
 
 
 def main():
@@ -32,14 +315,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=64)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp32_basis32"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--no-single", action="store_true", help="skip the single-instance FP64 comparator")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the w-correlation, forecast, continuation and eigen-method timings")
-    # The serving section is off unless asked for: a full run of it on the
-    # build with the FP32 basis copy ended with a GPU memory fault whose cause
-    # is not found (see the serving tests' skip reason).
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the FP64, 1D, MSSA, shaped and paper-context lines")
     ap.add_argument("--serve", type=int, default=0, metavar="N",
                     help="requests of the mixed serving workload for the latency runs (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -80,52 +362,13 @@ def main():
     groups = [[0, 1], [2, 3], [4, 5]]
     imgs = [W.image_2d(n=n, lw=lw, r=r, seed=1000 + i)["x"] for i in range(B)]
     xs = [torch.tensor(x, device=dev) for x in imgs]
-    outs = [torch.empty((len(groups), n, n), dtype=torch.float64, device=dev) for _ in range(B)]
 
-    def step(prec):
-        ds = ctx.decompose_batch_dev(xs, (lw, lw), r, precision=prec)
-        bad = [d for d in ds if isinstance(d, Exception)]
-        if bad:
-            raise bad[0]
-        S.Context.reconstruct_batch_dev(ds, groups, outs)
-        return ds
-
-    for _ in range(args.warmup):
-        ds = step(args.precision)
-        del ds
-    torch.cuda.synchronize()
-    # HIP events bracket one launch in every PROFILE_EVERY of each timed class
-    # (an odd period samples both directions of the column pass); each
-    # bracketed launch costs the stream two event records
-    ctx.profile(",".join(list(KERNELS) + ["lz_ritz"]), every=PROFILE_EVERY)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    last = None
-    for _ in range(args.steps):
-        last = None          # a step's results are released before the next step
-        last = step(args.precision)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = ctx.profile_read(list(KERNELS) + ["lz_ritz"])
-    ctx.profile(None)
+    note("headline batches")
+    value, ms_step, last, prof, rowfam = run_batched(S, ctx, torch, xs, (lw, lw), r, groups, args.precision,
+                                                     args.steps, args.warmup, extra_classes=("lz_ritz",))
+    roof, kern = product_roofline(prof, last, args.precision, rowfam, args.steps,
+                                  measured_traffic() if args.precision == "fp32" and B == 64 else None)
     stats = last[0].stats
-    dt = t1 - t0
-    value = B * args.steps / dt
-
-    # rooflines of the two product kernels; the dominant one (more time in
-    # the timed region) is the headline
-    roofs = {}
-    for cls, name in KERNELS.items():
-        p = prof[cls]
-        kern_ms = p["ms"] / max(p["launches"], 1)
-        kern_bytes = p["bytes"] / max(p["launches"], 1)
-        achieved = kern_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
-        traffic, traffic_kernel = measured_traffic(name)
-        roofs[cls] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": name,
-                      "ms_per_launch": kern_ms, "bytes_per_launch": kern_bytes, "launches": p["launches"],
-                      "ms_total": p["ms"], "timed_every": PROFILE_EVERY, "traffic_counters_on": traffic_kernel}
-    dominant = max(roofs, key=lambda c: roofs[c]["ms_total"])
     # the matrix-core kernel (FP64 Ritz rotation): its timing class counts
     # floating-point operations
     pr = prof["lz_ritz"]
@@ -135,11 +378,6 @@ def main():
         mfma = {"kernel": "k_lz_ritz", "dtype": "f64", "achieved": tf, "peak": FP64_MFMA_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": tf / FP64_MFMA_PEAK_TFLOPS, "launches": pr["launches"],
                 "ms_per_launch": pr["ms"] / pr["launches"], "flop_per_launch": pr["bytes"] / pr["launches"]}
-    # HbH product rate over the whole product (algorithmic bytes per product)
-    L, K = lw * lw, (n - lw + 1) ** 2
-    b = 4 if args.precision == "fp32" else 8
-    bmv = b * (K + L) + 2 * b * n * (n // 2 + 1)
-    products = 2 * sum(d.stats["steps"] for d in last)
 
     def run_extras():
         """The calls outside the timed batches (w-correlations, forecasts,
@@ -180,8 +418,8 @@ def main():
                      "finite": bool(np.isfinite(fv).all() and np.isfinite(fr).all() and np.isfinite(fw).all())}
         dm.free()
 
-        # continuation: one decomposition of the workload (FP32) extended by
-        # r/5 triplets, against decomposing it afresh with that many
+        # continuation: one decomposition of the workload extended by r/5
+        # triplets, against decomposing it afresh with that many
         r2 = r + max(1, r // 5)
         torch.cuda.synchronize()
         te0 = time.perf_counter()
@@ -230,22 +468,51 @@ def main():
 
     wcor = rforecast = extend = eigen = None
     if not args.no_extras:
+        note("extras")
         wcor, rforecast, extend, eigen = run_extras()
+    del last
+
+    # the same workload in FP64 (the paper's arithmetic), the other workloads,
+    # the reduced 2D workload the CPU oracle is timed on, and the paper's own
+    # timing experiments
+    configs = paper = None
+    if not args.no_configs:
+        configs = {}
+        note("headline workload in fp64")
+        n64 = max(2, args.steps // 2)
+        rate64, ms64, last64, prof64, rf64 = run_batched(S, ctx, torch, xs, (lw, lw), r, groups, "fp64", n64, 1)
+        roof64, kern64 = product_roofline(prof64, last64, "fp64", rf64, n64)
+        configs["image512_fp64"] = {"workload": "2D-SSA 512x512 image, 64x64 window, r=30 (as the headline)",
+                                    "batch": B, "precision": "fp64", "decomps_per_s": rate64, "ms_per_step": ms64,
+                                    "roofline": roof64, "roofline_kernels": kern64}
+        del last64
+        configs["series_1000_fp64"] = config_line(S, W, ctx, torch, 1, "fp64", 3, 1)
+        configs["mssa_50_fp32"] = config_line(S, W, ctx, torch, 3, "fp32", 3, 1)
+        configs["shaped_1024_fp32"] = config_line(S, W, ctx, torch, 4, "fp32", 2, 1)
+        w2 = W.config(2, "small")
+        xr = [torch.tensor(W.image_2d(n=128, lw=16, r=30, seed=2000 + i)["x"], device=dev) for i in range(64)]
+        rr, msr, lr, prr, rfr = run_batched(S, ctx, torch, xr, w2["window"], 30, groups, "fp64", 3, 1)
+        configs["image128_fp64"] = {"workload": "reduced 2D-SSA 128x128 image, 16x16 window, r=30 "
+                                                "(the workload the CPU oracle is timed on)",
+                                    "batch": 64, "precision": "fp64", "decomps_per_s": rr, "ms_per_step": msr}
+        del lr
+        note("paper context")
+        paper = paper_context(S, W, torch)
 
     # plain single-instance FP64 path (same kernels, batch of one)
     single = None
     if not args.no_single:
+        outs1 = [torch.empty((len(groups), n, n), dtype=torch.float64, device=dev) for _ in range(2)]
         reps = 2
         torch.cuda.synchronize()
         lat = []
         for i in range(reps):
             ta = time.perf_counter()
             d = ctx.decompose_batch_dev(xs[i:i + 1], (lw, lw), r, precision="fp64")[0]
-            S.Context.reconstruct_batch_dev([d], groups, outs[i:i + 1])
+            S.Context.reconstruct_batch_dev([d], groups, outs1[i:i + 1])
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - ta)
         single = {"decomps_per_s": reps / sum(lat), "latency_ms": 1e3 * float(np.median(lat))}
-
 
     serving = None
     if args.serve > 0:
@@ -253,7 +520,10 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(imgs[0], lw)
+        note("cpu oracle")
+        cpu = cpu_baseline(W)
+        if configs:
+            cpu["gpu_over_oracle_same_workload"] = configs["image128_fp64"]["decomps_per_s"] / cpu["value"]
 
     line = {
         "metric": "SSA decomps/s (decompose r=30 + reconstruct 3 groups), 512x512 image, 64x64 window",
@@ -262,31 +532,31 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * dt / args.steps,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": "2D-SSA 512x512 image, 64x64 window, r=30, groups {1,2},{3,4},{5,6}",
                    "batch": B, "precision": args.precision + (" products, fp64 Lanczos" if
-                                                             args.precision == "fp32" else ""),
+                                                             args.precision != "fp64" else ""),
                    "parallelism": "batched on 1 GPU"},
-        "roofline": roofs[dominant],
-        "roofline_kernels": roofs,
+        "roofline": roof,
+        "roofline_kernels": kern,
         "mfma": mfma,
-        "wcor": wcor,
-        "rforecast": rforecast,
-        "extend": extend,
-        "eigen": eigen,
-        "hbh_product": {"bytes_per_product": bmv, "products_per_step": products,
-                        "effective_GBs": bmv * products / (dt / args.steps) / 1e9},
         "lanczos": {"steps": stats["steps"], "restarts": stats["restarts"], "basis": stats["basis"],
                     "max_resid_over_sigma1": stats["max_resid"]},
         "host_ms_per_batch": {"setup": B * stats["ms_setup"], "lanczos": B * stats["ms_lanczos"],
                               "finish": B * stats["ms_finish"]},
         "fp64_single_instance": single,
         "speedup_vs_fp64_single": (value / single["decomps_per_s"]) if single else None,
+        "configs": configs,
+        "paper_context": paper,
+        "wcor": wcor,
+        "rforecast": rforecast,
+        "extend": extend,
+        "eigen": eigen,
         "cpu_baseline": cpu,
         "serving": serving,
     }
@@ -442,58 +712,6 @@ def serve_bench(S, W, n_req):
     if sustained:
         out["runs"].append(_served_run(S, data, "fp32", 0.8 * sustained, seed=13))
     return out
-
-
-# kernel classes timed in the timed region -> kernel names
-KERNELS = {"col": "k_colr", "row_mid": "k_rowr_mid"}
-PROFILE_EVERY = 7
-
-
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when the kernel sources have changed since the counters
-    were taken."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_image512_batch64_fp32_traffic.md")
-    if not os.path.exists(path):
-        return None, None
-    vals = {}
-    for line in open(path):
-        line = line.strip()
-        for key in ("traffic-bytes-per-launch:", "source-sha256:", "kernel-instance:"):
-            if line.startswith(key):
-                vals[key] = line[len(key):].strip()
-    h = hashlib.sha256()
-    for f in ("common.hpp", "device.hpp", "fft.hpp", "regfft.hpp", "kernels.hip"):
-        with open(os.path.join(ROOT, "paper_1309_5050_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    if vals.get("source-sha256:") != h.hexdigest() or "traffic-bytes-per-launch:" not in vals:
-        return None, vals.get("kernel-instance:")
-    return float(vals["traffic-bytes-per-launch:"]), vals.get("kernel-instance:")
-
-
-def cpu_baseline(x, lw):
-    """The oracle's explicit S = X X^T formation on a slice of rows of one
-    decomposition of the same workload, scaled to a whole decomposition.
-    The Jacobi eigen-decomposition of S and the averaging are left out, so
-    the true oracle rate is lower than the figure reported."""
-    import numpy as np
-
-    import oracle
-    t0 = time.perf_counter()
-    sh = oracle.shapes(x, window=(lw, lw))
-    X = oracle.trajectory(x, sh)
-    t_traj = time.perf_counter() - t0
-    rows = 48
-    t1 = time.perf_counter()
-    oracle.gram_rows(X, 0, rows)
-    t_slice = time.perf_counter() - t1
-    L = X.shape[0]
-    full = t_traj + t_slice * (L * L / 2.0) / (rows * L)
-    return {"value": 1.0 / full, "unit": "decomps/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"explicit trajectory matrix ({L}x{X.shape[1]}) + S=XX^T rows 0..{rows - 1} of {L}, "
-                      f"scaled to the full S; Jacobi eigen step and averaging not included (upper bound)",
-            "seconds_measured": t_traj + t_slice}
 
 
 if __name__ == "__main__":

@@ -61,16 +61,25 @@ enum {
                           one cell, unsupported transform length, NULL input */
     SSA_EEMPTY = -2,   /* no window position fits inside N (K is empty) */
     SSA_ERANK = -3,    /* r < 1 or r >= min(|L|, |K|): the rank of X is at
-                          most min(L, K) (Section 2.1, Step 2) */
+                          most min(L, K) (Section 2.1, Step 2); or r > 120:
+                          the Lanczos basis holds at most 128 vectors and a
+                          restart keeps r of them */
     SSA_ENOMEM = -4,   /* device memory or the context's budget exhausted */
-    SSA_ENOCONV = -5,  /* the bidiagonalisation reached its step limit; the
-                          triplets are still returned */
+    SSA_ENOCONV = -5,  /* the bidiagonalisation reached its step limit (3000
+                          steps, lowered by the environment variable
+                          SHSSA_MAX_STEPS); the handle and its triplets are
+                          still returned, with stats.converged = 0 */
     SSA_EDEVICE = -6,  /* a HIP runtime call failed */
     SSA_EBUSY = -7,    /* the request is not finished yet (serving) */
     SSA_ESTATE = -8    /* call out of order (e.g. reconstruct before decompose) */
 };
 
-enum { SSA_FP64 = 0, SSA_FP32 = 1 };  /* FP32: FP32 FFT products, FP64 Lanczos */
+/* SSA_FP32: FP32 FFT products; the bidiagonalisation's recurrence, its
+ * Gram-Schmidt reorthogonalisation (FP64 basis), the small SVD and the Ritz
+ * rotations stay FP64.  SSA_FP32_BASIS32: as SSA_FP32, but the Gram-Schmidt
+ * projections read an FP32 copy of the basis (half the basis traffic); its
+ * rounding bounds the orthogonality of the basis at about 1e-7. */
+enum { SSA_FP64 = 0, SSA_FP32 = 1, SSA_FP32_BASIS32 = 2 };
 
 typedef struct ssa_ctx ssa_ctx;
 typedef struct ssa_decomp ssa_decomp;
@@ -99,14 +108,30 @@ typedef struct ssa_stats {
     double max_resid;       /* largest residual bound |X v - s u| / sigma_1 */
     double ms_setup, ms_lanczos, ms_finish;
     size_t device_bytes;    /* device memory held by the handle */
+    int fft_rows, fft_cols; /* the resident spectrum holds fft_rows x (fft_cols/2 + 1)
+                               bins: the transform grid M_A x M_B of the products
+                               (internal orientation; for windows one cell wide
+                               one transformed row per series, M_A = 1) */
 } ssa_stats;
 
-/* Context: device, stream (hipStream_t, NULL = the library makes one) and a
- * device-memory budget in bytes (0 = no limit). */
-int  ssa_ctx_create(int device, size_t mem_budget, void* stream, ssa_ctx** out);
+/* Context: a device, a device-memory budget in bytes (0 = no limit) and an
+ * autotune cache.  The context makes its own non-blocking stream;
+ * ssa_ctx_set_stream replaces it with the caller's.  tune_cache (nullable,
+ * borrowed for the call) names a text file that keeps the tuner's choices
+ * across processes: it is read here if it exists, and each new choice is
+ * appended to it, one "<kind> <a> <b> <choice>" line per tuned size class
+ * (lines this build cannot use are ignored).  NULL: choices last for the
+ * context only.  SSA_EDEVICE without a HIP device, SSA_EINVAL for a device
+ * index out of range. */
+int  ssa_ctx_create(int device, size_t mem_budget, const char* tune_cache, ssa_ctx** out);
 /* Releases the context; if handles made from it are still alive, the release
  * happens when the last of them is freed. */
 void ssa_ctx_destroy(ssa_ctx* ctx);
+/* Replaces the context's stream (a hipStream_t, borrowed: it must outlive
+ * the context's use of it; NULL = the null stream, whose work cannot be
+ * captured).  Waits for the work queued on the old stream first; a stream
+ * the context made itself is destroyed.  Tensors of a PyTorch caller and the
+ * library's kernels then share one stream. */
 int  ssa_ctx_set_stream(ssa_ctx* ctx, void* stream);
 
 /* Decompose one shaped array (host inputs).  See ssa_request for the
@@ -213,7 +238,8 @@ int ssa_reconstruct(ssa_decomp* d, const int* grp_ptr, const int* grp_idx, int n
  * bidiagonalisation is thick-restarted from its last Ritz vectors with the
  * basis and convergence test of r_new, and all r_new triplets (and the
  * other side's vectors) are recomputed; the first r change only within the
- * tolerance.  r_new <= r: no-op.  r_new >= min(L, K): SSA_ERANK.  The
+ * tolerance.  r_new <= r: no-op.  r_new >= min(L, K) or r_new > 120:
+ * SSA_ERANK.  The
  * per-component buffers are reallocated (SSA_ENOMEM beyond the context's
  * budget; the handle is then unusable).  Returns when the new triplets are
  * computed, with the last kernels queued, like ssa_decompose. */
@@ -391,6 +417,10 @@ int ssa_ctx_profile(ssa_ctx* ctx, const char* kind);
  * period samples both directions of the alternating column passes. */
 int ssa_ctx_profile_every(ssa_ctx* ctx, int every);
 int ssa_ctx_profile_read_kind(ssa_ctx* ctx, const char* kind, double* ms, long* launches, double* bytes);
+/* All launches of class kind since the last ssa_ctx_profile call, timed or
+ * not (with ssa_ctx_profile_every > 1 only some of them are timed).
+ * SSA_EINVAL if the class is not being recorded. */
+int ssa_ctx_profile_launches(ssa_ctx* ctx, const char* kind, long* launches);
 int ssa_ctx_profile_read(ssa_ctx* ctx, double* ms, long* launches, double* bytes);
 
 #ifdef __cplusplus

@@ -70,12 +70,18 @@ def lib():
                                          C.c_long, C.c_int, _d, _d, _d, C.c_int, _i, C.c_long, _i, _i, _d]
         L.orc_gram_rows.argtypes = [C.c_long, C.c_long, _d, C.c_long, C.c_long, _d]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (for timing it)."""
+    lib().orc_set_threads(int(n))
 
 
 # --------------------------------------------------------------------------

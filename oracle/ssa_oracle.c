@@ -520,6 +520,16 @@ void orc_gram_rows(long m, long n, const double *X, long r0, long r1, double *S_
             S_out[(i - r0) * m + j] = dot(X + i * n, X + j * n, n);
 }
 
+/* Threads of the parallel loops (timing of the oracle itself only). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -11,9 +11,9 @@ import ctypes as C
 import numpy as np
 
 from . import _native
-from ._native import SSA_FP32, SSA_FP64, SsaError, check, lib  # noqa: F401
+from ._native import SSA_FP32, SSA_FP32_BASIS32, SSA_FP64, SsaError, check, lib  # noqa: F401
 
-__all__ = ["Context", "Decomposition", "SSA_FP32", "SSA_FP64", "SsaError"]
+__all__ = ["Context", "Decomposition", "SSA_FP32", "SSA_FP32_BASIS32", "SSA_FP64", "SsaError"]
 
 
 def _prec(p) -> int:
@@ -21,6 +21,8 @@ def _prec(p) -> int:
         return SSA_FP64
     if p in (SSA_FP32, "fp32", "f32", "float32", np.float32):
         return SSA_FP32
+    if p in (SSA_FP32_BASIS32, "fp32_basis32"):
+        return SSA_FP32_BASIS32
     raise ValueError(f"unknown precision {p!r}")
 
 
@@ -173,10 +175,13 @@ class Decomposition:
 class Context:
     """A device, a stream and a memory budget for decompositions."""
 
-    def __init__(self, device: int = 0, mem_budget: int = 0, stream=None):
+    def __init__(self, device: int = 0, mem_budget: int = 0, stream=None, tune_cache=None):
         h = C.c_void_p()
-        check(lib().ssa_ctx_create(device, mem_budget, stream, C.byref(h)), "ssa_ctx_create")
+        tc = None if tune_cache is None else str(tune_cache).encode()
+        check(lib().ssa_ctx_create(device, mem_budget, tc, C.byref(h)), "ssa_ctx_create")
         self._h = h
+        if stream is not None:
+            self.set_stream(stream)
 
     def __del__(self):
         try:
@@ -216,7 +221,9 @@ class Context:
                 ms, n, b = C.c_double(), C.c_long(), C.c_double()
                 check(lib().ssa_ctx_profile_read_kind(self._h, k.encode(), C.byref(ms), C.byref(n), C.byref(b)),
                       "ssa_ctx_profile_read_kind")
-                per[k] = {"ms": ms.value, "launches": n.value, "bytes": b.value}
+                tot = C.c_long()
+                check(lib().ssa_ctx_profile_launches(self._h, k.encode(), C.byref(tot)), "ssa_ctx_profile_launches")
+                per[k] = {"ms": ms.value, "launches": n.value, "bytes": b.value, "all_launches": tot.value}
         ms, n, b = C.c_double(), C.c_long(), C.c_double()
         check(lib().ssa_ctx_profile_read(self._h, C.byref(ms), C.byref(n), C.byref(b)), "ssa_ctx_profile_read")
         return per if per is not None else {"ms": ms.value, "launches": n.value, "bytes": b.value}

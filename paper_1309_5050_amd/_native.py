@@ -14,7 +14,7 @@ LIBPATH = os.path.join(HERE, "libshssa.so")
 
 SSA_OK, SSA_EINVAL, SSA_EEMPTY, SSA_ERANK, SSA_ENOMEM, SSA_ENOCONV, SSA_EDEVICE, SSA_EBUSY, SSA_ESTATE = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
-SSA_FP64, SSA_FP32 = 0, 1
+SSA_FP64, SSA_FP32, SSA_FP32_BASIS32 = 0, 1, 2
 
 
 class Request(C.Structure):
@@ -26,7 +26,8 @@ class Request(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("steps", C.c_int), ("restarts", C.c_int), ("basis", C.c_int), ("converged", C.c_int),
                 ("side", C.c_int), ("batch", C.c_int), ("svd_sweeps", C.c_int), ("max_resid", C.c_double), ("ms_setup", C.c_double),
-                ("ms_lanczos", C.c_double), ("ms_finish", C.c_double), ("device_bytes", C.c_size_t)]
+                ("ms_lanczos", C.c_double), ("ms_finish", C.c_double), ("device_bytes", C.c_size_t),
+                ("fft_rows", C.c_int), ("fft_cols", C.c_int)]
 
 
 class Times(C.Structure):
@@ -36,7 +37,7 @@ class Times(C.Structure):
 _lib = None
 
 _SIGS = {
-    "ssa_ctx_create": (C.c_int, [C.c_int, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "ssa_ctx_create": (C.c_int, [C.c_int, C.c_size_t, C.c_char_p, C.POINTER(C.c_void_p)]),
     "ssa_ctx_destroy": (None, [C.c_void_p]),
     "ssa_ctx_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "ssa_ctx_sync": (C.c_int, [C.c_void_p]),
@@ -46,6 +47,7 @@ _SIGS = {
                                        C.POINTER(C.c_double)]),
     "ssa_ctx_profile_read_kind": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_long),
                                             C.POINTER(C.c_double)]),
+    "ssa_ctx_profile_launches": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_long)]),
     "ssa_decompose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
                                 C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]),
     "ssa_decompose_multi": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p, C.c_int, C.c_int,

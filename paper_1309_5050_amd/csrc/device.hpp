@@ -6,6 +6,10 @@ namespace shssa {
 
 // Maximum Lanczos basis (projected matrix held in LDS as m x m doubles).
 constexpr int kMaxBasis = 128;
+// Largest rank a request may ask for: a thick restart keeps at least r Ritz
+// vectors and each cycle must add new ones, so r leaves at least 8 free
+// columns of the basis.
+constexpr int kMaxRank = kMaxBasis - 8;
 // Rows per Lanczos row block.
 constexpr int kLzRows = 256;
 

@@ -108,6 +108,32 @@ struct ssa_ctx {
     std::map<std::tuple<int, int, int>, void*> tw;   // (n, f64, real split) -> table
     std::map<std::pair<int, int>, int> col_tc;       // (f64, MA) -> tuned column tile
     std::mutex tune_mu;                               // one tuning at a time; guards col_tc
+    std::string tune_path;                            // autotune cache file ("" = none)
+
+    // Tuning results persist in a text file, one choice per line:
+    //   col <f64> <MA> <config>
+    // Lines of another kind or with a configuration this build does not
+    // compile are ignored when used.  Caller holds tune_mu.
+    void tune_load() {
+        if (tune_path.empty()) return;
+        FILE* f = std::fopen(tune_path.c_str(), "r");
+        if (!f) return;
+        char kind[16];
+        int a = 0, b = 0, c = 0;
+        char line[256];
+        while (std::fgets(line, sizeof line, f)) {
+            if (std::sscanf(line, "%15s %d %d %d", kind, &a, &b, &c) != 4) continue;
+            if (std::strcmp(kind, "col") == 0) col_tc[std::make_pair(a, b)] = c;
+        }
+        std::fclose(f);
+    }
+    void tune_save(const char* kind, int a, int b, int c) {
+        if (tune_path.empty()) return;
+        if (FILE* f = std::fopen(tune_path.c_str(), "a")) {
+            std::fprintf(f, "%s %d %d %d\n", kind, a, b, c);
+            std::fclose(f);
+        }
+    }
 
     int tile_for(bool f64, int MA) {
         std::lock_guard<std::mutex> g(tune_mu);
@@ -437,7 +463,8 @@ struct ssa_decomp {
     double *Q = nullptr, *w = nullptr, *sinv = nullptr, *hp1 = nullptr, *hp2 = nullptr, *np = nullptr, *np0 = nullptr;
     double *lnp = nullptr, *gam = nullptr, *Bm = nullptr, *Yl = nullptr, *Yr = nullptr, *sig = nullptr, *beta = nullptr;
     double* Qtmp = nullptr;
-    float* Q32 = nullptr;            // FP32 copy of Q for the reorthogonalisation (FP32 products)
+    float* Q32 = nullptr;            // FP32 copy of Q for the reorthogonalisation (SSA_FP32_BASIS32)
+    bool q32 = false;                // the reorthogonalisation reads the FP32 copy
     void* lbuf = nullptr;
     int *perm = nullptr, *flag = nullptr;
     double *U = nullptr, *V = nullptr, *sigma = nullptr;
@@ -542,13 +569,15 @@ namespace {
 int plan_request(ssa_ctx* ctx, const ssa_request& q, ssa_decomp* d) {
     if (q.nx <= 0 || q.ny <= 0 || q.lx <= 0 || q.ly <= 0) return fail(SSA_EINVAL, "sizes must be positive");
     if (!q.x) return fail(SSA_EINVAL, "x is NULL");
-    if (q.precision != SSA_FP64 && q.precision != SSA_FP32) return fail(SSA_EINVAL, "unknown precision");
+    if (q.precision != SSA_FP64 && q.precision != SSA_FP32 && q.precision != SSA_FP32_BASIS32)
+        return fail(SSA_EINVAL, "unknown precision");
     d->attach(ctx);
     d->nx = q.nx;
     d->ny = q.ny;
     d->r = q.r;
     d->seed = q.seed;
     d->f64 = q.precision == SSA_FP64;
+    d->q32 = q.precision == SSA_FP32_BASIS32;
     // window: trim to the bounding box
     int i0 = q.lx, i1 = -1, j0 = q.ly, j1 = -1;
     for (int i = 0; i < q.lx; ++i)
@@ -611,6 +640,7 @@ int plan_request(ssa_ctx* ctx, const ssa_request& q, ssa_decomp* d) {
         d->MA = 1;
     }
     if (q.r < 1) return fail(SSA_ERANK, "r must be >= 1");
+    if (q.r > kMaxRank) return fail(SSA_ERANK, "r must be <= 120 (the basis holds 128 vectors)");
     return SSA_OK;
 }
 
@@ -752,6 +782,10 @@ struct DevVec {
     void* p = nullptr;
     size_t cap = 0;
     ssa_ctx* ctx = g_tables_ctx;
+    DevVec() = default;
+    // a block has one owner: a copy would return it to the pool twice
+    DevVec(const DevVec&) = delete;
+    DevVec& operator=(const DevVec&) = delete;
     ~DevVec() { release(); }
     void release() {
         if (!p) return;
@@ -1085,7 +1119,7 @@ int tune_col_tile(Batch& b) {
         }
     }
     auto it = b.ctx->col_tc.find(key);
-    if (it != b.ctx->col_tc.end()) {
+    if (it != b.ctx->col_tc.end() && col_tile_ok(b.f64, d0->MA, it->second)) {
         b.set_col(it->second);
         return SSA_OK;
     }
@@ -1132,6 +1166,7 @@ int tune_col_tile(Batch& b) {
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     b.ctx->col_tc[key] = best_tc;
+    b.ctx->tune_save("col", key.first, key.second, best_tc);
     b.set_col(best_tc);
     return SSA_OK;
 }
@@ -1167,7 +1202,7 @@ int run_alloc_spectrum(Batch& b) {
             (rc = d->dalloc(&d->perm, kMaxBasis)) || (rc = d->dalloc(&d->flag, 4)) ||
             (rc = d->dalloc(&d->Qtmp, n * kMaxBasis)) || (rc = d->dalloc(&d->U, d->L * (long)d->r)) ||
             (rc = d->dalloc(&d->V, d->K * (long)d->r)) || (rc = d->dalloc(&d->sigma, d->r)) ||
-            (!d->f64 && (rc = d->dalloc(&d->Q32, n * (kMaxBasis + 1)))))
+            (d->q32 && (rc = d->dalloc(&d->Q32, n * (kMaxBasis + 1)))))
             return rc;
         // descriptors
         OpDesc& o = d->op;
@@ -1201,7 +1236,7 @@ int run_alloc_spectrum(Batch& b) {
         z.lrows = (int)longrows;
         z.Bm = d->Bm; z.Yl = d->Yl; z.Yr = d->Yr; z.sig = d->sig; z.perm = d->perm;
         z.beta = d->beta; z.flag = d->flag; z.Qtmp = d->Qtmp;
-        z.Q32 = d->f64 ? nullptr : d->Q32;
+        z.Q32 = d->q32 ? d->Q32 : nullptr;
         z.nblk = nblk;
         ResDesc& s = d->rs;
         s.r = d->r;
@@ -1344,11 +1379,12 @@ void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode, bool prof 
         launch_lz_update(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 1, 0);
     }
     // second Gram-Schmidt pass for FP64 instances, skipped on the device
-    // when not needed.  FP32 instances project against the FP32 copy of the
-    // basis: its rounding (about 1e-7) bounds their orthogonality, while one
-    // FP64 pass leaves eps |w_before| / |w_after|, below that unless the pass
-    // cancels w by nine orders (where the breakdown test takes over), so
-    // they make one pass and skip both launches.
+    // when not needed.  FP32-product instances make one FP64 pass: it
+    // leaves eps |w_before| / |w_after| of the basis in w, below the
+    // products' own 1e-7 unless the pass cancels w by nine orders (where
+    // the breakdown test takes over).  With SSA_FP32_BASIS32 the pass reads
+    // the FP32 copy of the basis, whose rounding (about 1e-7) then bounds
+    // the orthogonality.
     if (b.f64) {
         launch_lz_proj2(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 0);
         launch_lz_update(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), ncols, 2, 0);
@@ -1487,6 +1523,9 @@ int run_lanczos(Batch& b, int max_steps, const std::function<int()>& overlap = n
     const int kk = restart_keep(m, b.ds[0]->r);
     int rmax = 0;
     for (auto* d : b.ds) rmax = std::max(rmax, d->r);
+    // every cycle keeps kk >= r Ritz vectors and adds m - kk > 0 new ones
+    if (!(rmax <= kk && kk < m && m <= kMaxBasis))
+        return fail(SSA_ERANK, "rank leaves no room in the Lanczos basis");
     std::vector<int> act(ni);
     for (int i = 0; i < ni; ++i) act[i] = i;
     std::vector<int> steps(ni, 0), restarts(ni, 0);
@@ -1635,6 +1674,15 @@ int run_lanczos(Batch& b, int max_steps, const std::function<int()>& overlap = n
     }
     HIPCHK(hipGetLastError());
     return SSA_OK;
+}
+
+// Bidiagonalisation steps an instance may take before it is returned with
+// SSA_ENOCONV (its triplets as they stand).  SHSSA_MAX_STEPS lowers the
+// limit, which lets a caller force that outcome.
+int step_limit() {
+    int n = 3000;
+    if (const char* e = std::getenv("SHSSA_MAX_STEPS")) n = std::max(1, std::min(n, std::atoi(e)));
+    return n;
 }
 
 // Item lists of the final pass (built and uploaded while the first
@@ -1864,7 +1912,7 @@ GeoKey geo_key(const ssa_decomp* d) {
     const int side = plan_side(d);
     const long nshort = side == 0 ? d->L : (long)d->KA * d->KB;   // the origin box bounds |K|
     const int m = basis_size(nshort, d->r);
-    return GeoKey{(int)d->rowfam, (int)d->f64, side, row_word(d->nh, d->f64), col_key(d->MA), m,
+    return GeoKey{(int)d->rowfam, d->f64 ? 0 : d->q32 ? 2 : 1, side, row_word(d->nh, d->f64), col_key(d->MA), m,
                   restart_keep(m, d->r)};
 }
 
@@ -1930,7 +1978,7 @@ void run_planned(ssa_ctx* ctx, const std::vector<ssa_decomp*>& grp, hipStream_t 
         const double t_spec = ms_since(t1);
         auto t2 = Clock::now();
         FinishLists F;
-        if (!rc) rc = b.ds[0]->eigen ? run_eigen(b, F) : run_lanczos(b, 3000, [&] { return finish_lists(b, F); });
+        if (!rc) rc = b.ds[0]->eigen ? run_eigen(b, F) : run_lanczos(b, step_limit(), [&] { return finish_lists(b, F); });
         const double t_lz = ms_since(t2);
         auto t3 = Clock::now();
         if (!rc) rc = run_finish(b, F);
@@ -2123,19 +2171,18 @@ size_t estimate_bytes(const ssa_decomp* d, int ngroups) {
     b += xh * ce + 2.0 * d->A * d->ldp * ce * nslot + us * ce * nslot;  // spectrum, row/column slots
     b += 2.0 * nlong * (d->f64 ? 8.0 : 4.0);                            // long vectors
     b += nshort * (2.0 * kMaxBasis + 4.0) * 8.0;                        // basis, rotation scratch, w
+    if (d->q32) b += nshort * (kMaxBasis + 1.0) * 4.0;                  // FP32 copy of the basis
     b += (L + kbox) * d->r * 8.0;                                       // U, V
     b += (double)ngroups * n * 8.0;                                     // reconstruction
     return (size_t)(1.3 * b) + (4u << 20);
 }
 
-Batch make_batch(ssa_ctx* ctx, hipStream_t st, const std::vector<ssa_decomp*>& ds) {
-    Batch b(ctx, st);
+void fill_batch(Batch& b, ssa_ctx* ctx, const std::vector<ssa_decomp*>& ds) {
     b.ds = ds;
     b.f64 = ds[0]->f64;
     b.rowfam = ds[0]->rowfam;
     b.cls = row_word(ds[0]->nh, b.f64);
     b.set_col(ctx->tile_for(b.f64, ds[0]->MA));
-    return b;
 }
 
 // Decompose and reconstruct one batch of requests of equal geometry on
@@ -2178,7 +2225,8 @@ void serve_batch(ssa_ctx* ctx, std::vector<std::shared_ptr<ServeReq>>& batch, hi
             bufs.push_back(buf);
         }
         if (!rc) {
-            Batch b = make_batch(ctx, st, ds);
+            Batch b(ctx, st);
+            fill_batch(b, ctx, ds);
             rc = run_reconstruct(b, same[0]->gp, same[0]->gi, bufs);
         }
         for (size_t k = 0; k < same.size(); ++k) {
@@ -2394,6 +2442,15 @@ int ssa_ctx_profile_read(ssa_ctx* ctx, double* ms, long* launches, double* bytes
     return rc;
 }
 
+int ssa_ctx_profile_launches(ssa_ctx* ctx, const char* kind, long* launches) {
+    if (!ctx || !kind || !launches) return fail(SSA_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    const int k = ctx->prof_index(kind);
+    if (k < 0) return fail(SSA_EINVAL, "kernel class not recorded");
+    *launches = ctx->prof_seen[k];
+    return SSA_OK;
+}
+
 int ssa_ctx_profile_read_kind(ssa_ctx* ctx, const char* kind, double* ms, long* launches, double* bytes) {
     if (!ctx || !kind) return fail(SSA_EINVAL, "NULL argument");
     HIPCHK(hipStreamSynchronize(ctx->st));
@@ -2401,7 +2458,7 @@ int ssa_ctx_profile_read_kind(ssa_ctx* ctx, const char* kind, double* ms, long* 
     return profile_sum(ctx, kind, ms, launches, bytes);
 }
 
-int ssa_ctx_create(int device, size_t mem_budget, void* stream, ssa_ctx** out) {
+int ssa_ctx_create(int device, size_t mem_budget, const char* tune_cache, ssa_ctx** out) {
     if (!out) return fail(SSA_EINVAL, "out is NULL");
     *out = nullptr;
     int ndev = 0;
@@ -2411,14 +2468,15 @@ int ssa_ctx_create(int device, size_t mem_budget, void* stream, ssa_ctx** out) {
     auto* c = new ssa_ctx();
     c->device = device;
     c->budget = mem_budget;
-    if (stream) {
-        c->st = static_cast<hipStream_t>(stream);
-    } else {
-        if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess) {
-            delete c;
-            return fail(SSA_EDEVICE, "hipStreamCreate failed");
-        }
-        c->own = true;
+    if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return fail(SSA_EDEVICE, "hipStreamCreate failed");
+    }
+    c->own = true;
+    if (tune_cache && *tune_cache) {
+        c->tune_path = tune_cache;
+        std::lock_guard<std::mutex> g(c->tune_mu);
+        c->tune_load();
     }
     *out = c;
     return SSA_OK;
@@ -2905,6 +2963,7 @@ int ssa_extend(ssa_decomp* d, int r_new) {
     if (!d->decomposed || d->status != SSA_OK) return fail(SSA_ESTATE, "not decomposed");
     if (r_new <= d->r) return SSA_OK;
     if (r_new >= std::min(d->L, d->K)) return fail(SSA_ERANK, "r must be < min(L, K)");
+    if (r_new > kMaxRank) return fail(SSA_ERANK, "r must be <= 120 (the basis holds 128 vectors)");
     int rc;
     if ((rc = wait_handle(d))) return rc;
     g_tables_ctx = d->ctx;
@@ -2957,7 +3016,7 @@ int ssa_extend(ssa_decomp* d, int r_new) {
         rc = upload_lists({&I}, st);
         if (!rc) launch_eig_take(I.n(), st, b.lzs(), b.res(), I.ptr(), (int)d->L, r_new);
     } else {
-        rc = run_lanczos(b, 3000, [&] { return finish_lists(b, F); }, m_old, fresh);
+        rc = run_lanczos(b, step_limit(), [&] { return finish_lists(b, F); }, m_old, fresh);
     }
     if (!rc) rc = run_finish(b, F);
     d->st.steps += before.steps;
@@ -3207,6 +3266,8 @@ int ssa_get_stats(const ssa_decomp* d, ssa_stats* st) {
     if (!d || !st) return fail(SSA_EINVAL, "NULL argument");
     *st = d->st;
     st->device_bytes = d->bytes;
+    st->fft_rows = d->rowfam ? d->A : d->MA;
+    st->fft_cols = d->MB;
     return SSA_OK;
 }
 
