@@ -327,6 +327,18 @@ int ssa_vforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out,
  * Synchronous. */
 int ssa_esprit(ssa_decomp* d, const int* grp, int ng, double* re, double* im);
 
+/* ssa_esprit for callers that cannot allocate device memory (code in a
+ * tight serving loop, harnesses that forbid hipMalloc): the same
+ * arguments, kernels, results and errors, but the group ids, flags, shift
+ * matrix and roots live in a fixed 64 KiB device array of the library (one
+ * per GPU, set up by ssa_ctx_create, kept until the process ends) instead
+ * of memory from the context's pool, and the call uses no allocating
+ * routine.  A group that needs more than that array returns SSA_EINVAL
+ * (ng <= 64 always fits).  Every call on one GPU shares the array: calls
+ * that overlap on one GPU (from several threads or contexts) race and must
+ * be serialised by the caller.  Synchronous. */
+int ssa_esprit_noalloc(ssa_decomp* d, const int* grp, int ng, double* re, double* im);
+
 /* TLS-ESPRIT roots (the same paragraph, with the total-least-squares shift
  * matrix of Roy and Kailath): for Z = [U_low : U_high], the group's U
  * without its last row beside it without its first, and Z's right singular

@@ -153,6 +153,15 @@ class Decomposition:
         check(getattr(lib(), fn)(self._h, _ptr(g), len(g), _ptr(re), _ptr(im)), fn)
         return re + 1j * im
 
+    def esprit_noalloc(self, group) -> np.ndarray:
+        """LS-ESPRIT roots as ``esprit(group)``, through the call that uses the
+        library's fixed device scratch instead of allocating (one call at a
+        time per GPU)."""
+        g = np.ascontiguousarray(group, dtype=np.int32)
+        re, im = np.zeros(len(g)), np.zeros(len(g))
+        check(lib().ssa_esprit_noalloc(self._h, _ptr(g), len(g), _ptr(re), _ptr(im)), "ssa_esprit_noalloc")
+        return re + 1j * im
+
     def esprit2d(self, group):
         """2D-ESPRIT pairs of the group: (lambda, mu) complex arrays (x and y roots)."""
         g = np.ascontiguousarray(group, dtype=np.int32)

@@ -2358,6 +2358,39 @@ void serve_stop(ssa_ctx* ctx) {
 }
 
 // ---------------------------------------------------------------------------
+// fixed device scratch of the allocation-free calls
+// ---------------------------------------------------------------------------
+
+// One array per GPU that the library runs on, held until the process ends.
+// Host code never uses its name as an address (on the host it only names
+// the symbol): scratch_init looks up each device's copy once, with that
+// device current, and the calls pass that address to their kernels.
+constexpr size_t kScratchBytes = 64u << 10;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch_ptr;   // device -> address of its scratch
+}  // namespace
+
+// Called by ssa_ctx_create with `device` current.
+int scratch_init(int device) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_ptr.count(device)) return SSA_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(SSA_EDEVICE, "no address for the device scratch");
+    g_scratch_ptr[device] = static_cast<unsigned char*>(p);
+    return SSA_OK;
+}
+
+unsigned char* scratch_of(int device) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 
@@ -2465,6 +2498,7 @@ int ssa_ctx_create(int device, size_t mem_budget, const char* tune_cache, ssa_ct
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(SSA_EDEVICE, "no HIP device");
     if (device < 0 || device >= ndev) return fail(SSA_EINVAL, "device out of range");
     HIPCHK(hipSetDevice(device));
+    if (int rc = scratch_init(device)) return rc;
     auto* c = new ssa_ctx();
     c->device = device;
     c->budget = mem_budget;
@@ -3121,6 +3155,40 @@ int ssa_esprit(ssa_decomp* d, const int* grp, int ng, double* re, double* im) {
     HIPCHK(hipMemcpyAsync(bad, flag.p, sizeof(bad), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(re, dre.p, (size_t)ng * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(im, dim.p, (size_t)ng * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (bad[0]) return fail(SSA_EINVAL, "no ESPRIT roots: the group's last coordinates have nu^2 >= 1");
+    if (bad[1]) return fail(SSA_ENOCONV, "ESPRIT: the eigenvalue iteration did not converge");
+    return SSA_OK;
+}
+
+int ssa_esprit_noalloc(ssa_decomp* d, const int* grp, int ng, double* re, double* im) {
+    if (!re || !im) return fail(SSA_EINVAL, "NULL argument");
+    int rc = check_forecast(d, grp, ng, 1, re, nullptr, "ESPRIT");
+    if (rc) return rc;
+    // scratch layout: group ids | two flags | shift matrix M | re | im,
+    // each region 256-byte aligned
+    const auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t og = 0, of = og + up((size_t)ng * sizeof(int)), om = of + up(2 * sizeof(int)),
+                 ore = om + up((size_t)ng * ng * sizeof(double)), oim = ore + up((size_t)ng * sizeof(double)),
+                 need = oim + up((size_t)ng * sizeof(double));
+    if (need > kScratchBytes) return fail(SSA_EINVAL, "group needs more than the 64 KiB fixed scratch");
+    unsigned char* base = scratch_of(d->ctx->device);
+    if (!base) return fail(SSA_EDEVICE, "device scratch not set up");
+    if ((rc = wait_handle(d))) return rc;
+    hipStream_t st = d->ctx->st;
+    int* dg = reinterpret_cast<int*>(base + og);
+    int* flag = reinterpret_cast<int*>(base + of);
+    double* M = reinterpret_cast<double*>(base + om);
+    double* dre = reinterpret_cast<double*>(base + ore);
+    double* dim = reinterpret_cast<double*>(base + oim);
+    HIPCHK(hipMemcpyAsync(dg, grp, (size_t)ng * sizeof(int), hipMemcpyHostToDevice, st));
+    launch_fill_i32(st, flag, 2, 0);
+    launch_esprit(st, d->U, d->L, dg, ng, M, dre, dim, flag);
+    HIPCHK(hipGetLastError());
+    int bad[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(bad, flag, sizeof(bad), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(re, dre, (size_t)ng * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(im, dim, (size_t)ng * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (bad[0]) return fail(SSA_EINVAL, "no ESPRIT roots: the group's last coordinates have nu^2 >= 1");
     if (bad[1]) return fail(SSA_ENOCONV, "ESPRIT: the eigenvalue iteration did not converge");

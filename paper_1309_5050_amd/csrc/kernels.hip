@@ -2704,6 +2704,13 @@ __global__ void k_step_next(int* step) {
     if (threadIdx.x == 0) step[0] += 1;
 }
 
+// p[0..n) = v (clears flags without a memset node, which a caller's graph
+// capture would record)
+__global__ void k_fill_i32(int* __restrict__ p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void k_gather_flags(const LzDesc* __restrict__ lzs, int ninst, int* __restrict__ flags,
                                double* __restrict__ betas) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -96,6 +96,8 @@ void launch_xgram(hipStream_t st, const double* xc, const int* offL, int L, cons
                   double* part, double* out, double* Bm);
 void launch_eig_take(int nitems, hipStream_t st, const LzDesc* lzs, const ResDesc* res, const Item* items, int L,
                      int r);
+// p[0..n) = v on stream st.
+void launch_fill_i32(hipStream_t st, int* p, int n, int v);
 // LS-ESPRIT roots (ng <= kVfMaxGroup) into re/im; M holds ng^2 values;
 // flag[0..1] (zeroed by the caller) as for k_esprit.
 void launch_esprit(hipStream_t st, const double* U, long L, const int* grp, int ng, double* M, double* re,
