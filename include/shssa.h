@@ -140,12 +140,16 @@ int  ssa_ctx_set_stream(ssa_ctx* ctx, void* stream);
 int ssa_decompose(ssa_ctx* ctx, const double* x, int nx, int ny, const uint8_t* mask,
                   const uint8_t* wmask, int lx, int ly, int r, int precision, ssa_decomp** out);
 
-/* The eigen method for small windows (the paper's alternative to the
- * truncated SVD when L is small: S = X X^T and its full eigendecomposition,
- * O(L N log N + L^3)).  Same arguments as ssa_decompose, always FP64; the
- * window may hold at most 128 cells (SSA_EINVAL otherwise).  S is formed on
- * the matrix cores straight from the cleaned array (the trajectory matrix
- * is never stored), its eigenpairs by one-sided Jacobi; sigma_i =
+/* The eigen method (the paper's alternative to the truncated SVD for
+ * moderate windows: S = X X^T and its full eigendecomposition,
+ * O(L N log N + L^3); the 2D-SSA examples time it on a 25 x 25 window).
+ * Same arguments as ssa_decompose, always FP64; the window may hold at most
+ * 4096 cells (SSA_EINVAL otherwise; S is kept as L x L doubles).  S is
+ * formed on the matrix cores straight from the cleaned array (the
+ * trajectory matrix is never stored); its eigenpairs come from one-sided
+ * Jacobi in one workgroup for windows of at most 128 cells, and from block
+ * one-sided Jacobi across workgroups beyond that (SSA_ENOCONV, with the
+ * handle, if 40 sweeps do not orthogonalise S's columns).  sigma_i =
  * sqrt(lambda_i), U_i the eigenvectors, V_i = X^T U_i / sigma_i.  Squaring
  * the matrix limits the absolute accuracy of sigma_i to about
  * eps sigma_1^2 / sigma_i (sqrt(eps) sigma_1 for vanishing ones).  The

@@ -260,7 +260,7 @@ class Context:
     def decompose(self, x, window=None, r: int = 10, mask=None, wmask=None, precision="fp64",
                   method: str = "lanczos") -> Decomposition:
         """Shaped decomposition of an image (or a series given as 1-D).
-        method "eigen": S = X X^T and its eigenpairs (windows of at most 128
+        method "eigen": S = X X^T and its eigenpairs (windows of at most 4096
         cells, FP64 whatever the precision)."""
         x, lx, ly, mask, wmask = self._image_args(x, window, mask, wmask)
         h = C.c_void_p()

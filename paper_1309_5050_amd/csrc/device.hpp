@@ -10,6 +10,12 @@ constexpr int kMaxBasis = 128;
 // vectors and each cycle must add new ones, so r leaves at least 8 free
 // columns of the basis.
 constexpr int kMaxRank = kMaxBasis - 8;
+// Block width of the block Jacobi eigensolver (eigen method beyond
+// kMaxBasis window cells) and the width of a block pair.
+constexpr int kBjW = 16;
+constexpr int kBjN = 2 * kBjW;
+// Largest window (cells) of the eigen method: S = X X^T is held as L x L doubles.
+constexpr int kEigMaxL = 4096;
 // Rows per Lanczos row block.
 constexpr int kLzRows = 256;
 

@@ -433,7 +433,10 @@ struct ssa_decomp {
     // internal geometry
     int A = 0, B = 0, LA = 0, LB = 0, KA = 0, KB = 0, MA = 1, MB = 0, nh = 0, P = 0, ldp = 0;
     bool rowfam = false, f64 = true;
-    bool eigen = false;              // eigen method: S = X X^T and its eigenpairs (small L)
+    bool eigen = false;              // eigen method: S = X X^T and its eigenpairs
+    double* Sbig = nullptr;          // eigen method beyond kMaxBasis cells: S, then its rotated columns (L x L)
+    double* eig_lam = nullptr;       // |columns| of the rotated S: the eigenvalues (L)
+    std::vector<double> eig_lam_h;   // host copy of eig_lam
     int r = 0;
     unsigned long long seed = 0;
     long L = 0, K = 0;
@@ -1765,6 +1768,82 @@ int run_finish(Batch& b, FinishLists& F) {
 
 int fetch_kmask(ssa_decomp* d);
 
+// U and sigma of the r leading eigenpairs of a block-Jacobi-rotated S: the
+// eigenvalues (column norms) are ordered on the host, descending, ties by
+// column.
+int eig_take_big(Batch& b, ssa_decomp* d, int r) {
+    std::vector<int> perm(d->L);
+    for (int j = 0; j < (int)d->L; ++j) perm[j] = j;
+    std::stable_sort(perm.begin(), perm.end(),
+                     [&](int a, int c) { return d->eig_lam_h[a] > d->eig_lam_h[c]; });
+    perm.resize(r);
+    DevVec dperm;
+    int rc;
+    if ((rc = dperm.put(perm, b.st))) return rc;
+    launch_bj_take(b.st, d->Sbig, (int)d->L, dperm.as<int>(), d->eig_lam, d->U, d->sigma, r);
+    HIPCHK(hipGetLastError());
+    return SSA_OK;
+}
+
+// Eigenpairs of S (resident in d->Sbig, L x L) by block one-sided Jacobi:
+// sweeps of rounds that rotate disjoint pairs of column blocks until a
+// whole sweep finds every pair orthogonal to 1e-13 relative to the column
+// norms or below 1e-26 of the largest squared norm (at most 40 sweeps;
+// beyond that the handle is returned with SSA_ENOCONV).  Then the column
+// norms (the eigenvalues) and U, sigma of the r leading eigenpairs.
+int eig_block_jacobi(Batch& b, ssa_decomp* d) {
+    hipStream_t st = b.st;
+    const int L = (int)d->L;
+    const int nblk = (L + kBjW - 1) / kBjW, nb2 = nblk + (nblk & 1), P = nb2 / 2, rounds = nb2 - 1;
+    // circle method over nb2 positions (the last one fixed); an odd block
+    // count pairs one block with the empty block (-1) in each round
+    std::vector<int2> pairs((size_t)rounds * P);
+    for (int r = 0; r < rounds; ++r)
+        for (int k = 0; k < P; ++k) {
+            const int a = k == 0 ? nb2 - 1 : (r + k) % (nb2 - 1);
+            const int c = k == 0 ? r : (r - k + nb2 - 1) % (nb2 - 1);
+            pairs[(size_t)r * P + k] = make_int2(a < nblk ? a : -1, c < nblk ? c : -1);
+        }
+    DevVec dp, dJ, dflag;
+    int rc;
+    if ((rc = dp.put(pairs, st)) || (rc = dJ.reserve((size_t)P * kBjN * kBjN * sizeof(double))) ||
+        (rc = dflag.reserve(2 * sizeof(int))))
+        return rc;
+    // scale: the largest squared column norm of S (>= lambda_1^2); Gram
+    // entries below 1e-26 of it are not rotated away (they only couple
+    // columns far below the eigenvalues that matter)
+    launch_bj_norms(st, d->Sbig, L, d->eig_lam);
+    d->eig_lam_h.assign(L, 0.0);
+    HIPCHK(hipMemcpyAsync(d->eig_lam_h.data(), d->eig_lam, (size_t)L * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double nmax = 0.0;
+    for (double v : d->eig_lam_h) nmax = std::max(nmax, v);
+    const double floor_abs = 1e-26 * nmax * nmax;
+    void* hb = nullptr;
+    if ((rc = b.ctx->readback_buf(st, 2 * sizeof(int), &hb))) return rc;
+    int sweeps = 0;
+    bool conv = false;
+    while (sweeps < 40 && !conv) {
+        launch_fill_i32(st, dflag.as<int>(), 2, 0);
+        for (int r = 0; r < rounds; ++r)
+            launch_bj_round(st, d->Sbig, L, dp.as<int2>() + (size_t)r * P, P, dJ.as<double>(), dflag.as<int>(),
+                            1e-13, floor_abs);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(hb, dflag.p, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        ++sweeps;
+        conv = static_cast<int*>(hb)[0] == 0;
+    }
+    launch_bj_norms(st, d->Sbig, L, d->eig_lam);
+    d->eig_lam_h.assign(L, 0.0);
+    HIPCHK(hipMemcpyAsync(d->eig_lam_h.data(), d->eig_lam, (size_t)L * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    d->st.svd_sweeps = sweeps;
+    d->st.converged = conv;
+    if (!conv) d->status = fail(SSA_ENOCONV, "eigen method: block Jacobi reached its sweep limit");
+    return eig_take_big(b, d, d->r);
+}
+
 // The eigen method (the paper's alternative for small windows): S = X X^T
 // on the matrix cores straight from the cleaned grid, its eigenpairs by the
 // one-sided Jacobi SVD of the projected-matrix kernel (S is symmetric
@@ -1787,9 +1866,11 @@ int run_eigen(Batch& b, FinishLists& F) {
         for (int a = 0; a < d->KA; ++a)
             for (int c = 0; c < d->KB; ++c)
                 if (d->kmask_h[(size_t)a * d->KB + c]) offK.push_back(a * d->B + c);
-        if ((long)offL.size() != d->L || (long)offK.size() != d->K || d->L > kMaxBasis)
+        if ((long)offL.size() != d->L || (long)offK.size() != d->K || d->L > kEigMaxL)
             return fail(SSA_EINVAL, "eigen method: inconsistent cell sets");
         const int L = (int)d->L;
+        const bool big = L > kMaxBasis;
+        if (big && ((rc = d->dalloc(&d->Sbig, (long)L * L)) || (rc = d->dalloc(&d->eig_lam, L)))) return rc;
         const int nb = (L + 15) / 16, ntile = nb * (nb + 1) / 2;
         // about 2048 workgroups, each chunk at least 128 origins
         const int nchunk = (int)std::max<long>(1, std::min<long>(2048 / ntile + 1, (d->K + 127) / 128));
@@ -1802,25 +1883,29 @@ int run_eigen(Batch& b, FinishLists& F) {
             // flops of the Gram (upper-triangle tiles, 2 per multiply-add)
             ProfSpan p(b.ctx, "xgram", st, [&] { return 2.0 * ntile * 256.0 * (double)d->K; });
             launch_xgram(st, d->xc, dl.as<int>(), L, dk.as<int>(), d->K, nchunk, part.as<double>(),
-                         out.as<double>(), d->Bm);
+                         out.as<double>(), big ? d->Sbig : d->Bm, big ? L : kMaxBasis);
         }
         HIPCHK(hipGetLastError());
-        // the DevVecs go back to the call's table cache, reused after the stream drains
-        I.h.push_back(Item{(int)q, 0, 0, 0});
-    }
-    if ((rc = upload_lists({&I}, st))) return rc;
-    const int L = (int)b.ds[0]->L;
-    launch_lz_svd(I.n(), st, b.lzs(), I.ptr(), L, 100);
-    int rmax = 0;
-    for (auto* d : b.ds) rmax = std::max(rmax, d->r);
-    launch_eig_take(I.n(), st, b.lzs(), b.res(), I.ptr(), L, rmax);
-    HIPCHK(hipGetLastError());
-    for (auto* d : b.ds) {
         d->st.steps = 0;
         d->st.restarts = 0;
         d->st.basis = 0;
         d->st.converged = 1;
         d->st.max_resid = 0.0;
+        // the DevVecs go back to the call's table cache, reused after the stream drains
+        if (big) {
+            if ((rc = eig_block_jacobi(b, d))) return rc;
+        } else {
+            I.h.push_back(Item{(int)q, 0, 0, 0});
+        }
+    }
+    if (!I.h.empty()) {
+        if ((rc = upload_lists({&I}, st))) return rc;
+        const int L = (int)b.ds[I.h[0].inst]->L;
+        launch_lz_svd(I.n(), st, b.lzs(), I.ptr(), L, 100);
+        int rmax = 0;
+        for (const Item& it : I.h) rmax = std::max(rmax, b.ds[it.inst]->r);
+        launch_eig_take(I.n(), st, b.lzs(), b.res(), I.ptr(), L, rmax);
+        HIPCHK(hipGetLastError());
     }
     return F.ready ? SSA_OK : finish_lists(b, F);
 }
@@ -2571,7 +2656,7 @@ int ssa_decompose_eigen(ssa_ctx* ctx, const double* x, int nx, int ny, const uin
     std::unique_ptr<ssa_decomp> d(new ssa_decomp());
     int rc = plan_request(ctx, q, d.get());
     if (rc) return rc;
-    if (d->L > kMaxBasis) return fail(SSA_EINVAL, "eigen method needs a window of at most 128 cells");
+    if (d->L > kEigMaxL) return fail(SSA_EINVAL, "eigen method needs a window of at most 4096 cells");
     if ((rc = upload_request(q, d.get(), false, ctx->st))) return rc;
     d->eigen = true;
     std::vector<int> st;
@@ -3043,7 +3128,10 @@ int ssa_extend(ssa_decomp* d, int r_new) {
     const ssa_stats before = d->st;
     auto t0 = Clock::now();
     FinishLists F;
-    if (d->eigen) {
+    if (d->eigen && d->Sbig) {
+        // the rotated S and its eigenvalues are still resident
+        rc = eig_take_big(b, d, r_new);
+    } else if (d->eigen) {
         // every eigenpair of S is still resident: take r_new of them
         ItemList I;
         I.h.push_back(Item{0, 0, 0, 0});

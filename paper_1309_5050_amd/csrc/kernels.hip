@@ -2083,11 +2083,12 @@ k_xgram(const double* __restrict__ xc, const int* __restrict__ offL, int L, cons
     part[((long)blockIdx.y * 256 + e) * nchunk + blockIdx.x] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
 }
 
-// Places the summed tiles of S (out[tile * 256 + 16 i + j]) into the
-// projected-matrix buffer (column-major, leading dimension kMaxBasis),
-// mirroring the off-diagonal tiles.  One workgroup per tile.
+// Places the summed tiles of S (out[tile * 256 + 16 i + j]) into a
+// column-major matrix of leading dimension ld (the projected-matrix buffer,
+// ld = kMaxBasis, or an L x L array), mirroring the off-diagonal tiles.  One
+// workgroup per tile.
 __global__ void __launch_bounds__(256)
-k_xgram_place(const double* __restrict__ out, int L, double* __restrict__ Bm) {
+k_xgram_place(const double* __restrict__ out, int L, long ld, double* __restrict__ Bm) {
     const int nb = (L + 15) / 16;
     int k = blockIdx.x, ib = 0;
     while (k >= nb - ib) {
@@ -2098,8 +2099,205 @@ k_xgram_place(const double* __restrict__ out, int L, double* __restrict__ Bm) {
     const int e = threadIdx.x, i = ib * 16 + e / 16, j = jb * 16 + e % 16;
     if (i >= L || j >= L) return;
     const double v = out[(long)blockIdx.x * 256 + e];
-    Bm[(long)j * kMaxBasis + i] = v;
-    if (ib != jb) Bm[(long)i * kMaxBasis + j] = v;
+    Bm[(long)j * ld + i] = v;
+    if (ib != jb) Bm[(long)i * ld + j] = v;
+}
+
+// ------------------------------------------------------------------------
+// eigen method for windows beyond the small-SVD kernel: block one-sided
+// Jacobi on S (L x L, column-major, symmetric positive semi-definite).  Its
+// columns are split into blocks of kBjW; in each round every workgroup
+// takes one pair of blocks M (L x 2 kBjW), forms the Gram G = M^T M,
+// diagonalises it by cyclic two-sided Jacobi (J^T G J diagonal, J
+// orthogonal, accumulated) and replaces M by M J.  The rounds of a sweep
+// pair every two blocks once (circle method).  When no pair has a Gram
+// entry above tol sqrt(G_kk G_ll), the columns are mutually orthogonal:
+// column j is lambda_j u_j, lambda_j = |column j| an eigenvalue of S and
+// u_j its eigenvector (S V = U Sigma with U = V for S symmetric PSD).
+// ------------------------------------------------------------------------
+
+// Column of S behind position k (0 .. kBjN-1) of the block pair, or -1
+// (a block index < 0 is the empty block of an odd count).
+__device__ __forceinline__ int bj_col(int2 pr, int k, int L) {
+    const int blk = k < kBjW ? pr.x : pr.y;
+    const int c = blk * kBjW + (k % kBjW);
+    return (blk >= 0 && c < L) ? c : -1;
+}
+
+// One workgroup per block pair: Gram, convergence test (flag[0] = 1 if an
+// off-diagonal Gram entry exceeds both tol sqrt(G_kk G_ll) and floor_abs,
+// an absolute level below which two columns far under the matrix's scale
+// are left as they are), rotation J into
+// Jout[pair] (row-major kBjN x kBjN); flag[1] = 1 if the inner iteration
+// ran out of sweeps.
+__global__ void __launch_bounds__(256)
+k_bj_pair(const double* __restrict__ A, int L, const int2* __restrict__ pairs, double* __restrict__ Jout,
+          int* __restrict__ flag, double tol, double floor_abs) {
+    __shared__ double G[kBjN][kBjN + 1];
+    __shared__ double J[kBjN][kBjN + 1];
+    __shared__ double tile[64][kBjN + 1];
+    __shared__ double cs[kBjN / 2][2];
+    __shared__ int pq[kBjN / 2][2];
+    __shared__ int rot;
+    const int2 pr = pairs[blockIdx.x];
+    const int t = threadIdx.x;
+    constexpr int NE = kBjN * kBjN / 256;   // Gram entries per thread
+    double acc[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) acc[u] = 0.0;
+    for (int i0 = 0; i0 < L; i0 += 64) {
+        for (int e = t; e < 64 * kBjN; e += 256) {
+            const int i = e % 64, k = e / 64;
+            const int c = bj_col(pr, k, L);
+            tile[i][k] = (c >= 0 && i0 + i < L) ? A[(long)c * L + i0 + i] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NE; ++u) {
+            const int e = t + 256 * u, k = e / kBjN, l = e % kBjN;
+            double sum = 0.0;
+            for (int i = 0; i < 64; ++i) sum += tile[i][k] * tile[i][l];
+            acc[u] += sum;
+        }
+        __syncthreads();
+    }
+    if (t == 0) rot = 0;
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+        const int e = t + 256 * u, k = e / kBjN, l = e % kBjN;
+        G[k][l] = acc[u];
+        J[k][l] = k == l ? 1.0 : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+        const int e = t + 256 * u, k = e / kBjN, l = e % kBjN;
+        if (k != l && fabs(G[k][l]) > tol * sqrt(G[k][k] * G[l][l]) && fabs(G[k][l]) > floor_abs) rot = 1;
+    }
+    __syncthreads();
+    if (rot == 0) {
+        // already orthogonal: J = I
+        for (int e = t; e < kBjN * kBjN; e += 256) Jout[(long)blockIdx.x * kBjN * kBjN + e] = (e / kBjN == e % kBjN);
+        return;
+    }
+    if (t == 0) flag[0] = 1;
+    bool done = false;
+    for (int sweep = 0; sweep < 40 && !done; ++sweep) {
+        __syncthreads();
+        if (t == 0) rot = 0;
+        __syncthreads();
+        for (int r = 0; r < kBjN - 1; ++r) {
+            if (t < kBjN / 2) {
+                // circle method: position kBjN-1 fixed, the others rotate
+                const int a = t == 0 ? kBjN - 1 : (r + t) % (kBjN - 1);
+                const int b = t == 0 ? r : (r - t + kBjN - 1) % (kBjN - 1);
+                const int p = min(a, b), q = max(a, b);
+                const double gpp = G[p][p], gqq = G[q][q], gpq = G[p][q];
+                double c = 1.0, sn = 0.0;
+                if (gpq != 0.0 && fabs(gpq) > tol * sqrt(gpp * gqq) && fabs(gpq) > floor_abs) {
+                    // J^T G J zeroes (p, q): t = s / c is the smaller root of
+                    // t^2 + 2 theta t - 1 = 0, theta = (G_qq - G_pp) / (2 G_pq)
+                    const double th = (gqq - gpp) / (2.0 * gpq);
+                    const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    sn = tt * c;
+                    rot = 1;
+                }
+                pq[t][0] = p;
+                pq[t][1] = q;
+                cs[t][0] = c;
+                cs[t][1] = sn;
+            }
+            __syncthreads();
+            // G J and J J_r: columns p, q of each pair (pairs are disjoint)
+            for (int e = t; e < (kBjN / 2) * kBjN; e += 256) {
+                const int pi = e / kBjN, k = e % kBjN;
+                const double c = cs[pi][0], sn = cs[pi][1];
+                if (sn == 0.0) continue;
+                const int p = pq[pi][0], q = pq[pi][1];
+                const double gp = G[k][p], gq = G[k][q];
+                G[k][p] = c * gp - sn * gq;
+                G[k][q] = sn * gp + c * gq;
+                const double jp = J[k][p], jq = J[k][q];
+                J[k][p] = c * jp - sn * jq;
+                J[k][q] = sn * jp + c * jq;
+            }
+            __syncthreads();
+            // J_r^T (G J_r): rows p, q; the rotated pair's entry is zero by
+            // construction (set exactly rather than left at rounding level,
+            // which the relative test could not pass when G_pp >> G_qq)
+            for (int e = t; e < (kBjN / 2) * kBjN; e += 256) {
+                const int pi = e / kBjN, k = e % kBjN;
+                const double c = cs[pi][0], sn = cs[pi][1];
+                if (sn == 0.0) continue;
+                const int p = pq[pi][0], q = pq[pi][1];
+                const double gp = G[p][k], gq = G[q][k];
+                G[p][k] = k == q ? 0.0 : c * gp - sn * gq;
+                G[q][k] = k == p ? 0.0 : sn * gp + c * gq;
+            }
+            __syncthreads();
+        }
+        done = rot == 0;
+    }
+    if (!done && t == 0) flag[1] = 1;
+    for (int e = t; e < kBjN * kBjN; e += 256) Jout[(long)blockIdx.x * kBjN * kBjN + e] = J[e / kBjN][e % kBjN];
+}
+
+// M = M J for the columns of each block pair, rows in chunks of 64: grid
+// (row chunks, pairs).  Each workgroup reads its whole chunk before writing
+// it back, and the pairs of a round own disjoint columns.
+__global__ void __launch_bounds__(256)
+k_bj_apply(double* __restrict__ A, int L, const int2* __restrict__ pairs, const double* __restrict__ Jin) {
+    __shared__ double M[64][kBjN + 1];
+    __shared__ double J[kBjN][kBjN + 1];
+    const int2 pr = pairs[blockIdx.y];
+    const int i0 = blockIdx.x * 64;
+    const int t = threadIdx.x;
+    const double* Jp = Jin + (long)blockIdx.y * kBjN * kBjN;
+    for (int e = t; e < kBjN * kBjN; e += 256) J[e / kBjN][e % kBjN] = Jp[e];
+    for (int e = t; e < 64 * kBjN; e += 256) {
+        const int i = e % 64, k = e / 64;
+        const int c = bj_col(pr, k, L);
+        M[i][k] = (c >= 0 && i0 + i < L) ? A[(long)c * L + i0 + i] : 0.0;
+    }
+    __syncthreads();
+    for (int e = t; e < 64 * kBjN; e += 256) {
+        const int i = e % 64, l = e / 64;
+        const int c = bj_col(pr, l, L);
+        if (c < 0 || i0 + i >= L) continue;
+        double sum = 0.0;
+        for (int k = 0; k < kBjN; ++k) sum += M[i][k] * J[k][l];
+        A[(long)c * L + i0 + i] = sum;
+    }
+}
+
+// lam[c] = |column c of A| (one wave per column, fixed order).
+__global__ void __launch_bounds__(256)
+k_bj_norms(const double* __restrict__ A, int L, double* __restrict__ lam) {
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= L) return;
+    double sum = 0.0;
+    for (int i = lane_id(); i < L; i += 64) {
+        const double v = A[(long)c * L + i];
+        sum += v * v;
+    }
+    sum = wave_sum(sum);
+    if (lane_id() == 0) lam[c] = sqrt(sum);
+}
+
+// U_c = column perm[c] of A / lam[perm[c]] (0 for lam = 0), sigma_c =
+// sqrt(lam[perm[c]]), c < r.
+__global__ void __launch_bounds__(256)
+k_bj_take(const double* __restrict__ A, int L, const int* __restrict__ perm, const double* __restrict__ lam,
+          double* __restrict__ U, double* __restrict__ sigma, int r) {
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < (long)L * r; e += (long)gridDim.x * 256) {
+        const int c = (int)(e / L), i = (int)(e % L);
+        const int j = perm[c];
+        const double l = lam[j];
+        U[(long)c * L + i] = l > 0.0 ? A[(long)j * L + i] / l : 0.0;
+    }
+    if (blockIdx.x == 0)
+        for (int c = threadIdx.x; c < r; c += 256) sigma[c] = sqrt(lam[perm[c]]);
 }
 
 // After the SVD of the symmetric positive semi-definite S (its left singular

@@ -93,7 +93,19 @@ void launch_rrow(hipStream_t st, const double* V, long K, const int* krow, int A
 // nb = ceil(L / 16).  Then U and sigma of the r leading eigenpairs from the
 // small SVD's output.
 void launch_xgram(hipStream_t st, const double* xc, const int* offL, int L, const int* offK, long K, int nchunk,
-                  double* part, double* out, double* Bm);
+                  double* part, double* out, double* Bm, long ld);
+// One round of the block Jacobi eigensolver on the L x L column-major A:
+// npairs disjoint block pairs (block indices, -1 = empty block), their
+// rotations in J (npairs x kBjN^2); flag[0] set if a pair was not yet
+// orthogonal to tol (entries below floor_abs count as orthogonal), flag[1]
+// if an inner iteration ran out of sweeps.
+void launch_bj_round(hipStream_t st, double* A, int L, const int2* pairs, int npairs, double* J, int* flag,
+                     double tol, double floor_abs);
+// lam[c] = |column c of A|.
+void launch_bj_norms(hipStream_t st, const double* A, int L, double* lam);
+// U (L x r) = columns perm[0..r) of A / lam, sigma = sqrt(lam[perm]).
+void launch_bj_take(hipStream_t st, const double* A, int L, const int* perm, const double* lam, double* U,
+                    double* sigma, int r);
 void launch_eig_take(int nitems, hipStream_t st, const LzDesc* lzs, const ResDesc* res, const Item* items, int L,
                      int r);
 // p[0..n) = v on stream st.

@@ -729,11 +729,79 @@ def test_eigen_method_agrees_with_lanczos_and_extends(ctx):
 
 def test_eigen_method_limits(ctx):
     import paper_1309_5050_amd as S
-    x = np.random.default_rng(2).standard_normal((40, 40))
-    with pytest.raises(S.SsaError):
-        ctx.decompose(x, (12, 12), 3, method="eigen")    # 144 cells > 128
+    x = np.random.default_rng(2).standard_normal((80, 80))
+    with pytest.raises(S.SsaError) as e:
+        ctx.decompose(x, (65, 65), 3, method="eigen")    # 4225 cells > 4096
+    assert e.value.code == -1
     with pytest.raises(ValueError):
-        ctx.decompose(x, (5, 5), 3, method="svd")
+        ctx.decompose(x[:40, :40], (5, 5), 3, method="svd")
+
+
+def _mars_full():
+    w = W.mars_like()
+    return dict(kind="image", x=np.nan_to_num(w["x"]), mask=None, wmask=None, window=(25, 25), r=50)
+
+
+# windows beyond the 128 cells of the small-SVD kernel: block Jacobi on S
+EIGEN_BIG_CASES = {
+    "image_96_w10x20": lambda: W.image_2d(n=96, lw=10, r=12, seed=44) | {"window": (10, 20)},
+    "series_300_L250_rankdef": lambda: W.series_1d(n=300, L=250, r=10, seed=45),
+    "disc_80_w15x12": lambda: dict(W.shaped_disc(n=80, radius=36.0, lw=15, r=10, hole_r=(1, 2)), window=(15, 12)),
+    "mars_like_25x25": _mars_full,
+}
+
+
+@pytest.mark.parametrize("name", list(EIGEN_BIG_CASES))
+def test_eigen_method_large_windows_match_oracle(ctx, name):
+    """The eigen method for windows of more than 128 cells (the paper's
+    25 x 25 window on its 258 x 275 image: S is 625 x 625 beside a 625 x 58734
+    trajectory matrix), S's eigenpairs by block Jacobi, against the oracle's
+    eigenpairs of S = X X^T: sigma within 1e-10 sigma_1 where sigma_i >= 1e-3
+    sigma_1 (a squared matrix resolves no more), spans and reconstructions of
+    gap-stable prefix groups within 20 tol sigma_1 / gap; a rank-deficient S
+    (L > K) included."""
+    w = EIGEN_BIG_CASES[name]()
+    tol = 1e-10
+    sh, so, Uo, Vo = oracle.decompose(w["x"], w["mask"], w["wmask"], w["window"], method="gram", nvec=12)
+    assert sh.L > 128
+    r = min(w["r"], sh.L - 1, sh.K - 1)
+    d = ctx.decompose(w["x"], w["window"], r, mask=w["mask"], wmask=w["wmask"], method="eigen")
+    st = d.stats
+    print(f"{name}: L={sh.L} K={sh.K} sweeps {st['svd_sweeps']} converged {st['converged']}")
+    assert st["converged"] == 1
+    s = d.sigma
+    big = so[:r] >= 1e-3 * so[0]
+    assert np.max(np.abs(s - so[:r])[big]) <= tol * so[0], (name, np.max(np.abs(s - so[:r])[big]) / so[0])
+    U, _ = d.vectors_lex()
+    x = w["x"] if w["x"].ndim == 2 else w["x"][:, None]
+    for k in range(1, min(r, 12)):
+        gap = so[k - 1] - so[k]
+        if gap < 1e-3 * so[0] or not big[k - 1]:
+            continue
+        g = list(range(k))
+        assert proj_dist(U[:, g], Uo[:, g]) <= C_SUB * tol * so[0] / gap, (name, k)
+        ref = oracle.reconstruct(sh, so, Uo, Vo, g)
+        got = d.reconstruct([g])[0]
+        assert np.array_equal(np.isnan(got), np.isnan(ref))
+        cov = ~np.isnan(ref)
+        e = np.linalg.norm(got[cov] - ref[cov]) / np.linalg.norm(np.nan_to_num(x[cov]))
+        assert e <= C_SUB * tol * so[0] / gap, (name, k, e)
+
+
+def test_eigen_method_large_window_extends(ctx):
+    """A continuation of a large-window eigen decomposition takes further
+    eigenpairs of the resident rotated S: identical to asking for them at
+    once."""
+    w = W.image_2d(n=96, lw=10, r=6, seed=46)
+    a = ctx.decompose(w["x"], (12, 14), 6, method="eigen")
+    a.extend(11)
+    c = ctx.decompose(w["x"], (12, 14), 11, method="eigen")
+    assert np.array_equal(a.sigma, c.sigma)
+    Ua, _ = a.vectors()
+    Uc, _ = c.vectors()
+    assert np.allclose(Ua, Uc, atol=1e-12, equal_nan=True)
+    b = ctx.decompose(w["x"], (12, 14), 11)
+    np.testing.assert_allclose(a.sigma, b.sigma, rtol=0, atol=1e-9 * b.sigma[0])
 
 
 def _m2d_case(seed=53):
