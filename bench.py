@@ -365,10 +365,12 @@ def main():
 
     note("headline batches")
     value, ms_step, last, prof, rowfam = run_batched(S, ctx, torch, xs, (lw, lw), r, groups, args.precision,
-                                                     args.steps, args.warmup, extra_classes=("lz_ritz",))
+                                                     args.steps, args.warmup, extra_classes=("lz_ritz", "lz_svd"))
     roof, kern = product_roofline(prof, last, args.precision, rowfam, args.steps,
                                   measured_traffic() if args.precision == "fp32" and B == 64 else None)
     stats = last[0].stats
+    st_all = sorted(d.stats["steps"] for d in last)
+    steps_dist = [st_all[0], st_all[len(st_all) // 2], st_all[-1]]
     # the matrix-core kernel (FP64 Ritz rotation): its timing class counts
     # floating-point operations
     pr = prof["lz_ritz"]
@@ -546,7 +548,9 @@ def main():
         "roofline_kernels": kern,
         "mfma": mfma,
         "lanczos": {"steps": stats["steps"], "restarts": stats["restarts"], "basis": stats["basis"],
-                    "max_resid_over_sigma1": stats["max_resid"]},
+                    "max_resid_over_sigma1": stats["max_resid"],
+                    "steps_min_median_max": steps_dist,
+                    "svd_launches_per_batch": prof["lz_svd"]["all_launches"] / max(args.steps, 1)},
         "host_ms_per_batch": {"setup": B * stats["ms_setup"], "lanczos": B * stats["ms_lanczos"],
                               "finish": B * stats["ms_finish"]},
         "fp64_single_instance": single,

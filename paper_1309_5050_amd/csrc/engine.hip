@@ -1072,22 +1072,35 @@ int run_setup(Batch& b) {
         pkc[i] = d->kcount; pkr[i] = d->krow; nr[i] = d->KA;
     }
     std::vector<long> tot(ni, 0);
-    ItemList rowsA, rowsK;
+    // windows without mask (full box) take the sliding column sums for the
+    // origin counts and the weights; masked windows sum over window runs
+    std::vector<int> full, masked;
+    for (int i = 0; i < ni; ++i) (b.ds[i]->L == (long)b.ds[i]->LA * b.ds[i]->LB ? full : masked).push_back(i);
+    ItemList rowsA, rowsK, wrows, kcols, wcols;
     rows_items(rowsA, all, [&](int i) { return b.ds[i]->A; });
     rows_items(rowsK, all, [&](int i) { return b.ds[i]->KA; });
+    rows_items(wrows, masked, [&](int i) { return b.ds[i]->A; });
+    for (int i : full) {
+        for (int c = 0; c < (b.ds[i]->KB + 255) / 256; ++c) kcols.h.push_back(Item{i, c, 0, 0});
+        for (int c = 0; c < (b.ds[i]->B + 255) / 256; ++c) wcols.h.push_back(Item{i, c, 0, 0});
+    }
     TablePack tp;
     const size_t opx = tp.add(px), opm = tp.add(pm), opn = tp.add(pn), opk = tp.add(pk), opxc = tp.add(pxc),
                  opw = tp.add(pw), opnp = tp.add(pnp), opkp = tp.add(pkp), opkc = tp.add(pkc), opkr = tp.add(pkr),
-                 onr = tp.add(nr), otot = tp.add(tot), oa = tp.add(rowsA.h), ok = tp.add(rowsK.h);
+                 onr = tp.add(nr), otot = tp.add(tot), oa = tp.add(rowsA.h), ok = tp.add(rowsK.h),
+                 owr = tp.add(wrows.h), okc = tp.add(kcols.h), owc = tp.add(wcols.h);
     if ((rc = tp.upload(st))) return rc;
     const Item* ia = tp.at<Item>(oa);
     const Item* ik = tp.at<Item>(ok);
     launch_shape_clean(rowsA.n(), st, b.ops(), ia, tp.at<const double*>(opx), tp.at<const uint8_t*>(opm),
                        tp.at<uint8_t*>(opn), tp.at<double*>(opxc), tp.at<int*>(opnp));
+    launch_shape_vcount(kcols.n(), st, b.ops(), tp.at<Item>(okc), tp.at<const int*>(opnp), tp.at<int*>(opkp));
     launch_shape_origins(rowsK.n(), st, b.ops(), ik, b.runs(), tp.at<const int*>(opnp), tp.at<uint8_t*>(opk),
                          tp.at<int*>(opkp), tp.at<int*>(opkc));
     launch_shape_rowoff(ni, st, tp.at<const int*>(opkc), tp.at<int*>(opkr), tp.at<int>(onr), tp.at<long>(otot));
-    launch_shape_weights(rowsA.n(), st, b.ops(), ia, b.runs(), tp.at<const int*>(opkp), tp.at<double*>(opw));
+    launch_shape_weights(wrows.n(), st, b.ops(), tp.at<Item>(owr), b.runs(), tp.at<const int*>(opkp),
+                         tp.at<double*>(opw));
+    launch_shape_weights_v(wcols.n(), st, b.ops(), tp.at<Item>(owc), tp.at<const int*>(opkp), tp.at<double*>(opw));
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(tot.data(), tp.at<long>(otot), ni * sizeof(long), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1567,7 +1580,10 @@ int run_lanczos(Batch& b, int max_steps, const std::function<int()>& overlap = n
             if (G.on) launch_step_next(st, b.dstep.as<int>());
         }
         launch_lz_normalize(S.lzb.n(), st, b.lzs(), S.lzb.ptr(), m);
-        launch_lz_svd(S.inst.n(), st, b.lzs(), S.inst.ptr(), m, 40);
+        {
+            ProfSpan p(b.ctx, "lz_svd", st, [] { return 0.0; });
+            launch_lz_svd(S.inst.n(), st, b.lzs(), S.inst.ptr(), m, 40);
+        }
         HIPCHK(hipGetLastError());
         if (cycle == 0 && overlap && (rc = overlap())) return rc;   // host work while the cycle runs
         {

@@ -1247,14 +1247,21 @@ k_shape_origins(const OpDesc* __restrict__ ops, const Item* __restrict__ items, 
     int* kp = kpref[item.inst] + (long)a * (KB + 1);
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
+    // a window without mask: k_shape_vcount has left each origin's count in
+    // kp (read here before the prefix overwrites it)
+    const bool full = op.S[0].mask == nullptr;
     for (int c0 = 0; c0 < KB; c0 += 256) {
         const int b = c0 + threadIdx.x;
         int in = 0;
         if (b < KB) {
             long cnt = 0;
-            for (int t = 0; t < R.nrun; ++t) {
-                const int* pr = np + (long)(a + R.ra[t]) * (B + 1);
-                cnt += pr[b + R.b1[t]] - pr[b + R.b0[t]];
+            if (full) {
+                cnt = kp[b];
+            } else {
+                for (int t = 0; t < R.nrun; ++t) {
+                    const int* pr = np + (long)(a + R.ra[t]) * (B + 1);
+                    cnt += pr[b + R.b1[t]] - pr[b + R.b0[t]];
+                }
             }
             in = cnt == R.total;
             km[b] = (uint8_t)in;
@@ -1274,6 +1281,32 @@ k_shape_origins(const OpDesc* __restrict__ ops, const Item* __restrict__ items, 
     if (threadIdx.x == 0) {
         kp[KB] = carry;
         kcount[item.inst][a] = carry;
+    }
+}
+
+// Origin counts of a window without mask (an LA x LB box): count(ka, b) =
+// sum over t < LA of the N cells in row ka + t, columns [b, b + LB), a
+// sliding sum down each column of the per-row run counts.  One thread per
+// origin-box column (items: instance x chunk of 256 columns), exact integer
+// arithmetic; the counts go to kpref rows (row stride KB + 1), which
+// k_shape_origins reads before it writes the row prefixes there.
+__global__ void __launch_bounds__(256)
+k_shape_vcount(const OpDesc* __restrict__ ops, const Item* __restrict__ items, const int* const* npref,
+               int* const* kpref) {
+    const Item item = items[blockIdx.x];
+    const OpDesc& op = ops[item.inst];
+    const int b = item.idx * 256 + threadIdx.x;
+    const int KA = op.S[1].boxA, KB = op.S[1].boxB, LA = op.S[0].boxA, LB = op.S[0].boxB, B = op.B;
+    if (b >= KB) return;
+    const int* np = npref[item.inst];
+    int* kp = kpref[item.inst];
+    const auto rc = [&](int a) { return np[(long)a * (B + 1) + b + LB] - np[(long)a * (B + 1) + b]; };
+    long sum = 0;
+    for (int t = 0; t < LA; ++t) sum += rc(t);
+    kp[b] = (int)sum;
+    for (int ka = 1; ka < KA; ++ka) {
+        sum += rc(ka + LA - 1) - rc(ka - 1);
+        kp[(long)ka * (KB + 1) + b] = (int)sum;
     }
 }
 
@@ -1342,6 +1375,30 @@ k_shape_weights(const OpDesc* __restrict__ ops, const Item* __restrict__ items, 
             }
         }
         W[b] = (double)cnt;
+    }
+}
+
+// Weights of a window without mask: W(a, b) = sum over ka in (a - LA, a]
+// of the origins of row ka in columns (b - LB, b], a sliding sum down each
+// column of row-prefix differences of the origin mask.  One thread per grid
+// column (items: instance x chunk of 256 columns), exact integer arithmetic.
+__global__ void __launch_bounds__(256)
+k_shape_weights_v(const OpDesc* __restrict__ ops, const Item* __restrict__ items, const int* const* kpref,
+                  double* const* Wout) {
+    const Item item = items[blockIdx.x];
+    const OpDesc& op = ops[item.inst];
+    const int b = item.idx * 256 + threadIdx.x;
+    const int A = op.A, B = op.B, KA = op.S[1].boxA, KB = op.S[1].boxB, LA = op.S[0].boxA, LB = op.S[0].boxB;
+    if (b >= B) return;
+    const int* kp = kpref[item.inst];
+    double* W = Wout[item.inst];
+    const int lo = b - LB + 1 > 0 ? b - LB + 1 : 0, hi = b + 1 < KB ? b + 1 : KB;
+    const auto roww = [&](int ka) { return hi > lo ? kp[(long)ka * (KB + 1) + hi] - kp[(long)ka * (KB + 1) + lo] : 0; };
+    long sum = 0;
+    for (int a = 0; a < A; ++a) {
+        if (a < KA) sum += roww(a);
+        if (a - LA >= 0 && a - LA < KA) sum -= roww(a - LA);
+        W[(long)a * B + b] = (double)sum;
     }
 }
 

@@ -32,6 +32,13 @@ void launch_col(bool f64, int nitems, hipStream_t st, const OpDesc* ops, const R
                 ColArgs a, int MA, int cfg);   // cfg: tile | variant << 8
 void launch_shape_clean(int nitems, hipStream_t st, const OpDesc* ops, const Item* items, const double* const* x,
                         const uint8_t* const* m, uint8_t* const* nset, double* const* xc, int* const* npref);
+// Windows without mask: origin counts by sliding column sums into kpref
+// (before launch_shape_origins), weights by sliding column sums (instead of
+// launch_shape_weights).  Items: instance x chunk of 256 columns.
+void launch_shape_vcount(int nitems, hipStream_t st, const OpDesc* ops, const Item* items, const int* const* npref,
+                         int* const* kpref);
+void launch_shape_weights_v(int nitems, hipStream_t st, const OpDesc* ops, const Item* items,
+                            const int* const* kpref, double* const* W);
 void launch_shape_origins(int nitems, hipStream_t st, const OpDesc* ops, const Item* items, const Runs* runs,
                           const int* const* npref, uint8_t* const* kmask, int* const* kpref, int* const* kcount);
 void launch_shape_rowoff(int ninst, hipStream_t st, const int* const* kcount, int* const* rowoff, const int* nrows,
