@@ -219,6 +219,38 @@ def config_line(S, W, ctx, torch, which, prec, steps, warmup):
             "lanczos_steps_mean": float(np.mean([d.stats["steps"] for d in last]))}
 
 
+def continuous_line(S, W, ctx, torch, xs0, window, r, groups):
+    """256 images of the headline workload: four lockstep batch calls of 64
+    against one call of 256 with 64 slots (continuous batching: images
+    start as others finish).  Decompositions + reconstructions per second,
+    inputs on the device."""
+    dev = xs0[0].device
+    n = 256
+    xs = [torch.tensor(W.image_2d(n=512, lw=64, r=30, seed=3000 + i)["x"], device=dev) for i in range(n)]
+    outs = [torch.empty((len(groups),) + tuple(x.shape), dtype=torch.float64, device=dev) for x in xs]
+
+    def run(parts, slots):
+        ctx.set_slots(slots)
+        for p in parts:
+            ds = ctx.decompose_batch_dev([xs[i] for i in p], window, r, precision="fp32")
+            S.Context.reconstruct_batch_dev(ds, groups, [outs[i] for i in p])
+            del ds
+        torch.cuda.synchronize()
+
+    lock = [list(range(k, k + 64)) for k in range(0, n, 64)]
+    one = [list(range(n))]
+    run(lock[:1], 0)                                  # warm-ups (the memory pool grows to each call's size)
+    run(one, 64)
+    t0 = time.perf_counter()
+    run(lock, 0)
+    t1 = time.perf_counter()
+    run(one, 64)
+    t2 = time.perf_counter()
+    ctx.set_slots(0)
+    return {"workload": "256 images 512x512, 64x64 window, r=30, fp32", "lockstep_4x64_decomps_per_s": n / (t1 - t0),
+            "slots64_one_call_decomps_per_s": n / (t2 - t1)}
+
+
 def paper_context(S, W, torch):
     """The paper's decomposition timings re-run on a synthetic Mars-like
     stand-in (258 x 275, bright disc on a zero = NA background, planar sines
@@ -498,6 +530,8 @@ def main():
                                                 "(the workload the CPU oracle is timed on)",
                                     "batch": 64, "precision": "fp64", "decomps_per_s": rr, "ms_per_step": msr}
         del lr
+        note("continuous batching")
+        configs["continuous_image512_fp32"] = continuous_line(S, W, ctx, torch, xs, (lw, lw), r, groups)
         note("paper context")
         paper = paper_context(S, W, torch)
 

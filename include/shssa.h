@@ -411,6 +411,15 @@ int ssa_poll(ssa_ctx* ctx, uint64_t ticket, int* done);
 int ssa_wait(ssa_ctx* ctx, uint64_t ticket);
 int ssa_take(ssa_ctx* ctx, uint64_t ticket, ssa_decomp** out, double* recon, ssa_times* times);
 
+/* Continuous batching: at most `slots` decompositions of one kernel class
+ * advance together in a batch call (ssa_decompose_batch*); when some finish
+ * at a restart-cycle boundary, waiting requests of the call take their
+ * slots and begin while the others continue (each keeps its own step on the
+ * device).  A request's results are the same whether it runs alone or
+ * joins a running batch.  0 (the default): every request of a class starts
+ * at once.  SSA_EINVAL for slots < 0. */
+int ssa_ctx_set_slots(ssa_ctx* ctx, int slots);
+
 /* Blocks until all work queued on the context's stream is complete. */
 int ssa_ctx_sync(ssa_ctx* ctx);
 

@@ -210,6 +210,11 @@ class Context:
     def sync(self):
         check(lib().ssa_ctx_sync(self._h), "ssa_ctx_sync")
 
+    def set_slots(self, slots: int):
+        """Continuous batching: at most `slots` decompositions of a batch call
+        advance together, the others join as slots free up (0: all at once)."""
+        check(lib().ssa_ctx_set_slots(self._h, int(slots)), "ssa_ctx_set_slots")
+
     def set_stream(self, stream):
         check(lib().ssa_ctx_set_stream(self._h, stream), "ssa_ctx_set_stream")
 

@@ -41,6 +41,7 @@ _SIGS = {
     "ssa_ctx_destroy": (None, [C.c_void_p]),
     "ssa_ctx_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "ssa_ctx_sync": (C.c_int, [C.c_void_p]),
+    "ssa_ctx_set_slots": (C.c_int, [C.c_void_p, C.c_int]),
     "ssa_ctx_profile": (C.c_int, [C.c_void_p, C.c_char_p]),
     "ssa_ctx_profile_every": (C.c_int, [C.c_void_p, C.c_int]),
     "ssa_ctx_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_long),

@@ -109,6 +109,7 @@ struct ssa_ctx {
     std::map<std::pair<int, int>, int> col_tc;       // (f64, MA) -> tuned column tile
     std::mutex tune_mu;                               // one tuning at a time; guards col_tc
     std::string tune_path;                            // autotune cache file ("" = none)
+    int slots = 0;                                    // continuous batching: instances advancing together (0 = all)
 
     // Tuning results persist in a text file, one choice per line:
     //   col <f64> <MA> <config>
@@ -1407,29 +1408,36 @@ void launch_step(Batch& b, StepLists& S, int j, int jstart, int mode, bool prof 
     }
 }
 
-// Basis size of the thick-restart bidiagonalisation: r plus min(r + 20, 50)
-// further vectors.  Past about 50 extra vectors, each cycle's longer
-// reorthogonalisations and larger small SVD cost more than its fewer
-// restarts save: on 64-image batches of 512 x 512 with a 64 x 64 window
-// this beat r + max(r + 20, 2 r) by 1.4% at r = 30, 7.6% at r = 40 and
-// 4% at r = 60, and matched it at r <= 25.
+// Basis size m and restart size kk of the thick-restart bidiagonalisation.
+// The basis holds r plus min(r + 20, 50) further vectors (at most
+// kMaxBasis and the short side): past about 50 extra vectors each cycle's
+// longer reorthogonalisations and larger small SVD cost more than its fewer
+// restarts save (64-image batches of 512 x 512 with a 64 x 64 window).  A
+// restart keeps kk = m - m / q Ritz vectors, q >= 2 the smallest divisor of
+// m (m rounded down to a multiple of q) that leaves kk >= r: every cycle
+// after the first adds c = m / q vectors and the first one, from a start
+// vector, adds m = q c.  So an instance that starts at a cycle boundary of
+// a running batch meets all its later boundaries, with the steps it would
+// take alone (continuous batching).  For r <= 50 this keeps half the
+// basis, r + 10 Ritz vectors at r = 30, where keeping a quarter of the
+// extra vectors (42) measured the same within noise.
 int basis_size(long nshort, int r) {
-    int m = std::min(2 * r + 20, r + 50);
-    if (const char* e = std::getenv("SHSSA_BASIS")) m = std::max(r + 2, std::atoi(e));   // experiments
-    m = std::min(m, kMaxBasis);
-    if (nshort <= m) m = (int)nshort;
-    return m;
+    int m0 = std::min(2 * r + 20, r + 50);
+    if (const char* e = std::getenv("SHSSA_BASIS")) m0 = std::max(r + 2, std::atoi(e));   // experiments
+    m0 = std::min(m0, kMaxBasis);
+    if (nshort <= m0) m0 = (int)nshort;
+    for (int q = 2; q <= m0; ++q) {
+        const int m = m0 - m0 % q, kk = m - m / q;
+        if (kk >= r && kk < m) return m;
+    }
+    return m0;
 }
 
-// Ritz vectors kept by a thick restart of a basis of size m: r plus a
-// quarter of the rest.  Keeping fewer leaves more new steps per cycle (fewer
-// cycles, fewer small SVDs) and shorter reorthogonalisations; on the
-// 512 x 512 / r = 30 batch a quarter beat a half by about 8% (same
-// residual test).
+// Ritz vectors kept by a restart of a basis of size m (see basis_size).
 int restart_keep(int m, int r) {
-    int extra = (m - r) / 4;
-    if (const char* e = std::getenv("SHSSA_KEEP")) extra = std::atoi(e);   // experiments
-    return std::max(r, std::min(m - 1, r + extra));
+    for (int q = 2; q <= m; ++q)
+        if (m % q == 0 && m - m / q >= r && m - m / q < m) return m - m / q;
+    return std::max(r, m - 1);
 }
 
 // Bidiagonalisation steps (all their launches, each step read from the
@@ -1691,6 +1699,203 @@ int run_lanczos(Batch& b, int max_steps, const std::function<int()>& overlap = n
         }
         jstart = kk;
     }
+    HIPCHK(hipGetLastError());
+    return SSA_OK;
+}
+
+// Ritz vectors and singular values of instances whose bidiagonalisation is
+// done (into U or V by side, and sigma).
+int lanczos_outputs(Batch& b, const std::vector<int>& done, int m, int rmax) {
+    hipStream_t st = b.st;
+    const int ni = (int)b.ds.size();
+    int rc;
+    std::vector<double*> outs(ni, nullptr);
+    for (int i : done) outs[i] = b.ds[i]->side == 0 ? b.ds[i]->U : b.ds[i]->V;
+    DevVec douts;
+    if ((rc = douts.put(outs, st))) return rc;
+    ItemList R, I;
+    for (int i : done) {
+        const long n = b.ds[i]->nshort;
+        for (long rb = 0; rb < (n + 63) / 64; ++rb)
+            for (int cb = 0; cb < (b.ds[i]->r + 31) / 32; ++cb) R.h.push_back(Item{i, (int)rb, 0, cb});
+        I.h.push_back(Item{i, 0, 0, 0});
+    }
+    if ((rc = upload_lists({&R, &I}, st))) return rc;
+    {
+        ProfSpan p(b.ctx, "lz_ritz", st, [&] {
+            double f = 0.0;
+            for (int i : done) f += 2.0 * b.ds[i]->nshort * m * b.ds[i]->r;
+            return f;
+        });
+        launch_lz_ritz(R.n(), st, b.lzs(), R.ptr(), m, rmax, douts.as<double*>());
+    }
+    launch_lz_sigma(I.n(), st, b.lzs(), b.res(), I.ptr());
+    return SSA_OK;
+}
+
+// Continuous batching of one kernel class: at most `slots` instances of the
+// batch advance together; when some finish at a cycle boundary, waiting
+// instances of the batch take their slots and begin from their start
+// vectors.  Each instance keeps its own step counter [j, jstart] on the
+// device, which the step kernels read, so instances at different steps
+// share every launch.  With the cycle plan of basis_size and restart_keep
+// all boundaries are common (a first cycle lasts q later ones), and an
+// instance runs exactly the steps, restarts and reductions it would run
+// alone: its results do not depend on when it joined.
+int run_lanczos_cont(Batch& b, int max_steps, int slots, const std::function<int()>& overlap) {
+    hipStream_t st = b.st;
+    const int ni = (int)b.ds.size();
+    int rc;
+    const int m = basis_size(b.ds[0]->nshort, b.ds[0]->r);
+    const int kk = restart_keep(m, b.ds[0]->r);
+    const int c = m - kk;
+    int rmax = 0;
+    for (auto* d : b.ds) rmax = std::max(rmax, d->r);
+    if (!(rmax <= kk && kk < m && m <= kMaxBasis) || m % c != 0)
+        return fail(SSA_ERANK, "rank leaves no room in the Lanczos basis");
+    // per-instance step counters
+    DevVec dctr;
+    if ((rc = dctr.reserve((size_t)ni * 2 * sizeof(int)))) return rc;
+    for (int i = 0; i < ni; ++i) b.ds[i]->lz.step = dctr.as<int>() + 2 * i;
+    if ((rc = b.upload_descs())) return rc;
+    std::vector<int> act, pending;
+    for (int i = 0; i < ni; ++i) (i < slots ? act : pending).push_back(i);
+    std::vector<int> steps(ni, 0), restarts(ni, 0), jh(ni, 0), cycles(ni, 0), bdrest(ni, 0);
+    std::vector<int> flags(4 * ni);
+    std::vector<double> betas(2 * ni);
+    for (auto* d : b.ds) d->st.basis = m;
+    // start vectors and counters [0, 0] of instances entering the batch
+    const auto start = [&](const std::vector<int>& who) -> int {
+        ItemList Z, I;
+        for (int i : who) {
+            for (int k = 0; k < b.ds[i]->lz.nblk; ++k) Z.h.push_back(Item{i, k, 0, 0});
+            I.h.push_back(Item{i, 0, 0, 0});
+            jh[i] = 0;
+        }
+        int e;
+        if ((e = upload_lists({&Z, &I}, st))) return e;
+        launch_lz_start(Z.n(), st, b.lzs(), Z.ptr(), 0ULL);   // each instance's own seed
+        launch_step_set(I.n(), st, b.lzs(), I.ptr(), 0, 0);
+        return SSA_OK;
+    };
+    if ((rc = start(act))) return rc;
+    StepLists S;
+    build_step_lists(b, act, S);
+    if ((rc = upload_step_lists(S, st))) return rc;
+    bool first = true;
+    while (!act.empty()) {
+        for (int k = 0; k < c; ++k) {
+            launch_step(b, S, kStepDev, kStepDev, IN_LZ_STEP);
+            launch_step_next_inst(S.inst.n(), st, b.lzs(), S.inst.ptr());
+        }
+        HIPCHK(hipGetLastError());
+        if (first && overlap && (rc = overlap())) return rc;   // host work while the steps run
+        first = false;
+        std::vector<int> ends, rest;
+        for (int i : act) {
+            jh[i] += c;
+            (jh[i] == m ? ends : rest).push_back(i);
+        }
+        std::vector<int> done, cont, fresh;
+        if (!ends.empty()) {
+            ItemList N, I;
+            for (int i : ends) {
+                for (int k = 0; k < b.ds[i]->lz.nblk; ++k) N.h.push_back(Item{i, k, 0, 0});
+                I.h.push_back(Item{i, 0, 0, 0});
+            }
+            if ((rc = upload_lists({&N, &I}, st))) return rc;
+            launch_lz_normalize(N.n(), st, b.lzs(), N.ptr(), m);
+            {
+                ProfSpan p(b.ctx, "lz_svd", st, [] { return 0.0; });
+                launch_lz_svd(I.n(), st, b.lzs(), I.ptr(), m, 40);
+            }
+            HIPCHK(hipGetLastError());
+            const size_t fb = (size_t)ni * 4 * sizeof(int), bb = (size_t)ni * 2 * sizeof(double);
+            if (!b.dflag.p || b.dflag.cap < fb + bb) {
+                std::vector<char> z(fb + bb, 0);
+                if ((rc = b.dflag.put(z, st))) return rc;
+            }
+            char* dv = b.dflag.as<char>();
+            launch_gather_flags(ni, st, b.lzs(), reinterpret_cast<int*>(dv), reinterpret_cast<double*>(dv + fb));
+            void* hb = nullptr;
+            if ((rc = b.ctx->readback_buf(st, fb + bb, &hb))) return rc;
+            HIPCHK(hipMemcpyAsync(hb, dv, fb + bb, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            std::memcpy(flags.data(), hb, fb);
+            std::memcpy(betas.data(), static_cast<char*>(hb) + fb, bb);
+            // the decisions of the lockstep loop, per instance
+            for (int i : ends) {
+                steps[i] += m - (cycles[i] == 0 ? 0 : kk);
+                ++cycles[i];
+                auto* d = b.ds[i];
+                d->st.svd_sweeps += flags[4 * i + 1];
+                const bool ok = flags[4 * i] != 0;
+                const bool bd = flags[4 * i + 2] != 0;
+                if (bd && bdrest[i] < 2 && steps[i] < max_steps) {
+                    bdrest[i]++;
+                    restarts[i]++;
+                    fresh.push_back(i);
+                    cont.push_back(i);
+                    continue;
+                }
+                if (ok || bd || steps[i] >= max_steps) {
+                    done.push_back(i);
+                    d->st.converged = ok || bd;
+                    d->st.steps = steps[i];
+                    d->st.restarts = restarts[i];
+                    d->st.max_resid = betas[2 * i + 1];
+                    if (!(ok || bd)) d->status = fail(SSA_ENOCONV, "bidiagonalisation reached its step limit");
+                } else {
+                    cont.push_back(i);
+                    restarts[i]++;
+                }
+            }
+            if (!done.empty() && (rc = lanczos_outputs(b, done, m, rmax))) return rc;
+            if (!cont.empty()) {
+                // the random restart of a breakdown draws from the instance's
+                // own cycle count, as in the lockstep loop
+                std::map<int, std::vector<int>> by_cycle;
+                std::vector<char> isf(ni, 0);
+                for (int i : fresh) isf[i] = 1;
+                for (int i : cont) by_cycle[isf[i] ? cycles[i] : -1].push_back(i);
+                for (auto& kv : by_cycle) {
+                    const std::vector<int>& grp = kv.second;
+                    if ((rc = launch_restart(b, grp, kv.first < 0 ? std::vector<int>{} : grp, m, kk,
+                                             kv.first < 0 ? 0 : kv.first)))
+                        return rc;
+                }
+                ItemList I2;
+                for (int i : cont) {
+                    I2.h.push_back(Item{i, 0, 0, 0});
+                    jh[i] = kk;
+                }
+                if ((rc = upload_lists({&I2}, st))) return rc;
+                launch_step_set(I2.n(), st, b.lzs(), I2.ptr(), kk, kk);
+            }
+        }
+        // the next active set: continuing and mid-cycle instances, then
+        // waiting ones in the freed slots
+        std::vector<int> next = rest;
+        next.insert(next.end(), cont.begin(), cont.end());
+        std::vector<int> joiners;
+        while (!pending.empty() && (int)(next.size() + joiners.size()) < slots) {
+            joiners.push_back(pending.front());
+            pending.erase(pending.begin());
+        }
+        if (!joiners.empty() && (rc = start(joiners))) return rc;
+        next.insert(next.end(), joiners.begin(), joiners.end());
+        std::sort(next.begin(), next.end());
+        if (next != act) {
+            act = next;
+            if (!act.empty()) {
+                build_step_lists(b, act, S);
+                if ((rc = upload_step_lists(S, st))) return rc;
+            }
+        }
+    }
+    // the handles keep the batch's shared counter (continuations use it)
+    for (auto* d : b.ds) d->lz.step = b.dstep.as<int>();
+    if ((rc = b.upload_descs())) return rc;
     HIPCHK(hipGetLastError());
     return SSA_OK;
 }
@@ -2079,7 +2284,15 @@ void run_planned(ssa_ctx* ctx, const std::vector<ssa_decomp*>& grp, hipStream_t 
         const double t_spec = ms_since(t1);
         auto t2 = Clock::now();
         FinishLists F;
-        if (!rc) rc = b.ds[0]->eigen ? run_eigen(b, F) : run_lanczos(b, step_limit(), [&] { return finish_lists(b, F); });
+        if (!rc) {
+            const int slots = ctx->slots;
+            if (b.ds[0]->eigen)
+                rc = run_eigen(b, F);
+            else if (slots > 0 && (int)b.ds.size() > slots)
+                rc = run_lanczos_cont(b, step_limit(), slots, [&] { return finish_lists(b, F); });
+            else
+                rc = run_lanczos(b, step_limit(), [&] { return finish_lists(b, F); });
+        }
         const double t_lz = ms_since(t2);
         auto t3 = Clock::now();
         if (!rc) rc = run_finish(b, F);
@@ -2635,6 +2848,13 @@ int ssa_ctx_set_stream(ssa_ctx* ctx, void* stream) {
     if (ctx->own) (void)hipStreamDestroy(ctx->st);
     ctx->own = false;
     ctx->st = static_cast<hipStream_t>(stream);
+    return SSA_OK;
+}
+
+int ssa_ctx_set_slots(ssa_ctx* ctx, int slots) {
+    if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
+    if (slots < 0) return fail(SSA_EINVAL, "slots must be >= 0");
+    ctx->slots = slots;
     return SSA_OK;
 }
 

@@ -2959,6 +2959,23 @@ __global__ void k_step_next(int* step) {
     if (threadIdx.x == 0) step[0] += 1;
 }
 
+// Per-instance step counters (continuous batching: instances of one launch
+// may be at different steps).  Set [j, jstart] of the listed instances, or
+// advance their j by one.
+__global__ void k_step_set(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int n, int j, int js) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    int* c = const_cast<int*>(lzs[items[e].inst].step);
+    c[0] = j;
+    c[1] = js;
+}
+__global__ void k_step_next_inst(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int n) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    int* c = const_cast<int*>(lzs[items[e].inst].step);
+    c[0] += 1;
+}
+
 // p[0..n) = v (clears flags without a memset node, which a caller's graph
 // capture would record)
 __global__ void k_fill_i32(int* __restrict__ p, int n, int v) {

@@ -61,6 +61,10 @@ void launch_lz_sigma(int ninst, hipStream_t st, const LzDesc* lzs, const ResDesc
 void launch_sign_fix(int nitems, hipStream_t st, const OpDesc* ops, const ResDesc* res, const Item* items,
                      int with_v);
 void launch_gather_flags(int ninst, hipStream_t st, const LzDesc* lzs, int* flags, double* betas);
+// Per-instance step counters ([j, jstart] at each listed instance's
+// LzDesc::step): set them, or advance j by one.
+void launch_step_set(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items, int j, int js);
+void launch_step_next_inst(int nitems, hipStream_t st, const LzDesc* lzs, const Item* items);
 void launch_step_next(hipStream_t st, int* step);
 // Weighted Gram of narr arrays of ncell values over the cells with W > 0:
 // 16 x 16 tiles of the upper triangle (wgram_tiles of them), entry

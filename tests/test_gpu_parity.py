@@ -1190,3 +1190,66 @@ def test_tune_cache_persists_choices(tmp_path, capfd, monkeypatch):
     lines = [l.split() for l in path.read_text().splitlines()]
     assert any(l[0] == "col" and l[1] == "0" for l in lines), lines
     assert np.array_equal(out[0], out[1])
+
+
+def _cont_requests(kind):
+    if kind == "image":
+        out = []
+        for i in range(10):
+            n = 96 + (i % 3) * 7                      # uneven sizes in one kernel class
+            w = W.image_2d(n=n, lw=12, r=8, seed=500 + i)
+            out.append({"x": w["x"][:, : n - (i % 2) * 5], "window": (12, 12), "r": 8})
+        return out
+    out = []
+    for i in range(9):
+        n = 600 + 37 * i
+        w = W.series_1d(n=n, L=200, r=6, seed=600 + i)
+        out.append({"x": w["x"], "window": 200, "r": 6})
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", ["image", "series"])
+def test_continuous_batching_equals_alone(ctx, kind, prec):
+    """Continuous batching: with 4 slots, the requests of a batch call that
+    do not fit start as others finish, in the middle of the batch's run.
+    Every request's sigma and vectors are bit-identical to the same request
+    decomposed alone."""
+    import paper_1309_5050_amd as S
+    reqs = _cont_requests(kind)
+    c = S.Context(0)
+    try:
+        c.set_slots(4)
+        res = c.decompose_batch(reqs, precision=prec)
+    finally:
+        c.set_slots(0)
+    joined = 0
+    for q, d in zip(reqs, res):
+        assert not isinstance(d, Exception), d
+        assert d.status == 0 and d.stats["converged"] == 1
+        alone = ctx.decompose(q["x"], q["window"], q["r"], precision=prec)
+        assert np.array_equal(d.sigma, alone.sigma)
+        U, V = d.vectors_lex()
+        Ua, Va = alone.vectors_lex()
+        assert np.array_equal(U, Ua) and np.array_equal(V, Va)
+        joined += 1
+    assert joined == len(reqs)
+    c.close()
+
+
+def test_continuous_batching_fills_freed_slots(ctx):
+    """More requests than slots all finish, and the batch's instances report
+    the same step counts as alone (their cycles were not stretched by the
+    instances that joined)."""
+    import paper_1309_5050_amd as S
+    reqs = _cont_requests("image")
+    c = S.Context(0)
+    c.set_slots(3)
+    res = c.decompose_batch(reqs, precision="fp32")
+    for q, d in zip(reqs, res):
+        alone = ctx.decompose(q["x"], q["window"], q["r"], precision="fp32")
+        assert d.stats["steps"] == alone.stats["steps"]
+        assert d.stats["restarts"] == alone.stats["restarts"]
+    with pytest.raises(S.SsaError):
+        c.set_slots(-1)
+    c.close()
