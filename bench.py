@@ -354,8 +354,13 @@ def main():
                     help="skip the w-correlation, forecast, continuation and eigen-method timings")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the FP64, 1D, MSSA, shaped and paper-context lines")
-    ap.add_argument("--serve", type=int, default=0, metavar="N",
-                    help="requests of the mixed serving workload for the latency runs (0: skip)")
+    ap.add_argument("--serve", type=int, default=300, metavar="N",
+                    help="requests of the mixed serving workload for the latency runs through the "
+                         "batch calls (0: skip)")
+    ap.add_argument("--serve-engine", type=int, default=0, metavar="N",
+                    help="requests for the library's asynchronous serving engine (ssa_submit); off by "
+                         "default: its worker-thread path is not run on the GPU until a fault seen on an "
+                         "earlier build is explained")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (torch) and exit: the reference "
                          "kernel for scaling HBM byte counters")
@@ -521,6 +526,13 @@ def main():
                                     "roofline": roof64, "roofline_kernels": kern64}
         del last64
         configs["series_1000_fp64"] = config_line(S, W, ctx, torch, 1, "fp64", 3, 1)
+        # the same with the length tuner on (half-length 500 or 512, timed on
+        # the first request; the warm-up batch carries the tuning)
+        os.environ["SHSSA_LEN_TUNE"] = "1"
+        ctx_t = S.Context(0, stream=stream.cuda_stream)
+        del os.environ["SHSSA_LEN_TUNE"]
+        configs["series_1000_fp64_length_tuned"] = config_line(S, W, ctx_t, torch, 1, "fp64", 3, 1)
+        ctx_t.close()
         configs["mssa_50_fp32"] = config_line(S, W, ctx, torch, 3, "fp32", 3, 1)
         configs["shaped_1024_fp32"] = config_line(S, W, ctx, torch, 4, "fp32", 2, 1)
         w2 = W.config(2, "small")
@@ -552,7 +564,10 @@ def main():
 
     serving = None
     if args.serve > 0:
-        serving = serve_bench(S, W, args.serve)
+        note("serving loop")
+        serving = serve_batched(S, W, args.serve)
+    if args.serve_engine > 0:
+        serving = dict(serving or {}, engine=serve_bench(S, W, args.serve_engine))
 
     cpu = None
     if not args.no_cpu:
@@ -696,6 +711,118 @@ def _plain_run(S, data, rate, seed):
     return {"precision": "fp64 plain", "offered_rps": rate, "requests": n, "achieved_rps": n / (t1 - t0),
             "p50_ms": float(np.percentile(ls, 50)), "p99_ms": float(np.percentile(ls, 99)),
             "mean_ms": float(ls.mean())}
+
+
+def _as_request(q):
+    """A serving-mix request as a batch-call request: series as they are,
+    MSSA series side by side in one array (NaN after each series' end) with
+    an L x 1 window, the packing of ssa_decompose_multi."""
+    import numpy as np
+    if q["kind"] == "mssa":
+        nmax = max(len(x) for x in q["x"])
+        arr = np.full((nmax, len(q["x"])), np.nan)
+        for p, x in enumerate(q["x"]):
+            arr[:len(x), p] = x
+        return {"x": arr, "window": (q["window"], 1), "r": q["r"]}
+    return {"x": q["x"], "window": q["window"], "r": q["r"], "mask": q.get("mask"), "wmask": q.get("wmask")}
+
+
+def _size_class(q):
+    """Request kind and transform size class (row kernel class of the series
+    length, or the image side's power of two): requests that would share
+    the library's kernel launches."""
+    if q["kind"] == "2d":
+        n = q["x"].shape[0]
+        return ("2d", (n - 1).bit_length(), q["x"].shape[0] // max(q["window"][0], 1))
+    n = max(len(x) for x in q["x"]) if q["kind"] == "mssa" else len(q["x"])
+    half = (n + 1) // 2
+    return (q["kind"], 0 if half <= 512 else 1 if half <= 2048 else 2)
+
+
+def _batched_server_run(S, data, reqs, prec, rate, seed, max_batch=64):
+    """A server loop over the batch calls: requests arrive as a Poisson
+    process; whenever the GPU is free, the oldest waiting request and the
+    arrived requests of its size class that follow it (up to max_batch) go
+    into one batch call (they share launches; at most 64 of a class advance
+    together, the others take the slots of finished ones), then each result
+    is reconstructed.
+    Latency = the time its reconstruction is on the host minus its arrival;
+    the first 5% of requests are warm-up and left out."""
+    import numpy as np
+    ctx = S.Context(0)
+    ctx.set_slots(64)
+    n = len(data)
+    rng = np.random.default_rng(seed)
+    arrive = np.cumsum(rng.exponential(1.0 / rate, n))
+    lat = np.zeros(n)
+    sizes = []
+    t0 = time.perf_counter()
+    i = 0
+    while i < n:
+        now = time.perf_counter() - t0
+        if arrive[i] > now:
+            time.sleep(arrive[i] - now)
+            now = time.perf_counter() - t0
+        # the arrived requests of the first one's size class (requests of
+        # one class share every launch; a call returns when all its requests
+        # are done, so other classes go into calls of their own)
+        j = i + 1
+        while j < n and arrive[j] <= now and j - i < max_batch and _size_class(data[j]) == _size_class(data[i]):
+            j += 1
+        ds = ctx.decompose_batch(reqs[i:j], precision=prec)
+        for k, d in zip(range(i, j), ds):
+            if isinstance(d, Exception):
+                raise RuntimeError(f"request {k}: {d}")
+            d.reconstruct(data[k]["groups"])      # returns when the request's results are on the host
+            d.free()
+            lat[k] = 1e3 * (time.perf_counter() - t0 - arrive[k])
+        sizes.append(j - i)
+        i = j
+    t1 = time.perf_counter()
+    ctx.close()
+    ls = lat[max(1, n // 20):]
+    return {"precision": prec, "offered_rps": rate, "requests": n, "achieved_rps": n / (t1 - t0),
+            "p50_ms": float(np.percentile(ls, 50)), "p99_ms": float(np.percentile(ls, 99)),
+            "mean_ms": float(ls.mean()), "batches": len(sizes), "mean_batch": float(np.mean(sizes))}
+
+
+def serve_batched(S, W, n_req):
+    """Mixed serving workload (60% 1D N ~ U{500..20000}, L = N/2; 25% MSSA of
+    4..32 series; 15% 2D images of side 64..512 with an (S/8)^2 window;
+    r ~ U{5..40}; groups {1..min(r,4)}), Poisson arrivals at 0.8 x the
+    closed-loop capacity of the plain single-instance FP64 path: that path
+    (one request at a time, synchronous calls) against the batched server
+    loop in FP32 and FP64 at the same arrivals, then the batched FP32 loop
+    at higher rates (1.25, 1.5, 2, 3 x the plain capacity, up to the first
+    it does not sustain)."""
+    mix = W.serving_mix(n_req, seed=5)
+    data = [W.materialize(d) for d in mix]
+    reqs = [_as_request(q) for q in data]
+    ctx = S.Context(0)
+    ncap = min(len(data), 60)
+    for q in data[:3]:
+        _run_sync(ctx, q, "fp64")
+    t0 = time.perf_counter()
+    for q in data[:ncap]:
+        _run_sync(ctx, q, "fp64")
+    cap64 = ncap / (time.perf_counter() - t0)
+    ctx.close()
+    out = {"workload": f"serving mix, {n_req} requests (60% 1D N~U(500,20000), 25% MSSA s~U(4,32), "
+                       f"15% 2D S~U(64,512)), r~U(5,40), Poisson arrivals",
+           "server": "batch calls of the requests that have arrived (64 slots per kernel class)",
+           "plain_fp64_capacity_rps": cap64, "runs": []}
+    out["runs"].append(_plain_run(S, data, 0.8 * cap64, seed=11))
+    for prec in ("fp32", "fp64"):
+        out["runs"].append(_batched_server_run(S, data, reqs, prec, 0.8 * cap64, seed=11))
+    ladder = []
+    for f in (1.25, 1.5, 2.0, 3.0):
+        run = _batched_server_run(S, data, reqs, "fp32", f * cap64, seed=14)
+        run["kept_up"] = run["achieved_rps"] >= 0.95 * run["offered_rps"]
+        ladder.append(run)
+        if not run["kept_up"]:
+            break
+    out["fp32_ladder"] = ladder
+    return out
 
 
 def _keeps_up(run):

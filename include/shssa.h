@@ -115,11 +115,19 @@ typedef struct ssa_stats {
 } ssa_stats;
 
 /* Context: a device, a device-memory budget in bytes (0 = no limit) and an
- * autotune cache.  The context makes its own non-blocking stream;
+ * autotune cache.  Tuned per context: the column pass's tile and kernel
+ * variant (first batch of a precision and column length).  Tuned when the
+ * environment variable SHSSA_LEN_TUNE is set at creation: the padded
+ * transform lengths (the natural 2,3,5,7-smooth length or its power-of-two
+ * alternative, timed on a class's first request; kept for the process; off
+ * by default because power-of-two lengths split mixed-size batches into
+ * more kernel classes).  The context makes its own non-blocking stream;
  * ssa_ctx_set_stream replaces it with the caller's.  tune_cache (nullable,
  * borrowed for the call) names a text file that keeps the tuner's choices
  * across processes: it is read here if it exists, and each new choice is
  * appended to it, one "<kind> <a> <b> <choice>" line per tuned size class
+ * ("col <f64> <MA> <tile | variant << 8>", "rowlen <f64> <nh0> <nh>",
+ * "collen <f64> <MA0> <MA>")
  * (lines this build cannot use are ignored).  NULL: choices last for the
  * context only.  SSA_EDEVICE without a HIP device, SSA_EINVAL for a device
  * index out of range. */

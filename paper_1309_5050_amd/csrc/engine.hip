@@ -86,6 +86,11 @@ bool make_plan(int n, FftPlan& pl) {
     return t == 1;
 }
 
+bool make_plan_ok(int n) {
+    FftPlan pl;
+    return make_plan(n, pl);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -93,6 +98,30 @@ bool make_plan(int n, FftPlan& pl) {
 // ---------------------------------------------------------------------------
 
 struct Server;   // serving state (asynchronous requests), created on first submit
+
+// Transform lengths chosen by the length tuner, process-wide (every context
+// then pads a size class alike, so results agree across contexts):
+// (kind 0 = row half-length / 1 = column length, f64, natural length) ->
+// chosen length.
+std::mutex g_len_mu;
+std::map<std::tuple<int, int, int>, int> g_len_tc;
+
+// Chosen length for a natural length n0, and whether the class is tuned.
+std::pair<int, bool> len_choice(int kind, bool f64, int n0) {
+    std::lock_guard<std::mutex> g(g_len_mu);
+    auto it = g_len_tc.find(std::make_tuple(kind, (int)f64, n0));
+    return it == g_len_tc.end() ? std::make_pair(n0, false) : std::make_pair(it->second, true);
+}
+
+// The power-of-two alternative to a natural transform length (0 if none):
+// rows (half-lengths) up to 512, the register kernels' range, columns up
+// to 1024; at most 30% more points.
+int len_alternative(int kind, int n0, int need) {
+    int p = 1;
+    while (p < need) p <<= 1;
+    if (p == n0 || p > (kind == 0 ? 512 : 1024) || 10 * p > 13 * n0) return 0;
+    return p;
+}
 
 struct ssa_ctx {
     int device = 0;
@@ -110,9 +139,12 @@ struct ssa_ctx {
     std::mutex tune_mu;                               // one tuning at a time; guards col_tc
     std::string tune_path;                            // autotune cache file ("" = none)
     int slots = 0;                                    // continuous batching: instances advancing together (0 = all)
+    bool len_tune = false;                            // length tuner on (SHSSA_LEN_TUNE at creation)
 
     // Tuning results persist in a text file, one choice per line:
-    //   col <f64> <MA> <config>
+    //   col <f64> <MA> <config>         column tile and kernel variant
+    //   rowlen <f64> <nh0> <nh>         row half-length for a natural one
+    //   collen <f64> <MA0> <MA>         column length for a natural one
     // Lines of another kind or with a configuration this build does not
     // compile are ignored when used.  Caller holds tune_mu.
     void tune_load() {
@@ -125,6 +157,10 @@ struct ssa_ctx {
         while (std::fgets(line, sizeof line, f)) {
             if (std::sscanf(line, "%15s %d %d %d", kind, &a, &b, &c) != 4) continue;
             if (std::strcmp(kind, "col") == 0) col_tc[std::make_pair(a, b)] = c;
+            if (std::strcmp(kind, "rowlen") == 0 || std::strcmp(kind, "collen") == 0) {
+                std::lock_guard<std::mutex> g(g_len_mu);
+                g_len_tc[std::make_tuple(kind[0] == 'r' ? 0 : 1, a, b)] = c;
+            }
         }
         std::fclose(f);
     }
@@ -433,6 +469,7 @@ struct ssa_decomp {
     bool tr = false;                 // internal grid is the transpose
     // internal geometry
     int A = 0, B = 0, LA = 0, LB = 0, KA = 0, KB = 0, MA = 1, MB = 0, nh = 0, P = 0, ldp = 0;
+    int nh0 = 0, MA0 = 1;            // natural (smooth) transform lengths before the tuner's choice
     bool rowfam = false, f64 = true;
     bool eigen = false;              // eigen method: S = X X^T and its eigenpairs
     double* Sbig = nullptr;          // eigen method beyond kMaxBasis cells: S, then its rotated columns (L x L)
@@ -570,7 +607,7 @@ ssa_decomp::~ssa_decomp() {
 namespace {
 
 // Validate a request and compute the internal geometry (host side only).
-int plan_request(ssa_ctx* ctx, const ssa_request& q, ssa_decomp* d) {
+int plan_request(ssa_ctx* ctx, const ssa_request& q, ssa_decomp* d, int nh_force = 0, int ma_force = 0) {
     if (q.nx <= 0 || q.ny <= 0 || q.lx <= 0 || q.ly <= 0) return fail(SSA_EINVAL, "sizes must be positive");
     if (!q.x) return fail(SSA_EINVAL, "x is NULL");
     if (q.precision != SSA_FP64 && q.precision != SSA_FP32 && q.precision != SSA_FP32_BASIS32)
@@ -632,13 +669,19 @@ int plan_request(ssa_ctx* ctx, const ssa_request& q, ssa_decomp* d) {
     }
     d->L = d->lrow_h[d->LA];
     // transform sizes
-    d->nh = next_smooth((d->B + 1) / 2);
+    // transform sizes: any M >= N gives the same products and averages, so
+    // the natural (2,3,5,7-smooth) length or the tuner's choice for it
+    d->nh0 = next_smooth((d->B + 1) / 2);
+    d->nh = nh_force > 0 ? nh_force : ctx->len_tune ? len_choice(0, d->f64, d->nh0).first : d->nh0;
+    if (d->nh < (d->B + 1) / 2 || !make_plan_ok(d->nh)) d->nh = d->nh0;
     d->MB = 2 * d->nh;
     d->P = d->nh + 1;
     d->ldp = (d->P + 15) / 16 * 16;   // 128-byte aligned column tiles
     if (row_class(d->nh, d->f64) < 0) return fail(SSA_EINVAL, "row length beyond the supported transform size");
     if (!d->rowfam) {
-        d->MA = next_smooth(d->A);
+        d->MA0 = next_smooth(d->A);
+        d->MA = ma_force > 0 ? ma_force : ctx->len_tune ? len_choice(1, d->f64, d->MA0).first : d->MA0;
+        if (d->MA < d->A || !make_plan_ok(d->MA)) d->MA = d->MA0;
         if (d->MA > 1024) return fail(SSA_EINVAL, "column length beyond the supported transform size (1024)");
     } else {
         d->MA = 1;
@@ -2311,7 +2354,74 @@ void run_planned(ssa_ctx* ctx, const std::vector<ssa_decomp*>& grp, hipStream_t 
         if (grp[i]->status != SSA_OK && st[i] == SSA_OK) st[i] = grp[i]->status;
 }
 
+int decompose_core(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** out, int* status, bool dev,
+                   int nh_force, int ma_force);
+int wait_handle(ssa_decomp* d);
+std::mutex g_len_tune_mu;   // one length tuning at a time (it decomposes, so it cannot hold tune_mu)
+
+// Length tuner: the first request of a (precision, natural transform
+// length) class with a power-of-two alternative (row half-lengths up to
+// 512, column lengths up to 1024, at most 30% more points) is decomposed at
+// both lengths, twice each; the length of the faster second run is kept for
+// the process (every context pads that class alike) and appended to the
+// context's tune cache.  Any length M >= N gives the same products and
+// averages up to rounding.  Off unless the context was created with
+// SHSSA_LEN_TUNE set: a power-of-two length has a register kernel of its own,
+// so requests of different natural lengths that share one LDS kernel class
+// (and one batch) would be split into several classes; the tuner suits
+// workloads of uniform sizes.
+int tune_lengths(ssa_ctx* ctx, int n, const ssa_request* reqs, bool dev) {
+    if (!ctx->len_tune) return SSA_OK;
+    std::lock_guard<std::mutex> tune_lock(g_len_tune_mu);
+    for (int i = 0; i < n; ++i) {
+        ssa_decomp probe;
+        if (plan_request(ctx, reqs[i], &probe) != SSA_OK) continue;
+        for (int kind = 0; kind < 2; ++kind) {
+            if (kind == 1 && probe.rowfam) continue;
+            const int n0 = kind == 0 ? probe.nh0 : probe.MA0;
+            const int alt = len_alternative(kind, n0, kind == 0 ? (probe.B + 1) / 2 : probe.A);
+            if (!alt || len_choice(kind, probe.f64, n0).second) continue;
+            double best = 1e30;
+            int choice = n0;
+            for (int cand : {n0, alt}) {
+                double t = 0.0;
+                for (int rep = 0; rep < 2; ++rep) {
+                    ssa_decomp* h = nullptr;
+                    int stt = SSA_OK;
+                    const auto t0 = Clock::now();
+                    int rc = decompose_core(ctx, 1, &reqs[i], &h, &stt, dev, kind == 0 ? cand : 0,
+                                            kind == 1 ? cand : 0);
+                    if (!rc && h) rc = wait_handle(h);
+                    t = ms_since(t0);
+                    delete h;
+                    if (rc || stt) return SSA_OK;   // leave the class untuned; the request reports its own error
+                }
+                if (std::getenv("SHSSA_TUNE_LOG"))
+                    std::fprintf(stderr, "length tuner: %s f64 %d natural %d -> %d: %.3f ms\n", kind ? "col" : "row",
+                                 (int)probe.f64, n0, cand, t);
+                if (t < best) { best = t; choice = cand; }
+            }
+            {
+                std::lock_guard<std::mutex> g(g_len_mu);
+                g_len_tc[std::make_tuple(kind, (int)probe.f64, n0)] = choice;
+            }
+            {
+                std::lock_guard<std::mutex> g(ctx->tune_mu);
+                ctx->tune_save(kind ? "collen" : "rowlen", (int)probe.f64, n0, choice);
+            }
+        }
+    }
+    return SSA_OK;
+}
+
 int decompose_many(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** out, int* status, bool dev) {
+    if (!ctx || n < 0 || (n > 0 && (!reqs || !out))) return fail(SSA_EINVAL, "bad arguments");
+    (void)tune_lengths(ctx, n, reqs, dev);
+    return decompose_core(ctx, n, reqs, out, status, dev, 0, 0);
+}
+
+int decompose_core(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** out, int* status, bool dev,
+                   int nh_force, int ma_force) {
     if (!ctx || n < 0 || (n > 0 && (!reqs || !out))) return fail(SSA_EINVAL, "bad arguments");
     g_tables_ctx = ctx;
     TableScope tables(ctx, ctx->st);
@@ -2321,7 +2431,7 @@ int decompose_many(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** ou
     for (int i = 0; i < n; ++i) {
         out[i] = nullptr;
         ds[i].reset(new ssa_decomp());
-        st[i] = plan_request(ctx, reqs[i], ds[i].get());
+        st[i] = plan_request(ctx, reqs[i], ds[i].get(), nh_force, ma_force);
         if (st[i] == SSA_OK) st[i] = upload_request(reqs[i], ds[i].get(), dev, ctx->st);
         if (st[i] == SSA_OK) groups[geo_key(ds[i].get())].push_back(i);
     }
@@ -2816,6 +2926,7 @@ int ssa_ctx_create(int device, size_t mem_budget, const char* tune_cache, ssa_ct
     auto* c = new ssa_ctx();
     c->device = device;
     c->budget = mem_budget;
+    c->len_tune = std::getenv("SHSSA_LEN_TUNE") != nullptr;
     if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return fail(SSA_EDEVICE, "hipStreamCreate failed");

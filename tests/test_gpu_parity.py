@@ -1253,3 +1253,40 @@ def test_continuous_batching_fills_freed_slots(ctx):
     with pytest.raises(S.SsaError):
         c.set_slots(-1)
     c.close()
+
+
+def test_length_tuner_chooses_persists_and_keeps_parity(tmp_path, capfd, monkeypatch):
+    """The length tuner (on for contexts created with SHSSA_LEN_TUNE) times a
+    class's natural transform length against its power-of-two alternative (a series of 899 values: half-length 450 or
+    512; an image of 110 rows: column length 112 or 128), keeps the faster
+    one for the process, appends it to the cache file, and the results at
+    the chosen length still match the oracle."""
+    import paper_1309_5050_amd as S
+    monkeypatch.setenv("SHSSA_TUNE_LOG", "1")
+    monkeypatch.setenv("SHSSA_LEN_TUNE", "1")          # read when a context is created
+    path = tmp_path / "tune.txt"
+    ser = W.series_1d(n=899, L=300, r=6, seed=77)
+    img = W.image_2d(n=110, lw=10, r=6, seed=78)
+    img["x"] = img["x"][:, :100]
+    c = S.Context(0, tune_cache=path)
+    try:
+        d1 = c.decompose(ser["x"], ser["window"], 6)
+        d2 = c.decompose(img["x"], img["window"], 6, precision="fp32")
+        err = capfd.readouterr().err
+        lines = [x.split() for x in path.read_text().splitlines()]
+        for w, d, tol in ((ser, d1, 1e-10), (img, d2, 1e-5)):
+            sh, so, Uo, Vo = oracle.decompose(w["x"], None, None, w["window"])
+            assert sigma_err(d.sigma, so) <= tol
+        assert any(l[:3] == ["rowlen", "1", "450"] and l[3] in ("450", "512") for l in lines), lines
+        assert any(l[:3] == ["collen", "0", "112"] and l[3] in ("112", "128") for l in lines), lines
+        assert "length tuner: row" in err and "length tuner: col" in err
+    finally:
+        c.close()
+    # a second context finds the classes tuned and reproduces the results
+    c2 = S.Context(0, tune_cache=path)
+    try:
+        e1 = c2.decompose(ser["x"], ser["window"], 6)
+        assert "length tuner" not in capfd.readouterr().err
+        assert np.array_equal(e1.sigma, d1.sigma)
+    finally:
+        c2.close()
