@@ -408,6 +408,9 @@ def main():
     stats = last[0].stats
     st_all = sorted(d.stats["steps"] for d in last)
     steps_dist = [st_all[0], st_all[len(st_all) // 2], st_all[-1]]
+    # Jacobi sweeps per projected-matrix SVD (one SVD per restart cycle)
+    sweeps_per_svd = (sum(d.stats["svd_sweeps"] for d in last) /
+                      max(1, sum(d.stats["restarts"] + 1 for d in last)))
     # the matrix-core kernel (FP64 Ritz rotation): its timing class counts
     # floating-point operations
     pr = prof["lz_ritz"]
@@ -599,7 +602,10 @@ def main():
         "lanczos": {"steps": stats["steps"], "restarts": stats["restarts"], "basis": stats["basis"],
                     "max_resid_over_sigma1": stats["max_resid"],
                     "steps_min_median_max": steps_dist,
-                    "svd_launches_per_batch": prof["lz_svd"]["all_launches"] / max(args.steps, 1)},
+                    "svd_launches_per_batch": prof["lz_svd"]["all_launches"] / max(args.steps, 1),
+                    "svd_ms_per_launch": (prof["lz_svd"]["ms"] / prof["lz_svd"]["launches"]
+                                          if prof["lz_svd"]["launches"] else None),
+                    "svd_sweeps_per_svd": sweeps_per_svd},
         "host_ms_per_batch": {"setup": B * stats["ms_setup"], "lanczos": B * stats["ms_lanczos"],
                               "finish": B * stats["ms_finish"]},
         "fp64_single_instance": single,

@@ -1640,42 +1640,71 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
     return y;
 }
 
+// Moves x from another lane of its row by the data-parallel-primitive
+// control CTRL (two 32-bit moves for the double's halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+                                          static_cast<unsigned>(lo));
+}
+
+// Sum over each aligned group of 8 lanes: add lane ^ 1 (quad_perm 1,0,3,2),
+// then lane ^ 2 (quad_perm 2,3,0,1), then the mirrored lane 7 - i of the
+// half-row.  Each step adds the same two operands in every lane of a group
+// (addition commutes exactly), so all 8 lanes end with the same bits.
+__device__ __forceinline__ double group8_sum(double v) {
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    return v;
+}
+
 // SVD of the m x m projected matrix by one-sided (Hestenes) Jacobi, one
-// workgroup of 512 threads per instance.  The columns of B live in LDS; in
-// each round of the round-robin ordering every 8-thread group takes one
-// column pair into registers, forms the three inner products, rotates the
-// pair when it is not yet orthogonal and writes it back.  Only the last row
-// of the accumulated right rotations is needed downstream (the residual
-// estimates beta * Yr[m-1, i]), so only that row is rotated.  The singular
-// values are the final column norms, the left vectors the normalised
-// columns; they are ranked (descending) and the residual test
-// beta |Yr[m-1, i]| <= tol * sigma_1 is evaluated for the r leading ones.
-// PE: column entries per thread, 8 PE >= m (the entries past m are zeros
-// and only cost issue slots, so the launch picks the smallest PE that fits).
+// workgroup of 512 threads per instance.  The columns of B live in LDS,
+// zero-padded to 8 PE rows with a stride of 8 PE + 2 (the pad spreads the
+// columns that one wave reads over the banks); in each round of the
+// round-robin ordering every 8-lane group takes one column pair into
+// registers (lane g holds rows 2g, 2g + 1 of each 16-row slice, read as
+// 16-byte words), forms the three inner products, rotates the pair when it
+// is not yet orthogonal and writes it back.  Padding rows stay zero under
+// rotations, so loads and stores need no row test.  Only the last row of the
+// accumulated right rotations is needed downstream (the residual estimates
+// beta * Yr[m-1, i]), so only that row is rotated.  The singular values are
+// the final column norms, the left vectors the normalised columns; they are
+// ranked (descending) and the residual test beta |Yr[m-1, i]| <= tol * sigma_1
+// is evaluated for the r leading ones.
+// PE: column entries per lane (even), 8 PE >= m; the launch picks the
+// smallest PE that fits.
 template <int PE>
 __global__ void __launch_bounds__(512)
 k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, int max_sweeps) {
-    constexpr int LP = 8;                       // threads per column pair
-    static_assert(PE * LP <= kMaxBasis, "column entries beyond the basis");
-    __shared__ double Bs[kMaxBasis * kMaxBasis];
+    constexpr int LP = 8;                       // lanes per column pair
+    constexpr int R = LP * PE;                  // padded rows per column
+    constexpr int CS = R + 2;                   // column stride (doubles)
+    static_assert(PE % 2 == 0 && R <= kMaxBasis, "column entries beyond the basis");
+    __shared__ __align__(16) double Bs[R * CS];
     __shared__ double yl[kMaxBasis];
     __shared__ double cn[kMaxBasis];
     __shared__ int changed;
     const Item item = items[blockIdx.x];
     const LzDesc& lz = lzs[item.inst];
     const int nt = blockDim.x;
-    for (int e = threadIdx.x; e < m * m; e += nt) {
-        const int i = e % m, c = e / m;
-        Bs[c * m + i] = lz.Bm[(long)c * kMaxBasis + i];
+    const int nn = m + (m & 1);
+    for (int e = threadIdx.x; e < nn * R; e += nt) {
+        const int i = e % R, c = e / R;
+        Bs[c * CS + i] = (i < m && c < m) ? lz.Bm[(long)c * kMaxBasis + i] : 0.0;
     }
     for (int c = threadIdx.x; c < m; c += nt) yl[c] = c == m - 1 ? 1.0 : 0.0;
-    const int nn = m + (m & 1);
     const int npairs = nn / 2;
     const int t = threadIdx.x / LP, g = threadIdx.x % LP;
     // rotations stop at |a_p . a_q| <= jt |a_p| |a_q| (far below the
     // accuracy the operator precision can support)
     const double jt = lz.eps < 1e-8 ? 1e-15 : 1e-12;
     const double jt2 = jt * jt;
+    using d2 = double __attribute__((ext_vector_type(2)));
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
         if (threadIdx.x == 0) changed = 0;
@@ -1687,54 +1716,50 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
             const int p = a < b ? a : b, q = a < b ? b : a;
             if (t != 0) a = a + 1 == nn - 1 ? 0 : a + 1;
             b = b + 1 == nn - 1 ? 0 : b + 1;
-            if (t < npairs) {
-                if (q < m) {
-                    double* bp = Bs + p * m;
-                    double* bq = Bs + q * m;
-                    double x1[PE], x2[PE];
-                    // two partial sums per product: shorter dependent chains
-                    double al2[2] = {0.0, 0.0}, be2[2] = {0.0, 0.0}, ga2[2] = {0.0, 0.0};
+            if (t < npairs && q < m) {
+                d2* bp = reinterpret_cast<d2*>(Bs + p * CS) + g;
+                d2* bq = reinterpret_cast<d2*>(Bs + q * CS) + g;
+                d2 x1[PE / 2], x2[PE / 2];
 #pragma unroll
-                    for (int k = 0; k < PE; ++k) {
-                        const int i = g + LP * k;
-                        x1[k] = i < m ? bp[i] : 0.0;
-                        x2[k] = i < m ? bq[i] : 0.0;
-                        al2[k & 1] += x1[k] * x1[k];
-                        be2[k & 1] += x2[k] * x2[k];
-                        ga2[k & 1] += x1[k] * x2[k];
+                for (int k = 0; k < PE / 2; ++k) {
+                    x1[k] = bp[LP * k];
+                    x2[k] = bq[LP * k];
+                }
+                // two partial sums per product: shorter dependent chains
+                double al2[2] = {0.0, 0.0}, be2[2] = {0.0, 0.0}, ga2[2] = {0.0, 0.0};
+#pragma unroll
+                for (int k = 0; k < PE / 2; ++k) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        al2[h] = fma(x1[k][h], x1[k][h], al2[h]);
+                        be2[h] = fma(x2[k][h], x2[k][h], be2[h]);
+                        ga2[h] = fma(x1[k][h], x2[k][h], ga2[h]);
                     }
-                    double al = al2[0] + al2[1], be = be2[0] + be2[1], ga = ga2[0] + ga2[1];
-#pragma unroll
-                    for (int o = LP / 2; o > 0; o >>= 1) {
-                        al += __shfl_xor(al, o, LP);
-                        be += __shfl_xor(be, o, LP);
-                        ga += __shfl_xor(ga, o, LP);
+                }
+                const double al = group8_sum(al2[0] + al2[1]);
+                const double be = group8_sum(be2[0] + be2[1]);
+                const double ga = group8_sum(ga2[0] + ga2[1]);
+                if (ga != 0.0 && ga * ga > jt2 * (al * be)) {
+                    const double ze = (be - al) * rcp_nr(2.0 * ga);
+                    const double az = fabs(ze);
+                    double tt;
+                    if (az < 1e100) {
+                        const double q1 = 1.0 + ze * ze;
+                        tt = copysign(rcp_nr(az + q1 * rsqrt_nr(q1)), ze);
+                    } else {
+                        tt = 0.5 / ze;   // angle below rounding of 1 + ze^2
                     }
-                    if (ga != 0.0 && ga * ga > jt2 * (al * be)) {
-                        const double ze = (be - al) * rcp_nr(2.0 * ga);
-                        const double az = fabs(ze);
-                        double tt;
-                        if (az < 1e100) {
-                            const double q1 = 1.0 + ze * ze;
-                            tt = copysign(rcp_nr(az + q1 * rsqrt_nr(q1)), ze);
-                        } else {
-                            tt = 0.5 / ze;   // angle below rounding of 1 + ze^2
-                        }
-                        const double c = rsqrt_nr(1.0 + tt * tt), sn = c * tt;
+                    const double c = rsqrt_nr(1.0 + tt * tt), sn = c * tt;
 #pragma unroll
-                        for (int k = 0; k < PE; ++k) {
-                            const int i = g + LP * k;
-                            if (i < m) {
-                                bp[i] = c * x1[k] - sn * x2[k];
-                                bq[i] = sn * x1[k] + c * x2[k];
-                            }
-                        }
-                        if (g == 0) {
-                            const double y1 = yl[p], y2 = yl[q];
-                            yl[p] = c * y1 - sn * y2;
-                            yl[q] = sn * y1 + c * y2;
-                            changed = 1;
-                        }
+                    for (int k = 0; k < PE / 2; ++k) {
+                        bp[LP * k] = c * x1[k] - sn * x2[k];
+                        bq[LP * k] = sn * x1[k] + c * x2[k];
+                    }
+                    if (g == 0) {
+                        const double y1 = yl[p], y2 = yl[q];
+                        yl[p] = c * y1 - sn * y2;
+                        yl[q] = sn * y1 + c * y2;
+                        changed = 1;
                     }
                 }
             }
@@ -1747,13 +1772,13 @@ k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, 
     }
     for (int c = threadIdx.x; c < m; c += nt) {
         double s2 = 0.0;
-        for (int i = 0; i < m; ++i) s2 += Bs[c * m + i] * Bs[c * m + i];
+        for (int i = 0; i < m; ++i) s2 += Bs[c * CS + i] * Bs[c * CS + i];
         cn[c] = sqrt(s2);
     }
     __syncthreads();
     for (int e = threadIdx.x; e < m * m; e += nt) {
         const int i = e % m, c = e / m;
-        lz.Yl[(long)c * kMaxBasis + i] = cn[c] > 0 ? Bs[c * m + i] / cn[c] : 0.0;
+        lz.Yl[(long)c * kMaxBasis + i] = cn[c] > 0 ? Bs[c * CS + i] / cn[c] : 0.0;
     }
     for (int c = threadIdx.x; c < m; c += nt) lz.Yr[(long)c * kMaxBasis + (m - 1)] = yl[c];
     for (int i = threadIdx.x; i < m; i += nt) {
