@@ -1664,8 +1664,8 @@ __device__ __forceinline__ double group8_sum(double v) {
 
 // SVD of the m x m projected matrix by one-sided (Hestenes) Jacobi, one
 // workgroup of 512 threads per instance.  The columns of B live in LDS,
-// zero-padded to 8 PE rows with a stride of 8 PE + 2 (the pad spreads the
-// columns that one wave reads over the banks); in each round of the
+// zero-padded to 8 PE rows (stride 8 PE: a padded stride measured no
+// better); in each round of the
 // round-robin ordering every 8-lane group takes one column pair into
 // registers (lane g holds rows 2g, 2g + 1 of each 16-row slice, read as
 // 16-byte words), forms the three inner products, rotates the pair when it
@@ -1677,13 +1677,14 @@ __device__ __forceinline__ double group8_sum(double v) {
 // ranked (descending) and the residual test beta |Yr[m-1, i]| <= tol * sigma_1
 // is evaluated for the r leading ones.
 // PE: column entries per lane (even), 8 PE >= m; the launch picks the
-// smallest PE that fits.
+// smallest PE that fits (the round time grows with PE: 10 rather than 12 at
+// m = 80 took a fifth off).
 template <int PE>
 __global__ void __launch_bounds__(512)
 k_lz_svd(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, int m, int max_sweeps) {
     constexpr int LP = 8;                       // lanes per column pair
     constexpr int R = LP * PE;                  // padded rows per column
-    constexpr int CS = R + 2;                   // column stride (doubles)
+    constexpr int CS = R;                       // column stride (doubles)
     static_assert(PE % 2 == 0 && R <= kMaxBasis, "column entries beyond the basis");
     __shared__ __align__(16) double Bs[R * CS];
     __shared__ double yl[kMaxBasis];
