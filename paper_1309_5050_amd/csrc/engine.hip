@@ -6,6 +6,7 @@
 // lockstep through the bidiagonalisation cycles (instances that converge
 // drop out at the next cycle boundary).
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -26,6 +27,15 @@
 #include "common.hpp"
 #include "device.hpp"
 #include "launch.hpp"
+
+#ifdef SHSSA_HOST_AUDIT
+// Host audit build (tests only, with the mock runtime): called whenever a
+// device block becomes free for reuse; the mock reports queued work that
+// still uses it (reuse_on: the stream that reuses it at once, whose own
+// queue is ordered behind the earlier uses).
+extern "C" void shssa_audit_block(const void* p, size_t n, hipStream_t reuse_on);
+extern "C" void shssa_audit_take(const void* p, size_t n);   // a pooled block leaves the pool
+#endif
 
 using namespace shssa;
 
@@ -125,7 +135,8 @@ int len_alternative(int kind, int n0, int need) {
 
 struct ssa_ctx {
     int device = 0;
-    Server* srv = nullptr;
+    std::atomic<Server*> srv{nullptr};   // started by the first ssa_submit (under srv_mu)
+    std::mutex srv_mu;
     int refs = 0;            // live decompositions (guarded by mu)
     bool closing = false;    // ssa_ctx_destroy called; delete when refs drops to 0
     hipStream_t st = nullptr;
@@ -255,13 +266,21 @@ struct ssa_ctx {
             void* p = it->second.back();
             it->second.pop_back();
             pooled -= cls;
+#ifdef SHSSA_HOST_AUDIT
+            shssa_audit_take(p, cls);
+#endif
             return p;
         }
         void* p = nullptr;
         if (hipMalloc(&p, cls) != hipSuccess) {
             // release the pool and try once more
             for (auto& kv : pool)
-                for (void* q : kv.second) (void)hipFree(q);
+                for (void* q : kv.second) {
+#ifdef SHSSA_HOST_AUDIT
+                    shssa_audit_take(q, kv.first);
+#endif
+                    (void)hipFree(q);
+                }
             pool.clear();
             pooled = 0;
             if (hipMalloc(&p, cls) != hipSuccess) return nullptr;
@@ -269,6 +288,9 @@ struct ssa_ctx {
         return p;
     }
     void pool_put(void* p, size_t cls) {
+#ifdef SHSSA_HOST_AUDIT
+        shssa_audit_block(p, cls, nullptr);
+#endif
         if (nopool) {
             (void)hipFree(p);
             return;
@@ -445,7 +467,7 @@ struct ssa_ctx {
         }
         void* p = nullptr;
         const size_t bytes = (size_t)cnt * (f64 ? 16 : 8);
-        HIPCHK(hipMalloc(&p, bytes));
+        if (hipMalloc(&p, bytes) != hipSuccess) return fail(SSA_ENOMEM, "device memory (twiddle table)");
         if (f64) {
             HIPCHK(hipMemcpy(p, d.data(), bytes, hipMemcpyHostToDevice));
         } else {
@@ -558,7 +580,12 @@ struct ssa_decomp {
 
 namespace {
 
+// Context of the calling thread's current library call: the pool that small
+// batch tables come from (set by every entry point that makes them).
+thread_local ssa_ctx* g_tables_ctx = nullptr;
+
 void ctx_release(ssa_ctx* ctx) {
+    if (g_tables_ctx == ctx) g_tables_ctx = nullptr;
     (void)hipStreamSynchronize(ctx->st);
     for (auto x : ctx->sub_st) (void)hipStreamSynchronize(x);
     for (auto& df : ctx->deferred) {
@@ -786,7 +813,8 @@ int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStrea
 // batches
 // ---------------------------------------------------------------------------
 
-thread_local ssa_ctx* g_tables_ctx = nullptr;   // pool that small batch tables come from
+// (g_tables_ctx, the pool that small batch tables come from, is declared
+// with the context release)
 // Table blocks released by a serving worker stay with that worker (its
 // stream may still read them) until the worker has synchronised its stream;
 // then flush_table_cache returns them to the context pool.
@@ -828,8 +856,12 @@ struct TableScope {
 struct DevVec {
     void* p = nullptr;
     size_t cap = 0;
-    ssa_ctx* ctx = g_tables_ctx;
+    ssa_ctx* ctx = nullptr;   // context of the calling thread's library call, bound at first use
     DevVec() = default;
+    int bind() {
+        if (!ctx) ctx = g_tables_ctx;
+        return ctx ? SSA_OK : fail(SSA_EINVAL, "device tables outside a library call");
+    }
     // a block has one owner: a copy would return it to the pool twice
     DevVec(const DevVec&) = delete;
     DevVec& operator=(const DevVec&) = delete;
@@ -847,6 +879,7 @@ struct DevVec {
     }
     template <typename T>
     int put(const std::vector<T>& v, hipStream_t st) {
+        if (int rc = bind()) return rc;
         const size_t b = ssa_ctx::size_class(std::max<size_t>(v.size(), 1) * sizeof(T));
         if (b > cap) {
             release();
@@ -855,6 +888,9 @@ struct DevVec {
                     if ((*g_table_cache)[k].second == b) {
                         p = (*g_table_cache)[k].first;
                         g_table_cache->erase(g_table_cache->begin() + k);
+#ifdef SHSSA_HOST_AUDIT
+                        shssa_audit_block(p, b, st);   // reused on st: only other streams must be done
+#endif
                         break;
                     }
             }
@@ -870,6 +906,7 @@ struct DevVec {
     template <typename T> T* as() const { return static_cast<T*>(p); }
     // device space without contents (from the pool)
     int reserve(size_t bytes) {
+        if (int rc = bind()) return rc;
         const size_t b = ssa_ctx::size_class(std::max<size_t>(bytes, 1));
         if (b <= cap) return SSA_OK;
         release();
@@ -944,6 +981,15 @@ struct Batch {
     DevVec dflag, dstep;
 
     explicit Batch(ssa_ctx* c) : ctx(c), st(c->st) {}
+    // The handles outlive the batch: its step counter (released with it) must
+    // not stay in their descriptors.  Queued work keeps the uploaded copies.
+    ~Batch() {
+        const int* c = dstep.as<int>();
+        for (auto* d : ds)
+            if (d && c && d->lz.step == c) d->lz.step = nullptr;
+    }
+    Batch(const Batch&) = delete;
+    Batch& operator=(const Batch&) = delete;
     int colcfg() const { return TC | CV << 8; }
     void set_col(int cfg) {
         TC = cfg & 0xff;
@@ -1796,9 +1842,16 @@ int run_lanczos_cont(Batch& b, int max_steps, int slots, const std::function<int
     for (auto* d : b.ds) rmax = std::max(rmax, d->r);
     if (!(rmax <= kk && kk < m && m <= kMaxBasis) || m % c != 0)
         return fail(SSA_ERANK, "rank leaves no room in the Lanczos basis");
-    // per-instance step counters
+    // per-instance step counters; on every way out the handles point at the
+    // batch's shared counter again, never at these (released on return)
     DevVec dctr;
     if ((rc = dctr.reserve((size_t)ni * 2 * sizeof(int)))) return rc;
+    struct StepBack {
+        Batch& b;
+        ~StepBack() {
+            for (auto* d : b.ds) d->lz.step = b.dstep.as<int>();
+        }
+    } step_back{b};
     for (int i = 0; i < ni; ++i) b.ds[i]->lz.step = dctr.as<int>() + 2 * i;
     if ((rc = b.upload_descs())) return rc;
     std::vector<int> act, pending;
@@ -1936,7 +1989,7 @@ int run_lanczos_cont(Batch& b, int max_steps, int slots, const std::function<int
             }
         }
     }
-    // the handles keep the batch's shared counter (continuations use it)
+    // later launches of this batch (finish) see the batch's shared counter
     for (auto* d : b.ds) d->lz.step = b.dstep.as<int>();
     if ((rc = b.upload_descs())) return rc;
     HIPCHK(hipGetLastError());
@@ -2743,8 +2796,12 @@ void serve_worker(ssa_ctx* ctx, int w) {
     g_table_cache = nullptr;
 }
 
+// Starts the serving threads once per context; concurrent first calls of
+// ssa_submit from several threads start one server.
 int serve_start(ssa_ctx* ctx) {
-    if (ctx->srv) return SSA_OK;
+    if (ctx->srv.load(std::memory_order_acquire)) return SSA_OK;
+    std::lock_guard<std::mutex> start_lock(ctx->srv_mu);
+    if (ctx->srv.load(std::memory_order_acquire)) return SSA_OK;
     auto* S = new Server();
     int nw = 3;
     if (const char* e = std::getenv("SHSSA_SERVE_WORKERS")) nw = std::max(1, std::min(8, std::atoi(e)));
@@ -2757,7 +2814,7 @@ int serve_start(ssa_ctx* ctx) {
         }
         S->streams.push_back(s);
     }
-    ctx->srv = S;
+    ctx->srv.store(S, std::memory_order_release);
     for (int w = 0; w < nw; ++w) S->workers.emplace_back(serve_worker, ctx, w);
     return SSA_OK;
 }
@@ -3247,8 +3304,9 @@ int ssa_reconstruct(ssa_decomp* d, const int* gp, const int* gi, int ng, double*
     const long n = (long)d->A * d->B;
     g_tables_ctx = d->ctx;
     TableScope tables(d->ctx, d->ctx->st);
-    double* buf = nullptr;
-    HIPCHK(hipMalloc(&buf, n * ng * 8));
+    DevVec rbuf;   // from the pool: no device-wide synchronisation of hipFree
+    if ((rc = rbuf.reserve((size_t)n * ng * 8))) return rc;
+    double* buf = rbuf.as<double>();
     Batch b(d->ctx);
     b.ds = {d};
     b.f64 = d->f64;
@@ -3269,7 +3327,6 @@ int ssa_reconstruct(ssa_decomp* d, const int* gp, const int* gi, int ng, double*
                         out[g * n + (long)bb * d->A + a] = t[g * n + (long)a * d->B + bb];
         }
     }
-    (void)hipFree(buf);
     return rc;
 }
 
@@ -3638,6 +3695,7 @@ int ssa_esprit_tls(ssa_decomp* d, const int* grp, int ng, double* re, double* im
     if ((rc = wait_handle(d))) return rc;
     hipStream_t st = d->ctx->st;
     std::vector<int> g(grp, grp + ng);
+    g_tables_ctx = d->ctx;
     DevVec dg, flag, G, dre, dim;
     if ((rc = dg.put(g, st)) || (rc = flag.put(std::vector<int>{0, 0}, st)) ||
         (rc = G.reserve((size_t)4 * ng * ng * sizeof(double))) || (rc = dre.reserve((size_t)ng * sizeof(double))) ||
