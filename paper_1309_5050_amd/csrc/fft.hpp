@@ -24,6 +24,33 @@ namespace shssa {
 
 __host__ __device__ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
+// The transforms below are separate (not inlined) functions, so they take
+// generic pointers; they retype them at entry: the data buffer is always in
+// LDS, the twiddle tables are in LDS when the size class stages them there
+// (largest length NMAX <= 1024) and in global memory otherwise.  Typed
+// pointers let the compiler emit LDS and global instructions instead of
+// flat ones.
+template <int NMAX> inline constexpr bool kTwStaged = NMAX <= 1024;
+template <typename T> using lptr = __attribute__((address_space(3))) T*;
+template <typename T> using lcptr = const __attribute__((address_space(3))) T*;
+template <typename T> using gcptr = const __attribute__((address_space(1))) T*;
+template <typename T, bool LDS> struct TwPtr { using type = gcptr<T>; };
+template <typename T> struct TwPtr<T, true> { using type = lcptr<T>; };
+template <typename T> __device__ __forceinline__ lptr<T> to_lds(T* p) { return (lptr<T>)p; }
+template <typename T, bool LDS>
+__device__ __forceinline__ typename TwPtr<T, LDS>::type to_tw(const T* p) {
+    return (typename TwPtr<T, LDS>::type)p;
+}
+// element access through those pointers (field by field: no alignment
+// beyond the element type's is assumed)
+template <typename T, typename P>
+__device__ __forceinline__ cplx<T> ldc(P p) { return cplx<T>{p->x, p->y}; }
+template <typename T>
+__device__ __forceinline__ void stc(lptr<cplx<T>> p, cplx<T> v) {
+    p->x = v.x;
+    p->y = v.y;
+}
+
 // w * v with w = exp(i s) given as (c, s) and DIR folding the sign of s.
 template <typename T>
 __device__ __forceinline__ cplx<T> mul_i(cplx<T> a) { return {-a.y, a.x}; }   // i * a
@@ -137,9 +164,8 @@ __device__ __forceinline__ void butterfly(cplx<T>* a) {
 }
 
 // One Stockham pass of radix R over s[0..n), sub-transform size Ns so far.
-template <typename T, int R, int PMAX, int DIR>
-__device__ __forceinline__ void fft_pass(cplx<T>* s, int n, int Ns, const cplx<T>* __restrict__ tw,
-                                         int tid, int G) {
+template <typename T, int R, int PMAX, int DIR, typename TWP>
+__device__ __forceinline__ void fft_pass(lptr<cplx<T>> s, int n, int Ns, TWP tw, int tid, int G) {
     const int m = n / R;
     const int tstride = n / (Ns * R);
     cplx<T> v[PMAX][R];
@@ -150,9 +176,9 @@ __device__ __forceinline__ void fft_pass(cplx<T>* s, int n, int Ns, const cplx<T
             const int k = j % Ns;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                cplx<T> a = s[j + r * m];
+                cplx<T> a = ldc<T>(s + (j + r * m));
                 if (r > 0 && k > 0) {
-                    cplx<T> w = tw[r * k * tstride];
+                    cplx<T> w = ldc<T>(tw + r * k * tstride);
                     if (DIR > 0) w.y = -w.y;
                     a = cmul(a, w);
                 }
@@ -169,7 +195,7 @@ __device__ __forceinline__ void fft_pass(cplx<T>* s, int n, int Ns, const cplx<T
             const int k = j % Ns;
             const int base = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) s[base + r * Ns] = v[p][r];
+            for (int r = 0; r < R; ++r) stc<T>(s + (base + r * Ns), v[p][r]);
         }
     }
     __syncthreads();
@@ -182,7 +208,9 @@ __device__ __forceinline__ void fft_pass(cplx<T>* s, int n, int Ns, const cplx<T
 // compiled in, which keeps the register footprint of the kernel small).
 // tw: the plan's twiddle table (global, or a copy staged in LDS).
 template <typename T, int NMAX, int G, int DIR, bool P2 = false>
-__device__ void fft_lds(cplx<T>* s, const FftPlan& pl, const cplx<T>* tw, int tid) {
+__device__ void fft_lds(cplx<T>* sg, const FftPlan& pl, const cplx<T>* twg, int tid) {
+    const lptr<cplx<T>> s = to_lds(sg);
+    const auto tw = to_tw<cplx<T>, kTwStaged<NMAX>>(twg);
     int Ns = 1;
     for (int p = 0; p < pl.npass; ++p) {
         if constexpr (P2) {
@@ -207,19 +235,21 @@ __device__ void fft_lds(cplx<T>* s, const FftPlan& pl, const cplx<T>* tw, int ti
 // Real forward transform of length 2n held in s as n complex pairs.
 // On return s[0..n] = X[0..n] (n+1 values).  Ends synchronised.
 template <typename T, int NMAX, int G, bool P2 = false>
-__device__ void rfft_fwd(cplx<T>* s, const FftPlan& pl, const cplx<T>* tw, const cplx<T>* twr, int tid) {
-    fft_lds<T, NMAX, G, -1, P2>(s, pl, tw, tid);
+__device__ void rfft_fwd(cplx<T>* sg, const FftPlan& pl, const cplx<T>* tw, const cplx<T>* twrg, int tid) {
+    fft_lds<T, NMAX, G, -1, P2>(sg, pl, tw, tid);
+    const lptr<cplx<T>> s = to_lds(sg);
+    const auto twr = to_tw<cplx<T>, kTwStaged<NMAX>>(twrg);
     const int n = pl.n;
     for (int k = tid; k <= n / 2; k += G) {
         const int k2 = k == 0 ? 0 : n - k;
-        const cplx<T> zk = s[k], zn = s[k2];
+        const cplx<T> zk = ldc<T>(s + k), zn = ldc<T>(s + k2);
         // E = (Z_k + conj Z_{n-k}) / 2,  O = (Z_k - conj Z_{n-k}) / (2i)
         const cplx<T> e = {T(0.5) * (zk.x + zn.x), T(0.5) * (zk.y - zn.y)};
         const cplx<T> o = {T(0.5) * (zk.y + zn.y), T(-0.5) * (zk.x - zn.x)};
-        const cplx<T> wo = cmul(twr[k], o);
-        s[k] = cadd(e, wo);
+        const cplx<T> wo = cmul(ldc<T>(twr + k), o);
+        stc<T>(s + k, cadd(e, wo));
         const cplx<T> xm = csub(e, wo);
-        s[k == 0 ? n : n - k] = cconj(xm);
+        stc<T>(s + (k == 0 ? n : n - k), cconj(xm));
     }
     __syncthreads();
 }
@@ -227,21 +257,23 @@ __device__ void rfft_fwd(cplx<T>* s, const FftPlan& pl, const cplx<T>* tw, const
 // Inverse of rfft_fwd: from X[0..n] in s, leaves 2n * x (real, as n complex
 // pairs) in s[0..n).  Ends synchronised.
 template <typename T, int NMAX, int G, bool P2 = false>
-__device__ void rfft_inv(cplx<T>* s, const FftPlan& pl, const cplx<T>* tw, const cplx<T>* twr, int tid) {
+__device__ void rfft_inv(cplx<T>* sg, const FftPlan& pl, const cplx<T>* tw, const cplx<T>* twrg, int tid) {
+    const lptr<cplx<T>> s = to_lds(sg);
+    const auto twr = to_tw<cplx<T>, kTwStaged<NMAX>>(twrg);
     const int n = pl.n;
     for (int k = tid; k <= n / 2; k += G) {
         const int k2 = n - k;
-        const cplx<T> xk = s[k], xn = s[k2];
+        const cplx<T> xk = ldc<T>(s + k), xn = ldc<T>(s + k2);
         // E' = X_k + conj X_{n-k},  O' = (X_k - conj X_{n-k}) conj(W^k)
         const cplx<T> e = {xk.x + xn.x, xk.y - xn.y};
         const cplx<T> d = {xk.x - xn.x, xk.y + xn.y};
-        const cplx<T> o = cmulc(d, twr[k]);
+        const cplx<T> o = cmulc(d, ldc<T>(twr + k));
         // Z_k = E' + i O',  Z_{n-k} = conj E' + i conj O'
-        s[k] = {e.x - o.y, e.y + o.x};
-        if (k != 0 && k != k2) s[k2] = {e.x + o.y, -e.y + o.x};
+        stc<T>(s + k, cplx<T>{e.x - o.y, e.y + o.x});
+        if (k != 0 && k != k2) stc<T>(s + k2, cplx<T>{e.x + o.y, -e.y + o.x});
     }
     __syncthreads();
-    fft_lds<T, NMAX, G, +1, P2>(s, pl, tw, tid);
+    fft_lds<T, NMAX, G, +1, P2>(sg, pl, tw, tid);
 }
 
 }  // namespace shssa

@@ -124,7 +124,7 @@ __device__ __forceinline__ double sum_parts(const double* p, int n) {
 // workgroup must call this.
 template <typename T, int NMAX, bool REAL>
 struct TwStage {
-    static constexpr bool kOn = NMAX <= 1024;
+    static constexpr bool kOn = kTwStaged<NMAX>;   // the LDS transforms read staged tables as LDS
     static constexpr int kSize = kOn ? (REAL ? 2 * NMAX + 1 : NMAX) : 1;
 };
 
@@ -895,10 +895,19 @@ k_rowfam_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs,
     cplx<T>* s = buf[slot];
     T* sr = reinterpret_cast<T*>(s);
     const int n1 = prow.n + 1;
-    const cplx<T>* pa = static_cast<const cplx<T>*>(op.T2) + item.comp * op.tslot;
+    const gptr<const cplx<T>> pa = as_global(static_cast<const cplx<T>*>(op.T2)) + item.comp * op.tslot;
     for (int f = tid; f < n1; f += G) {
+        // eight rows' loads in flight at a time, added in row order
         cplx<T> acc = {T(0), T(0)};
-        for (int a = 0; a < op.A; ++a) acc = cadd(acc, pa[(long)a * op.ldp + f]);
+        int a = 0;
+        for (; a + 8 <= op.A; a += 8) {
+            cplx<T> v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = gload(pa + (long)(a + u) * op.ldp + f);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = cadd(acc, v[u]);
+        }
+        for (; a < op.A; ++a) acc = cadd(acc, gload(pa + (long)a * op.ldp + f));
         s[f] = acc;
     }
     __syncthreads();
