@@ -38,6 +38,28 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// Moves x from another lane of its row by the data-parallel-primitive
+// control CTRL (two 32-bit moves for the double's halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+                                          static_cast<unsigned>(lo));
+}
+
+// Sum over each aligned group of 8 lanes: add lane ^ 1 (quad_perm 1,0,3,2),
+// then lane ^ 2 (quad_perm 2,3,0,1), then the mirrored lane 7 - i of the
+// half-row.  Each step adds the same two operands in every lane of a group
+// (addition commutes exactly), so all 8 lanes end with the same bits.
+__device__ __forceinline__ double group8_sum(double v) {
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    return v;
+}
+
 
 // Visits the cells b = tid + c*G (c < CH, b < len) of set row a, in blocks
 // of up to 8 cells per thread: first every compact index of the block (from
@@ -1463,19 +1485,24 @@ k_lz_start(const LzDesc* __restrict__ lzs, const Item* __restrict__ items, unsig
     }
 }
 
-// Transposing butterfly over 16 values per lane: each step pairs lanes O
-// apart, each lane keeps half of its values (the lower half when bit O of
-// the lane is clear) and adds the partner's copy of that half.  After the
-// steps O = 8, 4, 2, 1 lane l holds value (l & 15) summed over its 16-lane
-// group; two more steps sum the four groups of the wave.
+// Transposing butterfly over 16 values per lane: each step pairs every lane
+// with a partner whose bit O differs, each lane keeps half of its values (the
+// lower half when bit O of the lane is clear) and adds the partner's copy of
+// that half.  After the steps O = 8, 4, 2, 1 lane l holds value (l & 15)
+// summed over its 16-lane row; two more steps sum the four rows of the wave.
+// The partners come from DPP moves within the row: lane ^ 8 (rotate by 8),
+// 7 - lane within each 8 (mirror: bit 2 differs and the lower bits only
+// permute a coset, so every lane of the row still enters each sum once),
+// lane ^ 2 and lane ^ 1 (quad permutes).
 template <int O>
 __device__ __forceinline__ void tr_step(double* v, int l) {
+    constexpr int ctrl = O == 8 ? 0x128 : O == 4 ? 0x141 : O == 2 ? 0x4E : 0xB1;
     const bool hi = (l & O) != 0;
 #pragma unroll
     for (int k = 0; k < O; ++k) {
         const double send = hi ? v[k] : v[k + O];
         const double keep = hi ? v[k + O] : v[k];
-        v[k] = keep + __shfl_xor(send, O);
+        v[k] = keep + dpp_f64<ctrl>(send);
     }
 }
 
@@ -1647,28 +1674,6 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
         y = fma(y, fma(-h, y, 0.5), y);
     }
     return y;
-}
-
-// Moves x from another lane of its row by the data-parallel-primitive
-// control CTRL (two 32-bit moves for the double's halves).
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double x) {
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
-    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
-                                          static_cast<unsigned>(lo));
-}
-
-// Sum over each aligned group of 8 lanes: add lane ^ 1 (quad_perm 1,0,3,2),
-// then lane ^ 2 (quad_perm 2,3,0,1), then the mirrored lane 7 - i of the
-// half-row.  Each step adds the same two operands in every lane of a group
-// (addition commutes exactly), so all 8 lanes end with the same bits.
-__device__ __forceinline__ double group8_sum(double v) {
-    v += dpp_f64<0xB1>(v);
-    v += dpp_f64<0x4E>(v);
-    v += dpp_f64<0x141>(v);
-    return v;
 }
 
 // SVD of the m x m projected matrix by one-sided (Hestenes) Jacobi, one
