@@ -2239,6 +2239,19 @@ int run_reconstruct(Batch& b, const std::vector<int>& gptr, const std::vector<in
     int rc;
     DevVec dgp, dgi;
     if ((rc = dgp.put(gptr, st)) || (rc = dgi.put(gidx, st))) return rc;
+    // the group tables and output buffers are this call's: on every way out
+    // the handles drop them (the uploaded descriptors keep them for the
+    // queued kernels)
+    struct Drop {
+        Batch& b;
+        ~Drop() {
+            for (auto* d : b.ds) {
+                d->rs.recon = nullptr;
+                d->rs.gptr = nullptr;
+                d->rs.gidx = nullptr;
+            }
+        }
+    } drop{b};
     for (int i = 0; i < ni; ++i) {
         b.ds[i]->rs.recon = recon[i];
         b.ds[i]->rs.gptr = dgp.as<int>();

@@ -131,6 +131,78 @@ static void batcher(ssa_ctx* ctx, int rounds) {
     }
 }
 
+// The other entry points on handles made in this thread (the mock's data
+// are not numbers the methods would meet: only the host side is checked
+// here, so their statuses are reported, not required, except that none may
+// report a runtime failure).
+static void extras(ssa_ctx* ctx) {
+    const bool verbose = std::getenv("AUDIT_VERBOSE") != nullptr;
+    auto ok = [verbose](int rc, const char* what) {
+        if (verbose) std::fprintf(stderr, "extras: %s -> %d\n", what, rc);
+        expect(rc != SSA_EDEVICE, what, rc);
+    };
+    // 1D series
+    const int n = 600;
+    std::vector<double> x(n);
+    for (int i = 0; i < n; ++i) x[i] = std::sin(0.2 * i) + 0.01 * i;
+    ssa_decomp* d = nullptr;
+    int rc = ssa_decompose(ctx, x.data(), n, 1, nullptr, nullptr, 200, 1, 6, SSA_FP64, &d);
+    ok(rc, "decompose series");
+    if (d) {
+        const int gp[3] = {0, 2, 4}, gi[4] = {0, 1, 2, 3}, grp[2] = {0, 1};
+        std::vector<double> rho(4), contrib(2), out(4 * n), re(2), im(2), fc(100);
+        int ns = 0;
+        ok(ssa_wcor(d, gp, gi, 2, rho.data(), contrib.data()), "wcor");
+        ok(ssa_rforecast(d, grp, 2, 50, fc.data(), &ns), "rforecast");
+        ok(ssa_vforecast(d, grp, 2, 50, fc.data(), &ns), "vforecast");
+        ok(ssa_esprit(d, grp, 2, re.data(), im.data()), "esprit");
+        ok(ssa_esprit_tls(d, grp, 2, re.data(), im.data()), "esprit tls");
+        ok(ssa_esprit_noalloc(d, grp, 2, re.data(), im.data()), "esprit noalloc");
+        ok(ssa_reconstruct(d, gp, gi, 2, out.data()), "reconstruct");
+        ok(ssa_extend(d, 9), "extend");
+        ok(ssa_reconstruct(d, gp, gi, 2, out.data()), "reconstruct after extend");
+        ssa_free(d);
+    }
+    // image: eigen method (small and blocked windows), vectors, weights, 2D-ESPRIT, row forecasts
+    const int side = 64;
+    std::vector<double> img((size_t)side * side);
+    for (size_t i = 0; i < img.size(); ++i) img[i] = std::cos(0.07 * (double)(i % side)) * std::sin(0.05 * (double)(i / side));
+    for (int lw : {8, 14}) {
+        ssa_decomp* e = nullptr;
+        rc = ssa_decompose_eigen(ctx, img.data(), side, side, nullptr, nullptr, lw, lw, 4, &e);
+        ok(rc, "decompose eigen");
+        if (e) {
+            const int grp[2] = {0, 1};
+            std::vector<double> U(4 * lw * lw), V(4 * (size_t)(side - lw + 1) * (side - lw + 1)), w(img.size());
+            std::vector<double> a(2), b(2), c(2), dd(2), fc(4 * 100);
+            int ns = 0;
+            ok(ssa_get_vectors(e, U.data(), V.data()), "vectors");
+            ok(ssa_get_weights(e, w.data()), "weights");
+            ok(ssa_esprit2d(e, grp, 2, a.data(), b.data(), c.data(), dd.data()), "esprit2d");
+            ok(ssa_rforecast_row(e, grp, 2, 5, nullptr, &ns), "row forecast size");
+            ok(ssa_extend(e, 6), "extend eigen");
+            ssa_free(e);
+        }
+    }
+    // MSSA and M-2D packings
+    std::vector<std::vector<double>> ser(3, std::vector<double>(300));
+    std::vector<const double*> sp(3);
+    std::vector<int> len(3, 300);
+    for (int j = 0; j < 3; ++j) {
+        for (int i = 0; i < 300; ++i) ser[j][i] = std::sin(0.1 * i * (j + 1));
+        sp[j] = ser[j].data();
+    }
+    ssa_decomp* m = nullptr;
+    ok(ssa_decompose_multi(ctx, sp.data(), len.data(), 3, 100, 4, SSA_FP32, &m), "decompose multi");
+    if (m) ssa_free(m);
+    std::vector<const double*> ims{img.data(), img.data()};
+    std::vector<int> nxs{side, side}, nys{side, side}, off(2);
+    ssa_decomp* m2 = nullptr;
+    ok(ssa_decompose_m2d(ctx, ims.data(), nxs.data(), nys.data(), 2, nullptr, 8, 8, 4, SSA_FP32, off.data(), &m2),
+       "decompose m2d");
+    if (m2) ssa_free(m2);
+}
+
 int main(int argc, char** argv) {
     const int nreq = argc > 1 ? std::atoi(argv[1]) : 40;
     const size_t budget = argc > 2 ? (size_t)std::strtoull(argv[2], nullptr, 10) : 0;
@@ -143,9 +215,11 @@ int main(int argc, char** argv) {
     std::thread c1(client, ctx, 1, nreq, true);
     std::thread c2(client, ctx, 2, nreq, false);
     std::thread bt(batcher, ctx, 3);
+    std::thread ex(extras, ctx);
     c1.join();
     c2.join();
     bt.join();
+    ex.join();
     ssa_ctx_destroy(ctx);   // requests of client 2 never taken are released here
     const int audit = mock_audit_errors();
     std::printf("driver: %d unexpected statuses, %d out of memory, %d audit reports\n", g_bad.load(),
