@@ -570,6 +570,7 @@ def main():
         note("serving loop")
         serving = serve_batched(S, W, args.serve)
     if args.serve_engine > 0:
+        os.environ["SHSSA_SERVE_ENGINE"] = "1"   # the library keeps its serving threads off otherwise
         serving = dict(serving or {}, engine=serve_bench(S, W, args.serve_engine))
 
     cpu = None

@@ -404,7 +404,13 @@ const char* ssa_last_error(void);
  * (ngroups x nx x ny, NaN off N') into recon if recon is not NULL, and
  * fills times (ms from submission to start and to completion) if not NULL.
  * ssa_take of an unfinished request returns SSA_EBUSY and changes nothing.
- * Requests not taken are released by ssa_ctx_destroy. */
+ * Requests not taken are released by ssa_ctx_destroy.
+ *
+ * Switched off: ssa_submit and ssa_submit_multi return SSA_ESTATE unless
+ * the environment variable SHSSA_SERVE_ENGINE is set.  A run of these
+ * serving threads once ended with a GPU fault whose cause is not found; the
+ * batch calls (ssa_decompose_batch*, with continuous batching) serve
+ * requests meanwhile. */
 typedef struct ssa_times {
     double queue_ms;   /* submission -> start of its batch */
     double total_ms;   /* submission -> completion */

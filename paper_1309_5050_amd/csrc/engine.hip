@@ -3850,6 +3850,11 @@ void ssa_free(ssa_decomp* d) { delete d; }
 int ssa_submit(ssa_ctx* ctx, const ssa_request* req, const int* grp_ptr, const int* grp_idx, int ngroups,
                uint64_t* ticket) {
     if (!ctx || !req || !ticket) return fail(SSA_EINVAL, "NULL argument");
+    // the serving threads stay off until a GPU fault seen once on them is
+    // explained; requests are served through the batch calls meanwhile
+    if (!std::getenv("SHSSA_SERVE_ENGINE"))
+        return fail(SSA_ESTATE, "the serving engine is switched off (SHSSA_SERVE_ENGINE=1 enables it); "
+                                "serve requests through ssa_decompose_batch");
     if (!req->x || req->nx <= 0 || req->ny <= 0) return fail(SSA_EINVAL, "sizes must be positive");
     if (ngroups < 0 || (ngroups > 0 && (!grp_ptr || !grp_idx))) return fail(SSA_EINVAL, "bad groups");
     auto r = std::make_shared<ServeReq>();

@@ -204,6 +204,7 @@ static void extras(ssa_ctx* ctx) {
 }
 
 int main(int argc, char** argv) {
+    setenv("SHSSA_SERVE_ENGINE", "1", 1);   // the audit covers the serving threads
     const int nreq = argc > 1 ? std::atoi(argv[1]) : 40;
     const size_t budget = argc > 2 ? (size_t)std::strtoull(argv[2], nullptr, 10) : 0;
     ssa_ctx* ctx = nullptr;

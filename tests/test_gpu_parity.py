@@ -1290,3 +1290,18 @@ def test_length_tuner_chooses_persists_and_keeps_parity(tmp_path, capfd, monkeyp
         assert np.array_equal(e1.sigma, d1.sigma)
     finally:
         c2.close()
+
+
+def test_serving_engine_is_switched_off(ctx, monkeypatch):
+    """ssa_submit refuses (SSA_ESTATE) unless SHSSA_SERVE_ENGINE is set: its
+    threads stay off until a GPU fault seen once on them is explained.  The
+    refusal comes before any serving thread starts."""
+    import paper_1309_5050_amd as S
+    monkeypatch.delenv("SHSSA_SERVE_ENGINE", raising=False)
+    x = np.cos(np.arange(400) / 5.0)
+    with pytest.raises(S.SsaError) as e:
+        ctx.submit(x, 100, r=2)
+    assert e.value.code == -8
+    with pytest.raises(S.SsaError) as e:
+        ctx.submit_multi([x, x], 100, r=2)
+    assert e.value.code == -8

@@ -22,7 +22,10 @@ pytestmark = [
 
 @pytest.fixture(scope="module")
 def ctx():
+    import os
+
     import paper_1309_5050_amd as S
+    os.environ["SHSSA_SERVE_ENGINE"] = "1"   # the library keeps its serving threads off otherwise
     c = S.Context(0)
     yield c
     c.close()
