@@ -41,6 +41,12 @@
  * A handle may be freed at any time: its device memory is reused only after
  * the work queued on it has completed.
  *
+ * Threads.  A context may be used from several threads.  Calls that queue
+ * work on its stream (decompositions, reconstructions, getters that wait,
+ * forecasts, ESPRIT, continuation, stream and profile reads) run one at a
+ * time per context: they share the stream and its staging buffers.  Use a
+ * context per thread for calls that should overlap on the GPU.
+ *
  * Errors.  Every int-returning function returns SSA_OK (0) or a negative
  * code; ssa_strerror gives a message, ssa_last_error the detail of the last
  * failure on the calling thread.

@@ -137,6 +137,9 @@ struct ssa_ctx {
     int device = 0;
     std::atomic<Server*> srv{nullptr};   // started by the first ssa_submit (under srv_mu)
     std::mutex srv_mu;
+    // Entry points that queue work on the context's stream run one at a
+    // time: they share the stream and its staging and readback buffers.
+    std::recursive_mutex call_mu;
     int refs = 0;            // live decompositions (guarded by mu)
     bool closing = false;    // ssa_ctx_destroy called; delete when refs drops to 0
     hipStream_t st = nullptr;
@@ -2890,6 +2893,17 @@ unsigned char* scratch_of(int device) {
 
 extern "C" {
 
+namespace {
+// Holds the context's call lock for one entry point (no lock for a null
+// context; the entry point then fails its argument check).
+struct CallLock {
+    std::unique_lock<std::recursive_mutex> lk;
+    explicit CallLock(ssa_ctx* c) {
+        if (c) lk = std::unique_lock<std::recursive_mutex>(c->call_mu);
+    }
+};
+}  // namespace
+
 int ssa_ctx_profile(ssa_ctx* ctx, const char* kind) {
     if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -2960,6 +2974,7 @@ static int profile_sum(ssa_ctx* ctx, const char* kind, double* ms, long* launche
 }
 
 int ssa_ctx_profile_read(ssa_ctx* ctx, double* ms, long* launches, double* bytes) {
+    CallLock call(ctx);
     if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
     HIPCHK(hipStreamSynchronize(ctx->st));
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -2979,6 +2994,7 @@ int ssa_ctx_profile_launches(ssa_ctx* ctx, const char* kind, long* launches) {
 }
 
 int ssa_ctx_profile_read_kind(ssa_ctx* ctx, const char* kind, double* ms, long* launches, double* bytes) {
+    CallLock call(ctx);
     if (!ctx || !kind) return fail(SSA_EINVAL, "NULL argument");
     HIPCHK(hipStreamSynchronize(ctx->st));
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -3024,6 +3040,7 @@ void ssa_ctx_destroy(ssa_ctx* ctx) {
 }
 
 int ssa_ctx_set_stream(ssa_ctx* ctx, void* stream) {
+    CallLock call(ctx);
     if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
     HIPCHK(hipStreamSynchronize(ctx->st));
     if (ctx->own) (void)hipStreamDestroy(ctx->st);
@@ -3033,6 +3050,7 @@ int ssa_ctx_set_stream(ssa_ctx* ctx, void* stream) {
 }
 
 int ssa_ctx_set_slots(ssa_ctx* ctx, int slots) {
+    CallLock call(ctx);
     if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
     if (slots < 0) return fail(SSA_EINVAL, "slots must be >= 0");
     ctx->slots = slots;
@@ -3040,21 +3058,25 @@ int ssa_ctx_set_slots(ssa_ctx* ctx, int slots) {
 }
 
 int ssa_ctx_sync(ssa_ctx* ctx) {
+    CallLock call(ctx);
     if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
     HIPCHK(hipStreamSynchronize(ctx->st));
     return SSA_OK;
 }
 
 int ssa_decompose_batch(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** out, int* status) {
+    CallLock call(ctx);
     return decompose_many(ctx, n, reqs, out, status, false);
 }
 
 int ssa_decompose_batch_dev(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** out, int* status) {
+    CallLock call(ctx);
     return decompose_many(ctx, n, reqs, out, status, true);
 }
 
 int ssa_decompose(ssa_ctx* ctx, const double* x, int nx, int ny, const uint8_t* mask, const uint8_t* wmask,
                   int lx, int ly, int r, int precision, ssa_decomp** out) {
+    CallLock call(ctx);
     if (!out) return fail(SSA_EINVAL, "out is NULL");
     ssa_request q{x, nx, ny, mask, wmask, lx, ly, r, precision, 0x5eedULL};
     int st = SSA_OK;
@@ -3064,6 +3086,7 @@ int ssa_decompose(ssa_ctx* ctx, const double* x, int nx, int ny, const uint8_t* 
 
 int ssa_decompose_eigen(ssa_ctx* ctx, const double* x, int nx, int ny, const uint8_t* mask, const uint8_t* wmask,
                         int lx, int ly, int r, ssa_decomp** out) {
+    CallLock call(ctx);
     if (!out) return fail(SSA_EINVAL, "out is NULL");
     *out = nullptr;
     if (!ctx) return fail(SSA_EINVAL, "context is NULL");
@@ -3086,6 +3109,7 @@ int ssa_decompose_eigen(ssa_ctx* ctx, const double* x, int nx, int ny, const uin
 
 int ssa_decompose_multi(ssa_ctx* ctx, const double* const* series, const int* len, int s, int L, int r,
                         int precision, ssa_decomp** out) {
+    CallLock call(ctx);
     if (!out) return fail(SSA_EINVAL, "out is NULL");
     *out = nullptr;
     if (!series || !len || s <= 0) return fail(SSA_EINVAL, "no series");
@@ -3108,6 +3132,7 @@ int ssa_decompose_multi(ssa_ctx* ctx, const double* const* series, const int* le
 
 int ssa_decompose_m2d(ssa_ctx* ctx, const double* const* images, const int* nx, const int* ny, int s,
                       const uint8_t* wmask, int lx, int ly, int r, int precision, int* col_off, ssa_decomp** out) {
+    CallLock call(ctx);
     if (!out) return fail(SSA_EINVAL, "out is NULL");
     *out = nullptr;
     if (!images || !nx || !ny || s <= 0) return fail(SSA_EINVAL, "no images");
@@ -3139,6 +3164,7 @@ int ssa_decompose_m2d(ssa_ctx* ctx, const double* const* images, const int* nx, 
 
 int ssa_decompose_mosaic(ssa_ctx* ctx, const double* const* series, int s, int t, const int* Ls, const int* Ks,
                          int r, int precision, int* col_off, ssa_decomp** out) {
+    CallLock call(ctx);
     if (!out) return fail(SSA_EINVAL, "out is NULL");
     *out = nullptr;
     if (!series || !Ls || !Ks || s <= 0 || t <= 0) return fail(SSA_EINVAL, "no blocks");
@@ -3193,6 +3219,7 @@ int ssa_get_dims(const ssa_decomp* d, int* lx, int* ly, int* kx, int* ky, long* 
 }
 
 int ssa_get_sigma(const ssa_decomp* dc, double* sigma) {
+    CallLock call(dc ? dc->ctx : nullptr);
     auto* d = const_cast<ssa_decomp*>(dc);
     if (!d || !sigma) return fail(SSA_EINVAL, "NULL argument");
     if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
@@ -3208,6 +3235,7 @@ int ssa_get_sigma(const ssa_decomp* dc, double* sigma) {
 }
 
 int ssa_get_vectors(const ssa_decomp* dc, double* U, double* V) {
+    CallLock call(dc ? dc->ctx : nullptr);
     auto* d = const_cast<ssa_decomp*>(dc);
     if (!d) return fail(SSA_EINVAL, "handle is NULL");
     if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
@@ -3237,6 +3265,7 @@ int ssa_get_vectors(const ssa_decomp* dc, double* U, double* V) {
 }
 
 int ssa_get_vectors_lex(const ssa_decomp* dc, double* U, double* V) {
+    CallLock call(dc ? dc->ctx : nullptr);
     auto* d = const_cast<ssa_decomp*>(dc);
     if (!d) return fail(SSA_EINVAL, "handle is NULL");
     const long lb = (long)d->lx * d->ly, kb = (long)d->kx * d->ky;
@@ -3282,6 +3311,7 @@ int ssa_get_vectors_lex(const ssa_decomp* dc, double* U, double* V) {
 }
 
 int ssa_get_weights(const ssa_decomp* dc, double* w) {
+    CallLock call(dc ? dc->ctx : nullptr);
     auto* d = const_cast<ssa_decomp*>(dc);
     if (!d || !w) return fail(SSA_EINVAL, "NULL argument");
     int rc;
@@ -3310,6 +3340,7 @@ static int check_groups(const ssa_decomp* d, const int* gp, const int* gi, int n
 }
 
 int ssa_reconstruct(ssa_decomp* d, const int* gp, const int* gi, int ng, double* out) {
+    CallLock call(d ? d->ctx : nullptr);
     if (!d || !out) return fail(SSA_EINVAL, "NULL argument");
     if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
     int rc = check_groups(d, gp, gi, ng);
@@ -3344,6 +3375,7 @@ int ssa_reconstruct(ssa_decomp* d, const int* gp, const int* gi, int ng, double*
 }
 
 int ssa_wcor(ssa_decomp* d, const int* gp, const int* gi, int ng, double* rho, double* contrib) {
+    CallLock call(d ? d->ctx : nullptr);
     if (!d || !rho) return fail(SSA_EINVAL, "NULL argument");
     if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
     int rc = check_groups(d, gp, gi, ng);
@@ -3410,6 +3442,7 @@ int ssa_wcor(ssa_decomp* d, const int* gp, const int* gi, int ng, double* rho, d
 }
 
 int ssa_rforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries) {
+    CallLock call(d ? d->ctx : nullptr);
     if (!d) return fail(SSA_EINVAL, "handle is NULL");
     if (!d->rowfam) return fail(SSA_EINVAL, "recurrent forecast needs a window one row or column wide");
     if (d->L != (long)d->LB) return fail(SSA_EINVAL, "recurrent forecast needs a window without mask");
@@ -3452,6 +3485,7 @@ int ssa_rforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int
 }
 
 int ssa_vforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries) {
+    CallLock call(d ? d->ctx : nullptr);
     if (!d) return fail(SSA_EINVAL, "handle is NULL");
     if (!d->rowfam) return fail(SSA_EINVAL, "vector forecast needs a window one row or column wide");
     if (d->L != (long)d->LB) return fail(SSA_EINVAL, "vector forecast needs a window without mask");
@@ -3495,6 +3529,7 @@ int ssa_vforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int
 }
 
 int ssa_extend(ssa_decomp* d, int r_new) {
+    CallLock call(d ? d->ctx : nullptr);
     if (!d) return fail(SSA_EINVAL, "handle is NULL");
     if (!d->decomposed || d->status != SSA_OK) return fail(SSA_ESTATE, "not decomposed");
     if (r_new <= d->r) return SSA_OK;
@@ -3640,6 +3675,7 @@ int row_forecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, bool
 }  // namespace
 
 int ssa_esprit(ssa_decomp* d, const int* grp, int ng, double* re, double* im) {
+    CallLock call(d ? d->ctx : nullptr);
     if (!re || !im) return fail(SSA_EINVAL, "NULL argument");
     int rc = check_forecast(d, grp, ng, 1, re, nullptr, "ESPRIT");
     if (rc) return rc;
@@ -3667,6 +3703,7 @@ int ssa_esprit(ssa_decomp* d, const int* grp, int ng, double* re, double* im) {
 }
 
 int ssa_esprit_noalloc(ssa_decomp* d, const int* grp, int ng, double* re, double* im) {
+    CallLock call(d ? d->ctx : nullptr);
     if (!re || !im) return fail(SSA_EINVAL, "NULL argument");
     int rc = check_forecast(d, grp, ng, 1, re, nullptr, "ESPRIT");
     if (rc) return rc;
@@ -3701,6 +3738,7 @@ int ssa_esprit_noalloc(ssa_decomp* d, const int* grp, int ng, double* re, double
 }
 
 int ssa_esprit_tls(ssa_decomp* d, const int* grp, int ng, double* re, double* im) {
+    CallLock call(d ? d->ctx : nullptr);
     if (!re || !im) return fail(SSA_EINVAL, "NULL argument");
     int rc = check_forecast(d, grp, ng, 1, re, nullptr, "ESPRIT");
     if (rc) return rc;
@@ -3728,6 +3766,7 @@ int ssa_esprit_tls(ssa_decomp* d, const int* grp, int ng, double* re, double* im
 }
 
 int ssa_esprit2d(ssa_decomp* d, const int* grp, int ng, double* lre, double* lim, double* mre, double* mim) {
+    CallLock call(d ? d->ctx : nullptr);
     if (!d || !grp || !lre || !lim || !mre || !mim) return fail(SSA_EINVAL, "NULL argument");
     if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
     if (d->rowfam || d->LA < 2 || d->LB < 2) return fail(SSA_EINVAL, "2D-ESPRIT needs a window at least 2 x 2");
@@ -3802,12 +3841,14 @@ int ssa_esprit2d(ssa_decomp* d, const int* grp, int ng, double* lre, double* lim
 }
 
 int ssa_rforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries) {
+    CallLock call(d ? d->ctx : nullptr);
     int rc = check_forecast(d, grp, ng, h, out, nseries, "row forecast");
     if (rc || !out) return rc;
     return row_forecast(d, grp, ng, h, out, false);
 }
 
 int ssa_vforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries) {
+    CallLock call(d ? d->ctx : nullptr);
     int rc = check_forecast(d, grp, ng, h, out, nseries, "row forecast");
     if (rc || !out) return rc;
     return row_forecast(d, grp, ng, h, out, true);
@@ -3815,6 +3856,7 @@ int ssa_vforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out,
 
 int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* gp, const int* gi, int ng,
                               double* const* out_dev) {
+    CallLock call(n > 0 && d && d[0] ? d[0]->ctx : nullptr);
     if (n <= 0 || !d || !out_dev) return fail(SSA_EINVAL, "bad arguments");
     for (int i = 0; i < n; ++i) {
         if (!d[i] || !d[i]->decomposed) return fail(SSA_ESTATE, "not decomposed");

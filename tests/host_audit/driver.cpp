@@ -207,8 +207,11 @@ int main(int argc, char** argv) {
     setenv("SHSSA_SERVE_ENGINE", "1", 1);   // the audit covers the serving threads
     const int nreq = argc > 1 ? std::atoi(argv[1]) : 40;
     const size_t budget = argc > 2 ? (size_t)std::strtoull(argv[2], nullptr, 10) : 0;
+    // the length tuner and the tune cache file run too (AUDIT_TUNE_CACHE: its path)
+    const char* cache = std::getenv("AUDIT_TUNE_CACHE");
+    if (cache) setenv("SHSSA_LEN_TUNE", "1", 1);
     ssa_ctx* ctx = nullptr;
-    int rc = ssa_ctx_create(0, budget, nullptr, &ctx);
+    int rc = ssa_ctx_create(0, budget, cache, &ctx);
     if (rc != SSA_OK) {
         std::fprintf(stderr, "DRIVER: context creation failed: %s\n", ssa_last_error());
         return 2;

@@ -75,3 +75,11 @@ def test_serving_and_pool_under_thread_sanitizer(tmpdir_mod):
     assert rc == 0, out[-4000:]
     assert "WARNING: ThreadSanitizer" not in out, out[-4000:]
     assert "0 unexpected statuses" in out and "0 audit reports" in out, out[-2000:]
+    # with the length tuner and a tune cache file (tuning runs and cache
+    # writes beside the other threads' calls on the same context)
+    cache = os.path.join(tmpdir_mod, "tune.txt")
+    rc, out = _run(exe, 12, {"TSAN_OPTIONS": "halt_on_error=1", "AUDIT_TUNE_CACHE": cache}, timeout=600)
+    assert rc == 0, out[-4000:]
+    assert "WARNING: ThreadSanitizer" not in out, out[-4000:]
+    assert "0 unexpected statuses" in out and "0 audit reports" in out, out[-2000:]
+    assert os.path.exists(cache)
