@@ -64,7 +64,11 @@ extern "C" {
 enum {
     SSA_OK = 0,
     SSA_EINVAL = -1,   /* bad sizes: window box beyond the array, L*K box of
-                          one cell, unsupported transform length, NULL input */
+                          one cell, unsupported transform length (the padded
+                          grid's rows hold at most 2 x 10200 real samples in
+                          FP64 and 2 x 16384 in FP32, i.e. series of about
+                          20,400 / 32,768 values; its columns at most 1024),
+                          NULL input */
     SSA_EEMPTY = -2,   /* no window position fits inside N (K is empty) */
     SSA_ERANK = -3,    /* r < 1 or r >= min(|L|, |K|): the rank of X is at
                           most min(L, K) (Section 2.1, Step 2); or r > 120:
