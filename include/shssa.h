@@ -66,9 +66,9 @@ enum {
     SSA_EINVAL = -1,   /* bad sizes: window box beyond the array, L*K box of
                           one cell, unsupported transform length (the padded
                           grid's rows hold at most 2 x 10200 real samples in
-                          FP64 and 2 x 16384 in FP32, i.e. series of about
-                          20,400 / 32,768 values; its columns at most 1024),
-                          NULL input */
+                          FP64 and 2 x 16384 in FP32, its columns at most
+                          1024; ssa_decompose takes longer series in
+                          segments, see there), NULL input */
     SSA_EEMPTY = -2,   /* no window position fits inside N (K is empty) */
     SSA_ERANK = -3,    /* r < 1 or r >= min(|L|, |K|): the rank of X is at
                           most min(L, K) (Section 2.1, Step 2); or r > 120:
@@ -157,6 +157,19 @@ int  ssa_ctx_set_stream(ssa_ctx* ctx, void* stream);
  * weights and the image spectrum on the device. */
 int ssa_decompose(ssa_ctx* ctx, const double* x, int nx, int ny, const uint8_t* mask,
                   const uint8_t* wmask, int lx, int ly, int r, int precision, ssa_decomp** out);
+/* A series (nx x 1 with an lx x 1 window, or 1 x ny with 1 x ly) longer
+ * than one transform row (Alg. 1 holds for any length) is decomposed as the
+ * MSSA (Section 3.1) of overlapping segments x[p B .. p B + B + L - 2],
+ * B + L - 1 = 16384 values in FP64 and 32768 in FP32: their trajectory
+ * matrices side by side are the series' own, so sigma and U are the
+ * series'.  The handle reports the series' geometry; ssa_get_vectors,
+ * ssa_get_vectors_lex, ssa_get_weights, ssa_reconstruct and ssa_wcor return
+ * the series' layout (V concatenated over the segments; weights and
+ * diagonal averages over the whole matrix, summed over the segments that
+ * hold each value).  Such a handle supports continuation and ESPRIT;
+ * forecasts and ssa_reconstruct_batch_dev return SSA_EINVAL, and so does a
+ * window of more than half a segment.  The batch calls and the eigen
+ * method take series up to one transform row only. */
 
 /* The eigen method (the paper's alternative to the truncated SVD for
  * moderate windows: S = X X^T and its full eigendecomposition,

@@ -489,6 +489,20 @@ struct ssa_ctx {
 
 struct ssa_decomp {
     ssa_ctx* ctx = nullptr;
+    // A series too long for one transform row (Alg. 1 allows any length):
+    // the handle holds the MSSA decomposition of overlapping segments,
+    // segment p = x[p B .. p B + B + L - 2], whose L x B trajectory matrices
+    // side by side are the series' own L x K matrix (columns p B .. p B + B
+    // - 1 each), so sigma and U are the series'.  The getters return the
+    // series' layout: V concatenated over the segments, weights and
+    // reconstructions summed over every segment that holds a value
+    // (diagonal averaging over the whole matrix).
+    struct Seg {
+        bool on = false;
+        bool col = true;              // series given as N x 1 (else 1 x N)
+        int N = 0, L = 0, B = 0, s = 0, nmax = 0;
+        std::vector<double> x;        // the series, NaN where missing
+    } seg;
     // caller geometry
     int nx = 0, ny = 0, lx = 0, ly = 0, kx = 0, ky = 0;
     bool tr = false;                 // internal grid is the transpose
@@ -2904,6 +2918,70 @@ struct CallLock {
 };
 }  // namespace
 
+namespace {
+
+// A one-dimensional request (window along the series, full box) whose
+// natural transform row is longer than one workgroup's transforms hold.
+bool long_series(const ssa_request& q) {
+    const bool colv = q.ny == 1 && q.ly == 1 && q.lx > 1, rowv = q.nx == 1 && q.lx == 1 && q.ly > 1;
+    if (!colv && !rowv) return false;
+    if (q.wmask)
+        for (long i = 0; i < (long)q.lx * q.ly; ++i)
+            if (!q.wmask[i]) return false;
+    const int n = colv ? q.nx : q.ny, l = colv ? q.lx : q.ly;
+    if (l >= n) return false;
+    return row_class(next_smooth((n + 1) / 2), q.precision == SSA_FP64) < 0;
+}
+
+// The segments' MSSA decomposition of a long series: segments of one
+// power-of-two transform row S = B + L - 1 (8192 complex points in FP64,
+// 16384 in FP32), the last one shorter.
+int decompose_long_series(ssa_ctx* ctx, const ssa_request& q, ssa_decomp** out) {
+    *out = nullptr;
+    const bool colv = q.ny == 1;
+    const int N = colv ? q.nx : q.ny, L = colv ? q.lx : q.ly;
+    const int S = 2 * (q.precision == SSA_FP64 ? 8192 : 16384);
+    if (2 * L > S)
+        return fail(SSA_EINVAL, "series longer than one transform row with a window of more than half a segment");
+    const int B = S - L + 1, K0 = N - L + 1;
+    const int s = (K0 + B - 1) / B, nmax = B + L - 1;
+    std::vector<double> xs(N);
+    for (int t = 0; t < N; ++t) xs[t] = (q.mask && !q.mask[t]) ? std::nan("") : q.x[t];
+    std::vector<double> packed((size_t)nmax * s, std::nan(""));
+    for (int p = 0; p < s; ++p) {
+        const int len = std::min(nmax, N - p * B);
+        for (int t = 0; t < len; ++t) packed[(size_t)t * s + p] = xs[(size_t)p * B + t];
+    }
+    ssa_request q2{packed.data(), nmax, s, nullptr, nullptr, L, 1, q.r, q.precision, q.seed};
+    int st = SSA_OK;
+    const int rc = decompose_many(ctx, 1, &q2, out, &st, false);
+    if (*out) {
+        auto& g = (*out)->seg;
+        g.on = true;
+        g.col = colv;
+        g.N = N;
+        g.L = L;
+        g.B = B;
+        g.s = s;
+        g.nmax = nmax;
+        g.x.swap(xs);
+    }
+    return rc ? rc : st;
+}
+
+// Sum over the segments of a packed array (nmax x s, row-major) onto the
+// series: out[t] = sum_p a(t - p B, p), NaN terms skipped.
+void seg_sum(const ssa_decomp::Seg& g, const double* a, double* out) {
+    for (int t = 0; t < g.N; ++t) out[t] = 0.0;
+    for (int p = 0; p < g.s; ++p)
+        for (int u = 0; u < g.nmax && (long)p * g.B + u < g.N; ++u) {
+            const double v = a[(size_t)u * g.s + p];
+            if (!std::isnan(v)) out[(size_t)p * g.B + u] += v;
+        }
+}
+
+}  // namespace
+
 int ssa_ctx_profile(ssa_ctx* ctx, const char* kind) {
     if (!ctx) return fail(SSA_EINVAL, "ctx is NULL");
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -3079,6 +3157,7 @@ int ssa_decompose(ssa_ctx* ctx, const double* x, int nx, int ny, const uint8_t* 
     CallLock call(ctx);
     if (!out) return fail(SSA_EINVAL, "out is NULL");
     ssa_request q{x, nx, ny, mask, wmask, lx, ly, r, precision, 0x5eedULL};
+    if (ctx && x && long_series(q)) return decompose_long_series(ctx, q, out);
     int st = SSA_OK;
     int rc = decompose_many(ctx, 1, &q, out, &st, false);
     return rc ? rc : st;
@@ -3206,6 +3285,20 @@ int ssa_decompose_mosaic(ssa_ctx* ctx, const double* const* series, int s, int t
 int ssa_get_dims(const ssa_decomp* d, int* lx, int* ly, int* kx, int* ky, long* L, long* K, int* r, int* nx,
                  int* ny) {
     if (!d) return fail(SSA_EINVAL, "handle is NULL");
+    if (d->seg.on) {   // the series' geometry (N x 1 or 1 x N)
+        const auto& g = d->seg;
+        const int K0 = g.N - g.L + 1;
+        if (lx) *lx = g.col ? g.L : 1;
+        if (ly) *ly = g.col ? 1 : g.L;
+        if (kx) *kx = g.col ? K0 : 1;
+        if (ky) *ky = g.col ? 1 : K0;
+        if (L) *L = d->L;
+        if (K) *K = d->K;
+        if (r) *r = d->r;
+        if (nx) *nx = g.col ? g.N : 1;
+        if (ny) *ny = g.col ? 1 : g.N;
+        return SSA_OK;
+    }
     if (lx) *lx = d->lx;
     if (ly) *ly = d->ly;
     if (kx) *kx = d->kx;
@@ -3234,10 +3327,29 @@ int ssa_get_sigma(const ssa_decomp* dc, double* sigma) {
     return SSA_OK;
 }
 
+static int vectors_raw(ssa_decomp* d, double* U, double* V);
+
 int ssa_get_vectors(const ssa_decomp* dc, double* U, double* V) {
     CallLock call(dc ? dc->ctx : nullptr);
     auto* d = const_cast<ssa_decomp*>(dc);
     if (!d) return fail(SSA_EINVAL, "handle is NULL");
+    if (!d->seg.on) return vectors_raw(d, U, V);
+    // segments: U as it is; V of the series = the segments' V side by side
+    const auto& g = d->seg;
+    std::vector<double> vm;
+    if (V) vm.resize((size_t)d->kx * d->ky * d->r);
+    int rc = vectors_raw(d, U, V ? vm.data() : nullptr);
+    if (rc || !V) return rc;
+    const long K0 = g.N - g.L + 1, box = (long)d->kx * d->ky;
+    for (int c = 0; c < d->r; ++c)
+        for (long k = 0; k < K0; ++k) {
+            const int p = (int)(k / g.B), u = (int)(k % g.B);
+            V[(long)c * K0 + k] = vm[(size_t)c * box + (size_t)u * g.s + p];
+        }
+    return SSA_OK;
+}
+
+static int vectors_raw(ssa_decomp* d, double* U, double* V) {
     if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
     int rc;
     if ((rc = wait_handle(d))) return rc;
@@ -3270,7 +3382,9 @@ int ssa_get_vectors_lex(const ssa_decomp* dc, double* U, double* V) {
     if (!d) return fail(SSA_EINVAL, "handle is NULL");
     const long lb = (long)d->lx * d->ly, kb = (long)d->kx * d->ky;
     std::vector<double> gu(lb * d->r), gv(kb * d->r);
-    int rc = ssa_get_vectors(d, gu.data(), V ? gv.data() : nullptr);
+    // (for a segmented series the segments' lexicographic order of K is the
+    // series' order: segment by segment, origins in order within each)
+    int rc = vectors_raw(d, gu.data(), V ? gv.data() : nullptr);
     if (rc) return rc;
     // lexicographic = column-major over the caller's box (row index fastest)
     auto pack = [&](const std::vector<double>& g, int bx, int by, long cnt, double* out) {
@@ -3310,10 +3424,20 @@ int ssa_get_vectors_lex(const ssa_decomp* dc, double* U, double* V) {
     return SSA_OK;
 }
 
+static int weights_raw(ssa_decomp* d, double* w);
+
 int ssa_get_weights(const ssa_decomp* dc, double* w) {
     CallLock call(dc ? dc->ctx : nullptr);
     auto* d = const_cast<ssa_decomp*>(dc);
     if (!d || !w) return fail(SSA_EINVAL, "NULL argument");
+    if (!d->seg.on) return weights_raw(d, w);
+    std::vector<double> wm((size_t)d->nx * d->ny);
+    const int rc = weights_raw(d, wm.data());
+    if (!rc) seg_sum(d->seg, wm.data(), w);
+    return rc;
+}
+
+static int weights_raw(ssa_decomp* d, double* w) {
     int rc;
     if ((rc = wait_handle(d))) return rc;
     const long n = (long)d->A * d->B;
@@ -3339,9 +3463,30 @@ static int check_groups(const ssa_decomp* d, const int* gp, const int* gi, int n
     return SSA_OK;
 }
 
+static int reconstruct_raw(ssa_decomp* d, const int* gp, const int* gi, int ng, double* out);
+
 int ssa_reconstruct(ssa_decomp* d, const int* gp, const int* gi, int ng, double* out) {
     CallLock call(d ? d->ctx : nullptr);
     if (!d || !out) return fail(SSA_EINVAL, "NULL argument");
+    if (!d->seg.on) return reconstruct_raw(d, gp, gi, ng, out);
+    if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
+    int rc = check_groups(d, gp, gi, ng);
+    if (rc) return rc;
+    // segments: x~_t = sum_p W_p x~_p / sum_p W_p over the segments holding t
+    const auto& g = d->seg;
+    const size_t np = (size_t)d->nx * d->ny;
+    std::vector<double> wm(np), rm(np * ng), num(g.N), den(g.N), wr(np);
+    if ((rc = weights_raw(d, wm.data())) || (rc = reconstruct_raw(d, gp, gi, ng, rm.data()))) return rc;
+    seg_sum(g, wm.data(), den.data());
+    for (int k = 0; k < ng; ++k) {
+        for (size_t e = 0; e < np; ++e) wr[e] = wm[e] > 0 ? wm[e] * rm[(size_t)k * np + e] : std::nan("");
+        seg_sum(g, wr.data(), num.data());
+        for (int t = 0; t < g.N; ++t) out[(size_t)k * g.N + t] = den[t] > 0 ? num[t] / den[t] : std::nan("");
+    }
+    return SSA_OK;
+}
+
+static int reconstruct_raw(ssa_decomp* d, const int* gp, const int* gi, int ng, double* out) {
     if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
     int rc = check_groups(d, gp, gi, ng);
     if (rc) return rc;
@@ -3380,6 +3525,31 @@ int ssa_wcor(ssa_decomp* d, const int* gp, const int* gi, int ng, double* rho, d
     if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
     int rc = check_groups(d, gp, gi, ng);
     if (rc || (rc = wait_handle(d))) return rc;
+    if (d->seg.on) {
+        // segmented series: the same weighted inner products over the
+        // series' reconstructions and weights (host, O(ng^2 N))
+        const auto& g = d->seg;
+        std::vector<double> rec((size_t)ng * g.N), w(g.N);
+        if ((rc = ssa_reconstruct(d, gp, gi, ng, rec.data())) || (rc = ssa_get_weights(d, w.data()))) return rc;
+        auto dot = [&](const double* a, const double* b) {
+            double acc = 0.0;
+            for (int t = 0; t < g.N; ++t)
+                if (w[t] > 0 && !std::isnan(a[t]) && !std::isnan(b[t])) acc += w[t] * a[t] * b[t];
+            return acc;
+        };
+        const double xx = dot(g.x.data(), g.x.data());
+        std::vector<double> nn(ng);
+        for (int a = 0; a < ng; ++a) nn[a] = dot(&rec[(size_t)a * g.N], &rec[(size_t)a * g.N]);
+        for (int a = 0; a < ng; ++a) {
+            for (int c = 0; c < ng; ++c) {
+                const double den = std::sqrt(nn[a] * nn[c]);
+                rho[(size_t)a * ng + c] =
+                    den > 0 ? (a == c ? nn[a] : dot(&rec[(size_t)a * g.N], &rec[(size_t)c * g.N])) / den : 0.0;
+            }
+            if (contrib) contrib[a] = xx > 0 ? nn[a] / xx : 0.0;
+        }
+        return SSA_OK;
+    }
     g_tables_ctx = d->ctx;
     TableScope tables(d->ctx, d->ctx->st);
     Batch b(d->ctx);
@@ -3443,6 +3613,8 @@ int ssa_wcor(ssa_decomp* d, const int* gp, const int* gi, int ng, double* rho, d
 
 int ssa_rforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries) {
     CallLock call(d ? d->ctx : nullptr);
+    if (d && d->seg.on)
+        return fail(SSA_EINVAL, "forecasts of a series decomposed in segments (longer than one transform row) are not supported");
     if (!d) return fail(SSA_EINVAL, "handle is NULL");
     if (!d->rowfam) return fail(SSA_EINVAL, "recurrent forecast needs a window one row or column wide");
     if (d->L != (long)d->LB) return fail(SSA_EINVAL, "recurrent forecast needs a window without mask");
@@ -3486,6 +3658,8 @@ int ssa_rforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int
 
 int ssa_vforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries) {
     CallLock call(d ? d->ctx : nullptr);
+    if (d && d->seg.on)
+        return fail(SSA_EINVAL, "forecasts of a series decomposed in segments (longer than one transform row) are not supported");
     if (!d) return fail(SSA_EINVAL, "handle is NULL");
     if (!d->rowfam) return fail(SSA_EINVAL, "vector forecast needs a window one row or column wide");
     if (d->L != (long)d->LB) return fail(SSA_EINVAL, "vector forecast needs a window without mask");
@@ -3842,6 +4016,8 @@ int ssa_esprit2d(ssa_decomp* d, const int* grp, int ng, double* lre, double* lim
 
 int ssa_rforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries) {
     CallLock call(d ? d->ctx : nullptr);
+    if (d && d->seg.on)
+        return fail(SSA_EINVAL, "forecasts of a series decomposed in segments (longer than one transform row) are not supported");
     int rc = check_forecast(d, grp, ng, h, out, nseries, "row forecast");
     if (rc || !out) return rc;
     return row_forecast(d, grp, ng, h, out, false);
@@ -3849,6 +4025,8 @@ int ssa_rforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out,
 
 int ssa_vforecast_row(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries) {
     CallLock call(d ? d->ctx : nullptr);
+    if (d && d->seg.on)
+        return fail(SSA_EINVAL, "forecasts of a series decomposed in segments (longer than one transform row) are not supported");
     int rc = check_forecast(d, grp, ng, h, out, nseries, "row forecast");
     if (rc || !out) return rc;
     return row_forecast(d, grp, ng, h, out, true);
@@ -3858,6 +4036,9 @@ int ssa_reconstruct_batch_dev(int n, ssa_decomp* const* d, const int* gp, const 
                               double* const* out_dev) {
     CallLock call(n > 0 && d && d[0] ? d[0]->ctx : nullptr);
     if (n <= 0 || !d || !out_dev) return fail(SSA_EINVAL, "bad arguments");
+    for (int i = 0; i < n; ++i)
+        if (d[i] && d[i]->seg.on)
+            return fail(SSA_EINVAL, "device reconstruction of a series decomposed in segments is not supported");
     for (int i = 0; i < n; ++i) {
         if (!d[i] || !d[i]->decomposed) return fail(SSA_ESTATE, "not decomposed");
         if (geo_key(d[i]) != geo_key(d[0])) return fail(SSA_EINVAL, "handles differ in kernel class");

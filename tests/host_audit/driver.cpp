@@ -184,6 +184,23 @@ static void extras(ssa_ctx* ctx) {
             ssa_free(e);
         }
     }
+    // a series longer than one transform row (decomposed in segments)
+    {
+        const int nl = 41000;
+        std::vector<double> xl(nl);
+        for (int i = 0; i < nl; ++i) xl[i] = std::sin(0.17 * i) + 0.001 * (i % 97);
+        ssa_decomp* ls = nullptr;
+        ok(ssa_decompose(ctx, xl.data(), nl, 1, nullptr, nullptr, 40, 1, 4, SSA_FP64, &ls), "decompose long series");
+        if (ls) {
+            const int gp[3] = {0, 2, 4}, gi[4] = {0, 1, 2, 3};
+            std::vector<double> rec(2 * (size_t)nl), w(nl), rho(4), U(4 * 40), V(4 * (size_t)(nl - 39));
+            ok(ssa_reconstruct(ls, gp, gi, 2, rec.data()), "reconstruct long series");
+            ok(ssa_get_weights(ls, w.data()), "weights long series");
+            ok(ssa_get_vectors(ls, U.data(), V.data()), "vectors long series");
+            ok(ssa_wcor(ls, gp, gi, 2, rho.data(), nullptr), "wcor long series");
+            ssa_free(ls);
+        }
+    }
     // MSSA and M-2D packings
     std::vector<std::vector<double>> ser(3, std::vector<double>(300));
     std::vector<const double*> sp(3);

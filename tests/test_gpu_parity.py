@@ -1305,3 +1305,47 @@ def test_serving_engine_is_switched_off(ctx, monkeypatch):
     with pytest.raises(S.SsaError) as e:
         ctx.submit_multi([x, x], 100, r=2)
     assert e.value.code == -8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_long_series_in_segments(ctx, prec):
+    """A series longer than one transform row (beyond 2 x 10200 values in
+    FP64, 2 x 16384 in FP32) runs as the MSSA of overlapping segments whose
+    trajectory matrices side by side are the series' own: sigma, the spans
+    of U and V, the weights and the reconstructions equal the oracle's on the
+    whole series (a missing value sits in the overlap of two segments)."""
+    g = np.random.default_rng(41)
+    N, L, r = 41000, 48, 5
+    t = np.arange(N)
+    x = 2.0 * np.sin(2 * np.pi * t / 37) + np.cos(2 * np.pi * t / 11) + 0.2 * g.standard_normal(N)
+    x[16340] = np.nan                       # segment 0 ends at 16383, segment 1 starts at 16337 (FP64)
+    sh, so, Uo, Vo = oracle.decompose(x, window=(L, 1))
+    d = ctx.decompose(x, L, r, precision=prec)
+    tol = TOL[prec]
+    assert d.shape == (N, 1) and (d.L, d.K) == (sh.L, sh.K)
+    assert sigma_err(d.sigma, so) <= tol
+    U, V = d.vectors_lex()
+    for grp, gap in stable_groups(so, r):
+        c = 10 * tol * so[0] / gap
+        assert proj_dist(U[:, grp], Uo[:, grp]) <= c
+        assert proj_dist(V[:, grp], Vo[:, grp]) <= c
+    Ub, Vb = d.vectors()
+    assert Vb.shape == (r, N - L + 1, 1)
+    assert np.allclose(np.nan_to_num(Vb[:, :, 0][:, sh.ki]), V.T, rtol=0, atol=0)   # box layout = compact order
+    assert np.array_equal(d.weights, sh.W)
+    groups = [[0, 1], [2, 3]]
+    rec = d.reconstruct(groups)
+    for k, grp in enumerate(groups):
+        ref = oracle.reconstruct(sh, so, Uo, Vo, grp)
+        assert np.array_equal(np.isnan(rec[k]), np.isnan(ref))
+        ok = ~np.isnan(ref)
+        # near-degenerate pairs: the reconstruction error scales with the
+        # pair's gap to the rest of the spectrum
+        gap = min(so[grp[0] - 1] - so[grp[0]] if grp[0] else np.inf, so[grp[-1]] - so[grp[-1] + 1])
+        bound = 10 * tol * (so[0] / gap) * np.sqrt(np.mean(np.nan_to_num(x) ** 2))
+        assert np.max(np.abs(rec[k][ok] - ref[ok])) <= bound
+    rho, _ = d.wcor([[0, 1], [2, 3], [4]])
+    assert np.allclose(np.diag(rho), 1.0)
+    assert abs(rho[0, 1]) < 0.05                               # the two sines are w-separable
+    with pytest.raises(Exception):
+        d.rforecast([0, 1], 10)
