@@ -506,6 +506,22 @@ def main():
                  "xgram_mfma_frac": xg_tf / FP64_MFMA_PEAK_TFLOPS if xg_tf else None}
         dq.free()
         dl.free()
+        # a series longer than one transform row (decomposed in segments):
+        # 200,000 values, L = 1000, r = 10, FP64, with reconstruction
+        xlong = W.series_1d(n=200000, L=1000, r=10)["x"]
+        d0 = ctx.decompose(xlong[:16384], 1000, 2)     # the segments' row length: kernels loaded
+        d0.free()
+        torch.cuda.synchronize()
+        tl0 = time.perf_counter()
+        dlong = ctx.decompose(xlong, 1000, 10)
+        _ = dlong.sigma
+        tl1 = time.perf_counter()
+        reclong = dlong.reconstruct([[0, 1], [2, 3]])
+        tl2 = time.perf_counter()
+        eigen["long_series"] = {"workload": "1D series N=200000, L=1000, r=10, fp64 (in segments of 16384 values)",
+                                "decompose_ms": 1e3 * (tl1 - tl0), "reconstruct_ms": 1e3 * (tl2 - tl1),
+                                "steps": dlong.stats["steps"], "finite": bool(np.isfinite(reclong).all())}
+        dlong.free()
         return wcor, rforecast, extend, eigen
 
     wcor = rforecast = extend = eigen = None
