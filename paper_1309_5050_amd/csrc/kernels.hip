@@ -134,10 +134,59 @@ __device__ __forceinline__ double slot_sum(double v, double* red) {
 // Sum of n partials p[0..n) by one wave: lane l adds p[l], p[l+64], ...,
 // then the lanes combine.  Every lane of every wave gets the same total
 // (the order is fixed, so the result does not depend on the caller).
+// The loads go out eight at a time (clamped addresses, unconditional), then
+// are added in the same order, so that a long list costs one memory round
+// trip per 512 partials instead of one per 64.
 __device__ __forceinline__ double sum_parts(const double* p, int n) {
+    const gptr<const double> g = as_global(p);
+    const int l = lane_id();
     double s = 0.0;
-    for (int q = lane_id(); q < n; q += 64) s += p[q];
+    for (int q0 = 0; q0 < n; q0 += 512) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int q = q0 + l + 64 * k;
+            v[k] = gload(g + (q < n ? q : 0));
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (q0 + l + 64 * k < n) s += v[k];
+    }
     return wave_sum(s);
+}
+
+// sum_parts of three lists at once (a: na partials; b0, b1: nb each), their
+// loads issued together: one memory round trip where three calls would take
+// three.  Each sum is formed in sum_parts' order (the same value).
+struct Sums3 {
+    double a, b0, b1;
+};
+__device__ __forceinline__ Sums3 sum_parts3(const double* pa, int na, const double* pb0, const double* pb1,
+                                            int nb) {
+    const gptr<const double> ga = as_global(pa), g0 = as_global(pb0), g1 = as_global(pb1);
+    const int l = lane_id();
+    double sa = 0.0, s0 = 0.0, s1 = 0.0;
+    const int n = na > nb ? na : nb;
+    for (int q0 = 0; q0 < n; q0 += 512) {
+        double va[8], v0[8], v1[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int q = q0 + l + 64 * k;
+            va[k] = gload(ga + (q < na ? q : 0));
+            v0[k] = gload(g0 + (q < nb ? q : 0));
+            v1[k] = gload(g1 + (q < nb ? q : 0));
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int q = q0 + l + 64 * k;
+            if (q < na) sa += va[k];
+            if (q < nb) {
+                s0 += v0[k];
+                s1 += v1[k];
+            }
+        }
+    }
+    return {wave_sum(sa), wave_sum(s0), wave_sum(s1)};
 }
 
 // Twiddle tables of a transform staged in LDS (one copy per workgroup,
@@ -192,22 +241,36 @@ __device__ __forceinline__ RowInSrc row_in_source(const OpDesc& op, const LzDesc
                                                   const Item& item, const RowInArgs& a0, bool leader) {
     RowInSrc r{nullptr, 1.0, nullptr, nullptr};
     RowInArgs args = a0;
-    if (args.mode == IN_LZ_STEP) {
-        const int j = lz.step[0], js = lz.step[1];
-        args.j = j;
-        args.mode = (j == js && js > 0) ? IN_LZ_SIN : IN_LZ_NORM;
-    }
-    if (args.mode == IN_LZ_NORM || args.mode == IN_LZ_PLAIN || args.mode == IN_LZ_SIN) {
-        const bool fresh = args.mode == IN_LZ_SIN && lz.flag[3] != 0;
+    if (args.mode == IN_LZ_NORM || args.mode == IN_LZ_PLAIN || args.mode == IN_LZ_SIN ||
+        args.mode == IN_LZ_STEP) {
+        // Everything the step may need is loaded first, together (the
+        // choices below depend on the loaded step counter; loads made after
+        // them would each wait for the previous one).
+        int js = 0;
+        if (args.mode == IN_LZ_STEP) {
+            args.j = lz.step[0];
+            js = lz.step[1];
+        }
+        const int f2 = lz.flag[2], f3 = lz.flag[3];
+        const double b2 = lz.beta[2], b3 = lz.beta[3];
+        // |w|^2 for beta_{j-1} and, for gamma_j (below), |l_{j-1}|^2 of both
+        // parities (the parity is known only with the step)
+        const bool gam_item = (args.mode == IN_LZ_STEP || args.mode == IN_LZ_NORM) && item.idx == 0;
+        const int nw = args.mode != IN_LZ_PLAIN ? lz.nblk : 0;
+        const int nl = gam_item ? op.S[1 - args.set].boxA : 0;
+        const Sums3 sums = sum_parts3(lz.np, nw, lz.lnp[0], lz.lnp[1], nl);
+        const double beta = sqrt(sums.a);
+        const double al0 = sums.b0, al1 = sums.b1;
+        if (args.mode == IN_LZ_STEP) args.mode = (args.j == js && js > 0) ? IN_LZ_SIN : IN_LZ_NORM;
+        const bool fresh = args.mode == IN_LZ_SIN && f3 != 0;
         if (args.mode == IN_LZ_NORM || fresh) {
             // q_j = w / beta_{j-1}.  A beta at rounding level (the short
             // Krylov space is exhausted) freezes the recurrence for the rest
             // of the cycle: q_j = 0 and B[j][j-1] = 0.  After a fresh random
             // restart w is a random vector orthogonal to the basis and has
             // no coupling to the previous column.
-            const double beta = sqrt(sum_parts(lz.np, lz.nblk));
-            const double scale = lz.beta[2 + ((args.j - 1) & 1)];
-            const bool bd = !fresh && (lz.flag[2] != 0 || (args.j > 0 && beta <= lz.eps * scale));
+            const double scale = ((args.j - 1) & 1) ? b3 : b2;
+            const bool bd = !fresh && (f2 != 0 || (args.j > 0 && beta <= lz.eps * scale));
             r.sc = (!bd && beta > 1e-300) ? 1.0 / beta : 0.0;
             r.src = lz.w;
             r.qout = lz.Q + (long)args.j * lz.n;
@@ -222,7 +285,7 @@ __device__ __forceinline__ RowInSrc row_in_source(const OpDesc& op, const LzDesc
             // cycle has none.
             if (args.mode == IN_LZ_NORM && item.idx == 0 && args.j > 0) {
                 const int p = args.j & 1;
-                const double alpha = sqrt(sum_parts(lz.lnp[p ^ 1], op.S[1 - args.set].boxA));
+                const double alpha = sqrt(p ? al0 : al1);   // lnp[p ^ 1]
                 const double gm = (!bd && alpha > 1e-300) ? beta / alpha : 0.0;
                 if (leader) lz.gam[p] = gm;
             }
@@ -408,9 +471,12 @@ __device__ __forceinline__ GkShort gk_short(const LzDesc& lz, const CellSet& Slo
         jstart = lz.step[1];
     }
     GkShort g;
-    g.alpha = sqrt(sum_parts(lz.lnp[j & 1], Slong.boxA));
+    // both parities' |l|^2 partials and |w|^2's, loaded together (the
+    // parity is known only with the step)
+    const Sums3 sm = sum_parts3(lz.np, lz.nblk, lz.lnp[0], lz.lnp[1], Slong.boxA);
+    g.alpha = sqrt((j & 1) ? sm.b1 : sm.b0);
     const double prev = lz.beta[2 + ((j - 1) & 1)];
-    const double beta_in = (j > jstart) ? sqrt(sum_parts(lz.np, lz.nblk)) : 0.0;
+    const double beta_in = (j > jstart) ? sqrt(sm.a) : 0.0;
     double scale = fmax(prev, beta_in);
     const bool bd = lz.flag[2] != 0 || (j > 0 && g.alpha <= lz.eps * scale);
     if (bd) g.alpha = 0.0;
@@ -510,16 +576,23 @@ __device__ __forceinline__ double lane_group_sum(double v) {
 // Z_k = E'_k + i O'_k for the thread's bins: E'_k = X_k + conj X_{n-k},
 // O'_k = (X_k - conj X_{n-k}) conj(W^k), W = exp(-2 pi i/2n); the inverse
 // complex transform of Z gives 2n x as pairs.  row: bins 0..n of the row.
-template <typename T, int LOGN, typename WRF>
-__device__ __forceinline__ void row_unsplit(gptr<const cplx<T>> row, WRF wr, int t, cplx<T> (&v)[8]) {
+// The loads (X_k and X_{n-k} of the thread's bins) are issued by
+// row_unsplit_load and consumed by row_unsplit_finish, so that a kernel can
+// keep them in flight while it stages its twiddle tables.
+template <typename T, int LOGN>
+__device__ __forceinline__ void row_unsplit_load(gptr<const cplx<T>> row, int t, cplx<T> (&X)[8], cplx<T> (&Y)[8]) {
     constexpr int N = RowReg<LOGN>::N, G = RowReg<LOGN>::G;
     const gptr<const cplx<T>> lo = row + t, hi = row + (N - t);
-    cplx<T> X[8], Y[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         X[e] = gload(lo + G * e);
         Y[e] = gload(hi - G * e);
     }
+}
+
+template <typename T, int LOGN, typename WRF>
+__device__ __forceinline__ void row_unsplit_finish(const cplx<T> (&X)[8], const cplx<T> (&Y)[8], WRF wr,
+                                                   cplx<T> (&v)[8]) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const cplx<T> ep = {X[e].x + Y[e].x, X[e].y - Y[e].y};
@@ -625,15 +698,45 @@ template <typename T, int LOGN>
 struct RowTw {
     static constexpr int N = RowReg<LOGN>::N, G = RowReg<LOGN>::G;
     static constexpr int TW = TwTable<T, LOGN>::SIZE;   // complex transform's table
-    static constexpr int LDS = TW + N;                   // LDS values
+    static constexpr int LDS = TW + N + 1;               // LDS values (the last one a discard slot)
+    // Staging runs in two halves: load() issues every global load of both
+    // tables at once (the values wait in registers), store() writes them to
+    // LDS and synchronises the workgroup (256 threads).  A kernel issues its
+    // own first loads between the two, so that they and the table loads are
+    // in flight together.
+    static constexpr int K1 = (TW + 255) / 256, K2 = (N + 255) / 256;
     cplx<T>* tab;
     int t;
+    cplx<T> r1[K1], r2[K2];
     __device__ __forceinline__ RowTw(cplx<T>* table, int tt) : tab(table), t(tt) {}
-    __device__ __forceinline__ void stage(const FftPlan& prow) {
+    __device__ __forceinline__ void load(const FftPlan& prow) {
         const gptr<const cplx<T>> tw = as_global(static_cast<const cplx<T>*>(prow.tw));
         const gptr<const cplx<T>> twr = as_global(static_cast<const cplx<T>*>(prow.twr));
-        TwTable<T, LOGN>::stage(tab, tw, threadIdx.x, blockDim.x);
-        for (int i = threadIdx.x; i < N; i += blockDim.x) tab[TW + i] = gload(twr + i);
+#pragma unroll
+        for (int k = 0; k < K1; ++k) {
+            const int i = threadIdx.x + 256 * k;
+            r1[k] = gload(tw + TwTable<T, LOGN>::src(i < TW ? i : 0));
+        }
+#pragma unroll
+        for (int k = 0; k < K2; ++k) {
+            const int i = threadIdx.x + 256 * k;
+            r2[k] = gload(twr + (i < N ? i : 0));
+        }
+    }
+    // Threads past a table's end write the discard slot (unconditional
+    // stores: a store under a condition lets the compiler sink its load into
+    // the branch, after the kernel's other loads).
+    __device__ __forceinline__ void store() {
+#pragma unroll
+        for (int k = 0; k < K1; ++k) {
+            const int i = threadIdx.x + 256 * k;
+            tab[i < TW ? i : TW + N] = r1[k];
+        }
+#pragma unroll
+        for (int k = 0; k < K2; ++k) {
+            const int i = threadIdx.x + 256 * k;
+            tab[i < N ? TW + i : TW + N] = r2[k];
+        }
         __syncthreads();
     }
     __device__ __forceinline__ auto W() const {
@@ -665,7 +768,7 @@ k_rowr_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
     const int a = item.idx + (valid ? c : 0);
     const OpDesc& op = ops[item.inst];
     RowTw<T, LOGN> tw(lds + XB, t);
-    tw.stage(op.prow);
+    tw.load(op.prow);
     const auto ad = [&](int pp) { return rx_addr_row<LOGN>(pp, c); };
     int xe = 0;
     cplx<T> v[8];
@@ -681,9 +784,11 @@ k_rowr_in(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const 
         pair_idx<G, decltype(dense)::value>(S, a, t, idx);
         double val[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) val[q] = load_or_zero(src, idx[q]) * rs.sc;
+        for (int q = 0; q < 16; ++q) val[q] = load_or_zero(src, idx[q]);
+        tw.store();   // the row's loads stay in flight across the barrier
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
+            val[q] *= rs.sc;
             if (wq && idx[q] >= 0) gstore(qout + idx[q], val[q]);
             if (wq32 && idx[q] >= 0) gstore(q32 + idx[q], static_cast<float>(val[q]));
             pair_part(v[q >> 1], q & 1) = to<T>(val[q]);
@@ -714,9 +819,12 @@ k_rowr_mid(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
     int xe = 0;
     cplx<T> v[8];
     RowTw<T, LOGN> tw(lds + XB, t);
-    tw.stage(op.prow);
+    tw.load(op.prow);
     {
-        row_unsplit<T, LOGN>(spec_row<T>(op.T2, item.comp * op.tslot, a, op.ldp), tw.WR(), t, v);
+        cplx<T> X[8], Y[8];
+        row_unsplit_load<T, LOGN>(spec_row<T>(op.T2, item.comp * op.tslot, a, op.ldp), t, X, Y);
+        tw.store();
+        row_unsplit_finish<T, LOGN>(X, Y, tw.WR(), v);
         reg_fft_tw<T, LOGN, +1, XS_WAVE>(v, tw.W(), lds, t, ad, xe);
     }
     const CellSet& S = op.S[args.set];
@@ -789,8 +897,13 @@ k_rowr_out(const OpDesc* __restrict__ ops, const LzDesc* __restrict__ lzs, const
     int xe = 0;
     cplx<T> v[8];
     RowTw<T, LOGN> tw(lds + XB, t);
-    tw.stage(op.prow);
-    row_unsplit<T, LOGN>(spec_row<T>(op.T2, item.comp * op.tslot, a, op.ldp), tw.WR(), t, v);
+    tw.load(op.prow);
+    {
+        cplx<T> X[8], Y[8];
+        row_unsplit_load<T, LOGN>(spec_row<T>(op.T2, item.comp * op.tslot, a, op.ldp), t, X, Y);
+        tw.store();
+        row_unsplit_finish<T, LOGN>(X, Y, tw.WR(), v);
+    }
     reg_fft_tw<T, LOGN, +1, XS_WAVE>(v, tw.W(), lds, t, ad, xe);
     const CellSet& S = op.S[args.set];
     if (args.mode == OUT_LZ) {
@@ -1133,7 +1246,7 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
     constexpr int G = RP::G;
     constexpr int XB = RP::LROWS * TC;
     constexpr int XSM = LTW ? XS_WG : XS_WG2;
-    __shared__ cplx<T> lds[(LTW ? 1 : 2) * XB + (LTW ? TwTable<T, LOGN>::SIZE : 0)];
+    __shared__ cplx<T> lds[(LTW ? 1 : 2) * XB + (LTW ? TwTable<T, LOGN>::SIZE + 1 : 0)];
     const Item item = items[xcd_block(blockIdx.x, gridDim.x)];
     int xe = 0;
     const OpDesc& op = ops[item.inst];
@@ -1145,9 +1258,11 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
     const int nin = col_rows(op, args.nin), nout = col_rows(op, args.nout);
     cplx<T> w[LTW ? 1 : RP::NTW];
     cplx<T>* tab = lds + XB;
+    typename TwTable<T, LOGN>::template Stage<G * TC> stage;
     if constexpr (LTW) {
-        // read first after an exchange barrier (the first pass has no twiddles)
-        TwTable<T, LOGN>::stage(tab, as_global(static_cast<const cplx<T>*>(op.pcol.tw)), threadIdx.x, G * TC);
+        // loaded here, written to LDS once the tile's loads are issued; read
+        // first after an exchange barrier (the first pass has no twiddles)
+        stage.load(as_global(static_cast<const cplx<T>*>(op.pcol.tw)), threadIdx.x);
     } else {
         reg_twiddles<T, LOGN>(static_cast<const cplx<T>*>(op.pcol.tw), t, w);
     }
@@ -1169,6 +1284,7 @@ k_colr(const OpDesc* __restrict__ ops, const Item* __restrict__ items, ColArgs a
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = fok ? gload(xh + e * estep + lo) : cplx<T>{T(0), T(0)};
     }
+    if constexpr (LTW) stage.store(tab, threadIdx.x);
     const auto ad = [&](int pp) { return rx_addr<TC>(pp, c); };
     if (nin <= G) reg_fft_tw<T, LOGN, -1, XSM, true>(v, W, lds, t, ad, xe, XB);
     else reg_fft_tw<T, LOGN, -1, XSM>(v, W, lds, t, ad, xe, XB);

@@ -98,9 +98,13 @@ struct TwTable {
     }
     // Exponent of entry i (the table holds w^src(i), w = exp(-2 pi i / N)).
     __device__ __forceinline__ static int src(int i) {
+        static_assert(RP::P8 <= 4, "segments of the radix-8 passes: Ns = 8, 64, 512");
         if (i < OFF_R) {
+            // segment of pass Ns starts at Ns - 8 (selects, not a loop: the
+            // address is ready early and its load issues with the others)
             int Ns = 8;
-            while (i >= 8 * Ns - 8) Ns *= 8;
+            Ns = i >= 56 ? 64 : Ns;
+            Ns = i >= 504 ? 512 : Ns;
             const int j = i - (Ns - 8);
             const int r = j / Ns + 1, k = j % Ns;
             return r * k * (RP::N / (8 * Ns));
@@ -110,11 +114,31 @@ struct TwTable {
         const int b = q2 / (RP::R - 1), r = q2 % (RP::R - 1) + 1;
         return r * (tt + b * RP::G);
     }
-    // Fills the table from the N values w^k (global memory); threads
-    // tid, tid + nthr, ... of the workgroup.
-    __device__ __forceinline__ static void stage(cplx<T>* dst, gptr<const cplx<T>> tw, int tid, int nthr) {
-        for (int i = tid; i < SIZE; i += nthr) dst[i] = gload(tw + src(i));
-    }
+    // Filling the table from the N values w^k (global memory) by the NTHR
+    // threads of a workgroup, in two halves: load() issues the thread's
+    // global loads, store() writes the values to LDS (dst holds SIZE + 1
+    // entries; threads past the end write the last, a discard slot, so the
+    // stores are unconditional and the compiler keeps the loads where they
+    // were issued).  A kernel issues its own loads between the two.
+    template <int NTHR>
+    struct Stage {
+        static constexpr int K = (SIZE + NTHR - 1) / NTHR;
+        cplx<T> r[K];
+        __device__ __forceinline__ void load(gptr<const cplx<T>> tw, int tid) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = tid + NTHR * k;
+                r[k] = gload(tw + src(i < SIZE ? i : 0));
+            }
+        }
+        __device__ __forceinline__ void store(cplx<T>* dst, int tid) const {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = tid + NTHR * k;
+                dst[i < SIZE ? i : SIZE] = r[k];
+            }
+        }
+    };
 };
 
 // Exchange synchronisation.  XS_WG: transforms spread over the waves of a
