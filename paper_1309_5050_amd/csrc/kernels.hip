@@ -243,22 +243,34 @@ __device__ __forceinline__ RowInSrc row_in_source(const OpDesc& op, const LzDesc
     RowInArgs args = a0;
     if (args.mode == IN_LZ_NORM || args.mode == IN_LZ_PLAIN || args.mode == IN_LZ_SIN ||
         args.mode == IN_LZ_STEP) {
-        // Everything the step may need is loaded first, together (the
-        // choices below depend on the loaded step counter; loads made after
-        // them would each wait for the previous one).
-        int js = 0;
-        if (args.mode == IN_LZ_STEP) {
-            args.j = lz.step[0];
-            js = lz.step[1];
-        }
-        const int f2 = lz.flag[2], f3 = lz.flag[3];
-        const double b2 = lz.beta[2], b3 = lz.beta[3];
-        // |w|^2 for beta_{j-1} and, for gamma_j (below), |l_{j-1}|^2 of both
-        // parities (the parity is known only with the step)
-        const bool gam_item = (args.mode == IN_LZ_STEP || args.mode == IN_LZ_NORM) && item.idx == 0;
+        // Everything the step may need is loaded first, together, in
+        // straight-line code: the descriptor's fields (one scalar round
+        // trip), then the step counter, flags, scales and partial sums (one
+        // vector round trip).  The choices below depend on the loaded step
+        // counter; loads made after them would each wait for the previous
+        // one.  Without a batch step counter the counter's loads read the
+        // flags instead (always allocated) and are not used.
+        const bool stepm = args.mode == IN_LZ_STEP;
+        const int* sp = stepm ? lz.step : lz.flag;
+        const gptr<const int> fl = as_global(static_cast<const int*>(lz.flag));
+        const gptr<const double> bt = as_global(static_cast<const double*>(lz.beta));
+        const bool gam_item = (stepm || args.mode == IN_LZ_NORM) && item.idx == 0;
         const int nw = args.mode != IN_LZ_PLAIN ? lz.nblk : 0;
         const int nl = gam_item ? op.S[1 - args.set].boxA : 0;
-        const Sums3 sums = sum_parts3(lz.np, nw, lz.lnp[0], lz.lnp[1], nl);
+        const double* np = lz.np;
+        const double* lnp0 = lz.lnp[0];
+        const double* lnp1 = lz.lnp[1];
+        const int s0 = gload(as_global(sp)), s1 = gload(as_global(sp) + 1);
+        const int f2 = gload(fl + 2), f3 = gload(fl + 3);
+        const double b2 = gload(bt + 2), b3 = gload(bt + 3);
+        // |w|^2 for beta_{j-1} and, for gamma_j (below), |l_{j-1}|^2 of both
+        // parities (the parity is known only with the step)
+        const Sums3 sums = sum_parts3(np, nw, lnp0, lnp1, nl);
+        int js = 0;
+        if (stepm) {
+            args.j = s0;
+            js = s1;
+        }
         const double beta = sqrt(sums.a);
         const double al0 = sums.b0, al1 = sums.b1;
         if (args.mode == IN_LZ_STEP) args.mode = (args.j == js && js > 0) ? IN_LZ_SIN : IN_LZ_NORM;
@@ -373,9 +385,16 @@ struct GkLong {
 
 template <typename T>
 __device__ __forceinline__ GkLong<T> gk_long(const LzDesc& lz, int j, int jstart) {
-    if (j == kStepDev) {
-        j = lz.step[0];
-        jstart = lz.step[1];
+    // straight-line loads (both parities' gamma with the step counter; the
+    // counter's loads read gam when there is no counter and go unused)
+    const bool stepm = j == kStepDev;
+    const int* sp = stepm ? lz.step : reinterpret_cast<const int*>(lz.gam);
+    const gptr<const double> gp = as_global(static_cast<const double*>(lz.gam));
+    const int s0 = gload(as_global(sp)), s1 = gload(as_global(sp) + 1);
+    const double gm0 = gload(gp), gm1 = gload(gp + 1);
+    if (stepm) {
+        j = s0;
+        jstart = s1;
     }
     GkLong<T> g;
     const int p = j & 1;
@@ -384,7 +403,7 @@ __device__ __forceinline__ GkLong<T> gk_long(const LzDesc& lz, int j, int jstart
     g.lnp = lz.lnp[p];
     // gamma_j was formed by this step's input pass (0 on the first step of
     // a cycle and after a breakdown)
-    const double gm = j != jstart ? lz.gam[p] : 0.0;
+    const double gm = j != jstart ? (p ? gm1 : gm0) : 0.0;
     g.gamma = static_cast<T>(gm);
     return g;
 }
@@ -466,19 +485,27 @@ struct GkShort {
 // space is exhausted) freezes the recurrence: alpha = 0 and w = 0.
 __device__ __forceinline__ GkShort gk_short(const LzDesc& lz, const CellSet& Slong, int j, int jstart,
                                             bool writer) {
-    if (j == kStepDev) {
-        j = lz.step[0];
-        jstart = lz.step[1];
+    // straight-line loads: the step counter (read from the flags, unused,
+    // when there is none), flag, both parities' scales and the partial sums
+    // (both parities of |l|^2 and |w|^2) go out together
+    const bool stepm = j == kStepDev;
+    const int* sp = stepm ? lz.step : lz.flag;
+    const gptr<const int> fl = as_global(static_cast<const int*>(lz.flag));
+    const gptr<const double> bt = as_global(static_cast<const double*>(lz.beta));
+    const int s0 = gload(as_global(sp)), s1 = gload(as_global(sp) + 1);
+    const int f2 = gload(fl + 2);
+    const double b2 = gload(bt + 2), b3 = gload(bt + 3);
+    const Sums3 sm = sum_parts3(lz.np, lz.nblk, lz.lnp[0], lz.lnp[1], Slong.boxA);
+    if (stepm) {
+        j = s0;
+        jstart = s1;
     }
     GkShort g;
-    // both parities' |l|^2 partials and |w|^2's, loaded together (the
-    // parity is known only with the step)
-    const Sums3 sm = sum_parts3(lz.np, lz.nblk, lz.lnp[0], lz.lnp[1], Slong.boxA);
     g.alpha = sqrt((j & 1) ? sm.b1 : sm.b0);
-    const double prev = lz.beta[2 + ((j - 1) & 1)];
+    const double prev = ((j - 1) & 1) ? b3 : b2;
     const double beta_in = (j > jstart) ? sqrt(sm.a) : 0.0;
     double scale = fmax(prev, beta_in);
-    const bool bd = lz.flag[2] != 0 || (j > 0 && g.alpha <= lz.eps * scale);
+    const bool bd = f2 != 0 || (j > 0 && g.alpha <= lz.eps * scale);
     if (bd) g.alpha = 0.0;
     g.inv_alpha = (!bd && g.alpha > 1e-300) ? 1.0 / g.alpha : 0.0;
     g.q = lz.Q + (long)j * lz.n;
