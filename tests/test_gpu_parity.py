@@ -1349,3 +1349,36 @@ def test_long_series_in_segments(ctx, prec):
     assert abs(rho[0, 1]) < 0.05                               # the two sines are w-separable
     with pytest.raises(Exception):
         d.rforecast([0, 1], 10)
+
+
+def test_memory_budget_refuses_with_enomem():
+    """A context's device-memory budget: a decomposition that does not fit
+    fails with SSA_ENOMEM, and the blocks it had taken go back (a small
+    request still fits afterwards, and repeating the pair changes nothing).
+    In a batch call the refused request is reported on its own while the
+    others run."""
+    import paper_1309_5050_amd as S
+    c = S.Context(0, mem_budget=8 << 20)                 # 8 MiB
+    try:
+        rng = np.random.default_rng(3)
+        big = rng.standard_normal((512, 512))
+        small = W.series_1d(n=300, L=100, r=4)
+        ref = None
+        for _ in range(3):
+            with pytest.raises(S.SsaError) as e:
+                c.decompose(big, (64, 64), 30, precision="fp32")
+            assert e.value.code == -4                    # SSA_ENOMEM
+            d = c.decompose(small["x"], small["window"], 4)
+            s = d.sigma.copy()
+            d.free()
+            if ref is None:
+                ref = s
+            assert np.array_equal(s, ref)
+        res = c.decompose_batch([{"x": big, "window": (64, 64), "r": 30},
+                                 {"x": small["x"], "window": small["window"], "r": 4}], precision="fp64")
+        assert isinstance(res[0], S.SsaError) and res[0].code == -4
+        assert isinstance(res[1], S.Decomposition)
+        assert np.allclose(res[1].sigma, ref, rtol=1e-10, atol=0)
+        res[1].free()
+    finally:
+        c.close()
