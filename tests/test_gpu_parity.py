@@ -1382,3 +1382,54 @@ def test_memory_budget_refuses_with_enomem():
         res[1].free()
     finally:
         c.close()
+
+
+_MIX_ORACLE = {}
+
+
+def _mix_request(q):
+    """A serving-mix request as a batch-call request: series as they are,
+    MSSA series side by side in one array (NaN after each series' end) with
+    an L x 1 window."""
+    if q["kind"] == "mssa":
+        nmax = max(len(x) for x in q["x"])
+        arr = np.full((nmax, len(q["x"])), np.nan)
+        for p, x in enumerate(q["x"]):
+            arr[:len(x), p] = x
+        return {"x": arr, "window": (q["window"], 1), "r": q["r"]}
+    return {"x": q["x"], "window": q["window"], "r": q["r"]}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_serving_mix_same_alone_and_in_the_mix(ctx, prec):
+    """The serving workload's mix (1D series, MSSA systems, images; r from
+    5 to 40) in one batch call with 4 slots per kernel class, so requests
+    start as others finish: every result (sigma, both vector sets) is bit for
+    bit the one the request gets alone, and the series' and images' sigma
+    match the oracle."""
+    import paper_1309_5050_amd as S
+    mix = W.serving_mix(14, seed=7, max_1d=1500, max_side=128)
+    data = [W.materialize(d) for d in mix]
+    reqs = [_mix_request(q) for q in data]
+    assert {q["kind"] for q in data} == {"1d", "mssa", "2d"}
+    c = S.Context(0)
+    try:
+        c.set_slots(4)
+        res = c.decompose_batch(reqs, precision=prec)
+        for q, rq, d in zip(data, reqs, res):
+            assert not isinstance(d, Exception), d
+            assert d.status == 0 and d.stats["converged"] == 1
+            alone = ctx.decompose(rq["x"], rq["window"], rq["r"], precision=prec)
+            assert np.array_equal(d.sigma, alone.sigma)
+            U, V = d.vectors_lex()
+            Ua, Va = alone.vectors_lex()
+            assert np.array_equal(U, Ua, equal_nan=True) and np.array_equal(V, Va, equal_nan=True)
+            if q["kind"] != "mssa":
+                key = (q["kind"], len(q["x"]), q["r"])
+                if key not in _MIX_ORACLE:
+                    _MIX_ORACLE[key] = oracle.decompose(rq["x"], None, None, rq["window"])[1]
+                assert sigma_err(d.sigma, _MIX_ORACLE[key]) <= TOL[prec]
+            alone.free()
+            d.free()
+    finally:
+        c.close()
