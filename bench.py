@@ -411,6 +411,11 @@ def main():
     # Jacobi sweeps per projected-matrix SVD (one SVD per restart cycle)
     sweeps_per_svd = (sum(d.stats["svd_sweeps"] for d in last) /
                       max(1, sum(d.stats["restarts"] + 1 for d in last)))
+    # each result's measured orthonormality (outside the timed region): the
+    # worst over the batch's last results
+    orth = [d.orthogonality() for d in last]
+    orth = {"max_UtU_minus_I": max(o[0] for o in orth), "max_VtV_minus_I": max(o[1] for o in orth),
+            "results": len(orth)}
     # the matrix-core kernel (FP64 Ritz rotation): its timing class counts
     # floating-point operations
     pr = prof["lz_ritz"]
@@ -622,7 +627,7 @@ def main():
                     "svd_launches_per_batch": prof["lz_svd"]["all_launches"] / max(args.steps, 1),
                     "svd_ms_per_launch": (prof["lz_svd"]["ms"] / prof["lz_svd"]["launches"]
                                           if prof["lz_svd"]["launches"] else None),
-                    "svd_sweeps_per_svd": sweeps_per_svd},
+                    "svd_sweeps_per_svd": sweeps_per_svd, "orthogonality": orth},
         "host_ms_per_batch": {"setup": B * stats["ms_setup"], "lanczos": B * stats["ms_lanczos"],
                               "finish": B * stats["ms_finish"]},
         "fp64_single_instance": single,

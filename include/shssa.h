@@ -261,6 +261,19 @@ int ssa_get_vectors_lex(const ssa_decomp* d, double* U, double* V);
 /* Weights w = |A_alpha| (Section 2.2), nx*ny; 0 outside N'. */
 int ssa_get_weights(const ssa_decomp* d, double* w);
 
+/* Measured orthonormality of the returned singular vectors (Section 2.1,
+ * the decomposition step: the U_i are orthonormal eigenvectors of XX^T and
+ * the V_i = X^T U_i / sqrt(lambda_i) orthonormal too): orth_u = max over
+ * i, j < r of |(U^T U)_ij - delta_ij| for the r compact vectors U (|L|
+ * entries each), orth_v the same for V (|K| entries).  A statement of each
+ * result's error beside the residual bound of ssa_stats: the basis side
+ * keeps about 1e-15 (FP64 reorthogonalisation), the other side is formed
+ * by one more product and reflects the operator precision (about 1e-7 for
+ * FP32 products, scaled by sigma_1 / sigma_r).  Computed on the device
+ * when called (two Gram matrices on the matrix cores); synchronous.
+ * SSA_EINVAL for NULL arguments, SSA_ESTATE before the decomposition. */
+int ssa_orthogonality(ssa_decomp* d, double* orth_u, double* orth_v);
+
 /* Reconstruction (Section 2.1, Step 4; Algorithms 4 and 5) of ngroups
  * groups given in CSR form (grp_ptr[ngroups+1], grp_idx, 0-based component
  * ids < r).  out: ngroups arrays of nx*ny, NaN outside N'. */

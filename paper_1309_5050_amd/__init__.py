@@ -180,6 +180,13 @@ class Decomposition:
         check(lib().ssa_wcor(self._h, _ptr(gp), _ptr(gi), len(groups), _ptr(rho), _ptr(contrib)), "ssa_wcor")
         return rho, contrib
 
+    def orthogonality(self):
+        """(max |U^T U - I|, max |V^T V - I|) of the r singular vectors,
+        measured on the device."""
+        ou, ov = C.c_double(), C.c_double()
+        check(lib().ssa_orthogonality(self._h, C.byref(ou), C.byref(ov)), "ssa_orthogonality")
+        return ou.value, ov.value
+
 
 class Context:
     """A device, a stream and a memory budget for decompositions."""

@@ -66,6 +66,7 @@ _SIGS = {
     "ssa_get_weights": (C.c_int, [C.c_void_p, C.c_void_p]),
     "ssa_reconstruct": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "ssa_wcor": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "ssa_orthogonality": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "ssa_rforecast": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_int)]),
     "ssa_extend": (C.c_int, [C.c_void_p, C.c_int]),
     "ssa_esprit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),

@@ -3611,6 +3611,55 @@ int ssa_wcor(ssa_decomp* d, const int* gp, const int* gi, int ng, double* rho, d
     return SSA_OK;
 }
 
+// max_ij |(Y^T Y)_ij - delta_ij| over the r columns Y[:, c] = y + c * n of
+// a device array (the Gram matrix on the matrix cores, unit weights),
+// queued on b's stream; the caller holds the context's call lock and a
+// table scope.
+static int gram_deviation(Batch& b, const double* y, long n, int r, double* dev) {
+    int rc;
+    std::vector<const double*> arr;
+    for (int c = 0; c < r; ++c) arr.push_back(y + (long)c * n);
+    DevVec darr, part, out;
+    if ((rc = darr.put(arr, b.st))) return rc;
+    const int tiles = wgram_tiles(r);
+    const int nchunk = (int)std::max<long>(1, std::min<long>(1024 / tiles + 1, n / 512));
+    if ((rc = part.reserve((size_t)tiles * 256 * nchunk * sizeof(double))) ||
+        (rc = out.reserve((size_t)tiles * 256 * sizeof(double))))
+        return rc;
+    launch_wgram(b.st, darr.as<const double*>(), r, nullptr, n, nchunk, part.as<double>(), out.as<double>());
+    HIPCHK(hipGetLastError());
+    std::vector<double> t((size_t)tiles * 256);
+    HIPCHK(hipMemcpyAsync(t.data(), out.p, t.size() * sizeof(double), hipMemcpyDeviceToHost, b.st));
+    HIPCHK(hipStreamSynchronize(b.st));
+    const int nb = (r + 15) / 16;
+    double m = 0.0;
+    int k = 0;
+    for (int ib = 0; ib < nb; ++ib)
+        for (int jb = ib; jb < nb; ++jb, ++k)
+            for (int i = 0; i < 16; ++i)
+                for (int j = 0; j < 16; ++j) {
+                    const int a = 16 * ib + i, c = 16 * jb + j;
+                    if (a >= r || c >= r || (ib == jb && j < i)) continue;
+                    const double v = t[(size_t)k * 256 + 16 * i + j] - (a == c ? 1.0 : 0.0);
+                    m = std::max(m, std::fabs(v));
+                }
+    *dev = m;
+    return SSA_OK;
+}
+
+int ssa_orthogonality(ssa_decomp* d, double* orth_u, double* orth_v) {
+    CallLock call(d ? d->ctx : nullptr);
+    if (!d || !orth_u || !orth_v) return fail(SSA_EINVAL, "NULL argument");
+    if (!d->decomposed) return fail(SSA_ESTATE, "not decomposed");
+    int rc;
+    if ((rc = wait_handle(d))) return rc;
+    g_tables_ctx = d->ctx;
+    TableScope tables(d->ctx, d->ctx->st);
+    Batch b(d->ctx);
+    if ((rc = gram_deviation(b, d->U, d->L, d->r, orth_u))) return rc;
+    return gram_deviation(b, d->V, d->K, d->r, orth_v);
+}
+
 int ssa_rforecast(ssa_decomp* d, const int* grp, int ng, int h, double* out, int* nseries) {
     CallLock call(d ? d->ctx : nullptr);
     if (d && d->seg.on)

@@ -2209,8 +2209,10 @@ __global__ void __launch_bounds__(256) k_transpose(const double* __restrict__ in
 // block ib (element (i, k) in lane i + 16 k), B = W times the 16 arrays of
 // block jb (element (k, j) in lane j + 16 k), so both operands of a lane are
 // the same cell of two arrays.  Only cells with W > 0 enter (the
-// reconstructions are NaN off the covered set).  Grid (chunks, tiles), 4
-// waves per workgroup; part[(tile * 256 + 16 i + j) * nchunk + chunk].
+// reconstructions are NaN off the covered set); W = nullptr: unit weights,
+// every cell enters (the Gram matrix of the singular vectors).  Grid
+// (chunks, tiles), 4 waves per workgroup;
+// part[(tile * 256 + 16 i + j) * nchunk + chunk].
 __global__ void __launch_bounds__(256)
 k_wgram(const double* const* __restrict__ arr, int narr, const double* __restrict__ W, long ncell, int nchunk,
         double* __restrict__ part) {
@@ -2225,9 +2227,11 @@ k_wgram(const double* const* __restrict__ arr, int narr, const double* __restric
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lo = lane & 15, hi = lane >> 4;
     const int ai = ib * 16 + lo, aj = jb * 16 + lo;
-    const gptr<const double> pi = as_global(ai < narr ? arr[ai] : W);   // unused rows read W (finite)
-    const gptr<const double> pj = as_global(aj < narr ? arr[aj] : W);
-    const gptr<const double> pw = as_global(W);
+    const bool unit = W == nullptr;
+    const double* spare = unit ? arr[0] : W;   // unused rows read a finite array
+    const gptr<const double> pi = as_global(ai < narr ? arr[ai] : spare);
+    const gptr<const double> pj = as_global(aj < narr ? arr[aj] : spare);
+    const gptr<const double> pw = as_global(spare);
     constexpr int U = 8;   // 4-cell steps whose operands are loaded together
     const long csz = ((ncell + nchunk - 1) / nchunk + 16 * U - 1) / (16 * U) * (16 * U);
     const long c0 = (long)blockIdx.x * csz;
@@ -2240,7 +2244,7 @@ k_wgram(const double* const* __restrict__ arr, int narr, const double* __restric
         for (int u = 0; u < U; ++u) {
             const long c = cb + 16 * u + hi;
             const bool in = c < c1;
-            w[u] = in ? gload(pw + c) : 0.0;
+            w[u] = in ? (unit ? 1.0 : gload(pw + c)) : 0.0;
             yi[u] = gload(pi + (in ? c : c0));
             yj[u] = gload(pj + (in ? c : c0));
         }

@@ -1433,3 +1433,24 @@ def test_serving_mix_same_alone_and_in_the_mix(ctx, prec):
             d.free()
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_orthogonality_is_measured_per_result(ctx, prec):
+    """ssa_orthogonality: max |U^T U - I| and max |V^T V - I| of a result's
+    singular vectors, formed on the device, equal the same quantities formed
+    on the host from the returned vectors; the basis side stays orthonormal
+    to FP64 rounding in both precisions, the other side to the operator
+    precision."""
+    cases = [W.series_1d(n=1000, L=500, r=10), W.image_2d(n=128, lw=16, r=12, seed=4), W.small_shaped(),
+             W.series_1d(n=41000, L=300, r=6, seed=9)]            # the last in segments
+    for w in cases:
+        d = ctx.decompose(w["x"], w["window"], w["r"], mask=w["mask"], wmask=w["wmask"], precision=prec)
+        ou, ov = d.orthogonality()
+        U, V = d.vectors_lex()
+        hu = np.max(np.abs(U.T @ U - np.eye(U.shape[1])))
+        hv = np.max(np.abs(V.T @ V - np.eye(V.shape[1])))
+        assert abs(ou - hu) <= 1e-11 and abs(ov - hv) <= 1e-11, (ou, hu, ov, hv)
+        assert min(ou, ov) <= 1e-12
+        assert max(ou, ov) <= (1e-9 if prec == "fp64" else 1e-4)
+        d.free()
