@@ -179,8 +179,9 @@ def note(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def config_line(S, W, ctx, torch, which, prec, steps, warmup):
-    """Batched rate and product roofline of one of the other workloads."""
+def config_line(S, W, ctx, torch, which, prec, steps, warmup, batch=None):
+    """Batched rate and product roofline of one of the other workloads
+    (batch: instances per batch call, default the workload's own)."""
     import numpy as np
     note(f"workload {which} ({prec})")
     dev = torch.device("cuda:0")
@@ -193,7 +194,7 @@ def config_line(S, W, ctx, torch, which, prec, steps, warmup):
         masks, window, r = None, (1, ws[0]["window"]), ws[0]["r"]
         name = "1D SSA N=1000, L=500, r=10, groups {1,2},{3,4},{5}"
     elif which == 3:
-        B, groups = 8, [[0, 1], [2, 3]]
+        B, groups = batch or 32, [[0, 1], [2, 3]]
         ws = [W.mssa_series(seed=3 + i) for i in range(B)]
         xs = []
         for w in ws:
@@ -205,7 +206,7 @@ def config_line(S, W, ctx, torch, which, prec, steps, warmup):
         masks, window, r = None, (1, ws[0]["window"]), ws[0]["r"]
         name = "MSSA 50 series N~U(1000,3000), L=500, r=20, groups {1,2},{3,4}"
     else:
-        B, groups = 8, [[0, 1, 2, 3]]
+        B, groups = batch or 32, [[0, 1, 2, 3]]
         ws = [W.shaped_disc(seed=4 + i) for i in range(B)]
         xs = [torch.tensor(w["x"], device=dev) for w in ws]
         masks = [torch.tensor(w["mask"], device=dev) for w in ws]
