@@ -6,7 +6,7 @@ noise, window 64x64, r = 30 eigentriples, reconstruction of the groups
 {1,2}, {3,4}, {5,6} (0-based {0,1}, {2,3}, {4,5}).  A step decomposes and
 reconstructs one batch of B images already resident in device memory.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--batch 64] [--precision fp32]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--batch 256] [--precision fp32]
 
 Prints one JSON line.  Besides the headline rate it reports:
 
@@ -40,7 +40,7 @@ GRID_CLASSES = ["row_in", "col", "row_mid", "row_out"]
 ROWFAM_CLASSES = ["row_in", "rowfam_mid", "rowfam_out"]
 KERNEL_OF = {"row_in": "k_rowr_in", "col": "k_colr", "row_mid": "k_rowr_mid", "row_out": "k_rowr_out",
              "rowfam_mid": "k_row_mid", "rowfam_out": "k_row_out"}
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fft_product_image512_batch64_fp32_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fft_product_image512_batch256_fp32_traffic.md")
 # the paper's decomposition timings (R, Rssa 0.10 with FFTW; hardware not
 # stated), elapsed seconds, for the three settings on its 258 x 275 image
 PAPER_SECONDS = {"eigen_25x25": 3.843, "lanczos_25x25": 0.519, "lanczos_160x80_r50": 0.587,
@@ -80,25 +80,27 @@ def class_bytes(ds, prec, rowfam):
     return out
 
 
-def measured_traffic():
+def measured_traffic(batch):
     """Counter bytes per dispatch of each product kernel from the committed
     rocprofv3 summary, or None when the kernel sources have changed since
-    the counters were taken."""
+    the counters were taken or the summary is of another batch size."""
     import hashlib
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
-    per, sha = {}, None
+    per, sha, tb = {}, None, None
     for line in open(TRAFFIC_SUMMARY):
         f = line.split()
         if len(f) >= 2 and f[0] == "source-sha256:":
             sha = f[1]
+        if len(f) == 2 and f[0] == "batch:":
+            tb = int(f[1])
         if len(f) == 4 and f[0] == "traffic:":
             per[f[1]] = (float(f[2]), float(f[3]))   # class -> (bytes per dispatch, dispatches counted)
     h = hashlib.sha256()
     for f in ("common.hpp", "device.hpp", "fft.hpp", "regfft.hpp", "kernels.hip"):
         with open(os.path.join(ROOT, "paper_1309_5050_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    return per if sha == h.hexdigest() and per else None
+    return per if sha == h.hexdigest() and per and tb == batch else None
 
 
 def product_roofline(prof, ds, prec, rowfam, nbatch, traffic=None):
@@ -347,7 +349,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp32_basis32"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--no-single", action="store_true", help="skip the single-instance FP64 comparator")
@@ -405,16 +407,16 @@ def main():
     value, ms_step, last, prof, rowfam = run_batched(S, ctx, torch, xs, (lw, lw), r, groups, args.precision,
                                                      args.steps, args.warmup, extra_classes=("lz_ritz", "lz_svd"))
     roof, kern = product_roofline(prof, last, args.precision, rowfam, args.steps,
-                                  measured_traffic() if args.precision == "fp32" and B == 64 else None)
+                                  measured_traffic(B) if args.precision == "fp32" else None)
     stats = last[0].stats
     st_all = sorted(d.stats["steps"] for d in last)
     steps_dist = [st_all[0], st_all[len(st_all) // 2], st_all[-1]]
     # Jacobi sweeps per projected-matrix SVD (one SVD per restart cycle)
     sweeps_per_svd = (sum(d.stats["svd_sweeps"] for d in last) /
                       max(1, sum(d.stats["restarts"] + 1 for d in last)))
-    # each result's measured orthonormality (outside the timed region): the
-    # worst over the batch's last results
-    orth = [d.orthogonality() for d in last]
+    # measured orthonormality of the results (outside the timed region): the
+    # worst over the first 16 results of the last batch
+    orth = [d.orthogonality() for d in last[:16]]
     orth = {"max_UtU_minus_I": max(o[0] for o in orth), "max_VtV_minus_I": max(o[1] for o in orth),
             "results": len(orth)}
     # the matrix-core kernel (FP64 Ritz rotation): its timing class counts
