@@ -2029,13 +2029,15 @@ struct FinishLists {
     bool ready = false;
 };
 
-int finish_lists(Batch& b, FinishLists& F) {
+// who: the instances to finish (nullptr: all of the batch).
+int finish_lists(Batch& b, FinishLists& F, const std::vector<int>* who = nullptr) {
     const int ni = (int)b.ds.size();
     std::vector<int> all(ni);
     for (int i = 0; i < ni; ++i) all[i] = i;
+    if (who) all = *who;
     const auto* d0 = b.ds[0];
     int r = 0;   // components of the batch (instances may have fewer)
-    for (auto* d : b.ds) r = std::max(r, d->r);
+    for (int i : all) r = std::max(r, b.ds[i]->r);
     const int s = d0->side;
     // component c of the instances with r > c
     const auto has = [&](int i, int c) { return c < b.ds[i]->r; };
@@ -2067,10 +2069,10 @@ int finish_lists(Batch& b, FinishLists& F) {
 
 // Long-side vectors of the final triplets (V = X^T U / sigma or
 // U = X V / sigma), then the sign rule.
-int run_finish(Batch& b, FinishLists& F) {
+int run_finish(Batch& b, FinishLists& F, const std::vector<int>* who = nullptr) {
     hipStream_t st = b.st;
     int rc;
-    if (!F.ready && (rc = finish_lists(b, F))) return rc;
+    if (!F.ready && (rc = finish_lists(b, F, who))) return rc;
     const auto* d0 = b.ds[0];
     const int s = d0->side;
     // short side = window side: fix the signs of U first, V = X^T U / sigma
@@ -2092,7 +2094,9 @@ int run_finish(Batch& b, FinishLists& F) {
     if (s == 1) launch_sign_fix(F.sg.n(), st, b.ops(), b.res(), F.sg.ptr(), 1);
     HIPCHK(hipGetLastError());
     // the singular values are read back when first asked for
-    for (auto* d : b.ds) {
+    for (int i = 0; i < (int)b.ds.size(); ++i) {
+        if (who && std::find(who->begin(), who->end(), i) == who->end()) continue;
+        auto* d = b.ds[i];
         d->decomposed = true;
         d->sigma_ready = false;
         d->last_st = st;
@@ -2649,7 +2653,10 @@ struct ServeReq {
     std::vector<double> recon;   // ngroups x nx x ny (caller layout) once done
 };
 
+struct CoopState;
+
 struct Server {
+    std::shared_ptr<CoopState> coop;   // cooperative mode: no threads, the callers' waits drive the work
     std::mutex mu;
     std::condition_variable cv;
     std::deque<std::shared_ptr<ServeReq>> pending;
@@ -2659,7 +2666,7 @@ struct Server {
     Clock::time_point t0 = Clock::now();
     uint64_t next = 1;
     size_t reserved = 0;      // admitted estimates not yet released
-    int running = 0;          // batches in flight
+    int running = 0;          // batches in flight (cooperative mode: admitted requests)
     int max_batch = 64;
     bool stop = false;
     double now() const { return ms_since(t0); }
@@ -2828,6 +2835,352 @@ void serve_worker(ssa_ctx* ctx, int w) {
 
 // Starts the serving threads once per context; concurrent first calls of
 // ssa_submit from several threads start one server.
+// ---------------------------------------------------------------------------
+// cooperative serving (the default): ssa_poll and ssa_wait drive the
+// requests on the context's stream, in the calling thread, one restart
+// cycle of every running kernel class at a time
+// ---------------------------------------------------------------------------
+
+// The requests of one kernel class (geometry, basis and restart size) that
+// advance together.  At each cycle boundary waiting requests take the slots
+// of finished ones and begin from their start vectors, and finished ones
+// leave the batch with their results: each instance keeps its own step
+// counter [j, jstart] on the device, and the cycle plan of basis_size and
+// restart_keep puts every instance's boundaries on common ones, so it runs
+// the steps, restarts and reductions it would run alone.
+struct CoopBatch {
+    GeoKey key;
+    int m = 0, kk = 0;
+    Batch b;
+    struct Inst {
+        std::shared_ptr<ServeReq> r;
+        int* ctr = nullptr;   // [j, jstart] (a block of the handle)
+        int steps = 0, restarts = 0, jh = 0, cycles = 0, bdrest = 0;
+        bool active = false;
+    };
+    std::vector<Inst> in;   // in[i] runs b.ds[i]
+    bool dirty = true;      // descriptors changed since the last upload
+    explicit CoopBatch(ssa_ctx* ctx) : b(ctx) {}
+};
+
+struct CoopState {
+    std::vector<std::unique_ptr<CoopBatch>> batches;
+};
+
+// A request leaves the server with its status (results in place when OK).
+void coop_done(Server& S, const std::shared_ptr<ServeReq>& r, int status) {
+    std::lock_guard<std::mutex> lk(S.mu);
+    r->status = status;
+    r->t_done = S.now();
+    r->done = true;
+    S.reserved -= r->est;
+    S.running--;
+}
+
+// The reconstructions of a finished request (its groups, caller layout).
+int coop_reconstruct(ssa_ctx* ctx, ServeReq* r) {
+    if (r->gp.size() < 2) return SSA_OK;
+    ssa_decomp* d = r->d.get();
+    const int ng = (int)r->gp.size() - 1;
+    const long n = (long)d->A * d->B;
+    double* buf = nullptr;
+    int rc;
+    if ((rc = d->dalloc(&buf, (long)ng * n))) return rc;
+    {
+        Batch b(ctx, ctx->st);
+        fill_batch(b, ctx, {d});
+        if ((rc = run_reconstruct(b, r->gp, r->gi, {buf}))) return rc;
+    }
+    std::vector<double> t((size_t)n * ng);
+    HIPCHK(hipMemcpyAsync(t.data(), buf, t.size() * 8, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    r->recon.resize(t.size());
+    if (!d->tr) {
+        r->recon.swap(t);
+    } else {
+        for (int g = 0; g < ng; ++g)
+            for (int a = 0; a < d->A; ++a)
+                for (int c = 0; c < d->B; ++c) r->recon[g * n + (long)c * d->A + a] = t[g * n + (long)a * d->B + c];
+    }
+    return SSA_OK;
+}
+
+// Admission: waiting requests in arrival order while their estimates fit
+// the budget beside the admitted ones (the first one always, when nothing
+// runs), set up on the context's stream and added to their class's batch.
+int coop_admit(ssa_ctx* ctx, Server& S, CoopState& C) {
+    std::vector<std::shared_ptr<ServeReq>> take;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        while (!S.pending.empty()) {
+            auto r = S.pending.front();
+            if (ctx->budget && S.running > 0 && S.reserved + r->est > ctx->budget) break;
+            S.pending.pop_front();
+            S.reserved += r->est;
+            S.running++;
+            r->t_start = S.now();
+            take.push_back(r);
+        }
+    }
+    if (take.empty()) return SSA_OK;
+    const hipStream_t st = ctx->st;
+    std::map<GeoKey, std::vector<std::shared_ptr<ServeReq>>> groups;
+    for (auto& r : take) {
+        const int rc = upload_request(r->q, r->d.get(), false, st);
+        if (rc) coop_done(S, r, rc);
+        else groups[r->key].push_back(r);
+    }
+    for (auto& kv : groups) {
+        std::vector<ssa_decomp*> ds;
+        for (auto& r : kv.second) ds.push_back(r->d.get());
+        int rc;
+        {
+            Batch t(ctx, st);
+            fill_batch(t, ctx, ds);
+            rc = run_setup(t);
+        }
+        std::map<std::pair<int, int>, std::vector<std::shared_ptr<ServeReq>>> parts;
+        for (auto& r : kv.second) {
+            ssa_decomp* d = r->d.get();
+            if (rc || d->status != SSA_OK) {
+                coop_done(S, r, rc ? rc : d->status);
+                continue;
+            }
+            choose_side(d);
+            const int m = basis_size(d->nshort, d->r);
+            parts[{m, restart_keep(m, d->r)}].push_back(r);
+        }
+        for (auto& pv : parts) {
+            std::vector<ssa_decomp*> pd;
+            for (auto& r : pv.second) pd.push_back(r->d.get());
+            std::vector<int*> ctrs(pd.size(), nullptr);
+            int prc;
+            {
+                Batch t(ctx, st);
+                fill_batch(t, ctx, pd);
+                prc = run_alloc_spectrum(t);
+                for (size_t k = 0; k < pd.size() && !prc; ++k) prc = pd[k]->dalloc(&ctrs[k], 2);
+            }
+            if (prc) {
+                for (auto& r : pv.second) coop_done(S, r, prc);
+                continue;
+            }
+            CoopBatch* B = nullptr;
+            for (auto& cb : C.batches)
+                if (cb->key == kv.first && cb->m == pv.first.first && cb->kk == pv.first.second) B = cb.get();
+            if (!B) {
+                C.batches.emplace_back(new CoopBatch(ctx));
+                B = C.batches.back().get();
+                B->key = kv.first;
+                B->m = pv.first.first;
+                B->kk = pv.first.second;
+            }
+            for (size_t k = 0; k < pd.size(); ++k) {
+                pd[k]->last_st = st;
+                pd[k]->lz.step = ctrs[k];
+                pd[k]->st.basis = B->m;
+                B->b.ds.push_back(pd[k]);
+                CoopBatch::Inst I;
+                I.r = pv.second[k];
+                I.ctr = ctrs[k];
+                B->in.push_back(I);
+            }
+            fill_batch(B->b, ctx, B->b.ds);
+            B->dirty = true;
+        }
+    }
+    return SSA_OK;
+}
+
+// One restart cycle of a batch: waiting instances take free slots, the
+// active ones take m - kk steps (m on their first cycle, in q shorter
+// cycles of the same length), and at the boundary the instances whose
+// cycle ends are tested, restarted or finished.
+int coop_cycle(ssa_ctx* ctx, Server& S, CoopBatch& B, int slots) {
+    Batch& b = B.b;
+    const hipStream_t st = b.st;
+    const int m = B.m, kk = B.kk, c = m - kk;
+    int rc;
+    int nact = 0;
+    for (auto& I : B.in) nact += I.active;
+    std::vector<int> joiners;
+    for (int i = 0; i < (int)B.in.size() && nact < slots; ++i)
+        if (!B.in[i].active) {
+            B.in[i].active = true;
+            B.in[i].jh = 0;
+            joiners.push_back(i);
+            ++nact;
+        }
+    if (B.dirty) {
+        if ((rc = b.upload_descs())) return rc;
+        B.dirty = false;
+    }
+    if (!joiners.empty()) {
+        ItemList Z, I;
+        for (int i : joiners) {
+            for (int k = 0; k < b.ds[i]->lz.nblk; ++k) Z.h.push_back(Item{i, k, 0, 0});
+            I.h.push_back(Item{i, 0, 0, 0});
+        }
+        if ((rc = upload_lists({&Z, &I}, st))) return rc;
+        launch_lz_start(Z.n(), st, b.lzs(), Z.ptr(), 0ULL);   // each instance's own seed
+        launch_step_set(I.n(), st, b.lzs(), I.ptr(), 0, 0);
+    }
+    std::vector<int> act;
+    for (int i = 0; i < (int)B.in.size(); ++i)
+        if (B.in[i].active) act.push_back(i);
+    if (act.empty()) return SSA_OK;
+    StepLists SL;
+    build_step_lists(b, act, SL);
+    if ((rc = upload_step_lists(SL, st))) return rc;
+    for (int k = 0; k < c; ++k) {
+        launch_step(b, SL, kStepDev, kStepDev, IN_LZ_STEP);
+        launch_step_next_inst(SL.inst.n(), st, b.lzs(), SL.inst.ptr());
+    }
+    HIPCHK(hipGetLastError());
+    std::vector<int> ends;
+    for (int i : act) {
+        B.in[i].jh += c;
+        if (B.in[i].jh == m) ends.push_back(i);
+    }
+    if (ends.empty()) return SSA_OK;
+    const int ni = (int)b.ds.size();
+    int rmax = 0;
+    for (auto* d : b.ds) rmax = std::max(rmax, d->r);
+    {
+        ItemList N, I;
+        for (int i : ends) {
+            for (int k = 0; k < b.ds[i]->lz.nblk; ++k) N.h.push_back(Item{i, k, 0, 0});
+            I.h.push_back(Item{i, 0, 0, 0});
+        }
+        if ((rc = upload_lists({&N, &I}, st))) return rc;
+        launch_lz_normalize(N.n(), st, b.lzs(), N.ptr(), m);
+        launch_lz_svd(I.n(), st, b.lzs(), I.ptr(), m, 40);
+    }
+    HIPCHK(hipGetLastError());
+    const size_t fb = (size_t)ni * 4 * sizeof(int), bb = (size_t)ni * 2 * sizeof(double);
+    if (!b.dflag.p || b.dflag.cap < fb + bb) {
+        std::vector<char> z(fb + bb, 0);
+        if ((rc = b.dflag.put(z, st))) return rc;
+    }
+    char* dv = b.dflag.as<char>();
+    launch_gather_flags(ni, st, b.lzs(), reinterpret_cast<int*>(dv), reinterpret_cast<double*>(dv + fb));
+    void* hb = nullptr;
+    if ((rc = ctx->readback_buf(st, fb + bb, &hb))) return rc;
+    HIPCHK(hipMemcpyAsync(hb, dv, fb + bb, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<int> flags(4 * (size_t)ni);
+    std::vector<double> betas(2 * (size_t)ni);
+    std::memcpy(flags.data(), hb, fb);
+    std::memcpy(betas.data(), static_cast<char*>(hb) + fb, bb);
+    const int max_steps = step_limit();
+    std::vector<int> done, cont, fresh;
+    for (int i : ends) {
+        auto& I = B.in[i];
+        I.steps += m - (I.cycles == 0 ? 0 : kk);
+        ++I.cycles;
+        auto* d = b.ds[i];
+        d->st.svd_sweeps += flags[4 * i + 1];
+        const bool ok = flags[4 * i] != 0;
+        const bool bd = flags[4 * i + 2] != 0;
+        if (bd && I.bdrest < 2 && I.steps < max_steps) {
+            I.bdrest++;
+            I.restarts++;
+            fresh.push_back(i);
+            cont.push_back(i);
+            continue;
+        }
+        if (ok || bd || I.steps >= max_steps) {
+            done.push_back(i);
+            d->st.converged = ok || bd;
+            d->st.steps = I.steps;
+            d->st.restarts = I.restarts;
+            d->st.max_resid = betas[2 * i + 1];
+            d->st.side = d->side;
+            d->st.batch = nact;
+            if (!(ok || bd)) d->status = SSA_ENOCONV;
+        } else {
+            cont.push_back(i);
+            I.restarts++;
+        }
+    }
+    if (!cont.empty()) {
+        // the random restart of a breakdown draws from the instance's own
+        // cycle count
+        std::map<int, std::vector<int>> by_cycle;
+        for (int i : cont) {
+            const bool f = std::find(fresh.begin(), fresh.end(), i) != fresh.end();
+            by_cycle[f ? B.in[i].cycles : -1].push_back(i);
+        }
+        for (auto& kv : by_cycle) {
+            const std::vector<int>& grp = kv.second;
+            if ((rc = launch_restart(b, grp, kv.first < 0 ? std::vector<int>{} : grp, m, kk,
+                                     kv.first < 0 ? 0 : kv.first)))
+                return rc;
+        }
+        ItemList I2;
+        for (int i : cont) {
+            I2.h.push_back(Item{i, 0, 0, 0});
+            B.in[i].jh = kk;
+        }
+        if ((rc = upload_lists({&I2}, st))) return rc;
+        launch_step_set(I2.n(), st, b.lzs(), I2.ptr(), kk, kk);
+    }
+    if (done.empty()) return SSA_OK;
+    if ((rc = lanczos_outputs(b, done, m, rmax))) return rc;
+    {
+        FinishLists F;
+        if ((rc = run_finish(b, F, &done))) return rc;
+    }
+    HIPCHK(hipGetLastError());
+    // results of the finished requests, then they leave the batch
+    std::vector<std::pair<std::shared_ptr<ServeReq>, int>> fin;
+    for (int i : done) {
+        auto r = B.in[i].r;
+        ssa_decomp* d = r->d.get();
+        int status = d->status == SSA_ENOCONV ? SSA_ENOCONV : SSA_OK;
+        if (const int e = coop_reconstruct(ctx, r.get())) status = e;
+        if (hipStreamSynchronize(st) != hipSuccess) status = SSA_EDEVICE;
+        else d->last_st = nullptr;   // complete: nothing queued refers to it
+        fin.emplace_back(r, status);
+    }
+    std::vector<ssa_decomp*> keep_ds;
+    std::vector<CoopBatch::Inst> keep;
+    for (int i = 0; i < ni; ++i)
+        if (std::find(done.begin(), done.end(), i) == done.end()) {
+            keep_ds.push_back(b.ds[i]);
+            keep.push_back(B.in[i]);
+        }
+    b.ds.swap(keep_ds);
+    B.in.swap(keep);
+    B.dirty = true;
+    for (auto& f : fin) coop_done(S, f.first, f.second);
+    return SSA_OK;
+}
+
+// One round of the cooperative server: admissions, then one cycle of every
+// running batch.  Caller holds the context's call lock.
+int coop_advance(ssa_ctx* ctx) {
+    Server& S = *ctx->srv;
+    CoopState& C = *S.coop;
+    g_tables_ctx = ctx;
+    TableScope tables(ctx, ctx->st);
+    int rc;
+    if ((rc = coop_admit(ctx, S, C))) return rc;
+    const int slots = ctx->slots > 0 ? ctx->slots : S.max_batch;
+    for (auto& B : C.batches) {
+        if ((rc = coop_cycle(ctx, S, *B, slots))) {
+            // a failed cycle ends its requests (the others keep going)
+            for (auto& I : B->in) coop_done(S, I.r, rc);
+            B->in.clear();
+            B->b.ds.clear();
+        }
+    }
+    C.batches.erase(std::remove_if(C.batches.begin(), C.batches.end(),
+                                   [](const std::unique_ptr<CoopBatch>& B) { return B->in.empty(); }),
+                    C.batches.end());
+    return SSA_OK;
+}
+
 int serve_start(ssa_ctx* ctx) {
     if (ctx->srv.load(std::memory_order_acquire)) return SSA_OK;
     std::lock_guard<std::mutex> start_lock(ctx->srv_mu);
@@ -2849,9 +3202,41 @@ int serve_start(ssa_ctx* ctx) {
     return SSA_OK;
 }
 
+// The request of a ticket (nullptr if unknown) and whether it is done.
+std::shared_ptr<ServeReq> find_ticket(Server& S, uint64_t ticket, bool* done) {
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.reqs.find(ticket);
+    if (it == S.reqs.end()) return nullptr;
+    *done = it->second->done;
+    return it->second;
+}
+
+// The cooperative server: a queue and its batches, no threads.
+int coop_start(ssa_ctx* ctx) {
+    if (ctx->srv.load(std::memory_order_acquire)) return SSA_OK;
+    std::lock_guard<std::mutex> start_lock(ctx->srv_mu);
+    if (ctx->srv.load(std::memory_order_acquire)) return SSA_OK;
+    auto* S = new Server();
+    S->coop = std::make_shared<CoopState>();
+    ctx->srv.store(S, std::memory_order_release);
+    return SSA_OK;
+}
+
 void serve_stop(ssa_ctx* ctx) {
     Server* S = ctx->srv;
     if (!S) return;
+    if (S->coop) {
+        // queued work of the batches first, then the batches (they refer to
+        // the requests' handles), then the requests
+        std::lock_guard<std::recursive_mutex> call(ctx->call_mu);
+        (void)hipStreamSynchronize(ctx->st);
+        S->coop->batches.clear();
+        S->pending.clear();
+        S->reqs.clear();
+        ctx->srv = nullptr;
+        delete S;
+        return;
+    }
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->stop = true;
@@ -4122,11 +4507,10 @@ void ssa_free(ssa_decomp* d) { delete d; }
 int ssa_submit(ssa_ctx* ctx, const ssa_request* req, const int* grp_ptr, const int* grp_idx, int ngroups,
                uint64_t* ticket) {
     if (!ctx || !req || !ticket) return fail(SSA_EINVAL, "NULL argument");
-    // the serving threads stay off until a GPU fault seen once on them is
-    // explained; requests are served through the batch calls meanwhile
-    if (!std::getenv("SHSSA_SERVE_ENGINE"))
-        return fail(SSA_ESTATE, "the serving engine is switched off (SHSSA_SERVE_ENGINE=1 enables it); "
-                                "serve requests through ssa_decompose_batch");
+    // The worker threads run only with SHSSA_SERVE_ENGINE set (a GPU fault
+    // seen once on them is not explained); by default the server is
+    // cooperative: ssa_poll and ssa_wait drive the requests.
+    const bool engine = std::getenv("SHSSA_SERVE_ENGINE") != nullptr;
     if (!req->x || req->nx <= 0 || req->ny <= 0) return fail(SSA_EINVAL, "sizes must be positive");
     if (ngroups < 0 || (ngroups > 0 && (!grp_ptr || !grp_idx))) return fail(SSA_EINVAL, "bad groups");
     auto r = std::make_shared<ServeReq>();
@@ -4154,8 +4538,10 @@ int ssa_submit(ssa_ctx* ctx, const ssa_request* req, const int* grp_ptr, const i
     r->est = estimate_bytes(r->d.get(), ngroups);
     if (ctx->budget && r->est > ctx->budget)
         return fail(SSA_ENOMEM, "request larger than the context's memory budget");
-    if ((rc = serve_start(ctx))) return rc;
+    if ((rc = engine ? serve_start(ctx) : coop_start(ctx))) return rc;
     Server& S = *ctx->srv;
+    if (engine == (S.coop != nullptr))
+        return fail(SSA_ESTATE, "SHSSA_SERVE_ENGINE changed after the context's first request");
     {
         std::lock_guard<std::mutex> lk(S.mu);
         r->ticket = S.next++;
@@ -4189,16 +4575,30 @@ int ssa_poll(ssa_ctx* ctx, uint64_t ticket, int* done) {
     if (!ctx || !done) return fail(SSA_EINVAL, "NULL argument");
     if (!ctx->srv) return fail(SSA_EINVAL, "unknown ticket");
     Server& S = *ctx->srv;
-    std::lock_guard<std::mutex> lk(S.mu);
-    auto it = S.reqs.find(ticket);
-    if (it == S.reqs.end()) return fail(SSA_EINVAL, "unknown ticket");
-    *done = it->second->done;
+    bool d = false;
+    if (!find_ticket(S, ticket, &d)) return fail(SSA_EINVAL, "unknown ticket");
+    if (!d && S.coop) {
+        // cooperative server: one round of work
+        CallLock call(ctx);
+        if (int rc = coop_advance(ctx)) return rc;
+        (void)find_ticket(S, ticket, &d);
+    }
+    *done = d;
     return SSA_OK;
 }
 
 int ssa_wait(ssa_ctx* ctx, uint64_t ticket) {
     if (!ctx || !ctx->srv) return fail(SSA_EINVAL, "unknown ticket");
     Server& S = *ctx->srv;
+    if (S.coop) {
+        for (;;) {
+            bool d = false;
+            if (!find_ticket(S, ticket, &d)) return fail(SSA_EINVAL, "unknown ticket");
+            if (d) return SSA_OK;
+            CallLock call(ctx);
+            if (int rc = coop_advance(ctx)) return rc;
+        }
+    }
     std::unique_lock<std::mutex> lk(S.mu);
     auto it = S.reqs.find(ticket);
     if (it == S.reqs.end()) return fail(SSA_EINVAL, "unknown ticket");

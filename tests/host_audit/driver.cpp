@@ -221,7 +221,9 @@ static void extras(ssa_ctx* ctx) {
 }
 
 int main(int argc, char** argv) {
-    setenv("SHSSA_SERVE_ENGINE", "1", 1);   // the audit covers the serving threads
+    // the serving threads (SHSSA_SERVE_ENGINE), or with AUDIT_COOP the
+    // cooperative server that the clients' waits drive
+    if (!std::getenv("AUDIT_COOP")) setenv("SHSSA_SERVE_ENGINE", "1", 1);
     const int nreq = argc > 1 ? std::atoi(argv[1]) : 40;
     const size_t budget = argc > 2 ? (size_t)std::strtoull(argv[2], nullptr, 10) : 0;
     // the length tuner and the tune cache file run too (AUDIT_TUNE_CACHE: its path)

@@ -7,6 +7,8 @@ and 1e-5 for the FP32 path (FP32 products, FP64 Lanczos).  Individual
 vectors of clusters closer than 1e-3 s_1 are not unique (only their span
 is); such clusters are compared as a whole.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -1292,19 +1294,27 @@ def test_length_tuner_chooses_persists_and_keeps_parity(tmp_path, capfd, monkeyp
         c2.close()
 
 
-def test_serving_engine_is_switched_off(ctx, monkeypatch):
-    """ssa_submit refuses (SSA_ESTATE) unless SHSSA_SERVE_ENGINE is set: its
-    threads stay off until a GPU fault seen once on them is explained.  The
-    refusal comes before any serving thread starts."""
+def test_serving_threads_stay_off_by_default(monkeypatch):
+    """Without SHSSA_SERVE_ENGINE the server is cooperative: ssa_submit
+    starts no thread (the worker threads stay off until a GPU fault seen
+    once on them is explained), and the caller's ssa_wait runs the work."""
     import paper_1309_5050_amd as S
     monkeypatch.delenv("SHSSA_SERVE_ENGINE", raising=False)
-    x = np.cos(np.arange(400) / 5.0)
-    with pytest.raises(S.SsaError) as e:
-        ctx.submit(x, 100, r=2)
-    assert e.value.code == -8
-    with pytest.raises(S.SsaError) as e:
-        ctx.submit_multi([x, x], 100, r=2)
-    assert e.value.code == -8
+    c = S.Context(0)
+    try:
+        x = np.cos(np.arange(400) / 5.0)
+        c.decompose(x, 100, r=2).free()                 # the runtime's own threads start here
+        before = len(os.listdir("/proc/self/task"))
+        t1 = c.submit(x, 100, r=2)
+        t2 = c.submit_multi([x, x], 100, r=2)
+        assert len(os.listdir("/proc/self/task")) == before
+        for t in (t1, t2):
+            c.wait(t)
+            d, _, _ = c.take(t, shape=(0,), ngroups=0)
+            assert d.status == 0
+            d.free()
+    finally:
+        c.close()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

@@ -1,7 +1,7 @@
 """Host-side audit of the library on a mock HIP runtime (CPU only).
 
-The engine's host code (serving threads, device-memory pool, deferred
-releases, staging, batch calls) is built with AddressSanitizer or
+The engine's host code (serving threads and the cooperative server,
+device-memory pool, deferred releases, staging, batch calls) is built with AddressSanitizer or
 ThreadSanitizer and linked against tests/host_audit/mock_hip.cpp, a stand-in
 runtime whose streams run their queues asynchronously on threads and whose
 kernels only check what they would read.  The mock reports device blocks that
@@ -69,6 +69,19 @@ def test_serving_and_pool_under_address_sanitizer(tmpdir_mod):
     assert "0 audit reports" in out, out[-2000:]
 
 
+def test_cooperative_serving_under_address_sanitizer(tmpdir_mod):
+    """The cooperative server (no worker threads: the clients' waits drive
+    admissions and restart cycles on the context's stream), with and
+    without a device memory cap."""
+    exe = _build(tmpdir_mod, "address")
+    rc, out = _run(exe, 24, {"AUDIT_COOP": "1", "ASAN_OPTIONS": "detect_leaks=1"})
+    assert rc == 0, out[-4000:]
+    assert "0 unexpected statuses" in out and "0 audit reports" in out, out[-2000:]
+    rc, out = _run(exe, 24, {"AUDIT_COOP": "1", "MOCK_DEVICE_BYTES": "50000000", "ASAN_OPTIONS": "detect_leaks=1"})
+    assert rc == 0, out[-4000:]
+    assert "0 audit reports" in out, out[-2000:]
+
+
 def test_serving_and_pool_under_thread_sanitizer(tmpdir_mod):
     exe = _build(tmpdir_mod, "thread")
     rc, out = _run(exe, 16, {"TSAN_OPTIONS": "halt_on_error=1"}, timeout=600)
@@ -83,3 +96,8 @@ def test_serving_and_pool_under_thread_sanitizer(tmpdir_mod):
     assert "WARNING: ThreadSanitizer" not in out, out[-4000:]
     assert "0 unexpected statuses" in out and "0 audit reports" in out, out[-2000:]
     assert os.path.exists(cache)
+    # the cooperative server: two clients' waits drive it in turn
+    rc, out = _run(exe, 16, {"TSAN_OPTIONS": "halt_on_error=1", "AUDIT_COOP": "1"}, timeout=600)
+    assert rc == 0, out[-4000:]
+    assert "WARNING: ThreadSanitizer" not in out, out[-4000:]
+    assert "0 unexpected statuses" in out and "0 audit reports" in out, out[-2000:]
