@@ -363,6 +363,8 @@ def main():
     ap.add_argument("--serve", type=int, default=300, metavar="N",
                     help="requests of the mixed serving workload for the latency runs through the "
                          "batch calls (0: skip)")
+    ap.add_argument("--serve-coop", type=int, default=300, metavar="N",
+                    help="requests of the serving mix through the cooperative server (0: skip)")
     ap.add_argument("--serve-engine", type=int, default=0, metavar="N",
                     help="requests for the library's asynchronous serving engine (ssa_submit); off by "
                          "default: its worker-thread path is not run on the GPU until a fault seen on an "
@@ -596,6 +598,10 @@ def main():
     if args.serve > 0:
         note("serving loop")
         serving = serve_batched(S, W, args.serve)
+    if args.serve_coop > 0:
+        note("cooperative server")
+        cap = serving.get("plain_fp64_capacity_rps") if serving else None
+        serving = dict(serving or {}, coop=serve_bench(S, W, args.serve_coop, cap64=cap, plain=cap is None))
     if args.serve_engine > 0:
         os.environ["SHSSA_SERVE_ENGINE"] = "1"   # the library keeps its serving threads off otherwise
         serving = dict(serving or {}, engine=serve_bench(S, W, args.serve_engine))
@@ -866,31 +872,39 @@ def _keeps_up(run):
             and run["p50_last_third_ms"] <= 2.0 * max(run["p50_first_third_ms"], 1.0))
 
 
-def serve_bench(S, W, n_req):
+def serve_bench(S, W, n_req, cap64=None, plain=True):
     """Mixed serving workload (60% 1D, 25% MSSA, 15% 2D, r ~ U{5..40},
-    groups {1..min(r,4)}): capacity of the plain single-instance FP64 path
-    (closed loop), then Poisson arrivals at 0.8 x that capacity through the
-    plain path (one request at a time) and the serving engine in FP32 and
-    FP64.  The served FP32 capacity is the highest
-    Poisson rate it sustains (a ladder of rates below the closed-loop
-    throughput, where all requests wait at once and form the largest
-    batches); the last run is at 0.8 x that sustained capacity."""
+    groups {1..min(r,4)}) through ssa_submit / ssa_wait / ssa_take (the
+    cooperative server, or the worker threads with SHSSA_SERVE_ENGINE):
+    capacity of the plain single-instance FP64 path (closed loop; cap64 when
+    already measured), then Poisson arrivals at 0.8 x that capacity through
+    the plain path (one request at a time; plain = False: measured
+    elsewhere at the same arrivals) and the server in FP32 and FP64.  The
+    served FP32 capacity is the highest Poisson rate it sustains (a ladder of
+    rates below the closed-loop throughput, where all requests wait at once
+    and form the largest batches); the last run is at 0.8 x that sustained
+    capacity."""
     mix = W.serving_mix(n_req, seed=5)
     data = [W.materialize(d) for d in mix]
-    ctx = S.Context(0)
-    ncap = min(len(data), 60)
-    for q in data[:3]:
-        _run_sync(ctx, q, "fp64")
-    t0 = time.perf_counter()
-    for q in data[:ncap]:
-        _run_sync(ctx, q, "fp64")
-    cap64 = ncap / (time.perf_counter() - t0)
-    ctx.close()
+    if cap64 is None:
+        ctx = S.Context(0)
+        ncap = min(len(data), 60)
+        for q in data[:3]:
+            _run_sync(ctx, q, "fp64")
+        t0 = time.perf_counter()
+        for q in data[:ncap]:
+            _run_sync(ctx, q, "fp64")
+        cap64 = ncap / (time.perf_counter() - t0)
+        ctx.close()
     out = {"workload": f"serving mix, {n_req} requests (60% 1D N~U(500,20000), 25% MSSA s~U(4,32), "
                        f"15% 2D S~U(64,512)), r~U(5,40)",
+           "server": ("library worker threads" if os.environ.get("SHSSA_SERVE_ENGINE") else
+                      "cooperative: the collecting thread's waits run admissions and restart cycles; requests "
+                      "join running batches as slots free"),
            "plain_fp64_capacity_rps": cap64, "runs": []}
-    # the same arrivals (seed 11) through the plain path and the serving engine
-    out["runs"].append(_plain_run(S, data, 0.8 * cap64, seed=11))
+    # the same arrivals (seed 11) through the plain path and the server
+    if plain:
+        out["runs"].append(_plain_run(S, data, 0.8 * cap64, seed=11))
     for prec in ("fp32", "fp64"):
         out["runs"].append(_served_run(S, data, prec, 0.8 * cap64, seed=11))
     closed = _served_run(S, data, "fp32", None, seed=12)

@@ -3157,8 +3157,10 @@ int coop_cycle(ssa_ctx* ctx, Server& S, CoopBatch& B, int slots) {
     return SSA_OK;
 }
 
-// One round of the cooperative server: admissions, then one cycle of every
-// running batch.  Caller holds the context's call lock.
+// One round of the cooperative server: admissions, then one cycle of the
+// batch that holds the oldest request (requests are served in arrival
+// order, each batch carrying the later requests of its class that have
+// joined it).  Caller holds the context's call lock.
 int coop_advance(ssa_ctx* ctx) {
     Server& S = *ctx->srv;
     CoopState& C = *S.coop;
@@ -3167,13 +3169,19 @@ int coop_advance(ssa_ctx* ctx) {
     int rc;
     if ((rc = coop_admit(ctx, S, C))) return rc;
     const int slots = ctx->slots > 0 ? ctx->slots : S.max_batch;
-    for (auto& B : C.batches) {
-        if ((rc = coop_cycle(ctx, S, *B, slots))) {
-            // a failed cycle ends its requests (the others keep going)
-            for (auto& I : B->in) coop_done(S, I.r, rc);
-            B->in.clear();
-            B->b.ds.clear();
-        }
+    CoopBatch* oldest = nullptr;
+    double t_old = 0.0;
+    for (auto& B : C.batches)
+        for (auto& I : B->in)
+            if (!oldest || I.r->t_submit < t_old) {
+                oldest = B.get();
+                t_old = I.r->t_submit;
+            }
+    if (oldest && (rc = coop_cycle(ctx, S, *oldest, slots))) {
+        // a failed cycle ends its requests (the others keep going)
+        for (auto& I : oldest->in) coop_done(S, I.r, rc);
+        oldest->in.clear();
+        oldest->b.ds.clear();
     }
     C.batches.erase(std::remove_if(C.batches.begin(), C.batches.end(),
                                    [](const std::unique_ptr<CoopBatch>& B) { return B->in.empty(); }),

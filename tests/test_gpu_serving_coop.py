@@ -90,9 +90,8 @@ def test_coop_served_equals_synchronous(ctx, prec):
 
 def test_coop_requests_join_running_batches():
     """With 2 slots, requests submitted while others run (after some rounds
-    of the server) join the running batch as slots free up; every result
-    equals the synchronous one, and a short request submitted later can
-    finish before a long one submitted earlier."""
+    of the server) join the running batches as slots free up; every result
+    equals the synchronous one."""
     import paper_1309_5050_amd as S
     c = S.Context(0)
     try:
