@@ -425,30 +425,42 @@ const char* ssa_last_error(void);
  * ssa_submit copies the request's host inputs (x, mask, wmask: as for
  * ssa_decompose) and the groups (CSR form: grp_ptr[ngroups+1],
  * 0-based component ids in grp_idx; ngroups may be 0 for no reconstruction)
- * and returns a ticket at once.  Library threads, each with its own HIP
- * stream on the context's device, admit waiting requests in arrival order
- * while their estimated device memory fits the context's budget beside the
- * running batches, put every waiting request of the same kernel class (as
- * for ssa_decompose_batch: sizes may differ) into the same batch (up to
- * 64), and run decomposition and reconstruction.  Errors that the plan shows at once (bad sizes, a request
- * larger than the whole budget: SSA_ENOMEM) are returned by ssa_submit.
+ * and returns a ticket at once; it does no device work.  Errors that the
+ * plan shows at once (bad sizes, a request larger than the whole budget:
+ * SSA_ENOMEM) are returned by ssa_submit.
+ *
+ * The server is cooperative: it has no threads of its own, and each call of
+ * ssa_poll on an unfinished request, and ssa_wait until its request is done,
+ * runs rounds of it on the context's stream in the calling thread.  A round
+ * admits waiting requests in arrival order while their estimated device
+ * memory fits the context's budget beside the admitted ones (the first
+ * always when none runs), sets them up and adds each to the batch of its
+ * kernel class (as for ssa_decompose_batch: sizes may differ), then runs one
+ * restart cycle of the batch that holds the oldest request: waiting
+ * requests of the batch take the slots (ssa_ctx_set_slots, 64 when 0) of
+ * finished ones and begin from their start vectors while the others
+ * continue, and requests whose cycle ends with convergence leave the batch
+ * with their reconstructions.  Every request runs the steps it would run
+ * alone, so its results equal the synchronous call's.  Calls from several
+ * threads are allowed (rounds run one at a time per context).
  *
  * ssa_poll sets *done = 1 once the request has finished (successfully or
- * not).  ssa_wait blocks until then.  ssa_take ends the request: it returns
+ * not).  ssa_wait returns then.  ssa_take ends the request: it returns
  * the request's status, hands over the handle (*out, freed by the caller
  * with ssa_free; NULL if the request failed), copies the reconstruction
  * (ngroups x nx x ny, NaN off N') into recon if recon is not NULL, and
- * fills times (ms from submission to start and to completion) if not NULL.
- * ssa_take of an unfinished request returns SSA_EBUSY and changes nothing.
- * Requests not taken are released by ssa_ctx_destroy.
+ * fills times (ms from submission to admission and to completion) if not
+ * NULL.  ssa_take of an unfinished request returns SSA_EBUSY and changes
+ * nothing.  Requests not taken are released by ssa_ctx_destroy.
  *
- * Switched off: ssa_submit and ssa_submit_multi return SSA_ESTATE unless
- * the environment variable SHSSA_SERVE_ENGINE is set.  A run of these
- * serving threads once ended with a GPU fault whose cause is not found; the
- * batch calls (ssa_decompose_batch*, with continuous batching) serve
- * requests meanwhile. */
+ * With the environment variable SHSSA_SERVE_ENGINE set when a context's
+ * first request is submitted, library threads (each with its own HIP
+ * stream) run whole batches instead, and ssa_wait blocks.  A run of those
+ * threads once ended with a GPU fault whose cause is not found; they are
+ * kept for that investigation and are not used by default.  Submitting
+ * after the variable changed returns SSA_ESTATE. */
 typedef struct ssa_times {
-    double queue_ms;   /* submission -> start of its batch */
+    double queue_ms;   /* submission -> admission (start of its batch for the threads) */
     double total_ms;   /* submission -> completion */
 } ssa_times;
 
