@@ -2860,6 +2860,8 @@ struct CoopBatch {
     };
     std::vector<Inst> in;   // in[i] runs b.ds[i]
     bool dirty = true;      // descriptors changed since the last upload
+    StepLists lists;        // item lists of the active set lists_for (kept while it stays)
+    std::vector<int> lists_for;
     explicit CoopBatch(ssa_ctx* ctx) : b(ctx) {}
 };
 
@@ -3014,6 +3016,7 @@ int coop_cycle(ssa_ctx* ctx, Server& S, CoopBatch& B, int slots) {
     if (B.dirty) {
         if ((rc = b.upload_descs())) return rc;
         B.dirty = false;
+        B.lists_for.clear();   // positions may have changed
     }
     if (!joiners.empty()) {
         ItemList Z, I;
@@ -3029,9 +3032,12 @@ int coop_cycle(ssa_ctx* ctx, Server& S, CoopBatch& B, int slots) {
     for (int i = 0; i < (int)B.in.size(); ++i)
         if (B.in[i].active) act.push_back(i);
     if (act.empty()) return SSA_OK;
-    StepLists SL;
-    build_step_lists(b, act, SL);
-    if ((rc = upload_step_lists(SL, st))) return rc;
+    StepLists& SL = B.lists;
+    if (act != B.lists_for) {
+        build_step_lists(b, act, SL);
+        if ((rc = upload_step_lists(SL, st))) return rc;
+        B.lists_for = act;
+    }
     for (int k = 0; k < c; ++k) {
         launch_step(b, SL, kStepDev, kStepDev, IN_LZ_STEP);
         launch_step_next_inst(SL.inst.n(), st, b.lzs(), SL.inst.ptr());
