@@ -2838,7 +2838,7 @@ void serve_worker(ssa_ctx* ctx, int w) {
 // ---------------------------------------------------------------------------
 // cooperative serving (the default): ssa_poll and ssa_wait drive the
 // requests on the context's stream, in the calling thread, one restart
-// cycle of every running kernel class at a time
+// cycle at a time
 // ---------------------------------------------------------------------------
 
 // The requests of one kernel class (geometry, basis and restart size) that
