@@ -679,21 +679,49 @@ __device__ __forceinline__ void pair_idx(const CellSet& S, int a, int t, int (&i
             idx[q] = b < lim ? base + b : -1;
         }
     } else {
+        // A masked row: cell b's index is the row offset plus the count of
+        // set cells before b in the row.  The counts come from the row's
+        // mask bytes by a scan across the row's G lanes (lane t holds cells
+        // 2 (t + G e) + h: segment e of 2G cells lies in order across the
+        // lanes), not from a stored prefix array: one byte per cell read
+        // instead of five.
         const gptr<const uint8_t> m = as_global(S.mask) + (long)ar * S.boxB;
-        const gptr<const int> pf = as_global(S.pref) + (long)ar * (S.boxB + 1);
-        uint8_t mv[16];
-        int pv[16];
+        int on[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int b = 2 * (t + G * (q >> 1)) + (q & 1);
             const int bb = b < S.boxB ? b : S.boxB - 1;
-            mv[q] = gload(m + bb);
-            pv[q] = gload(pf + bb);
+            const uint8_t mv = gload(m + bb);
+            on[q] = (b < lim && mv) ? 1 : 0;
         }
+        // the lane's counts of segments 0..3 and 4..7 in the bytes of two
+        // words (at most 2 per lane, 2 G <= 128 per segment: no carry)
+        unsigned lo = 0, hi = 0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int b = 2 * (t + G * (q >> 1)) + (q & 1);
-            idx[q] = (b < lim && mv[q]) ? base + pv[q] : -1;
+        for (int e = 0; e < 4; ++e) {
+            lo |= (unsigned)(on[2 * e] + on[2 * e + 1]) << (8 * e);
+            hi |= (unsigned)(on[8 + 2 * e] + on[8 + 2 * e + 1]) << (8 * e);
+        }
+        unsigned slo = lo, shi = hi;   // inclusive scans over the row's lanes
+#pragma unroll
+        for (int d = 1; d < G; d <<= 1) {
+            const unsigned ulo = __shfl_up(slo, d, G), uhi = __shfl_up(shi, d, G);
+            if (t >= d) {
+                slo += ulo;
+                shi += uhi;
+            }
+        }
+        const unsigned tlo = __shfl(slo, G - 1, G), thi = __shfl(shi, G - 1, G);   // segment totals
+        const unsigned xlo = slo - lo, xhi = shi - hi;                            // exclusive
+        int before = 0;   // set cells of the earlier segments
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const unsigned xs = e < 4 ? xlo : xhi, ts = e < 4 ? tlo : thi;
+            const int sh = 8 * (e & 3);
+            const int p0 = base + before + (int)((xs >> sh) & 0xffu);
+            idx[2 * e] = on[2 * e] ? p0 : -1;
+            idx[2 * e + 1] = on[2 * e + 1] ? p0 + on[2 * e] : -1;
+            before += (int)((ts >> sh) & 0xffu);
         }
     }
 }
