@@ -6,7 +6,7 @@ noise, window 64x64, r = 30 eigentriples, reconstruction of the groups
 {1,2}, {3,4}, {5,6} (0-based {0,1}, {2,3}, {4,5}).  A step decomposes and
 reconstructs one batch of B images already resident in device memory.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--batch 256] [--precision fp32]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--batch 768] [--precision fp32]
 
 Prints one JSON line.  Besides the headline rate it reports:
 
@@ -40,7 +40,7 @@ GRID_CLASSES = ["row_in", "col", "row_mid", "row_out"]
 ROWFAM_CLASSES = ["row_in", "rowfam_mid", "rowfam_out"]
 KERNEL_OF = {"row_in": "k_rowr_in", "col": "k_colr", "row_mid": "k_rowr_mid", "row_out": "k_rowr_out",
              "rowfam_mid": "k_row_mid", "rowfam_out": "k_row_out"}
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fft_product_image512_batch256_fp32_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fft_product_image512_batch768_fp32_traffic.md")
 # the paper's decomposition timings (R, Rssa 0.10 with FFTW; hardware not
 # stated), elapsed seconds, for the three settings on its 258 x 275 image
 PAPER_SECONDS = {"eigen_25x25": 3.843, "lanczos_25x25": 0.519, "lanczos_160x80_r50": 0.587,
@@ -352,7 +352,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--batch", type=int, default=768)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp32_basis32"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--no-single", action="store_true", help="skip the single-instance FP64 comparator")
@@ -542,6 +542,18 @@ def main():
         note("extras")
         wcor, rforecast, extend, eigen = run_extras()
     del last
+    # the lines below run in contexts of their own, each closed after it, so
+    # that one line's memory pool is returned before the next grows its own
+    # (the headline's pool holds a batch of 768 images' blocks)
+    def fresh():
+        return S.Context(0, stream=stream.cuda_stream)
+
+    def done(c):
+        c.close()
+        torch.cuda.empty_cache()
+
+    done(ctx)
+    ctx = fresh()
 
     # the same workload in FP64 (the paper's arithmetic), the other workloads,
     # the reduced 2D workload the CPU oracle is timed on, and the paper's own
@@ -551,29 +563,39 @@ def main():
         configs = {}
         note("headline workload in fp64")
         n64 = max(2, args.steps // 2)
-        rate64, ms64, last64, prof64, rf64 = run_batched(S, ctx, torch, xs, (lw, lw), r, groups, "fp64", n64, 1)
+        c = fresh()
+        rate64, ms64, last64, prof64, rf64 = run_batched(S, c, torch, xs, (lw, lw), r, groups, "fp64", n64, 1)
         roof64, kern64 = product_roofline(prof64, last64, "fp64", rf64, n64)
         configs["image512_fp64"] = {"workload": "2D-SSA 512x512 image, 64x64 window, r=30 (as the headline)",
                                     "batch": B, "precision": "fp64", "decomps_per_s": rate64, "ms_per_step": ms64,
                                     "roofline": roof64, "roofline_kernels": kern64}
         del last64
-        configs["series_1000_fp64"] = config_line(S, W, ctx, torch, 1, "fp64", 3, 1)
+        done(c)
+        c = fresh()
+        configs["series_1000_fp64"] = config_line(S, W, c, torch, 1, "fp64", 3, 1)
+        done(c)
         # the same with the length tuner on (half-length 500 or 512, timed on
         # the first request; the warm-up batch carries the tuning)
         os.environ["SHSSA_LEN_TUNE"] = "1"
-        ctx_t = S.Context(0, stream=stream.cuda_stream)
+        c = fresh()
         del os.environ["SHSSA_LEN_TUNE"]
-        configs["series_1000_fp64_length_tuned"] = config_line(S, W, ctx_t, torch, 1, "fp64", 3, 1)
-        ctx_t.close()
-        configs["mssa_50_fp32"] = config_line(S, W, ctx, torch, 3, "fp32", 3, 1)
-        configs["shaped_1024_fp32"] = config_line(S, W, ctx, torch, 4, "fp32", 2, 1)
+        configs["series_1000_fp64_length_tuned"] = config_line(S, W, c, torch, 1, "fp64", 3, 1)
+        done(c)
+        c = fresh()
+        configs["mssa_50_fp32"] = config_line(S, W, c, torch, 3, "fp32", 3, 1)
+        done(c)
+        c = fresh()
+        configs["shaped_1024_fp32"] = config_line(S, W, c, torch, 4, "fp32", 2, 1)
+        done(c)
         w2 = W.config(2, "small")
         xr = [torch.tensor(W.image_2d(n=128, lw=16, r=30, seed=2000 + i)["x"], device=dev) for i in range(64)]
-        rr, msr, lr, prr, rfr = run_batched(S, ctx, torch, xr, w2["window"], 30, groups, "fp64", 3, 1)
+        c = fresh()
+        rr, msr, lr, prr, rfr = run_batched(S, c, torch, xr, w2["window"], 30, groups, "fp64", 3, 1)
         configs["image128_fp64"] = {"workload": "reduced 2D-SSA 128x128 image, 16x16 window, r=30 "
                                                 "(the workload the CPU oracle is timed on)",
                                     "batch": 64, "precision": "fp64", "decomps_per_s": rr, "ms_per_step": msr}
         del lr
+        done(c)
         note("continuous batching")
         configs["continuous_image512_fp32"] = continuous_line(S, W, ctx, torch, xs, (lw, lw), r, groups)
         note("paper context")
@@ -584,6 +606,10 @@ def main():
     if not args.no_single:
         outs1 = [torch.empty((len(groups), n, n), dtype=torch.float64, device=dev) for _ in range(2)]
         reps = 2
+        # untimed: the context's first FP64 call carries the column tuning
+        d = ctx.decompose_batch_dev(xs[:1], (lw, lw), r, precision="fp64")[0]
+        S.Context.reconstruct_batch_dev([d], groups, outs1[:1])
+        del d
         torch.cuda.synchronize()
         lat = []
         for i in range(reps):
