@@ -196,7 +196,7 @@ def config_line(S, W, ctx, torch, which, prec, steps, warmup, batch=None):
         masks, window, r = None, (1, ws[0]["window"]), ws[0]["r"]
         name = "1D SSA N=1000, L=500, r=10, groups {1,2},{3,4},{5}"
     elif which == 3:
-        B, groups = batch or 256, [[0, 1], [2, 3]]
+        B, groups = batch or 512, [[0, 1], [2, 3]]
         ws = [W.mssa_series(seed=3 + i) for i in range(B)]
         xs = []
         for w in ws:
@@ -208,7 +208,7 @@ def config_line(S, W, ctx, torch, which, prec, steps, warmup, batch=None):
         masks, window, r = None, (1, ws[0]["window"]), ws[0]["r"]
         name = "MSSA 50 series N~U(1000,3000), L=500, r=20, groups {1,2},{3,4}"
     else:
-        B, groups = batch or 128, [[0, 1, 2, 3]]
+        B, groups = batch or 256, [[0, 1, 2, 3]]
         ws = [W.shaped_disc(seed=4 + i) for i in range(B)]
         xs = [torch.tensor(w["x"], device=dev) for w in ws]
         masks = [torch.tensor(w["mask"], device=dev) for w in ws]
