@@ -188,7 +188,7 @@ def config_line(S, W, ctx, torch, which, prec, steps, warmup, batch=None):
     note(f"workload {which} ({prec})")
     dev = torch.device("cuda:0")
     if which == 1:
-        B, groups = batch or 512, [[0, 1], [2, 3], [4]]
+        B, groups = batch or 1024, [[0, 1], [2, 3], [4]]
         ws = [W.series_1d(seed=1 + i) for i in range(B)]
         # a series as a one-row array with a one-row window (the same
         # trajectory matrix as the column orientation)
@@ -196,7 +196,7 @@ def config_line(S, W, ctx, torch, which, prec, steps, warmup, batch=None):
         masks, window, r = None, (1, ws[0]["window"]), ws[0]["r"]
         name = "1D SSA N=1000, L=500, r=10, groups {1,2},{3,4},{5}"
     elif which == 3:
-        B, groups = batch or 512, [[0, 1], [2, 3]]
+        B, groups = batch or 1024, [[0, 1], [2, 3]]
         ws = [W.mssa_series(seed=3 + i) for i in range(B)]
         xs = []
         for w in ws:
