@@ -561,43 +561,56 @@ def main():
     configs = paper = None
     if not args.no_configs:
         configs = {}
+
+        def guarded(name, fn, len_tune=False):
+            """One line in a context of its own.  A library error (say, an
+            allocation refused) is reported in the line's place instead of
+            ending the run."""
+            if len_tune:
+                os.environ["SHSSA_LEN_TUNE"] = "1"
+            c = fresh()
+            if len_tune:
+                del os.environ["SHSSA_LEN_TUNE"]
+            try:
+                configs[name] = fn(c)
+            except S.SsaError as e:
+                note(f"{name}: {e}")
+                configs[name] = {"error": str(e)}
+            finally:
+                done(c)
+
+        def fp64_line(c):
+            n64 = max(2, args.steps // 2)
+            rate64, ms64, last64, prof64, rf64 = run_batched(S, c, torch, xs, (lw, lw), r, groups, "fp64", n64, 1)
+            roof64, kern64 = product_roofline(prof64, last64, "fp64", rf64, n64)
+            return {"workload": "2D-SSA 512x512 image, 64x64 window, r=30 (as the headline)",
+                    "batch": B, "precision": "fp64", "decomps_per_s": rate64, "ms_per_step": ms64,
+                    "roofline": roof64, "roofline_kernels": kern64}
+
+        def reduced_line(c):
+            w2 = W.config(2, "small")
+            xr = [torch.tensor(W.image_2d(n=128, lw=16, r=30, seed=2000 + i)["x"], device=dev) for i in range(64)]
+            rr, msr, _, _, _ = run_batched(S, c, torch, xr, w2["window"], 30, groups, "fp64", 3, 1)
+            return {"workload": "reduced 2D-SSA 128x128 image, 16x16 window, r=30 "
+                                "(the workload the CPU oracle is timed on)",
+                    "batch": 64, "precision": "fp64", "decomps_per_s": rr, "ms_per_step": msr}
+
         note("headline workload in fp64")
-        n64 = max(2, args.steps // 2)
-        c = fresh()
-        rate64, ms64, last64, prof64, rf64 = run_batched(S, c, torch, xs, (lw, lw), r, groups, "fp64", n64, 1)
-        roof64, kern64 = product_roofline(prof64, last64, "fp64", rf64, n64)
-        configs["image512_fp64"] = {"workload": "2D-SSA 512x512 image, 64x64 window, r=30 (as the headline)",
-                                    "batch": B, "precision": "fp64", "decomps_per_s": rate64, "ms_per_step": ms64,
-                                    "roofline": roof64, "roofline_kernels": kern64}
-        del last64
-        done(c)
-        c = fresh()
-        configs["series_1000_fp64"] = config_line(S, W, c, torch, 1, "fp64", 3, 1)
-        done(c)
+        guarded("image512_fp64", fp64_line)
+        guarded("series_1000_fp64", lambda c: config_line(S, W, c, torch, 1, "fp64", 3, 1))
         # the same with the length tuner on (half-length 500 or 512, timed on
         # the first request; the warm-up batch carries the tuning)
-        os.environ["SHSSA_LEN_TUNE"] = "1"
-        c = fresh()
-        del os.environ["SHSSA_LEN_TUNE"]
-        configs["series_1000_fp64_length_tuned"] = config_line(S, W, c, torch, 1, "fp64", 3, 1)
-        done(c)
-        c = fresh()
-        configs["mssa_50_fp32"] = config_line(S, W, c, torch, 3, "fp32", 3, 1)
-        done(c)
-        c = fresh()
-        configs["shaped_1024_fp32"] = config_line(S, W, c, torch, 4, "fp32", 2, 1)
-        done(c)
-        w2 = W.config(2, "small")
-        xr = [torch.tensor(W.image_2d(n=128, lw=16, r=30, seed=2000 + i)["x"], device=dev) for i in range(64)]
-        c = fresh()
-        rr, msr, lr, prr, rfr = run_batched(S, c, torch, xr, w2["window"], 30, groups, "fp64", 3, 1)
-        configs["image128_fp64"] = {"workload": "reduced 2D-SSA 128x128 image, 16x16 window, r=30 "
-                                                "(the workload the CPU oracle is timed on)",
-                                    "batch": 64, "precision": "fp64", "decomps_per_s": rr, "ms_per_step": msr}
-        del lr
-        done(c)
+        guarded("series_1000_fp64_length_tuned", lambda c: config_line(S, W, c, torch, 1, "fp64", 3, 1),
+                len_tune=True)
+        guarded("mssa_50_fp32", lambda c: config_line(S, W, c, torch, 3, "fp32", 3, 1))
+        guarded("shaped_1024_fp32", lambda c: config_line(S, W, c, torch, 4, "fp32", 2, 1))
+        guarded("image128_fp64", reduced_line)
         note("continuous batching")
-        configs["continuous_image512_fp32"] = continuous_line(S, W, ctx, torch, xs, (lw, lw), r, groups)
+        try:
+            configs["continuous_image512_fp32"] = continuous_line(S, W, ctx, torch, xs, (lw, lw), r, groups)
+        except S.SsaError as e:
+            note(f"continuous batching: {e}")
+            configs["continuous_image512_fp32"] = {"error": str(e)}
         note("paper context")
         paper = paper_context(S, W, torch)
 
@@ -636,7 +649,7 @@ def main():
     if not args.no_cpu:
         note("cpu oracle")
         cpu = cpu_baseline(W)
-        if configs:
+        if configs and "decomps_per_s" in configs.get("image128_fp64", {}):
             cpu["gpu_over_oracle_same_workload"] = configs["image128_fp64"]["decomps_per_s"] / cpu["value"]
 
     line = {
