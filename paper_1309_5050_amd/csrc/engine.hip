@@ -788,30 +788,36 @@ int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStrea
     if ((rc = d->dalloc(&d->krow, d->KA + 1))) return rc;
     if ((rc = d->dalloc(&d->W, n))) return rc;
     const bool lfull = d->L == (long)d->LA * d->LB;
-    if (!lfull && (rc = d->dalloc(&d->lmask, (long)d->LA * d->LB))) return rc;
-    std::vector<int> lpref_h;
+    // The window's tables in one block and one upload: row offsets, runs
+    // and, for a shaped window, the per-row exclusive prefix counts and the
+    // mask bytes (from a 256-byte boundary).
+    const int nrun = (int)d->ra.size();
+    const size_t o_runs = (size_t)d->LA + 1;
+    const size_t o_pref = o_runs + 3 * (size_t)nrun;
+    const size_t n_pref = lfull ? 0 : (size_t)d->LA * (d->LB + 1);
+    const size_t o_mask = (o_pref + n_pref + 63) / 64 * 64;
+    const size_t n_mask = lfull ? 0 : ((size_t)d->LA * d->LB + 3) / 4;
+    std::vector<int> tab(o_mask + n_mask, 0);
+    std::copy(d->lrow_h.begin(), d->lrow_h.end(), tab.begin());
+    std::copy(d->ra.begin(), d->ra.end(), tab.begin() + o_runs);
+    std::copy(d->rb0.begin(), d->rb0.end(), tab.begin() + o_runs + nrun);
+    std::copy(d->rb1.begin(), d->rb1.end(), tab.begin() + o_runs + 2 * (size_t)nrun);
     if (!lfull) {
-        // per-row exclusive prefix counts of the window mask
-        lpref_h.assign((size_t)d->LA * (d->LB + 1), 0);
         for (int a = 0; a < d->LA; ++a) {
-            int* pr = lpref_h.data() + (size_t)a * (d->LB + 1);
+            int* pr = tab.data() + o_pref + (size_t)a * (d->LB + 1);
             for (int b = 0; b < d->LB; ++b) pr[b + 1] = pr[b] + d->lmask_h[(size_t)a * d->LB + b];
         }
-        if ((rc = d->dalloc(&d->lpref, (long)lpref_h.size()))) return rc;
+        std::memcpy(tab.data() + o_mask, d->lmask_h.data(), d->lmask_h.size());
     }
-    if ((rc = d->dalloc(&d->lrow, d->LA + 1))) return rc;
-    const int nrun = (int)d->ra.size();
-    if ((rc = d->dalloc(&d->runs, 3 * (long)nrun))) return rc;
+    int* blk = nullptr;
+    if ((rc = d->dalloc(&blk, tab.size()))) return rc;
+    if ((rc = d->ctx->upload(blk, tab.data(), tab.size() * sizeof(int), st))) return rc;
+    d->lrow = blk;
+    d->runs = blk + o_runs;
     if (!lfull) {
-        if ((rc = d->ctx->upload(d->lmask, d->lmask_h.data(), d->lmask_h.size(), st))) return rc;
-        if ((rc = d->ctx->upload(d->lpref, lpref_h.data(), lpref_h.size() * sizeof(int), st))) return rc;
+        d->lpref = blk + o_pref;
+        d->lmask = reinterpret_cast<uint8_t*>(blk + o_mask);
     }
-    if ((rc = d->ctx->upload(d->lrow, d->lrow_h.data(), (d->LA + 1) * sizeof(int), st))) return rc;
-    std::vector<int> rr;
-    rr.insert(rr.end(), d->ra.begin(), d->ra.end());
-    rr.insert(rr.end(), d->rb0.begin(), d->rb0.end());
-    rr.insert(rr.end(), d->rb1.begin(), d->rb1.end());
-    if ((rc = d->ctx->upload(d->runs, rr.data(), rr.size() * sizeof(int), st))) return rc;
     d->rn = Runs{d->runs, d->runs + nrun, d->runs + 2 * nrun, nrun, d->L};
     // descriptor (K set filled after the origin count)
     OpDesc& o = d->op;
