@@ -735,8 +735,11 @@ int plan_request(ssa_ctx* ctx, const ssa_request& q, ssa_decomp* d, int nh_force
     return SSA_OK;
 }
 
-// Upload the request's data in the internal orientation.
-int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStream_t st) {
+// Upload the request's data in the internal orientation.  With jobs, the
+// device-to-device copies of device inputs are queued there for one batched
+// launch (which the caller issues before any kernel reads the copies).
+int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStream_t st,
+                   std::vector<CopyJob>* jobs = nullptr) {
     const long n = (long)d->A * d->B;
     int rc;
     d->last_st = st;
@@ -744,7 +747,8 @@ int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStrea
     if (q.mask && (rc = d->dalloc(&d->mask, n))) return rc;
     if (dev_input) {
         if (!d->tr || d->nx == 1 || d->ny == 1) {
-            HIPCHK(hipMemcpyAsync(d->x, q.x, n * 8, hipMemcpyDeviceToDevice, st));
+            if (jobs) jobs->push_back({q.x, d->x, n * 8});
+            else HIPCHK(hipMemcpyAsync(d->x, q.x, n * 8, hipMemcpyDeviceToDevice, st));
         } else {
             launch_transpose(1, d->nx, d->ny, st, q.x, d->x);
         }
@@ -756,6 +760,8 @@ int upload_request(const ssa_request& q, ssa_decomp* d, bool dev_input, hipStrea
                 for (int i = 0; i < d->nx; ++i)
                     for (int j = 0; j < d->ny; ++j) tm[(size_t)j * d->nx + i] = hm[(size_t)i * d->ny + j];
                 if ((rc = d->ctx->upload(d->mask, tm.data(), n, st))) return rc;
+            } else if (jobs) {
+                jobs->push_back({q.mask, d->mask, n});
             } else {
                 HIPCHK(hipMemcpyAsync(d->mask, q.mask, n, hipMemcpyDeviceToDevice, st));
             }
@@ -2521,12 +2527,25 @@ int decompose_core(ssa_ctx* ctx, int n, const ssa_request* reqs, ssa_decomp** ou
     std::vector<std::unique_ptr<ssa_decomp>> ds(n);
     std::vector<int> st(n, SSA_OK);
     std::map<GeoKey, std::vector<int>> groups;
+    std::vector<CopyJob> jobs;
     for (int i = 0; i < n; ++i) {
         out[i] = nullptr;
         ds[i].reset(new ssa_decomp());
         st[i] = plan_request(ctx, reqs[i], ds[i].get(), nh_force, ma_force);
-        if (st[i] == SSA_OK) st[i] = upload_request(reqs[i], ds[i].get(), dev, ctx->st);
+        if (st[i] == SSA_OK) st[i] = upload_request(reqs[i], ds[i].get(), dev, ctx->st, &jobs);
         if (st[i] == SSA_OK) groups[geo_key(ds[i].get())].push_back(i);
+    }
+    // the device inputs' copies, all in one launch (before the set-up reads them)
+    DevVec jd;
+    if (!jobs.empty()) {
+        long mx = 0;
+        for (const CopyJob& j : jobs) mx = std::max(mx, j.bytes);
+        if (jobs.size() <= 65535 && jd.put(jobs, ctx->st) == SSA_OK) {
+            launch_copy_jobs(ctx->st, jd.as<CopyJob>(), (int)jobs.size(), mx);
+        } else {
+            for (const CopyJob& j : jobs)
+                HIPCHK(hipMemcpyAsync(j.dst, j.src, j.bytes, hipMemcpyDeviceToDevice, ctx->st));
+        }
     }
     // Concurrent sub-batches (SHSSA_BATCH_STREAMS = 2..4) gain about 5% on
     // the 512^2 batch-64 workload but share the GPU between product kernels

@@ -141,5 +141,15 @@ void launch_esprit2d(hipStream_t st, const double* U, long L, const int* grp, in
 void launch_wgram(hipStream_t st, const double* const* arr, int narr, const double* W, long ncell, int nchunk,
                   double* part, double* out);
 void launch_transpose(int nmat, int R, int C, hipStream_t st, const double* in, double* out);
+// Device-to-device copies of a batch call's inputs in one launch: job i
+// copies bytes from src to dst (device pointers, non-overlapping).  jobs is a
+// device array of njobs entries, njobs <= 65535; max_bytes bounds the jobs'
+// sizes (it sets the grid).
+struct CopyJob {
+    const void* src;
+    void* dst;
+    long bytes;
+};
+void launch_copy_jobs(hipStream_t st, const CopyJob* jobs, int njobs, long max_bytes);
 
 }  // namespace shssa
